@@ -1,0 +1,118 @@
+"""Plant plausible mistakes in copies of the oracle's C sources and check that
+the pin suite catches every one of them (CPU only; the real oracle is never
+modified).  This shows the pins are strong enough to trust the oracle."""
+import os
+import shutil
+import tempfile
+
+import pytest
+
+import oracle
+import pins
+from oracle import build as obuild
+
+SRC = os.path.dirname(os.path.abspath(oracle.__file__))
+
+# (file, original text, planted mistake, what it models)
+MUTANTS = [
+    ("dd_ops.h", "double e = (a - (s - bb)) + (b - bb);",
+     "double e = (a - (s - bb)) - (b - bb);", "sign error in TwoSum"),
+    ("dd_ops.h", "double e = fma(a, b, -p);", "double e = fma(a, b, p);",
+     "sign error in TwoProd"),
+    ("dd_ops.h", "double e = b - (s - a);", "double e = (s - a) - b;",
+     "sign error in FastTwoSum"),
+    ("dd_ops.h", "double c2 = fma(x.lo, y.hi, t1);", "double c2 = fma(x.lo, y.lo, t1);",
+     "wrong operand in a dd-mul cross term"),
+    ("dd_ops.h", "double t1 = fma(x.hi, y.lo, t0);", "double t1 = t0;",
+     "dropped dd-mul cross term"),
+    ("dd_ops.h", "double w = t.lo + v.lo;", "double w = v.lo;",
+     "dropped low-part error in dd add"),
+    ("dd_ops.h", "double v = x.lo + s.lo;", "double v = s.lo;",
+     "dropped low part in dd + double"),
+    ("dd_oracle.c", "int64_t idx = trans ? (c + r * ld) : (r + c * ld);",
+     "int64_t idx = trans ? (r + c * ld) : (c + r * ld);", "transposed operand"),
+    ("dd_oracle.c", "for (l = 0; l < k; ++l) {", "for (l = 1; l < k; ++l) {",
+     "dropped first term"),
+    ("dd_oracle.c", "return dd_mul(beta, c0);", "return c0;", "beta ignored when alpha = 0"),
+    ("dd_oracle.c", "c = dd_add(c, dd_mul(beta, c0));", "c = dd_add(c, dd_mul(alpha, c0));",
+     "alpha used for beta"),
+    ("dd_oracle.c", "int64_t i, lo_i = upper ? 0 : j, hi_i = upper ? j : n - 1;",
+     "int64_t i, lo_i = upper ? j : 0, hi_i = upper ? n - 1 : j;", "wrong Rsyrk triangle"),
+    ("dd_oracle.c", "tb = !ta;\n#pragma omp parallel for schedule(dynamic, 1)",
+     "tb = ta;\n#pragma omp parallel for schedule(dynamic, 1)", "Rsyrk without transpose"),
+    ("dd_oracle.c", "int64_t nrowa = nota ? m : k;", "int64_t nrowa = nota ? k : m;",
+     "wrong lda check"),
+    ("dd_oracle.c", "if (ldc < imax(1, m)) return 13;", "if (ldc < imax(1, m)) return 12;",
+     "wrong error code"),
+    ("dd_oracle.c",
+     "if (m == 0 || n == 0 || ((is_zero(alpha) || k == 0) && is_one(beta))) return 0;\n    ta",
+     "if (m == 0 || n == 0 || ((is_zero(alpha) || k == 0) && is_zero(beta))) return 0;\n    ta",
+     "wrong quick return"),
+    ("dd_oracle.c", "if (!is_zero(beta)) { c0.hi = Ch[i + j * ldc]; c0.lo = Cl[i + j * ldc]; }\n"
+     "            c = entry(ta, tb, i, j, k, alpha, Ah, Al, lda, Bh, Bl, ldb, beta, c0);",
+     "c0.hi = Ch[i + j * ldc]; c0.lo = Cl[i + j * ldc];\n"
+     "            c = entry(ta, tb, i, j, k, alpha, Ah, Al, lda, Bh, Bl, ldb, beta, c0);"
+     "\n            if (is_zero(beta)) { c.hi += 0.0 * c0.hi; c.lo += 0.0 * c0.lo; }",
+     "C read when beta = 0"),
+    ("ozaki_oracle.c", "int shift = (t == 0) ? wfirst : w;", "int shift = w;",
+     "first digit too wide"),
+    ("ozaki_oracle.c", "y = two_sum(zh - q, zl);", "y.hi = zh - q; y.lo = 0.0;",
+     "remainder drops the low part"),
+    ("ozaki_oracle.c", "ldexp((double)x, -(2 * wfirst + w * (d - 2)))",
+     "ldexp((double)x, -(2 * wfirst + w * (d - 1)))", "wrong anti-diagonal weight"),
+    ("ozaki_oracle.c", "p.hi = ldexp(p.hi, ea[i] + eb[j]);", "p.hi = ldexp(p.hi, ea[i]);",
+     "column scale dropped"),
+]
+
+CHECKS = [
+    pins.check_worked_example,
+    pins.check_primitives,
+    lambda lib: pins.check_exact_gemm(lib, seeds=[0, 1]),
+    lambda lib: pins.check_exact_syrk(lib, seeds=[0]),
+    pins.check_info_codes,
+    pins.check_identities,
+    lambda lib: pins.check_ozaki_split_exact(lib),
+    pins.check_ozaki_gemm_exact,
+]
+
+
+def _caught(lib):
+    for chk in CHECKS:
+        try:
+            chk(lib)
+        except (AssertionError, ValueError):
+            return True
+    return False
+
+
+@pytest.mark.parametrize("fname,orig,mut,what", MUTANTS, ids=[m[3] for m in MUTANTS])
+def test_mutant_is_caught(fname, orig, mut, what):
+    tmp = tempfile.mkdtemp(prefix="oracle_mut_")
+    try:
+        for f in ("dd_ops.h", "dd_oracle.c", "ozaki_oracle.c"):
+            shutil.copy(os.path.join(SRC, f), tmp)
+        path = os.path.join(tmp, fname)
+        text = open(path).read()
+        assert text.count(orig) == 1, f"mutation anchor not found once: {orig!r}"
+        open(path, "w").write(text.replace(orig, mut))
+        so = obuild.build(out=os.path.join(tmp, "libmut.so"),
+                          sources=["dd_oracle.c", "ozaki_oracle.c"], cwd=tmp,
+                          extra=["-I", tmp])
+        lib = oracle.load(so)
+        assert _caught(lib), f"planted mistake not caught: {what}"
+    finally:
+        shutil.rmtree(tmp, ignore_errors=True)
+
+
+def test_unmutated_copy_passes():
+    """Control: the same harness on an unmodified copy passes every check."""
+    tmp = tempfile.mkdtemp(prefix="oracle_ctl_")
+    try:
+        for f in ("dd_ops.h", "dd_oracle.c", "ozaki_oracle.c"):
+            shutil.copy(os.path.join(SRC, f), tmp)
+        so = obuild.build(out=os.path.join(tmp, "libctl.so"),
+                          sources=["dd_oracle.c", "ozaki_oracle.c"], cwd=tmp,
+                          extra=["-I", tmp])
+        assert not _caught(oracle.load(so))
+    finally:
+        shutil.rmtree(tmp, ignore_errors=True)
