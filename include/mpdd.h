@@ -1,0 +1,142 @@
+/*
+ * mpdd.h -- C ABI of libmpdd: double-double (dd) Rgemm and Rsyrk on one AMD
+ * Instinct MI355X (gfx950).
+ *
+ * Operations (MPLAPACK 2.0.1 manual, section "How to use reference MPBLAS",
+ * which gives Rgemm the calling convention of BLAS DGEMM, and Table
+ * "mpblasroutines", which lists Rgemm and Rsyrk among the level-3 MPBLAS
+ * routines; the CUDA dd versions of both are the manual's section "CUDA
+ * accelerated MPBLAS"):
+ *
+ *   Rgemm:  C <- alpha * op(A) * op(B) + beta * C,  op(X) = X or X^T
+ *   Rsyrk:  C <- alpha * A * A^T + beta * C   (trans = "N")
+ *           C <- alpha * A^T * A + beta * C   (trans = "T" or "C")
+ *           updating only the uplo triangle of C, diagonal included.
+ *
+ * Number format (section "Supported Floating point formats"): a dd value is
+ * the unevaluated sum hi + lo of two binary64 numbers, |lo| <= ulp(hi)/2,
+ * about 106 significant bits (Table "rlamch_dd": epsilon 2^-104).
+ *
+ * Storage.  Every matrix is column-major with a leading dimension, as in
+ * MPBLAS (entry (i, j) of X lives at X[i + j*ldx], 0-based), and is held as
+ * TWO separate binary64 planes of identical layout: X_hi and X_lo.  All matrix
+ * pointers are DEVICE pointers (hipMalloc / torch allocations on the current
+ * device).  Rows ld..: the padding rows between the matrix's row count and
+ * its leading dimension are never read or written.  Scalars alpha and beta are
+ * normalised dd values passed by value.
+ *
+ * Flags.  Only the first character counts and case is ignored (MPBLAS
+ * Mlsame): trans in {N, T, C} (C means T for real data), uplo in {U, L}.
+ *
+ * Return value ("info"):
+ *   0   success (work enqueued on `stream`; the call does not wait for it);
+ *  >0   the 1-based position of the first invalid argument, numbered as in
+ *       the BLAS argument lists (Rgemm: 1 transa, 2 transb, 3 m, 4 n, 5 k,
+ *       8 lda, 10 ldb, 13 ldc; Rsyrk: 1 uplo, 2 trans, 3 n, 4 k, 7 lda,
+ *       10 ldc) -- the codes BLAS xerbla reports, as the manual's MPBLAS
+ *       quality-assurance section requires.  Nothing is enqueued and C is
+ *       untouched.  The library never prints or aborts.
+ *  <0   a runtime error, one of the MPDD_ERR_* codes below.
+ *
+ * Semantics as BLAS: quick return (C untouched) when m = 0 or n = 0, or when
+ * (alpha = 0 or k = 0) and beta = 1.  When alpha = 0 or k = 0, A and B are not
+ * read and may be NULL.  When beta = 0, C is written without being read (NaN
+ * in C does not propagate).  Rsyrk never reads or writes the opposite
+ * triangle.
+ *
+ * Ownership and asynchrony.  The caller owns A, B and C; they must stay valid
+ * until the work enqueued on `stream` has completed.  `stream` is a
+ * hipStream_t passed as void* (NULL = the legacy default stream).  The handle
+ * owns only host state (tuning table); scratch memory that a call needs
+ * (split-k partial sums, split-form slices) is allocated stream-ordered on
+ * the call's stream and released on it.  Calls on one handle may be made from
+ * several host threads and streams at once.
+ */
+#ifndef MPDD_H
+#define MPDD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int64_t mpdd_int;                   /* MPBLAS mplapackint on Linux: 64-bit */
+typedef struct { double hi, lo; } mpdd_dd;  /* scalar dd, normalised */
+typedef struct mpdd_handle_s *mpdd_handle;
+
+#define MPDD_ERR_HIP (-1)         /* a HIP runtime call or kernel launch failed */
+#define MPDD_ERR_ALLOC (-2)       /* device scratch allocation failed */
+#define MPDD_ERR_BUDGET (-3)      /* request larger than the server's memory budget */
+#define MPDD_ERR_SHUTDOWN (-4)    /* server is shutting down */
+#define MPDD_ERR_UNSUPPORTED (-5) /* option value or size outside what is implemented */
+#define MPDD_ERR_HANDLE (-6)      /* NULL or destroyed handle */
+#define MPDD_ERR_ARG (-7)         /* invalid non-BLAS argument (options, ticket, pointer) */
+
+/* Create a handle bound to the current HIP device.  tuner_cache_path may be
+ * NULL (built-in tile choices) or a JSON file written by the autotuner.
+ * Returns 0 or MPDD_ERR_*. */
+int mpdd_create(mpdd_handle *h, const char *tuner_cache_path);
+
+/* Destroy a handle.  The caller must have synchronised the streams it used. */
+int mpdd_destroy(mpdd_handle h);
+
+/* Rgemm: C <- alpha*op(A)*op(B) + beta*C on dd planes (see above).
+ * op(A) is m x k, op(B) is k x n, C is m x n.  A is lda x (k or m) for
+ * transa N or T, B is ldb x (n or k) for transb N or T. */
+int mpdd_Rgemm(mpdd_handle h, const char *transa, const char *transb, mpdd_int m, mpdd_int n,
+               mpdd_int k, mpdd_dd alpha, const double *A_hi, const double *A_lo, mpdd_int lda,
+               const double *B_hi, const double *B_lo, mpdd_int ldb, mpdd_dd beta,
+               double *C_hi, double *C_lo, mpdd_int ldc, void *stream);
+
+/* Rsyrk: C <- alpha*A*A^T + beta*C (trans N, A is n x k) or
+ * C <- alpha*A^T*A + beta*C (trans T/C, A is k x n), uplo triangle only. */
+int mpdd_Rsyrk(mpdd_handle h, const char *uplo, const char *trans, mpdd_int n, mpdd_int k,
+               mpdd_dd alpha, const double *A_hi, const double *A_lo, mpdd_int lda,
+               mpdd_dd beta, double *C_hi, double *C_lo, mpdd_int ldc, void *stream);
+
+/* ---- explicit algorithm and tile choice ------------------------------------ */
+
+#define MPDD_PLAIN 0          /* lean dd multiply-accumulate (12 binary64 ops) */
+#define MPDD_OZAKI_I8 1       /* split form, INT8 slices on the INT8 matrix cores */
+#define MPDD_OZAKI_F64 2      /* split form, FP64 slices on the FP64 matrix cores */
+#define MPDD_PLAIN_ACCURATE 3 /* accurate dd add + mul per term (same steps as the
+                                 reference evaluation; 29 binary64 ops) */
+
+typedef struct {
+  int algo;     /* MPDD_PLAIN, MPDD_OZAKI_I8, MPDD_OZAKI_F64, MPDD_PLAIN_ACCURATE */
+  int nslices;  /* split form: slices per operand, 0 = default for the input */
+  int tile_id;  /* plain forms: index into the tile table, -1 = tuned choice */
+  int splitk;   /* plain forms: k-split factor, 0 = automatic, 1 = none */
+} mpdd_opts;
+
+/* As mpdd_Rgemm with explicit options (opts may be NULL = defaults).
+ * Returns MPDD_ERR_ARG for an unknown algo, MPDD_ERR_UNSUPPORTED for an
+ * out-of-range tile_id / splitk / nslices. */
+int mpdd_Rgemm_ex(mpdd_handle h, const mpdd_opts *opts, const char *transa, const char *transb,
+                  mpdd_int m, mpdd_int n, mpdd_int k, mpdd_dd alpha, const double *A_hi,
+                  const double *A_lo, mpdd_int lda, const double *B_hi, const double *B_lo,
+                  mpdd_int ldb, mpdd_dd beta, double *C_hi, double *C_lo, mpdd_int ldc,
+                  void *stream);
+
+/* As mpdd_Rsyrk with explicit options (plain forms only). */
+int mpdd_Rsyrk_ex(mpdd_handle h, const mpdd_opts *opts, const char *uplo, const char *trans,
+                  mpdd_int n, mpdd_int k, mpdd_dd alpha, const double *A_hi,
+                  const double *A_lo, mpdd_int lda, mpdd_dd beta, double *C_hi,
+                  double *C_lo, mpdd_int ldc, void *stream);
+
+/* Number of entries in the plain-kernel tile table, and a description of
+ * entry id: tile rows, tile columns, k-depth of one staged tile, threads per
+ * workgroup.  Returns 0 or MPDD_ERR_ARG. */
+int mpdd_tile_count(void);
+int mpdd_tile_info(int id, int *bm, int *bn, int *bk, int *threads);
+
+/* Library version string (static storage). */
+const char *mpdd_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MPDD_H */

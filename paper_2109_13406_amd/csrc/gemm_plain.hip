@@ -1,0 +1,372 @@
+// gemm_plain.hip -- plain dd Rgemm / Rsyrk kernels for gfx950.
+//
+// One workgroup computes a BM x BN tile of C.  Each k-tile of op(A)
+// (BM x BK) and op(B) (BK x BN) is read from the hi/lo planes in HBM with
+// coalesced 8-byte loads (leading dimensions may be odd, so columns are only
+// 8-byte aligned), held in registers while the previous k-tile is being
+// consumed, and written to LDS as interleaved double2 {hi, lo} so that one
+// ds_read_b128 delivers a whole dd operand.  LDS is double buffered: one
+// barrier per k-tile.  Each thread owns an RM x RN block of dd accumulators
+// (rows tm + TMX*r, columns tn + TNX*c: consecutive lanes read consecutive
+// LDS words, so operand reads are conflict-free) and updates it with the dd
+// multiply-accumulate of dd.hpp.
+//
+// The same kernel serves Rsyrk (manual Table "mpblasroutines"): op(B) is
+// op(A)^T read from the same planes, only tiles that meet the uplo triangle
+// are launched, and the epilogue masks the diagonal tiles element by element
+// so the opposite triangle is never written.
+//
+// With a k-split (skinny products with too few C tiles to fill 256 CUs),
+// blockIdx.z selects a k-range; each slice writes its dd partial sums to a
+// scratch buffer and dd_splitk_reduce adds them in a fixed order with
+// cross-lane shuffles, then applies alpha / beta.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "dd.hpp"
+#include "kernels.hpp"
+
+#pragma clang fp contract(off)
+
+namespace mpdd {
+
+// Decode tile coordinates of workgroup b.  Workgroups are dealt round-robin
+// to the 8 XCDs; remapping b so that each XCD receives a contiguous run of
+// tiles keeps neighbouring tiles (which share A row panels) in one L2.
+__device__ __forceinline__ void tile_coords(const GemmParams& p, int& bi, int& bj) {
+  int b = blockIdx.x;
+  const int nb = gridDim.x;
+  if ((nb & 7) == 0) b = (b & 7) * (nb >> 3) + (b >> 3);
+  if (p.tri == 0) {
+    bi = b % p.tiles_m;
+    bj = b / p.tiles_m;
+  } else {
+    // tiles (x, y) with x <= y, enumerated column by column: t = y(y+1)/2 + x
+    int y = (int)((__builtin_sqrt(8.0 * (double)b + 1.0) - 1.0) * 0.5);
+    while ((y + 1) * (y + 2) / 2 <= b) ++y;
+    while (y * (y + 1) / 2 > b) --y;
+    int x = b - y * (y + 1) / 2;
+    if (p.tri == 1) { bi = x; bj = y; }   // upper: tile row <= tile column
+    else { bi = y; bj = x; }              // lower: tile row >= tile column
+  }
+}
+
+template <int BM, int BN, int BK, int RM, int RN, bool TA, bool TB, bool ACC, bool PARTIAL>
+__global__ void __launch_bounds__((BM / RM) * (BN / RN))
+dd_gemm_kernel(GemmParams p) {
+  constexpr int TMX = BM / RM;
+  constexpr int TNX = BN / RN;
+  constexpr int NT = TMX * TNX;
+  constexpr int AE = BM * BK / NT;   // A-tile elements staged per thread
+  constexpr int BE = BN * BK / NT;
+  static_assert(AE * NT == BM * BK && BE * NT == BN * BK, "tile not divisible by threads");
+  static_assert(NT % BK == 0, "threads must cover whole k-columns");
+
+  __shared__ double2 As[2][BK][BM + 1];
+  __shared__ double2 Bs[2][BK][BN + 1];
+
+  const int tid = threadIdx.x;
+  const int tm = tid % TMX;
+  const int tn = tid / TMX;
+
+  int bi, bj;
+  tile_coords(p, bi, bj);
+  const int64_t i0 = (int64_t)bi * BM;
+  const int64_t j0 = (int64_t)bj * BN;
+  const int64_t kbeg = (int64_t)blockIdx.z * p.kchunk;
+  const int64_t kend = (kbeg + p.kchunk < p.k) ? kbeg + p.kchunk : p.k;
+
+  // Staging map.  Element e of this thread's share of a tile sits at
+  // (mn, kk) inside it.  Lanes walk the direction that is contiguous in
+  // memory: for op(A) = A (A[i + l*lda]) and op(B) = B^T (B[j + l*ldb]) that
+  // is the row/column index, otherwise it is k.
+  auto coord = [&](int e, bool mn_contig, int bmn, int& mn, int& kk) {
+    const int x = tid + NT * e;
+    if (mn_contig) { mn = x % bmn; kk = x / bmn; } else { kk = x % BK; mn = x / BK; }
+  };
+  // Element offsets relative to the k-tile start, rows/columns clamped into
+  // the matrix: values staged for rows >= m (columns >= n) only reach
+  // accumulators that are never stored, so any finite in-bounds value will do.
+  int64_t aoff[AE], boff[BE];
+  int akk[AE], bkk[BE];
+#pragma unroll
+  for (int e = 0; e < AE; ++e) {
+    int mn, kk;
+    coord(e, !TA, BM, mn, kk);
+    int64_t gi = i0 + mn;
+    gi = gi < p.m ? gi : p.m - 1;
+    akk[e] = kk;
+    aoff[e] = TA ? (int64_t)kk + gi * p.lda : gi + (int64_t)kk * p.lda;
+  }
+#pragma unroll
+  for (int e = 0; e < BE; ++e) {
+    int mn, kk;
+    coord(e, TB, BN, mn, kk);
+    int64_t gj = j0 + mn;
+    gj = gj < p.n ? gj : p.n - 1;
+    bkk[e] = kk;
+    boff[e] = TB ? gj + (int64_t)kk * p.ldb : (int64_t)kk + gj * p.ldb;
+  }
+  const int64_t astep = TA ? 1 : p.lda;   // distance between consecutive k
+  const int64_t bstep = TB ? p.ldb : 1;
+
+  double ch[RM][RN], cl[RM][RN];
+#pragma unroll
+  for (int r = 0; r < RM; ++r)
+#pragma unroll
+    for (int c = 0; c < RN; ++c) { ch[r][c] = 0.0; cl[r][c] = 0.0; }
+
+  double ah_r[AE], al_r[AE], bh_r[BE], bl_r[BE];
+
+  // Load the k-tile starting at k0.  `tail`: zero the terms at k >= kend.
+  auto load_tiles = [&](int64_t k0, bool tail) {
+    const double* pah = p.a_hi + k0 * astep;
+    const double* pal = p.a_lo + k0 * astep;
+    const double* pbh = p.b_hi + k0 * bstep;
+    const double* pbl = p.b_lo + k0 * bstep;
+#pragma unroll
+    for (int e = 0; e < AE; ++e) {
+      double h = 0.0, l = 0.0;
+      if (!tail || k0 + akk[e] < kend) { h = pah[aoff[e]]; l = pal[aoff[e]]; }
+      ah_r[e] = h;
+      al_r[e] = l;
+    }
+#pragma unroll
+    for (int e = 0; e < BE; ++e) {
+      double h = 0.0, l = 0.0;
+      if (!tail || k0 + bkk[e] < kend) { h = pbh[boff[e]]; l = pbl[boff[e]]; }
+      bh_r[e] = h;
+      bl_r[e] = l;
+    }
+  };
+
+  auto store_tiles = [&](int buf) {
+#pragma unroll
+    for (int e = 0; e < AE; ++e) {
+      int mn, kk;
+      coord(e, !TA, BM, mn, kk);
+      As[buf][kk][mn] = make_double2(ah_r[e], al_r[e]);
+    }
+#pragma unroll
+    for (int e = 0; e < BE; ++e) {
+      int mn, kk;
+      coord(e, TB, BN, mn, kk);
+      Bs[buf][kk][mn] = make_double2(bh_r[e], bl_r[e]);
+    }
+  };
+
+  const int64_t nkt = (kend > kbeg) ? (kend - kbeg + BK - 1) / BK : 0;
+  if (nkt > 0) {
+    load_tiles(kbeg, nkt == 1);
+    store_tiles(0);
+  }
+  __syncthreads();
+
+  for (int64_t kt = 0; kt < nkt; ++kt) {
+    const int cur = (int)(kt & 1);
+    const bool more = kt + 1 < nkt;
+    if (more) load_tiles(kbeg + (kt + 1) * BK, kt + 2 == nkt);
+    // Operands of step kk+1 are read from LDS while step kk computes.
+    double2 a[2][RM], b[2][RN];
+#pragma unroll
+    for (int r = 0; r < RM; ++r) a[0][r] = As[cur][0][tm + TMX * r];
+#pragma unroll
+    for (int c = 0; c < RN; ++c) b[0][c] = Bs[cur][0][tn + TNX * c];
+#pragma unroll
+    for (int kk = 0; kk < BK; ++kk) {
+      const int q = kk & 1;
+      if (kk + 1 < BK) {
+#pragma unroll
+        for (int r = 0; r < RM; ++r) a[q ^ 1][r] = As[cur][kk + 1][tm + TMX * r];
+#pragma unroll
+        for (int c = 0; c < RN; ++c) b[q ^ 1][c] = Bs[cur][kk + 1][tn + TNX * c];
+      }
+#pragma unroll
+      for (int x = 0; x < RM * RN; ++x) {
+        const int r = x / RN, c = x % RN;
+        if (ACC)
+          madd_accurate(ch[r][c], cl[r][c], a[q][r].x, a[q][r].y, b[q][c].x, b[q][c].y);
+        else
+          madd_lean(ch[r][c], cl[r][c], a[q][r].x, a[q][r].y, b[q][c].x, b[q][c].y);
+      }
+      // Fence: this step's arithmetic completes here and no later LDS read is
+      // hoisted above it, so only one step of operands is in flight (without
+      // it the compiler issues every LDS read of the k-tile up front and
+      // spills).  Emits no instructions.
+#pragma unroll
+      for (int r = 0; r < RM; ++r)
+#pragma unroll
+        for (int c = 0; c < RN; ++c) asm volatile("" : "+v"(ch[r][c]), "+v"(cl[r][c]));
+      asm volatile("" ::: "memory");
+    }
+    if (!ACC) {
+#pragma unroll
+      for (int r = 0; r < RM; ++r)
+#pragma unroll
+        for (int c = 0; c < RN; ++c) renorm(ch[r][c], cl[r][c]);
+    }
+    if (more) store_tiles(cur ^ 1);
+    __syncthreads();
+  }
+
+  // ---- epilogue ----
+#pragma unroll
+  for (int r = 0; r < RM; ++r) {
+    const int64_t i = i0 + tm + TMX * r;
+#pragma unroll
+    for (int c = 0; c < RN; ++c) {
+      const int64_t j = j0 + tn + TNX * c;
+      if (i >= p.m || j >= p.n) continue;
+      if (PARTIAL) {
+        // k-split partial sum (normalised) into scratch [z][j*m + i]
+        const int64_t w = (int64_t)blockIdx.z * p.m * p.n + j * p.m + i;
+        p.w_hi[w] = ch[r][c];
+        p.w_lo[w] = cl[r][c];
+        continue;
+      }
+      if (p.tri == 1 && i > j) continue;
+      if (p.tri == 2 && i < j) continue;
+      ddv acc{ch[r][c], cl[r][c]};
+      ddv v = dd_mul(ddv{p.alpha_hi, p.alpha_lo}, acc);
+      const int64_t ci = i + j * p.ldc;
+      if (!p.beta_zero)
+        v = dd_add(v, dd_mul(ddv{p.beta_hi, p.beta_lo}, ddv{p.c_hi[ci], p.c_lo[ci]}));
+      p.c_hi[ci] = v.hi;
+      p.c_lo[ci] = v.lo;
+    }
+  }
+}
+
+// Add the S k-split partials of every entry in a fixed order and apply the
+// alpha / beta update.  Lane groups of S lanes hold one entry's partials
+// (lane s reads partial s); a butterfly of cross-lane dd additions
+// (__shfl_xor, offsets 1, 2, 4, ...) combines them.  TwoSum and the dd add
+// are symmetric in their operands, so every lane of a group ends with the
+// same bits and the result does not depend on the schedule.
+__global__ void __launch_bounds__(256) dd_splitk_reduce(GemmParams p, int S) {
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int s = (int)(gid % S);
+  const int64_t e = gid / S;
+  const int64_t total = p.m * p.n;
+  const bool live = e < total;
+  ddv v{0.0, 0.0};
+  if (live) {
+    const int64_t w = (int64_t)s * total + e;
+    v.hi = p.w_hi[w];
+    v.lo = p.w_lo[w];
+  }
+  for (int off = 1; off < S; off <<= 1) {
+    ddv o;
+    o.hi = __shfl_xor(v.hi, off);
+    o.lo = __shfl_xor(v.lo, off);
+    v = dd_add(v, o);
+  }
+  if (!live || s != 0) return;
+  const int64_t i = e % p.m, j = e / p.m;
+  if (p.tri == 1 && i > j) return;
+  if (p.tri == 2 && i < j) return;
+  ddv r = dd_mul(ddv{p.alpha_hi, p.alpha_lo}, v);
+  const int64_t ci = i + j * p.ldc;
+  if (!p.beta_zero) r = dd_add(r, dd_mul(ddv{p.beta_hi, p.beta_lo}, ddv{p.c_hi[ci], p.c_lo[ci]}));
+  p.c_hi[ci] = r.hi;
+  p.c_lo[ci] = r.lo;
+}
+
+// C <- beta * C on the whole matrix (tri 0) or one triangle; beta = 0 writes
+// +0 without reading C.  Used when alpha = 0 or k = 0.
+__global__ void __launch_bounds__(256) dd_scale_kernel(GemmParams p) {
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= p.m * p.n) return;
+  const int64_t i = gid % p.m, j = gid / p.m;
+  if (p.tri == 1 && i > j) return;
+  if (p.tri == 2 && i < j) return;
+  const int64_t ci = i + j * p.ldc;
+  ddv r{0.0, 0.0};
+  if (!p.beta_zero) r = dd_mul(ddv{p.beta_hi, p.beta_lo}, ddv{p.c_hi[ci], p.c_lo[ci]});
+  p.c_hi[ci] = r.hi;
+  p.c_lo[ci] = r.lo;
+}
+
+// ---- tile table and launchers ------------------------------------------------
+
+// id, BM, BN, BK, RM, RN  (threads = (BM/RM) * (BN/RN))
+#define MPDD_TILES(X)      \
+  X(0, 64, 64, 16, 4, 4)   \
+  X(1, 64, 64, 8, 4, 4)    \
+  X(2, 32, 32, 16, 2, 2)   \
+  X(3, 128, 64, 8, 8, 4)
+
+static const TileInfo kTiles[] = {
+#define X(id, bm, bn, bk, rm, rn) {bm, bn, bk, (bm / rm) * (bn / rn)},
+    MPDD_TILES(X)
+#undef X
+};
+
+int tile_count() { return (int)(sizeof(kTiles) / sizeof(kTiles[0])); }
+const TileInfo* tile_info(int id) {
+  return (id >= 0 && id < tile_count()) ? &kTiles[id] : nullptr;
+}
+
+template <int BM, int BN, int BK, int RM, int RN, bool TA, bool TB, bool ACC>
+static hipError_t launch_t(const GemmParams& p, int nblocks, int splitk, hipStream_t st) {
+  dim3 grid(nblocks, 1, splitk), block((BM / RM) * (BN / RN));
+  if (splitk > 1)
+    hipLaunchKernelGGL((dd_gemm_kernel<BM, BN, BK, RM, RN, TA, TB, ACC, true>), grid, block, 0,
+                       st, p);
+  else
+    hipLaunchKernelGGL((dd_gemm_kernel<BM, BN, BK, RM, RN, TA, TB, ACC, false>), grid, block, 0,
+                       st, p);
+  return hipGetLastError();
+}
+
+template <int BM, int BN, int BK, int RM, int RN>
+static hipError_t launch_ops(const GemmParams& p, bool ta, bool tb, bool acc, int nblocks,
+                             int splitk, hipStream_t st) {
+#define L(TA, TB, AC) return launch_t<BM, BN, BK, RM, RN, TA, TB, AC>(p, nblocks, splitk, st)
+  if (acc) {
+    if (!ta && !tb) L(false, false, true);
+    if (!ta && tb) L(false, true, true);
+    if (ta && !tb) L(true, false, true);
+    L(true, true, true);
+  }
+  if (!ta && !tb) L(false, false, false);
+  if (!ta && tb) L(false, true, false);
+  if (ta && !tb) L(true, false, false);
+  L(true, true, false);
+#undef L
+}
+
+hipError_t launch_gemm(int tile, const GemmParams& p, bool ta, bool tb, bool accurate,
+                       int splitk, hipStream_t st) {
+  const TileInfo* t = tile_info(tile);
+  if (!t) return hipErrorInvalidValue;
+  int nblocks;
+  if (p.tri == 0)
+    nblocks = p.tiles_m * p.tiles_n;
+  else
+    nblocks = p.tiles_m * (p.tiles_m + 1) / 2;
+  switch (tile) {
+#define X(id, bm, bn, bk, rm, rn) \
+  case id: return launch_ops<bm, bn, bk, rm, rn>(p, ta, tb, accurate, nblocks, splitk, st);
+    MPDD_TILES(X)
+#undef X
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_splitk_reduce(const GemmParams& p, int splitk, hipStream_t st) {
+  const int64_t threads = p.m * p.n * splitk;
+  const int64_t blocks = (threads + 255) / 256;
+  hipLaunchKernelGGL(dd_splitk_reduce, dim3((unsigned)blocks), dim3(256), 0, st, p, splitk);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale(const GemmParams& p, hipStream_t st) {
+  const int64_t total = p.m * p.n;
+  const int64_t blocks = (total + 255) / 256;
+  hipLaunchKernelGGL(dd_scale_kernel, dim3((unsigned)blocks), dim3(256), 0, st, p);
+  return hipGetLastError();
+}
+
+}  // namespace mpdd

@@ -1,0 +1,50 @@
+// kernels.hpp -- launch interface between the C-ABI layer (mpdd.cpp) and the
+// HIP kernels.  Internal to libmpdd.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace mpdd {
+
+// Arguments of one plain dd update, passed by value to the kernels.
+struct GemmParams {
+  int64_t m, n, k;
+  double alpha_hi, alpha_lo, beta_hi, beta_lo;
+  const double *a_hi, *a_lo;
+  int64_t lda;
+  const double *b_hi, *b_lo;
+  int64_t ldb;
+  double *c_hi, *c_lo;
+  int64_t ldc;
+  double *w_hi, *w_lo;  // k-split partial sums, [z][j*m + i]
+  int64_t kchunk;       // k-range per k-split slice (multiple of the tile depth)
+  int tiles_m, tiles_n;
+  int tri;              // 0 full matrix, 1 upper triangle, 2 lower triangle
+  int beta_zero;        // C is not read
+};
+
+struct TileInfo {
+  int bm, bn, bk, threads;
+};
+
+int tile_count();
+const TileInfo* tile_info(int id);
+
+hipError_t launch_gemm(int tile, const GemmParams& p, bool ta, bool tb, bool accurate,
+                       int splitk, hipStream_t st);
+hipError_t launch_splitk_reduce(const GemmParams& p, int splitk, hipStream_t st);
+hipError_t launch_scale(const GemmParams& p, hipStream_t st);
+
+}  // namespace mpdd
+
+namespace mpdd {
+
+// Split-form (Ozaki) Rgemm (ozaki.hip).  Returns 0 or an MPDD_ERR_* code.
+int ozaki_gemm(const void* opts, bool ta, bool tb, int64_t m, int64_t n, int64_t k,
+               double alpha_hi, double alpha_lo, const double* a_hi, const double* a_lo,
+               int64_t lda, const double* b_hi, const double* b_lo, int64_t ldb,
+               double beta_hi, double beta_lo, double* c_hi, double* c_lo, int64_t ldc,
+               hipStream_t st);
+
+}  // namespace mpdd

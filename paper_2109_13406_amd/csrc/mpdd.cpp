@@ -1,0 +1,268 @@
+// mpdd.cpp -- the C ABI of libmpdd (declared in include/mpdd.h): argument
+// checking, BLAS quick returns, tile / k-split choice and kernel dispatch for
+// the plain dd Rgemm and Rsyrk.
+//
+// Argument checks and quick returns follow the BLAS reference DGEMM / DSYRK
+// (the MPLAPACK manual's section "How to use reference MPBLAS" gives Rgemm
+// DGEMM's argument list; its MPBLAS quality-assurance section requires error
+// codes equal to xerbla's).  Checks run on the host before any HIP call, so
+// an invalid call has no side effects at all.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <new>
+
+#include "../../include/mpdd.h"
+#include "kernels.hpp"
+#include "tuner.hpp"
+
+using namespace mpdd;
+
+struct mpdd_handle_s {
+  int device = 0;
+  int magic = 0x6d706464;
+  TuneTable tune;
+};
+
+namespace {
+
+bool lsame(const char* s, char ref) {
+  if (!s) return false;
+  char c = s[0];
+  if (c >= 'a' && c <= 'z') c = (char)(c - 'a' + 'A');
+  return c == ref;
+}
+
+bool is_zero(mpdd_dd x) { return x.hi == 0.0 && x.lo == 0.0; }
+bool is_one(mpdd_dd x) { return x.hi == 1.0 && x.lo == 0.0; }
+
+int check_gemm(const char* ta, const char* tb, mpdd_int m, mpdd_int n, mpdd_int k, mpdd_int lda,
+               mpdd_int ldb, mpdd_int ldc) {
+  const bool nota = lsame(ta, 'N'), notb = lsame(tb, 'N');
+  const mpdd_int nrowa = nota ? m : k;
+  const mpdd_int nrowb = notb ? k : n;
+  if (!nota && !lsame(ta, 'T') && !lsame(ta, 'C')) return 1;
+  if (!notb && !lsame(tb, 'T') && !lsame(tb, 'C')) return 2;
+  if (m < 0) return 3;
+  if (n < 0) return 4;
+  if (k < 0) return 5;
+  if (lda < std::max<mpdd_int>(1, nrowa)) return 8;
+  if (ldb < std::max<mpdd_int>(1, nrowb)) return 10;
+  if (ldc < std::max<mpdd_int>(1, m)) return 13;
+  return 0;
+}
+
+int check_syrk(const char* uplo, const char* trans, mpdd_int n, mpdd_int k, mpdd_int lda,
+               mpdd_int ldc) {
+  const bool upper = lsame(uplo, 'U');
+  const mpdd_int nrowa = lsame(trans, 'N') ? n : k;
+  if (!upper && !lsame(uplo, 'L')) return 1;
+  if (!lsame(trans, 'N') && !lsame(trans, 'T') && !lsame(trans, 'C')) return 2;
+  if (n < 0) return 3;
+  if (k < 0) return 4;
+  if (lda < std::max<mpdd_int>(1, nrowa)) return 7;
+  if (ldc < std::max<mpdd_int>(1, n)) return 10;
+  return 0;
+}
+
+int hip_status(hipError_t e) { return e == hipSuccess ? 0 : MPDD_ERR_HIP; }
+
+bool handle_ok(mpdd_handle h) { return h != nullptr && h->magic == 0x6d706464; }
+
+// Automatic k-split: enough C tiles to give every CU two workgroups, else
+// split k (keeping >= 1024 terms per slice) up to 16 ways.
+int auto_splitk(int64_t tiles, int64_t k, int bk) {
+  const int64_t target = 512;
+  if (tiles >= target) return 1;
+  int s = 1;
+  while (s < 16 && tiles * s < target && k / (2 * s) >= 1024 && (k / (2 * s)) % bk == 0) s *= 2;
+  return s;
+}
+
+struct Plan {
+  int tile;
+  int splitk;
+};
+
+Plan choose(const mpdd_handle h, const mpdd_opts* o, int op, bool ta, bool tb, int64_t m,
+            int64_t n, int64_t k, bool square_only) {
+  Plan pl{-1, 0};
+  if (o && o->tile_id >= 0) pl.tile = o->tile_id;
+  if (o && o->splitk > 0) pl.splitk = o->splitk;
+  if (pl.tile < 0 || pl.splitk == 0) {
+    TuneEntry e;
+    if (h->tune.lookup(op, ta, tb, m, n, k, e)) {
+      if (pl.tile < 0) pl.tile = e.tile;
+      if (pl.splitk == 0) pl.splitk = e.splitk;
+    }
+  }
+  if (pl.tile < 0) pl.tile = default_tile(m, n, k, square_only);
+  if (pl.splitk == 0) {
+    const TileInfo* t = tile_info(pl.tile);
+    const int64_t tiles = ((m + t->bm - 1) / t->bm) * ((n + t->bn - 1) / t->bn);
+    pl.splitk = square_only ? 1 : auto_splitk(tiles, k, t->bk);
+  }
+  return pl;
+}
+
+int run_plain(mpdd_handle h, const mpdd_opts* o, bool ta, bool tb, int tri, int64_t m, int64_t n,
+              int64_t k, mpdd_dd alpha, const double* Ah, const double* Al, int64_t lda,
+              const double* Bh, const double* Bl, int64_t ldb, mpdd_dd beta, double* Ch,
+              double* Cl, int64_t ldc, hipStream_t st) {
+  const bool accurate = o && o->algo == MPDD_PLAIN_ACCURATE;
+  GemmParams p{};
+  p.m = m; p.n = n; p.k = k;
+  p.alpha_hi = alpha.hi; p.alpha_lo = alpha.lo;
+  p.beta_hi = beta.hi; p.beta_lo = beta.lo;
+  p.a_hi = Ah; p.a_lo = Al; p.lda = lda;
+  p.b_hi = Bh; p.b_lo = Bl; p.ldb = ldb;
+  p.c_hi = Ch; p.c_lo = Cl; p.ldc = ldc;
+  p.tri = tri;
+  p.beta_zero = is_zero(beta) ? 1 : 0;
+
+  if (is_zero(alpha) || k == 0) return hip_status(launch_scale(p, st));
+
+  const int op = tri ? 1 : 0;
+  Plan pl = choose(h, o, op, ta, tb, m, n, k, tri != 0);
+  const TileInfo* t = tile_info(pl.tile);
+  if (!t) return MPDD_ERR_UNSUPPORTED;
+  if (tri && t->bm != t->bn) return MPDD_ERR_UNSUPPORTED;
+  if (pl.splitk < 1 || pl.splitk > 64 || (pl.splitk & (pl.splitk - 1)) != 0)
+    return MPDD_ERR_UNSUPPORTED;
+  p.tiles_m = (int)((m + t->bm - 1) / t->bm);
+  p.tiles_n = (int)((n + t->bn - 1) / t->bn);
+
+  int S = pl.splitk;
+  // k-range per slice: a whole number of staged k-tiles
+  int64_t chunk = (k + S - 1) / S;
+  chunk = (chunk + t->bk - 1) / t->bk * t->bk;
+  while (S > 1 && (int64_t)(S - 1) * chunk >= k) S >>= 1;   // no empty slices
+  if (S > 1) {
+    chunk = (k + S - 1) / S;
+    chunk = (chunk + t->bk - 1) / t->bk * t->bk;
+  } else {
+    chunk = k;
+  }
+  p.kchunk = chunk;
+
+  if (S == 1) return hip_status(launch_gemm(pl.tile, p, ta, tb, accurate, 1, st));
+
+  void* w = nullptr;
+  const size_t plane = (size_t)S * (size_t)m * (size_t)n * sizeof(double);
+  if (hipMallocAsync(&w, 2 * plane, st) != hipSuccess) return MPDD_ERR_ALLOC;
+  p.w_hi = (double*)w;
+  p.w_lo = (double*)((char*)w + plane);
+  hipError_t e = launch_gemm(pl.tile, p, ta, tb, accurate, S, st);
+  if (e == hipSuccess) e = launch_splitk_reduce(p, S, st);
+  hipError_t ef = hipFreeAsync(w, st);
+  if (e != hipSuccess) return MPDD_ERR_HIP;
+  return hip_status(ef);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* mpdd_version(void) { return "mpdd 0.1 (gfx950)"; }
+
+int mpdd_tile_count(void) { return tile_count(); }
+
+int mpdd_tile_info(int id, int* bm, int* bn, int* bk, int* threads) {
+  const TileInfo* t = tile_info(id);
+  if (!t) return MPDD_ERR_ARG;
+  if (bm) *bm = t->bm;
+  if (bn) *bn = t->bn;
+  if (bk) *bk = t->bk;
+  if (threads) *threads = t->threads;
+  return 0;
+}
+
+int mpdd_create(mpdd_handle* h, const char* tuner_cache_path) {
+  if (!h) return MPDD_ERR_ARG;
+  *h = nullptr;
+  auto* s = new (std::nothrow) mpdd_handle_s();
+  if (!s) return MPDD_ERR_ALLOC;
+  if (hipGetDevice(&s->device) != hipSuccess) {
+    delete s;
+    return MPDD_ERR_HIP;
+  }
+  if (tuner_cache_path && tuner_cache_path[0]) {
+    if (!s->tune.load(tuner_cache_path)) {
+      delete s;
+      return MPDD_ERR_ARG;
+    }
+  }
+  *h = s;
+  return 0;
+}
+
+int mpdd_destroy(mpdd_handle h) {
+  if (!handle_ok(h)) return MPDD_ERR_HANDLE;
+  h->magic = 0;
+  delete h;
+  return 0;
+}
+
+int mpdd_Rgemm_ex(mpdd_handle h, const mpdd_opts* opts, const char* transa, const char* transb,
+                  mpdd_int m, mpdd_int n, mpdd_int k, mpdd_dd alpha, const double* A_hi,
+                  const double* A_lo, mpdd_int lda, const double* B_hi, const double* B_lo,
+                  mpdd_int ldb, mpdd_dd beta, double* C_hi, double* C_lo, mpdd_int ldc,
+                  void* stream) {
+  const int info = check_gemm(transa, transb, m, n, k, lda, ldb, ldc);
+  if (info) return info;
+  if (!handle_ok(h)) return MPDD_ERR_HANDLE;
+  const int algo = opts ? opts->algo : MPDD_PLAIN;
+  if (algo != MPDD_PLAIN && algo != MPDD_PLAIN_ACCURATE && algo != MPDD_OZAKI_I8 &&
+      algo != MPDD_OZAKI_F64)
+    return MPDD_ERR_ARG;
+  if (m == 0 || n == 0 || ((is_zero(alpha) || k == 0) && is_one(beta))) return 0;
+  if (!C_hi || !C_lo) return MPDD_ERR_ARG;
+  if (!is_zero(alpha) && k > 0 && (!A_hi || !A_lo || !B_hi || !B_lo)) return MPDD_ERR_ARG;
+  const bool ta = !lsame(transa, 'N'), tb = !lsame(transb, 'N');
+  hipStream_t st = (hipStream_t)stream;
+  if (algo == MPDD_OZAKI_I8 || algo == MPDD_OZAKI_F64)
+    return ozaki_gemm(opts, ta, tb, m, n, k, alpha.hi, alpha.lo, A_hi, A_lo, lda, B_hi, B_lo,
+                      ldb, beta.hi, beta.lo, C_hi, C_lo, ldc, st);
+  return run_plain(h, opts, ta, tb, 0, m, n, k, alpha, A_hi, A_lo, lda, B_hi, B_lo, ldb, beta,
+                   C_hi, C_lo, ldc, st);
+}
+
+int mpdd_Rgemm(mpdd_handle h, const char* transa, const char* transb, mpdd_int m, mpdd_int n,
+               mpdd_int k, mpdd_dd alpha, const double* A_hi, const double* A_lo, mpdd_int lda,
+               const double* B_hi, const double* B_lo, mpdd_int ldb, mpdd_dd beta,
+               double* C_hi, double* C_lo, mpdd_int ldc, void* stream) {
+  return mpdd_Rgemm_ex(h, nullptr, transa, transb, m, n, k, alpha, A_hi, A_lo, lda, B_hi, B_lo,
+                       ldb, beta, C_hi, C_lo, ldc, stream);
+}
+
+int mpdd_Rsyrk_ex(mpdd_handle h, const mpdd_opts* opts, const char* uplo, const char* trans,
+                  mpdd_int n, mpdd_int k, mpdd_dd alpha, const double* A_hi,
+                  const double* A_lo, mpdd_int lda, mpdd_dd beta, double* C_hi,
+                  double* C_lo, mpdd_int ldc, void* stream) {
+  const int info = check_syrk(uplo, trans, n, k, lda, ldc);
+  if (info) return info;
+  if (!handle_ok(h)) return MPDD_ERR_HANDLE;
+  const int algo = opts ? opts->algo : MPDD_PLAIN;
+  if (algo != MPDD_PLAIN && algo != MPDD_PLAIN_ACCURATE) return MPDD_ERR_ARG;
+  if (n == 0 || ((is_zero(alpha) || k == 0) && is_one(beta))) return 0;
+  if (!C_hi || !C_lo) return MPDD_ERR_ARG;
+  if (!is_zero(alpha) && k > 0 && (!A_hi || !A_lo)) return MPDD_ERR_ARG;
+  // trans N: op(A) = A (n x k), op(B) = A^T; trans T: op(A) = A^T, op(B) = A.
+  const bool ta = !lsame(trans, 'N');
+  const bool tb = !ta;
+  const int tri = lsame(uplo, 'U') ? 1 : 2;
+  return run_plain(h, opts, ta, tb, tri, n, n, k, alpha, A_hi, A_lo, lda, A_hi, A_lo, lda, beta,
+                   C_hi, C_lo, ldc, (hipStream_t)stream);
+}
+
+int mpdd_Rsyrk(mpdd_handle h, const char* uplo, const char* trans, mpdd_int n, mpdd_int k,
+               mpdd_dd alpha, const double* A_hi, const double* A_lo, mpdd_int lda,
+               mpdd_dd beta, double* C_hi, double* C_lo, mpdd_int ldc, void* stream) {
+  return mpdd_Rsyrk_ex(h, nullptr, uplo, trans, n, k, alpha, A_hi, A_lo, lda, beta, C_hi, C_lo,
+                       ldc, stream);
+}
+
+}  // extern "C"

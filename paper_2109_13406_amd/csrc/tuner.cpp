@@ -1,0 +1,69 @@
+// tuner.cpp -- the tuning table of a handle (see tuner.hpp).
+#include "tuner.hpp"
+
+#include <cstdio>
+#include <cstring>
+
+#include "kernels.hpp"
+
+namespace mpdd {
+
+int shape_bucket(int64_t x) {
+  int b = 0;
+  while (b < 62 && ((int64_t)1 << b) < x) ++b;
+  return b;
+}
+
+static int op_code(const char* s) {
+  if (std::strcmp(s, "gemm") == 0) return 0;
+  if (std::strcmp(s, "syrk") == 0) return 1;
+  return -1;
+}
+
+bool TuneTable::load(const char* path) {
+  FILE* f = std::fopen(path, "r");
+  if (!f) return false;
+  char line[512];
+  bool ok = true;
+  while (std::fgets(line, sizeof line, f)) {
+    const char* p = std::strstr(line, "{\"op\"");
+    if (!p) continue;
+    char op[8] = {0}, tr[4] = {0};
+    int mb, nb, kb, tile, splitk, nsl = 0;
+    int got = std::sscanf(p,
+                          "{\"op\": \"%7[a-z]\", \"trans\": \"%3[NT]\", \"mb\": %d, \"nb\": %d, "
+                          "\"kb\": %d, \"tile\": %d, \"splitk\": %d, \"nslices\": %d",
+                          op, tr, &mb, &nb, &kb, &tile, &splitk, &nsl);
+    const int code = op_code(op);
+    if (got < 7 || code < 0 || std::strlen(tr) != 2 || !tile_info(tile) || splitk < 1) {
+      ok = false;
+      break;
+    }
+    TuneEntry e;
+    e.tile = tile;
+    e.splitk = splitk;
+    e.nslices = nsl;
+    map_[Key(code, tr[0] == 'T', tr[1] == 'T', mb, nb, kb)] = e;
+  }
+  std::fclose(f);
+  return ok;
+}
+
+bool TuneTable::lookup(int op, bool ta, bool tb, int64_t m, int64_t n, int64_t k,
+                       TuneEntry& out) const {
+  auto it = map_.find(Key(op, ta, tb, shape_bucket(m), shape_bucket(n), shape_bucket(k)));
+  if (it == map_.end()) return false;
+  out = it->second;
+  return true;
+}
+
+int default_tile(int64_t m, int64_t n, int64_t k, bool square_only) {
+  (void)k;
+  // 64x64 tiles give 4096 workgroups at n = 4096; small problems use 32x32
+  // tiles so that more CUs get work.
+  const int64_t t64 = ((m + 63) / 64) * ((n + 63) / 64);
+  if (t64 < 128 && (square_only || (m <= 1024 && n <= 1024))) return 2;
+  return 0;
+}
+
+}  // namespace mpdd

@@ -1,0 +1,37 @@
+// tuner.hpp -- tile / k-split choice per (operation, flags, shape bucket).
+// The table is filled by the autotuner (paper_2109_13406_amd/autotune.py),
+// which times every candidate on the device and writes a JSON cache; the
+// handle loads it at creation.  Without an entry, default_tile() applies.
+#pragma once
+#include <cstdint>
+#include <map>
+#include <tuple>
+
+namespace mpdd {
+
+struct TuneEntry {
+  int tile = -1;
+  int splitk = 0;
+  int nslices = 0;
+};
+
+// Shape bucket: ceil(log2(x)) (0 for x <= 1).
+int shape_bucket(int64_t x);
+
+class TuneTable {
+ public:
+  // Reads the autotuner's JSON cache (one entry object per line).  Returns
+  // false when the file cannot be read or an entry line is malformed.
+  bool load(const char* path);
+  bool lookup(int op, bool ta, bool tb, int64_t m, int64_t n, int64_t k, TuneEntry& out) const;
+  size_t size() const { return map_.size(); }
+
+ private:
+  using Key = std::tuple<int, int, int, int, int, int>;
+  std::map<Key, TuneEntry> map_;
+};
+
+// Built-in choice from the tile table when the tuner has no entry.
+int default_tile(int64_t m, int64_t n, int64_t k, bool square_only);
+
+}  // namespace mpdd

@@ -1,0 +1,125 @@
+"""The C-ABI library without a GPU: it loads, exports every symbol that
+include/*.h declares, and its host-side argument checks report the BLAS
+argument positions (checked before the handle, so no HIP call is made)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import pins
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    names = set()
+    inc = os.path.join(ROOT, "include")
+    for f in os.listdir(inc):
+        if not f.endswith(".h"):
+            continue
+        text = open(os.path.join(inc, f)).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        for m in re.finditer(r"^\s*[A-Za-z_][\w \*]*?\b(mpdd_\w+)\s*\(", text, flags=re.M):
+            names.add(m.group(1))
+    return sorted(names)
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2109_13406_amd import binding
+    return binding.load()
+
+
+def test_header_declares_entry_points():
+    names = _declared_functions()
+    for must in ("mpdd_create", "mpdd_destroy", "mpdd_Rgemm", "mpdd_Rsyrk", "mpdd_Rgemm_ex"):
+        assert must in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    for name in _declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_binding_names_match_header():
+    from paper_2109_13406_amd import binding
+    for name in binding.SIGNATURES:
+        assert name in _declared_functions(), name
+
+
+def _gemm(lib, transa="N", transb="N", m=2, n=2, k=2, lda=None, ldb=None, ldc=None):
+    from paper_2109_13406_amd import binding as b
+    nra = m if transa.upper() == "N" else k
+    nrb = k if transb.upper() == "N" else n
+    lda = max(1, nra) if lda is None else lda
+    ldb = max(1, nrb) if ldb is None else ldb
+    ldc = max(1, m) if ldc is None else ldc
+    return lib.mpdd_Rgemm(None, transa.encode(), transb.encode(), m, n, k, b.mpdd_dd(1.0, 0.0),
+                          None, None, lda, None, None, ldb, b.mpdd_dd(0.5, 0.0), None, None, ldc,
+                          None)
+
+
+def _syrk(lib, uplo="U", trans="N", n=2, k=2, lda=None, ldc=None):
+    from paper_2109_13406_amd import binding as b
+    nra = n if trans.upper() == "N" else k
+    lda = max(1, nra) if lda is None else lda
+    ldc = max(1, n) if ldc is None else ldc
+    return lib.mpdd_Rsyrk(None, uplo.encode(), trans.encode(), n, k, b.mpdd_dd(1.0, 0.0), None,
+                          None, lda, b.mpdd_dd(0.5, 0.0), None, None, ldc, None)
+
+
+def test_info_codes_match_blas_positions(lib):
+    from paper_2109_13406_amd import binding as b
+    pos = pins.read_arg_positions()
+    H = b.MPDD_ERR_HANDLE          # valid arguments reach the handle check
+    g = lambda **kw: _gemm(lib, **kw)
+    s = lambda **kw: _syrk(lib, **kw)
+    assert g() == H
+    for t in "NnTtCc":
+        assert g(transa=t) == H and g(transb=t) == H
+    assert g(transa="X") == pos[("gemm", "transa")]
+    assert g(transb="q") == pos[("gemm", "transb")]
+    assert g(transa="X", m=-1) == pos[("gemm", "transa")]
+    assert g(m=-1) == pos[("gemm", "m")]
+    assert g(n=-1) == pos[("gemm", "n")]
+    assert g(k=-1) == pos[("gemm", "k")]
+    assert g(m=5, lda=4) == pos[("gemm", "lda")]
+    assert g(transa="T", m=5, k=3, lda=3) == H
+    assert g(transa="T", m=3, k=5, lda=4) == pos[("gemm", "lda")]
+    assert g(k=5, ldb=4) == pos[("gemm", "ldb")]
+    assert g(transb="T", n=5, k=3, ldb=4) == pos[("gemm", "ldb")]
+    assert g(m=5, lda=5, ldc=4) == pos[("gemm", "ldc")]
+    assert g(m=0, lda=0) == pos[("gemm", "lda")]
+    assert s() == H
+    assert s(uplo="x") == pos[("syrk", "uplo")]
+    assert s(trans="z") == pos[("syrk", "trans")]
+    assert s(trans="c") == H
+    assert s(n=-1) == pos[("syrk", "n")]
+    assert s(k=-1) == pos[("syrk", "k")]
+    assert s(n=5, lda=4) == pos[("syrk", "lda")]
+    assert s(trans="T", n=3, k=5, lda=4) == pos[("syrk", "lda")]
+    assert s(n=5, lda=5, ldc=4) == pos[("syrk", "ldc")]
+
+
+def test_null_flag_is_invalid(lib):
+    from paper_2109_13406_amd import binding as b
+    info = lib.mpdd_Rgemm(None, None, b"N", 1, 1, 1, b.mpdd_dd(1.0, 0.0), None, None, 1, None,
+                          None, 1, b.mpdd_dd(0.0, 0.0), None, None, 1, None)
+    assert info == 1
+
+
+def test_tile_table(lib):
+    from paper_2109_13406_amd import binding as b
+    n = b.mpdd_tile_count()
+    assert n >= 1
+    for i in range(n):
+        bm, bn, bk, threads = b.mpdd_tile_info(i)
+        assert bm > 0 and bn > 0 and bk > 0 and threads % 64 == 0
+    with pytest.raises(ValueError):
+        b.mpdd_tile_info(n)
+
+
+def test_destroy_null_handle(lib):
+    from paper_2109_13406_amd import binding as b
+    assert lib.mpdd_destroy(None) == b.MPDD_ERR_HANDLE
