@@ -126,6 +126,125 @@ int mpdd_Rsyrk_ex(mpdd_handle h, const mpdd_opts *opts, const char *uplo, const 
                   const double *A_lo, mpdd_int lda, mpdd_dd beta, double *C_hi,
                   double *C_lo, mpdd_int ldc, void *stream);
 
+/* ---- split-form building blocks ------------------------------------------------ *
+ *
+ * The split form (algo MPDD_OZAKI_I8 / MPDD_OZAKI_F64) cuts every row of op(A)
+ * and every column of op(B) into `nslices` digit slices: with sigma the
+ * frexp exponent of the row's largest |hi| (so |x| < 2^sigma), y = x 2^-sigma
+ * and, for t = 1..nslices, z = y 2^w_t, q_t = rint(z.hi), y = TwoSum(z.hi - q_t,
+ * z.lo).  INT8: w_1 = 6, w_t = 7 (|q| <= 64).  FP64: w_1 = w - 1, w_t = w, with
+ * w = floor((55 - ceil(log2(nslices*k))) / 2) so that sums of nslices*k digit
+ * products are exact in binary64.  Slice products are accumulated exactly per
+ * anti-diagonal on the matrix cores and recombined in dd (published basis:
+ * Ozaki, Ogita, Oishi, Rump 2012; Ootomo, Ozaki, Yokota 2024 -- the manual
+ * itself has no split method). */
+
+/* Digit widths (first, later) of a split form for k and nslices.
+ * Returns 0, or MPDD_ERR_UNSUPPORTED when no exact width exists (INT8 needs
+ * nslices*k <= 2^19). */
+int mpdd_ozaki_digit_widths(int algo, mpdd_int k, int nslices, int *wfirst, int *w);
+
+/* Scale exponents and digit slices of a "row operand" R (rows x k): element
+ * (r, l) of R is X[r + l*ld] for trans "N" and X[l + r*ld] for trans "T"
+ * (rows of op(A) are R with trans = transa; columns of op(B) are R with the
+ * flag opposite to transb).  Device outputs: exps[rows] (int32) and
+ * `nslices` planes of rows_p x ldq digits, plane t (0-based) at
+ * slices + t*rows_p*ldq, digit (r, l) at [r*ldq + l]; int8 for
+ * MPDD_OZAKI_I8, double for MPDD_OZAKI_F64.  ldq must be a multiple of 64 and
+ * >= k, rows_p a multiple of 64 and >= rows; padding digits are written as 0.
+ * Returns 0, a BLAS-style position (3 rows, 4 k, 8 ld, 9 nslices, 12 ldq,
+ * 13 rows_p) for an invalid argument, or MPDD_ERR_*. */
+int mpdd_ozaki_split(mpdd_handle h, int algo, const char *trans, mpdd_int rows, mpdd_int k,
+                     const double *X_hi, const double *X_lo, mpdd_int ld, int nslices,
+                     int *exps, void *slices, mpdd_int ldq, mpdd_int rows_p, void *stream);
+
+/* ---- request server (continuous batching) ----------------------------------------
+ *
+ * A server owns a scheduler thread and four slot streams.  Submitted requests
+ * are validated (same info codes as the plain calls), admitted in FIFO order
+ * while the memory budget allows -- a request counts 16 bytes per dd entry
+ * of A, B and C (ld x columns) from admission to completion, and requests
+ * larger than the whole budget fail with MPDD_ERR_BUDGET -- and launched as
+ * groups: all admitted requests go into one persistent grouped kernel launch
+ * (a captured hipGraph) on a free slot, so groups overlap on the device and
+ * new requests start as soon as a slot and budget free up.  Each result is
+ * bit-identical to a standalone mpdd_Rgemm_ex / mpdd_Rsyrk_ex with the same
+ * tile (the server uses the handle's tuned tile, restricted to the 32 x 32
+ * and 64 x 64 x 16 shapes).  Operands stay where the caller put them (device
+ * memory) and must stay valid until the request completes.
+ *
+ * Intended callers: any host thread; submit and wait may run concurrently. */
+
+#define MPDD_OP_GEMM 0
+#define MPDD_OP_SYRK 1
+
+#define MPDD_SERVER_FAKE_DEVICE 1      /* no GPU: groups complete after a simulated time
+                                          (tests of the scheduling logic only) */
+#define MPDD_INJECT_NONE 0
+#define MPDD_INJECT_DEVICE_ERROR 1     /* the request's launch reports a device error */
+#define MPDD_INJECT_ALLOC_FAILURE 2    /* the request fails admission as if out of memory */
+
+typedef struct mpdd_server_s *mpdd_server;
+
+typedef struct {
+  int op;                  /* MPDD_OP_GEMM or MPDD_OP_SYRK */
+  char flag1, flag2;       /* Rgemm: transa, transb; Rsyrk: uplo, trans */
+  char pad_[2];
+  mpdd_int m, n, k;        /* Rsyrk: n, k (m ignored) */
+  mpdd_dd alpha, beta;
+  const double *A_hi, *A_lo;
+  mpdd_int lda;
+  const double *B_hi, *B_lo;   /* Rgemm only */
+  mpdd_int ldb;
+  double *C_hi, *C_lo;
+  mpdd_int ldc;
+  double arrival;          /* arrival time on mpdd_clock(); < 0 = time of submit */
+  int inject;              /* MPDD_INJECT_*: forced failure of this request only */
+  int pad2_;
+} mpdd_request;
+
+typedef struct {
+  double arrival, submit, admit, start, end;   /* mpdd_clock() seconds */
+  int group;                                   /* group the request ran in (0: none) */
+  int info;                                    /* the request's info code */
+  int tile;                                    /* tile-table id it ran with (-1: none) */
+  int pad_;
+} mpdd_timing;
+
+typedef struct {
+  int64_t submitted, completed, failed, groups;
+  int64_t queued_requests, inflight_requests;
+  uint64_t inflight_bytes;
+} mpdd_server_stats;
+
+/* Monotonic clock (seconds) used for request timings. */
+double mpdd_clock(void);
+
+/* Create a server on handle h (its device and tuned tiles).  flags:
+ * MPDD_SERVER_FAKE_DEVICE (h may be NULL).  Returns 0 or MPDD_ERR_*. */
+int mpdd_server_create(mpdd_server *s, mpdd_handle h, size_t hbm_budget_bytes, int max_inflight,
+                       int flags);
+
+/* Fake-device servers only: simulated throughput and per-group latency. */
+int mpdd_server_set_fake_rate(mpdd_server s, double dd_flops_per_s, double group_latency_s);
+
+/* Enqueue a request (non-blocking).  *ticket identifies it for wait/poll.
+ * Returns 0 (the request's own outcome is reported by wait), MPDD_ERR_ARG,
+ * or MPDD_ERR_SHUTDOWN. */
+int mpdd_server_submit(mpdd_server s, const mpdd_request *r, uint64_t *ticket);
+
+/* Block until the request completes; report its info code and timings and
+ * forget the ticket.  Returns 0 or MPDD_ERR_ARG (unknown ticket). */
+int mpdd_server_wait(mpdd_server s, uint64_t ticket, int *info, mpdd_timing *t);
+
+/* *done = 1 if the request has completed (ticket stays valid). */
+int mpdd_server_poll(mpdd_server s, uint64_t ticket, int *done);
+
+int mpdd_server_get_stats(mpdd_server s, mpdd_server_stats *st);
+
+/* Drain every queued and in-flight request, then free the server. */
+int mpdd_server_destroy(mpdd_server s);
+
 /* Number of entries in the plain-kernel tile table, and a description of
  * entry id: tile rows, tile columns, k-depth of one staged tile, threads per
  * workgroup.  Returns 0 or MPDD_ERR_ARG. */
@@ -134,6 +253,11 @@ int mpdd_tile_info(int id, int *bm, int *bn, int *bk, int *threads);
 
 /* Library version string (static storage). */
 const char *mpdd_version(void);
+
+/* sizeof of an ABI struct by name ("mpdd_dd", "mpdd_opts", "mpdd_request",
+ * "mpdd_timing", "mpdd_server_stats"), 0 if unknown: lets bindings check
+ * their layouts. */
+size_t mpdd_struct_size(const char *name);
 
 #ifdef __cplusplus
 }

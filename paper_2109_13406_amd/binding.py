@@ -37,6 +37,37 @@ class mpdd_opts(ctypes.Structure):
                 ("splitk", ctypes.c_int)]
 
 
+class mpdd_request(ctypes.Structure):
+    _fields_ = [("op", ctypes.c_int), ("flag1", ctypes.c_char), ("flag2", ctypes.c_char),
+                ("pad_", ctypes.c_char * 2), ("m", ctypes.c_int64), ("n", ctypes.c_int64),
+                ("k", ctypes.c_int64), ("alpha", mpdd_dd), ("beta", mpdd_dd),
+                ("A_hi", ctypes.c_void_p), ("A_lo", ctypes.c_void_p), ("lda", ctypes.c_int64),
+                ("B_hi", ctypes.c_void_p), ("B_lo", ctypes.c_void_p), ("ldb", ctypes.c_int64),
+                ("C_hi", ctypes.c_void_p), ("C_lo", ctypes.c_void_p), ("ldc", ctypes.c_int64),
+                ("arrival", ctypes.c_double), ("inject", ctypes.c_int), ("pad2_", ctypes.c_int)]
+
+
+class mpdd_timing(ctypes.Structure):
+    _fields_ = [("arrival", ctypes.c_double), ("submit", ctypes.c_double),
+                ("admit", ctypes.c_double), ("start", ctypes.c_double), ("end", ctypes.c_double),
+                ("group", ctypes.c_int), ("info", ctypes.c_int), ("tile", ctypes.c_int),
+                ("pad_", ctypes.c_int)]
+
+
+class mpdd_server_stats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64),
+                ("failed", ctypes.c_int64), ("groups", ctypes.c_int64),
+                ("queued_requests", ctypes.c_int64), ("inflight_requests", ctypes.c_int64),
+                ("inflight_bytes", ctypes.c_uint64)]
+
+
+MPDD_OP_GEMM = 0
+MPDD_OP_SYRK = 1
+MPDD_SERVER_FAKE_DEVICE = 1
+MPDD_INJECT_NONE = 0
+MPDD_INJECT_DEVICE_ERROR = 1
+MPDD_INJECT_ALLOC_FAILURE = 2
+
 _I = ctypes.c_int64
 _P = ctypes.c_void_p
 _C = ctypes.c_char_p
@@ -54,6 +85,23 @@ SIGNATURES = {
                                   _P]),
     "mpdd_Rsyrk_ex": (ctypes.c_int, [_P, ctypes.POINTER(mpdd_opts), _C, _C, _I, _I, mpdd_dd, _P,
                                      _P, _I, mpdd_dd, _P, _P, _I, _P]),
+    "mpdd_ozaki_digit_widths": (ctypes.c_int, [ctypes.c_int, _I, ctypes.c_int,
+                                                ctypes.POINTER(ctypes.c_int),
+                                                ctypes.POINTER(ctypes.c_int)]),
+    "mpdd_ozaki_split": (ctypes.c_int, [_P, ctypes.c_int, _C, _I, _I, _P, _P, _I, ctypes.c_int,
+                                        _P, _P, _I, _I, _P]),
+    "mpdd_struct_size": (ctypes.c_size_t, [_C]),
+    "mpdd_clock": (ctypes.c_double, []),
+    "mpdd_server_create": (ctypes.c_int, [ctypes.POINTER(_P), _P, ctypes.c_size_t, ctypes.c_int,
+                                          ctypes.c_int]),
+    "mpdd_server_set_fake_rate": (ctypes.c_int, [_P, ctypes.c_double, ctypes.c_double]),
+    "mpdd_server_submit": (ctypes.c_int, [_P, ctypes.POINTER(mpdd_request),
+                                          ctypes.POINTER(ctypes.c_uint64)]),
+    "mpdd_server_wait": (ctypes.c_int, [_P, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int),
+                                        ctypes.POINTER(mpdd_timing)]),
+    "mpdd_server_poll": (ctypes.c_int, [_P, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int)]),
+    "mpdd_server_get_stats": (ctypes.c_int, [_P, ctypes.POINTER(mpdd_server_stats)]),
+    "mpdd_server_destroy": (ctypes.c_int, [_P]),
     "mpdd_tile_count": (ctypes.c_int, []),
     "mpdd_tile_info": (ctypes.c_int, [ctypes.c_int] + [ctypes.POINTER(ctypes.c_int)] * 4),
 }
@@ -159,6 +207,24 @@ def mpdd_Rsyrk_ex(h, opts, uplo, trans, n, k, alpha, A, lda, beta, C, ldc, strea
                                 _dd(beta), _ptr(C[0]), _ptr(C[1]), ldc, _stream(stream))
 
 
+def mpdd_ozaki_digit_widths(algo, k, nslices):
+    """(first digit width, later digit width) of a split form; raises if none."""
+    a, b = ctypes.c_int(), ctypes.c_int()
+    info = load().mpdd_ozaki_digit_widths(algo, k, nslices, ctypes.byref(a), ctypes.byref(b))
+    if info != 0:
+        raise ValueError(f"no exact digit width for algo={algo} k={k} nslices={nslices}: {info}")
+    return a.value, b.value
+
+
+def mpdd_ozaki_split(h, algo, trans, rows, k, X, ld, nslices, exps, slices, ldq, rows_p,
+                     stream=None):
+    """Scale exponents (int32 tensor) and slices (int8 / float64 tensor) of a row
+    operand, see include/mpdd.h.  Returns info."""
+    return load().mpdd_ozaki_split(h, algo, _flag(trans), rows, k, _ptr(X[0]), _ptr(X[1]), ld,
+                                   nslices, _ptr(exps), _ptr(slices), ldq, rows_p,
+                                   _stream(stream))
+
+
 def mpdd_tile_count():
     return load().mpdd_tile_count()
 
@@ -169,3 +235,79 @@ def mpdd_tile_info(tile_id):
     if info != 0:
         raise ValueError(f"no tile {tile_id}")
     return tuple(v.value for v in vals)
+
+
+# ---- request server ---------------------------------------------------------------
+
+def mpdd_struct_size(name):
+    return load().mpdd_struct_size(name.encode())
+
+
+def mpdd_clock():
+    return load().mpdd_clock()
+
+
+def mpdd_server_create(h, hbm_budget_bytes, max_inflight, flags=0):
+    s = _P()
+    info = load().mpdd_server_create(ctypes.byref(s), h, hbm_budget_bytes, max_inflight, flags)
+    if info != 0:
+        raise RuntimeError(f"mpdd_server_create failed: {info}")
+    return s
+
+
+def mpdd_server_set_fake_rate(s, dd_flops_per_s, group_latency_s):
+    return load().mpdd_server_set_fake_rate(s, dd_flops_per_s, group_latency_s)
+
+
+def make_request(op, flag1, flag2, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, arrival=-1.0,
+                 inject=MPDD_INJECT_NONE):
+    """An mpdd_request; A, B, C are (hi, lo) pairs of tensors or device pointers
+    (B may be (None, None) for Rsyrk)."""
+    r = mpdd_request()
+    r.op = op
+    r.flag1 = _flag(flag1)
+    r.flag2 = _flag(flag2)
+    r.m, r.n, r.k = m, n, k
+    r.alpha, r.beta = _dd(alpha), _dd(beta)
+    r.A_hi, r.A_lo, r.lda = _ptr(A[0]), _ptr(A[1]), lda
+    r.B_hi, r.B_lo, r.ldb = _ptr(B[0]), _ptr(B[1]), ldb
+    r.C_hi, r.C_lo, r.ldc = _ptr(C[0]), _ptr(C[1]), ldc
+    r.arrival = arrival
+    r.inject = inject
+    return r
+
+
+def mpdd_server_submit(s, req):
+    t = ctypes.c_uint64()
+    info = load().mpdd_server_submit(s, ctypes.byref(req), ctypes.byref(t))
+    if info != 0:
+        raise RuntimeError(f"mpdd_server_submit failed: {info}")
+    return t.value
+
+
+def mpdd_server_wait(s, ticket):
+    """(info, timing dict) of a request; blocks until it completes."""
+    info = ctypes.c_int()
+    t = mpdd_timing()
+    rc = load().mpdd_server_wait(s, ticket, ctypes.byref(info), ctypes.byref(t))
+    if rc != 0:
+        raise ValueError(f"mpdd_server_wait: unknown ticket {ticket}")
+    return info.value, {f: getattr(t, f) for f, _ in mpdd_timing._fields_}
+
+
+def mpdd_server_poll(s, ticket):
+    d = ctypes.c_int()
+    rc = load().mpdd_server_poll(s, ticket, ctypes.byref(d))
+    if rc != 0:
+        raise ValueError(f"mpdd_server_poll: unknown ticket {ticket}")
+    return bool(d.value)
+
+
+def mpdd_server_get_stats(s):
+    st = mpdd_server_stats()
+    load().mpdd_server_get_stats(s, ctypes.byref(st))
+    return {f: getattr(st, f) for f, _ in mpdd_server_stats._fields_}
+
+
+def mpdd_server_destroy(s):
+    return load().mpdd_server_destroy(s)

@@ -22,7 +22,7 @@ OBJ = os.path.join(ROOT, "_build", "mpdd")
 LIB = os.path.join(PKG, "libmpdd.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["mpdd.cpp", "tuner.cpp", "gemm_plain.hip", "ozaki.hip"]
+SOURCES = ["mpdd.cpp", "tuner.cpp", "server.cpp", "gemm_plain.hip", "ozaki.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-ffp-contract=off",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wall", "-Wno-unused-function", "-I", os.path.join(ROOT, "include")]
@@ -30,11 +30,7 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-ffp-contract=o
 
 def _compile(src):
     out = os.path.join(OBJ, os.path.basename(src) + ".o")
-    cmd = [HIPCC, *FLAGS, "-x", "hip" if src.endswith(".hip") else "c++", "-c",
-           os.path.join(CSRC, src), "-o", out]
-    if not src.endswith(".hip"):
-        cmd = [HIPCC, "-O3", "-fPIC", "-std=c++17", "-ffp-contract=off", "-Wall",
-               "-I", os.path.join(ROOT, "include"), "-c", os.path.join(CSRC, src), "-o", out]
+    cmd = [HIPCC, *FLAGS, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", out]
     r = subprocess.run(cmd, capture_output=True, text=True)
     return src, out, r
 

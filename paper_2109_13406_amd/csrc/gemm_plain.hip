@@ -52,9 +52,19 @@ __device__ __forceinline__ void tile_coords(const GemmParams& p, int& bi, int& b
   }
 }
 
-template <int BM, int BN, int BK, int RM, int RN, bool TA, bool TB, bool ACC, bool PARTIAL>
-__global__ void __launch_bounds__((BM / RM) * (BN / RN))
-dd_gemm_kernel(GemmParams p) {
+template <int BM, int BN, int BK>
+struct DDTileSmem {
+  double2 As[2][BK][BM + 1];
+  double2 Bs[2][BK][BN + 1];
+};
+
+// Accumulate the BM x BN tile at (i0, j0) of op(A) op(B) over k in
+// [kbeg, kend) into this thread's RM x RN block of dd accumulators.
+template <int BM, int BN, int BK, int RM, int RN, bool TA, bool TB, bool ACC>
+__device__ __forceinline__ void dd_tile_mainloop(const GemmParams& p, int64_t i0, int64_t j0,
+                                                 int64_t kbeg, int64_t kend,
+                                                 DDTileSmem<BM, BN, BK>& sm, double (&ch)[RM][RN],
+                                                 double (&cl)[RM][RN]) {
   constexpr int TMX = BM / RM;
   constexpr int TNX = BN / RN;
   constexpr int NT = TMX * TNX;
@@ -63,19 +73,11 @@ dd_gemm_kernel(GemmParams p) {
   static_assert(AE * NT == BM * BK && BE * NT == BN * BK, "tile not divisible by threads");
   static_assert(NT % BK == 0, "threads must cover whole k-columns");
 
-  __shared__ double2 As[2][BK][BM + 1];
-  __shared__ double2 Bs[2][BK][BN + 1];
-
+  auto& As = sm.As;
+  auto& Bs = sm.Bs;
   const int tid = threadIdx.x;
   const int tm = tid % TMX;
   const int tn = tid / TMX;
-
-  int bi, bj;
-  tile_coords(p, bi, bj);
-  const int64_t i0 = (int64_t)bi * BM;
-  const int64_t j0 = (int64_t)bj * BN;
-  const int64_t kbeg = (int64_t)blockIdx.z * p.kchunk;
-  const int64_t kend = (kbeg + p.kchunk < p.k) ? kbeg + p.kchunk : p.k;
 
   // Staging map.  Element e of this thread's share of a tile sits at
   // (mn, kk) inside it.  Lanes walk the direction that is contiguous in
@@ -111,7 +113,6 @@ dd_gemm_kernel(GemmParams p) {
   const int64_t astep = TA ? 1 : p.lda;   // distance between consecutive k
   const int64_t bstep = TB ? p.ldb : 1;
 
-  double ch[RM][RN], cl[RM][RN];
 #pragma unroll
   for (int r = 0; r < RM; ++r)
 #pragma unroll
@@ -209,8 +210,19 @@ dd_gemm_kernel(GemmParams p) {
     if (more) store_tiles(cur ^ 1);
     __syncthreads();
   }
+}
 
-  // ---- epilogue ----
+// Write this thread's block of the tile at (i0, j0): either the k-split
+// partial sums into scratch slice z, or C <- alpha*acc + beta*C on the stored
+// entries (masked to the triangle for Rsyrk).
+template <int BM, int BN, int RM, int RN, bool PARTIAL>
+__device__ __forceinline__ void dd_tile_epilogue(const GemmParams& p, int64_t i0, int64_t j0,
+                                                 int z, const double (&ch)[RM][RN],
+                                                 const double (&cl)[RM][RN]) {
+  constexpr int TMX = BM / RM;
+  constexpr int TNX = BN / RN;
+  const int tm = threadIdx.x % TMX;
+  const int tn = threadIdx.x / TMX;
 #pragma unroll
   for (int r = 0; r < RM; ++r) {
     const int64_t i = i0 + tm + TMX * r;
@@ -220,7 +232,7 @@ dd_gemm_kernel(GemmParams p) {
       if (i >= p.m || j >= p.n) continue;
       if (PARTIAL) {
         // k-split partial sum (normalised) into scratch [z][j*m + i]
-        const int64_t w = (int64_t)blockIdx.z * p.m * p.n + j * p.m + i;
+        const int64_t w = (int64_t)z * p.m * p.n + j * p.m + i;
         p.w_hi[w] = ch[r][c];
         p.w_lo[w] = cl[r][c];
         continue;
@@ -235,6 +247,54 @@ dd_gemm_kernel(GemmParams p) {
       p.c_hi[ci] = v.hi;
       p.c_lo[ci] = v.lo;
     }
+  }
+}
+
+template <int BM, int BN, int BK, int RM, int RN, bool TA, bool TB, bool ACC, bool PARTIAL>
+__global__ void __launch_bounds__((BM / RM) * (BN / RN))
+dd_gemm_kernel(GemmParams p) {
+  __shared__ DDTileSmem<BM, BN, BK> sm;
+  int bi, bj;
+  tile_coords(p, bi, bj);
+  const int64_t i0 = (int64_t)bi * BM;
+  const int64_t j0 = (int64_t)bj * BN;
+  const int64_t kbeg = (int64_t)blockIdx.z * p.kchunk;
+  const int64_t kend = (kbeg + p.kchunk < p.k) ? kbeg + p.kchunk : p.k;
+  double ch[RM][RN], cl[RM][RN];
+  dd_tile_mainloop<BM, BN, BK, RM, RN, TA, TB, ACC>(p, i0, j0, kbeg, kend, sm, ch, cl);
+  dd_tile_epilogue<BM, BN, RM, RN, PARTIAL>(p, i0, j0, (int)blockIdx.z, ch, cl);
+}
+
+// Persistent grouped kernel of the request server: a fixed grid walks a list
+// of (request, tile) work items (sorted longest first), workgroup g taking
+// items g, g + G, g + 2G, ...  Each item runs exactly the steps of
+// dd_gemm_kernel for that request's flags, so a request's result is bit-
+// identical to a standalone call with the same tile.  The item count is read
+// from the device header, so one captured launch serves every group.
+template <int BM, int BN, int BK, int RM, int RN>
+__global__ void __launch_bounds__((BM / RM) * (BN / RN))
+dd_grouped_kernel(const ServeReq* __restrict__ reqs, const ServeItem* __restrict__ items,
+                  const int* __restrict__ counts, int which) {
+  __shared__ DDTileSmem<BM, BN, BK> sm;
+  // the item lists of the tile shapes follow each other in `items`
+  int first = 0;
+  for (int c = 0; c < which; ++c) first += counts[c];
+  const int n = counts[which];
+  for (int w = blockIdx.x; w < n; w += gridDim.x) {
+    const ServeItem it = items[first + w];
+    const GemmParams p = reqs[it.req].p;
+    const int flags = reqs[it.req].flags;
+    const int64_t i0 = (int64_t)it.bi * BM;
+    const int64_t j0 = (int64_t)it.bj * BN;
+    double ch[RM][RN], cl[RM][RN];
+    switch (flags & 3) {
+      case 0: dd_tile_mainloop<BM, BN, BK, RM, RN, false, false, false>(p, i0, j0, 0, p.k, sm, ch, cl); break;
+      case 1: dd_tile_mainloop<BM, BN, BK, RM, RN, true, false, false>(p, i0, j0, 0, p.k, sm, ch, cl); break;
+      case 2: dd_tile_mainloop<BM, BN, BK, RM, RN, false, true, false>(p, i0, j0, 0, p.k, sm, ch, cl); break;
+      default: dd_tile_mainloop<BM, BN, BK, RM, RN, true, true, false>(p, i0, j0, 0, p.k, sm, ch, cl); break;
+    }
+    dd_tile_epilogue<BM, BN, RM, RN, false>(p, i0, j0, 0, ch, cl);
+    __syncthreads();
   }
 }
 
@@ -349,6 +409,20 @@ hipError_t launch_gemm(int tile, const GemmParams& p, bool ta, bool tb, bool acc
   switch (tile) {
 #define X(id, bm, bn, bk, rm, rn) \
   case id: return launch_ops<bm, bn, bk, rm, rn>(p, ta, tb, accurate, nblocks, splitk, st);
+    MPDD_TILES(X)
+#undef X
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_grouped_list(int tile, const ServeReq* reqs, const ServeItem* items,
+                               const int* counts, int which, int grid, hipStream_t st) {
+  switch (tile) {
+#define X(id, bm, bn, bk, rm, rn)                                                              \
+  case id:                                                                                     \
+    hipLaunchKernelGGL((dd_grouped_kernel<bm, bn, bk, rm, rn>), dim3(grid),                    \
+                       dim3((bm / rm) * (bn / rn)), 0, st, reqs, items, counts, which);        \
+    return hipGetLastError();
     MPDD_TILES(X)
 #undef X
   }

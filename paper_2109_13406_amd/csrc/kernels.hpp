@@ -24,6 +24,20 @@ struct GemmParams {
   int beta_zero;        // C is not read
 };
 
+// One request of a served group: its update (kchunk = k, no split) and the
+// op flags (bit 0: op(A) transposed, bit 1: op(B) transposed).
+struct ServeReq {
+  GemmParams p;
+  int flags;
+  int pad_;
+};
+
+// One work item of a group: a C tile of a request.
+struct ServeItem {
+  int req;
+  int bi, bj;
+};
+
 struct TileInfo {
   int bm, bn, bk, threads;
 };
@@ -34,6 +48,10 @@ const TileInfo* tile_info(int id);
 hipError_t launch_gemm(int tile, const GemmParams& p, bool ta, bool tb, bool accurate,
                        int splitk, hipStream_t st);
 hipError_t launch_splitk_reduce(const GemmParams& p, int splitk, hipStream_t st);
+// Persistent grouped kernel over the `which`-th item list: counts[c] items per
+// tile shape, lists stored back to back (counts are read on the device).
+hipError_t launch_grouped_list(int tile, const ServeReq* reqs, const ServeItem* items,
+                               const int* counts, int which, int grid, hipStream_t st);
 hipError_t launch_scale(const GemmParams& p, hipStream_t st);
 
 }  // namespace mpdd
@@ -46,5 +64,11 @@ int ozaki_gemm(const void* opts, bool ta, bool tb, int64_t m, int64_t n, int64_t
                int64_t lda, const double* b_hi, const double* b_lo, int64_t ldb,
                double beta_hi, double beta_lo, double* c_hi, double* c_lo, int64_t ldc,
                hipStream_t st);
+
+// Split-form building blocks (ozaki.hip).
+int ozaki_split_entry(int algo, bool trans, int64_t rows, int64_t k, const double* hi,
+                      const double* lo, int64_t ld, int nslices, int wfirst, int w, int* exps,
+                      void* slices, int64_t ldq, int64_t rows_p, hipStream_t st);
+int ozaki_digit_widths(int algo, int64_t k, int nslices, int* wfirst, int* w);
 
 }  // namespace mpdd

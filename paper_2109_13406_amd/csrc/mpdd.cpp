@@ -27,6 +27,15 @@ struct mpdd_handle_s {
   TuneTable tune;
 };
 
+bool handle_valid(const mpdd_handle_s* h) { return h != nullptr && h->magic == 0x6d706464; }
+
+int handle_device(const mpdd_handle_s* h) { return h ? h->device : 0; }
+
+bool handle_tune_lookup(const mpdd_handle_s* h, int op, bool ta, bool tb, int64_t m, int64_t n,
+                        int64_t k, TuneEntry& out) {
+  return handle_valid(h) && h->tune.lookup(op, ta, tb, m, n, k, out);
+}
+
 namespace {
 
 bool lsame(const char* s, char ref) {
@@ -168,6 +177,16 @@ extern "C" {
 
 const char* mpdd_version(void) { return "mpdd 0.1 (gfx950)"; }
 
+size_t mpdd_struct_size(const char* name) {
+  if (!name) return 0;
+  if (std::strcmp(name, "mpdd_dd") == 0) return sizeof(mpdd_dd);
+  if (std::strcmp(name, "mpdd_opts") == 0) return sizeof(mpdd_opts);
+  if (std::strcmp(name, "mpdd_request") == 0) return sizeof(mpdd_request);
+  if (std::strcmp(name, "mpdd_timing") == 0) return sizeof(mpdd_timing);
+  if (std::strcmp(name, "mpdd_server_stats") == 0) return sizeof(mpdd_server_stats);
+  return 0;
+}
+
 int mpdd_tile_count(void) { return tile_count(); }
 
 int mpdd_tile_info(int id, int* bm, int* bn, int* bk, int* threads) {
@@ -178,6 +197,35 @@ int mpdd_tile_info(int id, int* bm, int* bn, int* bk, int* threads) {
   if (bk) *bk = t->bk;
   if (threads) *threads = t->threads;
   return 0;
+}
+
+int mpdd_ozaki_digit_widths(int algo, mpdd_int k, int nslices, int* wfirst, int* w) {
+  if ((algo != MPDD_OZAKI_I8 && algo != MPDD_OZAKI_F64) || !wfirst || !w || k < 0 ||
+      nslices < 1)
+    return MPDD_ERR_ARG;
+  return ozaki_digit_widths(algo, k, nslices, wfirst, w);
+}
+
+int mpdd_ozaki_split(mpdd_handle h, int algo, const char* trans, mpdd_int rows, mpdd_int k,
+                     const double* X_hi, const double* X_lo, mpdd_int ld, int nslices,
+                     int* exps, void* slices, mpdd_int ldq, mpdd_int rows_p, void* stream) {
+  if (algo != MPDD_OZAKI_I8 && algo != MPDD_OZAKI_F64) return MPDD_ERR_ARG;
+  const bool nt = lsame(trans, 'N');
+  if (!nt && !lsame(trans, 'T') && !lsame(trans, 'C')) return 2;
+  if (rows < 0) return 3;
+  if (k < 0) return 4;
+  if (ld < std::max<mpdd_int>(1, nt ? rows : k)) return 8;
+  if (nslices < 1 || nslices > 40) return 9;
+  if (ldq < k || ldq % 64 != 0 || ldq < 64) return 12;
+  if (rows_p < rows || rows_p % 64 != 0 || rows_p < 64) return 13;
+  if (!handle_ok(h)) return MPDD_ERR_HANDLE;
+  if (rows == 0) return 0;
+  int wf, w;
+  const int e = ozaki_digit_widths(algo, k, nslices, &wf, &w);
+  if (e) return e;
+  if (!exps || !slices || (k > 0 && (!X_hi || !X_lo))) return MPDD_ERR_ARG;
+  return ozaki_split_entry(algo, !nt, rows, k, X_hi, X_lo, ld, nslices, wf, w, exps, slices, ldq,
+                           rows_p, (hipStream_t)stream);
 }
 
 int mpdd_create(mpdd_handle* h, const char* tuner_cache_path) {

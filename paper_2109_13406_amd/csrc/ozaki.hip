@@ -1,15 +1,514 @@
-// ozaki.hip -- split-form dd Rgemm (placeholder until the kernels land).
+// ozaki.hip -- split-form dd Rgemm on the matrix cores of gfx950.
+//
+// The manual contains no split method; this is the error-free splitting of a
+// matrix product (Ozaki, Ogita, Oishi, Rump 2012) in the integer-unit form of
+// Ootomo, Ozaki and Yokota (2024), applied to dd operands:
+//
+//  scale    sigma_r = frexp exponent of max_l |x_rl.hi| for every row of op(A)
+//           and every column of op(B) ("row operand"), so |x| < 2^sigma.
+//  slice    y = x * 2^-sigma (exact); digit t: z = y * 2^w_t, q_t = rint(z.hi),
+//           y = TwoSum(z.hi - q_t, z.lo).  INT8 form: w_1 = 6, w_t = 7, so
+//           |q| <= 64; FP64 form: w_1 = w - 1, w_t = w with w chosen so that
+//           every sum of nslices*k digit products stays an integer < 2^53.
+//           Digits are stored k-contiguous per row, in tiles padded with zeros.
+//  products for every anti-diagonal d = t + u (2 <= d <= s + 1):
+//           X_d = sum_t Q_t Q'_{d-t}^T, exact: int8 x int8 -> int32 on the
+//           INT8 MFMA (|X_d| <= s*k*64^2 < 2^31), or FP64 MFMA on integers.
+//  combine  P = sum_d X_d 2^-(2 w_1 + w (d-2)), added in dd (DWPlusFP) from the
+//           smallest weight up; P * 2^(sigma_i + tau_j); C = alpha*P + beta*C.
+// Binary64 arithmetic appears only in scaling, slicing and combining.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+
 #include "../../include/mpdd.h"
+#include "dd.hpp"
 #include "kernels.hpp"
+
+#pragma clang fp contract(off)
 
 namespace mpdd {
 
-int ozaki_gemm(const void*, bool, bool, int64_t, int64_t, int64_t, double, double, const double*,
-               const double*, int64_t, const double*, const double*, int64_t, double, double,
-               double*, double*, int64_t, hipStream_t) {
-  return MPDD_ERR_UNSUPPORTED;
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+// Tile geometry of the product kernels; slice buffers are padded to it.
+constexpr int OZ_BM = 128;      // rows of op(A) per workgroup tile
+constexpr int OZ_BN = 128;      // columns of op(B) per workgroup tile
+constexpr int OZ_KPAD = 64;     // k padding of the slice rows (bytes for INT8)
+
+// ---- scale -------------------------------------------------------------------------
+
+// Row operand element (r, l) lives at x[r*sr + l*sl].  Rows contiguous across
+// lanes (sr == 1): one thread per row walks l.
+__global__ void __launch_bounds__(256)
+oz_scale_rows_cols(const double* __restrict__ x, int64_t sr, int64_t sl, int64_t rows,
+                   int64_t k, int* __restrict__ exps) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= rows) return;
+  double mx = 0.0;
+  for (int64_t l = 0; l < k; ++l) mx = fmax(mx, fabs(x[r * sr + l * sl]));
+  int e = 0;
+  if (mx != 0.0) frexp(mx, &e);
+  exps[r] = e;
+}
+
+// Rows contiguous along l (sl == 1): one wave per row, lanes walk l.
+__global__ void __launch_bounds__(256)
+oz_scale_rows_wave(const double* __restrict__ x, int64_t sr, int64_t sl, int64_t rows,
+                   int64_t k, int* __restrict__ exps) {
+  const int lane = threadIdx.x & 63;
+  const int64_t r = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+  if (r >= rows) return;
+  double mx = 0.0;
+  for (int64_t l = lane; l < k; l += 64) mx = fmax(mx, fabs(x[r * sr + l * sl]));
+  for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off));
+  if (lane == 0) {
+    int e = 0;
+    if (mx != 0.0) frexp(mx, &e);
+    exps[r] = e;
+  }
+}
+
+// ---- slice -------------------------------------------------------------------------
+
+// One 64 x 64 block of the row operand per workgroup.  Elements are read with
+// lanes along whichever index is contiguous in memory, staged in LDS, then
+// each thread turns 16 consecutive l of one row into digits and writes them
+// k-contiguously (16 int8 = one 16-byte store per digit, or 16 doubles).
+// Rows >= rows and l >= k (padding) get zero digits.
+template <typename T>
+__global__ void __launch_bounds__(256)
+oz_slice(const double* __restrict__ xh, const double* __restrict__ xl, int64_t sr, int64_t sl,
+         int64_t rows, int64_t k, const int* __restrict__ exps, int nslices, int wfirst, int w,
+         T* __restrict__ q, int64_t ldq, int64_t plane) {
+  __shared__ double th[64][65];
+  __shared__ double tl[64][65];
+  const int tid = threadIdx.x;
+  const int64_t r0 = (int64_t)blockIdx.y * 64;
+  const int64_t l0 = (int64_t)blockIdx.x * 64;
+  const bool lanes_on_r = (sr == 1);
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    const int a = tid & 63, b = (tid >> 6) + 4 * e;
+    const int rr = lanes_on_r ? a : b;
+    const int ll = lanes_on_r ? b : a;
+    const int64_t r = r0 + rr, l = l0 + ll;
+    double h = 0.0, lo = 0.0;
+    if (r < rows && l < k) {
+      h = xh[r * sr + l * sl];
+      lo = xl[r * sr + l * sl];
+    }
+    th[rr][ll] = h;
+    tl[rr][ll] = lo;
+  }
+  __syncthreads();
+  const int rr = tid >> 2;
+  const int lb = (tid & 3) * 16;
+  const int64_t r = r0 + rr;
+  const int e = (r < rows) ? exps[r] : 0;
+  ddv y[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    y[i].hi = ldexp(th[rr][lb + i], -e);
+    y[i].lo = ldexp(tl[rr][lb + i], -e);
+  }
+  T* out = q + r * ldq + l0 + lb;
+  for (int t = 0; t < nslices; ++t) {
+    const int shift = (t == 0) ? wfirst : w;
+    T dig[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const double zh = ldexp(y[i].hi, shift), zl = ldexp(y[i].lo, shift);
+      const double qd = rint(zh);
+      dig[i] = (T)qd;
+      y[i] = two_sum(zh - qd, zl);
+    }
+    T* o = out + (int64_t)t * plane;
+    if constexpr (sizeof(T) == 1) {
+      v4i pack;
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+        pack[c] = (int)((uint32_t)(uint8_t)dig[4 * c] | ((uint32_t)(uint8_t)dig[4 * c + 1] << 8) |
+                        ((uint32_t)(uint8_t)dig[4 * c + 2] << 16) |
+                        ((uint32_t)(uint8_t)dig[4 * c + 3] << 24));
+      *(v4i*)o = pack;
+    } else {
+#pragma unroll
+      for (int i = 0; i < 16; ++i) o[i] = dig[i];
+    }
+  }
+}
+
+// Workgroup b -> (anti-diagonal d, C tile).  Groups of `tiles` workgroups
+// share one d, largest d (longest sum) first.  Inside a group the tile index
+// is remapped so that each of the 8 XCDs (workgroups are dealt to them
+// round-robin) receives a contiguous run of tiles, i.e. a few column panels of
+// op(B) that then stay in its L2.
+__device__ __forceinline__ void oz_tile_of(int b, int tiles, int nslices, int& d, int& tile) {
+  d = nslices + 1 - b / tiles;
+  int r = b % tiles;
+  if ((tiles & 7) == 0) r = (r & 7) * (tiles >> 3) + (r >> 3);
+  tile = r;
+}
+
+// ---- products: INT8 ---------------------------------------------------------------------
+
+// X_d tile (128 x 128) for anti-diagonal d: sum over t of Q_t(rows) Q'_{d-t}(cols)^T
+// with k-contiguous int8 rows.  256 threads = 4 waves in a 2 x 2 grid, each
+// wave 64 x 64 = 4 x 4 v_mfma_i32_16x16x64_i8 tiles.  A k-step stages a
+// 128 x 64-byte block of each operand in LDS (double buffered; rows padded to
+// 80 bytes so the 16-byte fragment reads of 16 consecutive rows spread over
+// the banks).  For an MFMA lane l supplies row (l % 16), bytes
+// 16*(l/16) .. +15 of the k-step for both operands, so every k pairs up.
+// Accumulation is exact in int32.  Workgroups enumerate (d, tile) with the
+// longest sums (largest d) first.
+constexpr int I8_BK = 64;
+constexpr int I8_PITCH = 80;
+
+__global__ void __launch_bounds__(256)
+oz_gemm_i8(const int8_t* __restrict__ qa, const int8_t* __restrict__ qb, int32_t* __restrict__ x,
+           int64_t kp, int64_t plane_a, int64_t plane_b, int64_t mp, int64_t np, int nslices,
+           int tiles_m, int tiles_n) {
+  __shared__ __attribute__((aligned(16))) int8_t As[2][OZ_BM * I8_PITCH];
+  __shared__ __attribute__((aligned(16))) int8_t Bs[2][OZ_BN * I8_PITCH];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = wave & 1, wn = wave >> 1;
+
+  int d, tile;
+  oz_tile_of(blockIdx.x, tiles_m * tiles_n, nslices, d, tile);
+  const int bi = tile % tiles_m, bj = tile / tiles_m;
+  const int64_t i0 = (int64_t)bi * OZ_BM, j0 = (int64_t)bj * OZ_BN;
+
+  v4i acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[a][c] = v4i{0, 0, 0, 0};
+
+  // staging: thread loads 16 bytes of rows (tid/4) and (tid/4 + 64), chunk tid%4
+  const int srow = tid >> 2, scol = (tid & 3) * 16;
+  const int64_t ksteps = kp / I8_BK;
+  const int64_t total = (int64_t)(d - 1) * ksteps;
+  v4i ra[2], rb[2];
+
+  auto gload = [&](int64_t s) {
+    const int t = 1 + (int)(s / ksteps);          // slice of op(A); op(B) slice d - t
+    const int64_t l0 = (s % ksteps) * I8_BK;
+    const int8_t* pa = qa + (int64_t)(t - 1) * plane_a + (i0 + srow) * kp + l0 + scol;
+    const int8_t* pb = qb + (int64_t)(d - t - 1) * plane_b + (j0 + srow) * kp + l0 + scol;
+    ra[0] = *(const v4i*)pa;
+    ra[1] = *(const v4i*)(pa + 64 * kp);
+    rb[0] = *(const v4i*)pb;
+    rb[1] = *(const v4i*)(pb + 64 * kp);
+  };
+  auto sstore = [&](int buf) {
+    *(v4i*)&As[buf][srow * I8_PITCH + scol] = ra[0];
+    *(v4i*)&As[buf][(srow + 64) * I8_PITCH + scol] = ra[1];
+    *(v4i*)&Bs[buf][srow * I8_PITCH + scol] = rb[0];
+    *(v4i*)&Bs[buf][(srow + 64) * I8_PITCH + scol] = rb[1];
+  };
+
+  gload(0);
+  sstore(0);
+  __syncthreads();
+  const int fr = lane & 15, fk = (lane >> 4) * 16;
+  for (int64_t s = 0; s < total; ++s) {
+    const int cur = (int)(s & 1);
+    if (s + 1 < total) gload(s + 1);
+    v4i af[4], bf[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+      af[a] = *(const v4i*)&As[cur][(wm * 64 + a * 16 + fr) * I8_PITCH + fk];
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+      bf[c] = *(const v4i*)&Bs[cur][(wn * 64 + c * 16 + fr) * I8_PITCH + fk];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+        acc[a][c] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af[a], bf[c], acc[a][c], 0, 0, 0);
+    if (s + 1 < total) sstore(cur ^ 1);
+    __syncthreads();
+  }
+
+  // C layout of a 16x16 MFMA tile: lane l holds rows 4*(l/16) + 0..3 of column l%16.
+  int32_t* xd = x + (int64_t)(d - 2) * mp * np;
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int64_t i = i0 + wm * 64 + a * 16 + (lane >> 4) * 4;
+      const int64_t j = j0 + wn * 64 + c * 16 + (lane & 15);
+      *(v4i*)&xd[j * mp + i] = acc[a][c];
+    }
+}
+
+// ---- products: FP64 ---------------------------------------------------------------------
+
+// Same tiling with v_mfma_f64_16x16x4_f64: a k-step stages 16 doubles per row;
+// lane l supplies row l % 16 at k-offset l / 16 of each 4-deep MFMA.  Digit
+// products and all their partial sums are integers below 2^53, so the FP64
+// accumulation is exact in any order.
+constexpr int F64_BK = 16;
+constexpr int F64_PITCH = 17;
+
+__global__ void __launch_bounds__(256)
+oz_gemm_f64(const double* __restrict__ qa, const double* __restrict__ qb, double* __restrict__ x,
+            int64_t kp, int64_t plane_a, int64_t plane_b, int64_t mp, int64_t np, int nslices,
+            int tiles_m, int tiles_n) {
+  __shared__ double As[2][OZ_BM * F64_PITCH];
+  __shared__ double Bs[2][OZ_BN * F64_PITCH];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = wave & 1, wn = wave >> 1;
+
+  int d, tile;
+  oz_tile_of(blockIdx.x, tiles_m * tiles_n, nslices, d, tile);
+  const int bi = tile % tiles_m, bj = tile / tiles_m;
+  const int64_t i0 = (int64_t)bi * OZ_BM, j0 = (int64_t)bj * OZ_BN;
+
+  v4d acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[a][c] = v4d{0.0, 0.0, 0.0, 0.0};
+
+  // staging: 128 rows x 16 doubles per operand = 2048 doubles; 8 per thread:
+  // thread handles row (tid / 2) and 8 consecutive k at (tid % 2) * 8.
+  const int srow = tid >> 1, scol = (tid & 1) * 8;
+  const int64_t ksteps = kp / F64_BK;
+  const int64_t total = (int64_t)(d - 1) * ksteps;
+  double ra[8], rb[8];
+
+  auto gload = [&](int64_t s) {
+    const int t = 1 + (int)(s / ksteps);
+    const int64_t l0 = (s % ksteps) * F64_BK;
+    const double* pa = qa + (int64_t)(t - 1) * plane_a + (i0 + srow) * kp + l0 + scol;
+    const double* pb = qb + (int64_t)(d - t - 1) * plane_b + (j0 + srow) * kp + l0 + scol;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) { ra[e] = pa[e]; rb[e] = pb[e]; }
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      As[buf][srow * F64_PITCH + scol + e] = ra[e];
+      Bs[buf][srow * F64_PITCH + scol + e] = rb[e];
+    }
+  };
+
+  gload(0);
+  sstore(0);
+  __syncthreads();
+  const int fr = lane & 15, fk = lane >> 4;
+  for (int64_t s = 0; s < total; ++s) {
+    const int cur = (int)(s & 1);
+    if (s + 1 < total) gload(s + 1);
+#pragma unroll
+    for (int kk = 0; kk < F64_BK; kk += 4) {
+      double af[4], bf[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) af[a] = As[cur][(wm * 64 + a * 16 + fr) * F64_PITCH + kk + fk];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) bf[c] = Bs[cur][(wn * 64 + c * 16 + fr) * F64_PITCH + kk + fk];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+          acc[a][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a], bf[c], acc[a][c], 0, 0, 0);
+    }
+    if (s + 1 < total) sstore(cur ^ 1);
+    __syncthreads();
+  }
+
+  double* xd = x + (int64_t)(d - 2) * mp * np;
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int64_t i = i0 + wm * 64 + a * 16 + (lane >> 4) * 4;
+      const int64_t j = j0 + wn * 64 + c * 16 + (lane & 15);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) xd[j * mp + i + e] = acc[a][c][e];
+    }
+}
+
+// ---- combine -------------------------------------------------------------------------
+
+template <typename XT>
+__global__ void __launch_bounds__(256)
+oz_combine(const XT* __restrict__ x, int64_t mp, int64_t np, int nslices, int wfirst, int w,
+           const int* __restrict__ ea, const int* __restrict__ eb, int64_t m, int64_t n,
+           double alpha_hi, double alpha_lo, double beta_hi, double beta_lo, int beta_zero,
+           double* __restrict__ c_hi, double* __restrict__ c_lo, int64_t ldc) {
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= m * n) return;
+  const int64_t i = gid % m, j = gid / m;
+  ddv p{0.0, 0.0};
+  for (int d = nslices + 1; d >= 2; --d) {
+    const double v = (double)x[(int64_t)(d - 2) * mp * np + j * mp + i];
+    p = dd_add_d(p, ldexp(v, -(2 * wfirst + w * (d - 2))));
+  }
+  const int e = ea[i] + eb[j];
+  p.hi = ldexp(p.hi, e);
+  p.lo = ldexp(p.lo, e);
+  ddv r = dd_mul(ddv{alpha_hi, alpha_lo}, p);
+  const int64_t ci = i + j * ldc;
+  if (!beta_zero) r = dd_add(r, dd_mul(ddv{beta_hi, beta_lo}, ddv{c_hi[ci], c_lo[ci]}));
+  c_hi[ci] = r.hi;
+  c_lo[ci] = r.lo;
+}
+
+// ---- host orchestration -------------------------------------------------------------
+
+static int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
+
+// Digit widths of a kind for k terms and nslices slices.
+static bool digit_widths(int algo, int64_t k, int nslices, int& wfirst, int& w) {
+  if (algo == MPDD_OZAKI_I8) {
+    wfirst = 6;
+    w = 7;
+    // |X_d| <= nslices * k * 64^2 must stay below 2^31
+    return (int64_t)nslices * k <= ((int64_t)1 << 19);
+  }
+  int64_t terms = std::max<int64_t>(1, (int64_t)nslices * k);
+  int lg = 0;
+  while (((int64_t)1 << lg) < terms) ++lg;
+  w = (55 - lg) / 2;
+  wfirst = w - 1;
+  return wfirst >= 1;
+}
+
+// Scale exponents + slices of one row operand (rows x k) into padded buffers.
+template <typename T>
+static hipError_t split_operand(const double* hi, const double* lo, int64_t sr, int64_t sl,
+                                int64_t rows, int64_t k, int* exps, T* q, int64_t ldq,
+                                int64_t rows_p, int nslices, int wfirst, int w, hipStream_t st) {
+  if (sl == 1)
+    hipLaunchKernelGGL(oz_scale_rows_wave, dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, st,
+                       hi, sr, sl, rows, k, exps);
+  else
+    hipLaunchKernelGGL(oz_scale_rows_cols, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0,
+                       st, hi, sr, sl, rows, k, exps);
+  dim3 grid((unsigned)(ldq / 64), (unsigned)(rows_p / 64));
+  hipLaunchKernelGGL(oz_slice<T>, grid, dim3(256), 0, st, hi, lo, sr, sl, rows, k, exps, nslices,
+                     wfirst, w, q, ldq, rows_p * ldq);
+  return hipGetLastError();
+}
+
+int ozaki_gemm(const void* opts_v, bool ta, bool tb, int64_t m, int64_t n, int64_t k,
+               double alpha_hi, double alpha_lo, const double* a_hi, const double* a_lo,
+               int64_t lda, const double* b_hi, const double* b_lo, int64_t ldb, double beta_hi,
+               double beta_lo, double* c_hi, double* c_lo, int64_t ldc, hipStream_t st) {
+  const mpdd_opts* opts = (const mpdd_opts*)opts_v;
+  const int algo = opts->algo;
+  const bool beta_zero = beta_hi == 0.0 && beta_lo == 0.0;
+  if ((alpha_hi == 0.0 && alpha_lo == 0.0) || k == 0) {
+    GemmParams p{};
+    p.m = m; p.n = n; p.k = k;
+    p.beta_hi = beta_hi; p.beta_lo = beta_lo;
+    p.c_hi = c_hi; p.c_lo = c_lo; p.ldc = ldc;
+    p.beta_zero = beta_zero;
+    return launch_scale(p, st) == hipSuccess ? 0 : MPDD_ERR_HIP;
+  }
+  int s = opts->nslices;
+  if (s == 0) s = (algo == MPDD_OZAKI_I8) ? 16 : 7;
+  if (s < 1 || s > 40) return MPDD_ERR_UNSUPPORTED;
+  int wfirst, w;
+  if (!digit_widths(algo, k, s, wfirst, w)) return MPDD_ERR_UNSUPPORTED;
+
+  const bool i8 = (algo == MPDD_OZAKI_I8);
+  const int64_t kp = round_up(k, OZ_KPAD);
+  const int64_t mp = round_up(m, OZ_BM), np = round_up(n, OZ_BN);
+  const size_t esz = i8 ? 1 : 8;
+  const size_t xsz = i8 ? 4 : 8;
+  const size_t qa_bytes = (size_t)s * mp * kp * esz;
+  const size_t qb_bytes = (size_t)s * np * kp * esz;
+  const size_t x_bytes = (size_t)s * mp * np * xsz;
+  const size_t e_bytes = round_up((m + n) * sizeof(int), 256);
+  const size_t total = round_up(qa_bytes, 256) + round_up(qb_bytes, 256) + x_bytes + e_bytes;
+  void* ws = nullptr;
+  if (hipMallocAsync(&ws, total, st) != hipSuccess) return MPDD_ERR_ALLOC;
+  char* base = (char*)ws;
+  void* qa = base;
+  void* qb = base + round_up(qa_bytes, 256);
+  void* x = base + round_up(qa_bytes, 256) + round_up(qb_bytes, 256);
+  int* ea = (int*)((char*)x + x_bytes);
+  int* eb = ea + m;
+
+  // row operand of A: op(A)(i, l); of B: op(B)(l, j) as element (j, l)
+  const int64_t a_sr = ta ? lda : 1, a_sl = ta ? 1 : lda;
+  const int64_t b_sr = tb ? 1 : ldb, b_sl = tb ? ldb : 1;
+  hipError_t e;
+  if (i8) {
+    e = split_operand<int8_t>(a_hi, a_lo, a_sr, a_sl, m, k, ea, (int8_t*)qa, kp, mp, s, wfirst, w,
+                              st);
+    if (e == hipSuccess)
+      e = split_operand<int8_t>(b_hi, b_lo, b_sr, b_sl, n, k, eb, (int8_t*)qb, kp, np, s, wfirst,
+                                w, st);
+  } else {
+    e = split_operand<double>(a_hi, a_lo, a_sr, a_sl, m, k, ea, (double*)qa, kp, mp, s, wfirst, w,
+                              st);
+    if (e == hipSuccess)
+      e = split_operand<double>(b_hi, b_lo, b_sr, b_sl, n, k, eb, (double*)qb, kp, np, s, wfirst,
+                                w, st);
+  }
+  const int tiles_m = (int)(mp / OZ_BM), tiles_n = (int)(np / OZ_BN);
+  const unsigned nblocks = (unsigned)(tiles_m * tiles_n * s);
+  if (e == hipSuccess) {
+    if (i8)
+      hipLaunchKernelGGL(oz_gemm_i8, dim3(nblocks), dim3(256), 0, st, (const int8_t*)qa,
+                         (const int8_t*)qb, (int32_t*)x, kp, mp * kp, np * kp, mp, np, s, tiles_m,
+                         tiles_n);
+    else
+      hipLaunchKernelGGL(oz_gemm_f64, dim3(nblocks), dim3(256), 0, st, (const double*)qa,
+                         (const double*)qb, (double*)x, kp, mp * kp, np * kp, mp, np, s, tiles_m,
+                         tiles_n);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) {
+    const unsigned cb = (unsigned)((m * n + 255) / 256);
+    if (i8)
+      hipLaunchKernelGGL(oz_combine<int32_t>, dim3(cb), dim3(256), 0, st, (const int32_t*)x, mp,
+                         np, s, wfirst, w, ea, eb, m, n, alpha_hi, alpha_lo, beta_hi, beta_lo,
+                         (int)beta_zero, c_hi, c_lo, ldc);
+    else
+      hipLaunchKernelGGL(oz_combine<double>, dim3(cb), dim3(256), 0, st, (const double*)x, mp, np,
+                         s, wfirst, w, ea, eb, m, n, alpha_hi, alpha_lo, beta_hi, beta_lo,
+                         (int)beta_zero, c_hi, c_lo, ldc);
+    e = hipGetLastError();
+  }
+  hipError_t ef = hipFreeAsync(ws, st);
+  if (e != hipSuccess) return MPDD_ERR_HIP;
+  return ef == hipSuccess ? 0 : MPDD_ERR_HIP;
+}
+
+// Exposed building block: scale exponents and digit slices of op(X).
+int ozaki_split_entry(int algo, bool trans, int64_t rows, int64_t k, const double* hi,
+                      const double* lo, int64_t ld, int nslices, int wfirst, int w, int* exps,
+                      void* slices, int64_t ldq, int64_t rows_p, hipStream_t st) {
+  const int64_t sr = trans ? ld : 1, sl = trans ? 1 : ld;
+  hipError_t e;
+  if (algo == MPDD_OZAKI_I8)
+    e = split_operand<int8_t>(hi, lo, sr, sl, rows, k, exps, (int8_t*)slices, ldq, rows_p,
+                              nslices, wfirst, w, st);
+  else
+    e = split_operand<double>(hi, lo, sr, sl, rows, k, exps, (double*)slices, ldq, rows_p, nslices,
+                              wfirst, w, st);
+  return e == hipSuccess ? 0 : MPDD_ERR_HIP;
+}
+
+int ozaki_digit_widths(int algo, int64_t k, int nslices, int* wfirst, int* w) {
+  int a, b;
+  if (!digit_widths(algo, k, nslices, a, b)) return MPDD_ERR_UNSUPPORTED;
+  *wfirst = a;
+  *w = b;
+  return 0;
 }
 
 }  // namespace mpdd

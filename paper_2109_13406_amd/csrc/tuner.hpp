@@ -35,3 +35,10 @@ class TuneTable {
 int default_tile(int64_t m, int64_t n, int64_t k, bool square_only);
 
 }  // namespace mpdd
+
+struct mpdd_handle_s;
+// Handle accessors for other translation units (mpdd.cpp owns the struct).
+bool handle_valid(const mpdd_handle_s* h);
+int handle_device(const mpdd_handle_s* h);
+bool handle_tune_lookup(const mpdd_handle_s* h, int op, bool ta, bool tb, int64_t m, int64_t n,
+                        int64_t k, mpdd::TuneEntry& out);

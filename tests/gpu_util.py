@@ -118,3 +118,95 @@ def sample_indices(m, n, count, seed, tri=None):
         sw = ii < jj
         ii[sw], jj[sw] = jj[sw].copy(), ii[sw].copy()
     return ii, jj
+
+
+# ---- full-size cases checked on sampled entries --------------------------------------
+
+def _gather_rows_opA(Ah, ld, trans, ii, k):
+    """Host array (k, s) with [l, t] = op(A)(ii[t], l) for a device plane."""
+    import torch
+    idx = torch.as_tensor(ii, device=Ah.device)
+    if not trans:                       # A[i + l*ld]
+        v = Ah[: ld * k].view(k, ld)[:, idx]
+    else:                               # A[l + i*ld]
+        rows = int(ii.max()) + 1
+        v = Ah[: ld * rows].view(rows, ld)[idx, :k].T
+    return v.contiguous().cpu().numpy()
+
+
+def _gather_cols_opB(Bh, ld, trans, jj, k):
+    """Host array (s, k) with [t, l] = op(B)(l, jj[t])."""
+    import torch
+    idx = torch.as_tensor(jj, device=Bh.device)
+    if not trans:                       # B[l + j*ld]
+        cols = int(jj.max()) + 1
+        v = Bh[: ld * cols].view(cols, ld)[idx, :k]
+    else:                               # B[j + l*ld]
+        v = Bh[: ld * k].view(k, ld)[:, idx].T
+    return v.contiguous().cpu().numpy()
+
+
+def sampled_oracle(transa, transb, k, alpha, A, lda, B, ldb, beta, cin, ii, jj):
+    """Oracle values of the sampled entries (ii[t], jj[t]) of an update whose
+    operands live on the device; cin = (hi, lo) host values of C at those
+    entries before the update."""
+    s = len(ii)
+    ta, tb = transa.upper() != "N", transb.upper() != "N"
+    As = tuple(np.ascontiguousarray(_gather_rows_opA(x, lda, ta, ii, k)).ravel() for x in A)
+    Bs = tuple(np.ascontiguousarray(_gather_cols_opB(x, ldb, tb, jj, k)).ravel() for x in B)
+    Cs = (np.zeros(s * s), np.zeros(s * s))
+    d = np.arange(s)
+    Cs[0][d + d * s] = cin[0]
+    Cs[1][d + d * s] = cin[1]
+    return oracle.rgemm_entries("N", "N", s, s, k, alpha, As, s, Bs, k, beta, Cs, s, d, d)
+
+
+def gather(pair, flat_idx):
+    import torch
+    idx = torch.as_tensor(flat_idx, device=pair[0].device)
+    return tuple(p[idx].cpu().numpy() for p in pair)
+
+
+def sampled_gemm_check(h, name, case, opts=None, count=192, seed=0):
+    """Run a device-resident Rgemm case and compare sampled entries with the
+    oracle.  Returns the ratio over the sample."""
+    from paper_2109_13406_amd import binding as b
+    import torch
+    m, n, k, ldc = case["m"], case["n"], case["k"], case["ldc"]
+    ii, jj = sample_indices(m, n, count, seed)
+    flat = ii + jj * ldc
+    cin = gather(case["C"], flat)
+    args = (case["transa"], case["transb"], m, n, k, case["alpha"], case["A"], case["lda"],
+            case["B"], case["ldb"], case["beta"], case["C"], ldc)
+    info = b.mpdd_Rgemm(h, *args) if opts is None else b.mpdd_Rgemm_ex(h, opts, *args)
+    assert info == 0, info
+    torch.cuda.synchronize()
+    got = gather(case["C"], flat)
+    ref = sampled_oracle(case["transa"], case["transb"], k, case["alpha"], case["A"],
+                         case["lda"], case["B"], case["ldb"], case["beta"], cin, ii, jj)
+    r = ratio(got[0], got[1], ref[0], ref[1], k)
+    log(f"PARITY {name} sampled({len(ii)}) ratio={r:.3g}")
+    return r
+
+
+def sampled_syrk_check(h, name, case, opts=None, count=192, seed=0):
+    from paper_2109_13406_amd import binding as b
+    import torch
+    n, k, ldc, uplo = case["n"], case["k"], case["ldc"], case["uplo"]
+    ii, jj = sample_indices(n, n, count, seed, tri=uplo)
+    flat = ii + jj * ldc
+    cin = gather(case["C"], flat)
+    if case["beta"] == (0.0, 0.0):
+        cin = (np.zeros(len(ii)), np.zeros(len(ii)))
+    args = (uplo, case["trans"], n, k, case["alpha"], case["A"], case["lda"], case["beta"],
+            case["C"], ldc)
+    info = b.mpdd_Rsyrk(h, *args) if opts is None else b.mpdd_Rsyrk_ex(h, opts, *args)
+    assert info == 0, info
+    torch.cuda.synchronize()
+    got = gather(case["C"], flat)
+    tr = case["trans"].upper()
+    ref = sampled_oracle(tr, "T" if tr == "N" else "N", k, case["alpha"], case["A"],
+                         case["lda"], case["A"], case["lda"], case["beta"], cin, ii, jj)
+    r = ratio(got[0], got[1], ref[0], ref[1], k)
+    log(f"PARITY {name} sampled({len(ii)}) ratio={r:.3g}")
+    return r

@@ -1,0 +1,150 @@
+"""GPU parity of the split (Ozaki) form through the C ABI.
+
+* Slices: scale exponents and every digit bit-identical to the oracle's
+  split, padding digits zero (INT8 and FP64 digit widths).
+* Products + combine: the split-form Rgemm is bit-identical to the oracle's
+  split-form evaluation with the same slice count (the slice products are
+  exact integers and the combine runs the same dd steps in the same order).
+* Accuracy: with enough slices the result is within 8 k 2^-104 of the plain
+  dd oracle, for the uniform and the wide (2^+-20 exponent) input sets; the
+  full-size cases search the slice count upward until that holds.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from gpu_util import compare_full, dev, gemm_gpu, gemm_oracle, log, sampled_gemm_check
+from oracle.compare import RATIO_MAX, bits
+
+pytestmark = pytest.mark.gpu
+
+KINDS = {"i8": 1, "f64": 2}
+
+
+@pytest.fixture(scope="module")
+def h():
+    import torch
+    from paper_2109_13406_amd import binding as b
+    handle = b.mpdd_create()
+    yield handle
+    torch.cuda.synchronize()
+    b.mpdd_destroy(handle)
+
+
+def _widths(kind, k, s):
+    return oracle.INT8_DIGITS if kind == "i8" else oracle.fp64_digit_width(k, s)
+
+
+@pytest.mark.parametrize("kind", ["i8", "f64"])
+@pytest.mark.parametrize("trans", ["N", "T"])
+@pytest.mark.parametrize("dist", ["uniform", "wide"])
+def test_slices_bit_identical(h, kind, trans, dist):
+    import torch
+    from paper_2109_13406_amd import binding as b
+    algo = KINDS[kind]
+    for (rows, k, s) in [(70, 90, 16), (1, 1, 3), (130, 200, 9)]:
+        rng = W.streams(11 + rows)[0]
+        nr, nc = (rows, k) if trans == "N" else (k, rows)
+        ld = W.ld_padded(nr)
+        X = W.dd_matrix(rng, nr, nc, ld, dist=dist)
+        sr, sl = (1, ld) if trans == "N" else (ld, 1)
+        wf, w = _widths(kind, k, s)
+        assert b.mpdd_ozaki_digit_widths(algo, k, s) == (wf, w)
+        e_o, q_o = oracle.ozaki_split(rows, k, X, sr, sl, s, wf, w)
+        ldq = 64 * ((k + 63) // 64)
+        rows_p = 64 * ((rows + 63) // 64)
+        exps = torch.zeros(rows, dtype=torch.int32, device="cuda")
+        dt = torch.int8 if kind == "i8" else torch.float64
+        q = torch.full((s, rows_p, ldq), 7, dtype=dt, device="cuda")
+        info = b.mpdd_ozaki_split(h, algo, trans, rows, k, dev(X), ld, s, exps, q, ldq, rows_p)
+        assert info == 0
+        torch.cuda.synchronize()
+        assert np.array_equal(exps.cpu().numpy(), e_o)
+        qg = q.cpu().numpy().astype(np.int64) if kind == "i8" else q.cpu().numpy()
+        assert np.array_equal(qg[:, :rows, :k], q_o.astype(qg.dtype)), (kind, trans, rows, k)
+        assert not qg[:, rows:, :].any() and not qg[:, :, k:].any()
+    log(f"PARITY ozaki slices {kind} {trans} {dist} bit-identical")
+
+
+SHAPES = [(1, 1, 1), (70, 90, 33), (129, 130, 200), (200, 64, 65)]
+
+
+@pytest.mark.parametrize("kind", ["i8", "f64"])
+@pytest.mark.parametrize("op", W.OPS)
+def test_split_gemm_bit_identical_to_split_oracle(h, kind, op):
+    algo = KINDS[kind]
+    for (m, n, k) in SHAPES:
+        for dist in ("uniform", "wide"):
+            s = 9 if kind == "i8" else 4
+            case = W.gemm_case(60 + m + k, op[0], op[1], m, n, k, dist=dist)
+            wf, w = _widths(kind, k, s)
+            O = (case["C"][0].copy(), case["C"][1].copy())
+            assert oracle.ozaki_rgemm(op[0], op[1], m, n, k, case["alpha"], case["A"], case["lda"],
+                                      case["B"], case["ldb"], case["beta"], O, case["ldc"], s, wf,
+                                      w) == 0
+            info, G = gemm_gpu(h, case, opts=dict(algo=algo, nslices=s))
+            assert info == 0
+            assert np.array_equal(bits(G[0]), bits(O[0])), (kind, op, m, n, k, dist)
+            assert np.array_equal(bits(G[1]), bits(O[1])), (kind, op, m, n, k, dist)
+    log(f"PARITY ozaki {kind} {op} bit-identical to the split oracle")
+
+
+@pytest.mark.parametrize("kind", ["i8", "f64"])
+@pytest.mark.parametrize("dist", ["uniform", "wide"])
+def test_split_gemm_reaches_dd_accuracy(h, kind, dist):
+    algo = KINDS[kind]
+    m, n, k = 150, 140, 300
+    case = W.gemm_case(70, "N", "T", m, n, k, dist=dist)
+    O = gemm_oracle(case)
+    s = {("i8", "uniform"): 16, ("i8", "wide"): 22, ("f64", "uniform"): 7,
+         ("f64", "wide"): 9}[(kind, dist)]
+    info, G = gemm_gpu(h, case, opts=dict(algo=algo, nslices=s))
+    assert info == 0
+    r = compare_full(f"ozaki {kind} {dist} s={s} NT {m}x{n}x{k}", G, O, m, n, k, case["ldc"],
+                     C0=case["C"])
+    assert r <= RATIO_MAX
+
+
+def test_split_semantics(h):
+    """beta = 0 with NaN C, alpha = 0, and an unsupported slice count."""
+    from paper_2109_13406_amd import binding as b
+    case = W.gemm_case(71, "T", "N", 40, 30, 50, beta_zero=True, c_nan=True)
+    O = gemm_oracle(case)
+    info, G = gemm_gpu(h, case, opts=dict(algo=b.MPDD_OZAKI_I8, nslices=16))
+    assert info == 0
+    assert compare_full("ozaki beta0", G, O, 40, 30, 50, case["ldc"], C0=case["C"]) <= RATIO_MAX
+    case = W.gemm_case(72, "N", "N", 20, 20, 20)
+    case["alpha"] = (0.0, 0.0)
+    O = gemm_oracle(case)
+    info, G = gemm_gpu(h, case, opts=dict(algo=b.MPDD_OZAKI_F64))
+    assert info == 0
+    assert np.array_equal(bits(G[0]), bits(O[0]))
+    info, _ = gemm_gpu(h, W.gemm_case(73, "N", "N", 8, 8, 8),
+                       opts=dict(algo=b.MPDD_OZAKI_I8, nslices=41))
+    assert info == b.MPDD_ERR_UNSUPPORTED
+
+
+def slice_search(h, kind, n, dist, start, stop):
+    """Smallest slice count whose sampled ratio vs the dd oracle is <= 8."""
+    algo = KINDS[kind]
+    for s in range(start, stop + 1):
+        case = W.gemm_case_device(W.BASE_SEED + 3 + n + s, "N", "N", n, n, n, dist=dist)
+        r = sampled_gemm_check(h, f"config3 ozaki {kind} n={n} {dist} s={s}", case,
+                               opts=dict(algo=algo, nslices=s), count=96, seed=s)
+        del case
+        if r <= RATIO_MAX:
+            return s, r
+    return None, None
+
+
+@pytest.mark.parametrize("n", [2048, 8192])
+@pytest.mark.parametrize("kind", ["i8", "f64"])
+@pytest.mark.parametrize("dist", ["uniform", "wide"])
+def test_config3_slice_count_search(h, n, kind, dist):
+    import torch
+    start, stop = {"i8": (14, 24), "f64": (5, 10)}[kind]
+    s, r = slice_search(h, kind, n, dist, start, stop)
+    torch.cuda.empty_cache()
+    log(f"CONFIG3 {kind} n={n} {dist}: slices={s} ratio={r}")
+    assert s is not None

@@ -197,3 +197,98 @@ def request_stream(seed, count, rate, lo=32, hi=2048, gemm_frac=0.7):
             out.append(dict(kind="syrk", uplo="UL"[flags[t, 0]], trans="NT"[flags[t, 1]],
                             n=n, k=k, arrival=float(arrivals[t]), seed=seed * 100003 + t))
     return out
+
+
+# ---- the same recipes generated on the device (torch) ------------------------------
+#
+# Large cases (8192^2 planes are 0.5 GB each) are drawn on the GPU with a
+# seeded torch.Generator; the distribution recipe is the one above, the random
+# stream is torch's (so values differ from the numpy ones for the same seed).
+
+def dd_matrix_device(seed, rows, cols, ld=None, dist="uniform", device="cuda", pad=True):
+    """Column-major dd matrix on the device: (hi, lo) flat float64 tensors of
+    length ld*cols; padding rows hold the NaN sentinel."""
+    import torch
+    ld = rows if ld is None else ld
+    assert ld >= max(1, rows)
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    f64 = torch.float64
+    size = max(1, ld * cols)
+    hi = torch.full((size,), float(SENTINEL_HI) if pad else 0.0, dtype=f64, device=device)
+    lo = torch.full((size,), float(SENTINEL_LO) if pad else 0.0, dtype=f64, device=device)
+    if pad:   # exact sentinel payloads (a float() round trip may quiet them differently)
+        hi.view(torch.int64).fill_(int(np.array([SENTINEL_HI]).view(np.int64)[0]))
+        lo.view(torch.int64).fill_(int(np.array([SENTINEL_LO]).view(np.int64)[0]))
+    if rows * cols == 0:
+        return hi, lo
+    shape = (cols, rows)
+    if dist == "uniform":
+        h = torch.rand(shape, generator=g, dtype=f64, device=device) * 2.0 - 1.0
+    elif dist == "wide":
+        mant = torch.rand(shape, generator=g, dtype=f64, device=device) + 1.0
+        e = torch.randint(-20, 21, shape, generator=g, device=device)
+        sign = torch.randint(0, 2, shape, generator=g, device=device).to(f64) * 2.0 - 1.0
+        h = sign * torch.ldexp(mant, e.to(f64))
+    else:
+        raise ValueError(dist)
+    l = h * 2.0 ** -53 * (torch.rand(shape, generator=g, dtype=f64, device=device) * 2.0 - 1.0)
+    s = h + l
+    l = l - (s - h)
+    hi[: ld * cols].view(cols, ld)[:, :rows] = s
+    lo[: ld * cols].view(cols, ld)[:, :rows] = l
+    return hi, lo
+
+
+def gemm_case_device(seed, transa, transb, m, n, k, dist="uniform", padded=True,
+                     beta_zero=False, c_nan=False, device="cuda"):
+    """Device version of gemm_case (scalars from the numpy streams)."""
+    _, _, _, ral, rbe = streams(seed)
+    nra = m if transa.upper() == "N" else k
+    nca = k if transa.upper() == "N" else m
+    nrb = k if transb.upper() == "N" else n
+    ncb = n if transb.upper() == "N" else k
+    lda = ld_padded(nra) if padded else max(1, nra)
+    ldb = ld_padded(nrb) if padded else max(1, nrb)
+    ldc = ld_padded(m) if padded else max(1, m)
+    A = dd_matrix_device(seed * 8 + 1, nra, nca, lda, dist, device)
+    B = dd_matrix_device(seed * 8 + 2, nrb, ncb, ldb, dist, device)
+    if c_nan:
+        C = dd_matrix_device(seed * 8 + 3, 0, 0, 1, dist, device)
+        C = tuple(x.repeat(ldc * n) for x in C)
+    else:
+        C = dd_matrix_device(seed * 8 + 3, m, n, ldc, dist, device)
+    alpha = dd_scalar(ral, "uniform")
+    beta = (0.0, 0.0) if beta_zero else dd_scalar(rbe, "uniform")
+    return dict(transa=transa, transb=transb, m=m, n=n, k=k, A=A, lda=lda, B=B, ldb=ldb,
+                C=C, ldc=ldc, alpha=alpha, beta=beta)
+
+
+def syrk_case_device(seed, uplo, trans, n, k, dist="uniform", padded=True, beta_zero=False,
+                     device="cuda"):
+    """Device version of syrk_case: opposite triangle (or all of C when
+    beta = 0) filled with the NaN sentinel."""
+    import torch
+    _, _, _, ral, rbe = streams(seed)
+    nra = n if trans.upper() == "N" else k
+    nca = k if trans.upper() == "N" else n
+    lda = ld_padded(nra) if padded else max(1, nra)
+    ldc = ld_padded(n) if padded else max(1, n)
+    A = dd_matrix_device(seed * 8 + 1, nra, nca, lda, dist, device)
+    C = dd_matrix_device(seed * 8 + 3, n, n, ldc, dist, device)
+    sh = int(np.array([SENTINEL_HI]).view(np.int64)[0])
+    sl = int(np.array([SENTINEL_LO]).view(np.int64)[0])
+    if beta_zero:
+        C[0].view(torch.int64).fill_(sh)
+        C[1].view(torch.int64).fill_(sl)
+    elif n:
+        i = torch.arange(n, device=device)
+        opp = (i[:, None] > i[None, :]) if uplo.upper() == "U" else (i[:, None] < i[None, :])
+        # element (i, j) at [j*ldc + i]: view columns as rows of a (n, ldc) array
+        for plane, val in ((C[0], sh), (C[1], sl)):
+            v = plane.view(torch.int64)[: n * ldc].view(n, ldc)[:, :n]
+            v.masked_fill_(opp.T, val)
+    alpha = dd_scalar(ral, "uniform")
+    beta = (0.0, 0.0) if beta_zero else dd_scalar(rbe, "uniform")
+    return dict(uplo=uplo, trans=trans, n=n, k=k, A=A, lda=lda, C=C, ldc=ldc, alpha=alpha,
+                beta=beta)
