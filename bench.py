@@ -257,6 +257,9 @@ def main():
     ap.add_argument("--n", type=int, default=8192)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--sections", default="plain,syrk,ozaki,serve")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
+                    help="first run one device-to-device copy of BYTES bytes (a kernel of known "
+                         "traffic, to calibrate the HBM byte counters of a profiling pass)")
     ap.add_argument("--serve-count", type=int, default=10000)
     ap.add_argument("--serve-count-slow", type=int, default=1000)
     args = ap.parse_args()
@@ -273,6 +276,15 @@ def main():
     h = b.mpdd_create()
     sections = set(args.sections.split(","))
     n = args.n
+    if args.copy_probe:
+        src = torch.empty(args.copy_probe // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy probe: {args.copy_probe} bytes")
+        del src, dst
+        torch.cuda.empty_cache()
 
     case, total, per = bench_plain(h, args, stream)
     t_step = total / args.steps

@@ -273,10 +273,12 @@ dd_gemm_kernel(GemmParams p) {
 // from the device header, so one captured launch serves every group.
 template <int BM, int BN, int BK, int RM, int RN>
 __global__ void __launch_bounds__((BM / RM) * (BN / RN))
-dd_grouped_kernel(const ServeReq* __restrict__ reqs, const ServeItem* __restrict__ items,
-                  const int* __restrict__ counts, int which) {
+dd_grouped_kernel(const char* __restrict__ base, const ServeReq* __restrict__ reqs,
+                  const int* __restrict__ counts, const int* __restrict__ items_offset,
+                  int which) {
   __shared__ DDTileSmem<BM, BN, BK> sm;
-  // the item lists of the tile shapes follow each other in `items`
+  // the item lists of the tile shapes follow each other after the requests
+  const ServeItem* items = (const ServeItem*)(base + *items_offset);
   int first = 0;
   for (int c = 0; c < which; ++c) first += counts[c];
   const int n = counts[which];
@@ -415,13 +417,15 @@ hipError_t launch_gemm(int tile, const GemmParams& p, bool ta, bool tb, bool acc
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_grouped_list(int tile, const ServeReq* reqs, const ServeItem* items,
-                               const int* counts, int which, int grid, hipStream_t st) {
+hipError_t launch_grouped_list(int tile, const char* base, const ServeReq* reqs,
+                               const int* counts, const int* items_offset, int which, int grid,
+                               hipStream_t st) {
   switch (tile) {
-#define X(id, bm, bn, bk, rm, rn)                                                              \
-  case id:                                                                                     \
-    hipLaunchKernelGGL((dd_grouped_kernel<bm, bn, bk, rm, rn>), dim3(grid),                    \
-                       dim3((bm / rm) * (bn / rn)), 0, st, reqs, items, counts, which);        \
+#define X(id, bm, bn, bk, rm, rn)                                                               \
+  case id:                                                                                      \
+    hipLaunchKernelGGL((dd_grouped_kernel<bm, bn, bk, rm, rn>), dim3(grid),                     \
+                       dim3((bm / rm) * (bn / rn)), 0, st, base, reqs, counts, items_offset,    \
+                       which);                                                                  \
     return hipGetLastError();
     MPDD_TILES(X)
 #undef X

@@ -49,9 +49,12 @@ hipError_t launch_gemm(int tile, const GemmParams& p, bool ta, bool tb, bool acc
                        int splitk, hipStream_t st);
 hipError_t launch_splitk_reduce(const GemmParams& p, int splitk, hipStream_t st);
 // Persistent grouped kernel over the `which`-th item list: counts[c] items per
-// tile shape, lists stored back to back (counts are read on the device).
-hipError_t launch_grouped_list(int tile, const ServeReq* reqs, const ServeItem* items,
-                               const int* counts, int which, int grid, hipStream_t st);
+// tile shape, lists stored back to back starting at base + *items_offset
+// (counts and offset are read on the device, so a captured launch serves
+// every group).
+hipError_t launch_grouped_list(int tile, const char* base, const ServeReq* reqs,
+                               const int* counts, const int* items_offset, int which, int grid,
+                               hipStream_t st);
 hipError_t launch_scale(const GemmParams& p, hipStream_t st);
 
 }  // namespace mpdd

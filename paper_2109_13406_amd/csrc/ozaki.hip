@@ -42,14 +42,39 @@ constexpr int OZ_KPAD = 64;     // k padding of the slice rows (bytes for INT8)
 // ---- scale -------------------------------------------------------------------------
 
 // Row operand element (r, l) lives at x[r*sr + l*sl].  Rows contiguous across
-// lanes (sr == 1): one thread per row walks l.
+// lanes (sr == 1): a workgroup takes 64 rows x one chunk of OZ_SCALE_CHUNK
+// columns; lane r%64 of wave w reads columns w, w+4, ... of the chunk (each
+// wave load is 64 consecutive doubles), the 4 waves' maxima meet in LDS, and
+// the chunk maximum goes to part[chunk][row].  oz_scale_finish reduces the
+// chunks and takes the frexp exponent.
+constexpr int OZ_SCALE_CHUNK = 512;
+
 __global__ void __launch_bounds__(256)
-oz_scale_rows_cols(const double* __restrict__ x, int64_t sr, int64_t sl, int64_t rows,
-                   int64_t k, int* __restrict__ exps) {
+oz_scale_part_cols(const double* __restrict__ x, int64_t sr, int64_t sl, int64_t rows,
+                   int64_t k, double* __restrict__ part) {
+  __shared__ double red[4][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t r = (int64_t)blockIdx.x * 64 + lane;
+  const int64_t l0 = (int64_t)blockIdx.y * OZ_SCALE_CHUNK;
+  const int64_t l1 = (l0 + OZ_SCALE_CHUNK < k) ? l0 + OZ_SCALE_CHUNK : k;
+  double mx = 0.0;
+  if (r < rows)
+    for (int64_t l = l0 + wave; l < l1; l += 4) mx = fmax(mx, fabs(x[r * sr + l * sl]));
+  red[wave][lane] = mx;
+  __syncthreads();
+  if (wave == 0 && r < rows) {
+    mx = fmax(fmax(red[0][lane], red[1][lane]), fmax(red[2][lane], red[3][lane]));
+    part[(int64_t)blockIdx.y * rows + r] = mx;
+  }
+}
+
+__global__ void __launch_bounds__(256)
+oz_scale_finish(const double* __restrict__ part, int64_t rows, int nchunks,
+                int* __restrict__ exps) {
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= rows) return;
   double mx = 0.0;
-  for (int64_t l = 0; l < k; ++l) mx = fmax(mx, fabs(x[r * sr + l * sl]));
+  for (int c = 0; c < nchunks; ++c) mx = fmax(mx, part[(int64_t)c * rows + r]);
   int e = 0;
   if (mx != 0.0) frexp(mx, &e);
   exps[r] = e;
@@ -326,15 +351,17 @@ oz_gemm_f64(const double* __restrict__ qa, const double* __restrict__ qb, double
     __syncthreads();
   }
 
+  // C layout of the FP64 16x16 MFMA tile: lane l, register e holds row
+  // 4*e + l/16 of column l%16 (unlike the INT8 form's 4*(l/16) + e).
   double* xd = x + (int64_t)(d - 2) * mp * np;
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
-      const int64_t i = i0 + wm * 64 + a * 16 + (lane >> 4) * 4;
+      const int64_t i = i0 + wm * 64 + a * 16 + (lane >> 4);
       const int64_t j = j0 + wn * 64 + c * 16 + (lane & 15);
 #pragma unroll
-      for (int e = 0; e < 4; ++e) xd[j * mp + i + e] = acc[a][c][e];
+      for (int e = 0; e < 4; ++e) xd[j * mp + i + 4 * e] = acc[a][c][e];
     }
 }
 
@@ -385,20 +412,32 @@ static bool digit_widths(int algo, int64_t k, int nslices, int& wfirst, int& w) 
 }
 
 // Scale exponents + slices of one row operand (rows x k) into padded buffers.
+// `part` is scratch for the chunked maxima (rows * ceil(k / OZ_SCALE_CHUNK)
+// doubles, only used when the rows are contiguous across lanes).
 template <typename T>
 static hipError_t split_operand(const double* hi, const double* lo, int64_t sr, int64_t sl,
                                 int64_t rows, int64_t k, int* exps, T* q, int64_t ldq,
-                                int64_t rows_p, int nslices, int wfirst, int w, hipStream_t st) {
-  if (sl == 1)
+                                int64_t rows_p, int nslices, int wfirst, int w, double* part,
+                                hipStream_t st) {
+  if (sl == 1 || k == 0) {
     hipLaunchKernelGGL(oz_scale_rows_wave, dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, st,
                        hi, sr, sl, rows, k, exps);
-  else
-    hipLaunchKernelGGL(oz_scale_rows_cols, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0,
-                       st, hi, sr, sl, rows, k, exps);
+  } else {
+    const int nchunks = (int)((k + OZ_SCALE_CHUNK - 1) / OZ_SCALE_CHUNK);
+    hipLaunchKernelGGL(oz_scale_part_cols, dim3((unsigned)((rows + 63) / 64), nchunks), dim3(256),
+                       0, st, hi, sr, sl, rows, k, part);
+    hipLaunchKernelGGL(oz_scale_finish, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, st,
+                       part, rows, nchunks, exps);
+  }
   dim3 grid((unsigned)(ldq / 64), (unsigned)(rows_p / 64));
   hipLaunchKernelGGL(oz_slice<T>, grid, dim3(256), 0, st, hi, lo, sr, sl, rows, k, exps, nslices,
                      wfirst, w, q, ldq, rows_p * ldq);
   return hipGetLastError();
+}
+
+static size_t part_bytes(int64_t rows, int64_t k) {
+  const int64_t nchunks = (k + OZ_SCALE_CHUNK - 1) / OZ_SCALE_CHUNK;
+  return (size_t)((rows * std::max<int64_t>(nchunks, 1) * 8 + 255) / 256 * 256);
 }
 
 int ozaki_gemm(const void* opts_v, bool ta, bool tb, int64_t m, int64_t n, int64_t k,
@@ -431,7 +470,9 @@ int ozaki_gemm(const void* opts_v, bool ta, bool tb, int64_t m, int64_t n, int64
   const size_t qb_bytes = (size_t)s * np * kp * esz;
   const size_t x_bytes = (size_t)s * mp * np * xsz;
   const size_t e_bytes = round_up((m + n) * sizeof(int), 256);
-  const size_t total = round_up(qa_bytes, 256) + round_up(qb_bytes, 256) + x_bytes + e_bytes;
+  const size_t p_bytes = std::max(part_bytes(m, k), part_bytes(n, k));
+  const size_t total =
+      round_up(qa_bytes, 256) + round_up(qb_bytes, 256) + x_bytes + e_bytes + p_bytes;
   void* ws = nullptr;
   if (hipMallocAsync(&ws, total, st) != hipSuccess) return MPDD_ERR_ALLOC;
   char* base = (char*)ws;
@@ -440,6 +481,7 @@ int ozaki_gemm(const void* opts_v, bool ta, bool tb, int64_t m, int64_t n, int64
   void* x = base + round_up(qa_bytes, 256) + round_up(qb_bytes, 256);
   int* ea = (int*)((char*)x + x_bytes);
   int* eb = ea + m;
+  double* part = (double*)((char*)ea + e_bytes);
 
   // row operand of A: op(A)(i, l); of B: op(B)(l, j) as element (j, l)
   const int64_t a_sr = ta ? lda : 1, a_sl = ta ? 1 : lda;
@@ -447,16 +489,16 @@ int ozaki_gemm(const void* opts_v, bool ta, bool tb, int64_t m, int64_t n, int64
   hipError_t e;
   if (i8) {
     e = split_operand<int8_t>(a_hi, a_lo, a_sr, a_sl, m, k, ea, (int8_t*)qa, kp, mp, s, wfirst, w,
-                              st);
+                              part, st);
     if (e == hipSuccess)
       e = split_operand<int8_t>(b_hi, b_lo, b_sr, b_sl, n, k, eb, (int8_t*)qb, kp, np, s, wfirst,
-                                w, st);
+                                w, part, st);
   } else {
     e = split_operand<double>(a_hi, a_lo, a_sr, a_sl, m, k, ea, (double*)qa, kp, mp, s, wfirst, w,
-                              st);
+                              part, st);
     if (e == hipSuccess)
       e = split_operand<double>(b_hi, b_lo, b_sr, b_sl, n, k, eb, (double*)qb, kp, np, s, wfirst,
-                                w, st);
+                                w, part, st);
   }
   const int tiles_m = (int)(mp / OZ_BM), tiles_n = (int)(np / OZ_BN);
   const unsigned nblocks = (unsigned)(tiles_m * tiles_n * s);
@@ -493,14 +535,18 @@ int ozaki_split_entry(int algo, bool trans, int64_t rows, int64_t k, const doubl
                       const double* lo, int64_t ld, int nslices, int wfirst, int w, int* exps,
                       void* slices, int64_t ldq, int64_t rows_p, hipStream_t st) {
   const int64_t sr = trans ? ld : 1, sl = trans ? 1 : ld;
+  void* part = nullptr;
+  if (hipMallocAsync(&part, part_bytes(rows, k), st) != hipSuccess) return MPDD_ERR_ALLOC;
   hipError_t e;
   if (algo == MPDD_OZAKI_I8)
     e = split_operand<int8_t>(hi, lo, sr, sl, rows, k, exps, (int8_t*)slices, ldq, rows_p,
-                              nslices, wfirst, w, st);
+                              nslices, wfirst, w, (double*)part, st);
   else
     e = split_operand<double>(hi, lo, sr, sl, rows, k, exps, (double*)slices, ldq, rows_p, nslices,
-                              wfirst, w, st);
-  return e == hipSuccess ? 0 : MPDD_ERR_HIP;
+                              wfirst, w, (double*)part, st);
+  hipError_t ef = hipFreeAsync(part, st);
+  if (e != hipSuccess) return MPDD_ERR_HIP;
+  return ef == hipSuccess ? 0 : MPDD_ERR_HIP;
 }
 
 int ozaki_digit_widths(int algo, int64_t k, int nslices, int* wfirst, int* w) {

@@ -89,10 +89,12 @@ struct Slot {
   std::vector<Req*> reqs;
 };
 
-// Device buffer layout of a group.
+// Device buffer layout of a group: header | request descriptors | work items,
+// packed so that one copy of exactly the used bytes moves a group.
 struct GroupHeader {
   int count[kNumServeTiles];   // items per tile shape
-  int pad[64 - kNumServeTiles];
+  int items_offset;            // byte offset of the work items from the buffer start
+  int pad[64 - kNumServeTiles - 1];
 };
 
 }  // namespace
@@ -216,7 +218,7 @@ bool build_group(Slot& sl, const std::vector<Req*>& g, size_t& used, int counts[
   char* base = (char*)sl.host_buf;
   GroupHeader* hdr = (GroupHeader*)base;
   ServeReq* reqs = (ServeReq*)(base + sizeof(GroupHeader));
-  ServeItem* items0 = (ServeItem*)(reqs + kMaxGroupReqs);
+  ServeItem* items0 = (ServeItem*)(reqs + g.size());
   std::vector<std::vector<std::pair<int64_t, ServeItem>>> lists(kNumServeTiles);
   for (size_t qi = 0; qi < g.size(); ++qi) {
     const mpdd_request& r = g[qi]->r;
@@ -263,6 +265,7 @@ bool build_group(Slot& sl, const std::vector<Req*>& g, size_t& used, int counts[
   for (auto& L : lists) total += L.size();
   if (total > (size_t)kMaxGroupItems) return false;
   std::memset(hdr, 0, sizeof(GroupHeader));
+  hdr->items_offset = (int)((char*)items0 - base);
   ServeItem* out = items0;
   for (int c = 0; c < kNumServeTiles; ++c) {
     auto& L = lists[c];
@@ -280,10 +283,9 @@ bool build_group(Slot& sl, const std::vector<Req*>& g, size_t& used, int counts[
 // Capture the grouped schedule of a slot once: one persistent kernel per tile
 // shape, reading its work list and item count from the slot's device buffer.
 int capture_graph(Slot& sl) {
-  char* dbase = (char*)sl.dev_buf;
+  const char* dbase = (const char*)sl.dev_buf;
   const GroupHeader* hdr = (const GroupHeader*)dbase;
   const ServeReq* reqs = (const ServeReq*)(dbase + sizeof(GroupHeader));
-  const ServeItem* items = (const ServeItem*)(reqs + kMaxGroupReqs);
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return MPDD_ERR_HIP;
   int cus = 256;
@@ -292,10 +294,9 @@ int capture_graph(Slot& sl) {
   if (hipStreamBeginCapture(sl.stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
     return MPDD_ERR_HIP;
   hipError_t e = hipSuccess;
-  for (int c = 0; c < kNumServeTiles && e == hipSuccess; ++c) {
-    const int grid = 2 * cus;
-    e = launch_grouped_list(kServeTiles[c], reqs, items, hdr->count, c, grid, sl.stream);
-  }
+  for (int c = 0; c < kNumServeTiles && e == hipSuccess; ++c)
+    e = launch_grouped_list(kServeTiles[c], dbase, reqs, hdr->count, &hdr->items_offset, c,
+                            2 * cus, sl.stream);
   hipError_t e2 = hipStreamEndCapture(sl.stream, &graph);
   if (e != hipSuccess || e2 != hipSuccess || !graph) {
     if (graph) (void)hipGraphDestroy(graph);
@@ -466,10 +467,15 @@ void scheduler(mpdd_server_s* s) {
     for (Slot& sl : s->slots) busy = busy || sl.busy;
     if (s->stop && !busy && s->pending.empty() && s->admitted.empty()) break;
     if (progressed) continue;
-    if (busy)
-      s->cv_sched.wait_for(lk, std::chrono::microseconds(10));
-    else
+    if (busy) {
+      // groups in flight: poll their events without sleeping (a timed wait
+      // would add the timer's slack, tens of microseconds, to every request)
+      lk.unlock();
+      std::this_thread::yield();
+      lk.lock();
+    } else {
       s->cv_sched.wait(lk);
+    }
   }
 }
 
