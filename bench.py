@@ -83,9 +83,11 @@ def bench_plain(h, args, stream):
     A, B, C = case["A"], case["B"], case["C"]
     torch.cuda.synchronize()
 
+    opts = dict(algo=b.MPDD_PLAIN, tile_id=args.tile, splitk=0)
+
     def step():
-        info = b.mpdd_Rgemm(h, "N", "N", n, n, n, case["alpha"], A, case["lda"], B, case["ldb"],
-                            case["beta"], C, case["ldc"], stream=stream)
+        info = b.mpdd_Rgemm_ex(h, opts, "N", "N", n, n, n, case["alpha"], A, case["lda"], B,
+                               case["ldb"], case["beta"], C, case["ldc"], stream=stream)
         if info != 0:
             raise RuntimeError(f"mpdd_Rgemm info={info}")
 
@@ -257,6 +259,8 @@ def main():
     ap.add_argument("--n", type=int, default=8192)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--sections", default="plain,syrk,ozaki,serve")
+    ap.add_argument("--tile", type=int, default=-1,
+                    help="tile-table entry for the plain product (-1: the library's choice)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="first run one device-to-device copy of BYTES bytes (a kernel of known "
                          "traffic, to calibrate the HBM byte counters of a profiling pass)")

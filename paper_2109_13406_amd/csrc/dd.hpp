@@ -95,6 +95,19 @@ __device__ __forceinline__ void madd_lean(double& sh, double& sl, double ah, dou
   sh = s;
 }
 
+// Lean multiply-accumulate without the cross terms (10 binary64 ops): the
+// leading product and its rounding errors only; ah*bl + al*bh is accumulated
+// elsewhere (on the matrix cores) and added to sl once per tile.
+__device__ __forceinline__ void madd_lean_hi(double& sh, double& sl, double ah, double bh) {
+  double p = ah * bh;
+  double e = __builtin_fma(ah, bh, -p);
+  double s = sh + p;
+  double bb = s - sh;
+  double se = (sh - (s - bb)) + (p - bb);
+  sl = sl + (e + se);
+  sh = s;
+}
+
 __device__ __forceinline__ void renorm(double& sh, double& sl) {
   ddv r = two_sum(sh, sl);
   sh = r.hi;

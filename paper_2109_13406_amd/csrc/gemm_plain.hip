@@ -27,20 +27,31 @@
 #include "dd.hpp"
 #include "kernels.hpp"
 
+typedef double v4d __attribute__((ext_vector_type(4)));
+
 #pragma clang fp contract(off)
 
 namespace mpdd {
 
 // Decode tile coordinates of workgroup b.  Workgroups are dealt round-robin
 // to the 8 XCDs; remapping b so that each XCD receives a contiguous run of
-// tiles keeps neighbouring tiles (which share A row panels) in one L2.
+// tiles, and walking that run in 8 x 8 blocks of tiles, makes the ~64
+// workgroups an XCD runs at once share 8 row panels of op(A) and 8 column
+// panels of op(B) in its L2 (instead of 64 row panels and one column panel).
 __device__ __forceinline__ void tile_coords(const GemmParams& p, int& bi, int& bj) {
   int b = blockIdx.x;
   const int nb = gridDim.x;
   if ((nb & 7) == 0) b = (b & 7) * (nb >> 3) + (b >> 3);
   if (p.tri == 0) {
-    bi = b % p.tiles_m;
-    bj = b / p.tiles_m;
+    if ((p.tiles_m & 7) == 0 && (p.tiles_n & 7) == 0) {
+      const int sb = b >> 6, w = b & 63;
+      const int sm = p.tiles_m >> 3;
+      bi = (sb % sm) * 8 + (w & 7);
+      bj = (sb / sm) * 8 + (w >> 3);
+    } else {
+      bi = b % p.tiles_m;
+      bj = b / p.tiles_m;
+    }
   } else {
     // tiles (x, y) with x <= y, enumerated column by column: t = y(y+1)/2 + x
     int y = (int)((__builtin_sqrt(8.0 * (double)b + 1.0) - 1.0) * 0.5);
@@ -60,7 +71,7 @@ struct DDTileSmem {
 
 // Accumulate the BM x BN tile at (i0, j0) of op(A) op(B) over k in
 // [kbeg, kend) into this thread's RM x RN block of dd accumulators.
-template <int BM, int BN, int BK, int RM, int RN, bool TA, bool TB, bool ACC>
+template <int BM, int BN, int BK, int RM, int RN, bool TA, bool TB, bool ACC, bool XM = false>
 __device__ __forceinline__ void dd_tile_mainloop(const GemmParams& p, int64_t i0, int64_t j0,
                                                  int64_t kbeg, int64_t kend,
                                                  DDTileSmem<BM, BN, BK>& sm, double (&ch)[RM][RN],
@@ -164,10 +175,69 @@ __device__ __forceinline__ void dd_tile_mainloop(const GemmParams& p, int64_t i0
   }
   __syncthreads();
 
+  // XM: the cross terms ah*bl + al*bh of every product go to the FP64 matrix
+  // cores (v_mfma_f64_16x16x4_f64, accumulating in X) while the vector units
+  // run the 10-op leading-product update.  Wave w owns rows 0..BM-1 and the 16
+  // columns tn + 16c of its lanes: MFMA block rb covers rows 16rb..16rb+15 and
+  // those columns (column q of the block = local column (q%4) + 16(q/4)).
+  constexpr bool XMF = XM && !ACC;
+  static_assert(!XMF || (TMX == 16 && TNX == 16 && RN == 4 && NT == 256),
+                "matrix-core cross terms need the 16 x 16 thread grid");
+  const int lane = tid & 63, wv = tid >> 6;
+  const int xr = lane & 15, xk = lane >> 4;
+  const int xcol = 4 * wv + (lane & 3) + 16 * ((lane & 15) >> 2);
+  v4d X[RM];
+#pragma unroll
+  for (int r = 0; r < RM; ++r) X[r] = v4d{0.0, 0.0, 0.0, 0.0};
+
   for (int64_t kt = 0; kt < nkt; ++kt) {
     const int cur = (int)(kt & 1);
     const bool more = kt + 1 < nkt;
     if (more) load_tiles(kbeg + (kt + 1) * BK, kt + 2 == nkt);
+    if constexpr (XMF) {
+#pragma unroll
+      for (int kk = 0; kk < BK; kk += 4) {
+        const double2 xb = Bs[cur][kk + xk][xcol];
+#pragma unroll
+        for (int rb = 0; rb < RM; ++rb) {
+          const double2 xa = As[cur][kk + xk][16 * rb + xr];
+          X[rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa.x, xb.y, X[rb], 0, 0, 0);
+          X[rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa.y, xb.x, X[rb], 0, 0, 0);
+        }
+      }
+      double ahs[2][RM], bhs[2][RN];
+#pragma unroll
+      for (int r = 0; r < RM; ++r) ahs[0][r] = As[cur][0][tm + TMX * r].x;
+#pragma unroll
+      for (int c = 0; c < RN; ++c) bhs[0][c] = Bs[cur][0][tn + TNX * c].x;
+#pragma unroll
+      for (int kk = 0; kk < BK; ++kk) {
+        const int q = kk & 1;
+        if (kk + 1 < BK) {
+#pragma unroll
+          for (int r = 0; r < RM; ++r) ahs[q ^ 1][r] = As[cur][kk + 1][tm + TMX * r].x;
+#pragma unroll
+          for (int c = 0; c < RN; ++c) bhs[q ^ 1][c] = Bs[cur][kk + 1][tn + TNX * c].x;
+        }
+#pragma unroll
+        for (int x = 0; x < RM * RN; ++x) {
+          const int r = x / RN, c = x % RN;
+          madd_lean_hi(ch[r][c], cl[r][c], ahs[q][r], bhs[q][c]);
+        }
+#pragma unroll
+        for (int r = 0; r < RM; ++r)
+#pragma unroll
+          for (int c = 0; c < RN; ++c) asm volatile("" : "+v"(ch[r][c]), "+v"(cl[r][c]));
+        asm volatile("" ::: "memory");
+      }
+#pragma unroll
+      for (int r = 0; r < RM; ++r)
+#pragma unroll
+        for (int c = 0; c < RN; ++c) renorm(ch[r][c], cl[r][c]);
+      if (more) store_tiles(cur ^ 1);
+      __syncthreads();
+      continue;
+    }
     // Operands of step kk+1 are read from LDS while step kk computes.
     double2 a[2][RM], b[2][RN];
 #pragma unroll
@@ -210,6 +280,24 @@ __device__ __forceinline__ void dd_tile_mainloop(const GemmParams& p, int64_t i0
     if (more) store_tiles(cur ^ 1);
     __syncthreads();
   }
+  if constexpr (XMF) {
+    // hand the matrix-core cross terms to the threads that own the entries,
+    // through LDS (free after the final barrier of the k-loop)
+    double* xs = reinterpret_cast<double*>(&sm.As[0][0][0]) + wv * BM * 16;
+#pragma unroll
+    for (int rb = 0; rb < RM; ++rb)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) xs[(16 * rb + 4 * e + xk) * 16 + xr] = X[rb][e];
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < RM; ++r)
+#pragma unroll
+      for (int c = 0; c < RN; ++c) {
+        cl[r][c] += xs[(tm + TMX * r) * 16 + (tn - 4 * wv) + 4 * c];
+        renorm(ch[r][c], cl[r][c]);
+      }
+    __syncthreads();
+  }
 }
 
 // Write this thread's block of the tile at (i0, j0): either the k-split
@@ -250,7 +338,8 @@ __device__ __forceinline__ void dd_tile_epilogue(const GemmParams& p, int64_t i0
   }
 }
 
-template <int BM, int BN, int BK, int RM, int RN, bool TA, bool TB, bool ACC, bool PARTIAL>
+template <int BM, int BN, int BK, int RM, int RN, bool XM, bool TA, bool TB, bool ACC,
+          bool PARTIAL>
 __global__ void __launch_bounds__((BM / RM) * (BN / RN))
 dd_gemm_kernel(GemmParams p) {
   __shared__ DDTileSmem<BM, BN, BK> sm;
@@ -261,7 +350,7 @@ dd_gemm_kernel(GemmParams p) {
   const int64_t kbeg = (int64_t)blockIdx.z * p.kchunk;
   const int64_t kend = (kbeg + p.kchunk < p.k) ? kbeg + p.kchunk : p.k;
   double ch[RM][RN], cl[RM][RN];
-  dd_tile_mainloop<BM, BN, BK, RM, RN, TA, TB, ACC>(p, i0, j0, kbeg, kend, sm, ch, cl);
+  dd_tile_mainloop<BM, BN, BK, RM, RN, TA, TB, ACC, XM>(p, i0, j0, kbeg, kend, sm, ch, cl);
   dd_tile_epilogue<BM, BN, RM, RN, PARTIAL>(p, i0, j0, (int)blockIdx.z, ch, cl);
 }
 
@@ -271,7 +360,7 @@ dd_gemm_kernel(GemmParams p) {
 // dd_gemm_kernel for that request's flags, so a request's result is bit-
 // identical to a standalone call with the same tile.  The item count is read
 // from the device header, so one captured launch serves every group.
-template <int BM, int BN, int BK, int RM, int RN>
+template <int BM, int BN, int BK, int RM, int RN, bool XM>
 __global__ void __launch_bounds__((BM / RM) * (BN / RN))
 dd_grouped_kernel(const char* __restrict__ base, const ServeReq* __restrict__ reqs,
                   const int* __restrict__ counts, const int* __restrict__ items_offset,
@@ -290,10 +379,10 @@ dd_grouped_kernel(const char* __restrict__ base, const ServeReq* __restrict__ re
     const int64_t j0 = (int64_t)it.bj * BN;
     double ch[RM][RN], cl[RM][RN];
     switch (flags & 3) {
-      case 0: dd_tile_mainloop<BM, BN, BK, RM, RN, false, false, false>(p, i0, j0, 0, p.k, sm, ch, cl); break;
-      case 1: dd_tile_mainloop<BM, BN, BK, RM, RN, true, false, false>(p, i0, j0, 0, p.k, sm, ch, cl); break;
-      case 2: dd_tile_mainloop<BM, BN, BK, RM, RN, false, true, false>(p, i0, j0, 0, p.k, sm, ch, cl); break;
-      default: dd_tile_mainloop<BM, BN, BK, RM, RN, true, true, false>(p, i0, j0, 0, p.k, sm, ch, cl); break;
+      case 0: dd_tile_mainloop<BM, BN, BK, RM, RN, false, false, false, XM>(p, i0, j0, 0, p.k, sm, ch, cl); break;
+      case 1: dd_tile_mainloop<BM, BN, BK, RM, RN, true, false, false, XM>(p, i0, j0, 0, p.k, sm, ch, cl); break;
+      case 2: dd_tile_mainloop<BM, BN, BK, RM, RN, false, true, false, XM>(p, i0, j0, 0, p.k, sm, ch, cl); break;
+      default: dd_tile_mainloop<BM, BN, BK, RM, RN, true, true, false, XM>(p, i0, j0, 0, p.k, sm, ch, cl); break;
     }
     dd_tile_epilogue<BM, BN, RM, RN, false>(p, i0, j0, 0, ch, cl);
     __syncthreads();
@@ -352,15 +441,17 @@ __global__ void __launch_bounds__(256) dd_scale_kernel(GemmParams p) {
 
 // ---- tile table and launchers ------------------------------------------------
 
-// id, BM, BN, BK, RM, RN  (threads = (BM/RM) * (BN/RN))
-#define MPDD_TILES(X)      \
-  X(0, 64, 64, 16, 4, 4)   \
-  X(1, 64, 64, 8, 4, 4)    \
-  X(2, 32, 32, 16, 2, 2)   \
-  X(3, 128, 64, 8, 8, 4)
+// id, BM, BN, BK, RM, RN, XM  (threads = (BM/RM) * (BN/RN); XM: cross terms of
+// the lean madd on the FP64 matrix cores)
+#define MPDD_TILES(X)         \
+  X(0, 64, 64, 16, 4, 4, 0)   \
+  X(1, 64, 64, 8, 4, 4, 0)    \
+  X(2, 32, 32, 16, 2, 2, 0)   \
+  X(3, 128, 64, 8, 8, 4, 0)   \
+  X(4, 64, 64, 16, 4, 4, 1)
 
 static const TileInfo kTiles[] = {
-#define X(id, bm, bn, bk, rm, rn) {bm, bn, bk, (bm / rm) * (bn / rn)},
+#define X(id, bm, bn, bk, rm, rn, xm) {bm, bn, bk, (bm / rm) * (bn / rn)},
     MPDD_TILES(X)
 #undef X
 };
@@ -370,22 +461,22 @@ const TileInfo* tile_info(int id) {
   return (id >= 0 && id < tile_count()) ? &kTiles[id] : nullptr;
 }
 
-template <int BM, int BN, int BK, int RM, int RN, bool TA, bool TB, bool ACC>
+template <int BM, int BN, int BK, int RM, int RN, bool XM, bool TA, bool TB, bool ACC>
 static hipError_t launch_t(const GemmParams& p, int nblocks, int splitk, hipStream_t st) {
   dim3 grid(nblocks, 1, splitk), block((BM / RM) * (BN / RN));
   if (splitk > 1)
-    hipLaunchKernelGGL((dd_gemm_kernel<BM, BN, BK, RM, RN, TA, TB, ACC, true>), grid, block, 0,
-                       st, p);
+    hipLaunchKernelGGL((dd_gemm_kernel<BM, BN, BK, RM, RN, XM, TA, TB, ACC, true>), grid, block,
+                       0, st, p);
   else
-    hipLaunchKernelGGL((dd_gemm_kernel<BM, BN, BK, RM, RN, TA, TB, ACC, false>), grid, block, 0,
-                       st, p);
+    hipLaunchKernelGGL((dd_gemm_kernel<BM, BN, BK, RM, RN, XM, TA, TB, ACC, false>), grid, block,
+                       0, st, p);
   return hipGetLastError();
 }
 
-template <int BM, int BN, int BK, int RM, int RN>
+template <int BM, int BN, int BK, int RM, int RN, bool XM>
 static hipError_t launch_ops(const GemmParams& p, bool ta, bool tb, bool acc, int nblocks,
                              int splitk, hipStream_t st) {
-#define L(TA, TB, AC) return launch_t<BM, BN, BK, RM, RN, TA, TB, AC>(p, nblocks, splitk, st)
+#define L(TA, TB, AC) return launch_t<BM, BN, BK, RM, RN, XM, TA, TB, AC>(p, nblocks, splitk, st)
   if (acc) {
     if (!ta && !tb) L(false, false, true);
     if (!ta && tb) L(false, true, true);
@@ -409,8 +500,8 @@ hipError_t launch_gemm(int tile, const GemmParams& p, bool ta, bool tb, bool acc
   else
     nblocks = p.tiles_m * (p.tiles_m + 1) / 2;
   switch (tile) {
-#define X(id, bm, bn, bk, rm, rn) \
-  case id: return launch_ops<bm, bn, bk, rm, rn>(p, ta, tb, accurate, nblocks, splitk, st);
+#define X(id, bm, bn, bk, rm, rn, xm) \
+  case id: return launch_ops<bm, bn, bk, rm, rn, xm != 0>(p, ta, tb, accurate, nblocks, splitk, st);
     MPDD_TILES(X)
 #undef X
   }
@@ -421,9 +512,9 @@ hipError_t launch_grouped_list(int tile, const char* base, const ServeReq* reqs,
                                const int* counts, const int* items_offset, int which, int grid,
                                hipStream_t st) {
   switch (tile) {
-#define X(id, bm, bn, bk, rm, rn)                                                               \
+#define X(id, bm, bn, bk, rm, rn, xm)                                                           \
   case id:                                                                                      \
-    hipLaunchKernelGGL((dd_grouped_kernel<bm, bn, bk, rm, rn>), dim3(grid),                     \
+    hipLaunchKernelGGL((dd_grouped_kernel<bm, bn, bk, rm, rn, xm != 0>), dim3(grid),            \
                        dim3((bm / rm) * (bn / rn)), 0, st, base, reqs, counts, items_offset,    \
                        which);                                                                  \
     return hipGetLastError();

@@ -34,10 +34,11 @@ namespace mpdd {
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef double v4d __attribute__((ext_vector_type(4)));
 
-// Tile geometry of the product kernels; slice buffers are padded to it.
-constexpr int OZ_BM = 128;      // rows of op(A) per workgroup tile
-constexpr int OZ_BN = 128;      // columns of op(B) per workgroup tile
-constexpr int OZ_KPAD = 64;     // k padding of the slice rows (bytes for INT8)
+// Tile geometry of the FP64 product kernel; slice buffers are padded to the
+// product kernel's tile.
+constexpr int OZ_BM = 128;      // rows of op(A) per workgroup tile (FP64 form)
+constexpr int OZ_BN = 128;      // columns of op(B) per workgroup tile (FP64 form)
+constexpr int OZ_KPAD = 64;     // k padding of the slice rows
 
 // ---- scale -------------------------------------------------------------------------
 
@@ -181,15 +182,17 @@ __device__ __forceinline__ void oz_tile_of(int b, int tiles, int nslices, int& d
 
 // ---- products: INT8 ---------------------------------------------------------------------
 
-// X_d tile (128 x 128) for anti-diagonal d: sum over t of Q_t(rows) Q'_{d-t}(cols)^T
-// with k-contiguous int8 rows.  256 threads = 4 waves in a 2 x 2 grid, each
-// wave 64 x 64 = 4 x 4 v_mfma_i32_16x16x64_i8 tiles.  A k-step stages a
-// 128 x 64-byte block of each operand in LDS (double buffered; rows padded to
-// 80 bytes so the 16-byte fragment reads of 16 consecutive rows spread over
-// the banks).  For an MFMA lane l supplies row (l % 16), bytes
-// 16*(l/16) .. +15 of the k-step for both operands, so every k pairs up.
-// Accumulation is exact in int32.  Workgroups enumerate (d, tile) with the
-// longest sums (largest d) first.
+// X_d tile (256 x 256) for anti-diagonal d: sum over t of Q_t(rows) Q'_{d-t}(cols)^T
+// with k-contiguous int8 rows.  256 threads = 4 waves in a 2 x 2 grid; each
+// wave owns 128 x 128 outputs = 8 x 8 v_mfma_i32_16x16x64_i8 tiles (256
+// int32 accumulators, held in AGPRs), so each 16-byte LDS fragment feeds 8
+// MFMAs.  A k-step stages a 256 x 64-byte block of each operand in LDS
+// (double buffered; rows padded to 80 bytes so 16 consecutive rows' fragment
+// reads spread over the banks).  For an MFMA, lane l supplies row l % 16,
+// bytes 16*(l/16) .. +15 of the k-step, for both operands, so every k pairs
+// up.  Accumulation is exact in int32.
+constexpr int I8_BM = 256;
+constexpr int I8_BN = 256;
 constexpr int I8_BK = 64;
 constexpr int I8_PITCH = 80;
 
@@ -197,8 +200,8 @@ __global__ void __launch_bounds__(256)
 oz_gemm_i8(const int8_t* __restrict__ qa, const int8_t* __restrict__ qb, int32_t* __restrict__ x,
            int64_t kp, int64_t plane_a, int64_t plane_b, int64_t mp, int64_t np, int nslices,
            int tiles_m, int tiles_n) {
-  __shared__ __attribute__((aligned(16))) int8_t As[2][OZ_BM * I8_PITCH];
-  __shared__ __attribute__((aligned(16))) int8_t Bs[2][OZ_BN * I8_PITCH];
+  __shared__ __attribute__((aligned(16))) int8_t As[2][I8_BM * I8_PITCH];
+  __shared__ __attribute__((aligned(16))) int8_t Bs[2][I8_BN * I8_PITCH];
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
@@ -207,35 +210,37 @@ oz_gemm_i8(const int8_t* __restrict__ qa, const int8_t* __restrict__ qb, int32_t
   int d, tile;
   oz_tile_of(blockIdx.x, tiles_m * tiles_n, nslices, d, tile);
   const int bi = tile % tiles_m, bj = tile / tiles_m;
-  const int64_t i0 = (int64_t)bi * OZ_BM, j0 = (int64_t)bj * OZ_BN;
+  const int64_t i0 = (int64_t)bi * I8_BM, j0 = (int64_t)bj * I8_BN;
 
-  v4i acc[4][4];
+  v4i acc[8][8];
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int a = 0; a < 8; ++a)
 #pragma unroll
-    for (int c = 0; c < 4; ++c) acc[a][c] = v4i{0, 0, 0, 0};
+    for (int c = 0; c < 8; ++c) acc[a][c] = v4i{0, 0, 0, 0};
 
-  // staging: thread loads 16 bytes of rows (tid/4) and (tid/4 + 64), chunk tid%4
+  // staging: thread loads 16 bytes (chunk tid%4) of rows tid/4 + 64*e, e < 4
   const int srow = tid >> 2, scol = (tid & 3) * 16;
   const int64_t ksteps = kp / I8_BK;
   const int64_t total = (int64_t)(d - 1) * ksteps;
-  v4i ra[2], rb[2];
+  v4i ra[4], rb[4];
 
   auto gload = [&](int64_t s) {
     const int t = 1 + (int)(s / ksteps);          // slice of op(A); op(B) slice d - t
     const int64_t l0 = (s % ksteps) * I8_BK;
     const int8_t* pa = qa + (int64_t)(t - 1) * plane_a + (i0 + srow) * kp + l0 + scol;
     const int8_t* pb = qb + (int64_t)(d - t - 1) * plane_b + (j0 + srow) * kp + l0 + scol;
-    ra[0] = *(const v4i*)pa;
-    ra[1] = *(const v4i*)(pa + 64 * kp);
-    rb[0] = *(const v4i*)pb;
-    rb[1] = *(const v4i*)(pb + 64 * kp);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      ra[e] = *(const v4i*)(pa + 64 * e * kp);
+      rb[e] = *(const v4i*)(pb + 64 * e * kp);
+    }
   };
   auto sstore = [&](int buf) {
-    *(v4i*)&As[buf][srow * I8_PITCH + scol] = ra[0];
-    *(v4i*)&As[buf][(srow + 64) * I8_PITCH + scol] = ra[1];
-    *(v4i*)&Bs[buf][srow * I8_PITCH + scol] = rb[0];
-    *(v4i*)&Bs[buf][(srow + 64) * I8_PITCH + scol] = rb[1];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      *(v4i*)&As[buf][(srow + 64 * e) * I8_PITCH + scol] = ra[e];
+      *(v4i*)&Bs[buf][(srow + 64 * e) * I8_PITCH + scol] = rb[e];
+    }
   };
 
   gload(0);
@@ -245,30 +250,30 @@ oz_gemm_i8(const int8_t* __restrict__ qa, const int8_t* __restrict__ qb, int32_t
   for (int64_t s = 0; s < total; ++s) {
     const int cur = (int)(s & 1);
     if (s + 1 < total) gload(s + 1);
-    v4i af[4], bf[4];
+    v4i af[8], bf[8];
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
-      af[a] = *(const v4i*)&As[cur][(wm * 64 + a * 16 + fr) * I8_PITCH + fk];
+    for (int a = 0; a < 8; ++a)
+      af[a] = *(const v4i*)&As[cur][(wm * 128 + a * 16 + fr) * I8_PITCH + fk];
 #pragma unroll
-    for (int c = 0; c < 4; ++c)
-      bf[c] = *(const v4i*)&Bs[cur][(wn * 64 + c * 16 + fr) * I8_PITCH + fk];
+    for (int c = 0; c < 8; ++c)
+      bf[c] = *(const v4i*)&Bs[cur][(wn * 128 + c * 16 + fr) * I8_PITCH + fk];
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int a = 0; a < 8; ++a)
 #pragma unroll
-      for (int c = 0; c < 4; ++c)
+      for (int c = 0; c < 8; ++c)
         acc[a][c] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af[a], bf[c], acc[a][c], 0, 0, 0);
     if (s + 1 < total) sstore(cur ^ 1);
     __syncthreads();
   }
 
-  // C layout of a 16x16 MFMA tile: lane l holds rows 4*(l/16) + 0..3 of column l%16.
+  // C layout of a 16x16 INT8 MFMA tile: lane l holds rows 4*(l/16) + 0..3 of column l%16.
   int32_t* xd = x + (int64_t)(d - 2) * mp * np;
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int a = 0; a < 8; ++a)
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const int64_t i = i0 + wm * 64 + a * 16 + (lane >> 4) * 4;
-      const int64_t j = j0 + wn * 64 + c * 16 + (lane & 15);
+    for (int c = 0; c < 8; ++c) {
+      const int64_t i = i0 + wm * 128 + a * 16 + (lane >> 4) * 4;
+      const int64_t j = j0 + wn * 128 + c * 16 + (lane & 15);
       *(v4i*)&xd[j * mp + i] = acc[a][c];
     }
 }
@@ -463,7 +468,8 @@ int ozaki_gemm(const void* opts_v, bool ta, bool tb, int64_t m, int64_t n, int64
 
   const bool i8 = (algo == MPDD_OZAKI_I8);
   const int64_t kp = round_up(k, OZ_KPAD);
-  const int64_t mp = round_up(m, OZ_BM), np = round_up(n, OZ_BN);
+  const int64_t tbm = i8 ? I8_BM : OZ_BM, tbn = i8 ? I8_BN : OZ_BN;
+  const int64_t mp = round_up(m, tbm), np = round_up(n, tbn);
   const size_t esz = i8 ? 1 : 8;
   const size_t xsz = i8 ? 4 : 8;
   const size_t qa_bytes = (size_t)s * mp * kp * esz;
@@ -500,7 +506,7 @@ int ozaki_gemm(const void* opts_v, bool ta, bool tb, int64_t m, int64_t n, int64
       e = split_operand<double>(b_hi, b_lo, b_sr, b_sl, n, k, eb, (double*)qb, kp, np, s, wfirst,
                                 w, part, st);
   }
-  const int tiles_m = (int)(mp / OZ_BM), tiles_n = (int)(np / OZ_BN);
+  const int tiles_m = (int)(mp / tbm), tiles_n = (int)(np / tbn);
   const unsigned nblocks = (unsigned)(tiles_m * tiles_n * s);
   if (e == hipSuccess) {
     if (i8)

@@ -99,7 +99,7 @@ def test_splitk(h, splitk):
     for op in W.OPS:
         case = W.gemm_case(300 + splitk, op[0], op[1], 70, 9, 1000, dist="wide")
         O = gemm_oracle(case)
-        for tile in (0, 2):
+        for tile in (0, 2, 4):
             info, G = gemm_gpu(h, case, opts=dict(algo=b.MPDD_PLAIN, tile_id=tile, splitk=splitk))
             assert info == 0
             r = compare_full(f"splitk{splitk} {op} 70x9x1000 tile{tile}", G, O, 70, 9, 1000,
@@ -171,6 +171,7 @@ def test_invalid_argument_enqueues_nothing(h):
 
 
 SYRK_SHAPES = [(1, 1), (97, 45), (130, 1), (64, 200), (33, 7)]
+SQUARE_TILES = (0, 1, 2, 4)      # tile-table entries with BM == BN
 
 
 @pytest.mark.parametrize("uplo", "UL")
@@ -182,7 +183,7 @@ def test_syrk_ragged(h, uplo, trans, shape):
     for beta_zero in (False, True):
         case = W.syrk_case(800 + n + k, uplo, trans, n, k, dist="wide", beta_zero=beta_zero)
         O = syrk_oracle(case)
-        for tile in (0, 1, 2):
+        for tile in SQUARE_TILES:
             info, G = syrk_gpu(h, case, opts=dict(algo=b.MPDD_PLAIN, tile_id=tile, splitk=1))
             assert info == 0
             r = compare_full(f"syrk {uplo}{trans} {n}x{k} b0={beta_zero} tile{tile}", G, O, n, n,
