@@ -98,7 +98,9 @@ int mpdd_Rsyrk(mpdd_handle h, const char *uplo, const char *trans, mpdd_int n, m
 
 /* ---- explicit algorithm and tile choice ------------------------------------ */
 
-#define MPDD_PLAIN 0          /* lean dd multiply-accumulate (12 binary64 ops) */
+#define MPDD_PLAIN 0          /* lean dd multiply-accumulate (12 binary64 ops per
+                                 term; tile entry 4 runs 2 of them, the cross
+                                 terms, on the FP64 matrix cores) */
 #define MPDD_OZAKI_I8 1       /* split form, INT8 slices on the INT8 matrix cores */
 #define MPDD_OZAKI_F64 2      /* split form, FP64 slices on the FP64 matrix cores */
 #define MPDD_PLAIN_ACCURATE 3 /* accurate dd add + mul per term (same steps as the
@@ -169,9 +171,10 @@ int mpdd_ozaki_split(mpdd_handle h, int algo, const char *trans, mpdd_int rows, 
  * (a captured hipGraph) on a free slot, so groups overlap on the device and
  * new requests start as soon as a slot and budget free up.  Each result is
  * bit-identical to a standalone mpdd_Rgemm_ex / mpdd_Rsyrk_ex with the same
- * tile (the server uses the handle's tuned tile, restricted to the 32 x 32
- * and 64 x 64 x 16 shapes).  Operands stay where the caller put them (device
- * memory) and must stay valid until the request completes.
+ * tile (the server uses the handle's tuned tile, restricted to tile-table
+ * entries 2 and 4: 32 x 32 and 64 x 64 x 16).  Operands stay where the
+ * caller put them (device memory) and must stay valid until the request
+ * completes.
  *
  * Intended callers: any host thread; submit and wait may run concurrently. */
 

@@ -230,10 +230,13 @@ __device__ __forceinline__ void dd_tile_mainloop(const GemmParams& p, int64_t i0
           for (int c = 0; c < RN; ++c) asm volatile("" : "+v"(ch[r][c]), "+v"(cl[r][c]));
         asm volatile("" ::: "memory");
       }
+      // renormalise every second k-tile (every 32 terms): |sl| stays ~u|sh|
+      if ((kt & 1) || !more) {
 #pragma unroll
-      for (int r = 0; r < RM; ++r)
+        for (int r = 0; r < RM; ++r)
 #pragma unroll
-        for (int c = 0; c < RN; ++c) renorm(ch[r][c], cl[r][c]);
+          for (int c = 0; c < RN; ++c) renorm(ch[r][c], cl[r][c]);
+      }
       if (more) store_tiles(cur ^ 1);
       __syncthreads();
       continue;

@@ -186,22 +186,24 @@ __device__ __forceinline__ void oz_tile_of(int b, int tiles, int nslices, int& d
 // with k-contiguous int8 rows.  256 threads = 4 waves in a 2 x 2 grid; each
 // wave owns 128 x 128 outputs = 8 x 8 v_mfma_i32_16x16x64_i8 tiles (256
 // int32 accumulators, held in AGPRs), so each 16-byte LDS fragment feeds 8
-// MFMAs.  A k-step stages a 256 x 64-byte block of each operand in LDS
-// (double buffered; rows padded to 80 bytes so 16 consecutive rows' fragment
-// reads spread over the banks).  For an MFMA, lane l supplies row l % 16,
-// bytes 16*(l/16) .. +15 of the k-step, for both operands, so every k pairs
-// up.  Accumulation is exact in int32.
+// MFMAs.  A stage holds a 256 x 128-byte block of each operand in LDS (two
+// MFMA k-steps: 2048 MFMA cycles per wave hide the next stage's global
+// loads; double buffered, 147 KB; rows padded to 144 bytes so 16 consecutive
+// rows' fragment reads spread over the banks).  For an MFMA, lane l supplies
+// row l % 16, bytes 16*(l/16) .. +15 of the k-step, for both operands, so
+// every k pairs up.  Accumulation is exact in int32.
 constexpr int I8_BM = 256;
 constexpr int I8_BN = 256;
-constexpr int I8_BK = 64;
-constexpr int I8_PITCH = 80;
+constexpr int I8_BK = 128;
+constexpr int I8_PITCH = 144;
 
 __global__ void __launch_bounds__(256)
 oz_gemm_i8(const int8_t* __restrict__ qa, const int8_t* __restrict__ qb, int32_t* __restrict__ x,
            int64_t kp, int64_t plane_a, int64_t plane_b, int64_t mp, int64_t np, int nslices,
            int tiles_m, int tiles_n) {
-  __shared__ __attribute__((aligned(16))) int8_t As[2][I8_BM * I8_PITCH];
-  __shared__ __attribute__((aligned(16))) int8_t Bs[2][I8_BN * I8_PITCH];
+  __shared__ __attribute__((aligned(16))) int8_t oz_smem[2 * (I8_BM + I8_BN) * I8_PITCH];
+  int8_t* As0 = oz_smem;
+  int8_t* Bs0 = oz_smem + 2 * I8_BM * I8_PITCH;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
@@ -218,11 +220,11 @@ oz_gemm_i8(const int8_t* __restrict__ qa, const int8_t* __restrict__ qb, int32_t
 #pragma unroll
     for (int c = 0; c < 8; ++c) acc[a][c] = v4i{0, 0, 0, 0};
 
-  // staging: thread loads 16 bytes (chunk tid%4) of rows tid/4 + 64*e, e < 4
-  const int srow = tid >> 2, scol = (tid & 3) * 16;
+  // staging: thread loads 16-byte chunk (tid % 8) of rows tid/8 + 32*e, e < 8
+  const int srow = tid >> 3, scol = (tid & 7) * 16;
   const int64_t ksteps = kp / I8_BK;
   const int64_t total = (int64_t)(d - 1) * ksteps;
-  v4i ra[4], rb[4];
+  v4i ra[8], rb[8];
 
   auto gload = [&](int64_t s) {
     const int t = 1 + (int)(s / ksteps);          // slice of op(A); op(B) slice d - t
@@ -230,16 +232,18 @@ oz_gemm_i8(const int8_t* __restrict__ qa, const int8_t* __restrict__ qb, int32_t
     const int8_t* pa = qa + (int64_t)(t - 1) * plane_a + (i0 + srow) * kp + l0 + scol;
     const int8_t* pb = qb + (int64_t)(d - t - 1) * plane_b + (j0 + srow) * kp + l0 + scol;
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      ra[e] = *(const v4i*)(pa + 64 * e * kp);
-      rb[e] = *(const v4i*)(pb + 64 * e * kp);
+    for (int e = 0; e < 8; ++e) {
+      ra[e] = *(const v4i*)(pa + 32 * e * kp);
+      rb[e] = *(const v4i*)(pb + 32 * e * kp);
     }
   };
   auto sstore = [&](int buf) {
+    int8_t* As = As0 + buf * I8_BM * I8_PITCH;
+    int8_t* Bs = Bs0 + buf * I8_BN * I8_PITCH;
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      *(v4i*)&As[buf][(srow + 64 * e) * I8_PITCH + scol] = ra[e];
-      *(v4i*)&Bs[buf][(srow + 64 * e) * I8_PITCH + scol] = rb[e];
+    for (int e = 0; e < 8; ++e) {
+      *(v4i*)&As[(srow + 32 * e) * I8_PITCH + scol] = ra[e];
+      *(v4i*)&Bs[(srow + 32 * e) * I8_PITCH + scol] = rb[e];
     }
   };
 
@@ -249,19 +253,27 @@ oz_gemm_i8(const int8_t* __restrict__ qa, const int8_t* __restrict__ qb, int32_t
   const int fr = lane & 15, fk = (lane >> 4) * 16;
   for (int64_t s = 0; s < total; ++s) {
     const int cur = (int)(s & 1);
+    const int8_t* As = As0 + cur * I8_BM * I8_PITCH;
+    const int8_t* Bs = Bs0 + cur * I8_BN * I8_PITCH;
     if (s + 1 < total) gload(s + 1);
-    v4i af[8], bf[8];
 #pragma unroll
-    for (int a = 0; a < 8; ++a)
-      af[a] = *(const v4i*)&As[cur][(wm * 128 + a * 16 + fr) * I8_PITCH + fk];
+    for (int kk = 0; kk < I8_BK; kk += 64) {
+      v4i af[8], bf[8];
 #pragma unroll
-    for (int c = 0; c < 8; ++c)
-      bf[c] = *(const v4i*)&Bs[cur][(wn * 128 + c * 16 + fr) * I8_PITCH + fk];
-#pragma unroll
-    for (int a = 0; a < 8; ++a)
+      for (int a = 0; a < 8; ++a)
+        af[a] = *(const v4i*)&As[(wm * 128 + a * 16 + fr) * I8_PITCH + kk + fk];
 #pragma unroll
       for (int c = 0; c < 8; ++c)
-        acc[a][c] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af[a], bf[c], acc[a][c], 0, 0, 0);
+        bf[c] = *(const v4i*)&Bs[(wn * 128 + c * 16 + fr) * I8_PITCH + kk + fk];
+#pragma unroll
+      for (int a = 0; a < 8; ++a)
+#pragma unroll
+        for (int c = 0; c < 8; ++c)
+          acc[a][c] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af[a], bf[c], acc[a][c], 0, 0, 0);
+      // keep the next k-step's fragment reads below this one's MFMAs (one set
+      // of fragments live at a time)
+      asm volatile("" ::: "memory");
+    }
     if (s + 1 < total) sstore(cur ^ 1);
     __syncthreads();
   }
@@ -467,7 +479,7 @@ int ozaki_gemm(const void* opts_v, bool ta, bool tb, int64_t m, int64_t n, int64
   if (!digit_widths(algo, k, s, wfirst, w)) return MPDD_ERR_UNSUPPORTED;
 
   const bool i8 = (algo == MPDD_OZAKI_I8);
-  const int64_t kp = round_up(k, OZ_KPAD);
+  const int64_t kp = round_up(k, i8 ? I8_BK : OZ_KPAD);
   const int64_t tbm = i8 ? I8_BM : OZ_BM, tbn = i8 ? I8_BN : OZ_BN;
   const int64_t mp = round_up(m, tbm), np = round_up(n, tbn);
   const size_t esz = i8 ? 1 : 8;

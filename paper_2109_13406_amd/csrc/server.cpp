@@ -56,8 +56,8 @@ bool lsame(char c, char ref) {
 }
 
 // Tile shapes the grouped graph runs: a small one for small requests and the
-// large one that the dense products use.
-constexpr int kServeTiles[] = {2, 0};
+// large one that the dense products use (tile-table entries).
+constexpr int kServeTiles[] = {2, 4};
 constexpr int kNumServeTiles = 2;
 constexpr int kSlots = 4;
 constexpr int kMaxGroupReqs = 1024;

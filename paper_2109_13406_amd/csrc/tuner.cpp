@@ -59,11 +59,12 @@ bool TuneTable::lookup(int op, bool ta, bool tb, int64_t m, int64_t n, int64_t k
 
 int default_tile(int64_t m, int64_t n, int64_t k, bool square_only) {
   (void)k;
-  // 64x64 tiles give 4096 workgroups at n = 4096; small problems use 32x32
-  // tiles so that more CUs get work.
+  // 64 x 64 tiles with the cross terms on the matrix cores (entry 4) for
+  // everything that gives the CUs enough workgroups; small problems use
+  // 32 x 32 tiles (entry 2) so that more CUs get work.
   const int64_t t64 = ((m + 63) / 64) * ((n + 63) / 64);
   if (t64 < 128 && (square_only || (m <= 1024 && n <= 1024))) return 2;
-  return 0;
+  return 4;
 }
 
 }  // namespace mpdd
