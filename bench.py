@@ -213,6 +213,36 @@ def bench_ozaki(h, args, stream, t_plain):
     return out
 
 
+def bench_host(h, args):
+    """MPBLAS-shaped host call (dd_real pairs in host memory) at n: copies to
+    the device and back are inside the timed call, as in the manual's "with
+    host-GPU transfer" figures."""
+    import torch
+    import workloads as W
+    from paper_2109_13406_amd import binding as b
+    n = args.n
+    case = W.gemm_case_device(W.BASE_SEED + 5, "N", "N", n, n, n)
+    hp = lambda pl: torch.stack([pl[0], pl[1]], dim=1).cpu().numpy()
+    A, B, C = hp(case["A"]), hp(case["B"]), hp(case["C"])
+    del case
+    torch.cuda.empty_cache()
+    ld = W.ld_padded(n)
+    times = []
+    for it in range(3):
+        t0 = time.perf_counter()
+        info = b.mpdd_Rgemm_host(h, "N", "N", n, n, n, (0.5, 0.0), A, ld, B, ld, (0.25, 0.0), C,
+                                 ld)
+        dt = time.perf_counter() - t0
+        if info != 0:
+            raise RuntimeError(f"mpdd_Rgemm_host info={info}")
+        if it > 0:
+            times.append(dt)
+    t = min(times)
+    return {"workload": f"Rgemm NN m=n=k={n} ld={ld}, dd_real pairs in pageable host memory",
+            "ms": round(t * 1e3, 2), "dd_gflops_with_transfer": round(2.0 * n ** 3 / t / 1e9, 1),
+            "host_bytes_moved": 16 * ld * n * 4}
+
+
 def bench_serve(h, args):
     """Served request stream (Poisson arrivals) vs the same requests issued as
     sequential plain calls; p50 / p99 latency and aggregate dd-GFLOPS."""
@@ -258,7 +288,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=8192)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--sections", default="plain,syrk,ozaki,serve")
+    ap.add_argument("--sections", default="plain,syrk,ozaki,host,serve")
     ap.add_argument("--tile", type=int, default=-1,
                     help="tile-table entry for the plain product (-1: the library's choice)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
@@ -323,10 +353,14 @@ def main():
         log(f"rsyrk: {out['rsyrk']}")
     if "ozaki" in sections:
         out["ozaki"] = bench_ozaki(h, args, stream, t_kernel)
+    if "host" in sections:
+        out["host_api"] = bench_host(h, args)
+        log(f"host api: {out['host_api']}")
     if "serve" in sections:
         out["serving"] = bench_serve(h, args)
     out["context"] = {"paper_dd_rgemm_gflops": {"A100": 592, "V100": 435},
                       "paper_dd_rsyrk_gflops": {"V100": 428},
+                      "paper_dd_rgemm_gflops_with_transfer": {"V100": 318},
                       "dd_roofline_tflops": round(2 * FP64_PEAK_TFLOPS / 2 / OPS_PER_MADD_ALG, 3)}
     torch.cuda.synchronize()
     b.mpdd_destroy(h)

@@ -96,6 +96,26 @@ int mpdd_Rsyrk(mpdd_handle h, const char *uplo, const char *trans, mpdd_int n, m
                mpdd_dd alpha, const double *A_hi, const double *A_lo, mpdd_int lda,
                mpdd_dd beta, double *C_hi, double *C_lo, mpdd_int ldc, void *stream);
 
+/* ---- MPBLAS-shaped host entry points ---------------------------------------------
+ *
+ * The manual's MPBLAS Rgemm / Rsyrk take dd_real arrays in host memory (QD's
+ * layout: each entry a {hi, lo} pair of binary64, column-major with a
+ * leading dimension; sections "How to use reference MPBLAS" and "CUDA
+ * accelerated MPBLAS", where the CUDA dd library replaces the CPU one behind
+ * the same prototype).  These entry points take exactly that: A, B, C are
+ * HOST pointers to mpdd_dd arrays.  The call copies the operands to the
+ * device, runs mpdd_Rgemm / mpdd_Rsyrk, copies C back and returns when C is
+ * complete (synchronous).  Same info codes and BLAS semantics as the device
+ * calls; the whole of C (ldc x n) is copied both ways, so padding rows and
+ * (Rsyrk) the opposite triangle come back unchanged.  Scratch device memory
+ * is allocated and freed inside the call. */
+int mpdd_Rgemm_host(mpdd_handle h, const char *transa, const char *transb, mpdd_int m,
+                    mpdd_int n, mpdd_int k, mpdd_dd alpha, const mpdd_dd *A, mpdd_int lda,
+                    const mpdd_dd *B, mpdd_int ldb, mpdd_dd beta, mpdd_dd *C, mpdd_int ldc);
+int mpdd_Rsyrk_host(mpdd_handle h, const char *uplo, const char *trans, mpdd_int n, mpdd_int k,
+                    mpdd_dd alpha, const mpdd_dd *A, mpdd_int lda, mpdd_dd beta, mpdd_dd *C,
+                    mpdd_int ldc);
+
 /* ---- explicit algorithm and tile choice ------------------------------------ */
 
 #define MPDD_PLAIN 0          /* lean dd multiply-accumulate (12 binary64 ops per

@@ -90,6 +90,9 @@ SIGNATURES = {
                                                 ctypes.POINTER(ctypes.c_int)]),
     "mpdd_ozaki_split": (ctypes.c_int, [_P, ctypes.c_int, _C, _I, _I, _P, _P, _I, ctypes.c_int,
                                         _P, _P, _I, _I, _P]),
+    "mpdd_Rgemm_host": (ctypes.c_int, [_P, _C, _C, _I, _I, _I, mpdd_dd, _P, _I, _P, _I, mpdd_dd,
+                                       _P, _I]),
+    "mpdd_Rsyrk_host": (ctypes.c_int, [_P, _C, _C, _I, _I, mpdd_dd, _P, _I, mpdd_dd, _P, _I]),
     "mpdd_struct_size": (ctypes.c_size_t, [_C]),
     "mpdd_clock": (ctypes.c_double, []),
     "mpdd_server_create": (ctypes.c_int, [ctypes.POINTER(_P), _P, ctypes.c_size_t, ctypes.c_int,
@@ -205,6 +208,29 @@ def mpdd_Rsyrk_ex(h, opts, uplo, trans, n, k, alpha, A, lda, beta, C, ldc, strea
     return load().mpdd_Rsyrk_ex(h, ctypes.byref(o) if o is not None else None, _flag(uplo),
                                 _flag(trans), n, k, _dd(alpha), _ptr(A[0]), _ptr(A[1]), lda,
                                 _dd(beta), _ptr(C[0]), _ptr(C[1]), ldc, _stream(stream))
+
+
+def _host_pairs(x):
+    """Pointer to an interleaved {hi, lo} host array: a numpy float64 array of
+    shape (..., 2) / length 2*count, or None."""
+    if x is None:
+        return None
+    import numpy as np
+    assert x.dtype == np.float64 and x.flags.c_contiguous
+    return x.ctypes.data
+
+
+def mpdd_Rgemm_host(h, transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc):
+    """MPBLAS-shaped Rgemm on host dd_real arrays (numpy float64, {hi, lo}
+    interleaved).  Synchronous; returns info."""
+    return load().mpdd_Rgemm_host(h, _flag(transa), _flag(transb), m, n, k, _dd(alpha),
+                                  _host_pairs(A), lda, _host_pairs(B), ldb, _dd(beta),
+                                  _host_pairs(C), ldc)
+
+
+def mpdd_Rsyrk_host(h, uplo, trans, n, k, alpha, A, lda, beta, C, ldc):
+    return load().mpdd_Rsyrk_host(h, _flag(uplo), _flag(trans), n, k, _dd(alpha),
+                                  _host_pairs(A), lda, _dd(beta), _host_pairs(C), ldc)
 
 
 def mpdd_ozaki_digit_widths(algo, k, nslices):

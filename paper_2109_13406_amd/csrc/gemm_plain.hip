@@ -442,6 +442,39 @@ __global__ void __launch_bounds__(256) dd_scale_kernel(GemmParams p) {
   p.c_lo[ci] = r.lo;
 }
 
+// {hi, lo} pairs (QD's dd_real layout) <-> separate hi / lo planes.
+__global__ void __launch_bounds__(256)
+dd_split_pairs(const double* __restrict__ pairs, double* __restrict__ hi, double* __restrict__ lo,
+               int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double2 v = reinterpret_cast<const double2*>(pairs)[i];
+  hi[i] = v.x;
+  lo[i] = v.y;
+}
+
+__global__ void __launch_bounds__(256)
+dd_join_pairs(const double* __restrict__ hi, const double* __restrict__ lo,
+              double* __restrict__ pairs, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  reinterpret_cast<double2*>(pairs)[i] = make_double2(hi[i], lo[i]);
+}
+
+hipError_t launch_split_pairs(const double* pairs, double* hi, double* lo, int64_t n,
+                              hipStream_t st) {
+  hipLaunchKernelGGL(dd_split_pairs, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, pairs,
+                     hi, lo, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_join_pairs(const double* hi, const double* lo, double* pairs, int64_t n,
+                             hipStream_t st) {
+  hipLaunchKernelGGL(dd_join_pairs, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, hi, lo,
+                     pairs, n);
+  return hipGetLastError();
+}
+
 // ---- tile table and launchers ------------------------------------------------
 
 // id, BM, BN, BK, RM, RN, XM  (threads = (BM/RM) * (BN/RN); XM: cross terms of

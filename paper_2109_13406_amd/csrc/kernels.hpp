@@ -56,6 +56,11 @@ hipError_t launch_grouped_list(int tile, const char* base, const ServeReq* reqs,
                                const int* counts, const int* items_offset, int which, int grid,
                                hipStream_t st);
 hipError_t launch_scale(const GemmParams& p, hipStream_t st);
+// {hi, lo} pairs <-> hi / lo planes (n elements).
+hipError_t launch_split_pairs(const double* pairs, double* hi, double* lo, int64_t n,
+                              hipStream_t st);
+hipError_t launch_join_pairs(const double* hi, const double* lo, double* pairs, int64_t n,
+                             hipStream_t st);
 
 }  // namespace mpdd
 

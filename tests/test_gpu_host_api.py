@@ -1,0 +1,103 @@
+"""GPU parity of the MPBLAS-shaped host entry points (dd_real {hi, lo} pairs in
+host memory): results equal the oracle's within 8 k 2^-104, the worked example
+is exact, beta = 0 ignores NaN in C, padding rows and the opposite triangle
+come back bit-identical, and the info codes match the device calls'."""
+import numpy as np
+import pytest
+
+import oracle
+import pins
+import workloads as W
+from gpu_util import log
+from oracle.compare import RATIO_MAX, bits, ratio
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def h():
+    import torch
+    from paper_2109_13406_amd import binding as b
+    assert torch.cuda.is_available()
+    handle = b.mpdd_create()
+    yield handle
+    torch.cuda.synchronize()
+    b.mpdd_destroy(handle)
+
+
+def pairs(pl):
+    """(hi, lo) planes -> interleaved {hi, lo} array of shape (n, 2)."""
+    return np.ascontiguousarray(np.stack([pl[0], pl[1]], axis=1))
+
+
+def planes(pr):
+    return pr[:, 0].copy(), pr[:, 1].copy()
+
+
+def test_worked_example_host(h):
+    from paper_2109_13406_amd import binding as b
+    alpha, beta, v = pins.read_worked_example()
+    z = np.zeros(9)
+    A = pairs((pins.colmajor(v["A"]), z))
+    B = pairs((pins.colmajor(v["B"]), z))
+    C = pairs((pins.colmajor(v["C"]), z))
+    assert b.mpdd_Rgemm_host(h, "n", "n", 3, 3, 3, alpha, A, 3, B, 3, beta, C, 3) == 0
+    assert np.array_equal(C[:, 0], pins.colmajor(v["ANSWER"])) and np.all(C[:, 1] == 0)
+
+
+@pytest.mark.parametrize("op", W.OPS)
+def test_rgemm_host_vs_oracle(h, op):
+    from paper_2109_13406_amd import binding as b
+    for (m, n, k) in [(97, 131, 77), (1, 1, 1), (130, 65, 200)]:
+        for beta_zero in (False, True):
+            case = W.gemm_case(1500 + m, op[0], op[1], m, n, k, dist="wide",
+                               beta_zero=beta_zero, c_nan=beta_zero)
+            O = (case["C"][0].copy(), case["C"][1].copy())
+            assert oracle.rgemm(op[0], op[1], m, n, k, case["alpha"], case["A"], case["lda"],
+                                case["B"], case["ldb"], case["beta"], O, case["ldc"]) == 0
+            C = pairs(case["C"])
+            info = b.mpdd_Rgemm_host(h, op[0], op[1], m, n, k, case["alpha"], pairs(case["A"]),
+                                     case["lda"], pairs(case["B"]), case["ldb"], case["beta"], C,
+                                     case["ldc"])
+            assert info == 0
+            G = planes(C)
+            i, j = np.meshgrid(np.arange(m), np.arange(n), indexing="ij")
+            idx = (i + j * case["ldc"]).ravel()
+            r = ratio(G[0][idx], G[1][idx], O[0][idx], O[1][idx], k)
+            assert r <= RATIO_MAX, (op, m, n, k, r)
+            rest = np.ones(G[0].shape[0], bool)
+            rest[idx] = False
+            assert np.array_equal(bits(G[0])[rest], bits(case["C"][0])[rest])
+    log(f"PARITY host-pointer Rgemm {op} ok")
+
+
+@pytest.mark.parametrize("uplo", "UL")
+@pytest.mark.parametrize("trans", "NT")
+def test_rsyrk_host_vs_oracle(h, uplo, trans):
+    from paper_2109_13406_amd import binding as b
+    n, k = 97, 45
+    case = W.syrk_case(1600, uplo, trans, n, k, dist="wide")
+    O = (case["C"][0].copy(), case["C"][1].copy())
+    assert oracle.rsyrk(uplo, trans, n, k, case["alpha"], case["A"], case["lda"], case["beta"], O,
+                        case["ldc"]) == 0
+    C = pairs(case["C"])
+    assert b.mpdd_Rsyrk_host(h, uplo, trans, n, k, case["alpha"], pairs(case["A"]), case["lda"],
+                             case["beta"], C, case["ldc"]) == 0
+    G = planes(C)
+    i, j = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    sel = (i <= j) if uplo == "U" else (i >= j)
+    idx = (i + j * case["ldc"])[sel]
+    assert ratio(G[0][idx], G[1][idx], O[0][idx], O[1][idx], k) <= RATIO_MAX
+    rest = np.ones(G[0].shape[0], bool)
+    rest[idx] = False
+    assert np.array_equal(bits(G[0])[rest], bits(case["C"][0])[rest])
+    assert np.array_equal(bits(G[1])[rest], bits(case["C"][1])[rest])
+
+
+def test_host_info_codes(h):
+    from paper_2109_13406_amd import binding as b
+    C = np.zeros((9, 2))
+    assert b.mpdd_Rgemm_host(h, "X", "N", 3, 3, 3, 1.0, None, 3, None, 3, 0.0, C, 3) == 1
+    assert b.mpdd_Rgemm_host(h, "N", "N", 3, 3, 3, 1.0, None, 2, None, 3, 0.0, C, 3) == 8
+    assert b.mpdd_Rsyrk_host(h, "U", "N", 3, 3, 1.0, None, 3, 0.0, C, 2) == 10
+    assert b.mpdd_Rgemm_host(h, "N", "N", 0, 3, 3, 1.0, None, 1, None, 3, 0.0, C, 1) == 0
