@@ -182,28 +182,32 @@ __device__ __forceinline__ void oz_tile_of(int b, int tiles, int nslices, int& d
 
 // ---- products: INT8 ---------------------------------------------------------------------
 
-// X_d tile (256 x 256) for anti-diagonal d: sum over t of Q_t(rows) Q'_{d-t}(cols)^T
+// X_d tile (WM x WN) for anti-diagonal d: sum over t of Q_t(rows) Q'_{d-t}(cols)^T
 // with k-contiguous int8 rows.  256 threads = 4 waves in a 2 x 2 grid; each
-// wave owns 128 x 128 outputs = 8 x 8 v_mfma_i32_16x16x64_i8 tiles (256
-// int32 accumulators, held in AGPRs), so each 16-byte LDS fragment feeds 8
-// MFMAs.  A stage holds a 256 x 128-byte block of each operand in LDS (two
-// MFMA k-steps: 2048 MFMA cycles per wave hide the next stage's global
-// loads; double buffered, 147 KB; rows padded to 144 bytes so 16 consecutive
-// rows' fragment reads spread over the banks).  For an MFMA, lane l supplies
-// row l % 16, bytes 16*(l/16) .. +15 of the k-step, for both operands, so
-// every k pairs up.  Accumulation is exact in int32.
-constexpr int I8_BM = 256;
-constexpr int I8_BN = 256;
-constexpr int I8_BK = 128;
-constexpr int I8_PITCH = 144;
+// wave owns (WM/2) x (WN/2) outputs = (WM/32) x (WN/32) v_mfma_i32_16x16x64_i8
+// tiles (int32 accumulators, held in AGPRs when they do not fit beside the
+// fragments), so each 16-byte LDS fragment feeds several MFMAs.  A stage holds
+// a W x 64-byte block of each operand in LDS (double buffered; rows padded to
+// 80 bytes so the fragment reads of 16 consecutive rows hit distinct banks).
+// For an MFMA, lane l supplies row l % 16, bytes 16*(l/16) .. +15 of the
+// k-step, for both operands, so every k pairs up.  Accumulation is exact in
+// int32.  Variants (selected by mpdd_opts.tile_id for the INT8 form):
+//   0: 256 x 256 (128 x 128 per wave, 1 workgroup per CU)
+//   1: 256 x 128 (128 x 64 per wave, 2 workgroups per CU)
+//   2: 128 x 128 (64 x 64 per wave)
+constexpr int I8_BK = 64;
+constexpr int I8_PITCH = 80;
+constexpr int I8_PAD = 256;     // slice rows are padded to this for every variant
 
+template <int WM, int WN>
 __global__ void __launch_bounds__(256)
 oz_gemm_i8(const int8_t* __restrict__ qa, const int8_t* __restrict__ qb, int32_t* __restrict__ x,
            int64_t kp, int64_t plane_a, int64_t plane_b, int64_t mp, int64_t np, int nslices,
            int tiles_m, int tiles_n) {
-  __shared__ __attribute__((aligned(16))) int8_t oz_smem[2 * (I8_BM + I8_BN) * I8_PITCH];
-  int8_t* As0 = oz_smem;
-  int8_t* Bs0 = oz_smem + 2 * I8_BM * I8_PITCH;
+  constexpr int FA = WM / 32, FB = WN / 32;    // 16-row fragments per wave
+  constexpr int EA = WM / 64, EB = WN / 64;    // 16-byte staging loads per thread
+  __shared__ __attribute__((aligned(16))) int8_t As[2][WM * I8_PITCH];
+  __shared__ __attribute__((aligned(16))) int8_t Bs[2][WN * I8_PITCH];
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
@@ -212,19 +216,19 @@ oz_gemm_i8(const int8_t* __restrict__ qa, const int8_t* __restrict__ qb, int32_t
   int d, tile;
   oz_tile_of(blockIdx.x, tiles_m * tiles_n, nslices, d, tile);
   const int bi = tile % tiles_m, bj = tile / tiles_m;
-  const int64_t i0 = (int64_t)bi * I8_BM, j0 = (int64_t)bj * I8_BN;
+  const int64_t i0 = (int64_t)bi * WM, j0 = (int64_t)bj * WN;
 
-  v4i acc[8][8];
+  v4i acc[FA][FB];
 #pragma unroll
-  for (int a = 0; a < 8; ++a)
+  for (int a = 0; a < FA; ++a)
 #pragma unroll
-    for (int c = 0; c < 8; ++c) acc[a][c] = v4i{0, 0, 0, 0};
+    for (int c = 0; c < FB; ++c) acc[a][c] = v4i{0, 0, 0, 0};
 
-  // staging: thread loads 16-byte chunk (tid % 8) of rows tid/8 + 32*e, e < 8
-  const int srow = tid >> 3, scol = (tid & 7) * 16;
+  // staging: thread loads 16 bytes (chunk tid%4) of rows tid/4 + 64*e
+  const int srow = tid >> 2, scol = (tid & 3) * 16;
   const int64_t ksteps = kp / I8_BK;
   const int64_t total = (int64_t)(d - 1) * ksteps;
-  v4i ra[8], rb[8];
+  v4i ra[EA], rb[EB];
 
   auto gload = [&](int64_t s) {
     const int t = 1 + (int)(s / ksteps);          // slice of op(A); op(B) slice d - t
@@ -232,19 +236,15 @@ oz_gemm_i8(const int8_t* __restrict__ qa, const int8_t* __restrict__ qb, int32_t
     const int8_t* pa = qa + (int64_t)(t - 1) * plane_a + (i0 + srow) * kp + l0 + scol;
     const int8_t* pb = qb + (int64_t)(d - t - 1) * plane_b + (j0 + srow) * kp + l0 + scol;
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      ra[e] = *(const v4i*)(pa + 32 * e * kp);
-      rb[e] = *(const v4i*)(pb + 32 * e * kp);
-    }
+    for (int e = 0; e < EA; ++e) ra[e] = *(const v4i*)(pa + 64 * e * kp);
+#pragma unroll
+    for (int e = 0; e < EB; ++e) rb[e] = *(const v4i*)(pb + 64 * e * kp);
   };
   auto sstore = [&](int buf) {
-    int8_t* As = As0 + buf * I8_BM * I8_PITCH;
-    int8_t* Bs = Bs0 + buf * I8_BN * I8_PITCH;
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      *(v4i*)&As[(srow + 32 * e) * I8_PITCH + scol] = ra[e];
-      *(v4i*)&Bs[(srow + 32 * e) * I8_PITCH + scol] = rb[e];
-    }
+    for (int e = 0; e < EA; ++e) *(v4i*)&As[buf][(srow + 64 * e) * I8_PITCH + scol] = ra[e];
+#pragma unroll
+    for (int e = 0; e < EB; ++e) *(v4i*)&Bs[buf][(srow + 64 * e) * I8_PITCH + scol] = rb[e];
   };
 
   gload(0);
@@ -253,27 +253,19 @@ oz_gemm_i8(const int8_t* __restrict__ qa, const int8_t* __restrict__ qb, int32_t
   const int fr = lane & 15, fk = (lane >> 4) * 16;
   for (int64_t s = 0; s < total; ++s) {
     const int cur = (int)(s & 1);
-    const int8_t* As = As0 + cur * I8_BM * I8_PITCH;
-    const int8_t* Bs = Bs0 + cur * I8_BN * I8_PITCH;
     if (s + 1 < total) gload(s + 1);
+    v4i af[FA], bf[FB];
 #pragma unroll
-    for (int kk = 0; kk < I8_BK; kk += 64) {
-      v4i af[8], bf[8];
+    for (int a = 0; a < FA; ++a)
+      af[a] = *(const v4i*)&As[cur][(wm * (WM / 2) + a * 16 + fr) * I8_PITCH + fk];
 #pragma unroll
-      for (int a = 0; a < 8; ++a)
-        af[a] = *(const v4i*)&As[(wm * 128 + a * 16 + fr) * I8_PITCH + kk + fk];
+    for (int c = 0; c < FB; ++c)
+      bf[c] = *(const v4i*)&Bs[cur][(wn * (WN / 2) + c * 16 + fr) * I8_PITCH + fk];
 #pragma unroll
-      for (int c = 0; c < 8; ++c)
-        bf[c] = *(const v4i*)&Bs[(wn * 128 + c * 16 + fr) * I8_PITCH + kk + fk];
+    for (int a = 0; a < FA; ++a)
 #pragma unroll
-      for (int a = 0; a < 8; ++a)
-#pragma unroll
-        for (int c = 0; c < 8; ++c)
-          acc[a][c] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af[a], bf[c], acc[a][c], 0, 0, 0);
-      // keep the next k-step's fragment reads below this one's MFMAs (one set
-      // of fragments live at a time)
-      asm volatile("" ::: "memory");
-    }
+      for (int c = 0; c < FB; ++c)
+        acc[a][c] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af[a], bf[c], acc[a][c], 0, 0, 0);
     if (s + 1 < total) sstore(cur ^ 1);
     __syncthreads();
   }
@@ -281,11 +273,11 @@ oz_gemm_i8(const int8_t* __restrict__ qa, const int8_t* __restrict__ qb, int32_t
   // C layout of a 16x16 INT8 MFMA tile: lane l holds rows 4*(l/16) + 0..3 of column l%16.
   int32_t* xd = x + (int64_t)(d - 2) * mp * np;
 #pragma unroll
-  for (int a = 0; a < 8; ++a)
+  for (int a = 0; a < FA; ++a)
 #pragma unroll
-    for (int c = 0; c < 8; ++c) {
-      const int64_t i = i0 + wm * 128 + a * 16 + (lane >> 4) * 4;
-      const int64_t j = j0 + wn * 128 + c * 16 + (lane & 15);
+    for (int c = 0; c < FB; ++c) {
+      const int64_t i = i0 + wm * (WM / 2) + a * 16 + (lane >> 4) * 4;
+      const int64_t j = j0 + wn * (WN / 2) + c * 16 + (lane & 15);
       *(v4i*)&xd[j * mp + i] = acc[a][c];
     }
 }
@@ -479,9 +471,13 @@ int ozaki_gemm(const void* opts_v, bool ta, bool tb, int64_t m, int64_t n, int64
   if (!digit_widths(algo, k, s, wfirst, w)) return MPDD_ERR_UNSUPPORTED;
 
   const bool i8 = (algo == MPDD_OZAKI_I8);
-  const int64_t kp = round_up(k, i8 ? I8_BK : OZ_KPAD);
-  const int64_t tbm = i8 ? I8_BM : OZ_BM, tbn = i8 ? I8_BN : OZ_BN;
-  const int64_t mp = round_up(m, tbm), np = round_up(n, tbn);
+  const int64_t kp = round_up(k, OZ_KPAD);
+  // INT8 product variant (tile_id) and its workgroup tile
+  const int var = (i8 && opts->tile_id >= 0) ? opts->tile_id : 0;
+  if (i8 && var > 2) return MPDD_ERR_UNSUPPORTED;
+  const int64_t tbm = i8 ? (var == 2 ? 128 : 256) : OZ_BM;
+  const int64_t tbn = i8 ? (var == 0 ? 256 : 128) : OZ_BN;
+  const int64_t mp = round_up(m, i8 ? I8_PAD : OZ_BM), np = round_up(n, i8 ? I8_PAD : OZ_BN);
   const size_t esz = i8 ? 1 : 8;
   const size_t xsz = i8 ? 4 : 8;
   const size_t qa_bytes = (size_t)s * mp * kp * esz;
@@ -521,10 +517,13 @@ int ozaki_gemm(const void* opts_v, bool ta, bool tb, int64_t m, int64_t n, int64
   const int tiles_m = (int)(mp / tbm), tiles_n = (int)(np / tbn);
   const unsigned nblocks = (unsigned)(tiles_m * tiles_n * s);
   if (e == hipSuccess) {
-    if (i8)
-      hipLaunchKernelGGL(oz_gemm_i8, dim3(nblocks), dim3(256), 0, st, (const int8_t*)qa,
+    if (i8) {
+      auto kern = (var == 0) ? oz_gemm_i8<256, 256> : (var == 1) ? oz_gemm_i8<256, 128>
+                                                                 : oz_gemm_i8<128, 128>;
+      hipLaunchKernelGGL(kern, dim3(nblocks), dim3(256), 0, st, (const int8_t*)qa,
                          (const int8_t*)qb, (int32_t*)x, kp, mp * kp, np * kp, mp, np, s, tiles_m,
                          tiles_n);
+    }
     else
       hipLaunchKernelGGL(oz_gemm_f64, dim3(nblocks), dim3(256), 0, st, (const double*)qa,
                          (const double*)qb, (double*)x, kp, mp * kp, np * kp, mp, np, s, tiles_m,
