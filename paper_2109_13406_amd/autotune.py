@@ -75,6 +75,32 @@ def tune_shape(h, op, ta, tb, m, n, k, reps=3, splits=(1, 2, 4, 8, 16), verbose=
     return best, results
 
 
+def tune_ozaki(h, n, kind="i8", slices=(13, 16), reps=2, verbose=True):
+    """Time the split form's product-kernel variants (tile_id) at m = n = k."""
+    if ROOT not in sys.path:
+        sys.path.insert(0, ROOT)
+    import workloads as W
+    from paper_2109_13406_amd import binding as b
+    algo = b.MPDD_OZAKI_I8 if kind == "i8" else b.MPDD_OZAKI_F64
+    case = W.gemm_case_device(4321, "N", "N", n, n, n, padded=False)
+    out = []
+    for var in range(3 if kind == "i8" else 1):
+        for sl in slices:
+            opts = dict(algo=algo, nslices=sl, tile_id=var)
+            fn = lambda: b.mpdd_Rgemm_ex(h, opts, "N", "N", n, n, n, case["alpha"], case["A"],
+                                         case["lda"], case["B"], case["ldb"], case["beta"],
+                                         case["C"], case["ldc"])
+            if fn() != 0:
+                continue
+            t = _time(fn, reps)
+            out.append(dict(variant=var, nslices=sl, seconds=t, dd_gflops=2.0 * n ** 3 / t / 1e9,
+                            int8_tops=sl * (sl + 1) / 2 * 2.0 * n ** 3 / t / 1e12))
+            if verbose:
+                print(f"  ozaki {kind} n={n} variant {var} s={sl}: {t*1e3:.2f} ms "
+                      f"{out[-1]['int8_tops']:.0f} T(int)ops/s", flush=True)
+    return out
+
+
 SHAPE_SETS = {
     "bench": [("gemm", "N", "N", 8192, 8192, 8192), ("gemm", "N", "N", 4096, 4096, 4096),
               ("gemm", "N", "N", 8192, 64, 8192), ("gemm", "N", "N", 4096, 4096, 256),
@@ -120,6 +146,12 @@ def main():
     import torch
     from paper_2109_13406_amd import binding as b
     h = b.mpdd_create()
+    if args.shapes == "ozaki":
+        rep = {n: tune_ozaki(h, n) for n in (4096, 8192)}
+        with open(args.out, "w") as f:
+            json.dump(rep, f, indent=1)
+        b.mpdd_destroy(h)
+        return
     shapes = serve_shapes() if args.shapes == "serve" else SHAPE_SETS[args.shapes]
     entries, report = [], []
     for (op, ta, tb, m, n, k) in shapes:
