@@ -129,7 +129,10 @@ int mpdd_Rsyrk_host(mpdd_handle h, const char *uplo, const char *trans, mpdd_int
 typedef struct {
   int algo;     /* MPDD_PLAIN, MPDD_OZAKI_I8, MPDD_OZAKI_F64, MPDD_PLAIN_ACCURATE */
   int nslices;  /* split form: slices per operand, 0 = default for the input */
-  int tile_id;  /* plain forms: index into the tile table, -1 = tuned choice */
+  int tile_id;  /* plain forms: index into the tile table, -1 = tuned choice;
+                   INT8 split form: product workgroup tile, 0 = 256x256,
+                   1 = 256x128, 2 = 128x128, -1 = default (all give the same
+                   bits); ignored by the FP64 split form */
   int splitk;   /* plain forms: k-split factor, 0 = automatic, 1 = none */
 } mpdd_opts;
 

@@ -77,6 +77,9 @@ def _bind(lib):
                                        _I64, _DD, _D, _D, _I64, ctypes.c_int, ctypes.c_int,
                                        ctypes.c_int]
     lib.oracle_ozaki_Rgemm.restype = ctypes.c_int
+    lib.oracle_Cgemm.argtypes = [c, c, _I64, _I64, _I64, _D, _D, _D, _D, _D, _I64, _D, _D, _D,
+                                 _D, _I64, _D, _D, _D, _D, _D, _I64]
+    lib.oracle_Cgemm.restype = ctypes.c_int
     return lib
 
 
@@ -132,6 +135,26 @@ def rgemm(transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, lib=None
     return lib.oracle_Rgemm(_flag(transa), _flag(transb), m, n, k, _dd(alpha),
                             _p(A[0]), _p(A[1]), lda, _p(B[0]), _p(B[1]), ldb,
                             _dd(beta), _p(C[0]), _p(C[1]), ldc)
+
+
+def _cdd(x):
+    """complex dd scalar ((re_hi, re_lo), (im_hi, im_lo)), or a Python complex
+    (binary64 parts) -> float64[4] = re.hi, re.lo, im.hi, im.lo."""
+    if isinstance(x, complex) or np.isscalar(x):
+        x = complex(x)
+        return np.array([x.real, 0.0, x.imag, 0.0])
+    (rh, rl), (ih, il) = x
+    return np.array([rh, rl, ih, il], dtype=np.float64)
+
+
+def cgemm(transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, lib=None):
+    """In-place oracle Cgemm; A, B, C are 4-tuples of planes (re.hi, re.lo,
+    im.hi, im.lo); A, B may be 4-tuples of None when alpha == 0 or k == 0.
+    Returns info."""
+    lib = lib or load()
+    al, be = _cdd(alpha), _cdd(beta)
+    return lib.oracle_Cgemm(_flag(transa), _flag(transb), m, n, k, _p(al), *map(_p, A), lda,
+                            *map(_p, B), ldb, _p(be), *map(_p, C), ldc)
 
 
 def rsyrk(uplo, trans, n, k, alpha, A, lda, beta, C, ldc, lib=None):

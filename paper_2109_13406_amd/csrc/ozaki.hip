@@ -168,16 +168,28 @@ oz_slice(const double* __restrict__ xh, const double* __restrict__ xl, int64_t s
   }
 }
 
-// Workgroup b -> (anti-diagonal d, C tile).  Groups of `tiles` workgroups
-// share one d, largest d (longest sum) first.  Inside a group the tile index
-// is remapped so that each of the 8 XCDs (workgroups are dealt to them
-// round-robin) receives a contiguous run of tiles, i.e. a few column panels of
-// op(B) that then stay in its L2.
-__device__ __forceinline__ void oz_tile_of(int b, int tiles, int nslices, int& d, int& tile) {
+// Workgroup b -> (anti-diagonal d, C tile (bi, bj)).  Groups of tiles_m *
+// tiles_n workgroups share one d, largest d (longest sum) first.  Inside a
+// group, each of the 8 XCDs (workgroups are dealt to them round-robin)
+// receives a contiguous run of the tile sequence, and that sequence walks the
+// C grid in 8 x 8 super-tiles (bi fastest inside one): the workgroups an XCD
+// runs at the same time then cover a compact block of C and read a few row
+// panels of op(A) and column panels of op(B), which its L2 holds, instead of
+// every row panel of op(A) against one column panel.
+__device__ __forceinline__ void oz_tile_of(int b, int tiles_m, int tiles_n, int nslices, int& d,
+                                           int& bi, int& bj) {
+  const int tiles = tiles_m * tiles_n;
   d = nslices + 1 - b / tiles;
   int r = b % tiles;
   if ((tiles & 7) == 0) r = (r & 7) * (tiles >> 3) + (r >> 3);
-  tile = r;
+  if ((tiles_m & 7) == 0 && (tiles_n & 7) == 0) {
+    const int st = r >> 6, w = r & 63, stm = tiles_m >> 3;
+    bi = (st % stm) * 8 + (w & 7);
+    bj = (st / stm) * 8 + (w >> 3);
+  } else {
+    bi = r % tiles_m;
+    bj = r / tiles_m;
+  }
 }
 
 // ---- products: INT8 ---------------------------------------------------------------------
@@ -213,9 +225,8 @@ oz_gemm_i8(const int8_t* __restrict__ qa, const int8_t* __restrict__ qb, int32_t
   const int wave = tid >> 6;
   const int wm = wave & 1, wn = wave >> 1;
 
-  int d, tile;
-  oz_tile_of(blockIdx.x, tiles_m * tiles_n, nslices, d, tile);
-  const int bi = tile % tiles_m, bj = tile / tiles_m;
+  int d, bi, bj;
+  oz_tile_of(blockIdx.x, tiles_m, tiles_n, nslices, d, bi, bj);
   const int64_t i0 = (int64_t)bi * WM, j0 = (int64_t)bj * WN;
 
   v4i acc[FA][FB];
@@ -302,9 +313,8 @@ oz_gemm_f64(const double* __restrict__ qa, const double* __restrict__ qb, double
   const int wave = tid >> 6;
   const int wm = wave & 1, wn = wave >> 1;
 
-  int d, tile;
-  oz_tile_of(blockIdx.x, tiles_m * tiles_n, nslices, d, tile);
-  const int bi = tile % tiles_m, bj = tile / tiles_m;
+  int d, bi, bj;
+  oz_tile_of(blockIdx.x, tiles_m, tiles_n, nslices, d, bi, bj);
   const int64_t i0 = (int64_t)bi * OZ_BM, j0 = (int64_t)bj * OZ_BN;
 
   v4d acc[4][4];

@@ -467,3 +467,287 @@ def check_primitives(lib, count=400):
         z = oracle.dd_add(x, y, lib=lib)
         ex = F(*x) + F(*y)
         assert abs(F(*z) - ex) <= (3 * U2 + 13 * U2 / 2 ** 53) * abs(ex), (t, x, y)
+
+
+# ---- complex dd Cgemm ----------------------------------------------------------------
+
+def read_cgemm_example():
+    """The manual's Cgemm demo as decimal strings: dict with alpha, beta ((re, im)
+    strings) and A, B, C, ANSWER_BINARY64, ANSWER_DECIMAL (3 x 3 lists of
+    (re, im) strings, row by row)."""
+    out = {"A": [], "B": [], "C": [], "ANSWER_BINARY64": [], "ANSWER_DECIMAL": []}
+    with open(os.path.join(GOLDEN, "cgemm_worked_example.txt")) as f:
+        for line in f:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            key, rest = line.split(None, 1)
+            ents = [tuple(e.split()) for e in rest.split("|")]
+            if key in ("alpha", "beta"):
+                out[key] = ents[0]
+            else:
+                out[key].append(ents)
+    return out
+
+
+def _dd_of(x):
+    """Nearest dd (hi, lo) of an exact rational."""
+    hi = float(x)
+    return hi, float(x - Fraction(hi))
+
+
+def _cplanes(rows, conv):
+    """3 x 3 (re, im) entries -> four column-major planes through conv(str) -> (hi, lo)."""
+    n = len(rows)
+    planes = [np.zeros(n * n) for _ in range(4)]
+    for i in range(n):
+        for j in range(n):
+            (rh, rl), (ih, il) = conv(rows[i][j][0]), conv(rows[i][j][1])
+            for p, v in zip(planes, (rh, rl, ih, il)):
+                p[i + j * n] = v
+    return tuple(planes)
+
+
+def _exact_cgemm(alpha, A, B, beta, C):
+    """alpha A B + beta C over the rationals; entries complex as (re, im) Fractions."""
+    n = len(A)
+
+    def mul(x, y):
+        return (x[0] * y[0] - x[1] * y[1], x[0] * y[1] + x[1] * y[0])
+
+    out = []
+    for i in range(n):
+        row = []
+        for j in range(n):
+            acc = (Fraction(0), Fraction(0))
+            for l in range(n):
+                p = mul(A[i][l], B[l][j])
+                acc = (acc[0] + p[0], acc[1] + p[1])
+            a, b = mul(alpha, acc), mul(beta, C[i][j])
+            row.append((a[0] + b[0], a[1] + b[1]))
+        out.append(row)
+    return out
+
+
+def cgemm_bound(k):
+    """Per-component first-order bound of the dd Cgemm evaluation in units of
+    (|alpha|_1 sum_l |a_il|_1 |b_lj|_1 + |beta|_1 |c_ij|_1), |z|_1 = |re| + |im|:
+    each complex product is two dd products and a dd add (7 u^2), each of the k
+    running sums adds 3 u^2, and alpha, beta and the final add another 17 u^2."""
+    return (3 * k + 24) * U2 * Fraction(101, 100)
+
+
+def _abs1(z):
+    return abs(z[0]) + abs(z[1])
+
+
+def check_cgemm_worked_example(lib):
+    ex = read_cgemm_example()
+    dec = lambda s: Fraction(s)                     # noqa: E731
+    b64 = lambda s: Fraction(float(s))              # noqa: E731
+    for conv, ans_key, inflate in ((b64, "ANSWER_BINARY64", 0), (dec, "ANSWER_DECIMAL", 6)):
+        A = [[(conv(r), conv(i)) for r, i in row] for row in ex["A"]]
+        B = [[(conv(r), conv(i)) for r, i in row] for row in ex["B"]]
+        C = [[(conv(r), conv(i)) for r, i in row] for row in ex["C"]]
+        al = (conv(ex["alpha"][0]), conv(ex["alpha"][1]))
+        be = (conv(ex["beta"][0]), conv(ex["beta"][1]))
+        exact = _exact_cgemm(al, A, B, be, C)
+        printed = [[(Fraction(r), Fraction(i)) for r, i in row] for row in ex[ans_key]]
+        # the fixture itself: the printed answer is the exact result (the decimal
+        # one exactly, the 64-digit one to its printed digits)
+        for i in range(3):
+            for j in range(3):
+                for c in range(2):
+                    d = abs(printed[i][j][c] - exact[i][j][c])
+                    assert d <= Fraction(1, 10 ** 60) * max(abs(exact[i][j][c]), 1), (ans_key, i, j)
+        # the oracle on the dd-rounded inputs (binary64 inputs are exact dd numbers)
+        todd = lambda s: _dd_of(conv(s))            # noqa: E731
+        Ap, Bp, Cp = _cplanes(ex["A"], todd), _cplanes(ex["B"], todd), _cplanes(ex["C"], todd)
+        alpha = (todd(ex["alpha"][0]), todd(ex["alpha"][1]))
+        beta = (todd(ex["beta"][0]), todd(ex["beta"][1]))
+        bnd = cgemm_bound(3) + inflate * U2
+        for ta, tb in W.COPS:
+            # op(X) of the transformed copy is X itself
+            def prep(P, t):
+                M = [p.reshape(3, 3, order="F") for p in P]
+                if t != "N":
+                    M = [m.T for m in M]
+                if t == "C":
+                    M[2], M[3] = -M[2], -M[3]
+                return tuple(colmajor(m) for m in M)
+            Cw = tuple(p.copy() for p in Cp)
+            info = oracle.cgemm(ta, tb, 3, 3, 3, alpha, prep(Ap, ta), 3, prep(Bp, tb), 3, beta, Cw,
+                                3, lib=lib)
+            assert info == 0
+            for i in range(3):
+                for j in range(3):
+                    idx = i + 3 * j
+                    scale = _abs1(al) * sum(_abs1(A[i][l]) * _abs1(B[l][j]) for l in range(3)) \
+                        + _abs1(be) * _abs1(C[i][j])
+                    got = (F(Cw[0][idx], Cw[1][idx]), F(Cw[2][idx], Cw[3][idx]))
+                    for c in range(2):
+                        err = abs(got[c] - printed[i][j][c])
+                        assert err <= bnd * scale + Fraction(1, 10 ** 60) * scale, (
+                            ans_key, ta, tb, i, j, c, float(err / scale))
+
+
+def _cop(planes, ld, t):
+    """op(X)(r, c) as an exact (re, im) pair of Fractions; t in N, T, C."""
+    rh, rl, ih, il = planes
+
+    def get(r, c):
+        idx = (c + r * ld) if t != "N" else (r + c * ld)
+        re, im = F(rh[idx], rl[idx]), F(ih[idx], il[idx])
+        return (re, -im) if t == "C" else (re, im)
+    return get
+
+
+def check_exact_cgemm(lib, seeds=range(2), dist="uniform",
+                      sizes=((1, 1, 1), (2, 3, 4), (4, 3, 2), (3, 1, 5))):
+    for seed in seeds:
+        for (m, n, k) in sizes:
+            for ta, tb in W.COPS:
+                c = W.cgemm_case(3000 + seed, ta, tb, m, n, k, dist=dist)
+                C0 = tuple(p.copy() for p in c["C"])
+                info = oracle.cgemm(ta, tb, m, n, k, c["alpha"], c["A"], c["lda"], c["B"],
+                                    c["ldb"], c["beta"], c["C"], c["ldc"], lib=lib)
+                assert info == 0
+                opA, opB = _cop(c["A"], c["lda"], ta), _cop(c["B"], c["ldb"], tb)
+                al = (F(*c["alpha"][0]), F(*c["alpha"][1]))
+                be = (F(*c["beta"][0]), F(*c["beta"][1]))
+                bnd = cgemm_bound(k)
+                for i in range(m):
+                    for j in range(n):
+                        idx = i + j * c["ldc"]
+                        c0 = (F(C0[0][idx], C0[1][idx]), F(C0[2][idx], C0[3][idx]))
+                        acc = [Fraction(0), Fraction(0)]
+                        mag = Fraction(0)
+                        for l in range(k):
+                            a, b = opA(i, l), opB(l, j)
+                            acc[0] += a[0] * b[0] - a[1] * b[1]
+                            acc[1] += a[0] * b[1] + a[1] * b[0]
+                            mag += _abs1(a) * _abs1(b)
+                        ex = (al[0] * acc[0] - al[1] * acc[1] + be[0] * c0[0] - be[1] * c0[1],
+                              al[0] * acc[1] + al[1] * acc[0] + be[0] * c0[1] + be[1] * c0[0])
+                        tol = bnd * (_abs1(al) * mag + _abs1(be) * _abs1(c0))
+                        got = (F(c["C"][0][idx], c["C"][1][idx]), F(c["C"][2][idx], c["C"][3][idx]))
+                        for q in range(2):
+                            assert abs(got[q] - ex[q]) <= tol, (seed, m, n, k, ta, tb, i, j, q)
+                            h = c["C"][2 * q][idx]
+                            assert h + c["C"][2 * q + 1][idx] == h      # normalised
+                # padding rows of every plane untouched
+                ldc = c["ldc"]
+                pad = np.ones(ldc * n, bool)
+                for j in range(n):
+                    pad[j * ldc: j * ldc + m] = False
+                for p, p0 in zip(c["C"], C0):
+                    assert np.array_equal(bits(p)[pad], bits(p0)[pad])
+
+
+def check_cgemm_identities(lib):
+    z = ((0.0, 0.0), (0.0, 0.0))
+    one = ((1.0, 0.0), (0.0, 0.0))
+    # 1. transposed and conjugate-transposed copies give the same bits
+    c = W.cgemm_case(3100, "N", "N", 5, 4, 6, dist="wide", padded=False)
+    ref = tuple(p.copy() for p in c["C"])
+    assert oracle.cgemm("N", "N", 5, 4, 6, c["alpha"], c["A"], 5, c["B"], 6, c["beta"], ref, 5,
+                        lib=lib) == 0
+
+    def copy_as(P, rows, cols, t):
+        M = [p[: rows * cols].reshape(rows, cols, order="F") for p in P]
+        if t == "N":
+            return tuple(colmajor(m) for m in M)
+        out = [colmajor(m.T) for m in M]
+        if t == "C":
+            out[2], out[3] = -out[2], -out[3]
+        return tuple(out)
+    for ta, tb in W.COPS:
+        A = copy_as(c["A"], 5, 6, ta)
+        B = copy_as(c["B"], 6, 4, tb)
+        Cw = tuple(p.copy() for p in c["C"])
+        assert oracle.cgemm(ta, tb, 5, 4, 6, c["alpha"], A, 5 if ta == "N" else 6, B,
+                            6 if tb == "N" else 4, c["beta"], Cw, 5, lib=lib) == 0
+        for p, q in zip(Cw, ref):
+            assert np.array_equal(bits(p), bits(q)), (ta, tb)
+    # 2. real data: the real parts equal the real oracle's result, imaginary parts 0
+    g = W.gemm_case(3101, "T", "N", 6, 5, 7, dist="wide")
+    zA, zB, zC = (np.zeros_like(g["A"][0]),) * 2, (np.zeros_like(g["B"][0]),) * 2, \
+        (np.zeros_like(g["C"][0]),) * 2
+    Cc = (g["C"][0].copy(), g["C"][1].copy()) + tuple(x.copy() for x in zC)
+    Rr = (g["C"][0].copy(), g["C"][1].copy())
+    for t in ("T", "C"):
+        Cw = tuple(p.copy() for p in Cc)
+        assert oracle.cgemm(t, "N", 6, 5, 7, (g["alpha"], (0.0, 0.0)), g["A"] + zA, g["lda"],
+                            g["B"] + zB, g["ldb"], (g["beta"], (0.0, 0.0)), Cw, g["ldc"],
+                            lib=lib) == 0
+        if t == "T":
+            assert oracle.rgemm("T", "N", 6, 5, 7, g["alpha"], g["A"], g["lda"], g["B"],
+                                g["ldb"], g["beta"], Rr, g["ldc"], lib=lib) == 0
+        i, j = np.meshgrid(np.arange(6), np.arange(5), indexing="ij")
+        idx = (i + j * g["ldc"]).ravel()
+        assert np.array_equal(Cw[0][idx], Rr[0][idx]) and np.array_equal(Cw[1][idx], Rr[1][idx])
+        assert not Cw[2][idx].any() and not Cw[3][idx].any()
+    # 3. alpha = 0, beta = 1: quick return, C bit-identical (NaN sentinel kept)
+    c = W.cgemm_case(3102, "N", "C", 4, 4, 4, c_nan=True)
+    Cw = tuple(p.copy() for p in c["C"])
+    assert oracle.cgemm("N", "C", 4, 4, 4, z, c["A"], c["lda"], c["B"], c["ldb"], one, Cw,
+                        c["ldc"], lib=lib) == 0
+    for p, q in zip(Cw, c["C"]):
+        assert np.array_equal(bits(p), bits(q))
+    # 4. beta = 0: C (all NaN) is not read; alpha = 0 as well gives exact zeros
+    for alpha in (c["alpha"], z):
+        Cw = tuple(p.copy() for p in c["C"])
+        assert oracle.cgemm("N", "C", 4, 4, 4, alpha, c["A"], c["lda"], c["B"], c["ldb"], z, Cw,
+                            c["ldc"], lib=lib) == 0
+        i, j = np.meshgrid(np.arange(4), np.arange(4), indexing="ij")
+        idx = (i + j * c["ldc"]).ravel()
+        for p in Cw:
+            assert np.all(np.isfinite(p[idx]))
+            if alpha is z:
+                assert not p[idx].any()
+    # 4b. alpha = 0 with a complex beta of real part 1: C <- beta C (not a quick
+    # return), checked against the exact product
+    bq = ((1.0, 0.0), (0.5, 0.0))
+    c = W.cgemm_case(3104, "N", "N", 3, 3, 3)
+    Cw = tuple(p.copy() for p in c["C"])
+    assert oracle.cgemm("N", "N", 3, 3, 3, z, c["A"], c["lda"], c["B"], c["ldb"], bq, Cw,
+                        c["ldc"], lib=lib) == 0
+    for j in range(3):
+        for i in range(3):
+            o = i + j * c["ldc"]
+            re, im = F(c["C"][0][o], c["C"][1][o]), F(c["C"][2][o], c["C"][3][o])
+            ex = (re - Fraction(1, 2) * im, im + Fraction(1, 2) * re)
+            got = (F(Cw[0][o], Cw[1][o]), F(Cw[2][o], Cw[3][o]))
+            for q in range(2):
+                assert abs(got[q] - ex[q]) <= 20 * U2 * (abs(re) + abs(im)), (i, j, q)
+    # 5. identity: A = I, alpha = 1, beta = 0 gives op(B) bit-exactly
+    n = 4
+    b = W.cgemm_case(3103, "N", "C", n, n, n, padded=False)
+    I = (np.eye(n).ravel(order="F"), np.zeros(n * n), np.zeros(n * n), np.zeros(n * n))
+    Cw = tuple(np.zeros(n * n) for _ in range(4))
+    assert oracle.cgemm("N", "C", n, n, n, one, I, n, b["B"], n, z, Cw, n, lib=lib) == 0
+    Bh = [p.reshape(n, n, order="F").T.ravel(order="F") for p in b["B"]]
+    assert np.array_equal(Cw[0], Bh[0]) and np.array_equal(Cw[1], Bh[1])
+    assert np.array_equal(Cw[2], -Bh[2]) and np.array_equal(Cw[3], -Bh[3])
+
+
+def check_cgemm_info_codes(lib):
+    pos = read_arg_positions()
+    z = ((0.0, 0.0), (0.0, 0.0))
+    C = tuple(np.zeros(16) for _ in range(4))
+    N = (None,) * 4
+
+    def info(ta="N", tb="N", m=2, n=2, k=2, lda=None, ldb=None, ldc=None):
+        lda = lda if lda is not None else max(1, m if ta == "N" else k)
+        ldb = ldb if ldb is not None else max(1, k if tb == "N" else n)
+        ldc = ldc if ldc is not None else max(1, m)
+        return oracle.cgemm(ta, tb, m, n, k, ((1.0, 0.0), (0.0, 0.0)), N, lda, N, ldb, z, C, ldc,
+                            lib=lib)
+    assert info(ta="X") == pos[("gemm", "transa")]
+    assert info(tb="Q") == pos[("gemm", "transb")]
+    assert info(m=-1) == pos[("gemm", "m")]
+    assert info(n=-1) == pos[("gemm", "n")]
+    assert info(k=-1) == pos[("gemm", "k")]
+    assert info(ta="C", m=3, k=2, lda=1) == pos[("gemm", "lda")]
+    assert info(tb="C", n=3, k=2, ldb=2) == pos[("gemm", "ldb")]
+    assert info(m=3, ldc=2) == pos[("gemm", "ldc")]

@@ -67,7 +67,8 @@ def test_slices_bit_identical(h, kind, trans, dist):
     log(f"PARITY ozaki slices {kind} {trans} {dist} bit-identical")
 
 
-SHAPES = [(1, 1, 1), (70, 90, 33), (129, 130, 200), (200, 64, 65)]
+SHAPES = [(1, 1, 1), (70, 90, 33), (129, 130, 200), (200, 64, 65), (300, 270, 130)]
+VARIANTS = (0, 1, 2)     # INT8 product tilings 256x256, 256x128, 128x128
 
 
 @pytest.mark.parametrize("kind", ["i8", "f64"])
@@ -83,10 +84,12 @@ def test_split_gemm_bit_identical_to_split_oracle(h, kind, op):
             assert oracle.ozaki_rgemm(op[0], op[1], m, n, k, case["alpha"], case["A"], case["lda"],
                                       case["B"], case["ldb"], case["beta"], O, case["ldc"], s, wf,
                                       w) == 0
-            info, G = gemm_gpu(h, case, opts=dict(algo=algo, nslices=s))
-            assert info == 0
-            assert np.array_equal(bits(G[0]), bits(O[0])), (kind, op, m, n, k, dist)
-            assert np.array_equal(bits(G[1]), bits(O[1])), (kind, op, m, n, k, dist)
+            # every INT8 product variant (workgroup tiling) must give the same bits
+            for var in (VARIANTS if kind == "i8" else (-1,)):
+                info, G = gemm_gpu(h, case, opts=dict(algo=algo, nslices=s, tile_id=var))
+                assert info == 0
+                assert np.array_equal(bits(G[0]), bits(O[0])), (kind, op, m, n, k, dist, var)
+                assert np.array_equal(bits(G[1]), bits(O[1])), (kind, op, m, n, k, dist, var)
     log(f"PARITY ozaki {kind} {op} bit-identical to the split oracle")
 
 
@@ -122,6 +125,9 @@ def test_split_semantics(h):
     assert np.array_equal(bits(G[0]), bits(O[0]))
     info, _ = gemm_gpu(h, W.gemm_case(73, "N", "N", 8, 8, 8),
                        opts=dict(algo=b.MPDD_OZAKI_I8, nslices=41))
+    assert info == b.MPDD_ERR_UNSUPPORTED
+    info, _ = gemm_gpu(h, W.gemm_case(74, "N", "N", 8, 8, 8),
+                       opts=dict(algo=b.MPDD_OZAKI_I8, nslices=12, tile_id=3))
     assert info == b.MPDD_ERR_UNSUPPORTED
 
 

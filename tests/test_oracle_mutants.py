@@ -12,6 +12,7 @@ import pins
 from oracle import build as obuild
 
 SRC = os.path.dirname(os.path.abspath(oracle.__file__))
+SOURCES = list(obuild.SOURCES)
 
 # (file, original text, planted mistake, what it models)
 MUTANTS = [
@@ -62,6 +63,23 @@ MUTANTS = [
      "ldexp((double)x, -(2 * wfirst + w * (d - 1)))", "wrong anti-diagonal weight"),
     ("ozaki_oracle.c", "p.hi = ldexp(p.hi, ea[i] + eb[j]);", "p.hi = ldexp(p.hi, ea[i]);",
      "column scale dropped"),
+    ("cdd_oracle.c", "r.re = dd_add(dd_mul(x.re, y.re), dd_neg(dd_mul(x.im, y.im)));",
+     "r.re = dd_add(dd_mul(x.re, y.re), dd_mul(x.im, y.im));", "complex product: sign of bd"),
+    ("cdd_oracle.c", "r.im = dd_add(dd_mul(x.re, y.im), dd_mul(x.im, y.re));",
+     "r.im = dd_add(dd_mul(x.re, y.im), dd_mul(x.im, y.im));",
+     "complex product: wrong cross term"),
+    ("cdd_oracle.c", "if (mode == 2) v.im = dd_neg(v.im);", "",
+     "conjugate transpose without conjugation"),
+    ("cdd_oracle.c", "if (mode == 2) v.im = dd_neg(v.im);", "if (mode >= 1) v.im = dd_neg(v.im);",
+     "plain transpose conjugated"),
+    ("cdd_oracle.c", "c = c_add(c, c_mul(beta, c0));", "c = c_add(c, c_mul(alpha, c0));",
+     "complex: alpha used for beta"),
+    ("cdd_oracle.c", "return x.re.hi == 1.0 && x.re.lo == 0.0 && dd_is_zero(x.im);",
+     "return x.re.hi == 1.0 && x.re.lo == 0.0;", "complex quick return ignores Im(beta)"),
+    ("cdd_oracle.c", "if (ldb < c_imax(1, nrowb)) return 10;", "if (ldb < c_imax(1, nrowa)) return 10;",
+     "complex: wrong ldb check"),
+    ("cdd_oracle.c", "for (l = 0; l < k; ++l)\n", "for (l = 1; l < k; ++l)\n",
+     "complex: dropped first term"),
 ]
 
 CHECKS = [
@@ -73,6 +91,10 @@ CHECKS = [
     pins.check_identities,
     lambda lib: pins.check_ozaki_split_exact(lib),
     pins.check_ozaki_gemm_exact,
+    pins.check_cgemm_worked_example,
+    lambda lib: pins.check_exact_cgemm(lib, seeds=[0]),
+    pins.check_cgemm_identities,
+    pins.check_cgemm_info_codes,
 ]
 
 
@@ -89,14 +111,14 @@ def _caught(lib):
 def test_mutant_is_caught(fname, orig, mut, what):
     tmp = tempfile.mkdtemp(prefix="oracle_mut_")
     try:
-        for f in ("dd_ops.h", "dd_oracle.c", "ozaki_oracle.c"):
+        for f in SOURCES + ["dd_ops.h"]:
             shutil.copy(os.path.join(SRC, f), tmp)
         path = os.path.join(tmp, fname)
         text = open(path).read()
         assert text.count(orig) == 1, f"mutation anchor not found once: {orig!r}"
         open(path, "w").write(text.replace(orig, mut))
         so = obuild.build(out=os.path.join(tmp, "libmut.so"),
-                          sources=["dd_oracle.c", "ozaki_oracle.c"], cwd=tmp,
+                          sources=SOURCES, cwd=tmp,
                           extra=["-I", tmp])
         lib = oracle.load(so)
         assert _caught(lib), f"planted mistake not caught: {what}"
@@ -108,10 +130,10 @@ def test_unmutated_copy_passes():
     """Control: the same harness on an unmodified copy passes every check."""
     tmp = tempfile.mkdtemp(prefix="oracle_ctl_")
     try:
-        for f in ("dd_ops.h", "dd_oracle.c", "ozaki_oracle.c"):
+        for f in SOURCES + ["dd_ops.h"]:
             shutil.copy(os.path.join(SRC, f), tmp)
         so = obuild.build(out=os.path.join(tmp, "libctl.so"),
-                          sources=["dd_oracle.c", "ozaki_oracle.c"], cwd=tmp,
+                          sources=SOURCES, cwd=tmp,
                           extra=["-I", tmp])
         assert not _caught(oracle.load(so))
     finally:

@@ -153,6 +153,46 @@ SQUARE_SIZES = (1024, 2048, 4096, 8192)
 OPS = ("NN", "NT", "TN", "TT")
 
 
+def cdd_matrix(rng, rows, cols, ld=None, dist="uniform", pad=True):
+    """Complex dd matrix: (re.hi, re.lo, im.hi, im.lo) flat planes, the real
+    part drawn first, then the imaginary part, each by dd_matrix's recipe."""
+    re = dd_matrix(rng, rows, cols, ld, dist, pad)
+    im = dd_matrix(rng, rows, cols, ld, dist, pad)
+    return re + im
+
+
+def cdd_scalar(rng, dist="uniform"):
+    return dd_scalar(rng, dist), dd_scalar(rng, dist)
+
+
+CTRANS = ("N", "T", "C")
+COPS = [(a, b) for a in CTRANS for b in CTRANS]
+
+
+def cgemm_case(seed, transa, transb, m, n, k, dist="uniform", padded=True, beta_zero=False,
+               c_nan=False):
+    """One seeded Cgemm case: A, B, C as 4-tuples of planes, alpha and beta as
+    ((re.hi, re.lo), (im.hi, im.lo))."""
+    ra, rb, rc, ral, rbe = streams(seed)
+    nra = m if transa.upper() == "N" else k
+    nca = k if transa.upper() == "N" else m
+    nrb = k if transb.upper() == "N" else n
+    ncb = n if transb.upper() == "N" else k
+    lda = ld_padded(nra) if padded else max(1, nra)
+    ldb = ld_padded(nrb) if padded else max(1, nrb)
+    ldc = ld_padded(m) if padded else max(1, m)
+    A = cdd_matrix(ra, nra, nca, lda, dist)
+    B = cdd_matrix(rb, nrb, ncb, ldb, dist)
+    C = cdd_matrix(rc, m, n, ldc, dist)
+    if c_nan:
+        fill_sentinel(*C[:2])
+        fill_sentinel(*C[2:])
+    alpha = cdd_scalar(ral, "uniform")
+    beta = ((0.0, 0.0), (0.0, 0.0)) if beta_zero else cdd_scalar(rbe, "uniform")
+    return dict(transa=transa, transb=transb, m=m, n=n, k=k, A=A, lda=lda, B=B, ldb=ldb,
+                C=C, ldc=ldc, alpha=alpha, beta=beta)
+
+
 def config1_runs():
     """Plain Rgemm runs: four op combinations x square sizes, plus the
     rectangular 4096x4096x256 and skinny 8192x64x8192 shapes."""
@@ -292,3 +332,26 @@ def syrk_case_device(seed, uplo, trans, n, k, dist="uniform", padded=True, beta_
     beta = (0.0, 0.0) if beta_zero else dd_scalar(rbe, "uniform")
     return dict(uplo=uplo, trans=trans, n=n, k=k, A=A, lda=lda, C=C, ldc=ldc, alpha=alpha,
                 beta=beta)
+
+
+def cgemm_case_device(seed, transa, transb, m, n, k, dist="uniform", padded=True,
+                      beta_zero=False, device="cuda"):
+    """Device version of cgemm_case (scalars from the numpy streams)."""
+    _, _, _, ral, rbe = streams(seed)
+    nra = m if transa.upper() == "N" else k
+    nca = k if transa.upper() == "N" else m
+    nrb = k if transb.upper() == "N" else n
+    ncb = n if transb.upper() == "N" else k
+    lda = ld_padded(nra) if padded else max(1, nra)
+    ldb = ld_padded(nrb) if padded else max(1, nrb)
+    ldc = ld_padded(m) if padded else max(1, m)
+    A = (dd_matrix_device(seed * 8 + 1, nra, nca, lda, dist, device)
+         + dd_matrix_device(seed * 8 + 4, nra, nca, lda, dist, device))
+    B = (dd_matrix_device(seed * 8 + 2, nrb, ncb, ldb, dist, device)
+         + dd_matrix_device(seed * 8 + 5, nrb, ncb, ldb, dist, device))
+    C = (dd_matrix_device(seed * 8 + 3, m, n, ldc, dist, device)
+         + dd_matrix_device(seed * 8 + 6, m, n, ldc, dist, device))
+    alpha = cdd_scalar(ral, "uniform")
+    beta = ((0.0, 0.0), (0.0, 0.0)) if beta_zero else cdd_scalar(rbe, "uniform")
+    return dict(transa=transa, transb=transb, m=m, n=n, k=k, A=A, lda=lda, B=B, ldb=ldb,
+                C=C, ldc=ldc, alpha=alpha, beta=beta)
