@@ -1,7 +1,7 @@
 """Benchmark: dd Rgemm on one MI355X, plain and split forms, plus served latency.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 8192] [--no-cpu]
-                    [--sections plain,syrk,ozaki,serve]
+                    [--sections plain,syrk,cgemm,ozaki,host,serve]
 
 One step = one dd Rgemm NN, m = n = k = n (8192), leading dimensions 8195,
 C <- alpha*A*B + beta*C on float64 hi/lo planes already resident in HBM.
@@ -137,6 +137,33 @@ def bench_syrk(h, args, stream):
     torch.cuda.empty_cache()
     return {"workload": f"Rsyrk U N n={n} k={n} ld={W.ld_padded(n)}", "ms": round(t * 1e3, 3),
             "dd_gflops": round(flops / t / 1e9, 1)}
+
+
+def bench_cgemm(h, args, stream):
+    """Complex dd Cgemm NN at n/2 (a quarter of the real product's memory per
+    plane, the same number of real dd multiply-adds as the real n/2 product x 4).
+    Complex flops: 8 mnk (LAWN 41: 6 real multiplies + 2 adds per complex
+    multiply-add)."""
+    import torch
+    import workloads as W
+    from paper_2109_13406_amd import binding as b
+    n = max(1, args.n // 2)
+    case = W.cgemm_case_device(W.BASE_SEED + 5, "N", "N", n, n, n)
+    torch.cuda.synchronize()
+
+    def step():
+        info = b.mpdd_Cgemm(h, "N", "N", n, n, n, case["alpha"], case["A"], case["lda"],
+                            case["B"], case["ldb"], case["beta"], case["C"], case["ldc"],
+                            stream=stream)
+        if info != 0:
+            raise RuntimeError(f"mpdd_Cgemm info={info}")
+
+    total, per = timed_calls(step, max(1, args.steps // 2), 1, stream)
+    t = sum(per) / len(per)
+    del case
+    torch.cuda.empty_cache()
+    return {"workload": f"Cgemm NN m=n=k={n} ld={W.ld_padded(n)} (four real dd planes each)",
+            "ms": round(t * 1e3, 3), "complex_dd_gflops": round(8.0 * n ** 3 / t / 1e9, 1)}
 
 
 def ratio_gpu(C, R, m, n, ldc, k):
@@ -288,7 +315,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=8192)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--sections", default="plain,syrk,ozaki,host,serve")
+    ap.add_argument("--sections", default="plain,syrk,cgemm,ozaki,host,serve")
     ap.add_argument("--tile", type=int, default=-1,
                     help="tile-table entry for the plain product (-1: the library's choice)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
@@ -351,6 +378,9 @@ def main():
     if "syrk" in sections:
         out["rsyrk"] = bench_syrk(h, args, stream)
         log(f"rsyrk: {out['rsyrk']}")
+    if "cgemm" in sections:
+        out["cgemm"] = bench_cgemm(h, args, stream)
+        log(f"cgemm: {out['cgemm']}")
     if "ozaki" in sections:
         out["ozaki"] = bench_ozaki(h, args, stream, t_kernel)
     if "host" in sections:

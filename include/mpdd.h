@@ -131,8 +131,8 @@ typedef struct {
   int nslices;  /* split form: slices per operand, 0 = default for the input */
   int tile_id;  /* plain forms: index into the tile table, -1 = tuned choice;
                    INT8 split form: product workgroup tile, 0 = 256x256,
-                   1 = 256x128, 2 = 128x128, -1 = default (all give the same
-                   bits); ignored by the FP64 split form */
+                   1 = 256x128, 2 = 128x128, -1 = default (1); all give the
+                   same bits; ignored by the FP64 split form */
   int splitk;   /* plain forms: k-split factor, 0 = automatic, 1 = none */
 } mpdd_opts;
 
@@ -150,6 +150,31 @@ int mpdd_Rsyrk_ex(mpdd_handle h, const mpdd_opts *opts, const char *uplo, const 
                   mpdd_int n, mpdd_int k, mpdd_dd alpha, const double *A_hi,
                   const double *A_lo, mpdd_int lda, mpdd_dd beta, double *C_hi,
                   double *C_lo, mpdd_int ldc, void *stream);
+
+/* ---- complex dd: Cgemm ------------------------------------------------------------
+ *
+ * Cgemm: C <- alpha*op(A)*op(B) + beta*C on complex dd values (manual,
+ * section "How to use reference MPBLAS", the Cgemm part: ZGEMM's argument
+ * list with complex multiple-precision scalars and arrays).  op(X) = X for
+ * 'N', X^T for 'T', the conjugate transpose X^H for 'C' (first character,
+ * case-insensitive).  Every complex matrix is four DEVICE planes of binary64
+ * -- re.hi, re.lo, im.hi, im.lo -- each column-major with the matrix's
+ * leading dimension; sizes and leading dimensions as for mpdd_Rgemm.  Info
+ * codes, NULL rules (A and B may be NULL when alpha = 0 or k = 0), beta = 0
+ * (C not read) and quick returns (m = 0, n = 0, or (alpha = 0 or k = 0) and
+ * beta = 1) are ZGEMM's.  The product op(A) op(B) is formed by four real
+ * products on the plain dd kernels into a device scratch of 32*m*n bytes
+ * (stream-ordered allocation, released before return), then
+ * alpha*P + beta*C is formed in complex dd arithmetic.  Stream-ordered and
+ * asynchronous like mpdd_Rgemm; the caller owns every buffer. */
+typedef struct { mpdd_dd re, im; } mpdd_ddc;   /* complex dd scalar */
+
+int mpdd_Cgemm(mpdd_handle h, const char *transa, const char *transb, mpdd_int m, mpdd_int n,
+               mpdd_int k, mpdd_ddc alpha, const double *A_re_hi, const double *A_re_lo,
+               const double *A_im_hi, const double *A_im_lo, mpdd_int lda,
+               const double *B_re_hi, const double *B_re_lo, const double *B_im_hi,
+               const double *B_im_lo, mpdd_int ldb, mpdd_ddc beta, double *C_re_hi,
+               double *C_re_lo, double *C_im_hi, double *C_im_lo, mpdd_int ldc, void *stream);
 
 /* ---- split-form building blocks ------------------------------------------------ *
  *

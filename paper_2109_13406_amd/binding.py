@@ -32,6 +32,10 @@ class mpdd_dd(ctypes.Structure):
     _fields_ = [("hi", ctypes.c_double), ("lo", ctypes.c_double)]
 
 
+class mpdd_ddc(ctypes.Structure):
+    _fields_ = [("re", mpdd_dd), ("im", mpdd_dd)]
+
+
 class mpdd_opts(ctypes.Structure):
     _fields_ = [("algo", ctypes.c_int), ("nslices", ctypes.c_int), ("tile_id", ctypes.c_int),
                 ("splitk", ctypes.c_int)]
@@ -85,6 +89,8 @@ SIGNATURES = {
                                   _P]),
     "mpdd_Rsyrk_ex": (ctypes.c_int, [_P, ctypes.POINTER(mpdd_opts), _C, _C, _I, _I, mpdd_dd, _P,
                                      _P, _I, mpdd_dd, _P, _P, _I, _P]),
+    "mpdd_Cgemm": (ctypes.c_int, [_P, _C, _C, _I, _I, _I, mpdd_ddc, _P, _P, _P, _P, _I, _P, _P, _P,
+                                  _P, _I, mpdd_ddc, _P, _P, _P, _P, _I, _P]),
     "mpdd_ozaki_digit_widths": (ctypes.c_int, [ctypes.c_int, _I, ctypes.c_int,
                                                 ctypes.POINTER(ctypes.c_int),
                                                 ctypes.POINTER(ctypes.c_int)]),
@@ -145,6 +151,17 @@ def _dd(x):
     return mpdd_dd(float(x[0]), float(x[1]))
 
 
+def _ddc(x):
+    """complex dd scalar: mpdd_ddc, a Python complex / real number (binary64
+    parts), or ((re_hi, re_lo), (im_hi, im_lo))."""
+    if isinstance(x, mpdd_ddc):
+        return x
+    if isinstance(x, (int, float, complex)):
+        x = complex(x)
+        return mpdd_ddc(mpdd_dd(x.real, 0.0), mpdd_dd(x.imag, 0.0))
+    return mpdd_ddc(_dd(x[0]), _dd(x[1]))
+
+
 def _flag(s):
     return s.encode() if isinstance(s, str) else s
 
@@ -195,6 +212,14 @@ def mpdd_Rgemm_ex(h, opts, transa, transb, m, n, k, alpha, A, lda, B, ldb, beta,
                                 _flag(transb), m, n, k, _dd(alpha), _ptr(A[0]), _ptr(A[1]), lda,
                                 _ptr(B[0]), _ptr(B[1]), ldb, _dd(beta), _ptr(C[0]), _ptr(C[1]),
                                 ldc, _stream(stream))
+
+
+def mpdd_Cgemm(h, transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, stream=None):
+    """A, B, C: 4-tuples (re.hi, re.lo, im.hi, im.lo) of tensors or device
+    pointers.  Returns info."""
+    return load().mpdd_Cgemm(h, _flag(transa), _flag(transb), m, n, k, _ddc(alpha),
+                             *map(_ptr, A), lda, *map(_ptr, B), ldb, _ddc(beta), *map(_ptr, C),
+                             ldc, _stream(stream))
 
 
 def mpdd_Rsyrk(h, uplo, trans, n, k, alpha, A, lda, beta, C, ldc, stream=None):

@@ -22,7 +22,8 @@ OBJ = os.path.join(ROOT, "_build", "mpdd")
 LIB = os.path.join(PKG, "libmpdd.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["mpdd.cpp", "tuner.cpp", "server.cpp", "host_api.cpp", "gemm_plain.hip", "ozaki.hip"]
+SOURCES = ["mpdd.cpp", "tuner.cpp", "server.cpp", "host_api.cpp", "gemm_plain.hip", "ozaki.hip",
+           "complex.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-ffp-contract=off",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wall", "-Wno-unused-function", "-I", os.path.join(ROOT, "include")]

@@ -56,6 +56,20 @@ hipError_t launch_grouped_list(int tile, const char* base, const ServeReq* reqs,
                                const int* counts, const int* items_offset, int which, int grid,
                                hipStream_t st);
 hipError_t launch_scale(const GemmParams& p, hipStream_t st);
+
+// Complex dd epilogue of Cgemm (complex.hip): C <- alpha P + beta C when
+// use_p, else C <- beta C; beta_zero: C is not read.  alpha / beta are
+// {re.hi, re.lo, im.hi, im.lo}.
+struct CEpilogue {
+  int64_t m, n;
+  double alpha[4], beta[4];
+  const double *p_rh, *p_rl, *p_ih, *p_il;
+  int64_t ldp;
+  double *c_rh, *c_rl, *c_ih, *c_il;
+  int64_t ldc;
+  int use_p, beta_zero;
+};
+hipError_t launch_cgemm_epilogue(const CEpilogue& p, hipStream_t st);
 // {hi, lo} pairs <-> hi / lo planes (n elements).
 hipError_t launch_split_pairs(const double* pairs, double* hi, double* lo, int64_t n,
                               hipStream_t st);

@@ -180,6 +180,7 @@ const char* mpdd_version(void) { return "mpdd 0.1 (gfx950)"; }
 size_t mpdd_struct_size(const char* name) {
   if (!name) return 0;
   if (std::strcmp(name, "mpdd_dd") == 0) return sizeof(mpdd_dd);
+  if (std::strcmp(name, "mpdd_ddc") == 0) return sizeof(mpdd_ddc);
   if (std::strcmp(name, "mpdd_opts") == 0) return sizeof(mpdd_opts);
   if (std::strcmp(name, "mpdd_request") == 0) return sizeof(mpdd_request);
   if (std::strcmp(name, "mpdd_timing") == 0) return sizeof(mpdd_timing);
@@ -304,6 +305,74 @@ int mpdd_Rsyrk_ex(mpdd_handle h, const mpdd_opts* opts, const char* uplo, const 
   const int tri = lsame(uplo, 'U') ? 1 : 2;
   return run_plain(h, opts, ta, tb, tri, n, n, k, alpha, A_hi, A_lo, lda, A_hi, A_lo, lda, beta,
                    C_hi, C_lo, ldc, (hipStream_t)stream);
+}
+
+// Cgemm.  With sA = -1 when op(A) conjugates (transa 'C'), else +1, and
+// op_r(A), op_i(A) the real transposition of the real and imaginary planes,
+//   Re P = op_r(Ar) op_r(Br) - sA sB op_r(Ai) op_r(Bi)
+//   Im P = sB op_r(Ar) op_r(Bi) + sA op_r(Ai) op_r(Br),
+// four plain dd products (the second of each pair accumulates onto the first
+// through beta = 1), then C <- alpha P + beta C in complex dd.
+int mpdd_Cgemm(mpdd_handle h, const char* transa, const char* transb, mpdd_int m, mpdd_int n,
+               mpdd_int k, mpdd_ddc alpha, const double* A_re_hi, const double* A_re_lo,
+               const double* A_im_hi, const double* A_im_lo, mpdd_int lda,
+               const double* B_re_hi, const double* B_re_lo, const double* B_im_hi,
+               const double* B_im_lo, mpdd_int ldb, mpdd_ddc beta, double* C_re_hi,
+               double* C_re_lo, double* C_im_hi, double* C_im_lo, mpdd_int ldc, void* stream) {
+  const int info = check_gemm(transa, transb, m, n, k, lda, ldb, ldc);
+  if (info) return info;
+  if (!handle_ok(h)) return MPDD_ERR_HANDLE;
+  const bool alpha_zero = is_zero(alpha.re) && is_zero(alpha.im);
+  const bool beta_zero = is_zero(beta.re) && is_zero(beta.im);
+  const bool beta_one = is_one(beta.re) && is_zero(beta.im);
+  if (m == 0 || n == 0 || ((alpha_zero || k == 0) && beta_one)) return 0;
+  if (!C_re_hi || !C_re_lo || !C_im_hi || !C_im_lo) return MPDD_ERR_ARG;
+  const bool use_p = !alpha_zero && k > 0;
+  if (use_p && (!A_re_hi || !A_re_lo || !A_im_hi || !A_im_lo || !B_re_hi || !B_re_lo ||
+                !B_im_hi || !B_im_lo))
+    return MPDD_ERR_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  CEpilogue e{};
+  e.m = m; e.n = n;
+  e.alpha[0] = alpha.re.hi; e.alpha[1] = alpha.re.lo;
+  e.alpha[2] = alpha.im.hi; e.alpha[3] = alpha.im.lo;
+  e.beta[0] = beta.re.hi; e.beta[1] = beta.re.lo;
+  e.beta[2] = beta.im.hi; e.beta[3] = beta.im.lo;
+  e.c_rh = C_re_hi; e.c_rl = C_re_lo; e.c_ih = C_im_hi; e.c_il = C_im_lo;
+  e.ldc = ldc;
+  e.beta_zero = beta_zero ? 1 : 0;
+  e.use_p = use_p ? 1 : 0;
+  if (!use_p) return hip_status(launch_cgemm_epilogue(e, st));
+
+  const bool ta = !lsame(transa, 'N'), tb = !lsame(transb, 'N');
+  const double sa = lsame(transa, 'C') ? -1.0 : 1.0, sb = lsame(transb, 'C') ? -1.0 : 1.0;
+  const size_t plane = (size_t)m * (size_t)n * sizeof(double);
+  void* w = nullptr;
+  if (hipMallocAsync(&w, 4 * plane, st) != hipSuccess) return MPDD_ERR_ALLOC;
+  double* prh = (double*)w;
+  double* prl = (double*)((char*)w + plane);
+  double* pih = (double*)((char*)w + 2 * plane);
+  double* pil = (double*)((char*)w + 3 * plane);
+  const mpdd_dd zero{0.0, 0.0}, one{1.0, 0.0};
+  int rc = run_plain(h, nullptr, ta, tb, 0, m, n, k, one, A_re_hi, A_re_lo, lda, B_re_hi,
+                     B_re_lo, ldb, zero, prh, prl, m, st);
+  if (!rc)
+    rc = run_plain(h, nullptr, ta, tb, 0, m, n, k, mpdd_dd{-sa * sb, 0.0}, A_im_hi, A_im_lo, lda,
+                   B_im_hi, B_im_lo, ldb, one, prh, prl, m, st);
+  if (!rc)
+    rc = run_plain(h, nullptr, ta, tb, 0, m, n, k, mpdd_dd{sb, 0.0}, A_re_hi, A_re_lo, lda,
+                   B_im_hi, B_im_lo, ldb, zero, pih, pil, m, st);
+  if (!rc)
+    rc = run_plain(h, nullptr, ta, tb, 0, m, n, k, mpdd_dd{sa, 0.0}, A_im_hi, A_im_lo, lda,
+                   B_re_hi, B_re_lo, ldb, one, pih, pil, m, st);
+  if (!rc) {
+    e.p_rh = prh; e.p_rl = prl; e.p_ih = pih; e.p_il = pil;
+    e.ldp = m;
+    rc = hip_status(launch_cgemm_epilogue(e, st));
+  }
+  const hipError_t ef = hipFreeAsync(w, st);
+  if (rc) return rc;
+  return hip_status(ef);
 }
 
 int mpdd_Rsyrk(mpdd_handle h, const char* uplo, const char* trans, mpdd_int n, mpdd_int k,

@@ -210,3 +210,27 @@ def sampled_syrk_check(h, name, case, opts=None, count=192, seed=0):
     r = ratio(got[0], got[1], ref[0], ref[1], k)
     log(f"PARITY {name} sampled({len(ii)}) ratio={r:.3g}")
     return r
+
+
+def csub(c, I, J):
+    """The Cgemm case restricted to rows I of op(A) and columns J of op(B):
+    compact operands with the same op flags, C = C[I, J].  Entry (r, s) of its
+    result is entry (I[r], J[s]) of the full one, computed by the same steps."""
+    k, ta, tb = c["k"], c["transa"].upper(), c["transb"].upper()
+    li, lj = len(I), len(J)
+    ar = np.arange(k)
+    A, B = [], []
+    for p in c["A"]:
+        if ta == "N":     # op(A) rows I = storage rows I: li x k
+            A.append(p[(I[:, None] + ar[None, :] * c["lda"]).ravel(order="F")])
+        else:             # storage columns I: k x li
+            A.append(p[(ar[:, None] + I[None, :] * c["lda"]).ravel(order="F")])
+    for p in c["B"]:
+        if tb == "N":     # op(B) columns J = storage columns J: k x lj
+            B.append(p[(ar[:, None] + J[None, :] * c["ldb"]).ravel(order="F")])
+        else:             # storage rows J: lj x k
+            B.append(p[(J[:, None] + ar[None, :] * c["ldb"]).ravel(order="F")])
+    C = tuple(p[(I[:, None] + J[None, :] * c["ldc"]).ravel(order="F")] for p in c["C"])
+    return dict(transa=ta, transb=tb, m=li, n=lj, k=k, alpha=c["alpha"], beta=c["beta"],
+                A=tuple(A), lda=(li if ta == "N" else k), B=tuple(B), ldb=(k if tb == "N" else lj),
+                C=C, ldc=li)

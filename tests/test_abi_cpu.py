@@ -123,3 +123,37 @@ def test_tile_table(lib):
 def test_destroy_null_handle(lib):
     from paper_2109_13406_amd import binding as b
     assert lib.mpdd_destroy(None) == b.MPDD_ERR_HANDLE
+
+
+def test_cgemm_info_codes_before_handle(lib):
+    """Cgemm checks ZGEMM's argument positions on the host before anything
+    else; valid arguments reach the handle check."""
+    from paper_2109_13406_amd import binding as b
+    pos = pins.read_arg_positions()
+    one = b.mpdd_ddc(b.mpdd_dd(1.0, 0.0), b.mpdd_dd(0.0, 0.0))
+    N4 = (None,) * 4
+
+    def c(ta="N", tb="N", m=2, n=2, k=2, lda=None, ldb=None, ldc=None):
+        lda = lda if lda is not None else max(1, m if ta.upper() == "N" else k)
+        ldb = ldb if ldb is not None else max(1, k if tb.upper() == "N" else n)
+        ldc = ldc if ldc is not None else max(1, m)
+        return lib.mpdd_Cgemm(None, ta.encode(), tb.encode(), m, n, k, one, *N4, lda, *N4, ldb,
+                              one, *N4, ldc, None)
+    H = b.MPDD_ERR_HANDLE
+    for t in "NnTtCc":
+        assert c(ta=t) == H and c(tb=t) == H
+    assert c(ta="X") == pos[("gemm", "transa")]
+    assert c(tb="q") == pos[("gemm", "transb")]
+    assert c(m=-1) == pos[("gemm", "m")]
+    assert c(n=-1) == pos[("gemm", "n")]
+    assert c(k=-1) == pos[("gemm", "k")]
+    assert c(ta="C", m=3, k=2, lda=1) == pos[("gemm", "lda")]
+    assert c(tb="C", n=3, k=2, ldb=2) == pos[("gemm", "ldb")]
+    assert c(m=3, ldc=2) == pos[("gemm", "ldc")]
+
+
+def test_struct_sizes_match_binding(lib):
+    from paper_2109_13406_amd import binding as b
+    for name in ("mpdd_dd", "mpdd_ddc", "mpdd_opts", "mpdd_request", "mpdd_timing",
+                 "mpdd_server_stats"):
+        assert lib.mpdd_struct_size(name.encode()) == ctypes.sizeof(getattr(b, name)), name
