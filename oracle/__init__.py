@@ -1,8 +1,10 @@
-"""CPU oracle for the double-double Rgemm / Rsyrk path -- TEST INFRASTRUCTURE.
+"""CPU oracle for the double-double MPBLAS / MPLAPACK path -- TEST INFRASTRUCTURE.
 
 Only the test suite, the smoke check and the benchmark's CPU-baseline leg may
-import this package.  It loads oracle/liboracle.so (plain C, see
-dd_oracle.c / ozaki_oracle.c) and exposes numpy-facing wrappers.  It never
+import this package.  It loads oracle/liboracle.so (plain C: dd_oracle.c for
+Rgemm / Rsyrk, ozaki_oracle.c for the split form, cdd_oracle.c for the
+complex Cgemm, potrf_oracle.c for the Cholesky Rpotrf) and exposes
+numpy-facing wrappers.  It never
 imports, links or calls the GPU library.
 
 Matrices are passed as pairs (hi, lo) of float64 numpy arrays holding the
@@ -80,6 +82,12 @@ def _bind(lib):
     lib.oracle_Cgemm.argtypes = [c, c, _I64, _I64, _I64, _D, _D, _D, _D, _D, _I64, _D, _D, _D,
                                  _D, _I64, _D, _D, _D, _D, _D, _I64]
     lib.oracle_Cgemm.restype = ctypes.c_int
+    lib.oracle_Rpotrf.argtypes = [c, _I64, _D, _D, _I64]
+    lib.oracle_Rpotrf.restype = ctypes.c_int64
+    lib.oracle_dd_div.argtypes = [ctypes.c_double] * 4 + [_D, _D]
+    lib.oracle_dd_div.restype = None
+    lib.oracle_dd_sqrt.argtypes = [ctypes.c_double] * 2 + [_D, _D]
+    lib.oracle_dd_sqrt.restype = None
     return lib
 
 
@@ -123,6 +131,26 @@ def dd_mul(x, y, lib=None):
     s, e = ctypes.c_double(), ctypes.c_double()
     lib.oracle_dd_mul(x[0], x[1], y[0], y[1], ctypes.byref(s), ctypes.byref(e))
     return s.value, e.value
+
+
+def dd_div(x, y, lib=None):
+    lib = lib or load()
+    s, e = ctypes.c_double(), ctypes.c_double()
+    lib.oracle_dd_div(x[0], x[1], y[0], y[1], ctypes.byref(s), ctypes.byref(e))
+    return s.value, e.value
+
+
+def dd_sqrt(x, lib=None):
+    lib = lib or load()
+    s, e = ctypes.c_double(), ctypes.c_double()
+    lib.oracle_dd_sqrt(x[0], x[1], ctypes.byref(s), ctypes.byref(e))
+    return s.value, e.value
+
+
+def rpotrf(uplo, n, A, lda, lib=None):
+    """In-place oracle Rpotrf on a numpy (hi, lo) pair; returns LAPACK's info."""
+    lib = lib or load()
+    return int(lib.oracle_Rpotrf(_flag(uplo), n, _p(A[0]), _p(A[1]), lda))
 
 
 # ---- level 3 ------------------------------------------------------------------

@@ -77,4 +77,42 @@ static inline odd dd_add_d(odd x, double y)
     return fast_two_sum(s.hi, v);
 }
 
+/* DWTimesFP1 (Joldes-Muller-Popescu 2017): dd * binary64. */
+static inline odd dd_mul_d(odd x, double y)
+{
+    odd c = two_prod(x.hi, y);
+    double cl2 = x.lo * y;
+    odd t = fast_two_sum(c.hi, cl2);
+    double tl2 = t.lo + c.lo;
+    return fast_two_sum(t.hi, tl2);
+}
+
+/* DWDivDW2 (Joldes-Muller-Popescu 2017): dd / dd, relative error
+ * <= 15u^2 + 56u^3.  The quotient of the leading parts is corrected once by
+ * the remainder x - y*t_h, whose leading part cancels exactly. */
+static inline odd dd_div(odd x, odd y)
+{
+    double th = x.hi / y.hi;
+    odd r = dd_mul_d(y, th);
+    double pih = x.hi - r.hi;
+    double dl = x.lo - r.lo;
+    double d = pih + dl;
+    double tl = d / y.hi;
+    return fast_two_sum(th, tl);
+}
+
+/* Square root of a positive dd (Lefevre, Louvet, Muller, Picot, Rideau,
+ * "Accurate calculation of Euclidean norms using double-word arithmetic",
+ * ACM TOMS 2023: relative error <= 25/8 u^2): the binary64 root of the
+ * leading part, corrected once with the exact remainder x.hi - s^2 (an fma)
+ * plus the low part. */
+static inline odd dd_sqrt(odd x)
+{
+    double sh = sqrt(x.hi);
+    double r1 = fma(-sh, sh, x.hi);
+    double r2 = x.lo + r1;
+    double sl = r2 / (2.0 * sh);
+    return fast_two_sum(sh, sl);
+}
+
 #endif

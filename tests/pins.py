@@ -751,3 +751,168 @@ def check_cgemm_info_codes(lib):
     assert info(ta="C", m=3, k=2, lda=1) == pos[("gemm", "lda")]
     assert info(tb="C", n=3, k=2, ldb=2) == pos[("gemm", "ldb")]
     assert info(m=3, ldc=2) == pos[("gemm", "ldc")]
+
+
+# ---- dd division, square root and the Cholesky factorisation Rpotrf ------------------
+
+def check_div_sqrt(lib, count=300):
+    rng = np.random.default_rng(11)
+    for dist in ("uniform", "wide"):
+        xh, xl = W.dd_values(rng, count, dist)
+        yh, yl = W.dd_values(rng, count, dist)
+        for t in range(count):
+            if yh[t] == 0.0:
+                continue
+            x, y = F(xh[t], xl[t]), F(yh[t], yl[t])
+            z = F(*oracle.dd_div((xh[t], xl[t]), (yh[t], yl[t]), lib=lib))
+            q = x / y
+            assert abs(z - q) <= 16 * U2 * abs(q), ("div", dist, t)
+            # square root of |x|: (z - e)^2 <= |x| <= (z + e)^2 with e = 3.2 u^2 z
+            a = abs(x)
+            if a == 0:
+                continue
+            ah, al = (xh[t], xl[t]) if xh[t] > 0 else (-xh[t], -xl[t])
+            s = F(*oracle.dd_sqrt((ah, al), lib=lib))
+            e = Fraction(32, 10) * U2 * s
+            assert (s - e) ** 2 <= a <= (s + e) ** 2, ("sqrt", dist, t)
+    # exact cases
+    for (x, y, q) in ((6.0, 3.0, 2.0), (1.0, 4.0, 0.25), (7.0, 7.0, 1.0), (-9.0, 3.0, -3.0)):
+        assert oracle.dd_div((x, 0.0), (y, 0.0), lib=lib) == (q, 0.0)
+    for (x, r) in ((4.0, 2.0), (2.25, 1.5), (1.0, 1.0)):
+        assert oracle.dd_sqrt((x, 0.0), lib=lib) == (r, 0.0)
+    # (1 + 2^-40)^2 = 1 + 2^-39 + 2^-80: needs the low part to come out exact
+    assert oracle.dd_sqrt((1.0 + 2.0 ** -39, 2.0 ** -80), lib=lib) == (1.0 + 2.0 ** -40, 0.0)
+
+
+def _tri_full(M, n, ld, uplo):
+    """Column-major (hi, lo) planes of ld x n holding the uplo triangle of the
+    symmetric n x n array M (a list of (hi, lo) rows); the other triangle and
+    the padding rows hold the NaN sentinel."""
+    hi = np.full(ld * n, W.SENTINEL_HI)
+    lo = np.full(ld * n, W.SENTINEL_LO)
+    for i in range(n):
+        for j in range(n):
+            if (uplo == "L" and i >= j) or (uplo == "U" and i <= j):
+                hi[i + j * ld], lo[i + j * ld] = M[i][j]
+    return hi, lo
+
+
+def check_potrf_exact_integer(lib):
+    """A = L L^T with small integer L (positive diagonal): every quantity is an
+    integer, so both triangles come out exactly L (lo parts 0)."""
+    rng = np.random.default_rng(12)
+    for n in (1, 2, 5, 9, 12):
+        L = np.tril(rng.integers(-3, 4, (n, n))).astype(np.int64)
+        np.fill_diagonal(L, rng.integers(1, 5, n))
+        A = L @ L.T
+        M = [[(float(A[i, j]), 0.0) for j in range(n)] for i in range(n)]
+        for uplo in "LU":
+            ld = n + 2
+            hi, lo = _tri_full(M, n, ld, uplo)
+            h0, l0 = hi.copy(), lo.copy()
+            assert oracle.rpotrf(uplo, n, (hi, lo), ld, lib=lib) == 0
+            for i in range(n):
+                for j in range(n):
+                    o = i + j * ld
+                    inside = (i >= j) if uplo == "L" else (i <= j)
+                    if inside:
+                        want = L[i, j] if uplo == "L" else L[j, i]
+                        assert hi[o] == want and lo[o] == 0.0, (n, uplo, i, j)
+                    else:
+                        assert bits(hi[o:o + 1])[0] == bits(h0[o:o + 1])[0]
+                        assert bits(lo[o:o + 1])[0] == bits(l0[o:o + 1])[0]
+            pad = np.ones(ld * n, bool)
+            for j in range(n):
+                pad[j * ld: j * ld + n] = False
+            assert np.array_equal(bits(hi)[pad], bits(h0)[pad])
+
+
+def spd_matrix(rng, n, dist="uniform"):
+    """Symmetric positive definite dd matrix B B^T / n + I with dd-random B,
+    rounded to dd; returns an n x n list of (hi, lo)."""
+    bh, bl = W.dd_values(rng, n * n, dist if dist != "wide" else "uniform")
+    B = [[F(bh[i * n + j], bl[i * n + j]) for j in range(n)] for i in range(n)]
+    M = []
+    for i in range(n):
+        row = []
+        for j in range(n):
+            v = sum((B[i][l] * B[j][l] for l in range(n)), Fraction(0)) / n
+            if i == j:
+                v += 1
+            h = float(v)
+            row.append((h, float(v - Fraction(h))))
+        M.append(row)
+    for i in range(n):                 # exactly symmetric
+        for j in range(i):
+            M[j][i] = M[i][j]
+    return M
+
+
+def potrf_bound(n):
+    """Entrywise backward-error bound of the dd Cholesky in units of
+    (|L| |L|^T)_ij: each of the <= n subtracted products and sums costs at most
+    7 u^2, the square root 25/8 u^2 and the quotient 16 u^2."""
+    return (7 * n + 40) * U2
+
+
+def check_potrf_residual(lib, sizes=(1, 3, 6, 8)):
+    rng = np.random.default_rng(13)
+    for n in sizes:
+        M = spd_matrix(rng, n)
+        for uplo in "LU":
+            ld = n + 1
+            hi, lo = _tri_full(M, n, ld, uplo)
+            assert oracle.rpotrf(uplo, n, (hi, lo), ld, lib=lib) == 0
+
+            def Lv(i, l):
+                if i < l:
+                    return Fraction(0)
+                o = (i + l * ld) if uplo == "L" else (l + i * ld)
+                return F(hi[o], lo[o])
+            bnd = potrf_bound(n)
+            for i in range(n):
+                for j in range(i + 1):
+                    s = sum((Lv(i, l) * Lv(j, l) for l in range(n)), Fraction(0))
+                    mag = sum((abs(Lv(i, l) * Lv(j, l)) for l in range(n)), Fraction(0))
+                    a = F(*M[i][j])
+                    assert abs(s - a) <= bnd * mag, (n, uplo, i, j, float(abs(s - a) / mag))
+                    if i == j:
+                        assert Lv(i, i) > 0
+
+
+def check_potrf_transpose_and_info(lib):
+    rng = np.random.default_rng(14)
+    n, ld = 7, 9
+    M = spd_matrix(rng, n)
+    hl, ll = _tri_full(M, n, ld, "L")
+    hu, lu = _tri_full(M, n, ld, "U")
+    assert oracle.rpotrf("L", n, (hl, ll), ld, lib=lib) == 0
+    assert oracle.rpotrf("u", n, (hu, lu), ld, lib=lib) == 0
+    for i in range(n):
+        for j in range(i + 1):
+            a, b = i + j * ld, j + i * ld
+            assert bits(hl[a:a + 1])[0] == bits(hu[b:b + 1])[0]
+            assert bits(ll[a:a + 1])[0] == bits(lu[b:b + 1])[0]
+    # not positive definite at order k: info = k, earlier columns factored
+    for k in (1, 3, 7):
+        Mk = [[(1.0 if i == j else 0.0, 0.0) for j in range(n)] for i in range(n)]
+        Mk[k - 1][k - 1] = (-1.0, 0.0)
+        h, l = _tri_full(Mk, n, ld, "L")
+        assert oracle.rpotrf("L", n, (h, l), ld, lib=lib) == k
+        assert h[(k - 1) * (ld + 1)] == -1.0
+    # a zero pivot after elimination: [[1, 1], [1, 1]] -> info 2
+    h, l = _tri_full([[(1.0, 0.0), (1.0, 0.0)], [(1.0, 0.0), (1.0, 0.0)]], 2, 2, "U")
+    assert oracle.rpotrf("U", 2, (h, l), 2, lib=lib) == 2
+    # NaN on the diagonal
+    Mk = [[(1.0 if i == j else 0.0, 0.0) for j in range(3)] for i in range(3)]
+    Mk[1][1] = (float("nan"), 0.0)
+    h, l = _tri_full(Mk, 3, 3, "L")
+    assert oracle.rpotrf("L", 3, (h, l), 3, lib=lib) == 2
+    # LAPACK argument errors (negative positions), nothing written
+    h = np.full(4, 5.0)
+    l = np.zeros(4)
+    assert oracle.rpotrf("X", 2, (h, l), 2, lib=lib) == -1
+    assert oracle.rpotrf("L", -1, (h, l), 2, lib=lib) == -2
+    assert oracle.rpotrf("L", 2, (h, l), 1, lib=lib) == -4
+    assert oracle.rpotrf("L", 0, (h, l), 1, lib=lib) == 0
+    assert np.all(h == 5.0)

@@ -80,6 +80,24 @@ MUTANTS = [
      "complex: wrong ldb check"),
     ("cdd_oracle.c", "for (l = 0; l < k; ++l)\n", "for (l = 1; l < k; ++l)\n",
      "complex: dropped first term"),
+    ("dd_ops.h", "double tl = d / y.hi;", "double tl = 0.0 * d / y.hi;",
+     "dd division without the remainder correction"),
+    ("dd_ops.h", "double dl = x.lo - r.lo;", "double dl = x.lo + r.lo;",
+     "sign error in the division remainder"),
+    ("dd_ops.h", "double r2 = x.lo + r1;", "double r2 = r1;", "square root ignores the low part"),
+    ("dd_ops.h", "double sl = r2 / (2.0 * sh);", "double sl = r2 / sh;",
+     "square root correction not halved"),
+    ("potrf_oracle.c", "d = dd_add(d, p_neg(dd_mul(v, v)));", "d = dd_add(d, dd_mul(v, v));",
+     "Cholesky: diagonal update added"),
+    ("potrf_oracle.c", "odd a = {Ah[oi], Al[oi]}, b = {Ah[oj], Al[oj]};",
+     "odd a = {Ah[oi], Al[oi]}, b = {Ah[oi], Al[oi]};", "Cholesky: wrong row in the update"),
+    ("potrf_oracle.c", "return j + 1;", "return j;", "Cholesky: info off by one"),
+    ("potrf_oracle.c", "if (!(d.hi > 0.0)) {", "if (d.hi < 0.0) {",
+     "Cholesky: zero or NaN pivot accepted"),
+    ("potrf_oracle.c", "return upper ? (l + i * lda) : (i + l * lda);",
+     "return (i + l * lda);", "Cholesky: upper written as lower"),
+    ("potrf_oracle.c", "acc = dd_div(acc, ljj);", "acc = dd_div(acc, d);",
+     "Cholesky: divided by the pivot instead of its root"),
 ]
 
 CHECKS = [
@@ -95,6 +113,10 @@ CHECKS = [
     lambda lib: pins.check_exact_cgemm(lib, seeds=[0]),
     pins.check_cgemm_identities,
     pins.check_cgemm_info_codes,
+    pins.check_div_sqrt,
+    pins.check_potrf_exact_integer,
+    lambda lib: pins.check_potrf_residual(lib, sizes=(3, 6)),
+    pins.check_potrf_transpose_and_info,
 ]
 
 
