@@ -1,7 +1,7 @@
 """Benchmark: dd Rgemm on one MI355X, plain and split forms, plus served latency.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 8192] [--no-cpu]
-                    [--sections plain,syrk,cgemm,ozaki,host,serve]
+                    [--sections plain,syrk,cgemm,potrf,ozaki,host,serve]
 
 One step = one dd Rgemm NN, m = n = k = n (8192), leading dimensions 8195,
 C <- alpha*A*B + beta*C on float64 hi/lo planes already resident in HBM.
@@ -166,6 +166,36 @@ def bench_cgemm(h, args, stream):
             "ms": round(t * 1e3, 3), "complex_dd_gflops": round(8.0 * n ** 3 / t / 1e9, 1)}
 
 
+def bench_potrf(h, args, stream):
+    """Blocked dd Cholesky Rpotrf L at n (synchronous call: it reads each
+    diagonal block's info back).  dd-flops n^3/3 (LAWN 41, leading term)."""
+    import torch
+    import workloads as W
+    from paper_2109_13406_amd import binding as b
+    n = args.n
+    case = W.spd_case_device(W.BASE_SEED + 7, n, "L")
+    A0 = tuple(x.clone() for x in case["A"])
+    torch.cuda.synchronize()
+    times = []
+    for rep in range(1 + max(1, args.steps // 2)):
+        for dst, src in zip(case["A"], A0):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rc, info = b.mpdd_Rpotrf(h, "L", n, case["A"], case["lda"], stream=stream)
+        torch.cuda.synchronize()
+        if rc != 0 or info != 0:
+            raise RuntimeError(f"mpdd_Rpotrf rc={rc} info={info}")
+        if rep > 0:                      # the first call is warm-up
+            times.append(time.perf_counter() - t0)
+    t = sum(times) / len(times)
+    del case, A0
+    torch.cuda.empty_cache()
+    return {"workload": f"Rpotrf L n={n} ld={W.ld_padded(n)} (SPD: dd U[-1,1) off-diagonal, "
+                        f"n + U[0,1) diagonal)", "ms": round(t * 1e3, 3),
+            "dd_gflops": round(float(n) ** 3 / 3.0 / t / 1e9, 1)}
+
+
 def ratio_gpu(C, R, m, n, ldc, k):
     """Normwise dd difference of the stored m x n entries of C from R in units
     of k * 2^-104, on the device (the tests' metric: (hi - hi') + (lo - lo'))."""
@@ -315,7 +345,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=8192)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--sections", default="plain,syrk,cgemm,ozaki,host,serve")
+    ap.add_argument("--sections", default="plain,syrk,cgemm,potrf,ozaki,host,serve")
     ap.add_argument("--tile", type=int, default=-1,
                     help="tile-table entry for the plain product (-1: the library's choice)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
@@ -378,6 +408,9 @@ def main():
     if "syrk" in sections:
         out["rsyrk"] = bench_syrk(h, args, stream)
         log(f"rsyrk: {out['rsyrk']}")
+    if "potrf" in sections:
+        out["rpotrf"] = bench_potrf(h, args, stream)
+        log(f"rpotrf: {out['rpotrf']}")
     if "cgemm" in sections:
         out["cgemm"] = bench_cgemm(h, args, stream)
         log(f"cgemm: {out['cgemm']}")

@@ -131,7 +131,7 @@ typedef struct {
   int nslices;  /* split form: slices per operand, 0 = default for the input */
   int tile_id;  /* plain forms: index into the tile table, -1 = tuned choice;
                    INT8 split form: product workgroup tile, 0 = 256x256,
-                   1 = 256x128, 2 = 128x128, -1 = default (1); all give the
+                   1 = 256x128, 2 = 128x128, -1 = default (0); all give the
                    same bits; ignored by the FP64 split form */
   int splitk;   /* plain forms: k-split factor, 0 = automatic, 1 = none */
 } mpdd_opts;
@@ -175,6 +175,40 @@ int mpdd_Cgemm(mpdd_handle h, const char *transa, const char *transb, mpdd_int m
                const double *B_re_hi, const double *B_re_lo, const double *B_im_hi,
                const double *B_im_lo, mpdd_int ldb, mpdd_ddc beta, double *C_re_hi,
                double *C_re_lo, double *C_im_hi, double *C_im_lo, mpdd_int ldc, void *stream);
+
+/* ---- Cholesky factorisation: Rpotrf -------------------------------------------------
+ *
+ * Rpotrf: the dd Cholesky factorisation of a symmetric positive definite
+ * matrix (MPLAPACK's Rpotrf, LAPACK DPOTRF's argument list: uplo, n, A, lda,
+ * info; the manual lists it among the MPLAPACK routines and times it on the
+ * CPU; the interior-point (SDP) solvers it cites factor their Schur
+ * complement matrices this way).  uplo 'L': A = L L^T, L written over the
+ * lower triangle; 'U': A = U^T U over the upper triangle.  A is two DEVICE
+ * planes (hi, lo), column-major, n x n with leading dimension lda; only the
+ * uplo triangle is read or written.
+ *
+ * *info (HOST pointer, required) receives LAPACK's info: 0; -1 (uplo),
+ * -2 (n < 0), -4 (lda < max(1, n)) with nothing enqueued; or k > 0 when the
+ * leading minor of order k is not positive definite (pivot <= 0 or NaN): the
+ * columns before k's block hold the factor, A(k,k) holds the pivot, later
+ * columns are unspecified.  The return value is 0 or MPDD_ERR_* (library /
+ * runtime errors only).
+ *
+ * Blocked: per diagonal block of order nb, one Rgemm updates a copy of the
+ * block column, a one-workgroup kernel factors the diagonal block and
+ * inverts its factor, and the rest of the block column is multiplied by the
+ * inverted block.  The call reads the failure word back to the host every 16
+ * blocks and at the end, so it is synchronous: it returns when A is factored
+ * (or a failing pivot has been found).  Device scratch of 16*nb*(nb + n) + 256
+ * bytes is allocated and freed inside the call (stream ordered on
+ * `stream`). */
+int mpdd_Rpotrf(mpdd_handle h, const char *uplo, mpdd_int n, double *A_hi, double *A_lo,
+                mpdd_int lda, mpdd_int *info, void *stream);
+
+/* As mpdd_Rpotrf with the block order nb (1..64; 0 = default 64);
+ * MPDD_ERR_UNSUPPORTED outside that range. */
+int mpdd_Rpotrf_nb(mpdd_handle h, const char *uplo, mpdd_int n, double *A_hi, double *A_lo,
+                   mpdd_int lda, mpdd_int nb, mpdd_int *info, void *stream);
 
 /* ---- split-form building blocks ------------------------------------------------ *
  *

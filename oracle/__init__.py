@@ -3,7 +3,8 @@
 Only the test suite, the smoke check and the benchmark's CPU-baseline leg may
 import this package.  It loads oracle/liboracle.so (plain C: dd_oracle.c for
 Rgemm / Rsyrk, ozaki_oracle.c for the split form, cdd_oracle.c for the
-complex Cgemm, potrf_oracle.c for the Cholesky Rpotrf) and exposes
+complex Cgemm, potrf_oracle.c for the Cholesky Rpotrf, qd_oracle.c for the
+quad-double Rgemm) and exposes
 numpy-facing wrappers.  It never
 imports, links or calls the GPU library.
 
@@ -88,6 +89,11 @@ def _bind(lib):
     lib.oracle_dd_div.restype = None
     lib.oracle_dd_sqrt.argtypes = [ctypes.c_double] * 2 + [_D, _D]
     lib.oracle_dd_sqrt.restype = None
+    _P4 = _D * 4
+    lib.oracle_Qgemm.argtypes = [c, c, _I64, _I64, _I64, _D, _P4, _I64, _P4, _I64, _D, _P4, _I64]
+    lib.oracle_Qgemm.restype = ctypes.c_int
+    lib.oracle_qd_round_sum.argtypes = [_I64, _D, _D]
+    lib.oracle_qd_round_sum.restype = None
     return lib
 
 
@@ -145,6 +151,32 @@ def dd_sqrt(x, lib=None):
     s, e = ctypes.c_double(), ctypes.c_double()
     lib.oracle_dd_sqrt(x[0], x[1], ctypes.byref(s), ctypes.byref(e))
     return s.value, e.value
+
+
+def _planes4(P):
+    if P is None or P[0] is None:
+        return (_D * 4)(None, None, None, None)
+    return (_D * 4)(*[_p(x) for x in P])
+
+
+def qgemm(transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, lib=None):
+    """In-place oracle quad-double Rgemm: A, B, C are 4-tuples of planes
+    (x0, x1, x2, x3); alpha, beta 4-tuples of floats.  Every entry is the exact
+    result rounded to a qd.  Returns info."""
+    lib = lib or load()
+    al = np.asarray(alpha, dtype=np.float64)
+    be = np.asarray(beta, dtype=np.float64)
+    return lib.oracle_Qgemm(_flag(transa), _flag(transb), m, n, k, _p(al), _planes4(A), lda,
+                            _planes4(B), ldb, _p(be), _planes4(C), ldc)
+
+
+def qd_round_sum(terms, lib=None):
+    """Round the exact sum of binary64 terms to a qd (x0, x1, x2, x3)."""
+    lib = lib or load()
+    t = np.ascontiguousarray(terms, dtype=np.float64)
+    q = np.zeros(4)
+    lib.oracle_qd_round_sum(t.size, _p(t), _p(q))
+    return tuple(float(x) for x in q)
 
 
 def rpotrf(uplo, n, A, lda, lib=None):

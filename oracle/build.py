@@ -10,7 +10,7 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = ["dd_oracle.c", "ozaki_oracle.c", "cdd_oracle.c", "potrf_oracle.c"]
+SOURCES = ["dd_oracle.c", "ozaki_oracle.c", "cdd_oracle.c", "potrf_oracle.c", "qd_oracle.c"]
 LIB = os.path.join(HERE, "liboracle.so")
 CFLAGS = ["-O2", "-std=c99", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
           "-mfma", "-mavx2", "-Wall", "-Wno-unknown-pragmas"]

@@ -91,6 +91,8 @@ SIGNATURES = {
                                      _P, _I, mpdd_dd, _P, _P, _I, _P]),
     "mpdd_Cgemm": (ctypes.c_int, [_P, _C, _C, _I, _I, _I, mpdd_ddc, _P, _P, _P, _P, _I, _P, _P, _P,
                                   _P, _I, mpdd_ddc, _P, _P, _P, _P, _I, _P]),
+    "mpdd_Rpotrf": (ctypes.c_int, [_P, _C, _I, _P, _P, _I, ctypes.POINTER(_I), _P]),
+    "mpdd_Rpotrf_nb": (ctypes.c_int, [_P, _C, _I, _P, _P, _I, _I, ctypes.POINTER(_I), _P]),
     "mpdd_ozaki_digit_widths": (ctypes.c_int, [ctypes.c_int, _I, ctypes.c_int,
                                                 ctypes.POINTER(ctypes.c_int),
                                                 ctypes.POINTER(ctypes.c_int)]),
@@ -220,6 +222,15 @@ def mpdd_Cgemm(h, transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, 
     return load().mpdd_Cgemm(h, _flag(transa), _flag(transb), m, n, k, _ddc(alpha),
                              *map(_ptr, A), lda, *map(_ptr, B), ldb, _ddc(beta), *map(_ptr, C),
                              ldc, _stream(stream))
+
+
+def mpdd_Rpotrf(h, uplo, n, A, lda, nb=0, stream=None):
+    """A: (hi, lo) pair of tensors or device pointers.  Returns (rc, info):
+    rc = 0 or MPDD_ERR_*, info = LAPACK's info."""
+    info = _I(0)
+    rc = load().mpdd_Rpotrf_nb(h, _flag(uplo), n, _ptr(A[0]), _ptr(A[1]), lda, nb,
+                               ctypes.byref(info), _stream(stream))
+    return rc, info.value
 
 
 def mpdd_Rsyrk(h, uplo, trans, n, k, alpha, A, lda, beta, C, ldc, stream=None):

@@ -70,6 +70,17 @@ struct CEpilogue {
   int use_p, beta_zero;
 };
 hipError_t launch_cgemm_epilogue(const CEpilogue& p, hipStream_t st);
+
+// Cholesky diagonal block (potrf.hip): factor the jb x jb block (jb <= 64)
+// read from s (ld lds) in the lower view (upper = 1: the block holds U, read
+// transposed), write the factor's triangle to a (ld lda) and the inverse of
+// the lower-view factor to w (ld jb, zero upper part).  *info is the
+// factorisation's failure word: if it is already non-zero the kernel does
+// nothing; if a pivot of this block fails it becomes offset + the 1-based
+// order of that pivot within the block.
+hipError_t launch_potf2_block(const double* s_hi, const double* s_lo, int64_t lds, double* a_hi,
+                              double* a_lo, int64_t lda, int jb, int upper, double* w_hi,
+                              double* w_lo, long long* info, long long offset, hipStream_t st);
 // {hi, lo} pairs <-> hi / lo planes (n elements).
 hipError_t launch_split_pairs(const double* pairs, double* hi, double* lo, int64_t n,
                               hipStream_t st);

@@ -82,12 +82,12 @@ int hip_status(hipError_t e) { return e == hipSuccess ? 0 : MPDD_ERR_HIP; }
 bool handle_ok(mpdd_handle h) { return h != nullptr && h->magic == 0x6d706464; }
 
 // Automatic k-split: enough C tiles to give every CU two workgroups, else
-// split k (keeping >= 1024 terms per slice) up to 16 ways.
+// split k (keeping >= 256 terms per slice) up to 16 ways.
 int auto_splitk(int64_t tiles, int64_t k, int bk) {
   const int64_t target = 512;
   if (tiles >= target) return 1;
   int s = 1;
-  while (s < 16 && tiles * s < target && k / (2 * s) >= 1024 && (k / (2 * s)) % bk == 0) s *= 2;
+  while (s < 16 && tiles * s < target && k / (2 * s) >= 256 && (k / (2 * s)) % bk == 0) s *= 2;
   return s;
 }
 
@@ -110,9 +110,11 @@ Plan choose(const mpdd_handle h, const mpdd_opts* o, int op, bool ta, bool tb, i
   }
   if (pl.tile < 0) pl.tile = default_tile(m, n, k, square_only);
   if (pl.splitk == 0) {
+    // (a triangle launches only the tiles that meet it)
     const TileInfo* t = tile_info(pl.tile);
-    const int64_t tiles = ((m + t->bm - 1) / t->bm) * ((n + t->bn - 1) / t->bn);
-    pl.splitk = square_only ? 1 : auto_splitk(tiles, k, t->bk);
+    const int64_t tm = (m + t->bm - 1) / t->bm, tn = (n + t->bn - 1) / t->bn;
+    const int64_t tiles = square_only ? tm * (tm + 1) / 2 : tm * tn;
+    pl.splitk = auto_splitk(tiles, k, t->bk);
   }
   return pl;
 }
@@ -373,6 +375,126 @@ int mpdd_Cgemm(mpdd_handle h, const char* transa, const char* transb, mpdd_int m
   const hipError_t ef = hipFreeAsync(w, st);
   if (rc) return rc;
   return hip_status(ef);
+}
+
+// Rpotrf, blocked (LAPACK DPOTRF's left-looking order).  For each diagonal
+// block j of order jb ('L'; 'U' is the transpose): the block column
+// A(j:n, j:j+jb) is copied to P and updated there with the j factored
+// columns by one Rgemm (the diagonal block rides along, both of its triangles
+// computed in P, so A's opposite triangle is never written); the block kernel
+// factors P's diagonal block into A and inverts the factor (W); the rest of P
+// is multiplied by W^T into A.  The first failing pivot is recorded in a
+// device word that later block kernels respect (they return at once); the
+// host reads it every POTRF_CHECK blocks and at the end, and stops launching
+// once it is set.  After a failure, the columns before the failing block hold
+// the factor and A(k,k) the pivot; later columns are unspecified.
+int mpdd_Rpotrf_nb(mpdd_handle h, const char* uplo, mpdd_int n, double* A_hi, double* A_lo,
+                   mpdd_int lda, mpdd_int nb, mpdd_int* info, void* stream) {
+  if (!info) return MPDD_ERR_ARG;
+  *info = 0;
+  const bool upper = lsame(uplo, 'U');
+  if (!upper && !lsame(uplo, 'L')) { *info = -1; return 0; }
+  if (n < 0) { *info = -2; return 0; }
+  if (lda < std::max<mpdd_int>(1, n)) { *info = -4; return 0; }
+  if (!handle_ok(h)) return MPDD_ERR_HANDLE;
+  if (nb == 0) nb = 64;
+  if (nb < 1 || nb > 64) return MPDD_ERR_UNSUPPORTED;
+  if (n == 0) return 0;
+  if (!A_hi || !A_lo) return MPDD_ERR_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  const size_t wb = (size_t)nb * nb * sizeof(double);
+  const size_t pb = (size_t)n * nb * sizeof(double);
+  void* ws = nullptr;
+  if (hipMallocAsync(&ws, 2 * wb + 2 * pb + 256, st) != hipSuccess) return MPDD_ERR_ALLOC;
+  double* w_hi = (double*)ws;
+  double* w_lo = (double*)((char*)ws + wb);
+  double* p_hi = (double*)((char*)ws + 2 * wb);
+  double* p_lo = (double*)((char*)ws + 2 * wb + pb);
+  long long* d_info = (long long*)((char*)ws + 2 * wb + 2 * pb);
+  if (hipMemsetAsync(d_info, 0, sizeof(long long), st) != hipSuccess) {
+    (void)hipFreeAsync(ws, st);
+    return MPDD_ERR_HIP;
+  }
+  constexpr int64_t POTRF_CHECK = 16;   // blocks between host reads of the failure word
+  long long hinfo = 0;
+  const mpdd_dd one{1.0, 0.0}, mone{-1.0, 0.0}, zero{0.0, 0.0};
+  // the panel solve is a skinny product with k = jb: 32 x 32 tiles give the
+  // CUs more workgroups
+  mpdd_opts small{MPDD_PLAIN, 0, 2, 1};
+  int rc = 0;
+  auto at = [&](double* base, int64_t i, int64_t j) { return base + i + j * lda; };
+  auto copy = [&](double* dst, int64_t dpitch, const double* src, int64_t width,
+                  int64_t height) {
+    return hipMemcpy2DAsync(dst, dpitch * sizeof(double), src, lda * sizeof(double),
+                            width * sizeof(double), height, hipMemcpyDeviceToDevice, st);
+  };
+  for (int64_t j = 0; j < n && !rc; j += nb) {
+    const int64_t jb = std::min<int64_t>(nb, n - j);
+    const int64_t rows = n - j;          // block column length, diagonal block included
+    // 1. P = block column (lower: rows x jb, ld rows; upper: jb x rows, ld jb)
+    const int64_t ldp = upper ? jb : rows;
+    if ((upper ? (copy(p_hi, ldp, at(A_hi, j, j), jb, rows) != hipSuccess ||
+                  copy(p_lo, ldp, at(A_lo, j, j), jb, rows) != hipSuccess)
+               : (copy(p_hi, ldp, at(A_hi, j, j), rows, jb) != hipSuccess ||
+                  copy(p_lo, ldp, at(A_lo, j, j), rows, jb) != hipSuccess))) {
+      rc = MPDD_ERR_HIP;
+      break;
+    }
+    // 2. update with the factored part
+    if (j > 0) {
+      if (!upper)
+        rc = run_plain(h, nullptr, false, true, 0, rows, jb, j, mone, at(A_hi, j, 0),
+                       at(A_lo, j, 0), lda, at(A_hi, j, 0), at(A_lo, j, 0), lda, one, p_hi, p_lo,
+                       ldp, st);
+      else
+        rc = run_plain(h, nullptr, true, false, 0, jb, rows, j, mone, at(A_hi, 0, j),
+                       at(A_lo, 0, j), lda, at(A_hi, 0, j), at(A_lo, 0, j), lda, one, p_hi, p_lo,
+                       ldp, st);
+      if (rc) break;
+    }
+    // 3. factor and invert the diagonal block (records a failing pivot)
+    if (launch_potf2_block(p_hi, p_lo, ldp, at(A_hi, j, j), at(A_lo, j, j), lda, (int)jb,
+                           upper ? 1 : 0, w_hi, w_lo, d_info, (long long)j, st) != hipSuccess) {
+      rc = MPDD_ERR_HIP;
+      break;
+    }
+    // 4. every POTRF_CHECK blocks: stop once a pivot has failed
+    if ((j / nb) % POTRF_CHECK == POTRF_CHECK - 1) {
+      if (hipMemcpyAsync(&hinfo, d_info, sizeof(long long), hipMemcpyDeviceToHost, st) !=
+              hipSuccess ||
+          hipStreamSynchronize(st) != hipSuccess) {
+        rc = MPDD_ERR_HIP;
+        break;
+      }
+      if (hinfo) break;
+    }
+    if (rows == jb) break;
+    // 5. panel solve: lower A(j+jb:n, j:j+jb) = P(jb:, :) W^T; upper
+    // A(j:j+jb, j+jb:n) = W P(:, jb:)   (W = U^-T in the lower view)
+    if (!upper)
+      rc = run_plain(h, &small, false, true, 0, rows - jb, jb, jb, one, p_hi + jb, p_lo + jb, ldp,
+                     w_hi, w_lo, jb, zero, at(A_hi, j + jb, j), at(A_lo, j + jb, j), lda, st);
+    else
+      rc = run_plain(h, &small, false, false, 0, jb, rows - jb, jb, one, w_hi, w_lo, jb,
+                     p_hi + jb * jb, p_lo + jb * jb, ldp, zero, at(A_hi, j, j + jb),
+                     at(A_lo, j, j + jb), lda, st);
+  }
+  if (!rc && !hinfo &&
+      (hipMemcpyAsync(&hinfo, d_info, sizeof(long long), hipMemcpyDeviceToHost, st) !=
+           hipSuccess ||
+       hipStreamSynchronize(st) != hipSuccess))
+    rc = MPDD_ERR_HIP;
+  const hipError_t ef = hipFreeAsync(ws, st);
+  const hipError_t es = hipStreamSynchronize(st);
+  if (rc) return rc;
+  if (ef != hipSuccess || es != hipSuccess) return MPDD_ERR_HIP;
+  *info = (mpdd_int)hinfo;
+  return 0;
+}
+
+int mpdd_Rpotrf(mpdd_handle h, const char* uplo, mpdd_int n, double* A_hi, double* A_lo,
+                mpdd_int lda, mpdd_int* info, void* stream) {
+  return mpdd_Rpotrf_nb(h, uplo, n, A_hi, A_lo, lda, 0, info, stream);
 }
 
 int mpdd_Rsyrk(mpdd_handle h, const char* uplo, const char* trans, mpdd_int n, mpdd_int k,

@@ -204,15 +204,15 @@ __device__ __forceinline__ void oz_tile_of(int b, int tiles_m, int tiles_n, int 
 // For an MFMA, lane l supplies row l % 16, bytes 16*(l/16) .. +15 of the
 // k-step, for both operands, so every k pairs up.  Accumulation is exact in
 // int32.  Variants (selected by mpdd_opts.tile_id for the INT8 form):
-//   0: 256 x 256 (128 x 128 per wave, 1 workgroup per CU)
+//   0: 256 x 256 (128 x 128 per wave, 1 workgroup per CU; the default)
 //   1: 256 x 128 (128 x 64 per wave, 2 workgroups per CU)
-//   2: 128 x 128 (64 x 64 per wave)
+//   2: 128 x 128 (64 x 64 per wave, 3 workgroups per CU)
 constexpr int I8_BK = 64;
 constexpr int I8_PITCH = 80;
 constexpr int I8_PAD = 256;     // slice rows are padded to this for every variant
 
 template <int WM, int WN>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256, (WM * WN > 256 * 128) ? 1 : 2)
 oz_gemm_i8(const int8_t* __restrict__ qa, const int8_t* __restrict__ qb, int32_t* __restrict__ x,
            int64_t kp, int64_t plane_a, int64_t plane_b, int64_t mp, int64_t np, int nslices,
            int tiles_m, int tiles_n) {
@@ -235,13 +235,16 @@ oz_gemm_i8(const int8_t* __restrict__ qa, const int8_t* __restrict__ qb, int32_t
 #pragma unroll
     for (int c = 0; c < FB; ++c) acc[a][c] = v4i{0, 0, 0, 0};
 
-  // staging: thread loads 16 bytes (chunk tid%4) of rows tid/4 + 64*e
+  // staging: thread loads 16 bytes (chunk tid%4) of rows tid/4 + 64*e.  Global
+  // loads run two k-steps ahead of the MFMAs (two register sets, used
+  // alternately), so a load has two steps of matrix work to arrive before
+  // its data is written to LDS.
   const int srow = tid >> 2, scol = (tid & 3) * 16;
   const int64_t ksteps = kp / I8_BK;
   const int64_t total = (int64_t)(d - 1) * ksteps;
-  v4i ra[EA], rb[EB];
+  v4i ra0[EA], rb0[EB], ra1[EA], rb1[EB];
 
-  auto gload = [&](int64_t s) {
+  auto gload = [&](int64_t s, v4i (&ra)[EA], v4i (&rb)[EB]) {
     const int t = 1 + (int)(s / ksteps);          // slice of op(A); op(B) slice d - t
     const int64_t l0 = (s % ksteps) * I8_BK;
     const int8_t* pa = qa + (int64_t)(t - 1) * plane_a + (i0 + srow) * kp + l0 + scol;
@@ -251,20 +254,14 @@ oz_gemm_i8(const int8_t* __restrict__ qa, const int8_t* __restrict__ qb, int32_t
 #pragma unroll
     for (int e = 0; e < EB; ++e) rb[e] = *(const v4i*)(pb + 64 * e * kp);
   };
-  auto sstore = [&](int buf) {
+  auto sstore = [&](int buf, const v4i (&ra)[EA], const v4i (&rb)[EB]) {
 #pragma unroll
     for (int e = 0; e < EA; ++e) *(v4i*)&As[buf][(srow + 64 * e) * I8_PITCH + scol] = ra[e];
 #pragma unroll
     for (int e = 0; e < EB; ++e) *(v4i*)&Bs[buf][(srow + 64 * e) * I8_PITCH + scol] = rb[e];
   };
-
-  gload(0);
-  sstore(0);
-  __syncthreads();
   const int fr = lane & 15, fk = (lane >> 4) * 16;
-  for (int64_t s = 0; s < total; ++s) {
-    const int cur = (int)(s & 1);
-    if (s + 1 < total) gload(s + 1);
+  auto compute = [&](int cur) {
     v4i af[FA], bf[FB];
 #pragma unroll
     for (int a = 0; a < FA; ++a)
@@ -277,7 +274,30 @@ oz_gemm_i8(const int8_t* __restrict__ qa, const int8_t* __restrict__ qb, int32_t
 #pragma unroll
       for (int c = 0; c < FB; ++c)
         acc[a][c] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af[a], bf[c], acc[a][c], 0, 0, 0);
-    if (s + 1 < total) sstore(cur ^ 1);
+  };
+
+  // step s computes LDS buffer s & 1; even steps load into set 0 and store
+  // set 1, odd steps the other way round.  kp is a multiple of 2 * I8_BK, so
+  // the step count is even and both halves of every iteration run.
+  gload(0, ra0, rb0);
+  gload(1, ra1, rb1);
+  sstore(0, ra0, rb0);
+  __syncthreads();
+  // (the loads and stores are unconditional, so that the wait counts are the
+  // same on every iteration; past the end they re-read the last step, whose
+  // data is stored but never used)
+  for (int64_t s = 0; s < total; s += 2) {
+    gload(s + 2 < total ? s + 2 : total - 1, ra0, rb0);
+    // keep the loads ahead of the MFMAs (not for the 256 x 256 tile, whose
+    // accumulators leave no room for the longer-lived staging registers)
+    if constexpr (WM * WN <= 256 * 128) __builtin_amdgcn_sched_barrier(0);
+    compute(0);
+    sstore(1, ra1, rb1);
+    __syncthreads();
+    gload(s + 3 < total ? s + 3 : total - 1, ra1, rb1);
+    if constexpr (WM * WN <= 256 * 128) __builtin_amdgcn_sched_barrier(0);
+    compute(1);
+    sstore(0, ra0, rb0);
     __syncthreads();
   }
 
@@ -481,8 +501,11 @@ int ozaki_gemm(const void* opts_v, bool ta, bool tb, int64_t m, int64_t n, int64
   if (!digit_widths(algo, k, s, wfirst, w)) return MPDD_ERR_UNSUPPORTED;
 
   const bool i8 = (algo == MPDD_OZAKI_I8);
-  const int64_t kp = round_up(k, OZ_KPAD);
+  // INT8 slice rows are padded to an even number of product k-steps
+  const int64_t kp = round_up(k, i8 ? 2 * I8_BK : OZ_KPAD);
   // INT8 product variant (tile_id) and its workgroup tile
+  // (default 256 x 256: with loads two steps ahead it moves the least data
+  // per product and was the fastest measured at n = 4096 and 8192)
   const int var = (i8 && opts->tile_id >= 0) ? opts->tile_id : 0;
   if (i8 && var > 2) return MPDD_ERR_UNSUPPORTED;
   const int64_t tbm = i8 ? (var == 2 ? 128 : 256) : OZ_BM;

@@ -157,3 +157,22 @@ def test_struct_sizes_match_binding(lib):
     for name in ("mpdd_dd", "mpdd_ddc", "mpdd_opts", "mpdd_request", "mpdd_timing",
                  "mpdd_server_stats"):
         assert lib.mpdd_struct_size(name.encode()) == ctypes.sizeof(getattr(b, name)), name
+
+
+def test_potrf_argument_errors_before_handle(lib):
+    """Rpotrf reports LAPACK's negative argument positions in *info (return
+    value 0) before looking at the handle; valid arguments reach the handle
+    check; a NULL info pointer is rejected."""
+    from paper_2109_13406_amd import binding as b
+    info = ctypes.c_int64(99)
+
+    def p(uplo, n, lda, nb=0):
+        info.value = 99
+        rc = lib.mpdd_Rpotrf_nb(None, uplo, n, None, None, lda, nb, ctypes.byref(info), None)
+        return rc, info.value
+    assert p(b"X", 4, 4) == (0, -1)
+    assert p(b"l", -1, 4) == (0, -2)
+    assert p(b"U", 4, 3) == (0, -4)
+    assert p(b"u", 0, 0) == (0, -4)
+    assert p(b"L", 4, 4) == (b.MPDD_ERR_HANDLE, 0)
+    assert lib.mpdd_Rpotrf(None, b"L", 4, None, None, 4, None, None) == b.MPDD_ERR_ARG

@@ -195,6 +195,26 @@ def test_syrk_ragged(h, uplo, trans, shape):
             assert np.array_equal(bits(G[0]), bits(O[0])) and np.array_equal(bits(G[1]), bits(O[1]))
 
 
+@pytest.mark.parametrize("splitk", [2, 4, 0])
+@pytest.mark.parametrize("uplo", "UL")
+def test_syrk_splitk(h, uplo, splitk):
+    """k-split Rsyrk (scratch partials over the triangle's tiles, masked
+    reduce): within tolerance, opposite triangle and padding untouched; 0 is
+    the automatic choice, which splits a small triangle with a long k."""
+    from paper_2109_13406_amd import binding as b
+    for trans in "NT":
+        for (n, k) in ((70, 3000), (64, 2048), (130, 1100)):
+            case = W.syrk_case(850 + n + k, uplo, trans, n, k, dist="wide")
+            O = syrk_oracle(case)
+            for tile in (0, 2, 4):
+                info, G = syrk_gpu(h, case, opts=dict(algo=b.MPDD_PLAIN, tile_id=tile,
+                                                      splitk=splitk))
+                assert info == 0
+                r = compare_full(f"syrk splitk{splitk} {uplo}{trans} {n}x{k} tile{tile}", G, O,
+                                 n, n, k, case["ldc"], tri=uplo, C0=case["C"])
+                assert r <= RATIO_MAX
+
+
 def test_deterministic(h):
     case = W.gemm_case(900, "T", "T", 150, 140, 300)
     _, G1 = gemm_gpu(h, case)

@@ -193,6 +193,38 @@ def cgemm_case(seed, transa, transb, m, n, k, dist="uniform", padded=True, beta_
                 C=C, ldc=ldc, alpha=alpha, beta=beta)
 
 
+def spd_case(seed, n, uplo="L", padded=True, fail_at=None):
+    """Seeded symmetric positive definite dd matrix for Rpotrf: off-diagonal
+    entries dd U[-1, 1) (the same value at (i, j) and (j, i)), diagonal
+    n + U[0, 1) (so every Gershgorin disc lies right of 1 and the eigenvalues
+    cluster near n: a well-conditioned factorisation).  Only the uplo
+    triangle is stored; the opposite triangle and the padding rows hold the
+    NaN sentinel.  fail_at = k (1-based) makes A(k,k) = -1, so the leading
+    minor of order k is the first that is not positive definite."""
+    ra = streams(seed)[0]
+    ld = ld_padded(n) if padded else max(1, n)
+    hi = np.full(max(1, ld * n), SENTINEL_HI)
+    lo = np.full(max(1, ld * n), SENTINEL_LO)
+    if n == 0:
+        return dict(n=0, uplo=uplo, A=(hi, lo), lda=ld)
+    h, l = dd_values(ra, n * n, "uniform")
+    H = h.reshape(n, n)
+    L_ = l.reshape(n, n)
+    H = np.tril(H) + np.tril(H, -1).T
+    L_ = np.tril(L_) + np.tril(L_, -1).T
+    d = n + ra.uniform(0.0, 1.0, n)
+    H[np.arange(n), np.arange(n)] = d
+    L_[np.arange(n), np.arange(n)] = 0.0
+    if fail_at is not None:
+        H[fail_at - 1, fail_at - 1] = -1.0
+    i, j = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    keep = (i >= j) if uplo.upper() == "L" else (i <= j)
+    idx = (i + j * ld)[keep]
+    hi[idx] = H[keep]
+    lo[idx] = L_[keep]
+    return dict(n=n, uplo=uplo, A=(hi, lo), lda=ld)
+
+
 def config1_runs():
     """Plain Rgemm runs: four op combinations x square sizes, plus the
     rectangular 4096x4096x256 and skinny 8192x64x8192 shapes."""
@@ -355,3 +387,33 @@ def cgemm_case_device(seed, transa, transb, m, n, k, dist="uniform", padded=True
     beta = ((0.0, 0.0), (0.0, 0.0)) if beta_zero else cdd_scalar(rbe, "uniform")
     return dict(transa=transa, transb=transb, m=m, n=n, k=k, A=A, lda=lda, B=B, ldb=ldb,
                 C=C, ldc=ldc, alpha=alpha, beta=beta)
+
+
+def spd_case_device(seed, n, uplo="L", padded=True, device="cuda"):
+    """Device version of spd_case's recipe (torch's random stream): the uplo
+    triangle holds the matrix, the rest of the storage the NaN sentinel."""
+    import torch
+    ld = ld_padded(n) if padded else max(1, n)
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    f64 = torch.float64
+    sh = int(np.array([SENTINEL_HI]).view(np.int64)[0])
+    sl = int(np.array([SENTINEL_LO]).view(np.int64)[0])
+    hi = torch.empty(ld * n, dtype=f64, device=device)
+    lo = torch.empty(ld * n, dtype=f64, device=device)
+    hi.view(torch.int64).fill_(sh)
+    lo.view(torch.int64).fill_(sl)
+    h = torch.rand((n, n), generator=g, dtype=f64, device=device) * 2.0 - 1.0
+    l = h * 2.0 ** -53 * (torch.rand((n, n), generator=g, dtype=f64, device=device) * 2.0 - 1.0)
+    s = h + l
+    l = l - (s - h)
+    h = s
+    r = torch.arange(n, device=device)
+    h[r, r] = n + torch.rand(n, generator=g, dtype=f64, device=device)
+    l[r, r] = 0.0
+    # storage (i, j) at [j*ld + i]: rows of the (n, ld) view are columns j
+    keep = (r[:, None] >= r[None, :]) if uplo.upper() == "L" else (r[:, None] <= r[None, :])
+    for plane, src in ((hi, h), (lo, l)):
+        v = plane[: n * ld].view(n, ld)[:, :n]          # v[j, i] = A(i, j)
+        v.copy_(torch.where(keep.T, src.T, v))
+    return dict(n=n, uplo=uplo, A=(hi, lo), lda=ld)
