@@ -916,3 +916,125 @@ def check_potrf_transpose_and_info(lib):
     assert oracle.rpotrf("L", 2, (h, l), 1, lib=lib) == -4
     assert oracle.rpotrf("L", 0, (h, l), 1, lib=lib) == 0
     assert np.all(h == 5.0)
+
+
+# ---- quad-double Rgemm -----------------------------------------------------------------
+
+def qd_of(v):
+    """Greedy nearest rounding of an exact rational to a qd: x0 = RN(v),
+    x1 = RN(v - x0), ... (Python's float() of a Fraction rounds to nearest,
+    ties to even)."""
+    out = []
+    for _ in range(4):
+        x = float(v)
+        out.append(x)
+        v = v - Fraction(x)
+    return tuple(out)
+
+
+def QF(*parts):
+    return sum((Fraction(float(p)) for p in parts), Fraction(0))
+
+
+def check_qd_round(lib, count=200):
+    rng = np.random.default_rng(21)
+    for t in range(count):
+        n = int(rng.integers(1, 12))
+        e = rng.integers(-200, 60, n)
+        terms = np.ldexp(rng.uniform(-1.0, 1.0, n), e)
+        if t % 5 == 0:                       # heavy cancellation
+            terms = np.concatenate([terms, -terms[:1] * (1 + 2.0 ** -50)])
+        want = qd_of(sum((Fraction(float(x)) for x in terms), Fraction(0)))
+        got = oracle.qd_round_sum(terms, lib=lib)
+        assert got == want, (t, got, want)
+    assert oracle.qd_round_sum([0.1, 0.2], lib=lib) == (0.30000000000000004, -2.7755575615628914e-17,
+                                                       0.0, 0.0)
+    # ties to even on the last part: 1 + 2^-53 rounds to 1, remainder 2^-53 exactly
+    assert oracle.qd_round_sum([1.0, 2.0 ** -53], lib=lib) == (1.0, 2.0 ** -53, 0.0, 0.0)
+    assert oracle.qd_round_sum([], lib=lib) == (0.0, 0.0, 0.0, 0.0)
+
+
+def check_qgemm_exact(lib, seeds=range(2), dist="uniform",
+                      sizes=((1, 1, 1), (2, 3, 4), (4, 3, 2), (3, 2, 5))):
+    """Every entry of the oracle's qd Rgemm equals the greedy nearest qd of the
+    exact result (Fraction arithmetic), bit for bit, in all four op forms;
+    padding rows are untouched."""
+    for seed in seeds:
+        for (m, n, k) in sizes:
+            for ta in "NT":
+                for tb in "NT":
+                    c = W.qgemm_case(6000 + seed, ta, tb, m, n, k, dist=dist)
+                    C0 = tuple(p.copy() for p in c["C"])
+                    assert oracle.qgemm(ta, tb, m, n, k, c["alpha"], c["A"], c["lda"], c["B"],
+                                        c["ldb"], c["beta"], c["C"], c["ldc"], lib=lib) == 0
+                    al, be = QF(*c["alpha"]), QF(*c["beta"])
+
+                    def op(P, ld, t, r, q):
+                        idx = (q + r * ld) if t == "T" else (r + q * ld)
+                        return QF(*(p[idx] for p in P))
+                    for i in range(m):
+                        for j in range(n):
+                            o = i + j * c["ldc"]
+                            dot = sum((op(c["A"], c["lda"], ta, i, l) * op(c["B"], c["ldb"], tb, l, j)
+                                       for l in range(k)), Fraction(0))
+                            want = qd_of(al * dot + be * QF(*(p[o] for p in C0)))
+                            got = tuple(float(p[o]) for p in c["C"])
+                            assert got == want, (seed, m, n, k, ta, tb, i, j)
+                    ldc = c["ldc"]
+                    pad = np.ones(ldc * n, bool)
+                    for j in range(n):
+                        pad[j * ldc: j * ldc + m] = False
+                    for p, p0 in zip(c["C"], C0):
+                        assert np.array_equal(bits(p)[pad], bits(p0)[pad])
+
+
+def check_qgemm_semantics(lib):
+    """The worked Rgemm example in qd (integer data: exact), quick returns,
+    beta = 0 with a NaN C, alpha = 0, and the BLAS argument positions."""
+    alpha, beta, v = read_worked_example()
+    z = np.zeros(9)
+    for ta in "NT":
+        for tb in "NT":
+            A = colmajor(v["A"] if ta == "N" else v["A"].T)
+            B = colmajor(v["B"] if tb == "N" else v["B"].T)
+            C = (colmajor(v["C"]), z.copy(), z.copy(), z.copy())
+            assert oracle.qgemm(ta, tb, 3, 3, 3, (alpha, 0, 0, 0), (A, z, z, z), 3,
+                                (B, z, z, z), 3, (beta, 0, 0, 0), C, 3, lib=lib) == 0
+            assert np.array_equal(C[0], colmajor(v["ANSWER"]))
+            assert not C[1].any() and not C[2].any() and not C[3].any()
+    c = W.qgemm_case(6100, "N", "T", 5, 4, 3, c_nan=True)
+    one, zero = (1.0, 0.0, 0.0, 0.0), (0.0,) * 4
+    # alpha = 0, beta = 1: quick return, C bit-identical
+    Cw = tuple(p.copy() for p in c["C"])
+    assert oracle.qgemm("N", "T", 5, 4, 3, zero, c["A"], c["lda"], c["B"], c["ldb"], one, Cw,
+                        c["ldc"], lib=lib) == 0
+    for p, q in zip(Cw, c["C"]):
+        assert np.array_equal(bits(p), bits(q))
+    # beta = 0: NaN C not read; with alpha = 0 as well the result is exactly 0
+    for al in (c["alpha"], zero):
+        Cw = tuple(p.copy() for p in c["C"])
+        assert oracle.qgemm("N", "T", 5, 4, 3, al, c["A"], c["lda"], c["B"], c["ldb"], zero, Cw,
+                            c["ldc"], lib=lib) == 0
+        i, j = np.meshgrid(np.arange(5), np.arange(4), indexing="ij")
+        idx = (i + j * c["ldc"]).ravel()
+        for p in Cw:
+            assert np.all(np.isfinite(p[idx]))
+            if al is zero:
+                assert not p[idx].any()
+    pos = read_arg_positions()
+    N4 = (None,) * 4
+    C4 = tuple(np.zeros(9) for _ in range(4))
+
+    def info(ta="N", tb="N", m=2, n=2, k=2, lda=None, ldb=None, ldc=None):
+        lda = lda if lda is not None else max(1, m if ta == "N" else k)
+        ldb = ldb if ldb is not None else max(1, k if tb == "N" else n)
+        ldc = ldc if ldc is not None else max(1, m)
+        return oracle.qgemm(ta, tb, m, n, k, one, N4, lda, N4, ldb, zero, C4, ldc, lib=lib)
+    assert info(ta="X") == pos[("gemm", "transa")]
+    assert info(tb="q") == pos[("gemm", "transb")]
+    assert info(m=-1) == pos[("gemm", "m")]
+    assert info(n=-1) == pos[("gemm", "n")]
+    assert info(k=-1) == pos[("gemm", "k")]
+    assert info(m=3, lda=2) == pos[("gemm", "lda")]
+    assert info(k=3, ldb=2) == pos[("gemm", "ldb")]
+    assert info(m=3, lda=3, ldc=2) == pos[("gemm", "ldc")]

@@ -98,6 +98,21 @@ MUTANTS = [
      "return (i + l * lda);", "Cholesky: upper written as lower"),
     ("potrf_oracle.c", "acc = dd_div(acc, ljj);", "acc = dd_div(acc, d);",
      "Cholesky: divided by the pivot instead of its root"),
+    ("qd_oracle.c", "if (rem > half || (rem == half && (sticky || (mant & 1)))) mant += 1;",
+     "if (rem > half && 0) mant += 1;", "qd rounding truncates"),
+    ("qd_oracle.c", "if (rem > half || (rem == half && (sticky || (mant & 1)))) mant += 1;",
+     "if (rem >= half) mant += 1;", "qd rounding ties away from zero"),
+    ("qd_oracle.c", "    qacc_add(acc, e3);\n", "", "qd: last part of a triple product dropped"),
+    ("qd_oracle.c", "int64_t c = a->d[i] >> 32;     /* arithmetic shift: floor division */",
+     "int64_t c = a->d[i] >> 31;", "qd accumulator: wrong carry"),
+    ("qd_oracle.c", "for (p = 0; p < 4; ++p) qacc_add2(&acc, beta[r], C[p][o]);",
+     "for (p = 0; p < 4; ++p) qacc_add2(&acc, beta[0], C[p][o]);", "qd: beta's low parts ignored"),
+    ("qd_oracle.c", "if (alpha[r] == 0.0) continue;", "if (r > 0) continue;",
+     "qd: alpha's low parts ignored"),
+    ("qd_oracle.c", "((q_zero(alpha) || k == 0) && q_one(beta))) return 0;",
+     "((q_zero(alpha) || k == 0) && q_zero(beta))) return 0;", "qd: wrong quick return"),
+    ("qd_oracle.c", "    if (neg) {                          /* two's complement negate",
+     "    if (0) {                          /* two's complement negate", "qd: sign lost in rounding"),
 ]
 
 CHECKS = [
@@ -117,6 +132,9 @@ CHECKS = [
     pins.check_potrf_exact_integer,
     lambda lib: pins.check_potrf_residual(lib, sizes=(3, 6)),
     pins.check_potrf_transpose_and_info,
+    pins.check_qd_round,
+    lambda lib: pins.check_qgemm_exact(lib, seeds=[0]),
+    pins.check_qgemm_semantics,
 ]
 
 

@@ -225,6 +225,65 @@ def spd_case(seed, n, uplo="L", padded=True, fail_at=None):
     return dict(n=n, uplo=uplo, A=(hi, lo), lda=ld)
 
 
+def qd_values(rng, count, dist="uniform"):
+    """`count` normalised quad-doubles as four float64 arrays (x0, x1, x2, x3):
+    x0 by the dd recipe's leading-part distribution, then each further part
+    x_t = x_{t-1} 2^-54 U(-1, 1), below half an ulp of the part before."""
+    if dist == "uniform":
+        x0 = rng.uniform(-1.0, 1.0, count)
+    elif dist == "wide":
+        mant = rng.uniform(1.0, 2.0, count)
+        e = rng.integers(-20, 21, count)
+        sign = np.where(rng.integers(0, 2, count) == 0, -1.0, 1.0)
+        x0 = sign * np.ldexp(mant, e)
+    elif dist == "int":
+        return (rng.integers(-8, 9, count).astype(np.float64),) + (np.zeros(count),) * 3
+    else:
+        raise ValueError(dist)
+    parts = [x0]
+    for _ in range(3):
+        parts.append(parts[-1] * 2.0 ** -54 * rng.uniform(-1.0, 1.0, count))
+    return tuple(parts)
+
+
+def qd_matrix(rng, rows, cols, ld=None, dist="uniform", pad=True):
+    """Column-major qd matrix: four flat planes of length ld*cols; padding rows
+    hold the NaN sentinel (its hi pattern in every plane)."""
+    ld = rows if ld is None else ld
+    assert ld >= max(1, rows)
+    size = max(1, ld * cols)
+    planes = [np.full(size, SENTINEL_HI if pad else 0.0) for _ in range(4)]
+    if rows * cols:
+        vals = qd_values(rng, rows * cols, dist)
+        for p, v in zip(planes, vals):
+            p[: ld * cols].reshape(cols, ld)[:, :rows] = v.reshape(cols, rows)
+    return tuple(planes)
+
+
+def qgemm_case(seed, transa, transb, m, n, k, dist="uniform", padded=True, beta_zero=False,
+               c_nan=False):
+    """One seeded quad-double Rgemm case: A, B, C 4-tuples of planes, alpha and
+    beta 4-tuples of floats."""
+    ra, rb, rc, ral, rbe = streams(seed)
+    nra = m if transa.upper() == "N" else k
+    nca = k if transa.upper() == "N" else m
+    nrb = k if transb.upper() == "N" else n
+    ncb = n if transb.upper() == "N" else k
+    lda = ld_padded(nra) if padded else max(1, nra)
+    ldb = ld_padded(nrb) if padded else max(1, nrb)
+    ldc = ld_padded(m) if padded else max(1, m)
+    A = qd_matrix(ra, nra, nca, lda, dist)
+    B = qd_matrix(rb, nrb, ncb, ldb, dist)
+    C = qd_matrix(rc, m, n, ldc, dist)
+    if c_nan:
+        for p in C:
+            p[:] = SENTINEL_HI
+    alpha = tuple(float(v[0]) for v in qd_values(ral, 1, "uniform"))
+    beta = (0.0,) * 4 if beta_zero else tuple(float(v[0]) for v in qd_values(rbe, 1, "uniform"))
+    return dict(transa=transa, transb=transb, m=m, n=n, k=k, A=A, lda=lda, B=B, ldb=ldb,
+                C=C, ldc=ldc, alpha=alpha, beta=beta)
+
+
 def config1_runs():
     """Plain Rgemm runs: four op combinations x square sizes, plus the
     rectangular 4096x4096x256 and skinny 8192x64x8192 shapes."""
