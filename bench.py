@@ -1,7 +1,7 @@
 """Benchmark: dd Rgemm on one MI355X, plain and split forms, plus served latency.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 8192] [--no-cpu]
-                    [--sections plain,syrk,cgemm,potrf,ozaki,host,serve]
+                    [--sections plain,syrk,cgemm,potrf,qd,ozaki,host,serve]
 
 One step = one dd Rgemm NN, m = n = k = n (8192), leading dimensions 8195,
 C <- alpha*A*B + beta*C on float64 hi/lo planes already resident in HBM.
@@ -196,6 +196,41 @@ def bench_potrf(h, args, stream):
             "dd_gflops": round(float(n) ** 3 / 3.0 / t / 1e9, 1)}
 
 
+def bench_qd(h, args, stream):
+    """Quad-double Rgemm NN at n/4 (four planes per matrix; ~10x the binary64
+    work of a dd multiply-add).  qd-flops 2mnk."""
+    import torch
+    import workloads as W
+    from paper_2109_13406_amd import binding as b
+    n = max(1, args.n // 4)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(W.BASE_SEED + 9)
+    ld = W.ld_padded(n)
+
+    def qmat():
+        x0 = torch.rand(ld * n, generator=g, dtype=torch.float64, device="cuda") * 2 - 1
+        parts = [x0]
+        for _ in range(3):
+            u = torch.rand(ld * n, generator=g, dtype=torch.float64, device="cuda") * 2 - 1
+            parts.append(parts[-1] * 2.0 ** -54 * u)
+        return tuple(parts)
+    A, B, C = qmat(), qmat(), qmat()
+    alpha, beta = (0.75, 2.0 ** -60, 0.0, 0.0), (-0.5, 0.0, 0.0, 0.0)
+    torch.cuda.synchronize()
+
+    def step():
+        info = b.mpdd_Qgemm(h, "N", "N", n, n, n, alpha, A, ld, B, ld, beta, C, ld, stream=stream)
+        if info != 0:
+            raise RuntimeError(f"mpdd_Qgemm info={info}")
+
+    total, per = timed_calls(step, max(1, args.steps // 2), 1, stream)
+    t = sum(per) / len(per)
+    del A, B, C
+    torch.cuda.empty_cache()
+    return {"workload": f"Qgemm NN m=n=k={n} ld={ld} (quad-double, four binary64 planes each)",
+            "ms": round(t * 1e3, 3), "qd_gflops": round(2.0 * n ** 3 / t / 1e9, 1)}
+
+
 def ratio_gpu(C, R, m, n, ldc, k):
     """Normwise dd difference of the stored m x n entries of C from R in units
     of k * 2^-104, on the device (the tests' metric: (hi - hi') + (lo - lo'))."""
@@ -345,7 +380,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=8192)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--sections", default="plain,syrk,cgemm,potrf,ozaki,host,serve")
+    ap.add_argument("--sections", default="plain,syrk,cgemm,potrf,qd,ozaki,host,serve")
     ap.add_argument("--tile", type=int, default=-1,
                     help="tile-table entry for the plain product (-1: the library's choice)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
@@ -408,6 +443,9 @@ def main():
     if "syrk" in sections:
         out["rsyrk"] = bench_syrk(h, args, stream)
         log(f"rsyrk: {out['rsyrk']}")
+    if "qd" in sections:
+        out["qgemm"] = bench_qd(h, args, stream)
+        log(f"qgemm: {out['qgemm']}")
     if "potrf" in sections:
         out["rpotrf"] = bench_potrf(h, args, stream)
         log(f"rpotrf: {out['rpotrf']}")

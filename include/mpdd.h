@@ -176,6 +176,25 @@ int mpdd_Cgemm(mpdd_handle h, const char *transa, const char *transb, mpdd_int m
                const double *B_im_lo, mpdd_int ldb, mpdd_ddc beta, double *C_re_hi,
                double *C_re_lo, double *C_im_hi, double *C_im_lo, mpdd_int ldc, void *stream);
 
+/* ---- quad-double: Qgemm --------------------------------------------------------------
+ *
+ * Rgemm on quad-double values (manual, section "Supported Floating point
+ * formats": qd_real, four binary64 numbers x0 + x1 + x2 + x3, about 64 digits,
+ * epsilon 2^-209 in Table "rlamch_qd"; MPBLAS provides the same Rgemm for
+ * qd_real as for dd_real, section "How to use reference MPBLAS").
+ * C <- alpha*op(A)*op(B) + beta*C with DGEMM's arguments, info codes, NULL
+ * rules and quick returns.  Every matrix is four DEVICE planes (x0, x1, x2,
+ * x3), each column-major with the matrix's leading dimension; alpha and beta
+ * are qd scalars by value.  Inputs are assumed normalised (|x_{t+1}| <= half
+ * an ulp of x_t); outputs are.  Stream-ordered and asynchronous, no scratch. */
+typedef struct { double x[4]; } mpdd_qd;       /* quad-double scalar */
+
+int mpdd_Qgemm(mpdd_handle h, const char *transa, const char *transb, mpdd_int m, mpdd_int n,
+               mpdd_int k, mpdd_qd alpha, const double *A0, const double *A1, const double *A2,
+               const double *A3, mpdd_int lda, const double *B0, const double *B1,
+               const double *B2, const double *B3, mpdd_int ldb, mpdd_qd beta, double *C0,
+               double *C1, double *C2, double *C3, mpdd_int ldc, void *stream);
+
 /* ---- Cholesky factorisation: Rpotrf -------------------------------------------------
  *
  * Rpotrf: the dd Cholesky factorisation of a symmetric positive definite

@@ -36,6 +36,10 @@ class mpdd_ddc(ctypes.Structure):
     _fields_ = [("re", mpdd_dd), ("im", mpdd_dd)]
 
 
+class mpdd_qd(ctypes.Structure):
+    _fields_ = [("x", ctypes.c_double * 4)]
+
+
 class mpdd_opts(ctypes.Structure):
     _fields_ = [("algo", ctypes.c_int), ("nslices", ctypes.c_int), ("tile_id", ctypes.c_int),
                 ("splitk", ctypes.c_int)]
@@ -91,6 +95,8 @@ SIGNATURES = {
                                      _P, _I, mpdd_dd, _P, _P, _I, _P]),
     "mpdd_Cgemm": (ctypes.c_int, [_P, _C, _C, _I, _I, _I, mpdd_ddc, _P, _P, _P, _P, _I, _P, _P, _P,
                                   _P, _I, mpdd_ddc, _P, _P, _P, _P, _I, _P]),
+    "mpdd_Qgemm": (ctypes.c_int, [_P, _C, _C, _I, _I, _I, mpdd_qd, _P, _P, _P, _P, _I, _P, _P, _P,
+                                  _P, _I, mpdd_qd, _P, _P, _P, _P, _I, _P]),
     "mpdd_Rpotrf": (ctypes.c_int, [_P, _C, _I, _P, _P, _I, ctypes.POINTER(_I), _P]),
     "mpdd_Rpotrf_nb": (ctypes.c_int, [_P, _C, _I, _P, _P, _I, _I, ctypes.POINTER(_I), _P]),
     "mpdd_ozaki_digit_widths": (ctypes.c_int, [ctypes.c_int, _I, ctypes.c_int,
@@ -221,6 +227,22 @@ def mpdd_Cgemm(h, transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, 
     pointers.  Returns info."""
     return load().mpdd_Cgemm(h, _flag(transa), _flag(transb), m, n, k, _ddc(alpha),
                              *map(_ptr, A), lda, *map(_ptr, B), ldb, _ddc(beta), *map(_ptr, C),
+                             ldc, _stream(stream))
+
+
+def _qd(x):
+    if isinstance(x, mpdd_qd):
+        return x
+    if isinstance(x, (int, float)):
+        x = (float(x), 0.0, 0.0, 0.0)
+    return mpdd_qd((ctypes.c_double * 4)(*[float(v) for v in x]))
+
+
+def mpdd_Qgemm(h, transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, stream=None):
+    """Quad-double Rgemm.  A, B, C: 4-tuples of planes (x0..x3) as tensors or
+    device pointers; alpha, beta: 4-tuples of floats.  Returns info."""
+    return load().mpdd_Qgemm(h, _flag(transa), _flag(transb), m, n, k, _qd(alpha),
+                             *map(_ptr, A), lda, *map(_ptr, B), ldb, _qd(beta), *map(_ptr, C),
                              ldc, _stream(stream))
 
 

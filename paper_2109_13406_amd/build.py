@@ -23,7 +23,7 @@ LIB = os.path.join(PKG, "libmpdd.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = ["mpdd.cpp", "tuner.cpp", "server.cpp", "host_api.cpp", "gemm_plain.hip", "ozaki.hip",
-           "complex.hip", "potrf.hip"]
+           "complex.hip", "potrf.hip", "qd.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-ffp-contract=off",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wall", "-Wno-unused-function", "-I", os.path.join(ROOT, "include")]

@@ -71,6 +71,22 @@ struct CEpilogue {
 };
 hipError_t launch_cgemm_epilogue(const CEpilogue& p, hipStream_t st);
 
+// Quad-double Rgemm (qd.hip): four planes per matrix, alpha / beta as
+// {x0, x1, x2, x3}.  scale_only: C <- beta C (alpha = 0 or k = 0);
+// beta_zero: C is not read.
+struct QgemmParams {
+  int64_t m, n, k;
+  double alpha[4], beta[4];
+  const double* a[4];
+  int64_t lda;
+  const double* b[4];
+  int64_t ldb;
+  double* c[4];
+  int64_t ldc;
+  int beta_zero, scale_only;
+};
+hipError_t launch_qgemm(const QgemmParams& p, bool ta, bool tb, hipStream_t st);
+
 // Cholesky diagonal block (potrf.hip): factor the jb x jb block (jb <= 64)
 // read from s (ld lds) in the lower view (upper = 1: the block holds U, read
 // transposed), write the factor's triangle to a (ld lda) and the inverse of

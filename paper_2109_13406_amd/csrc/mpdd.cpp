@@ -183,6 +183,7 @@ size_t mpdd_struct_size(const char* name) {
   if (!name) return 0;
   if (std::strcmp(name, "mpdd_dd") == 0) return sizeof(mpdd_dd);
   if (std::strcmp(name, "mpdd_ddc") == 0) return sizeof(mpdd_ddc);
+  if (std::strcmp(name, "mpdd_qd") == 0) return sizeof(mpdd_qd);
   if (std::strcmp(name, "mpdd_opts") == 0) return sizeof(mpdd_opts);
   if (std::strcmp(name, "mpdd_request") == 0) return sizeof(mpdd_request);
   if (std::strcmp(name, "mpdd_timing") == 0) return sizeof(mpdd_timing);
@@ -495,6 +496,38 @@ int mpdd_Rpotrf_nb(mpdd_handle h, const char* uplo, mpdd_int n, double* A_hi, do
 int mpdd_Rpotrf(mpdd_handle h, const char* uplo, mpdd_int n, double* A_hi, double* A_lo,
                 mpdd_int lda, mpdd_int* info, void* stream) {
   return mpdd_Rpotrf_nb(h, uplo, n, A_hi, A_lo, lda, 0, info, stream);
+}
+
+// Quad-double Rgemm: one launch of the qd tile kernel (or the scale kernel
+// when alpha = 0 or k = 0).
+int mpdd_Qgemm(mpdd_handle h, const char* transa, const char* transb, mpdd_int m, mpdd_int n,
+               mpdd_int k, mpdd_qd alpha, const double* A0, const double* A1, const double* A2,
+               const double* A3, mpdd_int lda, const double* B0, const double* B1,
+               const double* B2, const double* B3, mpdd_int ldb, mpdd_qd beta, double* C0,
+               double* C1, double* C2, double* C3, mpdd_int ldc, void* stream) {
+  const int info = check_gemm(transa, transb, m, n, k, lda, ldb, ldc);
+  if (info) return info;
+  if (!handle_ok(h)) return MPDD_ERR_HANDLE;
+  auto qzero = [](const mpdd_qd& x) { return x.x[0] == 0 && x.x[1] == 0 && x.x[2] == 0 && x.x[3] == 0; };
+  const bool alpha_zero = qzero(alpha), beta_zero = qzero(beta);
+  const bool beta_one = beta.x[0] == 1.0 && beta.x[1] == 0 && beta.x[2] == 0 && beta.x[3] == 0;
+  if (m == 0 || n == 0 || ((alpha_zero || k == 0) && beta_one)) return 0;
+  if (!C0 || !C1 || !C2 || !C3) return MPDD_ERR_ARG;
+  const bool use_ab = !alpha_zero && k > 0;
+  if (use_ab && (!A0 || !A1 || !A2 || !A3 || !B0 || !B1 || !B2 || !B3)) return MPDD_ERR_ARG;
+  QgemmParams p{};
+  p.m = m; p.n = n; p.k = k;
+  for (int t = 0; t < 4; ++t) {
+    p.alpha[t] = alpha.x[t];
+    p.beta[t] = beta.x[t];
+  }
+  p.a[0] = A0; p.a[1] = A1; p.a[2] = A2; p.a[3] = A3; p.lda = lda;
+  p.b[0] = B0; p.b[1] = B1; p.b[2] = B2; p.b[3] = B3; p.ldb = ldb;
+  p.c[0] = C0; p.c[1] = C1; p.c[2] = C2; p.c[3] = C3; p.ldc = ldc;
+  p.beta_zero = beta_zero ? 1 : 0;
+  p.scale_only = use_ab ? 0 : 1;
+  return hip_status(launch_qgemm(p, !lsame(transa, 'N'), !lsame(transb, 'N'),
+                                 (hipStream_t)stream));
 }
 
 int mpdd_Rsyrk(mpdd_handle h, const char* uplo, const char* trans, mpdd_int n, mpdd_int k,

@@ -154,7 +154,7 @@ def test_cgemm_info_codes_before_handle(lib):
 
 def test_struct_sizes_match_binding(lib):
     from paper_2109_13406_amd import binding as b
-    for name in ("mpdd_dd", "mpdd_ddc", "mpdd_opts", "mpdd_request", "mpdd_timing",
+    for name in ("mpdd_dd", "mpdd_ddc", "mpdd_qd", "mpdd_opts", "mpdd_request", "mpdd_timing",
                  "mpdd_server_stats"):
         assert lib.mpdd_struct_size(name.encode()) == ctypes.sizeof(getattr(b, name)), name
 
@@ -176,3 +176,27 @@ def test_potrf_argument_errors_before_handle(lib):
     assert p(b"u", 0, 0) == (0, -4)
     assert p(b"L", 4, 4) == (b.MPDD_ERR_HANDLE, 0)
     assert lib.mpdd_Rpotrf(None, b"L", 4, None, None, 4, None, None) == b.MPDD_ERR_ARG
+
+
+def test_qgemm_info_codes_before_handle(lib):
+    from paper_2109_13406_amd import binding as b
+    pos = pins.read_arg_positions()
+    one = b._qd((1.0, 0.0, 0.0, 0.0))
+    N4 = (None,) * 4
+
+    def q(ta="N", tb="N", m=2, n=2, k=2, lda=None, ldb=None, ldc=None):
+        lda = lda if lda is not None else max(1, m if ta.upper() == "N" else k)
+        ldb = ldb if ldb is not None else max(1, k if tb.upper() == "N" else n)
+        ldc = ldc if ldc is not None else max(1, m)
+        return lib.mpdd_Qgemm(None, ta.encode(), tb.encode(), m, n, k, one, *N4, lda, *N4, ldb,
+                              one, *N4, ldc, None)
+    H = b.MPDD_ERR_HANDLE
+    assert q() == H and q(ta="t", tb="C") == H
+    assert q(ta="X") == pos[("gemm", "transa")]
+    assert q(tb="z") == pos[("gemm", "transb")]
+    assert q(m=-1) == pos[("gemm", "m")]
+    assert q(n=-1) == pos[("gemm", "n")]
+    assert q(k=-1) == pos[("gemm", "k")]
+    assert q(m=3, lda=2) == pos[("gemm", "lda")]
+    assert q(k=3, ldb=2) == pos[("gemm", "ldb")]
+    assert q(m=3, lda=3, ldc=2) == pos[("gemm", "ldc")]

@@ -1,0 +1,172 @@
+"""GPU parity of the quad-double Rgemm (through the C ABI) against the CPU
+oracle, whose entries are the exact results rounded to a qd: ragged shapes in
+all four op forms and both input sets, the manual's worked Rgemm example
+(exact), BLAS semantics (beta = 0 with NaN C, alpha = 0, k = 0, quick
+returns, untouched padding, info codes), and a 1024-size product checked on
+sampled rows and columns.
+
+Error metric: dC = sum_t (x_t,gpu - x_t,oracle) in binary64 per entry (the
+leading differences are exact for close values); pass when
+||dC||_F / ||C_oracle||_F <= 8 k 2^-209 (2^-209 is the qd epsilon of the
+manual's Table "rlamch_qd")."""
+import numpy as np
+import pytest
+
+import oracle
+import pins
+import workloads as W
+from gpu_util import csub, log
+from oracle.compare import bits
+
+pytestmark = pytest.mark.gpu
+
+EPS_QD = 2.0 ** -209
+RATIO_MAX = 8.0
+
+
+@pytest.fixture(scope="module")
+def h():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2109_13406_amd import binding as b
+    handle = b.mpdd_create()
+    yield handle
+    torch.cuda.synchronize()
+    b.mpdd_destroy(handle)
+
+
+def dev4(planes):
+    import torch
+    return tuple(torch.from_numpy(np.ascontiguousarray(x)).cuda() for x in planes)
+
+
+def host4(planes):
+    import torch
+    torch.cuda.synchronize()
+    return tuple(x.cpu().numpy() for x in planes)
+
+
+def qgemm_gpu(h, c):
+    from paper_2109_13406_amd import binding as b
+    C = dev4(c["C"])
+    info = b.mpdd_Qgemm(h, c["transa"], c["transb"], c["m"], c["n"], c["k"], c["alpha"],
+                        dev4(c["A"]), c["lda"], dev4(c["B"]), c["ldb"], c["beta"], C, c["ldc"])
+    return info, host4(C)
+
+
+def qgemm_oracle(c):
+    O = tuple(p.copy() for p in c["C"])
+    assert oracle.qgemm(c["transa"], c["transb"], c["m"], c["n"], c["k"], c["alpha"], c["A"],
+                        c["lda"], c["B"], c["ldb"], c["beta"], O, c["ldc"]) == 0
+    return O
+
+
+def qratio(G, O, idx, k):
+    d = sum((G[t][idx] - O[t][idx] for t in range(4)), np.zeros(len(idx)))
+    if not np.all(np.isfinite(d)):
+        return float("inf")
+    nref = np.linalg.norm(O[0][idx])
+    nd = np.linalg.norm(d)
+    if nref == 0.0:
+        return 0.0 if nd == 0.0 else float("inf")
+    return float(nd / nref / (max(k, 1) * EPS_QD))
+
+
+def stored(m, n, ldc):
+    i, j = np.meshgrid(np.arange(m), np.arange(n), indexing="ij")
+    return (i + j * ldc).ravel()
+
+
+def compare(label, G, O, C0, m, n, k, ldc):
+    idx = stored(m, n, ldc)
+    r = qratio(G, O, idx, k)
+    log(f"PARITY qgemm {label}: ratio {r:.4g}")
+    rest = np.ones(G[0].shape[0], bool)
+    rest[idx] = False
+    for g, c0 in zip(G, C0):
+        assert np.array_equal(bits(g)[rest], bits(c0)[rest]), label
+    return r
+
+
+def test_worked_example_exact(h):
+    alpha, beta, v = pins.read_worked_example()
+    z = np.zeros(9)
+    for ta in "NT":
+        for tb in "NT":
+            A = pins.colmajor(v["A"] if ta == "N" else v["A"].T)
+            B = pins.colmajor(v["B"] if tb == "N" else v["B"].T)
+            c = dict(transa=ta, transb=tb, m=3, n=3, k=3, alpha=(alpha, 0, 0, 0),
+                     beta=(beta, 0, 0, 0), A=(A, z, z, z), lda=3, B=(B, z, z, z), ldb=3,
+                     C=(pins.colmajor(v["C"]), z.copy(), z.copy(), z.copy()), ldc=3)
+            info, G = qgemm_gpu(h, c)
+            assert info == 0
+            assert np.array_equal(G[0], pins.colmajor(v["ANSWER"])), (ta, tb, G[0])
+            assert not G[1].any() and not G[2].any() and not G[3].any()
+
+
+SHAPES = [(1, 1, 1), (33, 47, 19), (70, 9, 65), (64, 64, 64), (5, 40, 130)]
+
+
+@pytest.mark.parametrize("op", W.OPS)
+def test_qgemm_ragged(h, op):
+    for (m, n, k) in SHAPES:
+        for dist in ("uniform", "wide"):
+            c = W.qgemm_case(7000 + m + k, op[0], op[1], m, n, k, dist=dist)
+            O = qgemm_oracle(c)
+            info, G = qgemm_gpu(h, c)
+            assert info == 0
+            r = compare(f"{op} {m}x{n}x{k} {dist}", G, O, c["C"], m, n, k, c["ldc"])
+            assert r <= RATIO_MAX, (op, m, n, k, dist, r)
+
+
+def test_qgemm_semantics(h):
+    from paper_2109_13406_amd import binding as b
+    zero, one = (0.0,) * 4, (1.0, 0.0, 0.0, 0.0)
+    N4 = (None,) * 4
+    # beta = 0: a NaN C is not read
+    c = W.qgemm_case(7100, "T", "N", 21, 18, 12, beta_zero=True, c_nan=True)
+    O = qgemm_oracle(c)
+    info, G = qgemm_gpu(h, c)
+    assert info == 0
+    assert compare("beta0", G, O, c["C"], 21, 18, 12, c["ldc"]) <= RATIO_MAX
+    # alpha = 0 (A, B NULL): C <- beta C; k = 0 likewise
+    for kk in (7, 0):
+        c = W.qgemm_case(7101 + kk, "N", "T", 13, 11, max(kk, 1))
+        c["alpha"], c["k"] = (zero if kk else c["alpha"]), kk
+        O = qgemm_oracle(c)
+        C = dev4(c["C"])
+        assert b.mpdd_Qgemm(h, "N", "T", 13, 11, kk, c["alpha"], N4, c["lda"], N4, c["ldb"],
+                            c["beta"], C, c["ldc"]) == 0
+        G = host4(C)
+        assert compare(f"alpha0/k0 k={kk}", G, O, c["C"], 13, 11, 1, c["ldc"]) <= RATIO_MAX
+    # quick returns leave C bit-identical; an invalid ldb enqueues nothing
+    c = W.qgemm_case(7103, "N", "N", 9, 9, 9, c_nan=True)
+    A, B = dev4(c["A"]), dev4(c["B"])
+    for (m, n, k, al, be, ldb, want) in ((0, 9, 9, c["alpha"], c["beta"], c["ldb"], 0),
+                                         (9, 9, 9, zero, one, c["ldb"], 0),
+                                         (9, 9, 0, c["alpha"], one, c["ldb"], 0),
+                                         (9, 9, 9, c["alpha"], c["beta"], 8, 10)):
+        C = dev4(c["C"])
+        assert b.mpdd_Qgemm(h, "N", "N", m, n, k, al, A, c["lda"], B, ldb, be, C,
+                            c["ldc"]) == want
+        for g, c0 in zip(host4(C), c["C"]):
+            assert np.array_equal(bits(g), bits(c0))
+
+
+def test_qgemm_1024_sampled(h):
+    """1024^3 (1024 workgroups) checked on 32 x 32 sampled entries: the oracle
+    runs on the gathered rows of op(A) and columns of op(B)."""
+    n = k = 1024
+    for ta, tb in (("N", "N"), ("T", "T")):
+        c = W.qgemm_case(W.BASE_SEED + 8, ta, tb, n, n, k)
+        info, G = qgemm_gpu(h, c)
+        assert info == 0
+        rng = np.random.default_rng(9)
+        I = np.sort(rng.choice(n, 32, replace=False))
+        J = np.sort(rng.choice(n, 32, replace=False))
+        sub = csub(c, I, J)
+        O = qgemm_oracle(sub)
+        Gs = tuple(p[(I[:, None] + J[None, :] * c["ldc"]).ravel(order="F")] for p in G)
+        r = qratio(Gs, O, np.arange(32 * 32), k)
+        log(f"PARITY qgemm 1024^3 {ta}{tb} sampled 32x32: ratio {r:.4g}")
+        assert r <= RATIO_MAX
