@@ -378,17 +378,22 @@ int mpdd_Cgemm(mpdd_handle h, const char* transa, const char* transb, mpdd_int m
   return hip_status(ef);
 }
 
-// Rpotrf, blocked (LAPACK DPOTRF's left-looking order).  For each diagonal
-// block j of order jb ('L'; 'U' is the transpose): the block column
-// A(j:n, j:j+jb) is copied to P and updated there with the j factored
-// columns by one Rgemm (the diagonal block rides along, both of its triangles
-// computed in P, so A's opposite triangle is never written); the block kernel
-// factors P's diagonal block into A and inverts the factor (W); the rest of P
-// is multiplied by W^T into A.  The first failing pivot is recorded in a
-// device word that later block kernels respect (they return at once); the
-// host reads it every POTRF_CHECK blocks and at the end, and stops launching
-// once it is set.  After a failure, the columns before the failing block hold
-// the factor and A(k,k) the pivot; later columns are unspecified.
+// Rpotrf, blocked (LAPACK DPOTRF's left-looking order, with look-ahead).
+// Block b (columns j = b*nb .. j+jb; 'L' shown, 'U' is the transpose) needs
+// its block column A(j:n, j:j+jb), copied to a scratch P_b, minus the
+// contributions of every factored block column c < b.  Those are applied in
+// two products: all c < b-1 at once (the bulk, on a second stream, started as
+// soon as block b-2 is finished, so it overlaps the critical work of block
+// b-1), then c = b-1 alone (k = nb, on the caller's stream).  Then the block
+// kernel factors P_b's diagonal block into A and inverts the factor (W), and
+// the rest of P_b is multiplied by W^T into A.  P is double buffered; events
+// order the two streams.  The diagonal block rides along in every product
+// (both of its triangles computed in P), so A's opposite triangle is never
+// written.  The first failing pivot is recorded in a device word that later
+// block kernels respect (they return at once); the host reads it every
+// POTRF_CHECK blocks and at the end, and stops launching once it is set.
+// After a failure, the columns before the failing block hold the factor and
+// A(k,k) the pivot; later columns are unspecified.
 int mpdd_Rpotrf_nb(mpdd_handle h, const char* uplo, mpdd_int n, double* A_hi, double* A_lo,
                    mpdd_int lda, mpdd_int nb, mpdd_int* info, void* stream) {
   if (!info) return MPDD_ERR_ARG;
@@ -403,64 +408,126 @@ int mpdd_Rpotrf_nb(mpdd_handle h, const char* uplo, mpdd_int n, double* A_hi, do
   if (n == 0) return 0;
   if (!A_hi || !A_lo) return MPDD_ERR_ARG;
   hipStream_t st = (hipStream_t)stream;
+  hipStream_t sb = nullptr;                       // bulk-update stream
+  hipEvent_t ev_bulk[2] = {nullptr, nullptr}, ev_done[2] = {nullptr, nullptr};
+  hipEvent_t ev_start = nullptr, ev_end = nullptr;
+  bool ok = hipStreamCreateWithFlags(&sb, hipStreamNonBlocking) == hipSuccess;
+  for (int t = 0; t < 2 && ok; ++t)
+    ok = hipEventCreateWithFlags(&ev_bulk[t], hipEventDisableTiming) == hipSuccess &&
+         hipEventCreateWithFlags(&ev_done[t], hipEventDisableTiming) == hipSuccess;
+  ok = ok && hipEventCreateWithFlags(&ev_start, hipEventDisableTiming) == hipSuccess &&
+       hipEventCreateWithFlags(&ev_end, hipEventDisableTiming) == hipSuccess;
+  auto release = [&]() {
+    for (int t = 0; t < 2; ++t) {
+      if (ev_bulk[t]) (void)hipEventDestroy(ev_bulk[t]);
+      if (ev_done[t]) (void)hipEventDestroy(ev_done[t]);
+    }
+    if (ev_start) (void)hipEventDestroy(ev_start);
+    if (ev_end) (void)hipEventDestroy(ev_end);
+    if (sb) (void)hipStreamDestroy(sb);
+  };
+  if (!ok) {
+    release();
+    return MPDD_ERR_HIP;
+  }
   const size_t wb = (size_t)nb * nb * sizeof(double);
   const size_t pb = (size_t)n * nb * sizeof(double);
   void* ws = nullptr;
-  if (hipMallocAsync(&ws, 2 * wb + 2 * pb + 256, st) != hipSuccess) return MPDD_ERR_ALLOC;
+  if (hipMallocAsync(&ws, 2 * wb + 4 * pb + 256, st) != hipSuccess) {
+    release();
+    return MPDD_ERR_ALLOC;
+  }
   double* w_hi = (double*)ws;
   double* w_lo = (double*)((char*)ws + wb);
-  double* p_hi = (double*)((char*)ws + 2 * wb);
-  double* p_lo = (double*)((char*)ws + 2 * wb + pb);
-  long long* d_info = (long long*)((char*)ws + 2 * wb + 2 * pb);
-  if (hipMemsetAsync(d_info, 0, sizeof(long long), st) != hipSuccess) {
-    (void)hipFreeAsync(ws, st);
-    return MPDD_ERR_HIP;
-  }
+  double* p_hi[2] = {(double*)((char*)ws + 2 * wb), (double*)((char*)ws + 2 * wb + 2 * pb)};
+  double* p_lo[2] = {(double*)((char*)ws + 2 * wb + pb), (double*)((char*)ws + 2 * wb + 3 * pb)};
+  long long* d_info = (long long*)((char*)ws + 2 * wb + 4 * pb);
+  int rc = 0;
+  if (hipMemsetAsync(d_info, 0, sizeof(long long), st) != hipSuccess ||
+      hipEventRecord(ev_start, st) != hipSuccess || hipStreamWaitEvent(sb, ev_start, 0) != hipSuccess)
+    rc = MPDD_ERR_HIP;
   constexpr int64_t POTRF_CHECK = 16;   // blocks between host reads of the failure word
   long long hinfo = 0;
   const mpdd_dd one{1.0, 0.0}, mone{-1.0, 0.0}, zero{0.0, 0.0};
   // the panel solve is a skinny product with k = jb: 32 x 32 tiles give the
   // CUs more workgroups
   mpdd_opts small{MPDD_PLAIN, 0, 2, 1};
-  int rc = 0;
   auto at = [&](double* base, int64_t i, int64_t j) { return base + i + j * lda; };
-  auto copy = [&](double* dst, int64_t dpitch, const double* src, int64_t width,
-                  int64_t height) {
-    return hipMemcpy2DAsync(dst, dpitch * sizeof(double), src, lda * sizeof(double),
-                            width * sizeof(double), height, hipMemcpyDeviceToDevice, st);
-  };
-  for (int64_t j = 0; j < n && !rc; j += nb) {
-    const int64_t jb = std::min<int64_t>(nb, n - j);
-    const int64_t rows = n - j;          // block column length, diagonal block included
-    // 1. P = block column (lower: rows x jb, ld rows; upper: jb x rows, ld jb)
+  const int64_t nblk = (n + nb - 1) / nb;
+  // copy block column b into P[b & 1] on stream s
+  auto load_block = [&](int64_t b, hipStream_t s) -> int {
+    const int64_t j = b * nb, jb = std::min<int64_t>(nb, n - j), rows = n - j;
     const int64_t ldp = upper ? jb : rows;
-    if ((upper ? (copy(p_hi, ldp, at(A_hi, j, j), jb, rows) != hipSuccess ||
-                  copy(p_lo, ldp, at(A_lo, j, j), jb, rows) != hipSuccess)
-               : (copy(p_hi, ldp, at(A_hi, j, j), rows, jb) != hipSuccess ||
-                  copy(p_lo, ldp, at(A_lo, j, j), rows, jb) != hipSuccess))) {
+    const int64_t w = upper ? jb : rows, hgt = upper ? rows : jb;
+    for (int t = 0; t < 2; ++t) {
+      double* dst = t ? p_lo[b & 1] : p_hi[b & 1];
+      const double* src = t ? at(A_lo, j, j) : at(A_hi, j, j);
+      if (hipMemcpy2DAsync(dst, ldp * sizeof(double), src, lda * sizeof(double),
+                           w * sizeof(double), hgt, hipMemcpyDeviceToDevice, s) != hipSuccess)
+        return MPDD_ERR_HIP;
+    }
+    return 0;
+  };
+  // P[b & 1] -= contributions of block columns [c0, c1) (c1 > c0) on stream s
+  auto update_block = [&](int64_t b, int64_t c0, int64_t c1, hipStream_t s) -> int {
+    const int64_t j = b * nb, jb = std::min<int64_t>(nb, n - j), rows = n - j;
+    const int64_t k0 = c0 * nb, kk = c1 * nb - k0;
+    double* ph = p_hi[b & 1];
+    double* pl = p_lo[b & 1];
+    if (!upper)
+      return run_plain(h, nullptr, false, true, 0, rows, jb, kk, mone, at(A_hi, j, k0),
+                       at(A_lo, j, k0), lda, at(A_hi, j, k0), at(A_lo, j, k0), lda, one, ph, pl,
+                       rows, s);
+    return run_plain(h, nullptr, true, false, 0, jb, rows, kk, mone, at(A_hi, k0, j),
+                     at(A_lo, k0, j), lda, at(A_hi, k0, j), at(A_lo, k0, j), lda, one, ph, pl, jb,
+                     s);
+  };
+  // bulk stream, block t: load P_t and apply block columns [0, t-1)
+  auto bulk = [&](int64_t t) -> int {
+    if (t >= 2 && hipStreamWaitEvent(sb, ev_done[t & 1], 0) != hipSuccess) return MPDD_ERR_HIP;
+    int r = load_block(t, sb);
+    if (!r && t >= 2) r = update_block(t, 0, t - 1, sb);
+    if (!r && hipEventRecord(ev_bulk[t & 1], sb) != hipSuccess) r = MPDD_ERR_HIP;
+    return r;
+  };
+  if (!rc) rc = bulk(0);
+  if (!rc && nblk > 1) rc = bulk(1);
+  for (int64_t b = 0; b < nblk && !rc; ++b) {
+    const int64_t j = b * nb, jb = std::min<int64_t>(nb, n - j), rows = n - j;
+    const int64_t ldp = upper ? jb : rows;
+    // critical path of block b on the caller's stream
+    if (hipStreamWaitEvent(st, ev_bulk[b & 1], 0) != hipSuccess) {
       rc = MPDD_ERR_HIP;
       break;
     }
-    // 2. update with the factored part
-    if (j > 0) {
+    if (b >= 1 && (rc = update_block(b, b - 1, b, st)) != 0) break;
+    if (launch_potf2_block(p_hi[b & 1], p_lo[b & 1], ldp, at(A_hi, j, j), at(A_lo, j, j), lda,
+                           (int)jb, upper ? 1 : 0, w_hi, w_lo, d_info, (long long)j,
+                           st) != hipSuccess) {
+      rc = MPDD_ERR_HIP;
+      break;
+    }
+    if (rows > jb) {
+      // panel solve: lower A(j+jb:n, j:j+jb) = P(jb:, :) W^T; upper
+      // A(j:j+jb, j+jb:n) = W P(:, jb:)   (W = U^-T in the lower view)
       if (!upper)
-        rc = run_plain(h, nullptr, false, true, 0, rows, jb, j, mone, at(A_hi, j, 0),
-                       at(A_lo, j, 0), lda, at(A_hi, j, 0), at(A_lo, j, 0), lda, one, p_hi, p_lo,
-                       ldp, st);
+        rc = run_plain(h, &small, false, true, 0, rows - jb, jb, jb, one, p_hi[b & 1] + jb,
+                       p_lo[b & 1] + jb, ldp, w_hi, w_lo, jb, zero, at(A_hi, j + jb, j),
+                       at(A_lo, j + jb, j), lda, st);
       else
-        rc = run_plain(h, nullptr, true, false, 0, jb, rows, j, mone, at(A_hi, 0, j),
-                       at(A_lo, 0, j), lda, at(A_hi, 0, j), at(A_lo, 0, j), lda, one, p_hi, p_lo,
-                       ldp, st);
+        rc = run_plain(h, &small, false, false, 0, jb, rows - jb, jb, one, w_hi, w_lo, jb,
+                       p_hi[b & 1] + jb * jb, p_lo[b & 1] + jb * jb, ldp, zero,
+                       at(A_hi, j, j + jb), at(A_lo, j, j + jb), lda, st);
       if (rc) break;
     }
-    // 3. factor and invert the diagonal block (records a failing pivot)
-    if (launch_potf2_block(p_hi, p_lo, ldp, at(A_hi, j, j), at(A_lo, j, j), lda, (int)jb,
-                           upper ? 1 : 0, w_hi, w_lo, d_info, (long long)j, st) != hipSuccess) {
+    // block b finished: block b+2's bulk update may start (it reuses P[b & 1])
+    if (hipEventRecord(ev_done[b & 1], st) != hipSuccess) {
       rc = MPDD_ERR_HIP;
       break;
     }
-    // 4. every POTRF_CHECK blocks: stop once a pivot has failed
-    if ((j / nb) % POTRF_CHECK == POTRF_CHECK - 1) {
+    if (b + 2 < nblk && (rc = bulk(b + 2)) != 0) break;
+    // every POTRF_CHECK blocks: stop once a pivot has failed
+    if (b % POTRF_CHECK == POTRF_CHECK - 1) {
       if (hipMemcpyAsync(&hinfo, d_info, sizeof(long long), hipMemcpyDeviceToHost, st) !=
               hipSuccess ||
           hipStreamSynchronize(st) != hipSuccess) {
@@ -469,24 +536,20 @@ int mpdd_Rpotrf_nb(mpdd_handle h, const char* uplo, mpdd_int n, double* A_hi, do
       }
       if (hinfo) break;
     }
-    if (rows == jb) break;
-    // 5. panel solve: lower A(j+jb:n, j:j+jb) = P(jb:, :) W^T; upper
-    // A(j:j+jb, j+jb:n) = W P(:, jb:)   (W = U^-T in the lower view)
-    if (!upper)
-      rc = run_plain(h, &small, false, true, 0, rows - jb, jb, jb, one, p_hi + jb, p_lo + jb, ldp,
-                     w_hi, w_lo, jb, zero, at(A_hi, j + jb, j), at(A_lo, j + jb, j), lda, st);
-    else
-      rc = run_plain(h, &small, false, false, 0, jb, rows - jb, jb, one, w_hi, w_lo, jb,
-                     p_hi + jb * jb, p_lo + jb * jb, ldp, zero, at(A_hi, j, j + jb),
-                     at(A_lo, j, j + jb), lda, st);
   }
+  // the caller's stream waits for the bulk stream before the scratch is freed
+  const bool joined = hipEventRecord(ev_end, sb) == hipSuccess &&
+                      hipStreamWaitEvent(st, ev_end, 0) == hipSuccess;
+  if (!rc && !joined) rc = MPDD_ERR_HIP;
   if (!rc && !hinfo &&
       (hipMemcpyAsync(&hinfo, d_info, sizeof(long long), hipMemcpyDeviceToHost, st) !=
            hipSuccess ||
        hipStreamSynchronize(st) != hipSuccess))
     rc = MPDD_ERR_HIP;
+  if (!joined) (void)hipStreamSynchronize(sb);
   const hipError_t ef = hipFreeAsync(ws, st);
   const hipError_t es = hipStreamSynchronize(st);
+  release();
   if (rc) return rc;
   if (ef != hipSuccess || es != hipSuccess) return MPDD_ERR_HIP;
   *info = (mpdd_int)hinfo;
