@@ -1,15 +1,16 @@
 """Benchmark: dd Rgemm on one MI355X, plain and split forms, plus served latency.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 8192] [--no-cpu]
-                    [--sections plain,syrk,cgemm,potrf,qd,ozaki,host,serve]
+                    [--sections plain,sizes,syrk,cgemm,potrf,qd,ozaki,host,serve]
 
 One step = one dd Rgemm NN, m = n = k = n (8192), leading dimensions 8195,
 C <- alpha*A*B + beta*C on float64 hi/lo planes already resident in HBM.
 The headline value is dd-GFLOPS = 2*m*n*k / time (one dd multiply-add = two
 dd flops), over exactly K timed steps bracketed by device synchronisations.
-Prints ONE JSON line.  Extra sections report the split forms, Rsyrk and the
-served request stream with the same inputs recipe; the CPU oracle is timed on
-a bounded sample of the same product.
+Prints ONE JSON line.  Extra sections report the other Rgemm sizes, Rsyrk,
+Cgemm, the Cholesky Rpotrf, the quad-double Rgemm, the split forms, the
+host-pointer call and the served request stream, with the same input recipes;
+the CPU oracle is timed on a bounded sample of the headline product.
 """
 import argparse
 import hashlib
@@ -93,6 +94,37 @@ def bench_plain(h, args, stream):
 
     total, per = timed_calls(step, args.steps, args.warmup, stream)
     return case, total, per
+
+
+def bench_sizes(h, args, stream):
+    """The other products of the Rgemm size sweep (square NN and TN at
+    1024 .. 4096, the 4096 x 4096 x 256 and 8192 x 64 x 8192 shapes), default
+    tile and k-split choice, padded leading dimensions."""
+    import torch
+    import workloads as W
+    from paper_2109_13406_amd import binding as b
+    out = []
+    for (ta, tb, m, n, k) in (("N", "N", 1024, 1024, 1024), ("N", "N", 2048, 2048, 2048),
+                              ("N", "N", 4096, 4096, 4096), ("T", "N", 4096, 4096, 4096),
+                              ("N", "T", 4096, 4096, 4096), ("T", "T", 4096, 4096, 4096),
+                              ("N", "N", 4096, 4096, 256), ("N", "N", 8192, 64, 8192)):
+        case = W.gemm_case_device(W.BASE_SEED + 1, ta, tb, m, n, k)
+        torch.cuda.synchronize()
+
+        def step():
+            info = b.mpdd_Rgemm(h, ta, tb, m, n, k, case["alpha"], case["A"], case["lda"],
+                                case["B"], case["ldb"], case["beta"], case["C"], case["ldc"],
+                                stream=stream)
+            if info != 0:
+                raise RuntimeError(f"mpdd_Rgemm info={info}")
+        _, per = timed_calls(step, 3, 1, stream)
+        t = sum(per) / len(per)
+        out.append({"op": ta + tb, "m": m, "n": n, "k": k, "ms": round(t * 1e3, 3),
+                    "dd_gflops": round(2.0 * m * n * k / t / 1e9, 1)})
+        log(f"size {out[-1]}")
+        del case
+        torch.cuda.empty_cache()
+    return out
 
 
 def cpu_baseline(case, n, cols=64):
@@ -380,7 +412,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=8192)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--sections", default="plain,syrk,cgemm,potrf,qd,ozaki,host,serve")
+    ap.add_argument("--sections", default="plain,sizes,syrk,cgemm,potrf,qd,ozaki,host,serve")
     ap.add_argument("--tile", type=int, default=-1,
                     help="tile-table entry for the plain product (-1: the library's choice)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
@@ -443,6 +475,8 @@ def main():
     if "syrk" in sections:
         out["rsyrk"] = bench_syrk(h, args, stream)
         log(f"rsyrk: {out['rsyrk']}")
+    if "sizes" in sections:
+        out["rgemm_sizes"] = bench_sizes(h, args, stream)
     if "qd" in sections:
         out["qgemm"] = bench_qd(h, args, stream)
         log(f"qgemm: {out['qgemm']}")

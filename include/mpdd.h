@@ -275,7 +275,9 @@ int mpdd_ozaki_split(mpdd_handle h, int algo, const char *trans, mpdd_int rows, 
  * tile (the server uses the handle's tuned tile, restricted to tile-table
  * entries 2 and 4: 32 x 32 and 64 x 64 x 16).  Operands stay where the
  * caller put them (device memory) and must stay valid until the request
- * completes.
+ * completes.  A group of one request is launched as a plain tile kernel.
+ * The scheduler thread polls (yielding its core) while work is in flight and
+ * for 50 ms after its last activity, then sleeps until the next submission.
  *
  * Intended callers: any host thread; submit and wait may run concurrently. */
 

@@ -13,9 +13,13 @@
 //   3. whenever a slot is free and requests are admitted, launches them all
 //      as one group: their C tiles become a work list (longest k first), the
 //      list is copied to the slot's device buffer and a captured hipGraph of
-//      persistent grouped kernels (one per tile shape) walks it.  Groups on
-//      different slots overlap on the device, so requests that arrive while
-//      others run start as soon as a slot and budget free up.
+//      persistent grouped kernels (one per tile shape) walks it; a group of
+//      one request launches its tile kernel directly.  Groups on different
+//      slots overlap on the device, so requests that arrive while others run
+//      start as soon as a slot and budget free up.
+// The thread polls without sleeping while groups are in flight and for
+// kIdleSpin seconds after its last activity (so steady traffic never waits
+// for a thread wake-up); after that it sleeps until the next submission.
 // The tile shape of each request is the handle's tuned choice (restricted to
 // the shapes the grouped graph holds), so a request's result is bit-identical
 // to a standalone call with that tile.
@@ -62,6 +66,10 @@ constexpr int kNumServeTiles = 2;
 constexpr int kSlots = 4;
 constexpr int kMaxGroupReqs = 1024;
 constexpr int kMaxGroupItems = 1 << 18;
+// the scheduler polls (yielding) for this long after its last activity before
+// it sleeps on the condition variable: under steady traffic a request never
+// waits for a thread wake-up
+constexpr double kIdleSpin = 0.05;
 
 struct Req {
   mpdd_request r;
@@ -214,6 +222,36 @@ void finish(mpdd_server_s* s, Req* q, int info, double t_end) {
 
 // Build the request descriptors and work list of a group into the slot's
 // pinned buffer.  Returns false if it does not fit.
+// The update of one request as the tile kernels take it (k = 0 and alpha = 0
+// when it is C <- beta C only), with its op flags and output shape.
+void make_params(const mpdd_request& r, GemmParams& p, bool& ta, bool& tb, int64_t& m,
+                 int64_t& n) {
+  const bool syrk = r.op == MPDD_OP_SYRK;
+  int64_t k;
+  shape_of(r, m, n, k);
+  const bool scale_only = dd_zero(r.alpha) || k == 0;
+  p.m = m; p.n = n; p.k = scale_only ? 0 : k;
+  p.kchunk = p.k;
+  p.alpha_hi = scale_only ? 0.0 : r.alpha.hi;
+  p.alpha_lo = scale_only ? 0.0 : r.alpha.lo;
+  p.beta_hi = r.beta.hi; p.beta_lo = r.beta.lo;
+  p.beta_zero = dd_zero(r.beta) ? 1 : 0;
+  p.c_hi = r.C_hi; p.c_lo = r.C_lo; p.ldc = r.ldc;
+  if (syrk) {
+    ta = !lsame(r.flag2, 'N');
+    tb = !ta;
+    p.a_hi = r.A_hi; p.a_lo = r.A_lo; p.lda = r.lda;
+    p.b_hi = r.A_hi; p.b_lo = r.A_lo; p.ldb = r.lda;
+    p.tri = lsame(r.flag1, 'U') ? 1 : 2;
+  } else {
+    ta = !lsame(r.flag1, 'N');
+    tb = !lsame(r.flag2, 'N');
+    p.a_hi = r.A_hi; p.a_lo = r.A_lo; p.lda = r.lda;
+    p.b_hi = r.B_hi; p.b_lo = r.B_lo; p.ldb = r.ldb;
+    p.tri = 0;
+  }
+}
+
 bool build_group(Slot& sl, const std::vector<Req*>& g, size_t& used, int counts[kNumServeTiles]) {
   char* base = (char*)sl.host_buf;
   GroupHeader* hdr = (GroupHeader*)base;
@@ -224,31 +262,9 @@ bool build_group(Slot& sl, const std::vector<Req*>& g, size_t& used, int counts[
     const mpdd_request& r = g[qi]->r;
     ServeReq d{};
     GemmParams& p = d.p;
-    const bool syrk = r.op == MPDD_OP_SYRK;
-    int64_t m, n, k;
-    shape_of(r, m, n, k);
-    const bool scale_only = dd_zero(r.alpha) || k == 0;
-    p.m = m; p.n = n; p.k = scale_only ? 0 : k;
-    p.kchunk = p.k;
-    p.alpha_hi = scale_only ? 0.0 : r.alpha.hi;
-    p.alpha_lo = scale_only ? 0.0 : r.alpha.lo;
-    p.beta_hi = r.beta.hi; p.beta_lo = r.beta.lo;
-    p.beta_zero = dd_zero(r.beta) ? 1 : 0;
-    p.c_hi = r.C_hi; p.c_lo = r.C_lo; p.ldc = r.ldc;
+    int64_t m, n;
     bool ta, tb;
-    if (syrk) {
-      ta = !lsame(r.flag2, 'N');
-      tb = !ta;
-      p.a_hi = r.A_hi; p.a_lo = r.A_lo; p.lda = r.lda;
-      p.b_hi = r.A_hi; p.b_lo = r.A_lo; p.ldb = r.lda;
-      p.tri = lsame(r.flag1, 'U') ? 1 : 2;
-    } else {
-      ta = !lsame(r.flag1, 'N');
-      tb = !lsame(r.flag2, 'N');
-      p.a_hi = r.A_hi; p.a_lo = r.A_lo; p.lda = r.lda;
-      p.b_hi = r.B_hi; p.b_lo = r.B_lo; p.ldb = r.ldb;
-      p.tri = 0;
-    }
+    make_params(r, p, ta, tb, m, n);
     d.flags = (ta ? 1 : 0) | (tb ? 2 : 0);
     reqs[qi] = d;
     const TileInfo* t = tile_info(kServeTiles[g[qi]->tile]);
@@ -351,6 +367,22 @@ int launch_group(mpdd_server_s* s, Slot& sl, std::vector<Req*>& g) {
     sl.fake_done = t0 + s->fake_latency + flops / s->fake_rate;
     return 0;
   }
+  if (g.size() == 1) {
+    // a group of one: launch its tile kernel directly with the update passed
+    // by value (no descriptor copy); the same tile code as the grouped
+    // kernel, so the result is the same
+    GemmParams p{};
+    bool ta, tb;
+    int64_t m, n;
+    make_params(g[0]->r, p, ta, tb, m, n);
+    const int tile = kServeTiles[g[0]->tile];
+    const TileInfo* ti = tile_info(tile);
+    p.tiles_m = (int)((m + ti->bm - 1) / ti->bm);
+    p.tiles_n = (int)((n + ti->bn - 1) / ti->bn);
+    if (launch_gemm(tile, p, ta, tb, false, 1, sl.stream) != hipSuccess) return MPDD_ERR_HIP;
+    if (hipEventRecord(sl.done_ev, sl.stream) != hipSuccess) return MPDD_ERR_HIP;
+    return 0;
+  }
   size_t used = 0;
   int counts[kNumServeTiles];
   if (!build_group(sl, g, used, counts)) return MPDD_ERR_UNSUPPORTED;
@@ -370,6 +402,7 @@ void release(mpdd_server_s* s, Req* q) {
 void scheduler(mpdd_server_s* s) {
   if (!s->fake) (void)hipSetDevice(s->device);   // HIP's current device is per thread
   std::unique_lock<std::mutex> lk(s->mu);
+  double last_active = now_s();
   for (;;) {
     bool progressed = false;
     // 1. completions
@@ -466,15 +499,21 @@ void scheduler(mpdd_server_s* s) {
     bool busy = false;
     for (Slot& sl : s->slots) busy = busy || sl.busy;
     if (s->stop && !busy && s->pending.empty() && s->admitted.empty()) break;
-    if (progressed) continue;
-    if (busy) {
-      // groups in flight: poll their events without sleeping (a timed wait
-      // would add the timer's slack, tens of microseconds, to every request)
+    if (progressed) {
+      last_active = now_s();
+      continue;
+    }
+    if (busy) last_active = now_s();
+    if (busy || now_s() - last_active < kIdleSpin) {
+      // groups in flight, or recent traffic: poll without sleeping (a timed
+      // wait, or a wake-up from the condition variable, would add tens of
+      // microseconds to every request)
       lk.unlock();
       std::this_thread::yield();
       lk.lock();
     } else {
       s->cv_sched.wait(lk);
+      last_active = now_s();
     }
   }
 }

@@ -23,6 +23,9 @@ hipError_t launch_grouped_list(int, const char*, const ServeReq*, const int*, co
                                hipStream_t) {
   return hipErrorInvalidValue;
 }
+hipError_t launch_gemm(int, const GemmParams&, bool, bool, bool, int, hipStream_t) {
+  return hipErrorInvalidValue;
+}
 }  // namespace mpdd
 bool handle_valid(const mpdd_handle_s*) { return false; }
 int handle_device(const mpdd_handle_s*) { return 0; }
