@@ -172,60 +172,31 @@ def bench_syrk(h, args, stream):
 
 
 def bench_cgemm(h, args, stream):
-    """Complex dd Cgemm NN at n/2 (a quarter of the real product's memory per
-    plane, the same number of real dd multiply-adds as the real n/2 product x 4).
-    Complex flops: 8 mnk (LAWN 41: 6 real multiplies + 2 adds per complex
-    multiply-add)."""
+    """Complex dd Cgemm NN at n/2, four-product (default) and three-product
+    forms.  Complex flops: 8 mnk (LAWN 41: 6 real multiplies + 2 adds per
+    complex multiply-add), for both forms."""
     import torch
     import workloads as W
     from paper_2109_13406_amd import binding as b
     n = max(1, args.n // 2)
     case = W.cgemm_case_device(W.BASE_SEED + 5, "N", "N", n, n, n)
     torch.cuda.synchronize()
+    out = {"workload": f"Cgemm NN m=n=k={n} ld={W.ld_padded(n)} (four real dd planes each)"}
+    for form, opts in (("4m", None), ("3m", dict(algo=b.MPDD_COMPLEX_3M))):
+        def step():
+            info = b.mpdd_Cgemm_ex(h, opts, "N", "N", n, n, n, case["alpha"], case["A"],
+                                   case["lda"], case["B"], case["ldb"], case["beta"], case["C"],
+                                   case["ldc"], stream=stream)
+            if info != 0:
+                raise RuntimeError(f"mpdd_Cgemm_ex info={info}")
 
-    def step():
-        info = b.mpdd_Cgemm(h, "N", "N", n, n, n, case["alpha"], case["A"], case["lda"],
-                            case["B"], case["ldb"], case["beta"], case["C"], case["ldc"],
-                            stream=stream)
-        if info != 0:
-            raise RuntimeError(f"mpdd_Cgemm info={info}")
-
-    total, per = timed_calls(step, max(1, args.steps // 2), 1, stream)
-    t = sum(per) / len(per)
+        total, per = timed_calls(step, max(1, args.steps // 2), 1, stream)
+        t = sum(per) / len(per)
+        out[f"ms_{form}"] = round(t * 1e3, 3)
+        out[f"complex_dd_gflops_{form}"] = round(8.0 * n ** 3 / t / 1e9, 1)
     del case
     torch.cuda.empty_cache()
-    return {"workload": f"Cgemm NN m=n=k={n} ld={W.ld_padded(n)} (four real dd planes each)",
-            "ms": round(t * 1e3, 3), "complex_dd_gflops": round(8.0 * n ** 3 / t / 1e9, 1)}
-
-
-def bench_potrf(h, args, stream):
-    """Blocked dd Cholesky Rpotrf L at n (synchronous call: it reads each
-    diagonal block's info back).  dd-flops n^3/3 (LAWN 41, leading term)."""
-    import torch
-    import workloads as W
-    from paper_2109_13406_amd import binding as b
-    n = args.n
-    case = W.spd_case_device(W.BASE_SEED + 7, n, "L")
-    A0 = tuple(x.clone() for x in case["A"])
-    torch.cuda.synchronize()
-    times = []
-    for rep in range(1 + max(1, args.steps // 2)):
-        for dst, src in zip(case["A"], A0):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        rc, info = b.mpdd_Rpotrf(h, "L", n, case["A"], case["lda"], stream=stream)
-        torch.cuda.synchronize()
-        if rc != 0 or info != 0:
-            raise RuntimeError(f"mpdd_Rpotrf rc={rc} info={info}")
-        if rep > 0:                      # the first call is warm-up
-            times.append(time.perf_counter() - t0)
-    t = sum(times) / len(times)
-    del case, A0
-    torch.cuda.empty_cache()
-    return {"workload": f"Rpotrf L n={n} ld={W.ld_padded(n)} (SPD: dd U[-1,1) off-diagonal, "
-                        f"n + U[0,1) diagonal)", "ms": round(t * 1e3, 3),
-            "dd_gflops": round(float(n) ** 3 / 3.0 / t / 1e9, 1)}
+    return out
 
 
 def bench_qd(h, args, stream):

@@ -123,6 +123,7 @@ int mpdd_Rsyrk_host(mpdd_handle h, const char *uplo, const char *trans, mpdd_int
                                  terms, on the FP64 matrix cores) */
 #define MPDD_OZAKI_I8 1       /* split form, INT8 slices on the INT8 matrix cores */
 #define MPDD_OZAKI_F64 2      /* split form, FP64 slices on the FP64 matrix cores */
+#define MPDD_COMPLEX_3M 4     /* Cgemm only: three real products (see mpdd_Cgemm_ex) */
 #define MPDD_PLAIN_ACCURATE 3 /* accurate dd add + mul per term (same steps as the
                                  reference evaluation; 29 binary64 ops) */
 
@@ -175,6 +176,21 @@ int mpdd_Cgemm(mpdd_handle h, const char *transa, const char *transb, mpdd_int m
                const double *B_re_hi, const double *B_re_lo, const double *B_im_hi,
                const double *B_im_lo, mpdd_int ldb, mpdd_ddc beta, double *C_re_hi,
                double *C_re_lo, double *C_im_hi, double *C_im_lo, mpdd_int ldc, void *stream);
+
+/* As mpdd_Cgemm with options (NULL = defaults): opts->algo MPDD_PLAIN (the
+ * four real products above) or MPDD_COMPLEX_3M (three real products:
+ * R1 = Ar Br, R2 = Ai Bi, R3 = (Ar + Ai)(Br + Bi) with the conjugation signs,
+ * Re P = R1 - R2, Im P = R3 - R1 - R2; a quarter less arithmetic, with the
+ * error of Im P relative to |Ar + Ai| |Br + Bi|; extra scratch
+ * 16 (m k + k n) bytes); tile_id / splitk choose the real products' tiling as
+ * in mpdd_Rgemm_ex.  MPDD_ERR_ARG for another algo. */
+int mpdd_Cgemm_ex(mpdd_handle h, const mpdd_opts *opts, const char *transa, const char *transb,
+                  mpdd_int m, mpdd_int n, mpdd_int k, mpdd_ddc alpha, const double *A_re_hi,
+                  const double *A_re_lo, const double *A_im_hi, const double *A_im_lo,
+                  mpdd_int lda, const double *B_re_hi, const double *B_re_lo,
+                  const double *B_im_hi, const double *B_im_lo, mpdd_int ldb, mpdd_ddc beta,
+                  double *C_re_hi, double *C_re_lo, double *C_im_hi, double *C_im_lo,
+                  mpdd_int ldc, void *stream);
 
 /* ---- quad-double: Qgemm --------------------------------------------------------------
  *

@@ -18,6 +18,7 @@ MPDD_PLAIN = 0
 MPDD_OZAKI_I8 = 1
 MPDD_OZAKI_F64 = 2
 MPDD_PLAIN_ACCURATE = 3
+MPDD_COMPLEX_3M = 4
 
 MPDD_ERR_HIP = -1
 MPDD_ERR_ALLOC = -2
@@ -95,6 +96,9 @@ SIGNATURES = {
                                      _P, _I, mpdd_dd, _P, _P, _I, _P]),
     "mpdd_Cgemm": (ctypes.c_int, [_P, _C, _C, _I, _I, _I, mpdd_ddc, _P, _P, _P, _P, _I, _P, _P, _P,
                                   _P, _I, mpdd_ddc, _P, _P, _P, _P, _I, _P]),
+    "mpdd_Cgemm_ex": (ctypes.c_int, [_P, ctypes.POINTER(mpdd_opts), _C, _C, _I, _I, _I, mpdd_ddc,
+                                     _P, _P, _P, _P, _I, _P, _P, _P, _P, _I, mpdd_ddc, _P, _P, _P,
+                                     _P, _I, _P]),
     "mpdd_Qgemm": (ctypes.c_int, [_P, _C, _C, _I, _I, _I, mpdd_qd, _P, _P, _P, _P, _I, _P, _P, _P,
                                   _P, _I, mpdd_qd, _P, _P, _P, _P, _I, _P]),
     "mpdd_Rpotrf": (ctypes.c_int, [_P, _C, _I, _P, _P, _I, ctypes.POINTER(_I), _P]),
@@ -228,6 +232,15 @@ def mpdd_Cgemm(h, transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, 
     return load().mpdd_Cgemm(h, _flag(transa), _flag(transb), m, n, k, _ddc(alpha),
                              *map(_ptr, A), lda, *map(_ptr, B), ldb, _ddc(beta), *map(_ptr, C),
                              ldc, _stream(stream))
+
+
+def mpdd_Cgemm_ex(h, opts, transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc,
+                  stream=None):
+    o = opts if opts is None or isinstance(opts, mpdd_opts) else _opts(**opts)
+    return load().mpdd_Cgemm_ex(h, ctypes.byref(o) if o is not None else None, _flag(transa),
+                                _flag(transb), m, n, k, _ddc(alpha), *map(_ptr, A), lda,
+                                *map(_ptr, B), ldb, _ddc(beta), *map(_ptr, C), ldc,
+                                _stream(stream))
 
 
 def _qd(x):

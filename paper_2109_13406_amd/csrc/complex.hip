@@ -3,9 +3,11 @@
 // Cgemm (MPLAPACK manual, section "How to use reference MPBLAS", the Cgemm
 // part: ZGEMM's calling convention on complex multiple-precision values)
 // runs its four real products op(A)_{re,im} op(B)_{re,im} on the plain dd
-// kernels into a product P = op(A) op(B) held as two dd planes pairs; this
+// kernels into a product P = op(A) op(B) held as two dd planes pairs (or, for
+// the three-product form, into R1, R2, R3 from which P is formed here); this
 // kernel then forms C <- alpha P + beta C in complex dd arithmetic, or
-// C <- beta C (alpha = 0 or k = 0).  A complex product is
+// C <- beta C (alpha = 0 or k = 0).  dd_axpy_planes forms the operand sums of
+// the three-product form.  A complex product is
 //   (a + ib)(c + id) = (ac - bd) + i(ad + bc),
 // each real product a dd multiply and each sum a dd add.
 //
@@ -37,7 +39,16 @@ __global__ void __launch_bounds__(256) dd_cgemm_epilogue(CEpilogue p) {
   ddv zr{0.0, 0.0}, zi{0.0, 0.0};
   if (p.use_p) {
     const int64_t pi = i + j * p.ldp;
-    cmul(ar, ai, ddv{p.p_rh[pi], p.p_rl[pi]}, ddv{p.p_ih[pi], p.p_il[pi]}, zr, zi);
+    ddv pr{p.p_rh[pi], p.p_rl[pi]}, pim{p.p_ih[pi], p.p_il[pi]};
+    if (p.three_m) {
+      // R1 = pr, R2 = pim, R3 = q: P = (R1 - R2) + i (R3 - R1 - R2)
+      const ddv r3{p.q_h[pi], p.q_l[pi]};
+      const ddv s12 = dd_add(pr, pim);
+      const ddv re = dd_add(pr, dd_neg(pim));
+      pim = dd_add(r3, dd_neg(s12));
+      pr = re;
+    }
+    cmul(ar, ai, pr, pim, zr, zi);
     if (!p.beta_zero) {
       ddv tr, ti;
       cmul(br, bi, ddv{p.c_rh[ci], p.c_rl[ci]}, ddv{p.c_ih[ci], p.c_il[ci]}, tr, ti);
@@ -53,7 +64,30 @@ __global__ void __launch_bounds__(256) dd_cgemm_epilogue(CEpilogue p) {
   p.c_il[ci] = zi.lo;
 }
 
+__global__ void __launch_bounds__(256)
+dd_axpy_planes(const double* __restrict__ xh, const double* __restrict__ xl,
+               const double* __restrict__ yh, const double* __restrict__ yl, int64_t ld, double s,
+               int64_t rows, int64_t cols, double* __restrict__ oh, double* __restrict__ ol) {
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= rows * cols) return;
+  const int64_t i = gid % rows, j = gid / rows;
+  const int64_t o = i + j * ld;
+  const ddv r = dd_add(ddv{xh[o], xl[o]}, ddv{s * yh[o], s * yl[o]});
+  oh[gid] = r.hi;
+  ol[gid] = r.lo;
+}
+
 }  // namespace
+
+hipError_t launch_dd_axpy_planes(const double* x_hi, const double* x_lo, const double* y_hi,
+                                 const double* y_lo, int64_t ld, double s, int64_t rows,
+                                 int64_t cols, double* o_hi, double* o_lo, hipStream_t st) {
+  const int64_t total = rows * cols;
+  if (total == 0) return hipSuccess;
+  hipLaunchKernelGGL(dd_axpy_planes, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st,
+                     x_hi, x_lo, y_hi, y_lo, ld, s, rows, cols, o_hi, o_lo);
+  return hipGetLastError();
+}
 
 hipError_t launch_cgemm_epilogue(const CEpilogue& p, hipStream_t st) {
   const int64_t total = p.m * p.n;

@@ -68,8 +68,16 @@ struct CEpilogue {
   double *c_rh, *c_rl, *c_ih, *c_il;
   int64_t ldc;
   int use_p, beta_zero;
+  // three_m: p_r = R1, p_i = R2, q = R3; P = (R1 - R2) + i (R3 - R1 - R2)
+  const double *q_h, *q_l;
+  int three_m;
 };
 hipError_t launch_cgemm_epilogue(const CEpilogue& p, hipStream_t st);
+// out = x + s y elementwise over a rows x cols matrix (x, y: hi / lo planes
+// with leading dimension ld; out compact, ld = rows), in dd (s = +-1).
+hipError_t launch_dd_axpy_planes(const double* x_hi, const double* x_lo, const double* y_hi,
+                                 const double* y_lo, int64_t ld, double s, int64_t rows,
+                                 int64_t cols, double* o_hi, double* o_lo, hipStream_t st);
 
 // Quad-double Rgemm (qd.hip): four planes per matrix, alpha / beta as
 // {x0, x1, x2, x3}.  scale_only: C <- beta C (alpha = 0 or k = 0);

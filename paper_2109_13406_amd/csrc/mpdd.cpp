@@ -311,20 +311,30 @@ int mpdd_Rsyrk_ex(mpdd_handle h, const mpdd_opts* opts, const char* uplo, const 
 }
 
 // Cgemm.  With sA = -1 when op(A) conjugates (transa 'C'), else +1, and
-// op_r(A), op_i(A) the real transposition of the real and imaginary planes,
+// op_r(A), op_i(A) the real transposition of the real and imaginary planes:
+//  4M (default):
 //   Re P = op_r(Ar) op_r(Br) - sA sB op_r(Ai) op_r(Bi)
 //   Im P = sB op_r(Ar) op_r(Bi) + sA op_r(Ai) op_r(Br),
-// four plain dd products (the second of each pair accumulates onto the first
-// through beta = 1), then C <- alpha P + beta C in complex dd.
-int mpdd_Cgemm(mpdd_handle h, const char* transa, const char* transb, mpdd_int m, mpdd_int n,
-               mpdd_int k, mpdd_ddc alpha, const double* A_re_hi, const double* A_re_lo,
-               const double* A_im_hi, const double* A_im_lo, mpdd_int lda,
-               const double* B_re_hi, const double* B_re_lo, const double* B_im_hi,
-               const double* B_im_lo, mpdd_int ldb, mpdd_ddc beta, double* C_re_hi,
-               double* C_re_lo, double* C_im_hi, double* C_im_lo, mpdd_int ldc, void* stream) {
+//   four plain dd products (the second of each pair accumulates onto the first
+//   through beta = 1);
+//  3M (MPDD_COMPLEX_3M): with R1 = op_r(Ar) op_r(Br), R2 = sA sB op_r(Ai) op_r(Bi)
+//   and R3 = op_r(Ar + sA Ai) op_r(Br + sB Bi) (the sums formed in dd,
+//   elementwise, into scratch), Re P = R1 - R2 and Im P = R3 - R1 - R2: three
+//   products, a quarter less arithmetic, at the price of the cancellation in
+//   Im P (its error is relative to |Ar + Ai| |Br + Bi| rather than to |P|);
+// then C <- alpha P + beta C in complex dd.
+int mpdd_Cgemm_ex(mpdd_handle h, const mpdd_opts* opts, const char* transa, const char* transb,
+                  mpdd_int m, mpdd_int n, mpdd_int k, mpdd_ddc alpha, const double* A_re_hi,
+                  const double* A_re_lo, const double* A_im_hi, const double* A_im_lo,
+                  mpdd_int lda, const double* B_re_hi, const double* B_re_lo,
+                  const double* B_im_hi, const double* B_im_lo, mpdd_int ldb, mpdd_ddc beta,
+                  double* C_re_hi, double* C_re_lo, double* C_im_hi, double* C_im_lo,
+                  mpdd_int ldc, void* stream) {
   const int info = check_gemm(transa, transb, m, n, k, lda, ldb, ldc);
   if (info) return info;
   if (!handle_ok(h)) return MPDD_ERR_HANDLE;
+  const int algo = opts ? opts->algo : MPDD_PLAIN;
+  if (algo != MPDD_PLAIN && algo != MPDD_COMPLEX_3M) return MPDD_ERR_ARG;
   const bool alpha_zero = is_zero(alpha.re) && is_zero(alpha.im);
   const bool beta_zero = is_zero(beta.re) && is_zero(beta.im);
   const bool beta_one = is_one(beta.re) && is_zero(beta.im);
@@ -347,35 +357,90 @@ int mpdd_Cgemm(mpdd_handle h, const char* transa, const char* transb, mpdd_int m
   e.use_p = use_p ? 1 : 0;
   if (!use_p) return hip_status(launch_cgemm_epilogue(e, st));
 
+  // the real products use the caller's tile / k-split choice
+  mpdd_opts ro{MPDD_PLAIN, 0, opts ? opts->tile_id : -1, opts ? opts->splitk : 0};
   const bool ta = !lsame(transa, 'N'), tb = !lsame(transb, 'N');
   const double sa = lsame(transa, 'C') ? -1.0 : 1.0, sb = lsame(transb, 'C') ? -1.0 : 1.0;
   const size_t plane = (size_t)m * (size_t)n * sizeof(double);
-  void* w = nullptr;
-  if (hipMallocAsync(&w, 4 * plane, st) != hipSuccess) return MPDD_ERR_ALLOC;
-  double* prh = (double*)w;
-  double* prl = (double*)((char*)w + plane);
-  double* pih = (double*)((char*)w + 2 * plane);
-  double* pil = (double*)((char*)w + 3 * plane);
   const mpdd_dd zero{0.0, 0.0}, one{1.0, 0.0};
-  int rc = run_plain(h, nullptr, ta, tb, 0, m, n, k, one, A_re_hi, A_re_lo, lda, B_re_hi,
-                     B_re_lo, ldb, zero, prh, prl, m, st);
+  e.ldp = m;
+  if (algo == MPDD_PLAIN) {
+    void* w = nullptr;
+    if (hipMallocAsync(&w, 4 * plane, st) != hipSuccess) return MPDD_ERR_ALLOC;
+    double* prh = (double*)w;
+    double* prl = (double*)((char*)w + plane);
+    double* pih = (double*)((char*)w + 2 * plane);
+    double* pil = (double*)((char*)w + 3 * plane);
+    int rc = run_plain(h, &ro, ta, tb, 0, m, n, k, one, A_re_hi, A_re_lo, lda, B_re_hi,
+                       B_re_lo, ldb, zero, prh, prl, m, st);
+    if (!rc)
+      rc = run_plain(h, &ro, ta, tb, 0, m, n, k, mpdd_dd{-sa * sb, 0.0}, A_im_hi, A_im_lo, lda,
+                     B_im_hi, B_im_lo, ldb, one, prh, prl, m, st);
+    if (!rc)
+      rc = run_plain(h, &ro, ta, tb, 0, m, n, k, mpdd_dd{sb, 0.0}, A_re_hi, A_re_lo, lda,
+                     B_im_hi, B_im_lo, ldb, zero, pih, pil, m, st);
+    if (!rc)
+      rc = run_plain(h, &ro, ta, tb, 0, m, n, k, mpdd_dd{sa, 0.0}, A_im_hi, A_im_lo, lda,
+                     B_re_hi, B_re_lo, ldb, one, pih, pil, m, st);
+    if (!rc) {
+      e.p_rh = prh; e.p_rl = prl; e.p_ih = pih; e.p_il = pil;
+      rc = hip_status(launch_cgemm_epilogue(e, st));
+    }
+    const hipError_t ef = hipFreeAsync(w, st);
+    if (rc) return rc;
+    return hip_status(ef);
+  }
+  // 3M: the operand sums in compact storage (op(A): rows_a x cols_a as stored)
+  const int64_t ra = ta ? k : m, ca = ta ? m : k, rb = tb ? n : k, cb = tb ? k : n;
+  const size_t sa_bytes = (size_t)ra * ca * sizeof(double), sb_bytes = (size_t)rb * cb * sizeof(double);
+  void* w = nullptr;
+  if (hipMallocAsync(&w, 6 * plane + 2 * sa_bytes + 2 * sb_bytes, st) != hipSuccess)
+    return MPDD_ERR_ALLOC;
+  char* base = (char*)w;
+  double* r1h = (double*)base;
+  double* r1l = (double*)(base + plane);
+  double* r2h = (double*)(base + 2 * plane);
+  double* r2l = (double*)(base + 3 * plane);
+  double* r3h = (double*)(base + 4 * plane);
+  double* r3l = (double*)(base + 5 * plane);
+  double* sah = (double*)(base + 6 * plane);
+  double* sal = (double*)(base + 6 * plane + sa_bytes);
+  double* sbh = (double*)(base + 6 * plane + 2 * sa_bytes);
+  double* sbl = (double*)(base + 6 * plane + 2 * sa_bytes + sb_bytes);
+  int rc = hip_status(launch_dd_axpy_planes(A_re_hi, A_re_lo, A_im_hi, A_im_lo, lda, sa, ra, ca,
+                                            sah, sal, st));
   if (!rc)
-    rc = run_plain(h, nullptr, ta, tb, 0, m, n, k, mpdd_dd{-sa * sb, 0.0}, A_im_hi, A_im_lo, lda,
-                   B_im_hi, B_im_lo, ldb, one, prh, prl, m, st);
+    rc = hip_status(launch_dd_axpy_planes(B_re_hi, B_re_lo, B_im_hi, B_im_lo, ldb, sb, rb, cb,
+                                          sbh, sbl, st));
   if (!rc)
-    rc = run_plain(h, nullptr, ta, tb, 0, m, n, k, mpdd_dd{sb, 0.0}, A_re_hi, A_re_lo, lda,
-                   B_im_hi, B_im_lo, ldb, zero, pih, pil, m, st);
+    rc = run_plain(h, &ro, ta, tb, 0, m, n, k, one, A_re_hi, A_re_lo, lda, B_re_hi, B_re_lo, ldb,
+                   zero, r1h, r1l, m, st);
   if (!rc)
-    rc = run_plain(h, nullptr, ta, tb, 0, m, n, k, mpdd_dd{sa, 0.0}, A_im_hi, A_im_lo, lda,
-                   B_re_hi, B_re_lo, ldb, one, pih, pil, m, st);
+    rc = run_plain(h, &ro, ta, tb, 0, m, n, k, mpdd_dd{sa * sb, 0.0}, A_im_hi, A_im_lo, lda,
+                   B_im_hi, B_im_lo, ldb, zero, r2h, r2l, m, st);
+  if (!rc)
+    rc = run_plain(h, &ro, ta, tb, 0, m, n, k, one, sah, sal, ra, sbh, sbl, rb, zero, r3h, r3l, m,
+                   st);
   if (!rc) {
-    e.p_rh = prh; e.p_rl = prl; e.p_ih = pih; e.p_il = pil;
-    e.ldp = m;
+    e.p_rh = r1h; e.p_rl = r1l; e.p_ih = r2h; e.p_il = r2l;
+    e.q_h = r3h; e.q_l = r3l;
+    e.three_m = 1;
     rc = hip_status(launch_cgemm_epilogue(e, st));
   }
   const hipError_t ef = hipFreeAsync(w, st);
   if (rc) return rc;
   return hip_status(ef);
+}
+
+int mpdd_Cgemm(mpdd_handle h, const char* transa, const char* transb, mpdd_int m, mpdd_int n,
+               mpdd_int k, mpdd_ddc alpha, const double* A_re_hi, const double* A_re_lo,
+               const double* A_im_hi, const double* A_im_lo, mpdd_int lda,
+               const double* B_re_hi, const double* B_re_lo, const double* B_im_hi,
+               const double* B_im_lo, mpdd_int ldb, mpdd_ddc beta, double* C_re_hi,
+               double* C_re_lo, double* C_im_hi, double* C_im_lo, mpdd_int ldc, void* stream) {
+  return mpdd_Cgemm_ex(h, nullptr, transa, transb, m, n, k, alpha, A_re_hi, A_re_lo, A_im_hi,
+                       A_im_lo, lda, B_re_hi, B_re_lo, B_im_hi, B_im_lo, ldb, beta, C_re_hi,
+                       C_re_lo, C_im_hi, C_im_lo, ldc, stream);
 }
 
 // Rpotrf, blocked (LAPACK DPOTRF's left-looking order, with look-ahead).

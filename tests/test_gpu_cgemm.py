@@ -40,11 +40,15 @@ def host4(planes):
     return tuple(x.cpu().numpy() for x in planes)
 
 
-def cgemm_gpu(h, c):
+def cgemm_gpu(h, c, opts=None):
     from paper_2109_13406_amd import binding as b
     C = dev4(c["C"])
-    info = b.mpdd_Cgemm(h, c["transa"], c["transb"], c["m"], c["n"], c["k"], c["alpha"],
-                        dev4(c["A"]), c["lda"], dev4(c["B"]), c["ldb"], c["beta"], C, c["ldc"])
+    args = (c["transa"], c["transb"], c["m"], c["n"], c["k"], c["alpha"], dev4(c["A"]), c["lda"],
+            dev4(c["B"]), c["ldb"], c["beta"], C, c["ldc"])
+    if opts is None:
+        info = b.mpdd_Cgemm(h, *args)
+    else:
+        info = b.mpdd_Cgemm_ex(h, opts, *args)
     return info, host4(C)
 
 
@@ -118,16 +122,34 @@ def test_worked_example(h):
 SHAPES = [(1, 1, 1), (97, 131, 77), (65, 1, 300), (130, 70, 33), (200, 190, 1)]
 
 
+@pytest.mark.parametrize("form", ["4M", "3M"])
 @pytest.mark.parametrize("op", W.COPS, ids=[a + b for a, b in W.COPS])
-def test_cgemm_ragged(h, op):
+def test_cgemm_ragged(h, op, form):
+    from paper_2109_13406_amd import binding as b
+    opts = None if form == "4M" else dict(algo=b.MPDD_COMPLEX_3M)
     for (m, n, k) in SHAPES:
         for dist in ("uniform", "wide"):
             c = W.cgemm_case(4000 + m + k, op[0], op[1], m, n, k, dist=dist)
             O = cgemm_oracle(c)
-            info, G = cgemm_gpu(h, c)
+            info, G = cgemm_gpu(h, c, opts)
             assert info == 0
-            r = compare(f"{op} {m}x{n}x{k} {dist}", G, O, c["C"], m, n, k, c["ldc"])
-            assert r <= RATIO_MAX, (op, m, n, k, dist, r)
+            r = compare(f"{form} {op} {m}x{n}x{k} {dist}", G, O, c["C"], m, n, k, c["ldc"])
+            assert r <= RATIO_MAX, (form, op, m, n, k, dist, r)
+
+
+def test_cgemm_3m_options(h):
+    """The three-product form at 512^3 (k-split and tile choices passed on),
+    and an unknown algo rejected before any work."""
+    from paper_2109_13406_amd import binding as b
+    c = W.cgemm_case(W.BASE_SEED + 5, "C", "N", 512, 512, 512)
+    O = cgemm_oracle(c)
+    for tile in (-1, 2):
+        info, G = cgemm_gpu(h, c, dict(algo=b.MPDD_COMPLEX_3M, tile_id=tile))
+        assert info == 0
+        assert compare(f"3M 512^3 CN tile{tile}", G, O, c["C"], 512, 512, 512,
+                       c["ldc"]) <= RATIO_MAX
+    info, G = cgemm_gpu(h, W.cgemm_case(1, "N", "N", 4, 4, 4), dict(algo=b.MPDD_OZAKI_I8))
+    assert info == b.MPDD_ERR_ARG
 
 
 def test_cgemm_semantics(h):
