@@ -199,8 +199,9 @@ __device__ __forceinline__ void oz_tile_of(int b, int tiles_m, int tiles_n, int 
 // wave owns (WM/2) x (WN/2) outputs = (WM/32) x (WN/32) v_mfma_i32_16x16x64_i8
 // tiles (int32 accumulators, held in AGPRs when they do not fit beside the
 // fragments), so each 16-byte LDS fragment feeds several MFMAs.  A stage holds
-// a W x 64-byte block of each operand in LDS (double buffered; rows padded to
-// 80 bytes so the fragment reads of 16 consecutive rows hit distinct banks).
+// a W x 64-byte block of each operand in LDS (double buffered; 16-byte chunks
+// XOR-permuted per row, i8_lds, so stores and fragment reads avoid bank
+// conflicts).
 // For an MFMA, lane l supplies row l % 16, bytes 16*(l/16) .. +15 of the
 // k-step, for both operands, so every k pairs up.  Accumulation is exact in
 // int32.  Variants (selected by mpdd_opts.tile_id for the INT8 form):
@@ -208,7 +209,16 @@ __device__ __forceinline__ void oz_tile_of(int b, int tiles_m, int tiles_n, int 
 //   1: 256 x 128 (128 x 64 per wave, 2 workgroups per CU)
 //   2: 128 x 128 (64 x 64 per wave, 3 workgroups per CU)
 constexpr int I8_BK = 64;
-constexpr int I8_PITCH = 80;
+constexpr int I8_PITCH = 64;   // bytes per staged row (one k-step), no padding
+
+// LDS position of 16-byte chunk c of staged row r: chunks are permuted by an
+// XOR with ((r >> 1) ^ (r >> 2)) & 3, so that both the staging stores (each 8
+// or 16 lanes write 2 or 4 whole rows) and the fragment reads (lanes l read
+// chunk l / 16 of rows r0 + l % 16, r0 a multiple of 16) touch distinct banks
+// whether the LDS serves 8 lanes per 128 bytes or 16 lanes per 256 bytes.
+__device__ __forceinline__ int i8_lds(int r, int c) {
+  return r * I8_PITCH + ((c ^ ((r >> 1) ^ (r >> 2))) & 3) * 16;
+}
 constexpr int I8_PAD = 256;     // slice rows are padded to this for every variant
 
 template <int WM, int WN>
@@ -239,7 +249,7 @@ oz_gemm_i8(const int8_t* __restrict__ qa, const int8_t* __restrict__ qb, int32_t
   // loads run two k-steps ahead of the MFMAs (two register sets, used
   // alternately), so a load has two steps of matrix work to arrive before
   // its data is written to LDS.
-  const int srow = tid >> 2, scol = (tid & 3) * 16;
+  const int srow = tid >> 2, schunk = tid & 3, scol = schunk * 16;
   const int64_t ksteps = kp / I8_BK;
   const int64_t total = (int64_t)(d - 1) * ksteps;
   v4i ra0[EA], rb0[EB], ra1[EA], rb1[EB];
@@ -256,19 +266,19 @@ oz_gemm_i8(const int8_t* __restrict__ qa, const int8_t* __restrict__ qb, int32_t
   };
   auto sstore = [&](int buf, const v4i (&ra)[EA], const v4i (&rb)[EB]) {
 #pragma unroll
-    for (int e = 0; e < EA; ++e) *(v4i*)&As[buf][(srow + 64 * e) * I8_PITCH + scol] = ra[e];
+    for (int e = 0; e < EA; ++e) *(v4i*)&As[buf][i8_lds(srow + 64 * e, schunk)] = ra[e];
 #pragma unroll
-    for (int e = 0; e < EB; ++e) *(v4i*)&Bs[buf][(srow + 64 * e) * I8_PITCH + scol] = rb[e];
+    for (int e = 0; e < EB; ++e) *(v4i*)&Bs[buf][i8_lds(srow + 64 * e, schunk)] = rb[e];
   };
-  const int fr = lane & 15, fk = (lane >> 4) * 16;
+  const int fr = lane & 15, fc = lane >> 4;
   auto compute = [&](int cur) {
     v4i af[FA], bf[FB];
 #pragma unroll
     for (int a = 0; a < FA; ++a)
-      af[a] = *(const v4i*)&As[cur][(wm * (WM / 2) + a * 16 + fr) * I8_PITCH + fk];
+      af[a] = *(const v4i*)&As[cur][i8_lds(wm * (WM / 2) + a * 16 + fr, fc)];
 #pragma unroll
     for (int c = 0; c < FB; ++c)
-      bf[c] = *(const v4i*)&Bs[cur][(wn * (WN / 2) + c * 16 + fr) * I8_PITCH + fk];
+      bf[c] = *(const v4i*)&Bs[cur][i8_lds(wn * (WN / 2) + c * 16 + fr, fc)];
 #pragma unroll
     for (int a = 0; a < FA; ++a)
 #pragma unroll
