@@ -132,8 +132,9 @@ typedef struct {
   int nslices;  /* split form: slices per operand, 0 = default for the input */
   int tile_id;  /* plain forms: index into the tile table, -1 = tuned choice;
                    INT8 split form: product workgroup tile, 0 = 256x256,
-                   1 = 256x128, 2 = 128x128, -1 = default (0); all give the
-                   same bits; ignored by the FP64 split form */
+                   1 = 256x128, 2 = 128x128, 3 = 256x256 with 8 waves,
+                   4 = 256x256 with 16 waves, -1 = default (3); all give
+                   the same bits; ignored by the FP64 split form */
   int splitk;   /* plain forms: k-split factor, 0 = automatic, 1 = none */
 } mpdd_opts;
 

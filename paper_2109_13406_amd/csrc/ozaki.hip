@@ -195,8 +195,8 @@ __device__ __forceinline__ void oz_tile_of(int b, int tiles_m, int tiles_n, int 
 // ---- products: INT8 ---------------------------------------------------------------------
 
 // X_d tile (WM x WN) for anti-diagonal d: sum over t of Q_t(rows) Q'_{d-t}(cols)^T
-// with k-contiguous int8 rows.  256 threads = 4 waves in a 2 x 2 grid; each
-// wave owns (WM/2) x (WN/2) outputs = (WM/32) x (WN/32) v_mfma_i32_16x16x64_i8
+// with k-contiguous int8 rows.  GM x GN waves; each wave owns (WM/GM) x (WN/GN)
+// outputs = (WM/GM/16) x (WN/GN/16) v_mfma_i32_16x16x64_i8
 // tiles (int32 accumulators, held in AGPRs when they do not fit beside the
 // fragments), so each 16-byte LDS fragment feeds several MFMAs.  A stage holds
 // a W x 64-byte block of each operand in LDS (double buffered; 16-byte chunks
@@ -205,9 +205,12 @@ __device__ __forceinline__ void oz_tile_of(int b, int tiles_m, int tiles_n, int 
 // For an MFMA, lane l supplies row l % 16, bytes 16*(l/16) .. +15 of the
 // k-step, for both operands, so every k pairs up.  Accumulation is exact in
 // int32.  Variants (selected by mpdd_opts.tile_id for the INT8 form):
-//   0: 256 x 256 (128 x 128 per wave, 1 workgroup per CU; the default)
-//   1: 256 x 128 (128 x 64 per wave, 2 workgroups per CU)
-//   2: 128 x 128 (64 x 64 per wave, 3 workgroups per CU)
+//   0: 256 x 256, 2 x 2 waves (128 x 128 each, 1 workgroup per CU)
+//   1: 256 x 128, 2 x 2 waves (128 x 64 each, 2 workgroups per CU)
+//   2: 128 x 128, 2 x 2 waves (64 x 64 each, 3 workgroups per CU)
+//   3: 256 x 256, 2 x 4 waves (128 x 64 each, 512 threads: 2 waves per SIMD;
+//      the default)
+//   4: 256 x 256, 4 x 4 waves (64 x 64 each, 1024 threads: 4 waves per SIMD)
 constexpr int I8_BK = 64;
 constexpr int I8_PITCH = 64;   // bytes per staged row (one k-step), no padding
 
@@ -221,19 +224,23 @@ __device__ __forceinline__ int i8_lds(int r, int c) {
 }
 constexpr int I8_PAD = 256;     // slice rows are padded to this for every variant
 
-template <int WM, int WN>
-__global__ void __launch_bounds__(256, (WM * WN > 256 * 128) ? 1 : 2)
+template <int WM, int WN, int GM, int GN>
+__global__ void __launch_bounds__(64 * GM * GN, (WM * WN / (GM * GN) > 128 * 64) ? 1 : (GM * GN > 8 ? 4 : 2))
 oz_gemm_i8(const int8_t* __restrict__ qa, const int8_t* __restrict__ qb, int32_t* __restrict__ x,
            int64_t kp, int64_t plane_a, int64_t plane_b, int64_t mp, int64_t np, int nslices,
            int tiles_m, int tiles_n) {
-  constexpr int FA = WM / 32, FB = WN / 32;    // 16-row fragments per wave
-  constexpr int EA = WM / 64, EB = WN / 64;    // 16-byte staging loads per thread
+  constexpr int NT = 64 * GM * GN;             // threads: a GM x GN grid of waves
+  constexpr int WR = WM / GM, WC = WN / GN;    // outputs per wave
+  constexpr int FA = WR / 16, FB = WC / 16;    // 16-row fragments per wave
+  constexpr int SR = NT / 4;                   // rows staged per pass (4 threads per row)
+  constexpr int EA = WM / SR, EB = WN / SR;    // 16-byte staging loads per thread
+  static_assert(WM % SR == 0 && WN % SR == 0, "staging must cover the tile");
   __shared__ __attribute__((aligned(16))) int8_t As[2][WM * I8_PITCH];
   __shared__ __attribute__((aligned(16))) int8_t Bs[2][WN * I8_PITCH];
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
-  const int wm = wave & 1, wn = wave >> 1;
+  const int wm = wave % GM, wn = wave / GM;
 
   int d, bi, bj;
   oz_tile_of(blockIdx.x, tiles_m, tiles_n, nslices, d, bi, bj);
@@ -260,25 +267,25 @@ oz_gemm_i8(const int8_t* __restrict__ qa, const int8_t* __restrict__ qb, int32_t
     const int8_t* pa = qa + (int64_t)(t - 1) * plane_a + (i0 + srow) * kp + l0 + scol;
     const int8_t* pb = qb + (int64_t)(d - t - 1) * plane_b + (j0 + srow) * kp + l0 + scol;
 #pragma unroll
-    for (int e = 0; e < EA; ++e) ra[e] = *(const v4i*)(pa + 64 * e * kp);
+    for (int e = 0; e < EA; ++e) ra[e] = *(const v4i*)(pa + SR * e * kp);
 #pragma unroll
-    for (int e = 0; e < EB; ++e) rb[e] = *(const v4i*)(pb + 64 * e * kp);
+    for (int e = 0; e < EB; ++e) rb[e] = *(const v4i*)(pb + SR * e * kp);
   };
   auto sstore = [&](int buf, const v4i (&ra)[EA], const v4i (&rb)[EB]) {
 #pragma unroll
-    for (int e = 0; e < EA; ++e) *(v4i*)&As[buf][i8_lds(srow + 64 * e, schunk)] = ra[e];
+    for (int e = 0; e < EA; ++e) *(v4i*)&As[buf][i8_lds(srow + SR * e, schunk)] = ra[e];
 #pragma unroll
-    for (int e = 0; e < EB; ++e) *(v4i*)&Bs[buf][i8_lds(srow + 64 * e, schunk)] = rb[e];
+    for (int e = 0; e < EB; ++e) *(v4i*)&Bs[buf][i8_lds(srow + SR * e, schunk)] = rb[e];
   };
   const int fr = lane & 15, fc = lane >> 4;
   auto compute = [&](int cur) {
     v4i af[FA], bf[FB];
 #pragma unroll
     for (int a = 0; a < FA; ++a)
-      af[a] = *(const v4i*)&As[cur][i8_lds(wm * (WM / 2) + a * 16 + fr, fc)];
+      af[a] = *(const v4i*)&As[cur][i8_lds(wm * WR + a * 16 + fr, fc)];
 #pragma unroll
     for (int c = 0; c < FB; ++c)
-      bf[c] = *(const v4i*)&Bs[cur][i8_lds(wn * (WN / 2) + c * 16 + fr, fc)];
+      bf[c] = *(const v4i*)&Bs[cur][i8_lds(wn * WC + c * 16 + fr, fc)];
 #pragma unroll
     for (int a = 0; a < FA; ++a)
 #pragma unroll
@@ -300,12 +307,12 @@ oz_gemm_i8(const int8_t* __restrict__ qa, const int8_t* __restrict__ qb, int32_t
     gload(s + 2 < total ? s + 2 : total - 1, ra0, rb0);
     // keep the loads ahead of the MFMAs (not for the 256 x 256 tile, whose
     // accumulators leave no room for the longer-lived staging registers)
-    if constexpr (WM * WN <= 256 * 128) __builtin_amdgcn_sched_barrier(0);
+    if constexpr (WR * WC <= 128 * 64) __builtin_amdgcn_sched_barrier(0);
     compute(0);
     sstore(1, ra1, rb1);
     __syncthreads();
     gload(s + 3 < total ? s + 3 : total - 1, ra1, rb1);
-    if constexpr (WM * WN <= 256 * 128) __builtin_amdgcn_sched_barrier(0);
+    if constexpr (WR * WC <= 128 * 64) __builtin_amdgcn_sched_barrier(0);
     compute(1);
     sstore(0, ra0, rb0);
     __syncthreads();
@@ -317,8 +324,8 @@ oz_gemm_i8(const int8_t* __restrict__ qa, const int8_t* __restrict__ qb, int32_t
   for (int a = 0; a < FA; ++a)
 #pragma unroll
     for (int c = 0; c < FB; ++c) {
-      const int64_t i = i0 + wm * (WM / 2) + a * 16 + (lane >> 4) * 4;
-      const int64_t j = j0 + wn * (WN / 2) + c * 16 + (lane & 15);
+      const int64_t i = i0 + wm * WR + a * 16 + (lane >> 4) * 4;
+      const int64_t j = j0 + wn * WC + c * 16 + (lane & 15);
       *(v4i*)&xd[j * mp + i] = acc[a][c];
     }
 }
@@ -514,12 +521,14 @@ int ozaki_gemm(const void* opts_v, bool ta, bool tb, int64_t m, int64_t n, int64
   // INT8 slice rows are padded to an even number of product k-steps
   const int64_t kp = round_up(k, i8 ? 2 * I8_BK : OZ_KPAD);
   // INT8 product variant (tile_id) and its workgroup tile
-  // (default 256 x 256: with loads two steps ahead it moves the least data
-  // per product and was the fastest measured at n = 4096 and 8192)
-  const int var = (i8 && opts->tile_id >= 0) ? opts->tile_id : 0;
-  if (i8 && var > 2) return MPDD_ERR_UNSUPPORTED;
+  // (default: 256 x 256 with 8 waves -- the largest tile, so the least data
+  // moved per product, and two waves per SIMD to overlap one wave's LDS and
+  // barrier waits with the other's matrix work; fastest measured at n = 4096
+  // and 8192)
+  const int var = (i8 && opts->tile_id >= 0) ? opts->tile_id : 3;
+  if (i8 && var > 4) return MPDD_ERR_UNSUPPORTED;
   const int64_t tbm = i8 ? (var == 2 ? 128 : 256) : OZ_BM;
-  const int64_t tbn = i8 ? (var == 0 ? 256 : 128) : OZ_BN;
+  const int64_t tbn = i8 ? ((var == 0 || var >= 3) ? 256 : 128) : OZ_BN;
   const int64_t mp = round_up(m, i8 ? I8_PAD : OZ_BM), np = round_up(n, i8 ? I8_PAD : OZ_BN);
   const size_t esz = i8 ? 1 : 8;
   const size_t xsz = i8 ? 4 : 8;
@@ -561,9 +570,13 @@ int ozaki_gemm(const void* opts_v, bool ta, bool tb, int64_t m, int64_t n, int64
   const unsigned nblocks = (unsigned)(tiles_m * tiles_n * s);
   if (e == hipSuccess) {
     if (i8) {
-      auto kern = (var == 0) ? oz_gemm_i8<256, 256> : (var == 1) ? oz_gemm_i8<256, 128>
-                                                                 : oz_gemm_i8<128, 128>;
-      hipLaunchKernelGGL(kern, dim3(nblocks), dim3(256), 0, st, (const int8_t*)qa,
+      auto kern = (var == 0)   ? oz_gemm_i8<256, 256, 2, 2>
+                  : (var == 1) ? oz_gemm_i8<256, 128, 2, 2>
+                  : (var == 2) ? oz_gemm_i8<128, 128, 2, 2>
+                  : (var == 3) ? oz_gemm_i8<256, 256, 2, 4>
+                               : oz_gemm_i8<256, 256, 4, 4>;
+      const unsigned nthreads = (var == 3) ? 512 : (var == 4) ? 1024 : 256;
+      hipLaunchKernelGGL(kern, dim3(nblocks), dim3(nthreads), 0, st, (const int8_t*)qa,
                          (const int8_t*)qb, (int32_t*)x, kp, mp * kp, np * kp, mp, np, s, tiles_m,
                          tiles_n);
     }
