@@ -108,7 +108,9 @@ int mpdd_Rsyrk(mpdd_handle h, const char *uplo, const char *trans, mpdd_int n, m
  * complete (synchronous).  Same info codes and BLAS semantics as the device
  * calls; the whole of C (ldc x n) is copied both ways, so padding rows and
  * (Rsyrk) the opposite triangle come back unchanged.  Scratch device memory
- * is allocated and freed inside the call. */
+ * is allocated and freed inside the call.  Rgemm works on up to 8 column
+ * chunks of B and C (at least 512 columns each): the copies of one chunk
+ * overlap the product of the previous one on a second stream. */
 int mpdd_Rgemm_host(mpdd_handle h, const char *transa, const char *transb, mpdd_int m,
                     mpdd_int n, mpdd_int k, mpdd_dd alpha, const mpdd_dd *A, mpdd_int lda,
                     const mpdd_dd *B, mpdd_int ldb, mpdd_dd beta, mpdd_dd *C, mpdd_int ldc);

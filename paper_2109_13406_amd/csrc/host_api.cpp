@@ -5,7 +5,8 @@
 // in place of the CPU one behind the same prototype).  The call copies the
 // operands to the device, splits them into hi/lo planes, runs the device
 // Rgemm / Rsyrk, interleaves C again and copies it back; it returns when C
-// is complete, like the CPU routine.
+// is complete, like the CPU routine.  Rgemm pipelines the copies of column
+// chunks of B and C with the products of the chunks before them.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -86,7 +87,7 @@ int mpdd_Rgemm_host(mpdd_handle h, const char* transa, const char* transb, mpdd_
   // device routine, which checks again)
   const bool nota = lsame(transa, 'N'), notb = lsame(transb, 'N');
   const mpdd_int nrowa = nota ? m : k, ncola = nota ? k : m;
-  const mpdd_int nrowb = notb ? k : n, ncolb = notb ? n : k;
+  const mpdd_int nrowb = notb ? k : n;
   if (!nota && !lsame(transa, 'T') && !lsame(transa, 'C')) return 1;
   if (!notb && !lsame(transb, 'T') && !lsame(transb, 'C')) return 2;
   if (m < 0) return 3;
@@ -99,26 +100,99 @@ int mpdd_Rgemm_host(mpdd_handle h, const char* transa, const char* transb, mpdd_
   if (m == 0 || n == 0 || ((dd_zero(alpha) || k == 0) && dd_one(beta))) return 0;
   const bool use_ab = !dd_zero(alpha) && k > 0;
   if (!C || (use_ab && (!A || !B))) return MPDD_ERR_ARG;
-  hipStream_t st;
-  if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return MPDD_ERR_HIP;
-  Staged bufs[3];
-  int rc = 0;
-  const size_t na = use_ab ? (size_t)lda * (size_t)ncola : 0;
-  const size_t nb = use_ab ? (size_t)ldb * (size_t)ncolb : 0;
-  const size_t nc = (size_t)ldc * (size_t)n;
-  if (!rc) rc = stage_alloc(bufs[0], na, st);
-  if (!rc) rc = stage_alloc(bufs[1], nb, st);
-  if (!rc) rc = stage_alloc(bufs[2], nc, st);
-  if (!rc) rc = upload(bufs[0], A, st);
-  if (!rc) rc = upload(bufs[1], B, st);
-  // C: uploaded whole (its padding rows come back unchanged); with beta = 0
-  // its values are not read by the product, only carried through
-  if (!rc) rc = upload(bufs[2], C, st);
-  if (!rc)
-    rc = mpdd_Rgemm(h, transa, transb, m, n, k, alpha, bufs[0].hi, bufs[0].lo, lda, bufs[1].hi,
-                    bufs[1].lo, ldb, beta, bufs[2].hi, bufs[2].lo, ldc, (void*)st);
-  if (!rc) rc = download(bufs[2], C, st);
-  return finish(bufs, 3, rc, st);
+
+  // Pipelined over column chunks of C: while chunk c is multiplied on the
+  // compute stream, chunk c+1's operands are copied in and chunk c-1's result
+  // copied out on the copy stream.  A is copied in once, first.
+  const int64_t nchunk = std::max<int64_t>(1, std::min<int64_t>(8, n / 512));
+  const int64_t cw = (n + nchunk - 1) / nchunk;          // columns per chunk
+  hipStream_t sc = nullptr, sx = nullptr;
+  hipEvent_t ev_in[2] = {nullptr, nullptr}, ev_out[2] = {nullptr, nullptr};
+  bool ok = hipStreamCreateWithFlags(&sc, hipStreamNonBlocking) == hipSuccess &&
+            hipStreamCreateWithFlags(&sx, hipStreamNonBlocking) == hipSuccess;
+  for (int t = 0; t < 2 && ok; ++t)
+    ok = hipEventCreateWithFlags(&ev_in[t], hipEventDisableTiming) == hipSuccess &&
+         hipEventCreateWithFlags(&ev_out[t], hipEventDisableTiming) == hipSuccess;
+  Staged sa, sbuf[2], scb[2];
+  int rc = ok ? 0 : MPDD_ERR_HIP;
+  // B chunk: columns j0.. of op(B): for 'N' the columns of B, for 'T' its rows
+  const size_t nb_chunk = use_ab ? (notb ? (size_t)ldb * cw : (size_t)cw * k) : 0;
+  const size_t nc_chunk = (size_t)ldc * cw;
+  if (!rc && use_ab) rc = stage_alloc(sa, (size_t)lda * (size_t)ncola, sx);
+  for (int t = 0; t < 2 && !rc; ++t) {
+    rc = stage_alloc(sbuf[t], nb_chunk, sx);
+    if (!rc) rc = stage_alloc(scb[t], nc_chunk, sx);
+  }
+  if (!rc && use_ab) rc = upload(sa, A, sx);
+  auto upload_chunk = [&](int64_t c) -> int {
+    const int64_t j0 = c * cw, w = std::min<int64_t>(cw, n - j0);
+    const int t = (int)(c & 1);
+    if (use_ab) {
+      if (notb) {
+        sbuf[t].n = (size_t)ldb * w;
+        if (int r = upload(sbuf[t], B + (size_t)j0 * ldb, sx)) return r;
+      } else {
+        // rows j0 .. j0+w of B (k columns): a 2-D copy into a compact w x k block
+        sbuf[t].n = (size_t)w * k;
+        if (hipMemcpy2DAsync(sbuf[t].pairs, w * sizeof(mpdd_dd), B + j0, ldb * sizeof(mpdd_dd),
+                             w * sizeof(mpdd_dd), k, hipMemcpyHostToDevice, sx) != hipSuccess ||
+            mpdd::launch_split_pairs((const double*)sbuf[t].pairs, sbuf[t].hi, sbuf[t].lo,
+                                     (int64_t)sbuf[t].n, sx) != hipSuccess)
+          return MPDD_ERR_HIP;
+      }
+    }
+    scb[t].n = (size_t)ldc * w;
+    if (int r = upload(scb[t], C + (size_t)j0 * ldc, sx)) return r;
+    return hipEventRecord(ev_in[t], sx) == hipSuccess ? 0 : MPDD_ERR_HIP;
+  };
+  auto multiply_chunk = [&](int64_t c) -> int {
+    const int64_t j0 = c * cw, w = std::min<int64_t>(cw, n - j0);
+    const int t = (int)(c & 1);
+    if (hipStreamWaitEvent(sc, ev_in[t], 0) != hipSuccess) return MPDD_ERR_HIP;
+    const mpdd_int ldbc = notb ? ldb : (mpdd_int)w;
+    int r = mpdd_Rgemm(h, transa, transb, m, w, k, alpha, sa.hi, sa.lo, lda, sbuf[t].hi,
+                       sbuf[t].lo, ldbc, beta, scb[t].hi, scb[t].lo, ldc, (void*)sc);
+    if (r) return r;
+    if (mpdd::launch_join_pairs(scb[t].hi, scb[t].lo, (double*)scb[t].pairs, (int64_t)scb[t].n,
+                                sc) != hipSuccess ||
+        hipEventRecord(ev_out[t], sc) != hipSuccess)
+      return MPDD_ERR_HIP;
+    return 0;
+  };
+  auto download_chunk = [&](int64_t c) -> int {
+    const int64_t j0 = c * cw;
+    const int t = (int)(c & 1);
+    if (hipStreamWaitEvent(sx, ev_out[t], 0) != hipSuccess ||
+        hipMemcpyAsync(C + (size_t)j0 * ldc, scb[t].pairs, scb[t].n * sizeof(mpdd_dd),
+                       hipMemcpyDeviceToHost, sx) != hipSuccess ||
+        hipStreamSynchronize(sx) != hipSuccess)
+      return MPDD_ERR_HIP;
+    return 0;
+  };
+  if (!rc) rc = upload_chunk(0);
+  if (!rc) rc = multiply_chunk(0);
+  for (int64_t c = 1; c < nchunk && !rc; ++c) {
+    // buffer c & 1 was last used by chunk c-2, downloaded (synchronously)
+    // in the previous iteration
+    rc = upload_chunk(c);
+    if (!rc) rc = multiply_chunk(c);
+    if (!rc) rc = download_chunk(c - 1);
+  }
+  if (!rc) rc = download_chunk(nchunk - 1);
+  // release (after both streams have drained; the scratch was allocated
+  // stream-ordered on the copy stream)
+  if (sc) (void)hipStreamSynchronize(sc);
+  Staged* all[5] = {&sa, &sbuf[0], &sbuf[1], &scb[0], &scb[1]};
+  for (Staged* b : all)
+    if (b->base) (void)hipFreeAsync(b->base, sx);
+  if (sx && hipStreamSynchronize(sx) != hipSuccess && !rc) rc = MPDD_ERR_HIP;
+  for (int t = 0; t < 2; ++t) {
+    if (ev_in[t]) (void)hipEventDestroy(ev_in[t]);
+    if (ev_out[t]) (void)hipEventDestroy(ev_out[t]);
+  }
+  if (sc) (void)hipStreamDestroy(sc);
+  if (sx) (void)hipStreamDestroy(sx);
+  return rc;
 }
 
 int mpdd_Rsyrk_host(mpdd_handle h, const char* uplo, const char* trans, mpdd_int n, mpdd_int k,

@@ -71,6 +71,31 @@ def test_rgemm_host_vs_oracle(h, op):
     log(f"PARITY host-pointer Rgemm {op} ok")
 
 
+@pytest.mark.parametrize("op", W.OPS)
+def test_rgemm_host_chunked(h, op):
+    """Wide C: several column chunks (ragged last chunk) whose copies overlap
+    the products of the chunks before them."""
+    from paper_2109_13406_amd import binding as b
+    for (m, n, k) in [(40, 4100, 50), (33, 1500, 70)]:
+        case = W.gemm_case(1700 + n, op[0], op[1], m, n, k, dist="wide")
+        O = (case["C"][0].copy(), case["C"][1].copy())
+        assert oracle.rgemm(op[0], op[1], m, n, k, case["alpha"], case["A"], case["lda"],
+                            case["B"], case["ldb"], case["beta"], O, case["ldc"]) == 0
+        C = pairs(case["C"])
+        assert b.mpdd_Rgemm_host(h, op[0], op[1], m, n, k, case["alpha"], pairs(case["A"]),
+                                 case["lda"], pairs(case["B"]), case["ldb"], case["beta"], C,
+                                 case["ldc"]) == 0
+        G = planes(C)
+        i, j = np.meshgrid(np.arange(m), np.arange(n), indexing="ij")
+        idx = (i + j * case["ldc"]).ravel()
+        r = ratio(G[0][idx], G[1][idx], O[0][idx], O[1][idx], k)
+        assert r <= RATIO_MAX, (op, m, n, k, r)
+        rest = np.ones(G[0].shape[0], bool)
+        rest[idx] = False
+        assert np.array_equal(bits(G[0])[rest], bits(case["C"][0])[rest])
+    log(f"PARITY host-pointer Rgemm chunked {op} ok")
+
+
 @pytest.mark.parametrize("uplo", "UL")
 @pytest.mark.parametrize("trans", "NT")
 def test_rsyrk_host_vs_oracle(h, uplo, trans):
