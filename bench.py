@@ -199,6 +199,36 @@ def bench_cgemm(h, args, stream):
     return out
 
 
+def bench_potrf(h, args, stream):
+    """Blocked dd Cholesky Rpotrf L at n (synchronous call: it reads each
+    diagonal block's info back).  dd-flops n^3/3 (LAWN 41, leading term)."""
+    import torch
+    import workloads as W
+    from paper_2109_13406_amd import binding as b
+    n = args.n
+    case = W.spd_case_device(W.BASE_SEED + 7, n, "L")
+    A0 = tuple(x.clone() for x in case["A"])
+    torch.cuda.synchronize()
+    times = []
+    for rep in range(1 + max(1, args.steps // 2)):
+        for dst, src in zip(case["A"], A0):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rc, info = b.mpdd_Rpotrf(h, "L", n, case["A"], case["lda"], stream=stream)
+        torch.cuda.synchronize()
+        if rc != 0 or info != 0:
+            raise RuntimeError(f"mpdd_Rpotrf rc={rc} info={info}")
+        if rep > 0:                      # the first call is warm-up
+            times.append(time.perf_counter() - t0)
+    t = sum(times) / len(times)
+    del case, A0
+    torch.cuda.empty_cache()
+    return {"workload": f"Rpotrf L n={n} ld={W.ld_padded(n)} (SPD: dd U[-1,1) off-diagonal, "
+                        f"n + U[0,1) diagonal)", "ms": round(t * 1e3, 3),
+            "dd_gflops": round(float(n) ** 3 / 3.0 / t / 1e9, 1)}
+
+
 def bench_qd(h, args, stream):
     """Quad-double Rgemm NN at n/4 (four planes per matrix; ~10x the binary64
     work of a dd multiply-add).  qd-flops 2mnk."""

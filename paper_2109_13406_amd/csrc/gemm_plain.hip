@@ -38,12 +38,26 @@ namespace mpdd {
 // tiles, and walking that run in 8 x 8 blocks of tiles, makes the ~64
 // workgroups an XCD runs at once share 8 row panels of op(A) and 8 column
 // panels of op(B) in its L2 (instead of 64 row panels and one column panel).
-__device__ __forceinline__ void tile_coords(const GemmParams& p, int& bi, int& bj) {
+// A triangle (Rsyrk) with a tile count that is a multiple of 8 is walked in
+// the same 8 x 8 blocks, taken over the triangle of blocks, so that each XCD
+// receives a near-equal share of the work; the workgroups of the tiles of a
+// diagonal block that lie outside the triangle return at once (false).
+// Other triangles launch only their tiles, column by column.
+__device__ __forceinline__ int tri_col(int t) {
+  // largest y with y(y+1)/2 <= t
+  int y = (int)((__builtin_sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+  while ((y + 1) * (y + 2) / 2 <= t) ++y;
+  while (y * (y + 1) / 2 > t) --y;
+  return y;
+}
+
+__device__ __forceinline__ bool tile_coords(const GemmParams& p, int& bi, int& bj) {
   int b = blockIdx.x;
   const int nb = gridDim.x;
   if ((nb & 7) == 0) b = (b & 7) * (nb >> 3) + (b >> 3);
+  const bool blocks8 = (p.tiles_m & 7) == 0 && (p.tiles_n & 7) == 0;
   if (p.tri == 0) {
-    if ((p.tiles_m & 7) == 0 && (p.tiles_n & 7) == 0) {
+    if (blocks8) {
       const int sb = b >> 6, w = b & 63;
       const int sm = p.tiles_m >> 3;
       bi = (sb % sm) * 8 + (w & 7);
@@ -52,15 +66,43 @@ __device__ __forceinline__ void tile_coords(const GemmParams& p, int& bi, int& b
       bi = b % p.tiles_m;
       bj = b / p.tiles_m;
     }
-  } else {
-    // tiles (x, y) with x <= y, enumerated column by column: t = y(y+1)/2 + x
-    int y = (int)((__builtin_sqrt(8.0 * (double)b + 1.0) - 1.0) * 0.5);
-    while ((y + 1) * (y + 2) / 2 <= b) ++y;
-    while (y * (y + 1) / 2 > b) --y;
-    int x = b - y * (y + 1) / 2;
-    if (p.tri == 1) { bi = x; bj = y; }   // upper: tile row <= tile column
-    else { bi = y; bj = x; }              // lower: tile row >= tile column
+    return true;
   }
+  if (blocks8) {
+    const int sb = b >> 6, w = b & 63;
+    const int s8 = p.tiles_m >> 3;
+    int sx, sy;
+    if ((s8 & 15) == 0) {
+      // each XCD's run of blocks: its share of the blocks above the diagonal
+      // (taken column by column), then its share of the diagonal blocks
+      const int nodd = s8 * (s8 - 1) / 2;
+      const int per = (nodd + s8) >> 3, oper = nodd >> 3, dper = s8 >> 3;
+      const int x = sb / per, j = sb - x * per;
+      if (j < oper) {
+        const int t = x * oper + j;
+        sy = tri_col(t) + 1;               // block (sx, sy), sx < sy
+        sx = t - sy * (sy - 1) / 2;
+      } else {
+        sx = sy = x * dper + (j - oper);
+      }
+    } else {
+      sy = tri_col(sb);                    // block (sx, sy), sx <= sy
+      sx = sb - sy * (sy + 1) / 2;
+    }
+    if (p.tri == 1) {            // upper: tile row <= tile column
+      bi = sx * 8 + (w & 7);
+      bj = sy * 8 + (w >> 3);
+      return bi <= bj;
+    }
+    bi = sy * 8 + (w & 7);       // lower: tile row >= tile column
+    bj = sx * 8 + (w >> 3);
+    return bi >= bj;
+  }
+  // tiles (x, y) with x <= y, enumerated column by column: t = y(y+1)/2 + x
+  const int y = tri_col(b), x = b - y * (y + 1) / 2;
+  if (p.tri == 1) { bi = x; bj = y; }
+  else { bi = y; bj = x; }
+  return true;
 }
 
 template <int BM, int BN, int BK>
@@ -347,7 +389,7 @@ __global__ void __launch_bounds__((BM / RM) * (BN / RN))
 dd_gemm_kernel(GemmParams p) {
   __shared__ DDTileSmem<BM, BN, BK> sm;
   int bi, bj;
-  tile_coords(p, bi, bj);
+  if (!tile_coords(p, bi, bj)) return;     // a tile outside the triangle
   const int64_t i0 = (int64_t)bi * BM;
   const int64_t j0 = (int64_t)bj * BN;
   const int64_t kbeg = (int64_t)blockIdx.z * p.kchunk;
@@ -531,10 +573,14 @@ hipError_t launch_gemm(int tile, const GemmParams& p, bool ta, bool tb, bool acc
   const TileInfo* t = tile_info(tile);
   if (!t) return hipErrorInvalidValue;
   int nblocks;
-  if (p.tri == 0)
+  if (p.tri == 0) {
     nblocks = p.tiles_m * p.tiles_n;
-  else
+  } else if ((p.tiles_m & 7) == 0) {           // 8 x 8 blocks over the triangle
+    const int s8 = p.tiles_m >> 3;
+    nblocks = 64 * (s8 * (s8 + 1) / 2);
+  } else {
     nblocks = p.tiles_m * (p.tiles_m + 1) / 2;
+  }
   switch (tile) {
 #define X(id, bm, bn, bk, rm, rn, xm) \
   case id: return launch_ops<bm, bn, bk, rm, rn, xm != 0>(p, ta, tb, accurate, nblocks, splitk, st);

@@ -220,3 +220,23 @@ def test_deterministic(h):
     _, G1 = gemm_gpu(h, case)
     _, G2 = gemm_gpu(h, case)
     assert np.array_equal(bits(G1[0]), bits(G2[0])) and np.array_equal(bits(G1[1]), bits(G2[1]))
+
+
+@pytest.mark.parametrize("n", [1024, 8192])
+@pytest.mark.parametrize("uplo", "UL")
+def test_syrk_triangle_coverage(h, uplo, n):
+    """Every tile of the triangle is computed exactly once and nothing outside
+    it is written, for the launch orders of triangles whose tile count is a
+    multiple of 8 (8 x 8 blocks; at 8192 and 64-wide tiles, 128 tiles a side,
+    each XCD's share of the blocks): full comparison with a short k."""
+    from paper_2109_13406_amd import binding as b
+    k = 8
+    case = W.syrk_case(870 + n, uplo, "N", n, k, dist="wide")
+    O = syrk_oracle(case)
+    for tile in (2, 4):                  # 32- and 64-wide square tiles
+        info, G = syrk_gpu(h, case, opts=dict(algo=b.MPDD_PLAIN, tile_id=tile, splitk=1))
+        assert info == 0
+        r = compare_full(f"syrk coverage {uplo}N {n}x{k} tile{tile}", G, O, n, n, k,
+                         case["ldc"], tri=uplo, C0=case["C"])
+        assert r <= RATIO_MAX
+        del G
