@@ -135,8 +135,11 @@ typedef struct {
   int tile_id;  /* plain forms: index into the tile table, -1 = tuned choice;
                    INT8 split form: product workgroup tile, 0 = 256x256,
                    1 = 256x128, 2 = 128x128, 3 = 256x256 with 8 waves,
-                   4 = 256x256 with 16 waves, -1 = default (3); all give
-                   the same bits; ignored by the FP64 split form */
+                   4 = 256x256 with 16 waves, 5 = 256x256 with 8 waves
+                   and digits loaded straight into LDS, 6 = as 5 with
+                   the next step's fragments read during the MFMAs,
+                   -1 = default (6);
+                   all give the same bits; ignored by the FP64 split form */
   int splitk;   /* plain forms: k-split factor, 0 = automatic, 1 = none */
 } mpdd_opts;
 

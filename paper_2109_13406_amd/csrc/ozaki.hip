@@ -208,9 +208,9 @@ __device__ __forceinline__ void oz_tile_of(int b, int tiles_m, int tiles_n, int 
 //   0: 256 x 256, 2 x 2 waves (128 x 128 each, 1 workgroup per CU)
 //   1: 256 x 128, 2 x 2 waves (128 x 64 each, 2 workgroups per CU)
 //   2: 128 x 128, 2 x 2 waves (64 x 64 each, 3 workgroups per CU)
-//   3: 256 x 256, 2 x 4 waves (128 x 64 each, 512 threads: 2 waves per SIMD;
-//      the default)
+//   3: 256 x 256, 2 x 4 waves (128 x 64 each, 512 threads: 2 waves per SIMD)
 //   4: 256 x 256, 4 x 4 waves (64 x 64 each, 1024 threads: 4 waves per SIMD)
+//   5, 6: the tiling of 3 in oz_gemm_i8_dma below (6 is the default)
 constexpr int I8_BK = 64;
 constexpr int I8_PITCH = 64;   // bytes per staged row (one k-step), no padding
 
@@ -319,6 +319,172 @@ oz_gemm_i8(const int8_t* __restrict__ qa, const int8_t* __restrict__ qb, int32_t
   }
 
   // C layout of a 16x16 INT8 MFMA tile: lane l holds rows 4*(l/16) + 0..3 of column l%16.
+  int32_t* xd = x + (int64_t)(d - 2) * mp * np;
+#pragma unroll
+  for (int a = 0; a < FA; ++a)
+#pragma unroll
+    for (int c = 0; c < FB; ++c) {
+      const int64_t i = i0 + wm * WR + a * 16 + (lane >> 4) * 4;
+      const int64_t j = j0 + wn * WC + c * 16 + (lane & 15);
+      *(v4i*)&xd[j * mp + i] = acc[a][c];
+    }
+}
+
+// Direct-to-LDS form of the same product (variant 5): the digits travel from
+// global memory straight into LDS (global_load_lds_dwordx4: lane l of a wave
+// writes 16 bytes at M0 + 16 l), so no registers stage them and no ds_write
+// stores them.  NS stages form a ring; the loads of a stage are issued NS - 1
+// steps before its matrix work, and one barrier per step both publishes the
+// stage about to be used and frees the one about to be refilled.  A DMA
+// instruction fills 16 staged rows (1 KB, the i8_lds layout); each lane picks
+// the global chunk that the layout places at its slot, so the XOR permutation
+// is applied on the global side.
+// Wait until at most VM of this wave's global loads (here: LDS DMA) and LGKM
+// of its LDS reads are outstanding, then meet the workgroup barrier.  One asm
+// statement with a memory clobber, so that no LDS access moves across it.
+template <int VM, int LGKM>
+__device__ __forceinline__ void i8_sync() {
+  static_assert(VM >= 0 && VM <= 63 && LGKM >= 0 && LGKM <= 15, "s_waitcnt fields");
+  asm volatile("s_waitcnt vmcnt(%0) lgkmcnt(%1)\n\ts_barrier" ::"n"(VM), "n"(LGKM) : "memory");
+}
+
+template <int WM, int WN, int GM, int GN, int NS, bool PF>
+__global__ void __launch_bounds__(64 * GM * GN, 1)
+oz_gemm_i8_dma(const int8_t* __restrict__ qa, const int8_t* __restrict__ qb,
+               int32_t* __restrict__ x, int64_t kp, int64_t plane_a, int64_t plane_b, int64_t mp,
+               int64_t np, int nslices, int tiles_m, int tiles_n) {
+  constexpr int NW = GM * GN;                  // waves
+  constexpr int WR = WM / GM, WC = WN / GN;    // outputs per wave
+  constexpr int FA = WR / 16, FB = WC / 16;    // 16-row fragments per wave
+  constexpr int RA = WM / NW, RB = WN / NW;    // rows of each operand one wave stages
+  constexpr int LA = RA / 16, LB = RB / 16;    // DMA instructions per operand and step
+  constexpr int STAGE = (WM + WN) * I8_PITCH;  // bytes per stage
+  static_assert(RA % 16 == 0 && RB % 16 == 0, "a DMA instruction stages 16 rows");
+  __shared__ __attribute__((aligned(1024))) int8_t smem[NS * STAGE];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wm = wave % GM, wn = wave / GM;
+
+  int d, bi, bj;
+  oz_tile_of(blockIdx.x, tiles_m, tiles_n, nslices, d, bi, bj);
+  const int64_t i0 = (int64_t)bi * WM, j0 = (int64_t)bj * WN;
+
+  v4i acc[FA][FB];
+#pragma unroll
+  for (int a = 0; a < FA; ++a)
+#pragma unroll
+    for (int c = 0; c < FB; ++c) acc[a][c] = v4i{0, 0, 0, 0};
+
+  // lane l of a DMA instruction fills staged row r0 + l/4 (r0 a multiple of
+  // 16), physical chunk l%4, which holds logical chunk (l%4) ^ g(row); g
+  // depends only on the row's low four bits, i.e. on l/4
+  const int lr = lane >> 2;
+  const int lc = ((lane & 3) ^ (lr >> 1) ^ (lr >> 2)) & 3;
+  const int64_t ksteps = kp / I8_BK;
+  const int64_t total = (int64_t)(d - 1) * ksteps;
+  const int8_t* ga = qa + (i0 + wave * RA + lr) * kp + lc * 16;
+  const int8_t* gb = qb + (j0 + wave * RB + lr) * kp + lc * 16;
+
+  // Steps are issued in order, step x into stage x % NS; (it, il0) is the
+  // slice and k offset of the next one.  Steps past the end re-load the last
+  // step (into a stage no later step reads), so that every step issues the
+  // same loads and the wait counts are constants.
+  int it = 1, ibuf = 0;
+  int64_t il0 = 0, inext = 0;
+  auto issue = [&]() {
+    const int8_t* pa = ga + (int64_t)(it - 1) * plane_a + il0;
+    const int8_t* pb = gb + (int64_t)(d - it - 1) * plane_b + il0;   // op(B) slice d - t
+    int8_t* st = smem + ibuf * STAGE;
+#pragma unroll
+    for (int e = 0; e < LA; ++e)
+      __builtin_amdgcn_global_load_lds(
+          (const void*)(pa + (int64_t)16 * e * kp),
+          (__attribute__((address_space(3))) void*)(st + (wave * RA + 16 * e) * I8_PITCH), 16, 0,
+          0);
+#pragma unroll
+    for (int e = 0; e < LB; ++e)
+      __builtin_amdgcn_global_load_lds(
+          (const void*)(pb + (int64_t)16 * e * kp),
+          (__attribute__((address_space(3))) void*)(st + WM * I8_PITCH +
+                                                    (wave * RB + 16 * e) * I8_PITCH),
+          16, 0, 0);
+    if (++inext < total) {
+      il0 += I8_BK;
+      if (il0 == kp) {
+        il0 = 0;
+        ++it;
+      }
+    }
+    ibuf = (ibuf + 1 == NS) ? 0 : ibuf + 1;
+  };
+  const int fr = lane & 15, fc = lane >> 4;
+  auto fetch = [&](int buf, v4i (&af)[FA], v4i (&bf)[FB]) {
+    const int8_t* As = smem + buf * STAGE;
+    const int8_t* Bs = As + WM * I8_PITCH;
+#pragma unroll
+    for (int a = 0; a < FA; ++a) af[a] = *(const v4i*)&As[i8_lds(wm * WR + a * 16 + fr, fc)];
+#pragma unroll
+    for (int c = 0; c < FB; ++c) bf[c] = *(const v4i*)&Bs[i8_lds(wn * WC + c * 16 + fr, fc)];
+  };
+  auto mfma = [&](const v4i (&af)[FA], const v4i (&bf)[FB]) {
+#pragma unroll
+    for (int a = 0; a < FA; ++a)
+#pragma unroll
+      for (int c = 0; c < FB; ++c)
+        acc[a][c] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af[a], bf[c], acc[a][c], 0, 0, 0);
+  };
+  // The fragments read one step earlier have long arrived: waiting for them
+  // (lgkmcnt(0), before the next prefetch is issued) costs nothing and tells
+  // the compiler that the MFMAs need not wait for the prefetch.
+  auto frags_landed = [&]() {
+    __builtin_amdgcn_s_waitcnt(0xC07F);        // lgkmcnt(0); vmcnt, expcnt not waited on
+    __builtin_amdgcn_sched_barrier(0);
+  };
+  constexpr int PER = LA + LB;                 // DMA instructions per step and wave
+
+#pragma unroll
+  for (int q = 0; q < NS - 1; ++q) issue();
+  if constexpr (!PF) {
+    // step s: issued 0 .. s + NS - 2, so step s has landed once the loads of
+    // NS - 2 later steps remain; no LDS read is in flight at the barrier (the
+    // reads of step s - 1 fed its MFMAs), so stage (s - 1) % NS may be refilled
+    for (int64_t s = 0; s < total; ++s) {
+      i8_sync<(NS - 2) * PER, 0>();
+      issue();                                 // step s + NS - 1
+      v4i af[FA], bf[FB];
+      fetch((int)(s % NS), af, bf);
+      mfma(af, bf);
+    }
+  } else {
+    // fragments of step s + 1 are read from LDS while the MFMAs of step s run
+    // (two register sets).  At step s, issued 0 .. s + NS - 2: step s + 1 has
+    // landed once the loads of NS - 3 later steps remain; the LDS reads of the
+    // prefetch of step s (FA + FB, the youngest) may still be in flight, those
+    // of step s - 1 are done, so stage (s - 1) % NS may be refilled.
+    static_assert(NS >= 4, "prefetch needs four stages");
+    v4i af0[FA], bf0[FB], af1[FA], bf1[FB];
+    i8_sync<(NS - 2) * PER, 0>();
+    fetch(0, af0, bf0);
+    // total is even (kp is a multiple of 2 * I8_BK)
+    for (int64_t s = 0; s < total; s += 2) {
+      i8_sync<(NS - 3) * PER, FA + FB>();
+      issue();                                 // step s + NS - 1
+      frags_landed();
+      fetch((int)((s + 1) % NS), af1, bf1);
+      mfma(af0, bf0);
+      // after the last pair this prefetches a stage no step uses: harmless
+      i8_sync<(NS - 3) * PER, FA + FB>();
+      issue();                                 // step s + NS
+      frags_landed();
+      fetch((int)((s + 2) % NS), af0, bf0);
+      mfma(af1, bf1);
+    }
+  }
+  // the loads past the end must land before the workgroup's LDS is released
+  __builtin_amdgcn_s_waitcnt(0x0F70);          // vmcnt(0), lgkmcnt not waited on
+  __builtin_amdgcn_sched_barrier(0);
+
   int32_t* xd = x + (int64_t)(d - 2) * mp * np;
 #pragma unroll
   for (int a = 0; a < FA; ++a)
@@ -521,12 +687,12 @@ int ozaki_gemm(const void* opts_v, bool ta, bool tb, int64_t m, int64_t n, int64
   // INT8 slice rows are padded to an even number of product k-steps
   const int64_t kp = round_up(k, i8 ? 2 * I8_BK : OZ_KPAD);
   // INT8 product variant (tile_id) and its workgroup tile
-  // (default: 256 x 256 with 8 waves -- the largest tile, so the least data
-  // moved per product, and two waves per SIMD to overlap one wave's LDS and
-  // barrier waits with the other's matrix work; fastest measured at n = 4096
-  // and 8192)
-  const int var = (i8 && opts->tile_id >= 0) ? opts->tile_id : 3;
-  if (i8 && var > 4) return MPDD_ERR_UNSUPPORTED;
+  // (default 6: 256 x 256 with 8 waves -- the largest tile, so the least data
+  // moved per product, two waves per SIMD -- with the digits loaded straight
+  // into a four-stage LDS ring and each step's fragments read during the
+  // previous step's MFMAs; fastest measured at n = 4096 and 8192)
+  const int var = (i8 && opts->tile_id >= 0) ? opts->tile_id : 6;
+  if (i8 && var > 6) return MPDD_ERR_UNSUPPORTED;
   const int64_t tbm = i8 ? (var == 2 ? 128 : 256) : OZ_BM;
   const int64_t tbn = i8 ? ((var == 0 || var >= 3) ? 256 : 128) : OZ_BN;
   const int64_t mp = round_up(m, i8 ? I8_PAD : OZ_BM), np = round_up(n, i8 ? I8_PAD : OZ_BN);
@@ -574,8 +740,10 @@ int ozaki_gemm(const void* opts_v, bool ta, bool tb, int64_t m, int64_t n, int64
                   : (var == 1) ? oz_gemm_i8<256, 128, 2, 2>
                   : (var == 2) ? oz_gemm_i8<128, 128, 2, 2>
                   : (var == 3) ? oz_gemm_i8<256, 256, 2, 4>
-                               : oz_gemm_i8<256, 256, 4, 4>;
-      const unsigned nthreads = (var == 3) ? 512 : (var == 4) ? 1024 : 256;
+                  : (var == 4) ? oz_gemm_i8<256, 256, 4, 4>
+                  : (var == 5) ? oz_gemm_i8_dma<256, 256, 2, 4, 4, false>
+                               : oz_gemm_i8_dma<256, 256, 2, 4, 4, true>;
+      const unsigned nthreads = (var == 4) ? 1024 : (var >= 3) ? 512 : 256;
       hipLaunchKernelGGL(kern, dim3(nblocks), dim3(nthreads), 0, st, (const int8_t*)qa,
                          (const int8_t*)qb, (int32_t*)x, kp, mp * kp, np * kp, mp, np, s, tiles_m,
                          tiles_n);
