@@ -84,7 +84,7 @@ def tune_ozaki(h, n, kind="i8", slices=(13, 16), reps=2, verbose=True):
     algo = b.MPDD_OZAKI_I8 if kind == "i8" else b.MPDD_OZAKI_F64
     case = W.gemm_case_device(4321, "N", "N", n, n, n, padded=False)
     out = []
-    for var in range(7 if kind == "i8" else 1):
+    for var in range(8 if kind == "i8" else 1):
         for sl in slices:
             opts = dict(algo=algo, nslices=sl, tile_id=var)
             fn = lambda: b.mpdd_Rgemm_ex(h, opts, "N", "N", n, n, n, case["alpha"], case["A"],

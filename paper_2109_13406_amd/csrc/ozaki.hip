@@ -211,6 +211,7 @@ __device__ __forceinline__ void oz_tile_of(int b, int tiles_m, int tiles_n, int 
 //   3: 256 x 256, 2 x 4 waves (128 x 64 each, 512 threads: 2 waves per SIMD)
 //   4: 256 x 256, 4 x 4 waves (64 x 64 each, 1024 threads: 4 waves per SIMD)
 //   5, 6: the tiling of 3 in oz_gemm_i8_dma below (6 is the default)
+//   7: 256 x 256, 2 x 2 waves in oz_gemm_i8_dma (1 wave per SIMD)
 constexpr int I8_BK = 64;
 constexpr int I8_PITCH = 64;   // bytes per staged row (one k-step), no padding
 
@@ -442,6 +443,10 @@ oz_gemm_i8_dma(const int8_t* __restrict__ qa, const int8_t* __restrict__ qb,
     __builtin_amdgcn_sched_barrier(0);
   };
   constexpr int PER = LA + LB;                 // DMA instructions per step and wave
+  // LDS reads that may stay in flight at a barrier: the prefetch (FA + FB
+  // reads), capped by the 4-bit counter (waiting for its oldest read as well
+  // is harmless)
+  constexpr int PFQ = (FA + FB < 15) ? FA + FB : 15;
 
 #pragma unroll
   for (int q = 0; q < NS - 1; ++q) issue();
@@ -468,13 +473,13 @@ oz_gemm_i8_dma(const int8_t* __restrict__ qa, const int8_t* __restrict__ qb,
     fetch(0, af0, bf0);
     // total is even (kp is a multiple of 2 * I8_BK)
     for (int64_t s = 0; s < total; s += 2) {
-      i8_sync<(NS - 3) * PER, FA + FB>();
+      i8_sync<(NS - 3) * PER, PFQ>();
       issue();                                 // step s + NS - 1
       frags_landed();
       fetch((int)((s + 1) % NS), af1, bf1);
       mfma(af0, bf0);
       // after the last pair this prefetches a stage no step uses: harmless
-      i8_sync<(NS - 3) * PER, FA + FB>();
+      i8_sync<(NS - 3) * PER, PFQ>();
       issue();                                 // step s + NS
       frags_landed();
       fetch((int)((s + 2) % NS), af0, bf0);
@@ -692,7 +697,7 @@ int ozaki_gemm(const void* opts_v, bool ta, bool tb, int64_t m, int64_t n, int64
   // into a four-stage LDS ring and each step's fragments read during the
   // previous step's MFMAs; fastest measured at n = 4096 and 8192)
   const int var = (i8 && opts->tile_id >= 0) ? opts->tile_id : 6;
-  if (i8 && var > 6) return MPDD_ERR_UNSUPPORTED;
+  if (i8 && var > 7) return MPDD_ERR_UNSUPPORTED;
   const int64_t tbm = i8 ? (var == 2 ? 128 : 256) : OZ_BM;
   const int64_t tbn = i8 ? ((var == 0 || var >= 3) ? 256 : 128) : OZ_BN;
   const int64_t mp = round_up(m, i8 ? I8_PAD : OZ_BM), np = round_up(n, i8 ? I8_PAD : OZ_BN);
@@ -742,8 +747,9 @@ int ozaki_gemm(const void* opts_v, bool ta, bool tb, int64_t m, int64_t n, int64
                   : (var == 3) ? oz_gemm_i8<256, 256, 2, 4>
                   : (var == 4) ? oz_gemm_i8<256, 256, 4, 4>
                   : (var == 5) ? oz_gemm_i8_dma<256, 256, 2, 4, 4, false>
-                               : oz_gemm_i8_dma<256, 256, 2, 4, 4, true>;
-      const unsigned nthreads = (var == 4) ? 1024 : (var >= 3) ? 512 : 256;
+                  : (var == 6) ? oz_gemm_i8_dma<256, 256, 2, 4, 4, true>
+                               : oz_gemm_i8_dma<256, 256, 2, 2, 4, true>;
+      const unsigned nthreads = (var == 4) ? 1024 : (var >= 3 && var <= 6) ? 512 : 256;
       hipLaunchKernelGGL(kern, dim3(nblocks), dim3(nthreads), 0, st, (const int8_t*)qa,
                          (const int8_t*)qb, (int32_t*)x, kp, mp * kp, np * kp, mp, np, s, tiles_m,
                          tiles_n);

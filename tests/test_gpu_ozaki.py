@@ -68,7 +68,7 @@ def test_slices_bit_identical(h, kind, trans, dist):
 
 
 SHAPES = [(1, 1, 1), (70, 90, 33), (129, 130, 200), (200, 64, 65), (300, 270, 130)]
-VARIANTS = (0, 1, 2, 3, 4, 5, 6)   # INT8 product tilings (see the tile_id options)
+VARIANTS = (0, 1, 2, 3, 4, 5, 6, 7)   # INT8 product tilings (see the tile_id options)
 
 
 @pytest.mark.parametrize("kind", ["i8", "f64"])
@@ -127,7 +127,7 @@ def test_split_semantics(h):
                        opts=dict(algo=b.MPDD_OZAKI_I8, nslices=41))
     assert info == b.MPDD_ERR_UNSUPPORTED
     info, _ = gemm_gpu(h, W.gemm_case(74, "N", "N", 8, 8, 8),
-                       opts=dict(algo=b.MPDD_OZAKI_I8, nslices=12, tile_id=7))
+                       opts=dict(algo=b.MPDD_OZAKI_I8, nslices=12, tile_id=8))
     assert info == b.MPDD_ERR_UNSUPPORTED
 
 
