@@ -12,7 +12,7 @@
 //   dd_add        AccurateDWPlusDW  (Joldes-Muller-Popescu 2017), rel. err. <= 3u^2.
 //   dd_mul        DWTimesDW3        (same paper), rel. err. <= 4u^2.
 //   dd_add_d      DWPlusFP          (same paper), rel. err. <= 2u^2.
-//   madd_lean     acc += a*b with deferred renormalisation (12 ops, see below).
+//   madd_lean     acc += a*b with deferred renormalisation (10 ops, see below).
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -76,35 +76,42 @@ __device__ __forceinline__ void madd_accurate(double& sh, double& sl, double ah,
   sl = r.lo;
 }
 
-// Lean multiply-accumulate (12 binary64 ops).  sh holds the running binary64
+// Lean multiply-accumulate (10 binary64 ops).  sh holds the running binary64
 // sum of the leading products p = fl(ah*bh); every rounding error made on the
-// way -- the product error fma(ah,bh,-p), the TwoSum error of sh + p -- and
-// the cross terms ah*bl + al*bh are accumulated in sl.  al*bl (below
-// u^2 |ab|) is dropped.  The pair is renormalised with two_sum once per
-// staged k-tile, so |sl| stays near u |sh|; sh + sl carries ~106 bits.
+// way -- the product error ah*bh - p and the TwoSum error of sh + p -- and the
+// cross terms ah*bl + al*bh are accumulated in sl.  al*bl (below u^2 |ab|) is
+// dropped.  The pair is renormalised with two_sum once per staged k-tile, so
+// |sl| stays near u |sh|; sh + sl carries ~106 bits.
+//
+// In TwoSum(sh, p) every operation after s = fl(sh + p) is exact, and its
+// error is (sh - (s - bb)) + (p - bb) with bb = s - sh.  The product error and
+// the second term together are ah*bh - bb exactly, which one fma evaluates
+// with a single rounding; so the two error terms cost four ops after s (bb,
+// s - bb, sh - (s - bb), the fma) instead of six, with the same O(u^2) error
+// per term as adding the exact errors one by one.
 __device__ __forceinline__ void madd_lean(double& sh, double& sl, double ah, double al,
                                           double bh, double bl) {
   double p = ah * bh;
-  double e = __builtin_fma(ah, bh, -p);
   double s = sh + p;
   double bb = s - sh;
-  double se = (sh - (s - bb)) + (p - bb);
+  double t2 = sh - (s - bb);
+  double u = __builtin_fma(ah, bh, -bb);      // (p - bb) + (ah*bh - p), rounded once
   double t = __builtin_fma(ah, bl, sl);
   t = __builtin_fma(al, bh, t);
-  sl = t + (e + se);
+  sl = t + (t2 + u);
   sh = s;
 }
 
-// Lean multiply-accumulate without the cross terms (10 binary64 ops): the
+// Lean multiply-accumulate without the cross terms (8 binary64 ops): the
 // leading product and its rounding errors only; ah*bl + al*bh is accumulated
 // elsewhere (on the matrix cores) and added to sl once per tile.
 __device__ __forceinline__ void madd_lean_hi(double& sh, double& sl, double ah, double bh) {
   double p = ah * bh;
-  double e = __builtin_fma(ah, bh, -p);
   double s = sh + p;
   double bb = s - sh;
-  double se = (sh - (s - bb)) + (p - bb);
-  sl = sl + (e + se);
+  double t2 = sh - (s - bb);
+  double u = __builtin_fma(ah, bh, -bb);      // (p - bb) + (ah*bh - p), rounded once
+  sl = sl + (t2 + u);
   sh = s;
 }
 
