@@ -23,7 +23,7 @@
 //
 // Tile: 32 x 32 outputs per workgroup of 256 threads, 2 x 2 outputs per thread
 // (rows tm + 16 r, columns tn + 16 c), k staged QD_BK deep through LDS as
-// double4 (x0..x3) entries.  About 120 binary64 operations per multiply-add,
+// double4 (x0..x3) entries.  About 110 binary64 operations per multiply-add,
 // so the kernel is FP64-issue-bound like the dd kernels.
 #include "dd.hpp"
 #include "kernels.hpp"
@@ -51,15 +51,26 @@ __device__ __forceinline__ void tp(double a, double b, double& p, double& e) {
   e = __builtin_fma(a, b, -p);
 }
 
+// s2 += fl(a*b) by TwoSum, returning the level-3 residue: the TwoSum error
+// (s2 - (s - bb)) + (p - bb) plus the product error a*b - p.  The last two add
+// up to a*b - bb exactly, which one fma gives with a single rounding (an error
+// of a level-3 size times 2^-53, like the plain additions of level 3).
+__device__ __forceinline__ double ts_prod(double& s2, double a, double b) {
+  const double p = a * b;
+  const double s = s2 + p;
+  const double bb = s - s2;
+  const double t2 = s2 - (s - bb);
+  const double u = __builtin_fma(a, b, -bb);
+  s2 = s;
+  return t2 + u;
+}
+
 // c += a * b by levels (see the file comment)
 __device__ __forceinline__ void qd_madd(qacc& c, const double4& a, const double4& b) {
-  double p00, e00, p01, e01, p10, e10, p02, e02, p11, e11, p20, e20;
+  double p00, e00, p01, e01, p10, e10;
   tp(a.x, b.x, p00, e00);
   tp(a.x, b.y, p01, e01);
   tp(a.y, b.x, p10, e10);
-  tp(a.x, b.z, p02, e02);
-  tp(a.y, b.y, p11, e11);
-  tp(a.z, b.x, p20, e20);
   double l3 = a.w * b.x;
   l3 = __builtin_fma(a.z, b.y, l3);
   l3 = __builtin_fma(a.y, b.z, l3);
@@ -83,11 +94,12 @@ __device__ __forceinline__ void qd_madd(qacc& c, const double4& a, const double4
   ts(c.s2, u4, c.s2, v); w += v;
   ts(c.s2, e01, c.s2, v); w += v;
   ts(c.s2, e10, c.s2, v); w += v;
-  ts(c.s2, p02, c.s2, v); w += v;
-  ts(c.s2, p11, c.s2, v); w += v;
-  ts(c.s2, p20, c.s2, v); w += v;
+  // a0b2, a1b1, a2b0 with their product errors (level 3) folded in
+  w += ts_prod(c.s2, a.x, b.z);
+  w += ts_prod(c.s2, a.y, b.y);
+  w += ts_prod(c.s2, a.z, b.x);
   // level 3
-  c.s3 = c.s3 + (w + ((e02 + e11) + (e20 + l3)));
+  c.s3 = c.s3 + (w + l3);
 }
 
 // two TwoSum sweeps: bottom-up (the sum gathers in s0), then top-down
