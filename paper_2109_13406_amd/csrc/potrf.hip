@@ -8,16 +8,20 @@
 // writes the factor to A (ld lda).  It works in the "lower view" L(i, l) of
 // the block (L(i, l) = A(i, l) for 'L', A(l, i) for 'U'):
 //
-//   1. right-looking Cholesky of the block in place, column by column:
-//      pivot d = L(c,c); d <= 0 or NaN -> info = offset + c+1 and stop (d
-//      stays in place); L(c,c) = sqrt(d); L(i,c) /= L(c,c); then the
-//      trailing lower triangle L(i,l) -= L(i,c) L(l,c).  The info word is
-//      shared by the blocks of one factorisation: a block that finds it set
-//      returns at once, so only the first failure is recorded;
-//   2. the inverse W = L^-1 (lower triangular, ld jb, zeros above the
-//      diagonal), row by row: W(i,i) = 1 / L(i,i) and, for t < i,
-//      W(i,t) = -(sum_{t<=l<i} L(i,l) W(l,t)) / L(i,i).  The panel solve of
-//      the driver is then a plain dd product with W, on the product kernels.
+//   right-looking Cholesky of the block in place, column by column, with the
+//   inverse W = L^-1 built in the same sweep (W starts as the identity; the
+//   forward elimination of L W = I proceeds in the column order of the
+//   factorisation).  For column c:
+//     A. pivot d = L(c,c); d <= 0 or NaN -> info = offset + c+1 and stop (d
+//        stays in place); p = sqrt(d) (every thread that needs it computes the
+//        same value itself); L(c,c) = p; L(i,c) /= p for i > c; row c of W,
+//        final apart from this step, is divided by p (W(c,c) = 1/p);
+//     B. trailing lower triangle L(i,l) -= L(i,c) L(l,c) for c < l <= i, and
+//        W(i,t) -= L(i,c) W(c,t) for i > c, t <= c.
+//   One barrier after each phase.  The info word is shared by the blocks of
+//   one factorisation: a block that finds it set returns at once, so only the
+//   first failure is recorded.  The panel solve of the driver is then a plain
+//   dd product with W, on the product kernels.
 //
 // One workgroup of 512 threads.  The block's lower triangle and W live in LDS
 // (packed by rows, 4 x 16.6 KB), so each of the O(jb) dependent steps costs
@@ -36,7 +40,6 @@ namespace {
 
 constexpr int POTF2_MAX = 64;       // largest block order
 constexpr int POTF2_THREADS = 512;
-constexpr int POTF2_LANES = 8;      // lanes per column of W in step 2
 constexpr int POTF2_PACK = POTF2_MAX * (POTF2_MAX + 1) / 2;
 
 __device__ __forceinline__ int64_t lv(int upper, int64_t i, int64_t l, int64_t lda) {
@@ -52,79 +55,75 @@ dd_potf2_block(const double* __restrict__ s_hi, const double* __restrict__ s_lo,
                int upper, double* __restrict__ w_hi, double* __restrict__ w_lo,
                long long* __restrict__ info, long long offset) {
   __shared__ double lh[POTF2_PACK], ll[POTF2_PACK], wh[POTF2_PACK], wl[POTF2_PACK];
-  __shared__ int s_fail;
+  // This workgroup is the critical path of the factorisation and shares its
+  // CU with the workgroups of the bulk update running beside it: raise its
+  // waves' issue priority so that their dependent chains are not starved.
+  __builtin_amdgcn_s_setprio(3);
   // an earlier block of this factorisation failed: leave this one alone
   if (*info != 0) return;
   const int tid = threadIdx.x;
-  if (tid == 0) s_fail = 0;
   for (int t = tid; t < jb * jb; t += POTF2_THREADS) {
     const int i = t % jb, l = t / jb;
     if (i < l) continue;
     const int64_t o = lv(upper, i, l, lds);
     lh[pk(i, l)] = s_hi[o];
     ll[pk(i, l)] = s_lo[o];
+    wh[pk(i, l)] = (i == l) ? 1.0 : 0.0;
+    wl[pk(i, l)] = 0.0;
   }
   __syncthreads();
 
-  // 1. right-looking factorisation in LDS
+  int fail = 0;
   for (int c = 0; c < jb; ++c) {
-    if (tid == 0) {
-      const ddv d{lh[pk(c, c)], ll[pk(c, c)]};
-      if (!(d.hi > 0.0)) {
-        s_fail = c + 1;
-      } else {
-        const ddv p = dd_sqrt(d);
-        lh[pk(c, c)] = p.hi;
-        ll[pk(c, c)] = p.lo;
-      }
-    }
-    __syncthreads();
-    if (s_fail) break;
-    const ddv piv{lh[pk(c, c)], ll[pk(c, c)]};
-    for (int i = c + 1 + tid; i < jb; i += POTF2_THREADS) {
-      const ddv q = dd_div(ddv{lh[pk(i, c)], ll[pk(i, c)]}, piv);
-      lh[pk(i, c)] = q.hi;
-      ll[pk(i, c)] = q.lo;
-    }
-    __syncthreads();
     const int m = jb - c - 1;
-    for (int t = tid; t < m * m; t += POTF2_THREADS) {
-      const int i = c + 1 + t % m, l = c + 1 + t / m;
-      if (i < l) continue;
-      const ddv p = dd_mul(ddv{lh[pk(i, c)], ll[pk(i, c)]}, ddv{lh[pk(l, c)], ll[pk(l, c)]});
-      const ddv r = dd_add(ddv{lh[pk(i, l)], ll[pk(i, l)]}, dd_neg(p));
-      lh[pk(i, l)] = r.hi;
-      ll[pk(i, l)] = r.lo;
+    // A. pivot, column c of L, row c of W (m + c + 1 = jb <= 64 items: wave 0).
+    //    L(c,c) itself is overwritten only in phase B, when no thread reads it.
+    const ddv d{lh[pk(c, c)], ll[pk(c, c)]};
+    if (!(d.hi > 0.0)) {            // the same decision in every thread
+      fail = c + 1;
+      break;
+    }
+    ddv piv{0.0, 0.0};
+    if (tid < m + c + 1) {
+      piv = dd_sqrt(d);
+      if (tid < m) {
+        const int i = c + 1 + tid;
+        const ddv q = dd_div(ddv{lh[pk(i, c)], ll[pk(i, c)]}, piv);
+        lh[pk(i, c)] = q.hi;
+        ll[pk(i, c)] = q.lo;
+      } else {
+        const int t = tid - m;      // 0 .. c
+        const ddv q = dd_div(ddv{wh[pk(c, t)], wl[pk(c, t)]}, piv);
+        wh[pk(c, t)] = q.hi;
+        wl[pk(c, t)] = q.lo;
+      }
     }
     __syncthreads();
-  }
-  const int fail = s_fail;
-
-  // 2. W = L^-1, row by row (8 lanes per column, fixed-order butterfly)
-  if (!fail) {
-    const int col = tid / POTF2_LANES, q = tid % POTF2_LANES;
-    for (int i = 0; i < jb; ++i) {
-      if (col < i) {
-        ddv s{0.0, 0.0};
-        for (int l = col + q; l < i; l += POTF2_LANES)
-          s = dd_add(s, dd_mul(ddv{lh[pk(i, l)], ll[pk(i, l)]}, ddv{wh[pk(l, col)], wl[pk(l, col)]}));
-#pragma unroll
-        for (int x = 1; x < POTF2_LANES; x <<= 1) {
-          const ddv o{__shfl_xor(s.hi, x), __shfl_xor(s.lo, x)};
-          s = (q & x) ? dd_add(o, s) : dd_add(s, o);
-        }
-        if (q == 0) {
-          const ddv r = dd_neg(dd_div(s, ddv{lh[pk(i, i)], ll[pk(i, i)]}));
-          wh[pk(i, col)] = r.hi;
-          wl[pk(i, col)] = r.lo;
-        }
-      } else if (col == i && q == 0) {
-        const ddv r = dd_div(ddv{1.0, 0.0}, ddv{lh[pk(i, i)], ll[pk(i, i)]});
-        wh[pk(i, i)] = r.hi;
-        wl[pk(i, i)] = r.lo;
-      }
-      __syncthreads();
+    if (tid == 0) {
+      lh[pk(c, c)] = piv.hi;
+      ll[pk(c, c)] = piv.lo;
     }
+    // B. trailing triangle of L (m * m slots, upper half skipped) and rows
+    //    c+1 .. jb-1 of W in columns 0 .. c
+    const int nl = m * m, nw = m * (c + 1);
+    for (int q = tid; q < nl + nw; q += POTF2_THREADS) {
+      if (q < nl) {
+        const int i = c + 1 + q % m, l = c + 1 + q / m;
+        if (i < l) continue;
+        const ddv p = dd_mul(ddv{lh[pk(i, c)], ll[pk(i, c)]}, ddv{lh[pk(l, c)], ll[pk(l, c)]});
+        const ddv r = dd_add(ddv{lh[pk(i, l)], ll[pk(i, l)]}, dd_neg(p));
+        lh[pk(i, l)] = r.hi;
+        ll[pk(i, l)] = r.lo;
+      } else {
+        const int r0 = q - nl;
+        const int i = c + 1 + r0 % m, t = r0 / m;
+        const ddv p = dd_mul(ddv{lh[pk(i, c)], ll[pk(i, c)]}, ddv{wh[pk(c, t)], wl[pk(c, t)]});
+        const ddv r = dd_add(ddv{wh[pk(i, t)], wl[pk(i, t)]}, dd_neg(p));
+        wh[pk(i, t)] = r.hi;
+        wl[pk(i, t)] = r.lo;
+      }
+    }
+    __syncthreads();
   }
 
   // write back the (partial, on failure) factor, and W with zeros above its diagonal
