@@ -83,12 +83,28 @@ bool handle_ok(mpdd_handle h) { return h != nullptr && h->magic == 0x6d706464; }
 
 // Automatic k-split: enough C tiles to give every CU two workgroups, else
 // split k (keeping >= 256 terms per slice) up to 16 ways.
-int auto_splitk(int64_t tiles, int64_t k, int bk) {
-  const int64_t target = 512;
-  if (tiles >= target) return 1;
+// k-split for a launch of `tiles` output tiles: aim at ~1024 workgroups (four
+// per CU) with k-ranges of >= 256, or for a triangle (whose diagonal tiles do
+// less work) ~2048 workgroups with k-ranges of >= 512.
+int auto_splitk(int64_t tiles, int64_t k, bool tri) {
+  const int64_t target = tri ? 2048 : 1024, min_range = tri ? 512 : 256;
   int s = 1;
-  while (s < 16 && tiles * s < target && k / (2 * s) >= 256 && (k / (2 * s)) % bk == 0) s *= 2;
+  while (s < 32 && tiles * s < target && k / (2 * s) >= min_range) s *= 2;
   return s;
+}
+
+// Tile for a stand-alone call without a tuned entry: 64 x 64 tiles with the
+// cross terms on the matrix cores (entry 4) when, split along k into ranges
+// of >= 512, they give enough workgroups (512; 1024 for a triangle);
+// otherwise 32 x 32 tiles (entry 2), four times the workgroups.  Measured on
+// skinny and small shapes (the block-column updates of Rpotrf: 2048 x 64 x
+// 6080 NT 657 -> 329 us, 7936 x 64 x 192 117 -> 53 us; Rsyrk 2048 x 512:
+// 533 -> 441 us) with no loss on the large ones.
+int choose_tile(int64_t m, int64_t n, int64_t k, bool tri) {
+  const int64_t tm = (m + 63) / 64, tn = (n + 63) / 64;
+  const int64_t tiles = tri ? tm * (tm + 1) / 2 : tm * tn;
+  const int64_t smax = std::min<int64_t>(32, std::max<int64_t>(1, k / 512));
+  return tiles * smax < (tri ? 1024 : 512) ? 2 : 4;
 }
 
 struct Plan {
@@ -108,13 +124,14 @@ Plan choose(const mpdd_handle h, const mpdd_opts* o, int op, bool ta, bool tb, i
       if (pl.splitk == 0) pl.splitk = e.splitk;
     }
   }
-  if (pl.tile < 0) pl.tile = default_tile(m, n, k, square_only);
+  if (pl.tile < 0) pl.tile = choose_tile(m, n, k, square_only);
   if (pl.splitk == 0) {
-    // (a triangle launches only the tiles that meet it)
+    // (a triangle computes only the tiles that meet it)
     const TileInfo* t = tile_info(pl.tile);
+    if (!t) return pl;                     // the caller reports the bad tile
     const int64_t tm = (m + t->bm - 1) / t->bm, tn = (n + t->bn - 1) / t->bn;
     const int64_t tiles = square_only ? tm * (tm + 1) / 2 : tm * tn;
-    pl.splitk = auto_splitk(tiles, k, t->bk);
+    pl.splitk = auto_splitk(tiles, k, square_only);
   }
   return pl;
 }

@@ -61,7 +61,8 @@ int default_tile(int64_t m, int64_t n, int64_t k, bool square_only) {
   (void)k;
   // 64 x 64 tiles with the cross terms on the matrix cores (entry 4) for
   // everything that gives the CUs enough workgroups; small problems use
-  // 32 x 32 tiles (entry 2) so that more CUs get work.
+  // 32 x 32 tiles (entry 2) so that more CUs get work.  (The stand-alone
+  // calls choose with the k-split in view; see choose_tile.)
   const int64_t t64 = ((m + 63) / 64) * ((n + 63) / 64);
   if (t64 < 128 && (square_only || (m <= 1024 && n <= 1024))) return 2;
   return 4;

@@ -240,3 +240,16 @@ def test_syrk_triangle_coverage(h, uplo, n):
                          case["ldc"], tri=uplo, C0=case["C"])
         assert r <= RATIO_MAX
         del G
+
+
+def test_bad_tile_with_automatic_split(h):
+    """An out-of-range tile-table entry is rejected (not dereferenced) also
+    when the k-split is left to the library."""
+    from paper_2109_13406_amd import binding as b
+    case = W.gemm_case(905, "N", "N", 40, 30, 50)
+    for split in (0, 1):
+        info, _ = gemm_gpu(h, case, opts=dict(algo=b.MPDD_PLAIN, tile_id=99, splitk=split))
+        assert info == b.MPDD_ERR_UNSUPPORTED
+    info, _ = syrk_gpu(h, W.syrk_case(906, "U", "N", 40, 50),
+                       opts=dict(algo=b.MPDD_PLAIN, tile_id=99, splitk=0))
+    assert info == b.MPDD_ERR_UNSUPPORTED
