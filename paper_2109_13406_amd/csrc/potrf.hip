@@ -11,17 +11,19 @@
 //   right-looking Cholesky of the block in place, column by column, with the
 //   inverse W = L^-1 built in the same sweep (W starts as the identity; the
 //   forward elimination of L W = I proceeds in the column order of the
-//   factorisation).  For column c:
-//     A. pivot d = L(c,c); d <= 0 or NaN -> info = offset + c+1 and stop (d
-//        stays in place); p = sqrt(d) (every thread that needs it computes the
-//        same value itself); L(c,c) = p; L(i,c) /= p for i > c; row c of W,
-//        final apart from this step, is divided by p (W(c,c) = 1/p);
-//     B. trailing lower triangle L(i,l) -= L(i,c) L(l,c) for c < l <= i, and
-//        W(i,t) -= L(i,c) W(c,t) for i > c, t <= c.
-//   One barrier after each phase.  The info word is shared by the blocks of
-//   one factorisation: a block that finds it set returns at once, so only the
-//   first failure is recorded.  The panel solve of the driver is then a plain
-//   dd product with W, on the product kernels.
+//   factorisation).  Finishing column c means: pivot d = L(c,c) (after the
+//   updates of columns < c); d <= 0 or NaN -> info = offset + c+1 and stop
+//   (d stays in place); p = sqrt(d); L(c,c) = p; L(i,c) /= p for i > c; row
+//   c of W is divided by p (W(c,c) = 1/p).  Column c then updates the
+//   trailing triangle, L(i,l) -= L(i,c) L(l,c) for c < l <= i, and W(i,t) -=
+//   L(i,c) W(c,t) for i > c, t <= c.
+//
+//   Look-ahead, one barrier per column: while waves 1-7 apply column c to the
+//   trailing entries outside column c+1 and row c+1 of W, wave 0 applies it to
+//   column c+1 and row c+1 of W (jb entries, one per lane), takes the updated
+//   pivot from lane 0 by a cross-lane broadcast and finishes column c+1.
+//   Every entry receives the same operations in the same order as in the
+//   plain column sweep.
 //
 // One workgroup of 512 threads.  The block's lower triangle and W live in LDS
 // (packed by rows, 4 x 16.6 KB), so each of the O(jb) dependent steps costs
@@ -73,54 +75,100 @@ dd_potf2_block(const double* __restrict__ s_hi, const double* __restrict__ s_lo,
   }
   __syncthreads();
 
+  const int lane = tid & 63;
+  // finish column 0 (wave 0); a failing pivot is left in place
+  if (tid < 64) {
+    const ddv d{lh[0], ll[0]};
+    if (d.hi > 0.0) {
+      const ddv piv = dd_sqrt(d);
+      if (lane >= 1 && lane < jb) {
+        const ddv q = dd_div(ddv{lh[pk(lane, 0)], ll[pk(lane, 0)]}, piv);
+        lh[pk(lane, 0)] = q.hi;
+        ll[pk(lane, 0)] = q.lo;
+      } else if (lane == 0) {
+        const ddv w = dd_div(ddv{1.0, 0.0}, piv);
+        wh[0] = w.hi;
+        wl[0] = w.lo;
+        lh[0] = piv.hi;
+        ll[0] = piv.lo;
+      }
+    }
+  }
+  __syncthreads();
+
   int fail = 0;
   for (int c = 0; c < jb; ++c) {
-    const int m = jb - c - 1;
-    // A. pivot, column c of L, row c of W (m + c + 1 = jb <= 64 items: wave 0).
-    //    L(c,c) itself is overwritten only in phase B, when no thread reads it.
-    const ddv d{lh[pk(c, c)], ll[pk(c, c)]};
-    if (!(d.hi > 0.0)) {            // the same decision in every thread
+    // column c is finished unless its pivot failed (nobody writes L(c,c)
+    // during this step, so every thread takes the same decision)
+    if (!(lh[pk(c, c)] > 0.0)) {
       fail = c + 1;
       break;
     }
-    ddv piv{0.0, 0.0};
-    if (tid < m + c + 1) {
-      piv = dd_sqrt(d);
-      if (tid < m) {
-        const int i = c + 1 + tid;
-        const ddv q = dd_div(ddv{lh[pk(i, c)], ll[pk(i, c)]}, piv);
-        lh[pk(i, c)] = q.hi;
-        ll[pk(i, c)] = q.lo;
-      } else {
-        const int t = tid - m;      // 0 .. c
-        const ddv q = dd_div(ddv{wh[pk(c, t)], wl[pk(c, t)]}, piv);
-        wh[pk(c, t)] = q.hi;
-        wl[pk(c, t)] = q.lo;
+    const int m = jb - c - 1;           // rows below the pivot
+    if (tid < 64) {
+      if (m > 0) {
+        // column c+1 (lanes 0 .. m-1: rows c+1 .. jb-1; lane 0 holds the
+        // pivot) and row c+1 of W (lanes m .. m+c: columns 0 .. c)
+        const ddv lc1{lh[pk(c + 1, c)], ll[pk(c + 1, c)]};      // L(c+1, c)
+        int o = 0;
+        bool in_w = false, active = lane < m + c + 1;
+        ddv z{0.0, 0.0};
+        if (lane < m) {
+          const int i = c + 1 + lane;
+          o = pk(i, c + 1);
+          z = dd_add(ddv{lh[o], ll[o]}, dd_neg(dd_mul(ddv{lh[pk(i, c)], ll[pk(i, c)]}, lc1)));
+        } else if (active) {
+          const int t = lane - m;
+          o = pk(c + 1, t);
+          in_w = true;
+          z = dd_add(ddv{wh[o], wl[o]}, dd_neg(dd_mul(lc1, ddv{wh[pk(c, t)], wl[pk(c, t)]})));
+        }
+        // the updated pivot, from lane 0 to the whole wave
+        const ddv d{__shfl(z.hi, 0), __shfl(z.lo, 0)};
+        if (d.hi > 0.0) {
+          const ddv piv = dd_sqrt(d);
+          if (lane == 0) {
+            const ddv w = dd_div(ddv{1.0, 0.0}, piv);     // W(c+1,c+1) = 1 / p
+            wh[pk(c + 1, c + 1)] = w.hi;
+            wl[pk(c + 1, c + 1)] = w.lo;
+            z = piv;
+          } else if (active) {
+            z = dd_div(z, piv);
+          }
+        }
+        if (active) {
+          if (in_w) {
+            wh[o] = z.hi;
+            wl[o] = z.lo;
+          } else {
+            lh[o] = z.hi;
+            ll[o] = z.lo;
+          }
+        }
       }
-    }
-    __syncthreads();
-    if (tid == 0) {
-      lh[pk(c, c)] = piv.hi;
-      ll[pk(c, c)] = piv.lo;
-    }
-    // B. trailing triangle of L (m * m slots, upper half skipped) and rows
-    //    c+1 .. jb-1 of W in columns 0 .. c
-    const int nl = m * m, nw = m * (c + 1);
-    for (int q = tid; q < nl + nw; q += POTF2_THREADS) {
-      if (q < nl) {
-        const int i = c + 1 + q % m, l = c + 1 + q / m;
-        if (i < l) continue;
-        const ddv p = dd_mul(ddv{lh[pk(i, c)], ll[pk(i, c)]}, ddv{lh[pk(l, c)], ll[pk(l, c)]});
-        const ddv r = dd_add(ddv{lh[pk(i, l)], ll[pk(i, l)]}, dd_neg(p));
-        lh[pk(i, l)] = r.hi;
-        ll[pk(i, l)] = r.lo;
-      } else {
-        const int r0 = q - nl;
-        const int i = c + 1 + r0 % m, t = r0 / m;
-        const ddv p = dd_mul(ddv{lh[pk(i, c)], ll[pk(i, c)]}, ddv{wh[pk(c, t)], wl[pk(c, t)]});
-        const ddv r = dd_add(ddv{wh[pk(i, t)], wl[pk(i, t)]}, dd_neg(p));
-        wh[pk(i, t)] = r.hi;
-        wl[pk(i, t)] = r.lo;
+    } else if (m > 1) {
+      // the rest of column c's update: L(i,l), c+2 <= l <= i (packed row by
+      // row), then W(i,t), i >= c+2, t <= c
+      const int m2 = m - 1;
+      const int nl = m2 * (m2 + 1) / 2, nw = m2 * (c + 1);
+      for (int q = tid - 64; q < nl + nw; q += POTF2_THREADS - 64) {
+        if (q < nl) {
+          int r = (int)((__builtin_sqrtf(8.0f * (float)q + 1.0f) - 1.0f) * 0.5f);
+          if ((r + 1) * (r + 2) / 2 <= q) ++r;
+          if (r * (r + 1) / 2 > q) --r;
+          const int i = c + 2 + r, l = c + 2 + (q - r * (r + 1) / 2);
+          const ddv p = dd_mul(ddv{lh[pk(i, c)], ll[pk(i, c)]}, ddv{lh[pk(l, c)], ll[pk(l, c)]});
+          const ddv v = dd_add(ddv{lh[pk(i, l)], ll[pk(i, l)]}, dd_neg(p));
+          lh[pk(i, l)] = v.hi;
+          ll[pk(i, l)] = v.lo;
+        } else {
+          const int r0 = q - nl;
+          const int i = c + 2 + r0 % m2, t = r0 / m2;
+          const ddv p = dd_mul(ddv{lh[pk(i, c)], ll[pk(i, c)]}, ddv{wh[pk(c, t)], wl[pk(c, t)]});
+          const ddv v = dd_add(ddv{wh[pk(i, t)], wl[pk(i, t)]}, dd_neg(p));
+          wh[pk(i, t)] = v.hi;
+          wl[pk(i, t)] = v.lo;
+        }
       }
     }
     __syncthreads();
