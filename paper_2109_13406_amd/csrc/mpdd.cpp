@@ -81,8 +81,6 @@ int hip_status(hipError_t e) { return e == hipSuccess ? 0 : MPDD_ERR_HIP; }
 
 bool handle_ok(mpdd_handle h) { return h != nullptr && h->magic == 0x6d706464; }
 
-// Automatic k-split: enough C tiles to give every CU two workgroups, else
-// split k (keeping >= 256 terms per slice) up to 16 ways.
 // k-split for a launch of `tiles` output tiles: aim at ~1024 workgroups (four
 // per CU) with k-ranges of >= 256, or for a triangle (whose diagonal tiles do
 // less work) ~2048 workgroups with k-ranges of >= 512.
@@ -490,23 +488,32 @@ int mpdd_Rpotrf_nb(mpdd_handle h, const char* uplo, mpdd_int n, double* A_hi, do
   if (n == 0) return 0;
   if (!A_hi || !A_lo) return MPDD_ERR_ARG;
   hipStream_t st = (hipStream_t)stream;
-  hipStream_t sb = nullptr;                       // bulk-update stream
-  hipEvent_t ev_bulk[2] = {nullptr, nullptr}, ev_done[2] = {nullptr, nullptr};
-  hipEvent_t ev_start = nullptr, ev_end = nullptr;
-  bool ok = hipStreamCreateWithFlags(&sb, hipStreamNonBlocking) == hipSuccess;
+  // Bulk updates alternate between two streams, so that one block's bulk
+  // product can start while the previous block's is still running; block b
+  // keeps its column in P[b % NP], so the bulk update of block b may start as
+  // soon as block b-2 is finished while blocks b-1 and b-2 still hold theirs.
+  constexpr int NP = 3;
+  hipStream_t sb[2] = {nullptr, nullptr};
+  hipEvent_t ev_bulk[NP] = {}, ev_done[NP] = {};
+  hipEvent_t ev_start = nullptr, ev_end[2] = {nullptr, nullptr};
+  auto make_event = [](hipEvent_t& e) {
+    return hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess;
+  };
+  bool ok = true;
   for (int t = 0; t < 2 && ok; ++t)
-    ok = hipEventCreateWithFlags(&ev_bulk[t], hipEventDisableTiming) == hipSuccess &&
-         hipEventCreateWithFlags(&ev_done[t], hipEventDisableTiming) == hipSuccess;
-  ok = ok && hipEventCreateWithFlags(&ev_start, hipEventDisableTiming) == hipSuccess &&
-       hipEventCreateWithFlags(&ev_end, hipEventDisableTiming) == hipSuccess;
+    ok = hipStreamCreateWithFlags(&sb[t], hipStreamNonBlocking) == hipSuccess;
+  for (int t = 0; t < NP && ok; ++t) ok = make_event(ev_bulk[t]) && make_event(ev_done[t]);
+  ok = ok && make_event(ev_start) && make_event(ev_end[0]) && make_event(ev_end[1]);
   auto release = [&]() {
-    for (int t = 0; t < 2; ++t) {
+    for (int t = 0; t < NP; ++t) {
       if (ev_bulk[t]) (void)hipEventDestroy(ev_bulk[t]);
       if (ev_done[t]) (void)hipEventDestroy(ev_done[t]);
     }
     if (ev_start) (void)hipEventDestroy(ev_start);
-    if (ev_end) (void)hipEventDestroy(ev_end);
-    if (sb) (void)hipStreamDestroy(sb);
+    for (int t = 0; t < 2; ++t) {
+      if (ev_end[t]) (void)hipEventDestroy(ev_end[t]);
+      if (sb[t]) (void)hipStreamDestroy(sb[t]);
+    }
   };
   if (!ok) {
     release();
@@ -515,18 +522,24 @@ int mpdd_Rpotrf_nb(mpdd_handle h, const char* uplo, mpdd_int n, double* A_hi, do
   const size_t wb = (size_t)nb * nb * sizeof(double);
   const size_t pb = (size_t)n * nb * sizeof(double);
   void* ws = nullptr;
-  if (hipMallocAsync(&ws, 2 * wb + 4 * pb + 256, st) != hipSuccess) {
+  if (hipMallocAsync(&ws, 2 * wb + 2 * NP * pb + 256, st) != hipSuccess) {
     release();
     return MPDD_ERR_ALLOC;
   }
   double* w_hi = (double*)ws;
   double* w_lo = (double*)((char*)ws + wb);
-  double* p_hi[2] = {(double*)((char*)ws + 2 * wb), (double*)((char*)ws + 2 * wb + 2 * pb)};
-  double* p_lo[2] = {(double*)((char*)ws + 2 * wb + pb), (double*)((char*)ws + 2 * wb + 3 * pb)};
-  long long* d_info = (long long*)((char*)ws + 2 * wb + 4 * pb);
+  double* p_hi[NP];
+  double* p_lo[NP];
+  for (int t = 0; t < NP; ++t) {
+    p_hi[t] = (double*)((char*)ws + 2 * wb + 2 * t * pb);
+    p_lo[t] = (double*)((char*)ws + 2 * wb + (2 * t + 1) * pb);
+  }
+  long long* d_info = (long long*)((char*)ws + 2 * wb + 2 * NP * pb);
   int rc = 0;
   if (hipMemsetAsync(d_info, 0, sizeof(long long), st) != hipSuccess ||
-      hipEventRecord(ev_start, st) != hipSuccess || hipStreamWaitEvent(sb, ev_start, 0) != hipSuccess)
+      hipEventRecord(ev_start, st) != hipSuccess ||
+      hipStreamWaitEvent(sb[0], ev_start, 0) != hipSuccess ||
+      hipStreamWaitEvent(sb[1], ev_start, 0) != hipSuccess)
     rc = MPDD_ERR_HIP;
   constexpr int64_t POTRF_CHECK = 16;   // blocks between host reads of the failure word
   long long hinfo = 0;
@@ -536,13 +549,13 @@ int mpdd_Rpotrf_nb(mpdd_handle h, const char* uplo, mpdd_int n, double* A_hi, do
   mpdd_opts small{MPDD_PLAIN, 0, 2, 1};
   auto at = [&](double* base, int64_t i, int64_t j) { return base + i + j * lda; };
   const int64_t nblk = (n + nb - 1) / nb;
-  // copy block column b into P[b & 1] on stream s
+  // copy block column b into P[b % NP] on stream s
   auto load_block = [&](int64_t b, hipStream_t s) -> int {
     const int64_t j = b * nb, jb = std::min<int64_t>(nb, n - j), rows = n - j;
     const int64_t ldp = upper ? jb : rows;
     const int64_t w = upper ? jb : rows, hgt = upper ? rows : jb;
     for (int t = 0; t < 2; ++t) {
-      double* dst = t ? p_lo[b & 1] : p_hi[b & 1];
+      double* dst = t ? p_lo[b % NP] : p_hi[b % NP];
       const double* src = t ? at(A_lo, j, j) : at(A_hi, j, j);
       if (hipMemcpy2DAsync(dst, ldp * sizeof(double), src, lda * sizeof(double),
                            w * sizeof(double), hgt, hipMemcpyDeviceToDevice, s) != hipSuccess)
@@ -550,12 +563,12 @@ int mpdd_Rpotrf_nb(mpdd_handle h, const char* uplo, mpdd_int n, double* A_hi, do
     }
     return 0;
   };
-  // P[b & 1] -= contributions of block columns [c0, c1) (c1 > c0) on stream s
+  // P[b % NP] -= contributions of block columns [c0, c1) (c1 > c0) on stream s
   auto update_block = [&](int64_t b, int64_t c0, int64_t c1, hipStream_t s) -> int {
     const int64_t j = b * nb, jb = std::min<int64_t>(nb, n - j), rows = n - j;
     const int64_t k0 = c0 * nb, kk = c1 * nb - k0;
-    double* ph = p_hi[b & 1];
-    double* pl = p_lo[b & 1];
+    double* ph = p_hi[b % NP];
+    double* pl = p_lo[b % NP];
     if (!upper)
       return run_plain(h, nullptr, false, true, 0, rows, jb, kk, mone, at(A_hi, j, k0),
                        at(A_lo, j, k0), lda, at(A_hi, j, k0), at(A_lo, j, k0), lda, one, ph, pl,
@@ -564,12 +577,16 @@ int mpdd_Rpotrf_nb(mpdd_handle h, const char* uplo, mpdd_int n, double* A_hi, do
                      at(A_lo, k0, j), lda, at(A_hi, k0, j), at(A_lo, k0, j), lda, one, ph, pl, jb,
                      s);
   };
-  // bulk stream, block t: load P_t and apply block columns [0, t-1)
+  // bulk stream t & 1, block t: load P_t and apply block columns [0, t-1),
+  // once block t-2 is finished (which also frees P[t % NP], last used by
+  // block t-3)
   auto bulk = [&](int64_t t) -> int {
-    if (t >= 2 && hipStreamWaitEvent(sb, ev_done[t & 1], 0) != hipSuccess) return MPDD_ERR_HIP;
-    int r = load_block(t, sb);
-    if (!r && t >= 2) r = update_block(t, 0, t - 1, sb);
-    if (!r && hipEventRecord(ev_bulk[t & 1], sb) != hipSuccess) r = MPDD_ERR_HIP;
+    hipStream_t s = sb[t & 1];
+    if (t >= 2 && hipStreamWaitEvent(s, ev_done[(t - 2) % NP], 0) != hipSuccess)
+      return MPDD_ERR_HIP;
+    int r = load_block(t, s);
+    if (!r && t >= 2) r = update_block(t, 0, t - 1, s);
+    if (!r && hipEventRecord(ev_bulk[t % NP], s) != hipSuccess) r = MPDD_ERR_HIP;
     return r;
   };
   if (!rc) rc = bulk(0);
@@ -578,12 +595,12 @@ int mpdd_Rpotrf_nb(mpdd_handle h, const char* uplo, mpdd_int n, double* A_hi, do
     const int64_t j = b * nb, jb = std::min<int64_t>(nb, n - j), rows = n - j;
     const int64_t ldp = upper ? jb : rows;
     // critical path of block b on the caller's stream
-    if (hipStreamWaitEvent(st, ev_bulk[b & 1], 0) != hipSuccess) {
+    if (hipStreamWaitEvent(st, ev_bulk[b % NP], 0) != hipSuccess) {
       rc = MPDD_ERR_HIP;
       break;
     }
     if (b >= 1 && (rc = update_block(b, b - 1, b, st)) != 0) break;
-    if (launch_potf2_block(p_hi[b & 1], p_lo[b & 1], ldp, at(A_hi, j, j), at(A_lo, j, j), lda,
+    if (launch_potf2_block(p_hi[b % NP], p_lo[b % NP], ldp, at(A_hi, j, j), at(A_lo, j, j), lda,
                            (int)jb, upper ? 1 : 0, w_hi, w_lo, d_info, (long long)j,
                            st) != hipSuccess) {
       rc = MPDD_ERR_HIP;
@@ -593,17 +610,17 @@ int mpdd_Rpotrf_nb(mpdd_handle h, const char* uplo, mpdd_int n, double* A_hi, do
       // panel solve: lower A(j+jb:n, j:j+jb) = P(jb:, :) W^T; upper
       // A(j:j+jb, j+jb:n) = W P(:, jb:)   (W = U^-T in the lower view)
       if (!upper)
-        rc = run_plain(h, &small, false, true, 0, rows - jb, jb, jb, one, p_hi[b & 1] + jb,
-                       p_lo[b & 1] + jb, ldp, w_hi, w_lo, jb, zero, at(A_hi, j + jb, j),
+        rc = run_plain(h, &small, false, true, 0, rows - jb, jb, jb, one, p_hi[b % NP] + jb,
+                       p_lo[b % NP] + jb, ldp, w_hi, w_lo, jb, zero, at(A_hi, j + jb, j),
                        at(A_lo, j + jb, j), lda, st);
       else
         rc = run_plain(h, &small, false, false, 0, jb, rows - jb, jb, one, w_hi, w_lo, jb,
-                       p_hi[b & 1] + jb * jb, p_lo[b & 1] + jb * jb, ldp, zero,
+                       p_hi[b % NP] + jb * jb, p_lo[b % NP] + jb * jb, ldp, zero,
                        at(A_hi, j, j + jb), at(A_lo, j, j + jb), lda, st);
       if (rc) break;
     }
-    // block b finished: block b+2's bulk update may start (it reuses P[b & 1])
-    if (hipEventRecord(ev_done[b & 1], st) != hipSuccess) {
+    // block b finished: block b+2's bulk update may start
+    if (hipEventRecord(ev_done[b % NP], st) != hipSuccess) {
       rc = MPDD_ERR_HIP;
       break;
     }
@@ -619,16 +636,19 @@ int mpdd_Rpotrf_nb(mpdd_handle h, const char* uplo, mpdd_int n, double* A_hi, do
       if (hinfo) break;
     }
   }
-  // the caller's stream waits for the bulk stream before the scratch is freed
-  const bool joined = hipEventRecord(ev_end, sb) == hipSuccess &&
-                      hipStreamWaitEvent(st, ev_end, 0) == hipSuccess;
+  // the caller's stream waits for the bulk streams before the scratch is freed
+  bool joined = true;
+  for (int t = 0; t < 2; ++t)
+    joined = joined && hipEventRecord(ev_end[t], sb[t]) == hipSuccess &&
+             hipStreamWaitEvent(st, ev_end[t], 0) == hipSuccess;
   if (!rc && !joined) rc = MPDD_ERR_HIP;
   if (!rc && !hinfo &&
       (hipMemcpyAsync(&hinfo, d_info, sizeof(long long), hipMemcpyDeviceToHost, st) !=
            hipSuccess ||
        hipStreamSynchronize(st) != hipSuccess))
     rc = MPDD_ERR_HIP;
-  if (!joined) (void)hipStreamSynchronize(sb);
+  if (!joined)
+    for (int t = 0; t < 2; ++t) (void)hipStreamSynchronize(sb[t]);
   const hipError_t ef = hipFreeAsync(ws, st);
   const hipError_t es = hipStreamSynchronize(st);
   release();
