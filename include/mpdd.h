@@ -236,14 +236,15 @@ int mpdd_Qgemm(mpdd_handle h, const char *transa, const char *transb, mpdd_int m
  * columns are unspecified.  The return value is 0 or MPDD_ERR_* (library /
  * runtime errors only).
  *
- * Blocked: per diagonal block of order nb, one Rgemm updates a copy of the
- * block column, a one-workgroup kernel factors the diagonal block and
+ * Blocked: per diagonal block of order nb, Rgemm calls update a copy of the
+ * block column (the bulk of them on two internal streams that overlap the
+ * work on `stream`), a one-workgroup kernel factors the diagonal block and
  * inverts its factor, and the rest of the block column is multiplied by the
  * inverted block.  The call reads the failure word back to the host every 16
  * blocks and at the end, so it is synchronous: it returns when A is factored
- * (or a failing pivot has been found).  Device scratch of 16*nb*(nb + n) + 256
- * bytes is allocated and freed inside the call (stream ordered on
- * `stream`). */
+ * (or a failing pivot has been found).  Device scratch of 16*nb*(nb + 3n) +
+ * 256 bytes, plus the k-split partial sums of the update products, is
+ * allocated and freed inside the call (stream ordered). */
 int mpdd_Rpotrf(mpdd_handle h, const char *uplo, mpdd_int n, double *A_hi, double *A_lo,
                 mpdd_int lda, mpdd_int *info, void *stream);
 

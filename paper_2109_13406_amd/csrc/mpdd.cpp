@@ -462,12 +462,12 @@ int mpdd_Cgemm(mpdd_handle h, const char* transa, const char* transb, mpdd_int m
 // Block b (columns j = b*nb .. j+jb; 'L' shown, 'U' is the transpose) needs
 // its block column A(j:n, j:j+jb), copied to a scratch P_b, minus the
 // contributions of every factored block column c < b.  Those are applied in
-// two products: all c < b-1 at once (the bulk, on a second stream, started as
-// soon as block b-2 is finished, so it overlaps the critical work of block
-// b-1), then c = b-1 alone (k = nb, on the caller's stream).  Then the block
-// kernel factors P_b's diagonal block into A and inverts the factor (W), and
-// the rest of P_b is multiplied by W^T into A.  P is double buffered; events
-// order the two streams.  The diagonal block rides along in every product
+// two products: all c < b-1 at once (the bulk, on one of two bulk streams,
+// started as soon as block b-2 is finished, so it overlaps the critical work
+// of block b-1), then c = b-1 alone (k = nb, on the caller's stream).  Then
+// the block kernel factors P_b's diagonal block into A and inverts the factor
+// (W), and the rest of P_b is multiplied by W^T into A.  P has three buffers;
+// events order the three streams.  The diagonal block rides along in every product
 // (both of its triangles computed in P), so A's opposite triangle is never
 // written.  The first failing pivot is recorded in a device word that later
 // block kernels respect (they return at once); the host reads it every
