@@ -91,20 +91,6 @@ int auto_splitk(int64_t tiles, int64_t k, bool tri) {
   return s;
 }
 
-// Tile for a stand-alone call without a tuned entry: 64 x 64 tiles with the
-// cross terms on the matrix cores (entry 4) when, split along k into ranges
-// of >= 512, they give enough workgroups (512; 1024 for a triangle);
-// otherwise 32 x 32 tiles (entry 2), four times the workgroups.  Measured on
-// skinny and small shapes (the block-column updates of Rpotrf: 2048 x 64 x
-// 6080 NT 657 -> 329 us, 7936 x 64 x 192 117 -> 53 us; Rsyrk 2048 x 512:
-// 533 -> 441 us) with no loss on the large ones.
-int choose_tile(int64_t m, int64_t n, int64_t k, bool tri) {
-  const int64_t tm = (m + 63) / 64, tn = (n + 63) / 64;
-  const int64_t tiles = tri ? tm * (tm + 1) / 2 : tm * tn;
-  const int64_t smax = std::min<int64_t>(32, std::max<int64_t>(1, k / 512));
-  return tiles * smax < (tri ? 1024 : 512) ? 2 : 4;
-}
-
 struct Plan {
   int tile;
   int splitk;
@@ -122,7 +108,7 @@ Plan choose(const mpdd_handle h, const mpdd_opts* o, int op, bool ta, bool tb, i
       if (pl.splitk == 0) pl.splitk = e.splitk;
     }
   }
-  if (pl.tile < 0) pl.tile = choose_tile(m, n, k, square_only);
+  if (pl.tile < 0) pl.tile = default_tile(m, n, k, square_only);
   if (pl.splitk == 0) {
     // (a triangle computes only the tiles that meet it)
     const TileInfo* t = tile_info(pl.tile);

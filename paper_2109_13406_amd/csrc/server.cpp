@@ -204,7 +204,7 @@ int serve_tile_index(mpdd_server_s* s, const mpdd_request& r) {
     const bool tb = syrk ? !ta : !lsame(r.flag2, 'N');
     if (handle_tune_lookup(s->h, syrk ? 1 : 0, ta, tb, m, n, k, e)) tile = e.tile;
   }
-  if (tile < 0) tile = default_tile(m, n, k, true);
+  if (tile < 0) tile = default_tile(m, n, k, r.op == MPDD_OP_SYRK);
   for (int i = 0; i < kNumServeTiles; ++i)
     if (kServeTiles[i] == tile) return i;
   // not a grouped shape: small tiles for small C, else the large ones

@@ -31,8 +31,9 @@ class TuneTable {
   std::map<Key, TuneEntry> map_;
 };
 
-// Built-in choice from the tile table when the tuner has no entry.
-int default_tile(int64_t m, int64_t n, int64_t k, bool square_only);
+// Built-in choice from the tile table when the tuner has no entry (tri: the
+// product is a triangle, of which only the tiles meeting it are computed).
+int default_tile(int64_t m, int64_t n, int64_t k, bool tri);
 
 }  // namespace mpdd
 
