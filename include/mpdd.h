@@ -108,9 +108,14 @@ int mpdd_Rsyrk(mpdd_handle h, const char *uplo, const char *trans, mpdd_int n, m
  * complete (synchronous).  Same info codes and BLAS semantics as the device
  * calls; the whole of C (ldc x n) is copied both ways, so padding rows and
  * (Rsyrk) the opposite triangle come back unchanged.  Scratch device memory
- * is allocated and freed inside the call.  Rgemm works on up to 8 column
- * chunks of B and C (at least 512 columns each): the copies of one chunk
- * overlap the product of the previous one on a second stream. */
+ * is allocated and freed inside the call.  Copies go through a ring of four
+ * 16 MiB pinned host buffers and three copy threads owned by the handle
+ * (created by its first host-pointer call, released by mpdd_destroy); the
+ * host-pointer calls on one handle are serialised.  Rgemm works on up to 8
+ * column chunks of B and C (at least 512 columns each): the copies of one
+ * chunk overlap the product of the previous one on a second stream, and
+ * with transa = 'N' and k >= 1024 the first chunk is multiplied in k-slices
+ * as the matching columns of A arrive (its C accumulated over the slices). */
 int mpdd_Rgemm_host(mpdd_handle h, const char *transa, const char *transb, mpdd_int m,
                     mpdd_int n, mpdd_int k, mpdd_dd alpha, const mpdd_dd *A, mpdd_int lda,
                     const mpdd_dd *B, mpdd_int ldb, mpdd_dd beta, mpdd_dd *C, mpdd_int ldc);
@@ -120,7 +125,7 @@ int mpdd_Rsyrk_host(mpdd_handle h, const char *uplo, const char *trans, mpdd_int
 
 /* ---- explicit algorithm and tile choice ------------------------------------ */
 
-#define MPDD_PLAIN 0          /* lean dd multiply-accumulate (12 binary64 ops per
+#define MPDD_PLAIN 0          /* lean dd multiply-accumulate (10 binary64 ops per
                                  term; tile entry 4 runs 2 of them, the cross
                                  terms, on the FP64 matrix cores) */
 #define MPDD_OZAKI_I8 1       /* split form, INT8 slices on the INT8 matrix cores */

@@ -25,7 +25,12 @@ struct mpdd_handle_s {
   int device = 0;
   int magic = 0x6d706464;
   TuneTable tune;
+  std::mutex host_mu;           // serialises the host-pointer calls on this handle
+  HostStager* stager = nullptr; // their pinned staging (created on first use)
 };
+
+std::mutex* handle_host_mutex(mpdd_handle_s* h) { return &h->host_mu; }
+HostStager** handle_stager(mpdd_handle_s* h) { return &h->stager; }
 
 bool handle_valid(const mpdd_handle_s* h) { return h != nullptr && h->magic == 0x6d706464; }
 
@@ -255,6 +260,7 @@ int mpdd_create(mpdd_handle* h, const char* tuner_cache_path) {
 int mpdd_destroy(mpdd_handle h) {
   if (!handle_ok(h)) return MPDD_ERR_HANDLE;
   h->magic = 0;
+  destroy_stager(h->stager);
   delete h;
   return 0;
 }

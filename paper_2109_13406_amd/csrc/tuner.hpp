@@ -5,6 +5,7 @@
 #pragma once
 #include <cstdint>
 #include <map>
+#include <mutex>
 #include <tuple>
 
 namespace mpdd {
@@ -38,6 +39,13 @@ int default_tile(int64_t m, int64_t n, int64_t k, bool tri);
 }  // namespace mpdd
 
 struct mpdd_handle_s;
+
+namespace mpdd { class HostStager; }
+// The pinned staging of the host-pointer calls (host_api.cpp), owned by the
+// handle: its lock, its stager slot, and its destruction with the handle.
+std::mutex* handle_host_mutex(mpdd_handle_s* h);
+mpdd::HostStager** handle_stager(mpdd_handle_s* h);
+void destroy_stager(mpdd::HostStager* st);
 // Handle accessors for other translation units (mpdd.cpp owns the struct).
 bool handle_valid(const mpdd_handle_s* h);
 int handle_device(const mpdd_handle_s* h);

@@ -74,9 +74,10 @@ def test_rgemm_host_vs_oracle(h, op):
 @pytest.mark.parametrize("op", W.OPS)
 def test_rgemm_host_chunked(h, op):
     """Wide C: several column chunks (ragged last chunk) whose copies overlap
-    the products of the chunks before them."""
+    the products of the chunks before them; with k >= 1024 and op(A) = A the
+    first chunk is multiplied in k-slices as A's columns arrive."""
     from paper_2109_13406_amd import binding as b
-    for (m, n, k) in [(40, 4100, 50), (33, 1500, 70)]:
+    for (m, n, k) in [(40, 4100, 50), (33, 1500, 70), (300, 1100, 2100)]:
         case = W.gemm_case(1700 + n, op[0], op[1], m, n, k, dist="wide")
         O = (case["C"][0].copy(), case["C"][1].copy())
         assert oracle.rgemm(op[0], op[1], m, n, k, case["alpha"], case["A"], case["lda"],
@@ -117,6 +118,57 @@ def test_rsyrk_host_vs_oracle(h, uplo, trans):
     rest[idx] = False
     assert np.array_equal(bits(G[0])[rest], bits(case["C"][0])[rest])
     assert np.array_equal(bits(G[1])[rest], bits(case["C"][1])[rest])
+
+
+@pytest.mark.parametrize("op", ["NN", "TN"])
+def test_rgemm_host_staged_pieces(h, op):
+    """Operands larger than one pinned staging buffer (16 MiB): A and each
+    column chunk of C travel in several pieces through the ring, up and
+    down; two handles in turn, and a second call that reuses the ring."""
+    from paper_2109_13406_amd import binding as b
+    m, n, k = 2100, 1100, 800
+    case = W.gemm_case(1800, op[0], op[1], m, n, k, dist="wide")
+    assert case["C"][0].size * 16 > 2 * (16 << 20)
+    O = (case["C"][0].copy(), case["C"][1].copy())
+    assert oracle.rgemm(op[0], op[1], m, n, k, case["alpha"], case["A"], case["lda"],
+                        case["B"], case["ldb"], case["beta"], O, case["ldc"]) == 0
+    i, j = np.meshgrid(np.arange(m), np.arange(n), indexing="ij")
+    idx = (i + j * case["ldc"]).ravel()
+    rest = np.ones(O[0].shape[0], bool)
+    rest[idx] = False
+    h2 = b.mpdd_create()
+    try:
+        for handle in (h, h2, h):
+            C = pairs(case["C"])
+            assert b.mpdd_Rgemm_host(handle, op[0], op[1], m, n, k, case["alpha"],
+                                     pairs(case["A"]), case["lda"], pairs(case["B"]),
+                                     case["ldb"], case["beta"], C, case["ldc"]) == 0
+            G = planes(C)
+            r = ratio(G[0][idx], G[1][idx], O[0][idx], O[1][idx], k)
+            assert r <= RATIO_MAX, (op, r)
+            assert np.array_equal(bits(G[0])[rest], bits(case["C"][0])[rest])
+    finally:
+        b.mpdd_destroy(h2)
+    log(f"PARITY host-pointer Rgemm {op} {m}x{n}x{k} through the pinned ring ok")
+
+
+def test_rsyrk_host_staged_pieces(h):
+    from paper_2109_13406_amd import binding as b
+    n, k = 1100, 1100
+    case = W.syrk_case(1810, "L", "N", n, k, dist="wide")
+    O = (case["C"][0].copy(), case["C"][1].copy())
+    assert oracle.rsyrk("L", "N", n, k, case["alpha"], case["A"], case["lda"], case["beta"], O,
+                        case["ldc"]) == 0
+    C = pairs(case["C"])
+    assert b.mpdd_Rsyrk_host(h, "L", "N", n, k, case["alpha"], pairs(case["A"]), case["lda"],
+                             case["beta"], C, case["ldc"]) == 0
+    G = planes(C)
+    i, j = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    idx = (i + j * case["ldc"])[i >= j]
+    assert ratio(G[0][idx], G[1][idx], O[0][idx], O[1][idx], k) <= RATIO_MAX
+    rest = np.ones(G[0].shape[0], bool)
+    rest[idx] = False
+    assert np.array_equal(bits(G[0])[rest], bits(case["C"][0])[rest])
 
 
 def test_host_info_codes(h):
