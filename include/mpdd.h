@@ -47,10 +47,12 @@
  * Ownership and asynchrony.  The caller owns A, B and C; they must stay valid
  * until the work enqueued on `stream` has completed.  `stream` is a
  * hipStream_t passed as void* (NULL = the legacy default stream).  The handle
- * owns only host state (tuning table); scratch memory that a call needs
- * (split-k partial sums, split-form slices) is allocated stream-ordered on
- * the call's stream and released on it.  Calls on one handle may be made from
- * several host threads and streams at once.
+ * belongs to the device current at mpdd_create and owns a tuning table and a
+ * stream-ordered memory pool on that device: scratch memory that a call
+ * needs (split-k partial sums, split-form slices, ...) is allocated from the
+ * pool on the call's stream and released on it; the pool keeps released
+ * memory for later calls (it holds its peak size until mpdd_destroy).  Calls
+ * on one handle may be made from several host threads and streams at once.
  */
 #ifndef MPDD_H
 #define MPDD_H

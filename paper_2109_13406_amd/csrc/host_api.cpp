@@ -194,11 +194,11 @@ struct Staged {
   size_t n = 0;
 };
 
-int stage_alloc(Staged& s, size_t elems, hipStream_t st) {
+int stage_alloc(Staged& s, size_t elems, hipStream_t st, hipMemPool_t pool) {
   s.n = elems;
   if (elems == 0) return 0;
   const size_t bytes = elems * (sizeof(mpdd_dd) + 2 * sizeof(double));
-  if (hipMallocAsync(&s.base, bytes, st) != hipSuccess) return MPDD_ERR_ALLOC;
+  if (hipMallocFromPoolAsync(&s.base, bytes, pool, st) != hipSuccess) return MPDD_ERR_ALLOC;
   s.pairs = (mpdd_dd*)s.base;
   s.hi = (double*)((char*)s.base + elems * sizeof(mpdd_dd));
   s.lo = s.hi + elems;
@@ -303,10 +303,10 @@ int mpdd_Rgemm_host(mpdd_handle h, const char* transa, const char* transb, mpdd_
   // B chunk: columns j0.. of op(B): for 'N' the columns of B, for 'T' its rows
   const size_t nb_chunk = use_ab ? (notb ? (size_t)ldb * cw : (size_t)cw * k) : 0;
   const size_t nc_chunk = (size_t)ldc * cw;
-  if (!rc && use_ab) rc = stage_alloc(sa, (size_t)lda * (size_t)ncola, sx);
+  if (!rc && use_ab) rc = stage_alloc(sa, (size_t)lda * (size_t)ncola, sx, handle_pool(h));
   for (int t = 0; t < 2 && !rc; ++t) {
-    rc = stage_alloc(sbuf[t], nb_chunk, sx);
-    if (!rc) rc = stage_alloc(scb[t], nc_chunk, sx);
+    rc = stage_alloc(sbuf[t], nb_chunk, sx, handle_pool(h));
+    if (!rc) rc = stage_alloc(scb[t], nc_chunk, sx, handle_pool(h));
   }
   if (!rc && use_ab && !slice_a) rc = upload(sa, A, sx, stg);
   auto upload_chunk = [&](int64_t c) -> int {
@@ -431,8 +431,8 @@ int mpdd_Rsyrk_host(mpdd_handle h, const char* uplo, const char* trans, mpdd_int
   int rc = 0;
   const size_t na = use_a ? (size_t)lda * (size_t)ncola : 0;
   const size_t nc = (size_t)ldc * (size_t)n;
-  if (!rc) rc = stage_alloc(bufs[0], na, st);
-  if (!rc) rc = stage_alloc(bufs[1], nc, st);
+  if (!rc) rc = stage_alloc(bufs[0], na, st, handle_pool(h));
+  if (!rc) rc = stage_alloc(bufs[1], nc, st, handle_pool(h));
   if (!rc) rc = upload(bufs[0], A, st, stg);
   if (!rc) rc = upload(bufs[1], C, st, stg);
   if (!rc)

@@ -120,12 +120,12 @@ int ozaki_gemm(const void* opts, bool ta, bool tb, int64_t m, int64_t n, int64_t
                double alpha_hi, double alpha_lo, const double* a_hi, const double* a_lo,
                int64_t lda, const double* b_hi, const double* b_lo, int64_t ldb,
                double beta_hi, double beta_lo, double* c_hi, double* c_lo, int64_t ldc,
-               hipStream_t st);
+               hipStream_t st, hipMemPool_t pool);
 
 // Split-form building blocks (ozaki.hip).
 int ozaki_split_entry(int algo, bool trans, int64_t rows, int64_t k, const double* hi,
                       const double* lo, int64_t ld, int nslices, int wfirst, int w, int* exps,
-                      void* slices, int64_t ldq, int64_t rows_p, hipStream_t st);
+                      void* slices, int64_t ldq, int64_t rows_p, hipStream_t st, hipMemPool_t pool);
 int ozaki_digit_widths(int algo, int64_t k, int nslices, int* wfirst, int* w);
 
 }  // namespace mpdd

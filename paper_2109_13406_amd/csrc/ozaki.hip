@@ -670,7 +670,8 @@ static size_t part_bytes(int64_t rows, int64_t k) {
 int ozaki_gemm(const void* opts_v, bool ta, bool tb, int64_t m, int64_t n, int64_t k,
                double alpha_hi, double alpha_lo, const double* a_hi, const double* a_lo,
                int64_t lda, const double* b_hi, const double* b_lo, int64_t ldb, double beta_hi,
-               double beta_lo, double* c_hi, double* c_lo, int64_t ldc, hipStream_t st) {
+               double beta_lo, double* c_hi, double* c_lo, int64_t ldc, hipStream_t st,
+               hipMemPool_t pool) {
   const mpdd_opts* opts = (const mpdd_opts*)opts_v;
   const int algo = opts->algo;
   const bool beta_zero = beta_hi == 0.0 && beta_lo == 0.0;
@@ -711,7 +712,7 @@ int ozaki_gemm(const void* opts_v, bool ta, bool tb, int64_t m, int64_t n, int64
   const size_t total =
       round_up(qa_bytes, 256) + round_up(qb_bytes, 256) + x_bytes + e_bytes + p_bytes;
   void* ws = nullptr;
-  if (hipMallocAsync(&ws, total, st) != hipSuccess) return MPDD_ERR_ALLOC;
+  if (hipMallocFromPoolAsync(&ws, total, pool, st) != hipSuccess) return MPDD_ERR_ALLOC;
   char* base = (char*)ws;
   void* qa = base;
   void* qb = base + round_up(qa_bytes, 256);
@@ -780,10 +781,12 @@ int ozaki_gemm(const void* opts_v, bool ta, bool tb, int64_t m, int64_t n, int64
 // Exposed building block: scale exponents and digit slices of op(X).
 int ozaki_split_entry(int algo, bool trans, int64_t rows, int64_t k, const double* hi,
                       const double* lo, int64_t ld, int nslices, int wfirst, int w, int* exps,
-                      void* slices, int64_t ldq, int64_t rows_p, hipStream_t st) {
+                      void* slices, int64_t ldq, int64_t rows_p, hipStream_t st,
+                      hipMemPool_t pool) {
   const int64_t sr = trans ? ld : 1, sl = trans ? 1 : ld;
   void* part = nullptr;
-  if (hipMallocAsync(&part, part_bytes(rows, k), st) != hipSuccess) return MPDD_ERR_ALLOC;
+  if (hipMallocFromPoolAsync(&part, part_bytes(rows, k), pool, st) != hipSuccess)
+    return MPDD_ERR_ALLOC;
   hipError_t e;
   if (algo == MPDD_OZAKI_I8)
     e = split_operand<int8_t>(hi, lo, sr, sl, rows, k, exps, (int8_t*)slices, ldq, rows_p,

@@ -3,6 +3,8 @@
 // which times every candidate on the device and writes a JSON cache; the
 // handle loads it at creation.  Without an entry, default_tile() applies.
 #pragma once
+#include <hip/hip_runtime.h>
+
 #include <cstdint>
 #include <map>
 #include <mutex>
@@ -44,6 +46,8 @@ namespace mpdd { class HostStager; }
 // The pinned staging of the host-pointer calls (host_api.cpp), owned by the
 // handle: its lock, its stager slot, and its destruction with the handle.
 std::mutex* handle_host_mutex(mpdd_handle_s* h);
+// The handle's stream-ordered scratch pool.
+hipMemPool_t handle_pool(const mpdd_handle_s* h);
 mpdd::HostStager** handle_stager(mpdd_handle_s* h);
 void destroy_stager(mpdd::HostStager* st);
 // Handle accessors for other translation units (mpdd.cpp owns the struct).
