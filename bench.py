@@ -28,7 +28,8 @@ HBM_PEAK_GBS = 8000.0
 INT8_PEAK_TOPS = 5000.0          # dense INT8 matrix peak, ops/s (MAC = 2 ops)
 OPS_PER_MADD_ALG = 20            # FP64 issue slots per dd multiply-add (roofline unit)
 OPS_PER_MADD_LEAN = 10           # what the plain kernel issues per dd multiply-add (8 vector + 2 MFMA)
-KERNEL_SOURCES = ["paper_2109_13406_amd/csrc/gemm_plain.hip", "paper_2109_13406_amd/csrc/dd.hpp"]
+KERNEL_SOURCES = ["paper_2109_13406_amd/csrc/gemm_plain.hip", "paper_2109_13406_amd/csrc/dd.hpp",
+                  "paper_2109_13406_amd/build.py"]    # (its per-source flags shape the kernel)
 
 
 def log(*a):

@@ -29,9 +29,17 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-ffp-contract=o
          "-Wall", "-Wno-unused-function", "-I", os.path.join(ROOT, "include")]
 
 
+# Per-source extra flags.  The plain dd kernels keep their FP64 MFMA
+# accumulators (the cross terms) in ordinary VGPRs: with AGPRs the compiler
+# copied them out and back every k-tile (64 v_accvgpr moves per 2 100 FP64
+# ops), and the register budget (two waves per SIMD) has room for them.
+EXTRA_FLAGS = {"gemm_plain.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
+
+
 def _compile(src):
     out = os.path.join(OBJ, os.path.basename(src) + ".o")
-    cmd = [HIPCC, *FLAGS, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", out]
+    cmd = [HIPCC, *FLAGS, *EXTRA_FLAGS.get(src, []), "-x", "hip", "-c", os.path.join(CSRC, src),
+           "-o", out]
     r = subprocess.run(cmd, capture_output=True, text=True)
     return src, out, r
 
