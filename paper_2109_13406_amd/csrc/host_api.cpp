@@ -41,7 +41,11 @@ class HostStager {
       if (hipHostMalloc(&slot_[i], kPiece, hipHostMallocDefault) != hipSuccess) return MPDD_ERR_ALLOC;
       if (hipEventCreateWithFlags(&ev_[i], hipEventDisableTiming) != hipSuccess) return MPDD_ERR_HIP;
     }
-    for (int i = 1; i < kThreads; ++i) workers_.emplace_back([this, i] { work(i); });
+    try {
+      for (int i = 1; i < kThreads; ++i) workers_.emplace_back([this, i] { work(i); });
+    } catch (...) {               // no thread: the destructor stops the ones started
+      return MPDD_ERR_ALLOC;
+    }
     return 0;
   }
 
