@@ -603,10 +603,19 @@ oz_combine(const XT* __restrict__ x, int64_t mp, int64_t np, int nslices, int wf
   const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (gid >= m * n) return;
   const int64_t i = gid % m, j = gid / m;
+  const XT* xp = x + j * mp + i;
+  const int64_t plane = mp * np;
+  // smallest weight first (d = nslices+1 down to 2); the sums of eight
+  // anti-diagonals are loaded before any is added, so eight loads are in
+  // flight per thread instead of one
   ddv p{0.0, 0.0};
-  for (int d = nslices + 1; d >= 2; --d) {
-    const double v = (double)x[(int64_t)(d - 2) * mp * np + j * mp + i];
-    p = dd_add_d(p, ldexp(v, -(2 * wfirst + w * (d - 2))));
+  for (int d0 = nslices + 1; d0 >= 2; d0 -= 8) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = d0 - u >= 2 ? (double)xp[(int64_t)(d0 - u - 2) * plane] : 0.0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (d0 - u >= 2) p = dd_add_d(p, ldexp(v[u], -(2 * wfirst + w * (d0 - u - 2))));
   }
   const int e = ea[i] + eb[j];
   p.hi = ldexp(p.hi, e);
