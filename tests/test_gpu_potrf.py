@@ -125,3 +125,89 @@ def test_potrf_1024(h, uplo):
     r = float(np.linalg.norm(d) / np.linalg.norm(O[0][idx]) / (n * EPS_DD))
     log(f"PARITY potrf {uplo} n={n}: factor ratio {r:.4g}")
     assert r <= 8.0
+
+
+@pytest.mark.parametrize("uplo", "LU")
+def test_potrf_8192_sampled(h, uplo):
+    """The benchmarked size (n = 8192, ld = 8195), checked where the oracle can
+    follow it: the leading 256 x 256 block equals the oracle's factor of the
+    leading principal submatrix, the first 256 entries of sampled later rows
+    equal the last row of the oracle's factor of the principal submatrix on
+    indices [0, 256) + {i} (a Cholesky factor's row i, columns < c, depends only
+    on A's leading c columns), and sampled entries of L L^T - A, formed in dd by
+    the oracle's Rgemm, are within LAPACK's threshold of the componentwise
+    backward-error bound n 2^-104 sqrt(A(i,i) A(j,j))."""
+    import torch
+    from paper_2109_13406_amd import binding as b
+    n, n0 = 8192, 256
+    c = W.spd_case_device(5400, n, uplo)
+    ld = c["lda"]
+
+    def lower_view(planes):
+        # X(r, l) of the lower view as an (n, n) torch view: 'L' A(r, l), 'U' A(l, r)
+        v = [p[: n * ld].view(n, ld)[:, :n] for p in planes]     # v[j, i] = A(i, j)
+        return [x.t() for x in v] if uplo == "L" else v
+
+    A0 = lower_view(c["A"])
+    A_lead = [x[:n0, :n0].cpu().numpy() for x in A0]
+    rng = np.random.default_rng(5401)
+    rows = np.sort(rng.choice(np.arange(n0, n), 8, replace=False))
+    A_rows = [[x[i, :n0].cpu().numpy() for x in A0] for i in rows]
+    A_rowdiag = [[float(x[i, i]) for x in A0] for i in rows]
+    ii = rng.integers(0, n, 48)
+    jj = (rng.random(48) * (ii + 1)).astype(np.int64)
+    ii = np.concatenate([ii, [n - 1, n - 1, n - 1]])
+    jj = np.concatenate([jj, [0, n - 2, n - 1]])
+    A_ij = [(float(A0[0][i, j]), float(A0[1][i, j])) for i, j in zip(ii, jj)]
+    diag = A0[0].diagonal().cpu().numpy().copy()
+
+    rc, info = b.mpdd_Rpotrf(h, uplo, n, c["A"], ld)
+    torch.cuda.synchronize()
+    assert rc == 0 and info == 0
+    L = lower_view(c["A"])
+
+    def lower_tri(M):
+        # oracle layout of an m x m lower-view matrix M (numpy, [r, l])
+        m = M.shape[0]
+        return np.ascontiguousarray(M.T if uplo == "L" else M).reshape(-1).copy()
+
+    # leading block
+    O = (lower_tri(A_lead[0]), lower_tri(A_lead[1]))
+    assert oracle.rpotrf(uplo, n0, O, n0) == 0
+    G = [x[:n0, :n0].cpu().numpy() for x in L]
+    Gf = (lower_tri(G[0]), lower_tri(G[1]))
+    idx = tri_idx(n0, n0, uplo)
+    d = (Gf[0][idx] - O[0][idx]) + (Gf[1][idx] - O[1][idx])
+    r = float(np.linalg.norm(d) / np.linalg.norm(O[0][idx]) / (n0 * EPS_DD))
+    log(f"PARITY potrf {uplo} n={n} leading {n0}: factor ratio {r:.4g}")
+    assert r <= 8.0
+
+    # sampled rows, first n0 columns
+    for t, i in enumerate(rows):
+        S = [np.zeros((n0 + 1, n0 + 1)) for _ in range(2)]
+        for p in range(2):
+            S[p][:n0, :n0] = np.tril(A_lead[p])
+            S[p][n0, :n0] = A_rows[t][p]
+            S[p][n0, n0] = A_rowdiag[t][p]
+        O = (lower_tri(S[0]), lower_tri(S[1]))
+        assert oracle.rpotrf(uplo, n0 + 1, O, n0 + 1) == 0
+        og = [O[p].reshape(n0 + 1, n0 + 1) for p in range(2)]   # [col, row] for L, [row, col] for U
+        orow = [(og[p][:n0, n0] if uplo == "L" else og[p][n0, :n0]) for p in range(2)]
+        grow = [x[i, :n0].cpu().numpy() for x in L]
+        d = (grow[0] - orow[0]) + (grow[1] - orow[1])
+        r = float(np.linalg.norm(d) / np.linalg.norm(orow[0]) / (n0 * EPS_DD))
+        log(f"PARITY potrf {uplo} n={n} row {i} cols <{n0}: ratio {r:.4g}")
+        assert r <= 8.0, (i, r)
+
+    # sampled residual entries (L L^T - A)(i, j), i >= j
+    worst = 0.0
+    for (i, j), (ah, al) in zip(zip(ii, jj), A_ij):
+        kk = int(j) + 1
+        Li = [np.ascontiguousarray(x[int(i), :kk].cpu().numpy()) for x in L]
+        Lj = [np.ascontiguousarray(x[int(j), :kk].cpu().numpy()) for x in L]
+        C = (np.array([ah]), np.array([al]))
+        assert oracle.rgemm("N", "T", 1, 1, kk, (1.0, 0.0), Li, 1, Lj, 1, (-1.0, 0.0), C, 1) == 0
+        res = abs(C[0][0] + C[1][0]) / (n * EPS_DD * np.sqrt(diag[i] * diag[j]))
+        worst = max(worst, res)
+    log(f"PARITY potrf {uplo} n={n}: worst sampled residual ratio {worst:.4g}")
+    assert worst <= THRESH
