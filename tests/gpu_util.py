@@ -212,25 +212,34 @@ def sampled_syrk_check(h, name, case, opts=None, count=192, seed=0):
     return r
 
 
+def take(p, idx):
+    """p[idx] as a numpy array, for a numpy plane or a device tensor."""
+    if isinstance(p, np.ndarray):
+        return p[idx]
+    import torch
+    return p[torch.from_numpy(np.ascontiguousarray(idx)).to(p.device)].cpu().numpy()
+
+
 def csub(c, I, J):
     """The Cgemm case restricted to rows I of op(A) and columns J of op(B):
     compact operands with the same op flags, C = C[I, J].  Entry (r, s) of its
-    result is entry (I[r], J[s]) of the full one, computed by the same steps."""
+    result is entry (I[r], J[s]) of the full one, computed by the same steps.
+    The planes may be numpy arrays or device tensors (gathered to the host)."""
     k, ta, tb = c["k"], c["transa"].upper(), c["transb"].upper()
     li, lj = len(I), len(J)
     ar = np.arange(k)
     A, B = [], []
     for p in c["A"]:
         if ta == "N":     # op(A) rows I = storage rows I: li x k
-            A.append(p[(I[:, None] + ar[None, :] * c["lda"]).ravel(order="F")])
+            A.append(take(p, (I[:, None] + ar[None, :] * c["lda"]).ravel(order="F")))
         else:             # storage columns I: k x li
-            A.append(p[(ar[:, None] + I[None, :] * c["lda"]).ravel(order="F")])
+            A.append(take(p, (ar[:, None] + I[None, :] * c["lda"]).ravel(order="F")))
     for p in c["B"]:
         if tb == "N":     # op(B) columns J = storage columns J: k x lj
-            B.append(p[(ar[:, None] + J[None, :] * c["ldb"]).ravel(order="F")])
+            B.append(take(p, (ar[:, None] + J[None, :] * c["ldb"]).ravel(order="F")))
         else:             # storage rows J: lj x k
-            B.append(p[(J[:, None] + ar[None, :] * c["ldb"]).ravel(order="F")])
-    C = tuple(p[(I[:, None] + J[None, :] * c["ldc"]).ravel(order="F")] for p in c["C"])
+            B.append(take(p, (J[:, None] + ar[None, :] * c["ldb"]).ravel(order="F")))
+    C = tuple(take(p, (I[:, None] + J[None, :] * c["ldc"]).ravel(order="F")) for p in c["C"])
     return dict(transa=ta, transb=tb, m=li, n=lj, k=k, alpha=c["alpha"], beta=c["beta"],
                 A=tuple(A), lda=(li if ta == "N" else k), B=tuple(B), ldb=(k if tb == "N" else lj),
                 C=C, ldc=li)

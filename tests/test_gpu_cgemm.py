@@ -12,7 +12,7 @@ import pytest
 import oracle
 import pins
 import workloads as W
-from gpu_util import csub, log
+from gpu_util import csub, log, take
 from oracle.compare import RATIO_MAX, bits, ratio
 
 pytestmark = pytest.mark.gpu
@@ -226,3 +226,29 @@ def test_cgemm_2048_sampled(h):
         r = cratio(Gs, O, np.arange(48 * 48), k)
         log(f"PARITY cgemm 2048^3 {ta}{tb} sampled 48x48: ratio {r:.4g}")
         assert r <= RATIO_MAX
+
+
+def test_cgemm_4096_sampled(h):
+    """The benchmarked size and inputs (4096^3 NN, device-generated operands,
+    both the four- and the three-product form) on 32 x 32 sampled entries: the
+    oracle runs on the gathered rows of op(A) and columns of op(B)."""
+    import torch
+    from paper_2109_13406_amd import binding as b
+    n = 4096
+    for form, opts in (("4M", None), ("3M", dict(algo=b.MPDD_COMPLEX_3M))):
+        c = W.cgemm_case_device(W.BASE_SEED + 5, "N", "N", n, n, n)
+        rng = np.random.default_rng(11)
+        I = np.sort(rng.choice(n, 32, replace=False))
+        J = np.sort(rng.choice(n, 32, replace=False))
+        sub = csub(c, I, J)
+        args = ("N", "N", n, n, n, c["alpha"], c["A"], c["lda"], c["B"], c["ldb"], c["beta"],
+                c["C"], c["ldc"])
+        info = b.mpdd_Cgemm(h, *args) if opts is None else b.mpdd_Cgemm_ex(h, opts, *args)
+        torch.cuda.synchronize()
+        assert info == 0
+        O = cgemm_oracle(sub)
+        Gs = tuple(take(p, (I[:, None] + J[None, :] * c["ldc"]).ravel(order="F")) for p in c["C"])
+        r = cratio(Gs, O, np.arange(32 * 32), n)
+        log(f"PARITY cgemm {n}^3 NN {form} (benchmarked inputs) sampled 32x32: ratio {r:.4g}")
+        assert r <= RATIO_MAX
+        del c

@@ -170,3 +170,21 @@ def test_qgemm_1024_sampled(h):
         r = qratio(Gs, O, np.arange(32 * 32), k)
         log(f"PARITY qgemm 1024^3 {ta}{tb} sampled 32x32: ratio {r:.4g}")
         assert r <= RATIO_MAX
+
+
+def test_qgemm_2048_sampled(h):
+    """The benchmarked size (2048^3 NN) on 24 x 24 sampled entries: the oracle
+    runs on the gathered rows of op(A) and columns of op(B)."""
+    n = k = 2048
+    c = W.qgemm_case(W.BASE_SEED + 10, "N", "N", n, n, k)
+    info, G = qgemm_gpu(h, c)
+    assert info == 0
+    rng = np.random.default_rng(12)
+    I = np.sort(rng.choice(n, 24, replace=False))
+    J = np.sort(rng.choice(n, 24, replace=False))
+    sub = csub(c, I, J)
+    O = qgemm_oracle(sub)
+    Gs = tuple(p[(I[:, None] + J[None, :] * c["ldc"]).ravel(order="F")] for p in G)
+    r = qratio(Gs, O, np.arange(24 * 24), k)
+    log(f"PARITY qgemm {n}^3 NN sampled 24x24: ratio {r:.4g}")
+    assert r <= RATIO_MAX
