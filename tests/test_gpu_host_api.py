@@ -178,3 +178,35 @@ def test_host_info_codes(h):
     assert b.mpdd_Rgemm_host(h, "N", "N", 3, 3, 3, 1.0, None, 2, None, 3, 0.0, C, 3) == 8
     assert b.mpdd_Rsyrk_host(h, "U", "N", 3, 3, 1.0, None, 3, 0.0, C, 2) == 10
     assert b.mpdd_Rgemm_host(h, "N", "N", 0, 3, 3, 1.0, None, 1, None, 3, 0.0, C, 1) == 0
+
+
+def test_rgemm_host_8192_sampled(h):
+    """The benchmarked host-pointer call (8192^3 NN, ld 8195, dd_real pairs in
+    pageable host memory, alpha 0.5, beta 0.25, the bench's device-generated
+    inputs brought to the host) on 64 sampled entries against the oracle, and
+    the padding rows of C untouched."""
+    import torch
+    from paper_2109_13406_amd import binding as b
+    n = 8192
+    case = W.gemm_case_device(W.BASE_SEED + 5, "N", "N", n, n, n)
+    hp = lambda pl: torch.stack([pl[0], pl[1]], dim=1).cpu().numpy()
+    A, B, C = hp(case["A"]), hp(case["B"]), hp(case["C"])
+    ld = case["lda"]
+    del case
+    torch.cuda.empty_cache()
+    C0 = C.copy()
+    alpha, beta = (0.5, 0.0), (0.25, 0.0)
+    assert b.mpdd_Rgemm_host(h, "N", "N", n, n, n, alpha, A, ld, B, ld, beta, C, ld) == 0
+    rng = np.random.default_rng(13)
+    ii = np.concatenate([rng.integers(0, n, 60), [0, n - 1, 0, n - 1]])
+    jj = np.concatenate([rng.integers(0, n, 60), [0, n - 1, n - 1, 0]])
+    P = lambda x: (np.ascontiguousarray(x[:, 0]), np.ascontiguousarray(x[:, 1]))
+    oh, ol = oracle.rgemm_entries("N", "N", n, n, n, alpha, P(A), ld, P(B), ld, beta, P(C0), ld,
+                                  ii, jj)
+    idx = ii + jj * ld
+    r = ratio(C[idx, 0], C[idx, 1], oh, ol, n)
+    log(f"PARITY host-pointer Rgemm {n}^3 NN sampled 64: ratio {r:.4g}")
+    assert r <= RATIO_MAX
+    pad = (np.arange(n, ld)[:, None] + np.arange(0, n, 97)[None, :] * ld).ravel()
+    assert np.array_equal(bits(C[pad, 0]), bits(C0[pad, 0]))
+    assert np.array_equal(bits(C[pad, 1]), bits(C0[pad, 1]))
