@@ -155,6 +155,89 @@ def _ptr(x):
     return x.data_ptr()
 
 
+def _extent(rows, cols, ld):
+    """Elements spanned by a column-major rows x cols matrix with leading
+    dimension ld (0 when it is empty)."""
+    return 0 if rows <= 0 or cols <= 0 else ld * (cols - 1) + rows
+
+
+def _first(flag):
+    if isinstance(flag, bytes):
+        flag = flag.decode(errors="replace")
+    return flag[:1].upper() if isinstance(flag, str) else ""
+
+
+def _dev(x, need, name, dtype=None):
+    """Pointer for a device argument that the call will touch over `need`
+    elements: a CUDA tensor of the expected dtype (float64 unless given),
+    contiguous, with at least `need` elements from its start, is checked
+    before the library sees it, since the kernels cannot tell a host pointer
+    or a short buffer from a good one.  Raw integer pointers and None pass
+    unchecked, and so does an argument the call does not touch (need 0)."""
+    if x is None or isinstance(x, int) or need <= 0:
+        return _ptr(x)
+    import torch
+    if not isinstance(x, torch.Tensor):
+        raise TypeError(f"{name}: expected a torch tensor or a device pointer, got {type(x)}")
+    want = dtype or torch.float64
+    if x.dtype != want:
+        raise ValueError(f"{name}: dtype {x.dtype}, expected {want}")
+    if not x.is_cuda:
+        raise ValueError(f"{name}: tensor on {x.device}, expected a CUDA device")
+    if not x.is_contiguous():
+        raise ValueError(f"{name}: tensor must be contiguous (column-major planes with ld)")
+    if x.numel() < need:
+        raise ValueError(f"{name}: {x.numel()} elements, the call touches {need}")
+    return x.data_ptr()
+
+
+def _planes(xs, need, name):
+    return [_dev(x, need, f"{name}[{i}]") for i, x in enumerate(xs)]
+
+
+def _gemm_extents(transa, transb, m, n, k, lda, ldb, ldc):
+    """(A, B, C) element extents of a valid Rgemm-shaped call, or None when an
+    argument is invalid (the library then returns its info code)."""
+    fa, fb = _first(transa), _first(transb)
+    if fa not in ("N", "T", "C") or fb not in ("N", "T", "C") or min(m, n, k) < 0:
+        return None
+    nra, nca = (m, k) if fa == "N" else (k, m)
+    nrb, ncb = (k, n) if fb == "N" else (n, k)
+    if lda < max(1, nra) or ldb < max(1, nrb) or ldc < max(1, m):
+        return None
+    return _extent(nra, nca, lda), _extent(nrb, ncb, ldb), _extent(m, n, ldc)
+
+
+def _syrk_extents(uplo, trans, n, k, lda, ldc):
+    """(A, C) element extents of a valid Rsyrk call, or None."""
+    fu, ft = _first(uplo), _first(trans)
+    if fu not in ("U", "L") or ft not in ("N", "T", "C") or min(n, k) < 0:
+        return None
+    nra, nca = (n, k) if ft == "N" else (k, n)
+    if lda < max(1, nra) or ldc < max(1, n):
+        return None
+    return _extent(nra, nca, lda), _extent(n, n, ldc)
+
+
+def _touches(ext, alpha_zero, beta_one, k, m, n):
+    """Extents actually read / written: (A and B, C).  A and B are not read
+    when alpha = 0 or k = 0; C is not touched on a quick return."""
+    if ext is None or m == 0 or n == 0:
+        return 0, 0
+    ab = not (alpha_zero or k == 0)
+    c_touched = ab or not beta_one
+    return ab, c_touched
+
+
+def _gemm_ptrs(nplanes, transa, transb, m, n, k, alpha_zero, beta_one, A, lda, B, ldb, C, ldc):
+    ext = _gemm_extents(transa, transb, m, n, k, lda, ldb, ldc)
+    ab, ct = _touches(ext, alpha_zero, beta_one, k, m, n)
+    ea, eb, ec = ext if ext else (0, 0, 0)
+    assert len(A) == nplanes and len(B) == nplanes and len(C) == nplanes
+    return (_planes(A, ea if ab else 0, "A"), _planes(B, eb if ab else 0, "B"),
+            _planes(C, ec if ct else 0, "C"))
+
+
 def _dd(x):
     if isinstance(x, mpdd_dd):
         return x
@@ -210,37 +293,54 @@ def mpdd_destroy(h):
     return load().mpdd_destroy(h)
 
 
+def _dd_zero(x):
+    return x.hi == 0.0 and x.lo == 0.0
+
+
+def _dd_one(x):
+    return x.hi == 1.0 and x.lo == 0.0
+
+
 def mpdd_Rgemm(h, transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, stream=None):
     """A, B, C: (hi, lo) pairs of tensors or device pointers.  Returns info."""
-    return load().mpdd_Rgemm(h, _flag(transa), _flag(transb), m, n, k, _dd(alpha), _ptr(A[0]),
-                             _ptr(A[1]), lda, _ptr(B[0]), _ptr(B[1]), ldb, _dd(beta), _ptr(C[0]),
-                             _ptr(C[1]), ldc, _stream(stream))
+    return mpdd_Rgemm_ex(h, None, transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc,
+                         stream, _entry="mpdd_Rgemm")
 
 
 def mpdd_Rgemm_ex(h, opts, transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc,
-                  stream=None):
+                  stream=None, _entry="mpdd_Rgemm_ex"):
+    a, bt = _dd(alpha), _dd(beta)
+    pa, pb, pc = _gemm_ptrs(2, transa, transb, m, n, k, _dd_zero(a), _dd_one(bt), A, lda, B, ldb,
+                            C, ldc)
+    args = (_flag(transa), _flag(transb), m, n, k, a, pa[0], pa[1], lda, pb[0], pb[1], ldb, bt,
+            pc[0], pc[1], ldc, _stream(stream))
+    if _entry == "mpdd_Rgemm":
+        return load().mpdd_Rgemm(h, *args)
     o = opts if opts is None or isinstance(opts, mpdd_opts) else _opts(**opts)
-    return load().mpdd_Rgemm_ex(h, ctypes.byref(o) if o is not None else None, _flag(transa),
-                                _flag(transb), m, n, k, _dd(alpha), _ptr(A[0]), _ptr(A[1]), lda,
-                                _ptr(B[0]), _ptr(B[1]), ldb, _dd(beta), _ptr(C[0]), _ptr(C[1]),
-                                ldc, _stream(stream))
+    return load().mpdd_Rgemm_ex(h, ctypes.byref(o) if o is not None else None, *args)
+
+
+def _cgemm_args(transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, stream):
+    a, bt = _ddc(alpha), _ddc(beta)
+    pa, pb, pc = _gemm_ptrs(4, transa, transb, m, n, k, _dd_zero(a.re) and _dd_zero(a.im),
+                            _dd_one(bt.re) and _dd_zero(bt.im), A, lda, B, ldb, C, ldc)
+    return (_flag(transa), _flag(transb), m, n, k, a, *pa, lda, *pb, ldb, bt, *pc, ldc,
+            _stream(stream))
 
 
 def mpdd_Cgemm(h, transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, stream=None):
     """A, B, C: 4-tuples (re.hi, re.lo, im.hi, im.lo) of tensors or device
     pointers.  Returns info."""
-    return load().mpdd_Cgemm(h, _flag(transa), _flag(transb), m, n, k, _ddc(alpha),
-                             *map(_ptr, A), lda, *map(_ptr, B), ldb, _ddc(beta), *map(_ptr, C),
-                             ldc, _stream(stream))
+    return load().mpdd_Cgemm(h, *_cgemm_args(transa, transb, m, n, k, alpha, A, lda, B, ldb,
+                                             beta, C, ldc, stream))
 
 
 def mpdd_Cgemm_ex(h, opts, transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc,
                   stream=None):
     o = opts if opts is None or isinstance(opts, mpdd_opts) else _opts(**opts)
-    return load().mpdd_Cgemm_ex(h, ctypes.byref(o) if o is not None else None, _flag(transa),
-                                _flag(transb), m, n, k, _ddc(alpha), *map(_ptr, A), lda,
-                                *map(_ptr, B), ldb, _ddc(beta), *map(_ptr, C), ldc,
-                                _stream(stream))
+    return load().mpdd_Cgemm_ex(h, ctypes.byref(o) if o is not None else None,
+                                *_cgemm_args(transa, transb, m, n, k, alpha, A, lda, B, ldb,
+                                             beta, C, ldc, stream))
 
 
 def _qd(x):
@@ -254,54 +354,81 @@ def _qd(x):
 def mpdd_Qgemm(h, transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, stream=None):
     """Quad-double Rgemm.  A, B, C: 4-tuples of planes (x0..x3) as tensors or
     device pointers; alpha, beta: 4-tuples of floats.  Returns info."""
-    return load().mpdd_Qgemm(h, _flag(transa), _flag(transb), m, n, k, _qd(alpha),
-                             *map(_ptr, A), lda, *map(_ptr, B), ldb, _qd(beta), *map(_ptr, C),
-                             ldc, _stream(stream))
+    a, bt = _qd(alpha), _qd(beta)
+    pa, pb, pc = _gemm_ptrs(4, transa, transb, m, n, k, all(v == 0.0 for v in a.x),
+                            list(bt.x) == [1.0, 0.0, 0.0, 0.0], A, lda, B, ldb, C, ldc)
+    return load().mpdd_Qgemm(h, _flag(transa), _flag(transb), m, n, k, a, *pa, lda, *pb, ldb,
+                             bt, *pc, ldc, _stream(stream))
 
 
 def mpdd_Rpotrf(h, uplo, n, A, lda, nb=0, stream=None):
     """A: (hi, lo) pair of tensors or device pointers.  Returns (rc, info):
     rc = 0 or MPDD_ERR_*, info = LAPACK's info."""
     info = _I(0)
-    rc = load().mpdd_Rpotrf_nb(h, _flag(uplo), n, _ptr(A[0]), _ptr(A[1]), lda, nb,
-                               ctypes.byref(info), _stream(stream))
+    ok = _first(uplo) in ("U", "L") and n >= 0 and lda >= max(1, n)
+    pa = _planes(A, _extent(n, n, lda) if ok else 0, "A")
+    rc = load().mpdd_Rpotrf_nb(h, _flag(uplo), n, pa[0], pa[1], lda, nb, ctypes.byref(info),
+                               _stream(stream))
     return rc, info.value
 
 
+def _syrk_args(uplo, trans, n, k, alpha, A, lda, beta, C, ldc, stream):
+    a, bt = _dd(alpha), _dd(beta)
+    ext = _syrk_extents(uplo, trans, n, k, lda, ldc)
+    ab, ct = _touches(ext, _dd_zero(a), _dd_one(bt), k, n, n)
+    ea, ec = ext if ext else (0, 0)
+    pa, pc = _planes(A, ea if ab else 0, "A"), _planes(C, ec if ct else 0, "C")
+    return (_flag(uplo), _flag(trans), n, k, a, pa[0], pa[1], lda, bt, pc[0], pc[1], ldc,
+            _stream(stream))
+
+
 def mpdd_Rsyrk(h, uplo, trans, n, k, alpha, A, lda, beta, C, ldc, stream=None):
-    return load().mpdd_Rsyrk(h, _flag(uplo), _flag(trans), n, k, _dd(alpha), _ptr(A[0]),
-                             _ptr(A[1]), lda, _dd(beta), _ptr(C[0]), _ptr(C[1]), ldc,
-                             _stream(stream))
+    return load().mpdd_Rsyrk(h, *_syrk_args(uplo, trans, n, k, alpha, A, lda, beta, C, ldc,
+                                            stream))
 
 
 def mpdd_Rsyrk_ex(h, opts, uplo, trans, n, k, alpha, A, lda, beta, C, ldc, stream=None):
     o = opts if opts is None or isinstance(opts, mpdd_opts) else _opts(**opts)
-    return load().mpdd_Rsyrk_ex(h, ctypes.byref(o) if o is not None else None, _flag(uplo),
-                                _flag(trans), n, k, _dd(alpha), _ptr(A[0]), _ptr(A[1]), lda,
-                                _dd(beta), _ptr(C[0]), _ptr(C[1]), ldc, _stream(stream))
+    return load().mpdd_Rsyrk_ex(h, ctypes.byref(o) if o is not None else None,
+                                *_syrk_args(uplo, trans, n, k, alpha, A, lda, beta, C, ldc,
+                                            stream))
 
 
-def _host_pairs(x):
-    """Pointer to an interleaved {hi, lo} host array: a numpy float64 array of
-    shape (..., 2) / length 2*count, or None."""
+def _host_pairs(x, need=0, name="array"):
+    """Pointer to an interleaved {hi, lo} host array: a C-contiguous numpy
+    float64 array of shape (..., 2) / length 2*count holding at least `need`
+    pairs, or None."""
     if x is None:
         return None
     import numpy as np
-    assert x.dtype == np.float64 and x.flags.c_contiguous
+    if not isinstance(x, np.ndarray) or x.dtype != np.float64 or not x.flags.c_contiguous:
+        raise ValueError(f"{name}: expected a C-contiguous numpy float64 array")
+    if x.size < 2 * need:
+        raise ValueError(f"{name}: {x.size // 2} dd values, the call touches {need}")
     return x.ctypes.data
 
 
 def mpdd_Rgemm_host(h, transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc):
     """MPBLAS-shaped Rgemm on host dd_real arrays (numpy float64, {hi, lo}
     interleaved).  Synchronous; returns info."""
-    return load().mpdd_Rgemm_host(h, _flag(transa), _flag(transb), m, n, k, _dd(alpha),
-                                  _host_pairs(A), lda, _host_pairs(B), ldb, _dd(beta),
-                                  _host_pairs(C), ldc)
+    a, bt = _dd(alpha), _dd(beta)
+    ext = _gemm_extents(transa, transb, m, n, k, lda, ldb, ldc)
+    ab, ct = _touches(ext, _dd_zero(a), _dd_one(bt), k, m, n)
+    ea, eb, ec = ext if ext else (0, 0, 0)
+    return load().mpdd_Rgemm_host(h, _flag(transa), _flag(transb), m, n, k, a,
+                                  _host_pairs(A, ea if ab else 0, "A"), lda,
+                                  _host_pairs(B, eb if ab else 0, "B"), ldb, bt,
+                                  _host_pairs(C, ec if ct else 0, "C"), ldc)
 
 
 def mpdd_Rsyrk_host(h, uplo, trans, n, k, alpha, A, lda, beta, C, ldc):
-    return load().mpdd_Rsyrk_host(h, _flag(uplo), _flag(trans), n, k, _dd(alpha),
-                                  _host_pairs(A), lda, _dd(beta), _host_pairs(C), ldc)
+    a, bt = _dd(alpha), _dd(beta)
+    ext = _syrk_extents(uplo, trans, n, k, lda, ldc)
+    ab, ct = _touches(ext, _dd_zero(a), _dd_one(bt), k, n, n)
+    ea, ec = ext if ext else (0, 0)
+    return load().mpdd_Rsyrk_host(h, _flag(uplo), _flag(trans), n, k, a,
+                                  _host_pairs(A, ea if ab else 0, "A"), lda, bt,
+                                  _host_pairs(C, ec if ct else 0, "C"), ldc)
 
 
 def mpdd_ozaki_digit_widths(algo, k, nslices):
@@ -317,9 +444,18 @@ def mpdd_ozaki_split(h, algo, trans, rows, k, X, ld, nslices, exps, slices, ldq,
                      stream=None):
     """Scale exponents (int32 tensor) and slices (int8 / float64 tensor) of a row
     operand, see include/mpdd.h.  Returns info."""
-    return load().mpdd_ozaki_split(h, algo, _flag(trans), rows, k, _ptr(X[0]), _ptr(X[1]), ld,
-                                   nslices, _ptr(exps), _ptr(slices), ldq, rows_p,
-                                   _stream(stream))
+    import torch
+    ft = _first(trans)
+    nr, nc = (rows, k) if ft == "N" else (k, rows)
+    ok = (ft in ("N", "T", "C") and rows >= 0 and k >= 0 and ld >= max(1, nr) and nslices >= 1
+          and ldq >= k and ldq % 64 == 0 and rows_p >= rows and rows_p % 64 == 0
+          and algo in (MPDD_OZAKI_I8, MPDD_OZAKI_F64))
+    px = _planes(X, _extent(nr, nc, ld) if ok else 0, "X")
+    pe = _dev(exps, rows if ok else 0, "exps", torch.int32)
+    pq = _dev(slices, nslices * rows_p * ldq if ok else 0, "slices",
+              torch.int8 if algo == MPDD_OZAKI_I8 else torch.float64)
+    return load().mpdd_ozaki_split(h, algo, _flag(trans), rows, k, px[0], px[1], ld, nslices,
+                                   pe, pq, ldq, rows_p, _stream(stream))
 
 
 def mpdd_tile_count():
@@ -366,9 +502,23 @@ def make_request(op, flag1, flag2, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc,
     r.flag2 = _flag(flag2)
     r.m, r.n, r.k = m, n, k
     r.alpha, r.beta = _dd(alpha), _dd(beta)
-    r.A_hi, r.A_lo, r.lda = _ptr(A[0]), _ptr(A[1]), lda
-    r.B_hi, r.B_lo, r.ldb = _ptr(B[0]), _ptr(B[1]), ldb
-    r.C_hi, r.C_lo, r.ldc = _ptr(C[0]), _ptr(C[1]), ldc
+    ea = eb = ec = 0
+    if op == MPDD_OP_SYRK:
+        ext = _syrk_extents(flag1, flag2, n, k, lda, ldc)
+        ab, ct = _touches(ext, _dd_zero(r.alpha), _dd_one(r.beta), k, n, n)
+        if ext:
+            ea, ec = ext
+    else:
+        ext = _gemm_extents(flag1, flag2, m, n, k, lda, ldb, ldc)
+        ab, ct = _touches(ext, _dd_zero(r.alpha), _dd_one(r.beta), k, m, n)
+        if ext:
+            ea, eb, ec = ext
+    pa = _planes(A, ea if ab else 0, "A")
+    pb = _planes(B, eb if ab else 0, "B")
+    pc = _planes(C, ec if ct else 0, "C")
+    r.A_hi, r.A_lo, r.lda = pa[0], pa[1], lda
+    r.B_hi, r.B_lo, r.ldb = pb[0], pb[1], ldb
+    r.C_hi, r.C_lo, r.ldc = pc[0], pc[1], ldc
     r.arrival = arrival
     r.inject = inject
     return r

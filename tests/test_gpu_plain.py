@@ -253,3 +253,26 @@ def test_bad_tile_with_automatic_split(h):
     info, _ = syrk_gpu(h, W.syrk_case(906, "U", "N", 40, 50),
                        opts=dict(algo=b.MPDD_PLAIN, tile_id=99, splitk=0))
     assert info == b.MPDD_ERR_UNSUPPORTED
+
+
+def test_binding_rejects_short_buffers(h):
+    """A device plane shorter than the operand it must hold is refused by the
+    binding before any kernel runs (the kernels cannot bounds-check a plain
+    pointer); C is left untouched."""
+    import torch
+    from paper_2109_13406_amd import binding as b
+    m = n = k = 64
+    A = tuple(torch.zeros(64 * 64, dtype=torch.float64, device="cuda") for _ in range(2))
+    Bs = tuple(torch.zeros(64 * 63, dtype=torch.float64, device="cuda") for _ in range(2))
+    C = tuple(torch.full((64 * 64,), 7.0, dtype=torch.float64, device="cuda") for _ in range(2))
+    with pytest.raises(ValueError, match="touches"):
+        b.mpdd_Rgemm(h, "N", "N", m, n, k, 1.0, A, 64, Bs, 64, 0.0, C, 64)
+    with pytest.raises(ValueError, match="touches"):
+        b.mpdd_Rsyrk(h, "U", "N", 64, 64, 1.0, A, 64, 0.0, Bs, 64)
+    with pytest.raises(ValueError, match="contiguous"):
+        b.mpdd_Rgemm(h, "N", "N", 32, 32, 32, 1.0, tuple(x.view(64, 64)[:, :32] for x in A), 64,
+                     A, 64, 0.0, C, 64)
+    torch.cuda.synchronize()
+    assert bool((C[0] == 7.0).all()) and bool((C[1] == 7.0).all())
+    # alpha = 0, beta = 1: nothing is touched, so nothing is checked
+    assert b.mpdd_Rgemm(h, "N", "N", m, n, k, 0.0, Bs, 64, Bs, 64, 1.0, C, 64) == 0
