@@ -110,36 +110,44 @@ __global__ void __launch_bounds__(256)
 oz_slice(const double* __restrict__ xh, const double* __restrict__ xl, int64_t sr, int64_t sl,
          int64_t rows, int64_t k, const int* __restrict__ exps, int nslices, int wfirst, int w,
          T* __restrict__ q, int64_t ldq, int64_t plane) {
-  __shared__ double th[64][65];
-  __shared__ double tl[64][65];
+  // one 33 KB staging buffer, used for the hi plane and then the lo plane
+  // (four workgroups per CU instead of two with both planes staged at once)
+  __shared__ double t[64][65];
   const int tid = threadIdx.x;
   const int64_t r0 = (int64_t)blockIdx.y * 64;
   const int64_t l0 = (int64_t)blockIdx.x * 64;
   const bool lanes_on_r = (sr == 1);
-#pragma unroll
-  for (int e = 0; e < 16; ++e) {
-    const int a = tid & 63, b = (tid >> 6) + 4 * e;
-    const int rr = lanes_on_r ? a : b;
-    const int ll = lanes_on_r ? b : a;
-    const int64_t r = r0 + rr, l = l0 + ll;
-    double h = 0.0, lo = 0.0;
-    if (r < rows && l < k) {
-      h = xh[r * sr + l * sl];
-      lo = xl[r * sr + l * sl];
-    }
-    th[rr][ll] = h;
-    tl[rr][ll] = lo;
-  }
-  __syncthreads();
   const int rr = tid >> 2;
   const int lb = (tid & 3) * 16;
   const int64_t r = r0 + rr;
   const int e = (r < rows) ? exps[r] : 0;
   ddv y[16];
 #pragma unroll
-  for (int i = 0; i < 16; ++i) {
-    y[i].hi = ldexp(th[rr][lb + i], -e);
-    y[i].lo = ldexp(tl[rr][lb + i], -e);
+  for (int half = 0; half < 2; ++half) {
+    const double* __restrict__ src = half ? xl : xh;
+    double v[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int a = tid & 63, b = (tid >> 6) + 4 * q;
+      const int ri = lanes_on_r ? a : b;
+      const int li = lanes_on_r ? b : a;
+      const int64_t rg = r0 + ri, lg = l0 + li;
+      v[q] = (rg < rows && lg < k) ? src[rg * sr + lg * sl] : 0.0;
+    }
+    if (half) __syncthreads();               // the hi values have been read
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int a = tid & 63, b = (tid >> 6) + 4 * q;
+      t[lanes_on_r ? a : b][lanes_on_r ? b : a] = v[q];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      if (half)
+        y[i].lo = ldexp(t[rr][lb + i], -e);
+      else
+        y[i].hi = ldexp(t[rr][lb + i], -e);
+    }
   }
   T* out = q + r * ldq + l0 + lb;
   for (int t = 0; t < nslices; ++t) {
