@@ -9,7 +9,7 @@ import oracle
 from oracle.compare import bits, ratio
 
 RESULTS = os.environ.get("MPDD_PARITY_LOG", os.path.join(
-    os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "gpurun_out", "parity.log"))
+    os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "_build", "parity.log"))
 
 
 def log(msg):
