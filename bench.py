@@ -24,12 +24,15 @@ sys.path.insert(0, ROOT)
 
 METRIC = "dd-GFLOPS Rgemm n=8192 (plain vs Ozaki-split); served p50/p99 latency"
 FP64_PEAK_TFLOPS = 78.6          # MI355X FP64 vector peak (FMA = 2 flops)
+FP64_SLOTS_PER_S = 39.3e12       # 256 CU x 64 lanes x 2.4 GHz: one add, mul or fma per lane-cycle
 HBM_PEAK_GBS = 8000.0
 INT8_PEAK_TOPS = 5000.0          # dense INT8 matrix peak, ops/s (MAC = 2 ops)
-OPS_PER_MADD_ALG = 20            # FP64 issue slots per dd multiply-add (roofline unit)
-OPS_PER_MADD_LEAN = 10           # what the plain kernel issues per dd multiply-add (8 vector + 2 MFMA)
+OPS_PER_MADD_ALG = 20            # FP64 issue slots per dd multiply-add (the dd roofline unit)
+RATIO_MAX = 8.0                  # normwise parity bound, units of k * 2^-104
+# sources whose code or build flags shape the plain kernel: a counter record
+# taken on other sources is not used
 KERNEL_SOURCES = ["paper_2109_13406_amd/csrc/gemm_plain.hip", "paper_2109_13406_amd/csrc/dd.hpp",
-                  "paper_2109_13406_amd/build.py"]    # (its per-source flags shape the kernel)
+                  "paper_2109_13406_amd/csrc/kernels.hpp"]
 
 
 def log(*a):
@@ -37,10 +40,12 @@ def log(*a):
 
 
 def kernel_sha():
+    from paper_2109_13406_amd import build as B
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
+    h.update(json.dumps([B.FLAGS, B.EXTRA_FLAGS.get("gemm_plain.hip", [])]).encode())
     return h.hexdigest()[:16]
 
 
@@ -63,9 +68,10 @@ def timed_calls(fn, steps, warmup, stream):
     return total, per
 
 
-def traffic_record(name):
-    """HBM traffic of the dominant kernel from the committed rocprofv3 counter
-    summary, or None if it is missing or was taken on other kernel sources."""
+def counter_record(name):
+    """The committed rocprofv3 counter summary of the dominant kernel
+    (profiles/<name>.json), or None if it is missing or was taken on other
+    kernel sources or build flags."""
     path = os.path.join(ROOT, "profiles", f"{name}.json")
     if not os.path.exists(path):
         return None
@@ -73,7 +79,36 @@ def traffic_record(name):
         rec = json.load(f)
     if rec.get("kernel_sha") != kernel_sha():
         return None
-    return rec.get("bytes_per_launch")
+    return rec
+
+
+def plain_roofline(madds, t_kernel):
+    """roofline object of the plain kernel.  Its bound is the FP64 issue rate
+    (vector ALUs and FP64 matrix cores share one datapath of 256 CU x 64
+    lanes x 2.4 GHz = 39.3e12 slots/s, 78.6 TFLOP/s counting an FMA as 2).
+    achieved = FP64 slots the kernel executes per dd multiply-add (from the
+    committed SQ counter record of this kernel) x madds / launch time,
+    expressed FMA-equivalent in TFLOP/s; frac = achieved / peak.  The dd
+    roofline of 20 slots per madd is reported as dd_roofline_ratio."""
+    rec = counter_record("dd_gemm_nn8192")
+    if rec is not None:
+        slots = rec["fp64_valu_ops_per_madd"] + rec["mfma_fp64_fma_per_madd"]
+        src = ("profiles/dd_gemm_nn8192.json: SQ_INSTS_VALU_{ADD,MUL,FMA}_F64 x 64 lanes and "
+               "SQ_INSTS_VALU_MFMA_MOPS_F64 x 512 / 2, per madd")
+    else:   # sources changed since the counters: the count from the kernel's code
+        slots = 8.0 + 6.0 / 32.0 + 2.0
+        src = "static: 8 vector ops + 6 per 32-term renormalisation + 2 matrix-core FMAs"
+    dd_tflops = 2.0 * madds / t_kernel / 1e12
+    dd_roof = 2.0 * FP64_SLOTS_PER_S / OPS_PER_MADD_ALG / 1e12
+    achieved = 2.0 * slots * madds / t_kernel / 1e12
+    return {"bound": "alu", "achieved": round(achieved, 2), "peak": FP64_PEAK_TFLOPS,
+            "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
+            "traffic": rec.get("bytes_per_launch") if rec else None,
+            "kernel": "dd_gemm_kernel (plain, NN)", "kernel_ms": round(t_kernel * 1e3, 3),
+            "fp64_slots_per_madd": round(slots, 3), "slots_source": src,
+            "dd_tflops": round(dd_tflops, 3), "dd_roofline_tflops": round(dd_roof, 3),
+            "dd_roofline_ratio": round(dd_tflops / dd_roof, 4),
+            "dd_roofline_ops_per_madd": OPS_PER_MADD_ALG}
 
 
 def bench_plain(h, args, stream):
@@ -94,7 +129,7 @@ def bench_plain(h, args, stream):
             raise RuntimeError(f"mpdd_Rgemm info={info}")
 
     total, per = timed_calls(step, args.steps, args.warmup, stream)
-    return case, total, per
+    return case, total, per, step
 
 
 def bench_sizes(h, args, stream):
@@ -149,27 +184,143 @@ def cpu_baseline(case, n, cols=64):
                       f"timed product), beta=0, {dt:.2f} s wall, OpenMP threads={ncores}"}
 
 
+def oracle_sample(case, count, seed):
+    """Oracle values of sampled entries (workloads.sample_indices) of a
+    device-resident Rgemm case's update, from its current C; with the input C
+    and the componentwise denominators |op(A)| |op(B)| at those entries."""
+    import numpy as np
+    import oracle
+    import torch
+    import workloads as W
+    m, n, k, ldc = case["m"], case["n"], case["k"], case["ldc"]
+    ii, jj = W.sample_indices(m, n, count, seed)
+    flat = ii + jj * ldc
+    idx = torch.as_tensor(flat, device=case["C"][0].device)
+    cin = tuple(p[idx].cpu().numpy() for p in case["C"])
+    ta, tb = case["transa"].upper() != "N", case["transb"].upper() != "N"
+    As = tuple(W.gather_op_rows(x, case["lda"], ta, ii, k) for x in case["A"])
+    Bs = tuple(W.gather_op_cols(x, case["ldb"], tb, jj, k) for x in case["B"])
+    s = len(ii)
+    d = np.arange(s)
+    Cs = (np.zeros(s * s), np.zeros(s * s))
+    Cs[0][d + d * s], Cs[1][d + d * s] = cin
+    ref = oracle.rgemm_entries("N", "N", s, s, k, case["alpha"], tuple(x.ravel() for x in As),
+                               s, tuple(x.ravel() for x in Bs), k, case["beta"], Cs, s, d, d)
+    absab = np.einsum("lt,tl->t", np.abs(As[0]), np.abs(Bs[0]))
+    return dict(flat=flat, ref=ref, absab=absab, cin=cin, k=k, alpha=case["alpha"],
+                beta=case["beta"])
+
+
+def oracle_compare(smp, C):
+    """(normwise ratio, componentwise error) of device result C at the
+    sampled entries against the oracle values in smp."""
+    import torch
+    from oracle.compare import componentwise, ratio
+    idx = torch.as_tensor(smp["flat"], device=C[0].device)
+    got = tuple(p[idx].cpu().numpy() for p in C)
+    ref = smp["ref"]
+    return (ratio(got[0], got[1], ref[0], ref[1], smp["k"]),
+            componentwise(got[0], got[1], ref[0], ref[1], smp["absab"], smp["alpha"],
+                          smp["beta"], smp["cin"][0]))
+
+
+def verify_served(arena, samples=8, seed=0):
+    """Every served result of a request stream against the CPU oracle on
+    `samples` sampled entries per request (entries of the updated triangle
+    for Rsyrk); C before the update is the arena's reset value.  Returns the
+    worst normwise ratio (units of k 2^-104), the worst componentwise error
+    (units of 2^-104) and the number of requests over the tolerance."""
+    import numpy as np
+    import oracle
+    import torch
+    import workloads as W
+    from oracle.compare import componentwise, ratio
+    ab = tuple(x.cpu().numpy() for x in arena.ab)
+    plan, flat = [], []
+    for i, r in enumerate(arena.reqs):
+        gemm = r["kind"] == "gemm"
+        m, n, k = (r["m"] if gemm else r["n"]), r["n"], r["k"]
+        tri = None if gemm else r["uplo"]
+        ii, jj = W.sample_indices(m, n, samples, seed * 100003 + i, tri)
+        ii, jj = ii[:samples], jj[:samples]      # the random entries only
+        plan.append((ii, jj))
+        flat.append(arena.c_off[i] + ii + jj * m)
+    flat = np.concatenate(flat)
+    idx = torch.as_tensor(flat, device=arena.c[0].device)
+    got = tuple(p[idx].cpu().numpy() for p in arena.c)
+    cin = tuple(p[idx].cpu().numpy() for p in arena.c0)
+    worst_r, worst_c, over, pos = 0.0, 0.0, 0, 0
+    for i, r in enumerate(arena.reqs):
+        ii, jj = plan[i]
+        s = len(ii)
+        k = r["k"]
+        l = np.arange(k)[:, None]
+        A, lda, _, ldb, _, _ = arena.ptrs(i)
+        ao, bo = arena.a_off[i], arena.b_off[i]
+        if r["kind"] == "gemm":
+            ta, tb = r["transa"] != "N", r["transb"] != "N"
+            ia = ao + (l * lda + ii[None, :] if ta is False else l + ii[None, :] * lda)
+            ib = bo + (l + jj[None, :] * ldb if tb is False else jj[None, :] + l * ldb)
+        else:
+            tn = r["trans"] == "N"
+            ia = ao + (ii[None, :] + l * lda if tn else l + ii[None, :] * lda)
+            ib = ao + (jj[None, :] + l * lda if tn else l + jj[None, :] * lda)
+        As = tuple(np.ascontiguousarray(p[ia]).ravel() for p in ab)      # [l, t]
+        Bs = tuple(np.ascontiguousarray(p[ib].T).ravel() for p in ab)    # [t, l]
+        d = np.arange(s)
+        Cs = (np.zeros(s * s), np.zeros(s * s))
+        Cs[0][d + d * s] = cin[0][pos:pos + s]
+        Cs[1][d + d * s] = cin[1][pos:pos + s]
+        alpha, beta = arena.scal[i]
+        ref = oracle.rgemm_entries("N", "N", s, s, k, alpha, As, s, Bs, k, beta, Cs, s, d, d)
+        g = (got[0][pos:pos + s], got[1][pos:pos + s])
+        rr = ratio(g[0], g[1], ref[0], ref[1], k)
+        absab = np.abs(As[0]).reshape(k, s).T * np.abs(Bs[0]).reshape(s, k)
+        cc = componentwise(g[0], g[1], ref[0], ref[1], absab.sum(axis=1), alpha, beta,
+                           Cs[0][d + d * s])
+        worst_r, worst_c = max(worst_r, rr), max(worst_c, cc)
+        over += rr > RATIO_MAX
+        pos += s
+    return {"requests": len(arena.reqs), "samples_per_request": samples,
+            "worst_ratio": round(worst_r, 4), "worst_componentwise": round(worst_c, 2),
+            "over_tolerance": int(over)}
+
+
 def bench_syrk(h, args, stream):
+    """Rsyrk: the headline shape (U N, n = k = args.n) and every config-2
+    variant, uplo U/L x trans N/T x n in {2048, 8192} x k in {512, 8192},
+    with a random dd beta (C read) and the opposite triangle NaN-sentinelled.
+    dd-flops n(n+1)k."""
     import torch
     import workloads as W
     from paper_2109_13406_amd import binding as b
-    n = args.n
-    case = W.syrk_case_device(W.BASE_SEED + 2, "U", "N", n, n)
-    torch.cuda.synchronize()
+    out = {"variants": []}
+    sizes = [(nn, kk) for nn in (2048, args.n) for kk in (512, args.n)]
+    for (n, k) in sorted(set(sizes)):
+        for uplo in "UL":
+            for trans in "NT":
+                case = W.syrk_case_device(W.BASE_SEED + 2, uplo, trans, n, k)
+                torch.cuda.synchronize()
 
-    def step():
-        info = b.mpdd_Rsyrk(h, "U", "N", n, n, case["alpha"], case["A"], case["lda"],
-                            case["beta"], case["C"], case["ldc"], stream=stream)
-        if info != 0:
-            raise RuntimeError(f"mpdd_Rsyrk info={info}")
-
-    total, per = timed_calls(step, max(1, args.steps // 2), 1, stream)
-    t = sum(per) / len(per)
-    flops = float(n) * (n + 1) * n
-    del case
-    torch.cuda.empty_cache()
-    return {"workload": f"Rsyrk U N n={n} k={n} ld={W.ld_padded(n)}", "ms": round(t * 1e3, 3),
-            "dd_gflops": round(flops / t / 1e9, 1)}
+                def step():
+                    info = b.mpdd_Rsyrk(h, uplo, trans, n, k, case["alpha"], case["A"],
+                                        case["lda"], case["beta"], case["C"], case["ldc"],
+                                        stream=stream)
+                    if info != 0:
+                        raise RuntimeError(f"mpdd_Rsyrk info={info}")
+                steps = max(1, args.steps // 2) if n == k == args.n else 2
+                _, per = timed_calls(step, steps, 1, stream)
+                t = sum(per) / len(per)
+                rec = {"uplo": uplo, "trans": trans, "n": n, "k": k, "ms": round(t * 1e3, 3),
+                       "dd_gflops": round(float(n) * (n + 1) * k / t / 1e9, 1)}
+                out["variants"].append(rec)
+                if n == k == args.n and uplo == "U" and trans == "N":
+                    out["workload"] = f"Rsyrk U N n={n} k={k} ld={W.ld_padded(n)}"
+                    out["ms"], out["dd_gflops"] = rec["ms"], rec["dd_gflops"]
+                log(f"rsyrk {rec}")
+                del case
+                torch.cuda.empty_cache()
+    return out
 
 
 def bench_cgemm(h, args, stream):
@@ -278,64 +429,84 @@ def ratio_gpu(C, R, m, n, ldc, k):
     return float(torch.linalg.vector_norm(d)) / nr / (k * 2.0 ** -104)
 
 
-def bench_ozaki(h, args, stream, t_plain):
-    """Split forms at n: for each kind and input set, the smallest slice count
-    whose result agrees with the plain kernel's to <= 4 k 2^-104 (the plain
-    result is itself within ~0.01 of the oracle on these inputs), then timed."""
+def bench_ozaki(h, args, stream, t_plain_main):
+    """Split forms at n in {2048, args.n}, NN, both input sets (config 3).  For
+    each kind the slice count is searched upward from a small start until the
+    normwise error of sampled entries against the CPU oracle is <= 8 k 2^-104
+    (the entries and the inputs are those of the GPU test that repeats this
+    search), then that call is timed.  Reported per (kind, n, input set): the
+    slice count, the ratio and componentwise error against the oracle, the
+    ratio against the plain kernel's result (all entries), time and speedup
+    over the plain kernel."""
     import torch
     import workloads as W
     from paper_2109_13406_amd import binding as b
-    n = args.n
     out = {}
-    for dist in ("uniform", "wide"):
-        case = W.gemm_case_device(W.BASE_SEED + 3, "N", "N", n, n, n, dist=dist)
-        C0 = tuple(x.clone() for x in case["C"])
-        P = tuple(x.clone() for x in C0)
-        args_ = ("N", "N", n, n, n, case["alpha"], case["A"], case["lda"], case["B"], case["ldb"],
-                 case["beta"])
-        assert b.mpdd_Rgemm(h, *args_, P, case["ldc"], stream=stream) == 0
-        for kind, algo, rng_s in (("i8", b.MPDD_OZAKI_I8, range(13, 25)),
-                                  ("f64", b.MPDD_OZAKI_F64, range(4, 11))):
-            C = tuple(torch.empty_like(x) for x in C0)
-            found = None
-            for sl in rng_s:
-                for dst, src in zip(C, C0):
-                    dst.copy_(src)
-                info = b.mpdd_Rgemm_ex(h, dict(algo=algo, nslices=sl), *args_, C, case["ldc"],
-                                       stream=stream)
-                if info != 0:
-                    break
-                r = ratio_gpu(C, P, n, n, case["ldc"], n)
-                if r <= 4.0:
-                    found = (sl, r)
-                    break
-            if found is None:
-                out[f"{kind}_{dist}"] = {"nslices": None}
-                continue
-            sl, r = found
-
-            def step():
-                info = b.mpdd_Rgemm_ex(h, dict(algo=algo, nslices=sl), *args_, C, case["ldc"],
-                                       stream=stream)
-                if info != 0:
-                    raise RuntimeError(info)
-            _, per = timed_calls(step, 3, 1, stream)
-            t = sum(per) / len(per)
-            pairs = sl * (sl + 1) // 2
-            rec = {"nslices": sl, "ratio_vs_plain": round(r, 4), "ms": round(t * 1e3, 2),
-                   "dd_gflops": round(2.0 * n ** 3 / t / 1e9, 1),
-                   "speedup_vs_plain": round(t_plain / t, 3),
-                   "slice_products": pairs}
-            if kind == "i8":
-                rec["int8_tops_whole_call"] = round(pairs * 2.0 * n ** 3 / t / 1e12, 1)
-                rec["int8_peak_tops"] = INT8_PEAK_TOPS
+    kinds = (("i8", b.MPDD_OZAKI_I8, range(10, 25)), ("f64", b.MPDD_OZAKI_F64, range(3, 11)))
+    for n in sorted({2048, args.n}):
+        for dist in ("uniform", "wide"):
+            case = W.gemm_case_device(W.BASE_SEED + 3, "N", "N", n, n, n, dist=dist)
+            C0 = tuple(x.clone() for x in case["C"])
+            smp = oracle_sample(case, W.CONFIG3_SAMPLE, W.BASE_SEED + 3)
+            args_ = ("N", "N", n, n, n, case["alpha"], case["A"], case["lda"], case["B"],
+                     case["ldb"], case["beta"])
+            P = tuple(x.clone() for x in C0)
+            plain = lambda: b.mpdd_Rgemm(h, *args_, P, case["ldc"], stream=stream)
+            assert plain() == 0
+            plain_vs_oracle = oracle_compare(smp, P)
+            if n == args.n:
+                t_plain = t_plain_main
             else:
-                rec["fp64_mfma_tflops_whole_call"] = round(pairs * 2.0 * n ** 3 / t / 1e12, 2)
-                rec["fp64_peak_tflops"] = FP64_PEAK_TFLOPS
-            out[f"{kind}_{dist}"] = rec
-            log(f"ozaki {kind} {dist}: {rec}")
-        del case, C0, P, C
-        torch.cuda.empty_cache()
+                for dst, src in zip(P, C0):
+                    dst.copy_(src)
+                _, per = timed_calls(plain, 3, 1, stream)
+                t_plain = sum(per) / len(per)
+            C = tuple(torch.empty_like(x) for x in C0)
+            for kind, algo, rng_s in kinds:
+                found = None
+                for sl in rng_s:
+                    for dst, src in zip(C, C0):
+                        dst.copy_(src)
+                    info = b.mpdd_Rgemm_ex(h, dict(algo=algo, nslices=sl), *args_, C,
+                                           case["ldc"], stream=stream)
+                    if info != 0:
+                        break
+                    r, c = oracle_compare(smp, C)
+                    if r <= RATIO_MAX:
+                        found = (sl, r, c, ratio_gpu(C, P, n, n, case["ldc"], n))
+                        break
+                key = f"{kind}_{dist}" + ("" if n == args.n else f"_n{n}")
+                if found is None:
+                    out[key] = {"n": n, "nslices": None}
+                    continue
+                sl, r, c, rp = found
+
+                def step():
+                    info = b.mpdd_Rgemm_ex(h, dict(algo=algo, nslices=sl), *args_, C,
+                                           case["ldc"], stream=stream)
+                    if info != 0:
+                        raise RuntimeError(info)
+                _, per = timed_calls(step, 3, 1, stream)
+                t = sum(per) / len(per)
+                pairs = sl * (sl + 1) // 2
+                rec = {"n": n, "nslices": sl, "ratio_vs_oracle": round(r, 4),
+                       "componentwise_vs_oracle": round(c, 2),
+                       "oracle_sample": len(smp["flat"]),
+                       "ratio_vs_plain": round(rp, 4),
+                       "plain_ratio_vs_oracle": round(plain_vs_oracle[0], 4),
+                       "ms": round(t * 1e3, 2), "dd_gflops": round(2.0 * n ** 3 / t / 1e9, 1),
+                       "plain_ms": round(t_plain * 1e3, 2),
+                       "speedup_vs_plain": round(t_plain / t, 3), "slice_products": pairs}
+                if kind == "i8":
+                    rec["int8_tops_whole_call"] = round(pairs * 2.0 * n ** 3 / t / 1e12, 1)
+                    rec["int8_peak_tops"] = INT8_PEAK_TOPS
+                else:
+                    rec["fp64_mfma_tflops_whole_call"] = round(pairs * 2.0 * n ** 3 / t / 1e12, 2)
+                    rec["fp64_peak_tflops"] = FP64_PEAK_TFLOPS
+                out[key] = rec
+                log(f"ozaki {kind} {dist} n={n}: {rec}")
+            del case, C0, P, C
+            torch.cuda.empty_cache()
     return out
 
 
@@ -369,41 +540,69 @@ def bench_host(h, args):
             "host_bytes_moved": 16 * ld * n * 4}
 
 
-def bench_serve(h, args):
-    """Served request stream (Poisson arrivals) vs the same requests issued as
-    sequential plain calls; p50 / p99 latency and aggregate dd-GFLOPS."""
+def bench_serve(args):
+    """Served request stream (config 4: 10,000 requests, Poisson arrivals at
+    1000/s and at 100/s) vs the same requests issued as sequential plain
+    calls: p50 / p99 latency and aggregate dd-GFLOPS; every served result is
+    checked against the CPU oracle on sampled entries.  The handle loads the
+    autotuner's committed tile table for these shapes."""
     import torch
     import workloads as W
+    from paper_2109_13406_amd import binding as b
     from paper_2109_13406_amd.loadgen import Arena, percentiles, sequential, serve
-    out = {}
+    table = os.path.join(ROOT, "paper_2109_13406_amd", "tuning", "serve_gfx950.json")
+    tuned = os.path.exists(table)
+    h = b.mpdd_create(table if tuned else None)
+    out = {"tuned_tiles": tuned,
+           "tile_table": os.path.relpath(table, ROOT) if tuned else None}
+    arena = None
+    b2b = None
     for rate, count in ((1000.0, args.serve_count), (100.0, args.serve_count_slow)):
         reqs = W.request_stream(W.BASE_SEED + 4, count, rate)
-        arena = Arena(reqs, seed=W.BASE_SEED + 4)
+        if arena is None or len(arena.reqs) != count:
+            arena = Arena(reqs, seed=W.BASE_SEED + 4)
+            b2b = None
+        else:   # same sizes and operands, arrival times of this rate
+            assert all(x["kind"] == y["kind"] and x["n"] == y["n"] and x["k"] == y["k"]
+                       for x, y in zip(arena.reqs, reqs))
+            arena.reqs = reqs
         flops = sum(arena.flops(i) for i in range(count))
+        prog = lambda tag: (lambda i: log(f"serve {rate:.0f}/s {tag}: {i}/{count}"))
         arena.reset_c()
-        tm, wall = serve(h, arena, paced=True)
+        tm, wall = serve(h, arena, paced=True, progress=prog("served"))
+        check = verify_served(arena, samples=8, seed=W.BASE_SEED + 4)
+        log(f"serve {rate:.0f}/s oracle check: {check}")
         bad = sum(1 for t in tm if t["info"] != 0)
         lat = [t["end"] - t["arrival"] for t in tm]
         groups = len({t["group"] for t in tm})
         arena.reset_c()
-        slat, swall = sequential(h, arena, paced=True)
-        arena.reset_c()
-        tb, bwall = serve(h, arena, paced=False)
-        arena.reset_c()
-        _, sbwall = sequential(h, arena, paced=False)
+        slat, swall = sequential(h, arena, paced=True, progress=prog("sequential"))
+        if b2b is None:   # back-to-back: arrival times do not matter
+            arena.reset_c()
+            _, bwall = serve(h, arena, paced=False)
+            arena.reset_c()
+            _, sbwall = sequential(h, arena, paced=False)
+            b2b = (round(flops / bwall / 1e9, 1), round(flops / sbwall / 1e9, 1))
         rec = {"requests": count, "rate_per_s": rate, "failed": bad, "groups": groups,
                "served": {k: round(v * 1e3, 3) for k, v in percentiles(lat).items()},
                "sequential": {k: round(v * 1e3, 3) for k, v in percentiles(slat).items()},
                "latency_unit": "ms",
                "served_dd_gflops": round(flops / wall / 1e9, 1),
                "sequential_dd_gflops": round(flops / swall / 1e9, 1),
-               "back_to_back_served_dd_gflops": round(flops / bwall / 1e9, 1),
-               "back_to_back_sequential_dd_gflops": round(flops / sbwall / 1e9, 1),
-               "offered_dd_gflops": round(flops / reqs[-1]["arrival"] / 1e9, 1)}
+               "back_to_back_served_dd_gflops": b2b[0],
+               "back_to_back_sequential_dd_gflops": b2b[1],
+               "offered_dd_gflops": round(flops / reqs[-1]["arrival"] / 1e9, 1),
+               "served_worst_ratio": check["worst_ratio"],
+               "served_worst_componentwise": check["worst_componentwise"],
+               "served_over_tolerance": check["over_tolerance"],
+               "oracle_entries_per_request": check["samples_per_request"],
+               "requests_checked": check["requests"]}
         out[f"poisson_{int(rate)}"] = rec
         log(f"serve {rate}/s: {rec}")
-        del arena
-        torch.cuda.empty_cache()
+    del arena
+    torch.cuda.synchronize()
+    b.mpdd_destroy(h)
+    torch.cuda.empty_cache()
     return out
 
 
@@ -413,7 +612,9 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=8192)
-    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle timing")
+    ap.add_argument("--no-oracle", action="store_true",
+                    help="skip the oracle check of the headline product (profiling runs)")
     ap.add_argument("--sections", default="plain,sizes,syrk,cgemm,potrf,qd,ozaki,host,serve")
     ap.add_argument("--tile", type=int, default=-1,
                     help="tile-table entry for the plain product (-1: the library's choice)")
@@ -421,7 +622,7 @@ def main():
                     help="first run one device-to-device copy of BYTES bytes (a kernel of known "
                          "traffic, to calibrate the HBM byte counters of a profiling pass)")
     ap.add_argument("--serve-count", type=int, default=10000)
-    ap.add_argument("--serve-count-slow", type=int, default=1000)
+    ap.add_argument("--serve-count-slow", type=int, default=10000)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -429,6 +630,7 @@ def main():
         sys.exit(2)
 
     import torch
+    import workloads as W
     from paper_2109_13406_amd import binding as b
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
@@ -446,20 +648,15 @@ def main():
         del src, dst
         torch.cuda.empty_cache()
 
-    case, total, per = bench_plain(h, args, stream)
+    case, total, per, step = bench_plain(h, args, stream)
     t_step = total / args.steps
     flops = 2.0 * n * n * n
     value = flops / t_step / 1e9
     t_kernel = sum(per) / len(per)
     madds = float(n) ** 3
-    achieved = 2.0 * OPS_PER_MADD_ALG * madds / t_kernel / 1e12
-    roof = {"bound": "alu", "achieved": round(achieved, 2), "peak": FP64_PEAK_TFLOPS,
-            "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
-            "traffic": traffic_record("dd_gemm_nn8192"),
-            "kernel": "dd_gemm_kernel (plain, NN)",
-            "kernel_ms": round(t_kernel * 1e3, 3),
-            "issue_frac": round(OPS_PER_MADD_LEAN * madds / t_kernel / (FP64_PEAK_TFLOPS / 2 * 1e12), 4)}
-    log(f"plain NN {n}: {t_step*1e3:.2f} ms/step, {value:.1f} dd-GFLOPS, kernel {t_kernel*1e3:.2f} ms")
+    roof = plain_roofline(madds, t_kernel)
+    log(f"plain NN {n}: {t_step*1e3:.2f} ms/step, {value:.1f} dd-GFLOPS, "
+        f"kernel {t_kernel*1e3:.2f} ms")
 
     out = {"metric": METRIC, "value": round(value, 1), "unit": "dd-GFLOPS", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(t_step * 1e3, 3),
@@ -469,6 +666,18 @@ def main():
                                   "(float64 hi/lo planes, hi~U[-1,1), plain form)",
                       "m": n, "n": n, "k": n, "algo": "plain"},
            "roofline": roof}
+    if not args.no_oracle:
+        # one more call of the timed product from its current C, checked on
+        # sampled entries against the CPU oracle
+        smp = oracle_sample(case, 256, W.BASE_SEED + 1)
+        step()
+        torch.cuda.synchronize()
+        r, c = oracle_compare(smp, case["C"])
+        out["parity"] = {"oracle_sample": len(smp["flat"]), "ratio": round(r, 4),
+                         "componentwise": round(c, 2), "bound": RATIO_MAX,
+                         "ratio_unit": "k * 2^-104 (normwise, Frobenius)",
+                         "componentwise_unit": "2^-104 of |alpha||A||B| + |beta||C|"}
+        log(f"plain parity: {out['parity']}")
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(case, n)
         log(f"cpu baseline: {out['cpu_baseline']}")
@@ -476,7 +685,6 @@ def main():
     torch.cuda.empty_cache()
     if "syrk" in sections:
         out["rsyrk"] = bench_syrk(h, args, stream)
-        log(f"rsyrk: {out['rsyrk']}")
     if "sizes" in sections:
         out["rgemm_sizes"] = bench_sizes(h, args, stream)
     if "qd" in sections:
@@ -494,7 +702,7 @@ def main():
         out["host_api"] = bench_host(h, args)
         log(f"host api: {out['host_api']}")
     if "serve" in sections:
-        out["serving"] = bench_serve(h, args)
+        out["serving"] = bench_serve(args)
     out["context"] = {"paper_dd_rgemm_gflops": {"A100": 592, "V100": 435},
                       "paper_dd_rsyrk_gflops": {"V100": 428},
                       "paper_dd_rgemm_gflops_with_transfer": {"V100": 318},

@@ -108,8 +108,10 @@ int mpdd_Rsyrk(mpdd_handle h, const char *uplo, const char *trans, mpdd_int n, m
  * HOST pointers to mpdd_dd arrays.  The call copies the operands to the
  * device, runs mpdd_Rgemm / mpdd_Rsyrk, copies C back and returns when C is
  * complete (synchronous).  Same info codes and BLAS semantics as the device
- * calls; the whole of C (ldc x n) is copied both ways, so padding rows and
- * (Rsyrk) the opposite triangle come back unchanged.  Scratch device memory
+ * calls.  Every array is accessed over its BLAS extent only, ld*(cols-1) + rows
+ * entries (a tightly sized array is enough); C is copied both ways over that
+ * extent, so padding rows inside it and (Rsyrk) the opposite triangle come
+ * back unchanged, and nothing past it is read or written.  Scratch device memory
  * is allocated and freed inside the call.  Copies go through a ring of four
  * 16 MiB pinned host buffers and three copy threads owned by the handle
  * (created by its first host-pointer call, released by mpdd_destroy); the
@@ -275,7 +277,8 @@ int mpdd_Rpotrf_nb(mpdd_handle h, const char *uplo, mpdd_int n, double *A_hi, do
 
 /* Digit widths (first, later) of a split form for k and nslices.
  * Returns 0, or MPDD_ERR_UNSUPPORTED when no exact width exists (INT8 needs
- * nslices*k <= 2^19). */
+ * nslices*k < 2^19, so that every anti-diagonal sum, at most
+ * nslices*k*64^2 in magnitude, stays below 2^31). */
 int mpdd_ozaki_digit_widths(int algo, mpdd_int k, int nslices, int *wfirst, int *w);
 
 /* Scale exponents and digit slices of a "row operand" R (rows x k): element
@@ -306,7 +309,10 @@ int mpdd_ozaki_split(mpdd_handle h, int algo, const char *trans, mpdd_int rows, 
  * tile (the server uses the handle's tuned tile, restricted to tile-table
  * entries 2 and 4: 32 x 32 and 64 x 64 x 16).  Operands stay where the
  * caller put them (device memory) and must stay valid until the request
- * completes.  A group of one request is launched as a plain tile kernel.
+ * completes.  A group of one request is launched as a plain tile kernel;
+ * when the server is idle (nothing queued or admitted, a slot free) and the
+ * submitting thread has the server's device current, submit launches the
+ * request itself instead of handing it to the scheduler thread.
  * The scheduler thread polls (yielding its core) while work is in flight and
  * for 50 ms after its last activity, then sleeps until the next submission.
  *

@@ -1,10 +1,11 @@
 """mpdd: double-double Rgemm / Rsyrk on AMD Instinct MI355X (gfx950).
 
 The compute path is libmpdd.so (hand-written HIP kernels behind the C ABI in
-include/mpdd.h); `binding` marshals arguments to it with ctypes, and
-`device` offers torch-tensor helpers (torch supplies device memory and
-streams only).  Importing this package does not load the library; the first
-call does, and raises if it is missing.
+include/mpdd.h); `binding` marshals arguments to it with ctypes (torch
+supplies device memory and streams only); `loadgen` drives the request
+server and `autotune` writes tile tables for it.  Importing this package
+does not load the library; the first call does, and raises if it is
+missing.
 """
 from .binding import (MPDD_OZAKI_F64, MPDD_OZAKI_I8, MPDD_PLAIN, MPDD_PLAIN_ACCURATE,  # noqa
                       load, mpdd_create, mpdd_destroy, mpdd_Rgemm, mpdd_Rgemm_ex, mpdd_Rsyrk,

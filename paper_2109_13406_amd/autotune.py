@@ -75,6 +75,16 @@ def tune_shape(h, op, ta, tb, m, n, k, reps=3, splits=(1, 2, 4, 8, 16), verbose=
     return best, results
 
 
+SERVE_TILES = (2, 4)   # tile entries the request server's grouped launches run (unsplit)
+
+
+def serve_best(results):
+    """Fastest unsplit candidate among the tiles the server runs (None if
+    none was timed)."""
+    cand = [r for r in results if r["splitk"] == 1 and r["tile"] in SERVE_TILES]
+    return min(cand, key=lambda r: r["seconds"]) if cand else None
+
+
 def tune_ozaki(h, n, kind="i8", slices=(13, 16), reps=2, verbose=True):
     """Time the split form's product-kernel variants (tile_id) at m = n = k."""
     if ROOT not in sys.path:
@@ -123,14 +133,16 @@ def serve_shapes():
 
 
 def write_cache(path, entries):
+    """One entry object per line: op, flags, shape buckets, the stand-alone
+    (tile, splitk) and, for the request server, the best unsplit served tile."""
     with open(path, "w") as f:
         f.write('{"version": 1, "arch": "gfx950", "entries": [\n')
         lines = []
         for e in entries:
             lines.append('{"op": "%s", "trans": "%s", "mb": %d, "nb": %d, "kb": %d, "tile": %d, '
-                         '"splitk": %d, "nslices": 0, "dd_gflops": %.1f}'
+                         '"splitk": %d, "nslices": 0, "serve_tile": %d, "dd_gflops": %.1f}'
                          % (e["op"], e["trans"], e["mb"], e["nb"], e["kb"], e["tile"],
-                            e["splitk"], e["dd_gflops"]))
+                            e["splitk"], e.get("serve_tile", -1), e["dd_gflops"]))
         f.write(",\n".join(lines))
         f.write("\n]}\n")
 
@@ -158,10 +170,12 @@ def main():
         best, res = tune_shape(h, op, ta, tb, m, n, k, reps=args.reps)
         print(f"BEST {op} {ta}{tb} {m}x{n}x{k}: tile {best['tile']} split {best['splitk']} "
               f"{best['dd_gflops']:.1f} dd-GFLOPS", flush=True)
+        sb = serve_best(res)
         combos = ("NN", "NT", "TN", "TT") if op == "gemm" else ("NT", "TN")
         for tr in combos:
             entries.append(dict(op=op, trans=tr, mb=bucket(m), nb=bucket(n), kb=bucket(k),
                                 tile=best["tile"], splitk=best["splitk"],
+                                serve_tile=sb["tile"] if sb else -1,
                                 dd_gflops=best["dd_gflops"]))
         report.append(dict(op=op, m=m, n=n, k=k, best=best, all=res))
         torch.cuda.empty_cache()

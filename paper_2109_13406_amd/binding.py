@@ -320,6 +320,30 @@ def mpdd_Rgemm_ex(h, opts, transa, transb, m, n, k, alpha, A, lda, B, ldb, beta,
     return load().mpdd_Rgemm_ex(h, ctypes.byref(o) if o is not None else None, *args)
 
 
+def prepared_Rgemm_ex(h, opts, transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc,
+                      stream=None):
+    """The same call as mpdd_Rgemm_ex with every argument checked and
+    marshalled now: returns a callable that issues it (returning info).  For
+    callers that issue a prepared call at a later moment (a load generator
+    pacing requests) without paying the marshalling then."""
+    import functools
+    a, bt = _dd(alpha), _dd(beta)
+    pa, pb, pc = _gemm_ptrs(2, transa, transb, m, n, k, _dd_zero(a), _dd_one(bt), A, lda, B, ldb,
+                            C, ldc)
+    o = opts if opts is None or isinstance(opts, mpdd_opts) else _opts(**opts)
+    return functools.partial(load().mpdd_Rgemm_ex, h, ctypes.byref(o) if o is not None else None,
+                             _flag(transa), _flag(transb), m, n, k, a, pa[0], pa[1], lda, pb[0],
+                             pb[1], ldb, bt, pc[0], pc[1], ldc, _stream(stream))
+
+
+def prepared_Rsyrk_ex(h, opts, uplo, trans, n, k, alpha, A, lda, beta, C, ldc, stream=None):
+    """As prepared_Rgemm_ex, for mpdd_Rsyrk_ex."""
+    import functools
+    o = opts if opts is None or isinstance(opts, mpdd_opts) else _opts(**opts)
+    return functools.partial(load().mpdd_Rsyrk_ex, h, ctypes.byref(o) if o is not None else None,
+                             *_syrk_args(uplo, trans, n, k, alpha, A, lda, beta, C, ldc, stream))
+
+
 def _cgemm_args(transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, stream):
     a, bt = _ddc(alpha), _ddc(beta)
     pa, pb, pc = _gemm_ptrs(4, transa, transb, m, n, k, _dd_zero(a.re) and _dd_zero(a.im),
@@ -530,6 +554,21 @@ def mpdd_server_submit(s, req):
     if info != 0:
         raise RuntimeError(f"mpdd_server_submit failed: {info}")
     return t.value
+
+
+def prepared_submit(s):
+    """A submit function for server s with its ticket buffer marshalled once:
+    submit(req) -> ticket (req from make_request)."""
+    t = ctypes.c_uint64()
+    tref = ctypes.byref(t)
+    fn = load().mpdd_server_submit
+
+    def submit(req):
+        info = fn(s, ctypes.byref(req), tref)
+        if info != 0:
+            raise RuntimeError(f"mpdd_server_submit failed: {info}")
+        return t.value
+    return submit
 
 
 def mpdd_server_wait(s, ticket):

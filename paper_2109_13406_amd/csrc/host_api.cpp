@@ -18,6 +18,7 @@
 #include <vector>
 
 #include "../../include/mpdd.h"
+#include "extent.hpp"
 #include "kernels.hpp"
 #include "tuner.hpp"
 
@@ -307,7 +308,7 @@ int mpdd_Rgemm_host(mpdd_handle h, const char* transa, const char* transb, mpdd_
   // B chunk: columns j0.. of op(B): for 'N' the columns of B, for 'T' its rows
   const size_t nb_chunk = use_ab ? (notb ? (size_t)ldb * cw : (size_t)cw * k) : 0;
   const size_t nc_chunk = (size_t)ldc * cw;
-  if (!rc && use_ab) rc = stage_alloc(sa, (size_t)lda * (size_t)ncola, sx, handle_pool(h));
+  if (!rc && use_ab) rc = stage_alloc(sa, mpdd::blas_extent(lda, nrowa, ncola), sx, handle_pool(h));
   for (int t = 0; t < 2 && !rc; ++t) {
     rc = stage_alloc(sbuf[t], nb_chunk, sx, handle_pool(h));
     if (!rc) rc = stage_alloc(scb[t], nc_chunk, sx, handle_pool(h));
@@ -318,7 +319,7 @@ int mpdd_Rgemm_host(mpdd_handle h, const char* transa, const char* transb, mpdd_
     const int t = (int)(c & 1);
     if (use_ab) {
       if (notb) {
-        sbuf[t].n = (size_t)ldb * w;
+        sbuf[t].n = mpdd::blas_extent(ldb, k, w);
         if (int r = upload(sbuf[t], B + (size_t)j0 * ldb, sx, stg)) return r;
       } else {
         // rows j0 .. j0+w of B (k columns): a 2-D copy into a compact w x k block
@@ -330,7 +331,7 @@ int mpdd_Rgemm_host(mpdd_handle h, const char* transa, const char* transb, mpdd_
           return MPDD_ERR_HIP;
       }
     }
-    scb[t].n = (size_t)ldc * w;
+    scb[t].n = mpdd::blas_extent(ldc, m, w);
     if (int r = upload(scb[t], C + (size_t)j0 * ldc, sx, stg)) return r;
     return hipEventRecord(ev_in[t], sx) == hipSuccess ? 0 : MPDD_ERR_HIP;
   };
@@ -357,7 +358,7 @@ int mpdd_Rgemm_host(mpdd_handle h, const char* transa, const char* transb, mpdd_
     const mpdd_dd one{1.0, 0.0};
     for (int64_t sl = 0; sl < nks; ++sl) {
       const int64_t k0 = sl * kcs, kk = std::min<int64_t>(kcs, k - k0);
-      const size_t off = (size_t)k0 * lda, cnt = (size_t)kk * lda;
+      const size_t off = (size_t)k0 * lda, cnt = mpdd::blas_extent(lda, m, kk);
       if (int r = stg->h2d(sa.pairs + off, A + off, cnt * sizeof(mpdd_dd), sx)) return r;
       if (mpdd::launch_split_pairs((const double*)(sa.pairs + off), sa.hi + off, sa.lo + off,
                                    (int64_t)cnt, sx) != hipSuccess ||
@@ -433,8 +434,8 @@ int mpdd_Rsyrk_host(mpdd_handle h, const char* uplo, const char* trans, mpdd_int
   if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return MPDD_ERR_HIP;
   Staged bufs[2];
   int rc = 0;
-  const size_t na = use_a ? (size_t)lda * (size_t)ncola : 0;
-  const size_t nc = (size_t)ldc * (size_t)n;
+  const size_t na = use_a ? mpdd::blas_extent(lda, nrowa, ncola) : 0;
+  const size_t nc = mpdd::blas_extent(ldc, n, n);
   if (!rc) rc = stage_alloc(bufs[0], na, st, handle_pool(h));
   if (!rc) rc = stage_alloc(bufs[1], nc, st, handle_pool(h));
   if (!rc) rc = upload(bufs[0], A, st, stg);

@@ -268,6 +268,7 @@ int mpdd_create(mpdd_handle* h, const char* tuner_cache_path) {
   }
   if (tuner_cache_path && tuner_cache_path[0]) {
     if (!s->tune.load(tuner_cache_path)) {
+      (void)hipMemPoolDestroy(s->pool);
       delete s;
       return MPDD_ERR_ARG;
     }

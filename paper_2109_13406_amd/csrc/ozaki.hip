@@ -644,8 +644,8 @@ static bool digit_widths(int algo, int64_t k, int nslices, int& wfirst, int& w) 
   if (algo == MPDD_OZAKI_I8) {
     wfirst = 6;
     w = 7;
-    // |X_d| <= nslices * k * 64^2 must stay below 2^31
-    return (int64_t)nslices * k <= ((int64_t)1 << 19);
+    // |X_d| <= nslices * k * 64^2 must stay below 2^31, i.e. nslices * k < 2^19
+    return (int64_t)nslices * k < ((int64_t)1 << 19);
   }
   int64_t terms = std::max<int64_t>(1, (int64_t)nslices * k);
   int lg = 0;

@@ -17,6 +17,8 @@
 //      one request launches its tile kernel directly.  Groups on different
 //      slots overlap on the device, so requests that arrive while others run
 //      start as soon as a slot and budget free up.
+// When the server is idle, a submitted request is launched by the submitting
+// thread itself, as a group of one (no hand-off to the scheduler).
 // The thread polls without sleeping while groups are in flight and for
 // kIdleSpin seconds after its last activity (so steady traffic never waits
 // for a thread wake-up); after that it sleeps until the next submission.
@@ -202,7 +204,8 @@ int serve_tile_index(mpdd_server_s* s, const mpdd_request& r) {
     const bool syrk = r.op == MPDD_OP_SYRK;
     const bool ta = syrk ? !lsame(r.flag2, 'N') : !lsame(r.flag1, 'N');
     const bool tb = syrk ? !ta : !lsame(r.flag2, 'N');
-    if (handle_tune_lookup(s->h, syrk ? 1 : 0, ta, tb, m, n, k, e)) tile = e.tile;
+    if (handle_tune_lookup(s->h, syrk ? 1 : 0, ta, tb, m, n, k, e))
+      tile = e.serve_tile >= 0 ? e.serve_tile : e.tile;
   }
   if (tile < 0) tile = default_tile(m, n, k, r.op == MPDD_OP_SYRK);
   for (int i = 0; i < kNumServeTiles; ++i)
@@ -518,6 +521,44 @@ void scheduler(mpdd_server_s* s) {
   }
 }
 
+// An idle server (nothing queued or admitted) with a free slot and room in
+// the budget launches a request from the submitting thread itself: the
+// request skips the hand-off to the scheduler, which then only has to see it
+// complete.  FIFO order holds because nothing waits ahead of it.  Requests
+// with an injected failure take the scheduler's path.  Called with the lock
+// held; true when the request was launched (or failed at launch).
+bool launch_from_submit(mpdd_server_s* s, Req* q) {
+  if (!s->pending.empty() || !s->admitted.empty() || q->r.inject != MPDD_INJECT_NONE) return false;
+  if (s->inflight_count >= s->max_inflight || s->inflight_bytes + q->bytes > s->budget ||
+      q->items > kMaxGroupItems)
+    return false;
+  if (!s->fake) {
+    // the slot streams belong to the server's device; a caller thread with
+    // another device current goes through the scheduler (which set it)
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev != s->device) return false;
+  }
+  Slot* free_sl = nullptr;
+  for (Slot& sl : s->slots)
+    if (!sl.busy) { free_sl = &sl; break; }
+  if (!free_sl) return false;
+  q->t.admit = now_s();
+  s->inflight_bytes += q->bytes;
+  s->inflight_count += 1;
+  std::vector<Req*> g{q};
+  const int rc = launch_group(s, *free_sl, g);
+  if (rc != 0) {
+    finish(s, q, rc, now_s());
+    release(s, q);
+    s->cv_done.notify_all();
+  } else {
+    free_sl->reqs = g;
+    free_sl->busy = true;
+  }
+  s->cv_sched.notify_one();   // the scheduler watches for its completion
+  return true;
+}
+
 }  // namespace
 
 extern "C" {
@@ -619,6 +660,7 @@ int mpdd_server_submit(mpdd_server s, const mpdd_request* r, uint64_t* ticket) {
   const int64_t tm = (m + ti->bm - 1) / ti->bm, tn = (n + ti->bn - 1) / ti->bn;
   q->items = (r->op == MPDD_OP_SYRK) ? tm * (tm + 1) / 2 : tm * tn;
   q->flops = (r->op == MPDD_OP_SYRK) ? (double)n * (n + 1) * k : 2.0 * m * n * k;
+  if (launch_from_submit(s, q)) return 0;
   s->pending.push_back(q);
   s->cv_sched.notify_one();
   return 0;

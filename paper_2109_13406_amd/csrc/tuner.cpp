@@ -44,6 +44,14 @@ bool TuneTable::load(const char* path) {
     e.tile = tile;
     e.splitk = splitk;
     e.nslices = nsl;
+    if (const char* st = std::strstr(p, "\"serve_tile\":")) {
+      int t = -1;
+      if (std::sscanf(st, "\"serve_tile\": %d", &t) != 1 || (t >= 0 && !tile_info(t))) {
+        ok = false;
+        break;
+      }
+      e.serve_tile = t;
+    }
     map_[Key(code, tr[0] == 'T', tr[1] == 'T', mb, nb, kb)] = e;
   }
   std::fclose(f);

@@ -13,9 +13,10 @@
 namespace mpdd {
 
 struct TuneEntry {
-  int tile = -1;
-  int splitk = 0;
+  int tile = -1;         // stand-alone calls: tile-table entry
+  int splitk = 0;        // stand-alone calls: k-split
   int nslices = 0;
+  int serve_tile = -1;   // request server (unsplit grouped launches): tile entry, -1 = tile
 };
 
 // Shape bucket: ceil(log2(x)) (0 for x <= 1).

@@ -6,7 +6,8 @@ import sys
 import numpy as np
 
 import oracle
-from oracle.compare import bits, ratio
+import workloads as W
+from oracle.compare import bits, componentwise, ratio
 
 RESULTS = os.environ.get("MPDD_PARITY_LOG", os.path.join(
     os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "_build", "parity.log"))
@@ -87,11 +88,49 @@ def entries_mask(m, n, ldc, tri=None):
     return (i + j * ldc)[sel]
 
 
-def compare_full(name, G, O, m, n, k, ldc, tri=None, check_rest=True, C0=None):
-    """Ratio over the stored entries; everything else bit-identical to C0."""
+def op_abs(case, which):
+    """|op(X)| of the hi plane as a dense numpy array: op(A) m x k (which
+    "A"), op(B) k x n ("B"); for an Rsyrk case op(A) n x k and op(B) its
+    transpose."""
+    if "uplo" in case:
+        n, k, ld, tr = case["n"], case["k"], case["lda"], case["trans"].upper()
+        X = np.abs(case["A"][0][: ld * (k if tr == "N" else n)])
+        X = X.reshape(-1, ld).T              # column-major storage rows x cols
+        opa = X[:n, :k] if tr == "N" else X[:k, :n].T
+        return opa if which == "A" else opa.T
+    m, n, k = case["m"], case["n"], case["k"]
+    if which == "A":
+        ld, tr, rows, cols = case["lda"], case["transa"].upper(), m, k
+        X = case["A"][0]
+    else:
+        ld, tr, rows, cols = case["ldb"], case["transb"].upper(), k, n
+        X = case["B"][0]
+    sr, sc = (rows, cols) if tr == "N" else (cols, rows)
+    S = np.abs(X[: ld * sc]).reshape(sc, ld).T[:sr, :]
+    return S if tr == "N" else S.T
+
+
+def comp_full(G, O, case, m, n, ldc, tri=None):
+    """Componentwise error (units of 2^-104) over the stored entries."""
+    if min(m, n, case["k"]) == 0:
+        return 0.0
+    absab = op_abs(case, "A") @ op_abs(case, "B")
+    i, j = np.meshgrid(np.arange(m), np.arange(n), indexing="ij")
+    sel = np.ones_like(i, dtype=bool) if tri is None else (i <= j if tri == "U" else i >= j)
+    idx = (i + j * ldc)[sel]
+    return componentwise(G[0][idx], G[1][idx], O[0][idx], O[1][idx], absab[sel],
+                         case["alpha"], case["beta"], case["C"][0][idx])
+
+
+def compare_full(name, G, O, m, n, k, ldc, tri=None, check_rest=True, C0=None, case=None):
+    """Ratio over the stored entries; everything else bit-identical to C0.
+    With the case's inputs, the componentwise error is logged too."""
     idx = entries_mask(m, n, ldc, tri)
     r = ratio(G[0][idx], G[1][idx], O[0][idx], O[1][idx], k)
-    log(f"PARITY {name} ratio={r:.3g}")
+    extra = ""
+    if case is not None:
+        extra = f" comp={comp_full(G, O, case, m, n, ldc, tri):.3g}"
+    log(f"PARITY {name} ratio={r:.3g}{extra}")
     if check_rest and C0 is not None:
         rest = np.ones(G[0].shape[0], bool)
         rest[idx] = False
@@ -101,55 +140,21 @@ def compare_full(name, G, O, m, n, k, ldc, tri=None, check_rest=True, C0=None):
 
 
 def sample_indices(m, n, count, seed, tri=None):
-    """Random entries plus the corners and edges of the matrix (ragged tails
-    and tile boundaries live there)."""
-    rng = np.random.default_rng(seed)
-    ii = list(rng.integers(0, m, count))
-    jj = list(rng.integers(0, n, count))
-    for i in (0, m - 1, m // 2):
-        for j in (0, n - 1, n // 2, min(n - 1, 63), min(n - 1, 64)):
-            ii.append(i)
-            jj.append(j)
-    ii, jj = np.array(ii), np.array(jj)
-    if tri == "U":
-        sw = ii > jj
-        ii[sw], jj[sw] = jj[sw].copy(), ii[sw].copy()
-    elif tri == "L":
-        sw = ii < jj
-        ii[sw], jj[sw] = jj[sw].copy(), ii[sw].copy()
-    return ii, jj
+    return W.sample_indices(m, n, count, seed, tri)
 
 
 # ---- full-size cases checked on sampled entries --------------------------------------
 
-def _gather_rows_opA(Ah, ld, trans, ii, k):
-    """Host array (k, s) with [l, t] = op(A)(ii[t], l) for a device plane."""
-    import torch
-    idx = torch.as_tensor(ii, device=Ah.device)
-    if not trans:                       # A[i + l*ld]
-        v = Ah[: ld * k].view(k, ld)[:, idx]
-    else:                               # A[l + i*ld]
-        rows = int(ii.max()) + 1
-        v = Ah[: ld * rows].view(rows, ld)[idx, :k].T
-    return v.contiguous().cpu().numpy()
+_gather_rows_opA = W.gather_op_rows
+_gather_cols_opB = W.gather_op_cols
 
 
-def _gather_cols_opB(Bh, ld, trans, jj, k):
-    """Host array (s, k) with [t, l] = op(B)(l, jj[t])."""
-    import torch
-    idx = torch.as_tensor(jj, device=Bh.device)
-    if not trans:                       # B[l + j*ld]
-        cols = int(jj.max()) + 1
-        v = Bh[: ld * cols].view(cols, ld)[idx, :k]
-    else:                               # B[j + l*ld]
-        v = Bh[: ld * k].view(k, ld)[:, idx].T
-    return v.contiguous().cpu().numpy()
-
-
-def sampled_oracle(transa, transb, k, alpha, A, lda, B, ldb, beta, cin, ii, jj):
+def sampled_oracle(transa, transb, k, alpha, A, lda, B, ldb, beta, cin, ii, jj,
+                   with_abs=False):
     """Oracle values of the sampled entries (ii[t], jj[t]) of an update whose
     operands live on the device; cin = (hi, lo) host values of C at those
-    entries before the update."""
+    entries before the update.  with_abs: also return (|op(A)| |op(B)|) at
+    those entries (hi parts, binary64), the componentwise denominator."""
     s = len(ii)
     ta, tb = transa.upper() != "N", transb.upper() != "N"
     As = tuple(np.ascontiguousarray(_gather_rows_opA(x, lda, ta, ii, k)).ravel() for x in A)
@@ -158,7 +163,11 @@ def sampled_oracle(transa, transb, k, alpha, A, lda, B, ldb, beta, cin, ii, jj):
     d = np.arange(s)
     Cs[0][d + d * s] = cin[0]
     Cs[1][d + d * s] = cin[1]
-    return oracle.rgemm_entries("N", "N", s, s, k, alpha, As, s, Bs, k, beta, Cs, s, d, d)
+    ref = oracle.rgemm_entries("N", "N", s, s, k, alpha, As, s, Bs, k, beta, Cs, s, d, d)
+    if not with_abs:
+        return ref
+    absab = np.einsum("lt,tl->t", np.abs(As[0].reshape(k, s)), np.abs(Bs[0].reshape(s, k)))
+    return ref, absab
 
 
 def gather(pair, flat_idx):
@@ -182,10 +191,12 @@ def sampled_gemm_check(h, name, case, opts=None, count=192, seed=0):
     assert info == 0, info
     torch.cuda.synchronize()
     got = gather(case["C"], flat)
-    ref = sampled_oracle(case["transa"], case["transb"], k, case["alpha"], case["A"],
-                         case["lda"], case["B"], case["ldb"], case["beta"], cin, ii, jj)
+    ref, absab = sampled_oracle(case["transa"], case["transb"], k, case["alpha"], case["A"],
+                                case["lda"], case["B"], case["ldb"], case["beta"], cin, ii, jj,
+                                with_abs=True)
     r = ratio(got[0], got[1], ref[0], ref[1], k)
-    log(f"PARITY {name} sampled({len(ii)}) ratio={r:.3g}")
+    c = componentwise(got[0], got[1], ref[0], ref[1], absab, case["alpha"], case["beta"], cin[0])
+    log(f"PARITY {name} sampled({len(ii)}) ratio={r:.3g} comp={c:.3g}")
     return r
 
 
@@ -205,10 +216,12 @@ def sampled_syrk_check(h, name, case, opts=None, count=192, seed=0):
     torch.cuda.synchronize()
     got = gather(case["C"], flat)
     tr = case["trans"].upper()
-    ref = sampled_oracle(tr, "T" if tr == "N" else "N", k, case["alpha"], case["A"],
-                         case["lda"], case["A"], case["lda"], case["beta"], cin, ii, jj)
+    ref, absab = sampled_oracle(tr, "T" if tr == "N" else "N", k, case["alpha"], case["A"],
+                                case["lda"], case["A"], case["lda"], case["beta"], cin, ii, jj,
+                                with_abs=True)
     r = ratio(got[0], got[1], ref[0], ref[1], k)
-    log(f"PARITY {name} sampled({len(ii)}) ratio={r:.3g}")
+    c = componentwise(got[0], got[1], ref[0], ref[1], absab, case["alpha"], case["beta"], cin[0])
+    log(f"PARITY {name} sampled({len(ii)}) ratio={r:.3g} comp={c:.3g}")
     return r
 
 

@@ -200,3 +200,20 @@ def test_qgemm_info_codes_before_handle(lib):
     assert q(m=3, lda=2) == pos[("gemm", "lda")]
     assert q(k=3, ldb=2) == pos[("gemm", "ldb")]
     assert q(m=3, lda=3, ldc=2) == pos[("gemm", "ldc")]
+
+
+def test_int8_digit_width_guard_is_strict():
+    """INT8 split form: every anti-diagonal sum is at most nslices*k*64^2 in
+    magnitude and must stay below 2^31, so nslices*k must be below 2^19;
+    s*k = 2^19 is rejected, one less is accepted."""
+    from paper_2109_13406_amd import binding as b
+    wf, w = ctypes.c_int(), ctypes.c_int()
+    lib = b.load()
+    for s, k, ok in ((16, 1 << 15, False), (8, 1 << 16, False), (1, 1 << 19, False),
+                     (16, (1 << 15) - 1, True), (13, 8192, True), (1, (1 << 19) - 1, True)):
+        rc = lib.mpdd_ozaki_digit_widths(b.MPDD_OZAKI_I8, k, s, ctypes.byref(wf), ctypes.byref(w))
+        assert (rc == 0) == ok, (s, k, rc)
+        if not ok:
+            assert rc == b.MPDD_ERR_UNSUPPORTED
+        else:
+            assert (wf.value, w.value) == (6, 7)

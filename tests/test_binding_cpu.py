@@ -58,3 +58,23 @@ def test_host_pairs_checked():
     with pytest.raises(ValueError, match="touches"):
         b.mpdd_Rgemm_host(None, "N", "N", 3, 3, 3, 1.0, np.zeros(16), 3, np.zeros(18), 3, 0.0,
                           np.zeros(18), 3)
+
+
+def test_library_extent_helper_matches_binding(tmp_path):
+    """The host-pointer calls size every copy with one C++ helper
+    (csrc/extent.hpp); it must give the same extents as the binding's check,
+    ld*(cols-1) + rows, and 0 for an empty matrix."""
+    import os
+    import subprocess
+    cases = [(5, 5, 3), (8195, 8192, 8192), (7, 3, 1), (4, 0, 5), (4, 3, 0), (1, 1, 1),
+             (1100, 1000, 137)]
+    src = tmp_path / "extent_main.cpp"
+    inc = os.path.join(os.path.dirname(b.__file__), "csrc")
+    body = "".join(f'  std::printf("%zu\\n", mpdd::blas_extent({ld}, {r}, {c}));\n'
+                   for ld, r, c in cases)
+    src.write_text('#include <cstdio>\n#include "extent.hpp"\nint main() {\n' + body + "}\n")
+    exe = tmp_path / "extent_main"
+    subprocess.run(["g++", "-std=c++17", "-I", inc, str(src), "-o", str(exe)], check=True)
+    got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True,
+                                          check=True).stdout.split()]
+    assert got == [b._extent(r, c, ld) for ld, r, c in cases]

@@ -210,3 +210,68 @@ def test_rgemm_host_8192_sampled(h):
     pad = (np.arange(n, ld)[:, None] + np.arange(0, n, 97)[None, :] * ld).ravel()
     assert np.array_equal(bits(C[pad, 0]), bits(C0[pad, 0]))
     assert np.array_equal(bits(C[pad, 1]), bits(C0[pad, 1]))
+
+
+def tight(pl, extent, pad=37):
+    """Interleaved pairs of the first `extent` entries of planes `pl`, as a
+    view of a larger buffer whose `pad` further pairs hold a NaN sentinel."""
+    buf = np.empty((extent + pad, 2))
+    buf[:extent] = pairs((pl[0][:extent], pl[1][:extent]))
+    buf[extent:] = np.array([0x7FF8DEAD00000001, 0x7FF8DEAD00000002], np.uint64).view(np.float64)
+    return buf, buf[:extent]
+
+
+@pytest.mark.parametrize("op", W.OPS)
+def test_rgemm_host_exact_extent(h, op):
+    """Arrays sized exactly to their BLAS extent ld*(cols-1) + rows (large
+    enough for column chunks and k-slices): the result matches the oracle and
+    nothing past any array's extent is written."""
+    from paper_2109_13406_amd import binding as b
+    m, n, k = 300, 1100, 1090
+    case = W.gemm_case(1900, op[0], op[1], m, n, k, dist="wide")
+    ra, ca = (m, k) if op[0] == "N" else (k, m)
+    rb, cb = (k, n) if op[1] == "N" else (n, k)
+    ea = case["lda"] * (ca - 1) + ra
+    eb = case["ldb"] * (cb - 1) + rb
+    ec = case["ldc"] * (n - 1) + m
+    O = (case["C"][0].copy(), case["C"][1].copy())
+    assert oracle.rgemm(op[0], op[1], m, n, k, case["alpha"], case["A"], case["lda"],
+                        case["B"], case["ldb"], case["beta"], O, case["ldc"]) == 0
+    bufs = [tight(case["A"], ea), tight(case["B"], eb), tight(case["C"], ec)]
+    before = [x[0].copy() for x in bufs]
+    assert b.mpdd_Rgemm_host(h, op[0], op[1], m, n, k, case["alpha"], bufs[0][1], case["lda"],
+                             bufs[1][1], case["ldb"], case["beta"], bufs[2][1], case["ldc"]) == 0
+    for (full, _), old, e in zip(bufs, before, (ea, eb, ec)):
+        assert np.array_equal(bits(full[e:].ravel()), bits(old[e:].ravel())), op
+    G = planes(bufs[2][1])
+    idx = (np.arange(m)[:, None] + np.arange(n)[None, :] * case["ldc"]).ravel()
+    r = ratio(G[0][idx], G[1][idx], O[0][idx], O[1][idx], k)
+    assert r <= RATIO_MAX, (op, r)
+    rest = np.ones(ec, bool)
+    rest[idx] = False
+    assert np.array_equal(bits(G[0])[rest], bits(case["C"][0][:ec])[rest])
+    log(f"PARITY host-pointer Rgemm {op} exact-extent arrays ratio={r:.3g}")
+
+
+@pytest.mark.parametrize("trans", ["N", "T"])
+def test_rsyrk_host_exact_extent(h, trans):
+    from paper_2109_13406_amd import binding as b
+    n, k = 260, 300
+    case = W.syrk_case(1910, "U", trans, n, k, dist="wide")
+    ra, ca = (n, k) if trans == "N" else (k, n)
+    ea = case["lda"] * (ca - 1) + ra
+    ec = case["ldc"] * (n - 1) + n
+    O = (case["C"][0].copy(), case["C"][1].copy())
+    assert oracle.rsyrk("U", trans, n, k, case["alpha"], case["A"], case["lda"], case["beta"], O,
+                        case["ldc"]) == 0
+    bufs = [tight(case["A"], ea), tight(case["C"], ec)]
+    before = [x[0].copy() for x in bufs]
+    assert b.mpdd_Rsyrk_host(h, "U", trans, n, k, case["alpha"], bufs[0][1], case["lda"],
+                             case["beta"], bufs[1][1], case["ldc"]) == 0
+    for (full, _), old, e in zip(bufs, before, (ea, ec)):
+        assert np.array_equal(bits(full[e:].ravel()), bits(old[e:].ravel())), trans
+    G = planes(bufs[1][1])
+    i, j = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    idx = (i + j * case["ldc"])[i <= j]
+    assert ratio(G[0][idx], G[1][idx], O[0][idx], O[1][idx], k) <= RATIO_MAX
+    log(f"PARITY host-pointer Rsyrk U {trans} exact-extent arrays ok")

@@ -51,7 +51,7 @@ def test_config0_rgemm_256(h):
     O = gemm_oracle(case)
     info, G = gemm_gpu(h, case)
     assert info == 0
-    r = compare_full("config0 NN 256 plain", G, O, 256, 256, 256, 256)
+    r = compare_full("config0 NN 256 plain", G, O, 256, 256, 256, 256, case=case)
     assert r <= RATIO_MAX
 
 
@@ -71,7 +71,7 @@ def test_plain_ragged_all_tiles(h, op, shape):
             info, G = gemm_gpu(h, case, opts=dict(algo=b.MPDD_PLAIN, tile_id=tile, splitk=1))
             assert info == 0
             r = compare_full(f"ragged {op} {m}x{n}x{k} {dist} tile{tile}", G, O, m, n, k,
-                             case["ldc"], C0=case["C"])
+                             case["ldc"], C0=case["C"], case=case)
             assert r <= RATIO_MAX
 
 
@@ -103,7 +103,7 @@ def test_splitk(h, splitk):
             info, G = gemm_gpu(h, case, opts=dict(algo=b.MPDD_PLAIN, tile_id=tile, splitk=splitk))
             assert info == 0
             r = compare_full(f"splitk{splitk} {op} 70x9x1000 tile{tile}", G, O, 70, 9, 1000,
-                             case["ldc"], C0=case["C"])
+                             case["ldc"], C0=case["C"], case=case)
             assert r <= RATIO_MAX
 
 
@@ -113,7 +113,8 @@ def test_beta_zero_does_not_read_c(h):
         O = gemm_oracle(case)
         info, G = gemm_gpu(h, case)
         assert info == 0
-        r = compare_full(f"beta0 {op}", G, O, 45, 38, 20, case["ldc"], C0=case["C"])
+        r = compare_full(f"beta0 {op}", G, O, 45, 38, 20, case["ldc"], C0=case["C"],
+                         case=case)
         assert r <= RATIO_MAX
 
 
@@ -187,7 +188,7 @@ def test_syrk_ragged(h, uplo, trans, shape):
             info, G = syrk_gpu(h, case, opts=dict(algo=b.MPDD_PLAIN, tile_id=tile, splitk=1))
             assert info == 0
             r = compare_full(f"syrk {uplo}{trans} {n}x{k} b0={beta_zero} tile{tile}", G, O, n, n,
-                             k, case["ldc"], tri=uplo, C0=case["C"])
+                             k, case["ldc"], tri=uplo, C0=case["C"], case=case)
             assert r <= RATIO_MAX
             info, G = syrk_gpu(h, case, opts=dict(algo=b.MPDD_PLAIN_ACCURATE, tile_id=tile,
                                                   splitk=1))
@@ -211,7 +212,8 @@ def test_syrk_splitk(h, uplo, splitk):
                                                       splitk=splitk))
                 assert info == 0
                 r = compare_full(f"syrk splitk{splitk} {uplo}{trans} {n}x{k} tile{tile}", G, O,
-                                 n, n, k, case["ldc"], tri=uplo, C0=case["C"])
+                                 n, n, k, case["ldc"], tri=uplo, C0=case["C"],
+                                 case=case)
                 assert r <= RATIO_MAX
 
 
@@ -237,7 +239,7 @@ def test_syrk_triangle_coverage(h, uplo, n):
         info, G = syrk_gpu(h, case, opts=dict(algo=b.MPDD_PLAIN, tile_id=tile, splitk=1))
         assert info == 0
         r = compare_full(f"syrk coverage {uplo}N {n}x{k} tile{tile}", G, O, n, n, k,
-                         case["ldc"], tri=uplo, C0=case["C"])
+                         case["ldc"], tri=uplo, C0=case["C"], case=case)
         assert r <= RATIO_MAX
         del G
 

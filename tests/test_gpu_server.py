@@ -137,3 +137,61 @@ def test_tight_budget_completes_everything(h, arena):
     assert all(info == 0 for info, _ in tms)
     admits = [tm["admit"] for _, tm in tms]
     assert admits == sorted(admits)
+
+
+def test_served_stream_verified_like_the_benchmark(h, arena):
+    """The benchmark's check of a served stream (every request, sampled
+    entries against the oracle) on this stream: all within 8 k 2^-104."""
+    import bench
+    from paper_2109_13406_amd.loadgen import serve
+    arena.reset_c()
+    timings, _ = serve(h, arena, paced=False)
+    assert all(t["info"] == 0 for t in timings)
+    check = bench.verify_served(arena, samples=8, seed=99)
+    log(f"SERVE verify_served: {check}")
+    assert check["requests"] == len(arena.reqs)
+    assert check["over_tolerance"] == 0 and check["worst_ratio"] <= RATIO_MAX
+
+
+def test_tuned_table_picks_served_tiles(arena, tmp_path):
+    """A tile table written by the autotuner steers the server: with the
+    32 x 32 tile recorded as the served tile of every bucket, every request
+    runs with it, and each result is bit-identical to a standalone call with
+    that tile.  A malformed table is refused at handle creation."""
+    import torch
+    from paper_2109_13406_amd import autotune as AT
+    from paper_2109_13406_amd import binding as b
+    from paper_2109_13406_amd.loadgen import serve
+    entries = []
+    for op, combos in (("gemm", ("NN", "NT", "TN", "TT")), ("syrk", ("NT", "TN"))):
+        for mb in range(0, 10):
+            for nb in range(0, 10):
+                for kb in range(0, 10):
+                    if op == "syrk" and mb != nb:
+                        continue
+                    for tr in combos:
+                        entries.append(dict(op=op, trans=tr, mb=mb, nb=nb, kb=kb, tile=4,
+                                            splitk=1, serve_tile=2, dd_gflops=0.0))
+    path = str(tmp_path / "tune.json")
+    AT.write_cache(path, entries)
+    ht = b.mpdd_create(path)
+    try:
+        arena.reset_c()
+        timings, _ = serve(ht, arena, paced=False)
+        assert all(t["info"] == 0 and t["tile"] == 2 for t in timings)
+        served = _snapshot(arena)
+        arena.reset_c()
+        stream = torch.cuda.current_stream()
+        for i in range(len(arena.reqs)):
+            assert arena.call_plain(ht, i, stream, tile_id=2) == 0
+        plain = _snapshot(arena)
+        for i in range(len(arena.reqs)):
+            _same(served[i], plain[i], i, "tuned served tile vs standalone call")
+    finally:
+        torch.cuda.synchronize()
+        b.mpdd_destroy(ht)
+    bad = tmp_path / "bad.json"
+    bad.write_text('{"entries": [\n{"op": "gemm", "trans": "NN", "mb": 1}\n]}\n')
+    with pytest.raises(RuntimeError):
+        b.mpdd_create(str(bad))
+    log("SERVE tuned table: served tiles follow the table")

@@ -191,3 +191,19 @@ def test_struct_layouts_match_binding():
     import ctypes
     for name in ("mpdd_dd", "mpdd_opts", "mpdd_request", "mpdd_timing", "mpdd_server_stats"):
         assert b.mpdd_struct_size(name) == ctypes.sizeof(getattr(b, name)), name
+
+
+def test_idle_server_launches_from_submit(server_factory):
+    """With nothing queued or admitted and a slot free, submit launches the
+    request itself: when it returns, the request is already in flight as a
+    group (no hand-off to the scheduler thread)."""
+    s = server_factory(rate=1e6, latency=0.2)
+    t = b.mpdd_server_submit(s, _gemm(40, 40, 40))
+    st = b.mpdd_server_get_stats(s)
+    assert st["inflight_requests"] == 1 and st["queued_requests"] == 0 and st["groups"] == 1
+    info, tm = b.mpdd_server_wait(s, t)
+    assert info == 0 and tm["group"] == 1
+    assert tm["submit"] <= tm["admit"] <= tm["start"] <= tm["end"]
+    # an injected failure still takes the scheduler's path and stays isolated
+    bad = b.mpdd_server_submit(s, _gemm(30, 30, 30, inject=1))
+    assert b.mpdd_server_wait(s, bad)[0] == b.MPDD_ERR_HIP

@@ -476,3 +476,59 @@ def spd_case_device(seed, n, uplo="L", padded=True, device="cuda"):
         v = plane[: n * ld].view(n, ld)[:, :n]          # v[j, i] = A(i, j)
         v.copy_(torch.where(keep.T, src.T, v))
     return dict(n=n, uplo=uplo, A=(hi, lo), lda=ld)
+
+
+# ---- sampled entries (for checks at sizes the oracle cannot cover in full) ---------
+
+# random entries checked per split-form result at the config-3 sizes (the
+# benchmark's slice-count search and the GPU test that repeats it)
+CONFIG3_SAMPLE = 256
+
+
+def sample_indices(m, n, count, seed, tri=None):
+    """Entries (ii, jj) of an m x n result to check: `count` uniform random
+    ones plus the corners, edges and middle (ragged tails and tile boundaries
+    live there); for tri "U" / "L" the entries are mirrored into that
+    triangle."""
+    rng = np.random.default_rng(seed)
+    ii = list(rng.integers(0, m, count))
+    jj = list(rng.integers(0, n, count))
+    for i in (0, m - 1, m // 2):
+        for j in (0, n - 1, n // 2, min(n - 1, 63), min(n - 1, 64)):
+            ii.append(i)
+            jj.append(j)
+    ii, jj = np.array(ii), np.array(jj)
+    if tri == "U":
+        sw = ii > jj
+        ii[sw], jj[sw] = jj[sw].copy(), ii[sw].copy()
+    elif tri == "L":
+        sw = ii < jj
+        ii[sw], jj[sw] = jj[sw].copy(), ii[sw].copy()
+    return ii, jj
+
+
+def gather_op_rows(plane, ld, trans, ii, k):
+    """Host array (k, len(ii)) with [l, t] = op(X)(ii[t], l) for a device
+    plane X stored column-major with leading dimension ld (op(X) = X for
+    trans False, X^T for True): the rows of op(A) that sampled entries use."""
+    import torch
+    idx = torch.as_tensor(ii, device=plane.device)
+    if not trans:                       # X[i + l*ld]
+        v = plane[: ld * k].view(k, ld)[:, idx]
+    else:                               # X[l + i*ld]
+        rows = int(ii.max()) + 1
+        v = plane[: ld * rows].view(rows, ld)[idx, :k].T
+    return v.contiguous().cpu().numpy()
+
+
+def gather_op_cols(plane, ld, trans, jj, k):
+    """Host array (len(jj), k) with [t, l] = op(X)(l, jj[t]): the columns of
+    op(B) that sampled entries use."""
+    import torch
+    idx = torch.as_tensor(jj, device=plane.device)
+    if not trans:                       # X[l + j*ld]
+        cols = int(jj.max()) + 1
+        v = plane[: ld * cols].view(cols, ld)[idx, :k]
+    else:                               # X[j + l*ld]
+        v = plane[: ld * k].view(k, ld)[:, idx].T
+    return v.contiguous().cpu().numpy()
