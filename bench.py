@@ -45,7 +45,10 @@ def kernel_sha():
     for f in KERNEL_SOURCES:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
-    h.update(json.dumps([B.FLAGS, B.EXTRA_FLAGS.get("gemm_plain.hip", [])]).encode())
+    # the include directory is an absolute path: hashed relative to the tree,
+    # so that the same sources give the same hash wherever the tree lives
+    flags = [os.path.relpath(f, ROOT) if os.path.isabs(f) else f for f in B.FLAGS]
+    h.update(json.dumps([flags, B.EXTRA_FLAGS.get("gemm_plain.hip", [])]).encode())
     return h.hexdigest()[:16]
 
 
