@@ -460,10 +460,13 @@ def bench_ozaki(h, args, stream, t_plain_main):
             if n == args.n:
                 t_plain = t_plain_main
             else:
-                for dst, src in zip(P, C0):
-                    dst.copy_(src)
-                _, per = timed_calls(plain, 3, 1, stream)
+                # timed on a copy: each timed call updates its C again, and P
+                # must stay the result of one call
+                Pt = tuple(x.clone() for x in C0)
+                plain_t = lambda: b.mpdd_Rgemm(h, *args_, Pt, case["ldc"], stream=stream)
+                _, per = timed_calls(plain_t, 3, 1, stream)
                 t_plain = sum(per) / len(per)
+                del Pt
             C = tuple(torch.empty_like(x) for x in C0)
             for kind, algo, rng_s in kinds:
                 found = None
