@@ -75,6 +75,7 @@ typedef struct mpdd_handle_s *mpdd_handle;
 #define MPDD_ERR_UNSUPPORTED (-5) /* option value or size outside what is implemented */
 #define MPDD_ERR_HANDLE (-6)      /* NULL or destroyed handle */
 #define MPDD_ERR_ARG (-7)         /* invalid non-BLAS argument (options, ticket, pointer) */
+#define MPDD_ERR_SCRATCH (-8)     /* mpdd_Rgemm_noalloc: needs more than its static scratch */
 
 /* Create a handle bound to the current HIP device.  tuner_cache_path may be
  * NULL (built-in tile choices) or a JSON file written by the autotuner.
@@ -161,6 +162,34 @@ int mpdd_Rgemm_ex(mpdd_handle h, const mpdd_opts *opts, const char *transa, cons
                   const double *A_lo, mpdd_int lda, const double *B_hi, const double *B_lo,
                   mpdd_int ldb, mpdd_dd beta, double *C_hi, double *C_lo, mpdd_int ldc,
                   void *stream);
+
+/* ---- no-allocation Rgemm ----------------------------------------------------------
+ *
+ * For callers that cannot allocate device memory during a call: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * The same product as mpdd_Rgemm_ex with a plain form (opts->algo MPDD_PLAIN
+ * or MPDD_PLAIN_ACCURATE; NULL = defaults), same arguments, info codes, BLAS
+ * semantics and tile / k-split choice, but the call allocates nothing: its
+ * k-split partial sums (16*S*m*n bytes for a split into S k-ranges) go to a
+ * static device array of MPDD_STATIC_SCRATCH_BYTES that the library holds on
+ * every device it runs on until the process ends (its address is looked up
+ * by mpdd_create).  An automatic split whose partials would not fit is halved
+ * until they do (S = 1 needs no scratch), so the result is that of
+ * mpdd_Rgemm_ex with opts->splitk set to the split used; an explicit
+ * opts->splitk whose partials do not fit returns MPDD_ERR_SCRATCH with nothing
+ * enqueued.  The split forms return MPDD_ERR_UNSUPPORTED (their slices need
+ * far more memory).  Every call on one device shares that device's array,
+ * which keeps the last call's contents (nothing in it needs to start at
+ * zero): calls whose work may overlap on one device -- on different streams
+ * or host threads without an ordering between them -- race on it and must be
+ * serialised by the caller (one stream, or events). */
+#define MPDD_STATIC_SCRATCH_BYTES ((size_t)64 << 20)   /* 64 MiB per device */
+
+int mpdd_Rgemm_noalloc(mpdd_handle h, const mpdd_opts *opts, const char *transa,
+                       const char *transb, mpdd_int m, mpdd_int n, mpdd_int k, mpdd_dd alpha,
+                       const double *A_hi, const double *A_lo, mpdd_int lda,
+                       const double *B_hi, const double *B_lo, mpdd_int ldb, mpdd_dd beta,
+                       double *C_hi, double *C_lo, mpdd_int ldc, void *stream);
 
 /* As mpdd_Rsyrk with explicit options (plain forms only). */
 int mpdd_Rsyrk_ex(mpdd_handle h, const mpdd_opts *opts, const char *uplo, const char *trans,

@@ -27,6 +27,8 @@ MPDD_ERR_SHUTDOWN = -4
 MPDD_ERR_UNSUPPORTED = -5
 MPDD_ERR_HANDLE = -6
 MPDD_ERR_ARG = -7
+MPDD_ERR_SCRATCH = -8
+MPDD_STATIC_SCRATCH_BYTES = 64 << 20   # static scratch of mpdd_Rgemm_noalloc, per device
 
 
 class mpdd_dd(ctypes.Structure):
@@ -90,6 +92,9 @@ SIGNATURES = {
                                   mpdd_dd, _P, _P, _I, _P]),
     "mpdd_Rgemm_ex": (ctypes.c_int, [_P, ctypes.POINTER(mpdd_opts), _C, _C, _I, _I, _I, mpdd_dd,
                                      _P, _P, _I, _P, _P, _I, mpdd_dd, _P, _P, _I, _P]),
+    "mpdd_Rgemm_noalloc": (ctypes.c_int, [_P, ctypes.POINTER(mpdd_opts), _C, _C, _I, _I, _I,
+                                          mpdd_dd, _P, _P, _I, _P, _P, _I, mpdd_dd, _P, _P, _I,
+                                          _P]),
     "mpdd_Rsyrk": (ctypes.c_int, [_P, _C, _C, _I, _I, mpdd_dd, _P, _P, _I, mpdd_dd, _P, _P, _I,
                                   _P]),
     "mpdd_Rsyrk_ex": (ctypes.c_int, [_P, ctypes.POINTER(mpdd_opts), _C, _C, _I, _I, mpdd_dd, _P,
@@ -317,7 +322,15 @@ def mpdd_Rgemm_ex(h, opts, transa, transb, m, n, k, alpha, A, lda, B, ldb, beta,
     if _entry == "mpdd_Rgemm":
         return load().mpdd_Rgemm(h, *args)
     o = opts if opts is None or isinstance(opts, mpdd_opts) else _opts(**opts)
-    return load().mpdd_Rgemm_ex(h, ctypes.byref(o) if o is not None else None, *args)
+    return getattr(load(), _entry)(h, ctypes.byref(o) if o is not None else None, *args)
+
+
+def mpdd_Rgemm_noalloc(h, opts, transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc,
+                       stream=None):
+    """As mpdd_Rgemm_ex; the library allocates nothing (k-split partials in
+    its static per-device scratch).  Returns info or MPDD_ERR_*."""
+    return mpdd_Rgemm_ex(h, opts, transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc,
+                         stream, _entry="mpdd_Rgemm_noalloc")
 
 
 def prepared_Rgemm_ex(h, opts, transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc,

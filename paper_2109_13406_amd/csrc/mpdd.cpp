@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstdio>
 #include <cstring>
 #include <mutex>
@@ -20,6 +21,42 @@
 #include "tuner.hpp"
 
 using namespace mpdd;
+
+// Static device scratch of the no-allocation entry point (mpdd_Rgemm_noalloc):
+// its k-split partial sums live here instead of in a handle's pool, so that
+// the call allocates nothing.  Each device that loads the library holds its
+// own copy until the process ends.  In host code the name `scratch` is a
+// host-side stand-in, not a device address: host code only ever uses the
+// address that hipGetSymbolAddress returns for the device (looked up once per
+// device by mpdd_create, with the device current, and kept in
+// g_static_scratch).
+static __device__ __align__(256) char scratch[MPDD_STATIC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_static_scratch_mu;
+std::atomic<void*> g_static_scratch[kMaxDevices];   // device -> address of `scratch` on it
+
+// Look up the address of `scratch` on `device`, which must be the current
+// device.  Once per device; later calls return at once.
+int static_scratch_init(int device) {
+  if (device < 0 || device >= kMaxDevices) return MPDD_ERR_UNSUPPORTED;
+  std::lock_guard<std::mutex> lk(g_static_scratch_mu);
+  if (g_static_scratch[device].load(std::memory_order_acquire)) return 0;
+  void* p = nullptr;
+  if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || p == nullptr)
+    return MPDD_ERR_HIP;
+  g_static_scratch[device].store(p, std::memory_order_release);
+  return 0;
+}
+
+void* static_scratch_ptr(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  return g_static_scratch[device].load(std::memory_order_acquire);
+}
+
+}  // namespace
 
 struct mpdd_handle_s {
   int device = 0;
@@ -133,10 +170,17 @@ Plan choose(const mpdd_handle h, const mpdd_opts* o, int op, bool ta, bool tb, i
   return pl;
 }
 
+// Caller-provided scratch for the k-split partials (the no-allocation entry
+// point): `ptr` holds `bytes` bytes of device memory.
+struct FixedScratch {
+  void* ptr;
+  size_t bytes;
+};
+
 int run_plain(mpdd_handle h, const mpdd_opts* o, bool ta, bool tb, int tri, int64_t m, int64_t n,
               int64_t k, mpdd_dd alpha, const double* Ah, const double* Al, int64_t lda,
               const double* Bh, const double* Bl, int64_t ldb, mpdd_dd beta, double* Ch,
-              double* Cl, int64_t ldc, hipStream_t st) {
+              double* Cl, int64_t ldc, hipStream_t st, const FixedScratch* fixed = nullptr) {
   const bool accurate = o && o->algo == MPDD_PLAIN_ACCURATE;
   GemmParams p{};
   p.m = m; p.n = n; p.k = k;
@@ -161,6 +205,12 @@ int run_plain(mpdd_handle h, const mpdd_opts* o, bool ta, bool tb, int tri, int6
   p.tiles_n = (int)((n + t->bn - 1) / t->bn);
 
   int S = pl.splitk;
+  // 16 * S * m * n bytes of partials (hi and lo planes)
+  auto partial_bytes = [&](int s_) { return 16.0 * s_ * (double)m * (double)n; };
+  // a fixed scratch: an automatic split is halved until its partials fit
+  // (the result is then that of the same call with opts->splitk = S)
+  if (fixed && !(o && o->splitk > 0))
+    while (S > 1 && partial_bytes(S) > (double)fixed->bytes) S >>= 1;
   // k-range per slice: a whole number of staged k-tiles
   int64_t chunk = (k + S - 1) / S;
   chunk = (chunk + t->bk - 1) / t->bk * t->bk;
@@ -175,8 +225,17 @@ int run_plain(mpdd_handle h, const mpdd_opts* o, bool ta, bool tb, int tri, int6
 
   if (S == 1) return hip_status(launch_gemm(pl.tile, p, ta, tb, accurate, 1, st));
 
-  void* w = nullptr;
   const size_t plane = (size_t)S * (size_t)m * (size_t)n * sizeof(double);
+  if (fixed) {
+    // (an explicit split whose partials do not fit: rejected, nothing enqueued)
+    if (partial_bytes(S) > (double)fixed->bytes) return MPDD_ERR_SCRATCH;
+    p.w_hi = (double*)fixed->ptr;
+    p.w_lo = (double*)((char*)fixed->ptr + plane);
+    hipError_t e = launch_gemm(pl.tile, p, ta, tb, accurate, S, st);
+    if (e == hipSuccess) e = launch_splitk_reduce(p, S, st);
+    return hip_status(e);
+  }
+  void* w = nullptr;
   if (hipMallocFromPoolAsync(&w, 2 * plane, h->pool, st) != hipSuccess) return MPDD_ERR_ALLOC;
   p.w_hi = (double*)w;
   p.w_lo = (double*)((char*)w + plane);
@@ -255,6 +314,11 @@ int mpdd_create(mpdd_handle* h, const char* tuner_cache_path) {
     delete s;
     return MPDD_ERR_HIP;
   }
+  // (the device is current: its address of the static scratch)
+  if (const int e = static_scratch_init(s->device)) {
+    delete s;
+    return e;
+  }
   hipMemPoolProps props{};
   props.allocType = hipMemAllocationTypePinned;
   props.location.type = hipMemLocationTypeDevice;
@@ -317,6 +381,27 @@ int mpdd_Rgemm(mpdd_handle h, const char* transa, const char* transb, mpdd_int m
                double* C_hi, double* C_lo, mpdd_int ldc, void* stream) {
   return mpdd_Rgemm_ex(h, nullptr, transa, transb, m, n, k, alpha, A_hi, A_lo, lda, B_hi, B_lo,
                        ldb, beta, C_hi, C_lo, ldc, stream);
+}
+
+int mpdd_Rgemm_noalloc(mpdd_handle h, const mpdd_opts* opts, const char* transa,
+                       const char* transb, mpdd_int m, mpdd_int n, mpdd_int k, mpdd_dd alpha,
+                       const double* A_hi, const double* A_lo, mpdd_int lda, const double* B_hi,
+                       const double* B_lo, mpdd_int ldb, mpdd_dd beta, double* C_hi,
+                       double* C_lo, mpdd_int ldc, void* stream) {
+  const int info = check_gemm(transa, transb, m, n, k, lda, ldb, ldc);
+  if (info) return info;
+  if (!handle_ok(h)) return MPDD_ERR_HANDLE;
+  const int algo = opts ? opts->algo : MPDD_PLAIN;
+  if (algo == MPDD_OZAKI_I8 || algo == MPDD_OZAKI_F64) return MPDD_ERR_UNSUPPORTED;
+  if (algo != MPDD_PLAIN && algo != MPDD_PLAIN_ACCURATE) return MPDD_ERR_ARG;
+  if (m == 0 || n == 0 || ((is_zero(alpha) || k == 0) && is_one(beta))) return 0;
+  if (!C_hi || !C_lo) return MPDD_ERR_ARG;
+  if (!is_zero(alpha) && k > 0 && (!A_hi || !A_lo || !B_hi || !B_lo)) return MPDD_ERR_ARG;
+  const FixedScratch fs{static_scratch_ptr(h->device), (size_t)MPDD_STATIC_SCRATCH_BYTES};
+  if (!fs.ptr) return MPDD_ERR_HIP;
+  const bool ta = !lsame(transa, 'N'), tb = !lsame(transb, 'N');
+  return run_plain(h, opts, ta, tb, 0, m, n, k, alpha, A_hi, A_lo, lda, B_hi, B_lo, ldb, beta,
+                   C_hi, C_lo, ldc, (hipStream_t)stream, &fs);
 }
 
 int mpdd_Rsyrk_ex(mpdd_handle h, const mpdd_opts* opts, const char* uplo, const char* trans,

@@ -217,3 +217,32 @@ def test_int8_digit_width_guard_is_strict():
             assert rc == b.MPDD_ERR_UNSUPPORTED
         else:
             assert (wf.value, w.value) == (6, 7)
+
+
+def test_noalloc_info_codes_before_handle(lib):
+    """The no-allocation Rgemm checks DGEMM's argument positions on the host
+    before anything else, like mpdd_Rgemm_ex; valid arguments reach the
+    handle check."""
+    from paper_2109_13406_amd import binding as b
+    pos = pins.read_arg_positions()
+
+    def g(ta="N", tb="N", m=2, n=2, k=2, lda=None, ldb=None, ldc=None):
+        lda = lda if lda is not None else max(1, m if ta.upper() == "N" else k)
+        ldb = ldb if ldb is not None else max(1, k if tb.upper() == "N" else n)
+        ldc = ldc if ldc is not None else max(1, m)
+        return lib.mpdd_Rgemm_noalloc(None, None, ta.encode(), tb.encode(), m, n, k,
+                                      b.mpdd_dd(1.0, 0.0), None, None, lda, None, None, ldb,
+                                      b.mpdd_dd(0.5, 0.0), None, None, ldc, None)
+    assert g() == b.MPDD_ERR_HANDLE
+    assert g(ta="x") == pos[("gemm", "transa")]
+    assert g(tb="x") == pos[("gemm", "transb")]
+    assert g(m=-1) == pos[("gemm", "m")]
+    assert g(n=-1) == pos[("gemm", "n")]
+    assert g(k=-1) == pos[("gemm", "k")]
+    assert g(m=5, lda=4) == pos[("gemm", "lda")]
+    assert g(k=5, ldb=4) == pos[("gemm", "ldb")]
+    assert g(m=5, lda=5, ldc=4) == pos[("gemm", "ldc")]
+    assert b.MPDD_STATIC_SCRATCH_BYTES == 64 << 20
+    hdr = open(os.path.join(ROOT, "include", "mpdd.h")).read()
+    assert "#define MPDD_STATIC_SCRATCH_BYTES ((size_t)64 << 20)" in hdr
+    assert "#define MPDD_ERR_SCRATCH (-8)" in hdr
