@@ -74,11 +74,11 @@ def _bind(lib):
         getattr(lib, f).argtypes = [ctypes.c_double] * 4 + [_D, _D]
         getattr(lib, f).restype = None
     lib.oracle_ozaki_split.argtypes = [_I64, _I64, _D, _D, _I64, _I64, ctypes.c_int,
-                                       ctypes.c_int, ctypes.c_int, _I32P, _I32P]
+                                       ctypes.c_int, ctypes.c_int, ctypes.c_int, _I32P, _I32P]
     lib.oracle_ozaki_split.restype = ctypes.c_int
     lib.oracle_ozaki_Rgemm.argtypes = [c, c, _I64, _I64, _I64, _DD, _D, _D, _I64, _D, _D,
                                        _I64, _DD, _D, _D, _I64, ctypes.c_int, ctypes.c_int,
-                                       ctypes.c_int]
+                                       ctypes.c_int, ctypes.c_int]
     lib.oracle_ozaki_Rgemm.restype = ctypes.c_int
     lib.oracle_Cgemm.argtypes = [c, c, _I64, _I64, _I64, _D, _D, _D, _D, _D, _I64, _D, _D, _D,
                                  _D, _I64, _D, _D, _D, _D, _D, _I64]
@@ -263,7 +263,20 @@ def rsyrk_entries(uplo, trans, n, k, alpha, A, lda, beta, C, ldc, ii, jj, lib=No
 
 # ---- split form -----------------------------------------------------------------
 
-INT8_DIGITS = (6, 7)       # (first digit width, later digit width): |q| <= 64
+INT8_QMAX = 127            # largest int8 digit: later digits are carried into [-128, 127]
+
+
+def int8_digit_widths(k, nslices):
+    """(first, later) digit widths of INT8 slices, or None: 8-bit later
+    digits while nslices*k < 2^17, 7-bit ones (|q| <= 64) while
+    nslices*k < 2^19, so that every anti-diagonal sum of at most nslices*k
+    digit products (each at most 2^(2w-2) in magnitude) stays below 2^31."""
+    terms = int(k) * int(nslices)
+    if terms < 2 ** 17:
+        return 6, 8
+    if terms < 2 ** 19:
+        return 6, 7
+    return None
 
 
 def fp64_digit_width(k, nslices):
@@ -276,13 +289,14 @@ def fp64_digit_width(k, nslices):
     return w - 1, w
 
 
-def ozaki_split(rows, k, X, sr, sl, nslices, wfirst, w, lib=None):
+def ozaki_split(rows, k, X, sr, sl, nslices, wfirst, w, qmax=0, lib=None):
     """Scale exponents (rows,) and digits (nslices, rows, k) of a row operand
-    whose element (r, l) is X[r*sr + l*sl] (flat hi/lo arrays)."""
+    whose element (r, l) is X[r*sr + l*sl] (flat hi/lo arrays); qmax > 0
+    carries the digits after the first into [.., qmax]."""
     lib = lib or load()
     exps = np.zeros(rows, dtype=np.int32)
     digs = np.zeros((nslices, rows, k), dtype=np.int32)
-    info = lib.oracle_ozaki_split(rows, k, _p(X[0]), _p(X[1]), sr, sl, nslices, wfirst, w,
+    info = lib.oracle_ozaki_split(rows, k, _p(X[0]), _p(X[1]), sr, sl, nslices, wfirst, w, qmax,
                                   exps.ctypes.data_as(_I32P), digs.ctypes.data_as(_I32P))
     if info != 0:
         raise ValueError("oracle_ozaki_split failed")
@@ -290,8 +304,8 @@ def ozaki_split(rows, k, X, sr, sl, nslices, wfirst, w, lib=None):
 
 
 def ozaki_rgemm(transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, nslices,
-                wfirst, w, lib=None):
+                wfirst, w, qmax=0, lib=None):
     lib = lib or load()
     return lib.oracle_ozaki_Rgemm(_flag(transa), _flag(transb), m, n, k, _dd(alpha),
                                   _p(A[0]), _p(A[1]), lda, _p(B[0]), _p(B[1]), ldb,
-                                  _dd(beta), _p(C[0]), _p(C[1]), ldc, nslices, wfirst, w)
+                                  _dd(beta), _p(C[0]), _p(C[1]), ldc, nslices, wfirst, w, qmax)

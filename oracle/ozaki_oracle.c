@@ -20,7 +20,19 @@
  *     even), y_t = TwoSum(z.hi - q_t, z.lo).  w_1 = wfirst, w_t = w after.
  *     Then x = 2^sigma * (sum_t q_t 2^-W_t + y_s 2^-W_s), W_t = wfirst +
  *     w (t-1), and |q_t| <= 2^{wfirst} (first digit) and <= 2^{w-1} (rest).
- *     INT8 slices: wfirst = 6, w = 7, so |q_t| <= 64.
+ *  2b. Storage range.  When the digits are stored in a narrow integer type
+ *     whose largest value is qmax (int8: 127), every digit after the first
+ *     that exceeds qmax is lowered by 2^w and the digit before it raised by
+ *     one, from the last digit to the second.  The represented value does not
+ *     change (2^w units of digit t make one unit of digit t-1).  Rounded
+ *     digits lie in [-2^{w-1}, 2^{w-1}] and a digit receives a carry of at
+ *     most one, so with qmax = 2^{w-1} - 1 every later digit ends in
+ *     [-2^{w-1}, 2^{w-1} - 1] and the first in [-2^wfirst, 2^wfirst + 1].
+ *     INT8 slices: wfirst = 6 and w = 8 (digits in [-128, 127]) while
+ *     nslices * k < 2^17, else w = 7 (|q_t| <= 64, no carry ever needed)
+ *     while nslices * k < 2^19: every anti-diagonal sum of at most
+ *     nslices * k digit products, each at most 2^{2w-2} in magnitude, then
+ *     stays below 2^31.
  *  3. Products.  For every anti-diagonal d = t + u, 2 <= d <= s + 1:
  *     X_d = sum_{t+u=d} Q_t Q'_u^T, computed exactly (integers).
  *  4. Recombine.  P_ij = sum_d X_d(i,j) 2^-(2 wfirst + w (d-2)), summed in dd
@@ -45,9 +57,11 @@ static inline odd at(const double *hi, const double *lo, int64_t sr, int64_t sl,
 }
 
 /* Scale exponents and digits of a rows x k row operand.
- * exps[r]: sigma_r.  digits[(t*rows + r)*k + l]: q_{t+1} of element (r, l). */
+ * exps[r]: sigma_r.  digits[(t*rows + r)*k + l]: q_{t+1} of element (r, l).
+ * qmax > 0: carry the digits after the first into [.., qmax] (step 2b);
+ * qmax = 0: digits as rounded. */
 int oracle_ozaki_split(int64_t rows, int64_t k, const double *hi, const double *lo,
-                       int64_t sr, int64_t sl, int nslices, int wfirst, int w,
+                       int64_t sr, int64_t sl, int nslices, int wfirst, int w, int qmax,
                        int32_t *exps, int32_t *digits)
 {
     int64_t r;
@@ -75,6 +89,15 @@ int oracle_ozaki_split(int64_t rows, int64_t k, const double *hi, const double *
                 digits[((int64_t)t * rows + r) * k + l] = (int32_t)q;
                 y = two_sum(zh - q, zl);
             }
+            if (qmax > 0) {
+                for (t = nslices - 1; t >= 1; --t) {
+                    int32_t *q = &digits[((int64_t)t * rows + r) * k + l];
+                    if (*q > qmax) {
+                        *q -= (int32_t)1 << w;
+                        digits[((int64_t)(t - 1) * rows + r) * k + l] += 1;
+                    }
+                }
+            }
         }
     }
     return 0;
@@ -88,7 +111,7 @@ int oracle_ozaki_Rgemm(const char *transa, const char *transb, int64_t m, int64_
                        int64_t k, odd alpha, const double *Ah, const double *Al,
                        int64_t lda, const double *Bh, const double *Bl, int64_t ldb,
                        odd beta, double *Ch, double *Cl, int64_t ldc,
-                       int nslices, int wfirst, int w)
+                       int nslices, int wfirst, int w, int qmax)
 {
     int ta = !(transa[0] == 'N' || transa[0] == 'n');
     int tb = !(transb[0] == 'N' || transb[0] == 'n');
@@ -121,9 +144,11 @@ int oracle_ozaki_Rgemm(const char *transa, const char *transb, int64_t m, int64_
     qb = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nslices * n * k));
     if (!ea || !eb || !qa || !qb) { free(ea); free(eb); free(qa); free(qb); return -1; }
     /* row operand of A: op(A)(i, l) */
-    oracle_ozaki_split(m, k, Ah, Al, ta ? lda : 1, ta ? 1 : lda, nslices, wfirst, w, ea, qa);
+    oracle_ozaki_split(m, k, Ah, Al, ta ? lda : 1, ta ? 1 : lda, nslices, wfirst, w, qmax, ea,
+                       qa);
     /* row operand of B: op(B)(l, j) seen as element (j, l) */
-    oracle_ozaki_split(n, k, Bh, Bl, tb ? 1 : ldb, tb ? ldb : 1, nslices, wfirst, w, eb, qb);
+    oracle_ozaki_split(n, k, Bh, Bl, tb ? 1 : ldb, tb ? ldb : 1, nslices, wfirst, w, qmax, eb,
+                       qb);
 
 #pragma omp parallel for schedule(dynamic, 1)
     for (j = 0; j < n; ++j) {

@@ -365,17 +365,30 @@ def check_identities(lib):
 
 # ---- split form -----------------------------------------------------------------------
 
+def _split_forms(k, nslices):
+    """(wfirst, w, qmax) of every digit form the split oracle serves: INT8 with
+    8-bit and with 7-bit later digits (carried into int8's range), FP64."""
+    return [(6, 8, oracle.INT8_QMAX), (6, 7, oracle.INT8_QMAX),
+            oracle.fp64_digit_width(k, nslices) + (0,)]
+
+
 def check_ozaki_split_exact(lib, dist="wide", nslices=18):
     """Digits reconstruct the scaled value exactly up to the last remainder,
-    stay within their bounds, and the scale puts every row inside (-1, 1)."""
+    stay within their bounds, and the scale puts every row inside (-1, 1);
+    a digit after the first that would exceed int8's range is carried into
+    the digit before it (checked on inputs whose digits are worked out by
+    hand)."""
     for (rows, k, trans) in [(5, 7, False), (4, 9, True), (1, 1, False)]:
         rng = W.streams(4000 + rows)[0]
         ld = rows + 2 if not trans else k + 1
         nr, nc = (rows, k) if not trans else (k, rows)
         X = W.dd_matrix(rng, nr, nc, ld, dist=dist)
         sr, sl = (1, ld) if not trans else (ld, 1)
-        for (wf, w) in (oracle.INT8_DIGITS, oracle.fp64_digit_width(k, nslices)):
-            exps, digs = oracle.ozaki_split(rows, k, X, sr, sl, nslices, wf, w, lib=lib)
+        for (wf, w, qmax) in _split_forms(k, nslices):
+            # digits may carry only where the rounded range [-2^(w-1), 2^(w-1)]
+            # exceeds qmax
+            carries = qmax > 0 and 2 ** (w - 1) > qmax
+            exps, digs = oracle.ozaki_split(rows, k, X, sr, sl, nslices, wf, w, qmax, lib=lib)
             for r in range(rows):
                 vals = [F(X[0][r * sr + l * sl], X[1][r * sr + l * sl]) for l in range(k)]
                 mx = max(abs(float(X[0][r * sr + l * sl])) for l in range(k))
@@ -387,13 +400,42 @@ def check_ozaki_split_exact(lib, dist="wide", nslices=18):
                     recon = Fraction(0)
                     for t in range(nslices):
                         q = int(digs[t, r, l])
-                        lim = 2 ** wf if t == 0 else 2 ** (w - 1)
-                        assert abs(q) <= lim, (t, q, lim)
+                        if t == 0:
+                            assert abs(q) <= 2 ** wf + (1 if carries else 0), (t, q)
+                        else:
+                            assert -2 ** (w - 1) <= q <= 2 ** (w - 1), (t, q)
+                            if qmax > 0:
+                                assert q <= qmax, (t, q, qmax)
                         W_t = wf + w * t
                         recon += Fraction(q, 2 ** W_t)
-                        # remainder after digit t lies within half a unit of it
-                        assert abs(x - recon) <= Fraction(1, 2 ** (W_t + 1)) * Fraction(
+                        # remainder after digit t lies within half a unit of
+                        # it, plus the unit a carry from digit t+1 may add
+                        slack = 1 if (carries and t < nslices - 1) else 0
+                        assert abs(x - recon) <= (Fraction(1, 2) + slack) / 2 ** W_t * Fraction(
                             1000001, 1000000), (t, float(x - recon))
+    # worked carries (first digit width 6, later 8, int8 storage): a row
+    # [0.75, x] has scale exponent 0, so x's digits are those of x itself.
+    #   x = (20 + 127.75/256) / 64: rounded digits 20, 128 (127.75 rounds
+    #   up), -64 (the remainder -0.25 times 256), then 0; 128 exceeds 127,
+    #   so it becomes 128 - 256 = -128 and the first digit 21.
+    #   x = (20 + (127 + 127.75/256)/256) / 64: rounded digits 20, 127, 128,
+    #   -64; the carry out of the third digit makes the second 128, which
+    #   carries again: 21, -128, -128, -64.
+    cases = [(Fraction(20 * 256 + Fraction(511, 4), 256 * 64), [21, -128, -64, 0, 0]),
+             (Fraction(20 * 256 * 256 + 127 * 256 + Fraction(511, 4), 256 * 256 * 64),
+              [21, -128, -128, -64, 0])]
+    for x, want in cases:
+        hi = float(x)
+        lo = float(x - Fraction(hi))
+        X = (np.array([0.75, hi]), np.array([0.0, lo]))
+        exps, digs = oracle.ozaki_split(1, 2, X, 0, 1, 5, 6, 8, oracle.INT8_QMAX, lib=lib)
+        assert int(exps[0]) == 0
+        assert [int(v) for v in digs[:, 0, 1]] == want, (digs[:, 0, 1], want)
+        recon = sum(Fraction(int(q), 2 ** (6 + 8 * t)) for t, q in enumerate(digs[:, 0, 1]))
+        assert recon == x
+        # without the storage limit the rounded digits stay as they are
+        _, raw = oracle.ozaki_split(1, 2, X, 0, 1, 5, 6, 8, 0, lib=lib)
+        assert int(raw[0, 0, 1]) == 20 and 128 in [int(v) for v in raw[:, 0, 1]]
 
 
 def check_ozaki_gemm_exact(lib):
@@ -404,16 +446,18 @@ def check_ozaki_gemm_exact(lib):
     for ta in "NT":
         for tb in "NT":
             c = W.gemm_case(5000, ta, tb, m, n, k, dist="wide")
-            for (wf, w) in (oracle.INT8_DIGITS, oracle.fp64_digit_width(k, s)):
+            for (wf, w, qmax) in _split_forms(k, s):
                 C = (c["C"][0].copy(), c["C"][1].copy())
                 C0 = (c["C"][0].copy(), c["C"][1].copy())
                 assert oracle.ozaki_rgemm(ta, tb, m, n, k, c["alpha"], c["A"], c["lda"], c["B"],
-                                          c["ldb"], c["beta"], C, c["ldc"], s, wf, w,
+                                          c["ldb"], c["beta"], C, c["ldc"], s, wf, w, qmax,
                                           lib=lib) == 0
                 ea, qa = oracle.ozaki_split(m, k, c["A"], c["lda"] if ta == "T" else 1,
-                                            1 if ta == "T" else c["lda"], s, wf, w, lib=lib)
+                                            1 if ta == "T" else c["lda"], s, wf, w, qmax,
+                                            lib=lib)
                 eb, qb = oracle.ozaki_split(n, k, c["B"], 1 if tb == "T" else c["ldb"],
-                                            c["ldb"] if tb == "T" else 1, s, wf, w, lib=lib)
+                                            c["ldb"] if tb == "T" else 1, s, wf, w, qmax,
+                                            lib=lib)
                 al, be = F(*c["alpha"]), F(*c["beta"])
                 for i in range(m):
                     for j in range(n):

@@ -33,7 +33,8 @@ def h():
 
 
 def _widths(kind, k, s):
-    return oracle.INT8_DIGITS if kind == "i8" else oracle.fp64_digit_width(k, s)
+    """(wfirst, w, qmax) of the library's digits for k terms and s slices."""
+    return (6, 7, oracle.INT8_QMAX) if kind == "i8" else oracle.fp64_digit_width(k, s) + (0,)
 
 
 @pytest.mark.parametrize("kind", ["i8", "f64"])
@@ -49,9 +50,9 @@ def test_slices_bit_identical(h, kind, trans, dist):
         ld = W.ld_padded(nr)
         X = W.dd_matrix(rng, nr, nc, ld, dist=dist)
         sr, sl = (1, ld) if trans == "N" else (ld, 1)
-        wf, w = _widths(kind, k, s)
+        wf, w, qmax = _widths(kind, k, s)
         assert b.mpdd_ozaki_digit_widths(algo, k, s) == (wf, w)
-        e_o, q_o = oracle.ozaki_split(rows, k, X, sr, sl, s, wf, w)
+        e_o, q_o = oracle.ozaki_split(rows, k, X, sr, sl, s, wf, w, qmax)
         ldq = 64 * ((k + 63) // 64)
         rows_p = 64 * ((rows + 63) // 64)
         exps = torch.zeros(rows, dtype=torch.int32, device="cuda")
@@ -79,11 +80,11 @@ def test_split_gemm_bit_identical_to_split_oracle(h, kind, op):
         for dist in ("uniform", "wide"):
             s = 9 if kind == "i8" else 4
             case = W.gemm_case(60 + m + k, op[0], op[1], m, n, k, dist=dist)
-            wf, w = _widths(kind, k, s)
+            wf, w, qmax = _widths(kind, k, s)
             O = (case["C"][0].copy(), case["C"][1].copy())
             assert oracle.ozaki_rgemm(op[0], op[1], m, n, k, case["alpha"], case["A"], case["lda"],
                                       case["B"], case["ldb"], case["beta"], O, case["ldc"], s, wf,
-                                      w) == 0
+                                      w, qmax) == 0
             # every INT8 product variant (workgroup tiling) must give the same bits
             for var in (VARIANTS if kind == "i8" else (-1,)):
                 info, G = gemm_gpu(h, case, opts=dict(algo=algo, nslices=s, tile_id=var))

@@ -63,6 +63,13 @@ MUTANTS = [
      "ldexp((double)x, -(2 * wfirst + w * (d - 1)))", "wrong anti-diagonal weight"),
     ("ozaki_oracle.c", "p.hi = ldexp(p.hi, ea[i] + eb[j]);", "p.hi = ldexp(p.hi, ea[i]);",
      "column scale dropped"),
+    ("ozaki_oracle.c", "if (*q > qmax) {", "if (0) {", "digits not carried into int8's range"),
+    ("ozaki_oracle.c", "digits[((int64_t)(t - 1) * rows + r) * k + l] += 1;",
+     "digits[((int64_t)(t - 1) * rows + r) * k + l] += 0;", "carry lost"),
+    ("ozaki_oracle.c", "*q -= (int32_t)1 << w;", "*q -= (int32_t)1 << (w - 1);",
+     "carry of the wrong weight"),
+    ("ozaki_oracle.c", "for (t = nslices - 1; t >= 1; --t) {", "for (t = 1; t < nslices; ++t) {",
+     "carries propagated in the wrong order"),
     ("cdd_oracle.c", "r.re = dd_add(dd_mul(x.re, y.re), dd_neg(dd_mul(x.im, y.im)));",
      "r.re = dd_add(dd_mul(x.re, y.re), dd_mul(x.im, y.im));", "complex product: sign of bd"),
     ("cdd_oracle.c", "r.im = dd_add(dd_mul(x.re, y.im), dd_mul(x.im, y.re));",

@@ -129,6 +129,7 @@ def test_ozaki_converges_to_plain(lib):
         for s, ok in ((s_ok, True), (6, False)):
             Z = (c["C"][0].copy(), c["C"][1].copy())
             oracle.ozaki_rgemm("N", "N", 40, 36, 64, c["alpha"], c["A"], c["lda"], c["B"],
-                               c["ldb"], c["beta"], Z, c["ldc"], s, *oracle.INT8_DIGITS, lib=lib)
+                               c["ldb"], c["beta"], Z, c["ldc"], s,
+                               *oracle.int8_digit_widths(64, s), oracle.INT8_QMAX, lib=lib)
             r = ratio(Z[0][idx], Z[1][idx], P[0][idx], P[1][idx], 64)
             assert (r <= 8.0) == ok, (dist, s, r)
