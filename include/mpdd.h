@@ -297,7 +297,10 @@ int mpdd_Rpotrf_nb(mpdd_handle h, const char *uplo, mpdd_int n, double *A_hi, do
  * and every column of op(B) into `nslices` digit slices: with sigma the
  * frexp exponent of the row's largest |hi| (so |x| < 2^sigma), y = x 2^-sigma
  * and, for t = 1..nslices, z = y 2^w_t, q_t = rint(z.hi), y = TwoSum(z.hi - q_t,
- * z.lo).  INT8: w_1 = 6, w_t = 7 (|q| <= 64).  FP64: w_1 = w - 1, w_t = w, with
+ * z.lo).  INT8: w_1 = 6 and w_t = 8 while nslices*k < 2^17 -- a later digit
+ * above 127 (it rounds to 128, or a carry lifts a 127) loses 256 and the digit
+ * before it gains one, from the last digit up, so later digits lie in
+ * [-128, 127] -- else w_t = 7 (|q| <= 64).  FP64: w_1 = w - 1, w_t = w, with
  * w = floor((55 - ceil(log2(nslices*k))) / 2) so that sums of nslices*k digit
  * products are exact in binary64.  Slice products are accumulated exactly per
  * anti-diagonal on the matrix cores and recombined in dd (published basis:
@@ -307,7 +310,8 @@ int mpdd_Rpotrf_nb(mpdd_handle h, const char *uplo, mpdd_int n, double *A_hi, do
 /* Digit widths (first, later) of a split form for k and nslices.
  * Returns 0, or MPDD_ERR_UNSUPPORTED when no exact width exists (INT8 needs
  * nslices*k < 2^19, so that every anti-diagonal sum, at most
- * nslices*k*64^2 in magnitude, stays below 2^31). */
+ * nslices*k*2^(2w-2) in magnitude, stays below 2^31: w = 8 below 2^17,
+ * w = 7 from there). */
 int mpdd_ozaki_digit_widths(int algo, mpdd_int k, int nslices, int *wfirst, int *w);
 
 /* Scale exponents and digit slices of a "row operand" R (rows x k): element

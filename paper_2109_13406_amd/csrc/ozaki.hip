@@ -7,13 +7,16 @@
 //  scale    sigma_r = frexp exponent of max_l |x_rl.hi| for every row of op(A)
 //           and every column of op(B) ("row operand"), so |x| < 2^sigma.
 //  slice    y = x * 2^-sigma (exact); digit t: z = y * 2^w_t, q_t = rint(z.hi),
-//           y = TwoSum(z.hi - q_t, z.lo).  INT8 form: w_1 = 6, w_t = 7, so
-//           |q| <= 64; FP64 form: w_1 = w - 1, w_t = w with w chosen so that
-//           every sum of nslices*k digit products stays an integer < 2^53.
-//           Digits are stored k-contiguous per row, in tiles padded with zeros.
+//           y = TwoSum(z.hi - q_t, z.lo).  INT8 form: w_1 = 6 and w_t = 8 while
+//           nslices*k < 2^17 (a later digit that rounds to 128, or reaches it
+//           by a carry, loses 256 and the digit before it gains one, so every
+//           later digit is in [-128, 127]), else w_t = 7 (|q| <= 64); FP64
+//           form: w_1 = w - 1, w_t = w with w chosen so that every sum of
+//           nslices*k digit products stays an integer < 2^53.  Digits are
+//           stored k-contiguous per row, in tiles padded with zeros.
 //  products for every anti-diagonal d = t + u (2 <= d <= s + 1):
 //           X_d = sum_t Q_t Q'_{d-t}^T, exact: int8 x int8 -> int32 on the
-//           INT8 MFMA (|X_d| <= s*k*64^2 < 2^31), or FP64 MFMA on integers.
+//           INT8 MFMA (|X_d| <= s*k*2^(2w-2) < 2^31), or FP64 MFMA on integers.
 //  combine  P = sum_d X_d 2^-(2 w_1 + w (d-2)), added in dd (DWPlusFP) from the
 //           smallest weight up; P * 2^(sigma_i + tau_j); C = alpha*P + beta*C.
 // Binary64 arithmetic appears only in scaling, slicing and combining.
@@ -149,6 +152,41 @@ oz_slice(const double* __restrict__ xh, const double* __restrict__ xl, int64_t s
         y[i].hi = ldexp(t[rr][lb + i], -e);
     }
   }
+  // 8-bit int8 digits: a later digit of 128 does not fit, so it is carried
+  // into the digit before it (it loses 2^w = 256, that digit gains one; the
+  // value does not change).  A carry can turn a 127 into 128, so it runs on
+  // through digits of 127.  A first pass over the digits finds every carry:
+  // a digit of 128 carries, and so does each 127 directly before it in a run
+  // that ends in 128; any other digit ends the run.  Bit t of cm[i] is the
+  // carry out of digit t of element i (never the first digit's).  The second
+  // pass recomputes the same digits and stores them carried.
+  uint64_t cm[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) cm[i] = 0;
+  if (sizeof(T) == 1 && w > 7) {
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      ddv z = y[i];
+      uint64_t run = 0, c = 0;
+      for (int t = 0; t < nslices; ++t) {
+        const int shift = (t == 0) ? wfirst : w;
+        const double zh = ldexp(z.hi, shift), zl = ldexp(z.lo, shift);
+        const double qd = rint(zh);
+        z = two_sum(zh - qd, zl);
+        if (t == 0) continue;
+        const uint64_t bit = (uint64_t)1 << t;
+        if (qd >= 128.0) {
+          c |= run | bit;
+          run = 0;
+        } else if (qd == 127.0) {
+          run |= bit;
+        } else {
+          run = 0;
+        }
+      }
+      cm[i] = c;
+    }
+  }
   T* out = q + r * ldq + l0 + lb;
   for (int t = 0; t < nslices; ++t) {
     const int shift = (t == 0) ? wfirst : w;
@@ -157,7 +195,9 @@ oz_slice(const double* __restrict__ xh, const double* __restrict__ xl, int64_t s
     for (int i = 0; i < 16; ++i) {
       const double zh = ldexp(y[i].hi, shift), zl = ldexp(y[i].lo, shift);
       const double qd = rint(zh);
-      dig[i] = (T)qd;
+      // carry in from digit t + 1, carry out of digit t
+      const int cin = (int)((cm[i] >> (t + 1)) & 1), cout = (int)((cm[i] >> t) & 1);
+      dig[i] = (sizeof(T) == 1) ? (T)((int)qd + cin - (cout << w)) : (T)qd;
       y[i] = two_sum(zh - qd, zl);
     }
     T* o = out + (int64_t)t * plane;
@@ -642,10 +682,13 @@ static int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
 // Digit widths of a kind for k terms and nslices slices.
 static bool digit_widths(int algo, int64_t k, int nslices, int& wfirst, int& w) {
   if (algo == MPDD_OZAKI_I8) {
+    // |X_d| <= nslices * k * 2^(2w-2) must stay below 2^31: 8-bit later
+    // digits (|q| <= 128) while nslices * k < 2^17, 7-bit ones (|q| <= 64)
+    // while nslices * k < 2^19
+    const int64_t terms = (int64_t)nslices * k;
     wfirst = 6;
-    w = 7;
-    // |X_d| <= nslices * k * 64^2 must stay below 2^31, i.e. nslices * k < 2^19
-    return (int64_t)nslices * k < ((int64_t)1 << 19);
+    w = (terms < ((int64_t)1 << 17)) ? 8 : 7;
+    return terms < ((int64_t)1 << 19);
   }
   int64_t terms = std::max<int64_t>(1, (int64_t)nslices * k);
   int lg = 0;

@@ -203,20 +203,26 @@ def test_qgemm_info_codes_before_handle(lib):
 
 
 def test_int8_digit_width_guard_is_strict():
-    """INT8 split form: every anti-diagonal sum is at most nslices*k*64^2 in
-    magnitude and must stay below 2^31, so nslices*k must be below 2^19;
-    s*k = 2^19 is rejected, one less is accepted."""
+    """INT8 split form: every anti-diagonal sum is at most nslices*k*2^(2w-2)
+    in magnitude and must stay below 2^31: 8-bit later digits while
+    nslices*k < 2^17, 7-bit ones while nslices*k < 2^19; s*k = 2^19 is
+    rejected, one less is accepted, and the widths follow the oracle's rule."""
+    import oracle
     from paper_2109_13406_amd import binding as b
     wf, w = ctypes.c_int(), ctypes.c_int()
     lib = b.load()
-    for s, k, ok in ((16, 1 << 15, False), (8, 1 << 16, False), (1, 1 << 19, False),
-                     (16, (1 << 15) - 1, True), (13, 8192, True), (1, (1 << 19) - 1, True)):
+    for s, k, ok, want in ((16, 1 << 15, False, None), (8, 1 << 16, False, None),
+                           (1, 1 << 19, False, None), (16, (1 << 15) - 1, True, (6, 7)),
+                           (1, (1 << 19) - 1, True, (6, 7)), (16, 1 << 13, True, (6, 7)),
+                           (16, (1 << 13) - 1, True, (6, 8)), (13, 8192, True, (6, 8)),
+                           (1, (1 << 17) - 1, True, (6, 8)), (1, 1 << 17, True, (6, 7))):
         rc = lib.mpdd_ozaki_digit_widths(b.MPDD_OZAKI_I8, k, s, ctypes.byref(wf), ctypes.byref(w))
         assert (rc == 0) == ok, (s, k, rc)
+        assert oracle.int8_digit_widths(k, s) == want
         if not ok:
             assert rc == b.MPDD_ERR_UNSUPPORTED
         else:
-            assert (wf.value, w.value) == (6, 7)
+            assert (wf.value, w.value) == want, (s, k)
 
 
 def test_noalloc_info_codes_before_handle(lib):

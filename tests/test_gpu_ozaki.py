@@ -34,7 +34,9 @@ def h():
 
 def _widths(kind, k, s):
     """(wfirst, w, qmax) of the library's digits for k terms and s slices."""
-    return (6, 7, oracle.INT8_QMAX) if kind == "i8" else oracle.fp64_digit_width(k, s) + (0,)
+    if kind == "i8":
+        return oracle.int8_digit_widths(k, s) + (oracle.INT8_QMAX,)
+    return oracle.fp64_digit_width(k, s) + (0,)
 
 
 @pytest.mark.parametrize("kind", ["i8", "f64"])
@@ -44,7 +46,8 @@ def test_slices_bit_identical(h, kind, trans, dist):
     import torch
     from paper_2109_13406_amd import binding as b
     algo = KINDS[kind]
-    for (rows, k, s) in [(70, 90, 16), (1, 1, 3), (130, 200, 9)]:
+    # (the last shape has nslices*k >= 2^17: 7-bit INT8 digits)
+    for (rows, k, s) in [(70, 90, 16), (1, 1, 3), (130, 200, 9), (3, 9000, 16)]:
         rng = W.streams(11 + rows)[0]
         nr, nc = (rows, k) if trans == "N" else (k, rows)
         ld = W.ld_padded(nr)
@@ -66,6 +69,43 @@ def test_slices_bit_identical(h, kind, trans, dist):
         assert np.array_equal(qg[:, :rows, :k], q_o.astype(qg.dtype)), (kind, trans, rows, k)
         assert not qg[:, rows:, :].any() and not qg[:, :, k:].any()
     log(f"PARITY ozaki slices {kind} {trans} {dist} bit-identical")
+
+
+def test_int8_slices_carry_chains(h):
+    """8-bit INT8 digits that round to 128 are carried into the digit before
+    them, through runs of 127: rows built from values whose digits are
+    worked out by hand (first digit 20, then 128, or 127 then 128), beside
+    0.75 for the scale, give the oracle's carried digits bit for bit."""
+    import torch
+    from fractions import Fraction
+    from paper_2109_13406_amd import binding as b
+    vals = [Fraction(20 * 256 + Fraction(511, 4), 256 * 64),
+            Fraction(20 * 256 * 256 + 127 * 256 + Fraction(511, 4), 256 * 256 * 64)]
+    rows, k, s = 2, 64, 6
+    X = (np.zeros(rows * k), np.zeros(rows * k))     # row-major rows: trans "T", ld = k
+    for r, x in enumerate(vals):
+        X[0][r * k] = 0.75
+        for l in range(1, k):
+            sign = -1 if l % 2 else 1
+            hi = float(x) * sign
+            X[0][r * k + l] = hi
+            X[1][r * k + l] = float(sign * x - Fraction(hi))
+    wf, w, qmax = _widths("i8", k, s)
+    assert (wf, w) == (6, 8)
+    e_o, q_o = oracle.ozaki_split(rows, k, X, k, 1, s, wf, w, qmax)
+    # odd l hold -x (no carry: -128 fits), even l > 0 hold x (carried)
+    assert [int(v) for v in q_o[:, 0, 2]] == [21, -128, -64, 0, 0, 0]
+    assert [int(v) for v in q_o[:, 1, 2]] == [21, -128, -128, -64, 0, 0]
+    assert [int(v) for v in q_o[:, 0, 1]] == [-20, -128, 64, 0, 0, 0]
+    exps = torch.zeros(rows, dtype=torch.int32, device="cuda")
+    q = torch.full((s, 64, 64), 7, dtype=torch.int8, device="cuda")
+    info = b.mpdd_ozaki_split(h, b.MPDD_OZAKI_I8, "T", rows, k, dev(X), k, s, exps, q, 64, 64)
+    assert info == 0
+    torch.cuda.synchronize()
+    assert np.array_equal(exps.cpu().numpy(), e_o)
+    qg = q.cpu().numpy().astype(np.int64)
+    assert np.array_equal(qg[:, :rows, :k], q_o.astype(np.int64))
+    log("PARITY ozaki int8 carry chains bit-identical")
 
 
 SHAPES = [(1, 1, 1), (70, 90, 33), (129, 130, 200), (200, 64, 65), (300, 270, 130)]
@@ -159,10 +199,10 @@ def slice_search(h, kind, n, dist, start, stop):
 @pytest.mark.parametrize("dist", ["uniform", "wide"])
 def test_config3_slice_count_search(h, n, kind, dist):
     """Config 3: the slice count is searched upward from below any count
-    that can reach dd accuracy (INT8 from 10 slices, FP64 from 3) until the
+    that can reach dd accuracy (INT8 from 8 slices, FP64 from 3) until the
     result is within 8 k 2^-104 of the oracle; the counts below it are
     checked and fail, the one found passes."""
-    start, stop = {"i8": (10, 24), "f64": (3, 10)}[kind]
+    start, stop = {"i8": (8, 24), "f64": (3, 10)}[kind]
     s, r = slice_search(h, kind, n, dist, start, stop)
     log(f"CONFIG3 {kind} n={n} {dist}: slices={s} ratio={r}")
     assert s is not None and s > start
