@@ -148,8 +148,8 @@ typedef struct {
                    4 = 256x256 with 16 waves, 5 = 256x256 with 8 waves
                    and digits loaded straight into LDS, 6 = as 5 with
                    the next step's fragments read during the MFMAs,
-                   7 = as 6 with 4 waves (128x128 each), -1 = default
-                   (6);
+                   7 = as 6 with 4 waves (128x128 each), 8 = as 6 with
+                   32x32x32 matrix instructions, -1 = default (6);
                    all give the same bits; ignored by the FP64 split form */
   int splitk;   /* plain forms: k-split factor, 0 = automatic, 1 = none */
 } mpdd_opts;

@@ -25,6 +25,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <type_traits>
 
 #include "../../include/mpdd.h"
 #include "dd.hpp"
@@ -103,78 +104,140 @@ oz_scale_rows_wave(const double* __restrict__ x, int64_t sr, int64_t sl, int64_t
 
 // ---- slice -------------------------------------------------------------------------
 
-// One 64 x 64 block of the row operand per workgroup.  Elements are read with
-// lanes along whichever index is contiguous in memory, staged in LDS, then
-// each thread turns 16 consecutive l of one row into digits and writes them
-// k-contiguously (16 int8 = one 16-byte store per digit, or 16 doubles).
-// Rows >= rows and l >= k (padding) get zero digits.
+// One 64 x 64 block of the row operand per workgroup of 512 threads.
+// Elements are read with lanes along whichever index is contiguous in memory,
+// staged in LDS, then each thread turns 8 consecutive l of one row into
+// digits and writes them k-contiguously (8 int8 = one 8-byte store per digit,
+// or 8 doubles).  Rows >= rows and l >= k (padding) get zero digits.
+//
+// 8-bit int8 digits: a later digit of 128 does not fit, so it is carried into
+// the digit before it (it loses 2^w = 256, that digit gains one; the value
+// does not change).  A carry can turn a 127 into 128, so it runs on through
+// digits of 127: a digit of 128 carries out, and so does each 127 directly
+// before it in a run that ends in 128; any other digit ends the run.  With at
+// most 16 digits the raw digits of an element stay in registers and every
+// carry is known once its last digit is: digit t is then stored as
+// raw_t + carry_in_t wrapped to 8 bits (a carried 128 + c becomes c - 128, a
+// carried 127 + 1 becomes -128, the others do not wrap).  Longer digit
+// strings take two passes: the first finds the carries, the second recomputes
+// the digits and stores them carried.
+//
+// The remainder after a digit, (z.hi - q) + z.lo, is formed with FastTwoSum:
+// z.hi - q is exact and a whole multiple of ulp(z.hi) (q is an integer, and
+// |z.hi - q| <= 1/2 keeps it within z.hi's binade or below), so it is zero or
+// at least ulp(z.hi) in magnitude, while |z.lo| <= ulp(z.hi)/2 for a
+// normalised pair -- FastTwoSum's condition holds and it returns the same
+// pair as TwoSum in half the operations.
+constexpr int OZ_SLICE_REG_DIGITS = 16;
+
 template <typename T>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(512)
 oz_slice(const double* __restrict__ xh, const double* __restrict__ xl, int64_t sr, int64_t sl,
          int64_t rows, int64_t k, const int* __restrict__ exps, int nslices, int wfirst, int w,
          T* __restrict__ q, int64_t ldq, int64_t plane) {
   // one 33 KB staging buffer, used for the hi plane and then the lo plane
-  // (four workgroups per CU instead of two with both planes staged at once)
   __shared__ double t[64][65];
   const int tid = threadIdx.x;
   const int64_t r0 = (int64_t)blockIdx.y * 64;
   const int64_t l0 = (int64_t)blockIdx.x * 64;
   const bool lanes_on_r = (sr == 1);
-  const int rr = tid >> 2;
-  const int lb = (tid & 3) * 16;
+  const int rr = tid >> 3;
+  const int lb = (tid & 7) * 8;
   const int64_t r = r0 + rr;
   const int e = (r < rows) ? exps[r] : 0;
-  ddv y[16];
+  ddv y[8];
 #pragma unroll
   for (int half = 0; half < 2; ++half) {
     const double* __restrict__ src = half ? xl : xh;
-    double v[16];
+    double v[8];
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int a = tid & 63, b = (tid >> 6) + 4 * q;
+    for (int c = 0; c < 8; ++c) {
+      const int a = tid & 63, b = (tid >> 6) + 8 * c;
       const int ri = lanes_on_r ? a : b;
       const int li = lanes_on_r ? b : a;
       const int64_t rg = r0 + ri, lg = l0 + li;
-      v[q] = (rg < rows && lg < k) ? src[rg * sr + lg * sl] : 0.0;
+      v[c] = (rg < rows && lg < k) ? src[rg * sr + lg * sl] : 0.0;
     }
     if (half) __syncthreads();               // the hi values have been read
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int a = tid & 63, b = (tid >> 6) + 4 * q;
-      t[lanes_on_r ? a : b][lanes_on_r ? b : a] = v[q];
+    for (int c = 0; c < 8; ++c) {
+      const int a = tid & 63, b = (tid >> 6) + 8 * c;
+      t[lanes_on_r ? a : b][lanes_on_r ? b : a] = v[c];
     }
     __syncthreads();
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
+    for (int i = 0; i < 8; ++i) {
       if (half)
         y[i].lo = ldexp(t[rr][lb + i], -e);
       else
         y[i].hi = ldexp(t[rr][lb + i], -e);
     }
   }
-  // 8-bit int8 digits: a later digit of 128 does not fit, so it is carried
-  // into the digit before it (it loses 2^w = 256, that digit gains one; the
-  // value does not change).  A carry can turn a 127 into 128, so it runs on
-  // through digits of 127.  A first pass over the digits finds every carry:
-  // a digit of 128 carries, and so does each 127 directly before it in a run
-  // that ends in 128; any other digit ends the run.  Bit t of cm[i] is the
-  // carry out of digit t of element i (never the first digit's).  The second
-  // pass recomputes the same digits and stores them carried.
-  uint64_t cm[16];
+  T* out = q + r * ldq + l0 + lb;
+  const bool carry = sizeof(T) == 1 && w > 7;
+
+  if (carry && nslices <= OZ_SLICE_REG_DIGITS) {
+    // fw[g][t]: carried digit t of elements 4g .. 4g+3, one byte each
+    uint32_t fw[2][OZ_SLICE_REG_DIGITS];
 #pragma unroll
-  for (int i = 0; i < 16; ++i) cm[i] = 0;
-  if (sizeof(T) == 1 && w > 7) {
+    for (int i = 0; i < 8; ++i) {
+      ddv z = y[i];
+      int raw[OZ_SLICE_REG_DIGITS];
+      uint32_t run = 0, cm = 0;                // bit t of cm: carry out of digit t
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
+      for (int d = 0; d < OZ_SLICE_REG_DIGITS; ++d) {
+        raw[d] = 0;
+        if (d < nslices) {
+          const int shift = (d == 0) ? wfirst : w;
+          const double zh = ldexp(z.hi, shift), zl = ldexp(z.lo, shift);
+          const double qd = rint(zh);
+          z = fast_two_sum(zh - qd, zl);
+          raw[d] = (int)qd;
+          if (d > 0) {
+            const uint32_t bit = 1u << d;
+            if (raw[d] >= 128) {
+              cm |= run | bit;
+              run = 0;
+            } else if (raw[d] == 127) {
+              run |= bit;
+            } else {
+              run = 0;
+            }
+          }
+        }
+      }
+#pragma unroll
+      for (int d = 0; d < OZ_SLICE_REG_DIGITS; ++d) {
+        const uint32_t byte = (uint32_t)(raw[d] + (int)((cm >> (d + 1)) & 1u)) & 0xFFu;
+        if ((i & 3) == 0)
+          fw[i >> 2][d] = byte;
+        else
+          fw[i >> 2][d] |= byte << (8 * (i & 3));
+      }
+    }
+#pragma unroll
+    for (int d = 0; d < OZ_SLICE_REG_DIGITS; ++d)
+      if (d < nslices) *(uint2*)(out + (int64_t)d * plane) = uint2{fw[0][d], fw[1][d]};
+    return;
+  }
+
+  // (longer 8-bit digit strings) first pass: the carries; bit d of cm[i] is
+  // the carry out of digit d of element i
+  uint64_t cm[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) cm[i] = 0;
+  if (carry) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
       ddv z = y[i];
       uint64_t run = 0, c = 0;
-      for (int t = 0; t < nslices; ++t) {
-        const int shift = (t == 0) ? wfirst : w;
+      for (int d = 0; d < nslices; ++d) {
+        const int shift = (d == 0) ? wfirst : w;
         const double zh = ldexp(z.hi, shift), zl = ldexp(z.lo, shift);
         const double qd = rint(zh);
-        z = two_sum(zh - qd, zl);
-        if (t == 0) continue;
-        const uint64_t bit = (uint64_t)1 << t;
+        z = fast_two_sum(zh - qd, zl);
+        if (d == 0) continue;
+        const uint64_t bit = (uint64_t)1 << d;
         if (qd >= 128.0) {
           c |= run | bit;
           run = 0;
@@ -187,31 +250,29 @@ oz_slice(const double* __restrict__ xh, const double* __restrict__ xl, int64_t s
       cm[i] = c;
     }
   }
-  T* out = q + r * ldq + l0 + lb;
-  for (int t = 0; t < nslices; ++t) {
-    const int shift = (t == 0) ? wfirst : w;
-    T dig[16];
+  for (int d = 0; d < nslices; ++d) {
+    const int shift = (d == 0) ? wfirst : w;
+    T dig[8];
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
+    for (int i = 0; i < 8; ++i) {
       const double zh = ldexp(y[i].hi, shift), zl = ldexp(y[i].lo, shift);
       const double qd = rint(zh);
-      // carry in from digit t + 1, carry out of digit t
-      const int cin = (int)((cm[i] >> (t + 1)) & 1), cout = (int)((cm[i] >> t) & 1);
+      // carry in from digit d + 1, carry out of digit d
+      const int cin = (int)((cm[i] >> (d + 1)) & 1), cout = (int)((cm[i] >> d) & 1);
       dig[i] = (sizeof(T) == 1) ? (T)((int)qd + cin - (cout << w)) : (T)qd;
-      y[i] = two_sum(zh - qd, zl);
+      y[i] = fast_two_sum(zh - qd, zl);
     }
-    T* o = out + (int64_t)t * plane;
+    T* o = out + (int64_t)d * plane;
     if constexpr (sizeof(T) == 1) {
-      v4i pack;
-#pragma unroll
-      for (int c = 0; c < 4; ++c)
-        pack[c] = (int)((uint32_t)(uint8_t)dig[4 * c] | ((uint32_t)(uint8_t)dig[4 * c + 1] << 8) |
-                        ((uint32_t)(uint8_t)dig[4 * c + 2] << 16) |
-                        ((uint32_t)(uint8_t)dig[4 * c + 3] << 24));
-      *(v4i*)o = pack;
+      uint2 pack;
+      pack.x = (uint32_t)(uint8_t)dig[0] | ((uint32_t)(uint8_t)dig[1] << 8) |
+               ((uint32_t)(uint8_t)dig[2] << 16) | ((uint32_t)(uint8_t)dig[3] << 24);
+      pack.y = (uint32_t)(uint8_t)dig[4] | ((uint32_t)(uint8_t)dig[5] << 8) |
+               ((uint32_t)(uint8_t)dig[6] << 16) | ((uint32_t)(uint8_t)dig[7] << 24);
+      *(uint2*)o = pack;
     } else {
 #pragma unroll
-      for (int i = 0; i < 16; ++i) o[i] = dig[i];
+      for (int i = 0; i < 8; i += 2) *(double2*)(o + i) = double2{dig[i], dig[i + 1]};
     }
   }
 }
@@ -260,6 +321,7 @@ __device__ __forceinline__ void oz_tile_of(int b, int tiles_m, int tiles_n, int 
 //   4: 256 x 256, 4 x 4 waves (64 x 64 each, 1024 threads: 4 waves per SIMD)
 //   5, 6: the tiling of 3 in oz_gemm_i8_dma below (6 is the default)
 //   7: 256 x 256, 2 x 2 waves in oz_gemm_i8_dma (1 wave per SIMD)
+//   8: as 6 with v_mfma_i32_32x32x32_i8 (4 x 2 tiles of 32 x 32 per wave)
 constexpr int I8_BK = 64;
 constexpr int I8_PITCH = 64;   // bytes per staged row (one k-step), no padding
 
@@ -397,14 +459,16 @@ __device__ __forceinline__ void i8_sync() {
   asm volatile("s_waitcnt vmcnt(%0) lgkmcnt(%1)\n\ts_barrier" ::"n"(VM), "n"(LGKM) : "memory");
 }
 
-template <int WM, int WN, int GM, int GN, int NS, bool PF>
+template <int WM, int WN, int GM, int GN, int NS, bool PF, bool M32>
 __global__ void __launch_bounds__(64 * GM * GN, 1)
 oz_gemm_i8_dma(const int8_t* __restrict__ qa, const int8_t* __restrict__ qb,
                int32_t* __restrict__ x, int64_t kp, int64_t plane_a, int64_t plane_b, int64_t mp,
                int64_t np, int nslices, int tiles_m, int tiles_n) {
   constexpr int NW = GM * GN;                  // waves
   constexpr int WR = WM / GM, WC = WN / GN;    // outputs per wave
-  constexpr int FA = WR / 16, FB = WC / 16;    // 16-row fragments per wave
+  constexpr int MT = M32 ? 32 : 16;            // MFMA tile edge
+  constexpr int KS = M32 ? 2 : 1;              // MFMA k-slabs per 64-byte step
+  constexpr int FA = WR / MT, FB = WC / MT;    // fragments per wave and slab
   constexpr int RA = WM / NW, RB = WN / NW;    // rows of each operand one wave stages
   constexpr int LA = RA / 16, LB = RB / 16;    // DMA instructions per operand and step
   constexpr int STAGE = (WM + WN) * I8_PITCH;  // bytes per stage
@@ -419,11 +483,13 @@ oz_gemm_i8_dma(const int8_t* __restrict__ qa, const int8_t* __restrict__ qb,
   oz_tile_of(blockIdx.x, tiles_m, tiles_n, nslices, d, bi, bj);
   const int64_t i0 = (int64_t)bi * WM, j0 = (int64_t)bj * WN;
 
-  v4i acc[FA][FB];
+  typedef int v16i __attribute__((ext_vector_type(16)));
+  typedef typename std::conditional<M32, v16i, v4i>::type accv;
+  accv acc[FA][FB];
 #pragma unroll
   for (int a = 0; a < FA; ++a)
 #pragma unroll
-    for (int c = 0; c < FB; ++c) acc[a][c] = v4i{0, 0, 0, 0};
+    for (int c = 0; c < FB; ++c) acc[a][c] = accv{};
 
   // lane l of a DMA instruction fills staged row r0 + l/4 (r0 a multiple of
   // 16), physical chunk l%4, which holds logical chunk (l%4) ^ g(row); g
@@ -467,21 +533,36 @@ oz_gemm_i8_dma(const int8_t* __restrict__ qa, const int8_t* __restrict__ qb,
     }
     ibuf = (ibuf + 1 == NS) ? 0 : ibuf + 1;
   };
-  const int fr = lane & 15, fc = lane >> 4;
-  auto fetch = [&](int buf, v4i (&af)[FA], v4i (&bf)[FB]) {
+  // fragment row and 16-byte chunk of this lane: 16 x 16 x 64 MFMAs take
+  // row l % 16, chunk l / 16; 32 x 32 x 32 ones take row l % 32, chunk
+  // 2 h + l / 32 of k-slab h
+  const int fr = lane & (MT - 1), fc = lane / MT;
+  auto fetch = [&](int buf, v4i (&af)[KS * FA], v4i (&bf)[KS * FB]) {
     const int8_t* As = smem + buf * STAGE;
     const int8_t* Bs = As + WM * I8_PITCH;
 #pragma unroll
-    for (int a = 0; a < FA; ++a) af[a] = *(const v4i*)&As[i8_lds(wm * WR + a * 16 + fr, fc)];
+    for (int h = 0; h < KS; ++h) {
 #pragma unroll
-    for (int c = 0; c < FB; ++c) bf[c] = *(const v4i*)&Bs[i8_lds(wn * WC + c * 16 + fr, fc)];
-  };
-  auto mfma = [&](const v4i (&af)[FA], const v4i (&bf)[FB]) {
-#pragma unroll
-    for (int a = 0; a < FA; ++a)
+      for (int a = 0; a < FA; ++a)
+        af[h * FA + a] = *(const v4i*)&As[i8_lds(wm * WR + a * MT + fr, KS * h + fc)];
 #pragma unroll
       for (int c = 0; c < FB; ++c)
-        acc[a][c] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af[a], bf[c], acc[a][c], 0, 0, 0);
+        bf[h * FB + c] = *(const v4i*)&Bs[i8_lds(wn * WC + c * MT + fr, KS * h + fc)];
+    }
+  };
+  auto mfma = [&](const v4i (&af)[KS * FA], const v4i (&bf)[KS * FB]) {
+#pragma unroll
+    for (int h = 0; h < KS; ++h)
+#pragma unroll
+      for (int a = 0; a < FA; ++a)
+#pragma unroll
+        for (int c = 0; c < FB; ++c) {
+          if constexpr (M32)
+            acc[a][c] = __builtin_amdgcn_mfma_i32_32x32x32_i8(af[h * FA + a], bf[h * FB + c],
+                                                              acc[a][c], 0, 0, 0);
+          else
+            acc[a][c] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af[a], bf[c], acc[a][c], 0, 0, 0);
+        }
   };
   // The fragments read one step earlier have long arrived: waiting for them
   // (lgkmcnt(0), before the next prefetch is issued) costs nothing and tells
@@ -494,7 +575,7 @@ oz_gemm_i8_dma(const int8_t* __restrict__ qa, const int8_t* __restrict__ qb,
   // LDS reads that may stay in flight at a barrier: the prefetch (FA + FB
   // reads), capped by the 4-bit counter (waiting for its oldest read as well
   // is harmless)
-  constexpr int PFQ = (FA + FB < 15) ? FA + FB : 15;
+  constexpr int PFQ = (KS * (FA + FB) < 15) ? KS * (FA + FB) : 15;
 
 #pragma unroll
   for (int q = 0; q < NS - 1; ++q) issue();
@@ -505,7 +586,7 @@ oz_gemm_i8_dma(const int8_t* __restrict__ qa, const int8_t* __restrict__ qb,
     for (int64_t s = 0; s < total; ++s) {
       i8_sync<(NS - 2) * PER, 0>();
       issue();                                 // step s + NS - 1
-      v4i af[FA], bf[FB];
+      v4i af[KS * FA], bf[KS * FB];
       fetch((int)(s % NS), af, bf);
       mfma(af, bf);
     }
@@ -516,7 +597,7 @@ oz_gemm_i8_dma(const int8_t* __restrict__ qa, const int8_t* __restrict__ qb,
     // prefetch of step s (FA + FB, the youngest) may still be in flight, those
     // of step s - 1 are done, so stage (s - 1) % NS may be refilled.
     static_assert(NS >= 4, "prefetch needs four stages");
-    v4i af0[FA], bf0[FB], af1[FA], bf1[FB];
+    v4i af0[KS * FA], bf0[KS * FB], af1[KS * FA], bf1[KS * FB];
     i8_sync<(NS - 2) * PER, 0>();
     fetch(0, af0, bf0);
     // total is even (kp is a multiple of 2 * I8_BK)
@@ -538,14 +619,26 @@ oz_gemm_i8_dma(const int8_t* __restrict__ qa, const int8_t* __restrict__ qb,
   __builtin_amdgcn_s_waitcnt(0x0F70);          // vmcnt(0), lgkmcnt not waited on
   __builtin_amdgcn_sched_barrier(0);
 
+  // C layout: 16 x 16 tile, lane l holds rows 4 (l / 16) + 0..3 of column
+  // l % 16; 32 x 32 tile, lane l holds rows 8 g + 4 (l / 32) + 0..3 of column
+  // l % 32 in registers 4 g .. 4 g + 3
   int32_t* xd = x + (int64_t)(d - 2) * mp * np;
 #pragma unroll
   for (int a = 0; a < FA; ++a)
 #pragma unroll
     for (int c = 0; c < FB; ++c) {
-      const int64_t i = i0 + wm * WR + a * 16 + (lane >> 4) * 4;
-      const int64_t j = j0 + wn * WC + c * 16 + (lane & 15);
-      *(v4i*)&xd[j * mp + i] = acc[a][c];
+      const int64_t j = j0 + wn * WC + c * MT + (lane & (MT - 1));
+      if constexpr (M32) {
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+          const int64_t i = i0 + wm * WR + a * MT + 8 * g + 4 * (lane >> 5);
+          *(v4i*)&xd[j * mp + i] = v4i{acc[a][c][4 * g], acc[a][c][4 * g + 1],
+                                       acc[a][c][4 * g + 2], acc[a][c][4 * g + 3]};
+        }
+      } else {
+        const int64_t i = i0 + wm * WR + a * MT + (lane >> 4) * 4;
+        *(v4i*)&xd[j * mp + i] = acc[a][c];
+      }
     }
 }
 
@@ -642,37 +735,54 @@ oz_gemm_f64(const double* __restrict__ qa, const double* __restrict__ qb, double
 
 // ---- combine -------------------------------------------------------------------------
 
+// Four consecutive rows i0 .. i0+3 of one column j per thread: each
+// anti-diagonal sum is one 16-byte (int32) or 32-byte (fp64) load per thread
+// (plane rows are padded to a multiple of 256, so the four are in range and
+// aligned), four anti-diagonals are loaded before any is added.  Per entry
+// the steps are the same as one entry at a time: smallest weight first
+// (d = nslices+1 down to 2), DWPlusFP, then the scale and alpha / beta.
 template <typename XT>
 __global__ void __launch_bounds__(256)
 oz_combine(const XT* __restrict__ x, int64_t mp, int64_t np, int nslices, int wfirst, int w,
            const int* __restrict__ ea, const int* __restrict__ eb, int64_t m, int64_t n,
            double alpha_hi, double alpha_lo, double beta_hi, double beta_lo, int beta_zero,
            double* __restrict__ c_hi, double* __restrict__ c_lo, int64_t ldc) {
+  typedef XT xv4 __attribute__((ext_vector_type(4)));
+  const int64_t mq = (m + 3) / 4;
   const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (gid >= m * n) return;
-  const int64_t i = gid % m, j = gid / m;
-  const XT* xp = x + j * mp + i;
+  if (gid >= mq * n) return;
+  const int64_t i0 = (gid % mq) * 4, j = gid / mq;
+  const XT* xp = x + j * mp + i0;
   const int64_t plane = mp * np;
-  // smallest weight first (d = nslices+1 down to 2); the sums of eight
-  // anti-diagonals are loaded before any is added, so eight loads are in
-  // flight per thread instead of one
-  ddv p{0.0, 0.0};
-  for (int d0 = nslices + 1; d0 >= 2; d0 -= 8) {
-    double v[8];
+  ddv p[4];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) v[u] = d0 - u >= 2 ? (double)xp[(int64_t)(d0 - u - 2) * plane] : 0.0;
+  for (int r = 0; r < 4; ++r) p[r] = ddv{0.0, 0.0};
+  for (int d0 = nslices + 1; d0 >= 2; d0 -= 4) {
+    xv4 v[4];
 #pragma unroll
-    for (int u = 0; u < 8; ++u)
-      if (d0 - u >= 2) p = dd_add_d(p, ldexp(v[u], -(2 * wfirst + w * (d0 - u - 2))));
+    for (int u = 0; u < 4; ++u)
+      v[u] = d0 - u >= 2 ? *(const xv4*)(xp + (int64_t)(d0 - u - 2) * plane) : xv4{0, 0, 0, 0};
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (d0 - u < 2) continue;
+      const int sh = -(2 * wfirst + w * (d0 - u - 2));
+#pragma unroll
+      for (int r = 0; r < 4; ++r) p[r] = dd_add_d(p[r], ldexp((double)v[u][r], sh));
+    }
   }
-  const int e = ea[i] + eb[j];
-  p.hi = ldexp(p.hi, e);
-  p.lo = ldexp(p.lo, e);
-  ddv r = dd_mul(ddv{alpha_hi, alpha_lo}, p);
-  const int64_t ci = i + j * ldc;
-  if (!beta_zero) r = dd_add(r, dd_mul(ddv{beta_hi, beta_lo}, ddv{c_hi[ci], c_lo[ci]}));
-  c_hi[ci] = r.hi;
-  c_lo[ci] = r.lo;
+  const ddv alpha{alpha_hi, alpha_lo}, beta{beta_hi, beta_lo};
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int64_t i = i0 + r;
+    if (i >= m) break;
+    const int e = ea[i] + eb[j];
+    ddv pr{ldexp(p[r].hi, e), ldexp(p[r].lo, e)};
+    ddv res = dd_mul(alpha, pr);
+    const int64_t ci = i + j * ldc;
+    if (!beta_zero) res = dd_add(res, dd_mul(beta, ddv{c_hi[ci], c_lo[ci]}));
+    c_hi[ci] = res.hi;
+    c_lo[ci] = res.lo;
+  }
 }
 
 // ---- host orchestration -------------------------------------------------------------
@@ -717,7 +827,7 @@ static hipError_t split_operand(const double* hi, const double* lo, int64_t sr, 
                        part, rows, nchunks, exps);
   }
   dim3 grid((unsigned)(ldq / 64), (unsigned)(rows_p / 64));
-  hipLaunchKernelGGL(oz_slice<T>, grid, dim3(256), 0, st, hi, lo, sr, sl, rows, k, exps, nslices,
+  hipLaunchKernelGGL(oz_slice<T>, grid, dim3(512), 0, st, hi, lo, sr, sl, rows, k, exps, nslices,
                      wfirst, w, q, ldq, rows_p * ldq);
   return hipGetLastError();
 }
@@ -758,7 +868,7 @@ int ozaki_gemm(const void* opts_v, bool ta, bool tb, int64_t m, int64_t n, int64
   // into a four-stage LDS ring and each step's fragments read during the
   // previous step's MFMAs; fastest measured at n = 4096 and 8192)
   const int var = (i8 && opts->tile_id >= 0) ? opts->tile_id : 6;
-  if (i8 && var > 7) return MPDD_ERR_UNSUPPORTED;
+  if (i8 && var > 8) return MPDD_ERR_UNSUPPORTED;
   const int64_t tbm = i8 ? (var == 2 ? 128 : 256) : OZ_BM;
   const int64_t tbn = i8 ? ((var == 0 || var >= 3) ? 256 : 128) : OZ_BN;
   const int64_t mp = round_up(m, i8 ? I8_PAD : OZ_BM), np = round_up(n, i8 ? I8_PAD : OZ_BN);
@@ -807,10 +917,11 @@ int ozaki_gemm(const void* opts_v, bool ta, bool tb, int64_t m, int64_t n, int64
                   : (var == 2) ? oz_gemm_i8<128, 128, 2, 2>
                   : (var == 3) ? oz_gemm_i8<256, 256, 2, 4>
                   : (var == 4) ? oz_gemm_i8<256, 256, 4, 4>
-                  : (var == 5) ? oz_gemm_i8_dma<256, 256, 2, 4, 4, false>
-                  : (var == 6) ? oz_gemm_i8_dma<256, 256, 2, 4, 4, true>
-                               : oz_gemm_i8_dma<256, 256, 2, 2, 4, true>;
-      const unsigned nthreads = (var == 4) ? 1024 : (var >= 3 && var <= 6) ? 512 : 256;
+                  : (var == 5) ? oz_gemm_i8_dma<256, 256, 2, 4, 4, false, false>
+                  : (var == 6) ? oz_gemm_i8_dma<256, 256, 2, 4, 4, true, false>
+                  : (var == 7) ? oz_gemm_i8_dma<256, 256, 2, 2, 4, true, false>
+                               : oz_gemm_i8_dma<256, 256, 2, 4, 4, true, true>;
+      const unsigned nthreads = (var == 4) ? 1024 : (var >= 3 && var != 7) ? 512 : 256;
       hipLaunchKernelGGL(kern, dim3(nblocks), dim3(nthreads), 0, st, (const int8_t*)qa,
                          (const int8_t*)qb, (int32_t*)x, kp, mp * kp, np * kp, mp, np, s, tiles_m,
                          tiles_n);
@@ -822,7 +933,7 @@ int ozaki_gemm(const void* opts_v, bool ta, bool tb, int64_t m, int64_t n, int64
     e = hipGetLastError();
   }
   if (e == hipSuccess) {
-    const unsigned cb = (unsigned)((m * n + 255) / 256);
+    const unsigned cb = (unsigned)(((m + 3) / 4 * n + 255) / 256);
     if (i8)
       hipLaunchKernelGGL(oz_combine<int32_t>, dim3(cb), dim3(256), 0, st, (const int32_t*)x, mp,
                          np, s, wfirst, w, ea, eb, m, n, alpha_hi, alpha_lo, beta_hi, beta_lo,

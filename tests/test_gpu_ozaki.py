@@ -46,8 +46,9 @@ def test_slices_bit_identical(h, kind, trans, dist):
     import torch
     from paper_2109_13406_amd import binding as b
     algo = KINDS[kind]
-    # (the last shape has nslices*k >= 2^17: 7-bit INT8 digits)
-    for (rows, k, s) in [(70, 90, 16), (1, 1, 3), (130, 200, 9), (3, 9000, 16)]:
+    # (3 x 9000 x 16 has nslices*k >= 2^17: 7-bit INT8 digits; 40 x 300 x 20
+    # has more 8-bit digits than the slicing kernel keeps in registers)
+    for (rows, k, s) in [(70, 90, 16), (1, 1, 3), (130, 200, 9), (3, 9000, 16), (40, 300, 20)]:
         rng = W.streams(11 + rows)[0]
         nr, nc = (rows, k) if trans == "N" else (k, rows)
         ld = W.ld_padded(nr)
@@ -109,7 +110,7 @@ def test_int8_slices_carry_chains(h):
 
 
 SHAPES = [(1, 1, 1), (70, 90, 33), (129, 130, 200), (200, 64, 65), (300, 270, 130)]
-VARIANTS = (0, 1, 2, 3, 4, 5, 6, 7)   # INT8 product tilings (see the tile_id options)
+VARIANTS = (0, 1, 2, 3, 4, 5, 6, 7, 8)   # INT8 product tilings (see the tile_id options)
 
 
 @pytest.mark.parametrize("kind", ["i8", "f64"])
@@ -169,7 +170,7 @@ def test_split_semantics(h):
                        opts=dict(algo=b.MPDD_OZAKI_I8, nslices=41))
     assert info == b.MPDD_ERR_UNSUPPORTED
     info, _ = gemm_gpu(h, W.gemm_case(74, "N", "N", 8, 8, 8),
-                       opts=dict(algo=b.MPDD_OZAKI_I8, nslices=12, tile_id=8))
+                       opts=dict(algo=b.MPDD_OZAKI_I8, nslices=12, tile_id=9))
     assert info == b.MPDD_ERR_UNSUPPORTED
 
 
