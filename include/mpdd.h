@@ -354,12 +354,6 @@ int mpdd_ozaki_split(mpdd_handle h, int algo, const char *trans, mpdd_int rows, 
 #define MPDD_OP_GEMM 0
 #define MPDD_OP_SYRK 1
 
-#define MPDD_SERVER_FAKE_DEVICE 1      /* no GPU: groups complete after a simulated time
-                                          (tests of the scheduling logic only) */
-#define MPDD_INJECT_NONE 0
-#define MPDD_INJECT_DEVICE_ERROR 1     /* the request's launch reports a device error */
-#define MPDD_INJECT_ALLOC_FAILURE 2    /* the request fails admission as if out of memory */
-
 typedef struct mpdd_server_s *mpdd_server;
 
 typedef struct {
@@ -375,7 +369,7 @@ typedef struct {
   double *C_hi, *C_lo;
   mpdd_int ldc;
   double arrival;          /* arrival time on mpdd_clock(); < 0 = time of submit */
-  int inject;              /* MPDD_INJECT_*: forced failure of this request only */
+  int inject;              /* 0; other values are test hooks (mpdd_testing.h) */
   int pad2_;
 } mpdd_request;
 
@@ -396,13 +390,11 @@ typedef struct {
 /* Monotonic clock (seconds) used for request timings. */
 double mpdd_clock(void);
 
-/* Create a server on handle h (its device and tuned tiles).  flags:
- * MPDD_SERVER_FAKE_DEVICE (h may be NULL).  Returns 0 or MPDD_ERR_*. */
+/* Create a server on handle h (its device and tuned tiles) with a memory
+ * budget and at most max_inflight admitted requests.  flags: 0 (other values
+ * are test hooks, mpdd_testing.h).  Returns 0 or MPDD_ERR_*. */
 int mpdd_server_create(mpdd_server *s, mpdd_handle h, size_t hbm_budget_bytes, int max_inflight,
                        int flags);
-
-/* Fake-device servers only: simulated throughput and per-group latency. */
-int mpdd_server_set_fake_rate(mpdd_server s, double dd_flops_per_s, double group_latency_s);
 
 /* Enqueue a request (non-blocking).  *ticket identifies it for wait/poll.
  * Returns 0 (the request's own outcome is reported by wait), MPDD_ERR_ARG,

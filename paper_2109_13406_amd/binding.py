@@ -74,6 +74,7 @@ class mpdd_server_stats(ctypes.Structure):
 
 MPDD_OP_GEMM = 0
 MPDD_OP_SYRK = 1
+# test hooks of the request server (include/mpdd_testing.h)
 MPDD_SERVER_FAKE_DEVICE = 1
 MPDD_INJECT_NONE = 0
 MPDD_INJECT_DEVICE_ERROR = 1

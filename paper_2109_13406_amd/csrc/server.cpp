@@ -44,6 +44,7 @@
 #include <vector>
 
 #include "../../include/mpdd.h"
+#include "../../include/mpdd_testing.h"
 #include "kernels.hpp"
 #include "tuner.hpp"
 

@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "../../include/mpdd.h"
+#include "../../include/mpdd_testing.h"
 #include "../../paper_2109_13406_amd/csrc/kernels.hpp"
 #include "../../paper_2109_13406_amd/csrc/tuner.hpp"
 
