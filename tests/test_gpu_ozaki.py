@@ -174,6 +174,69 @@ def test_split_semantics(h):
     assert info == b.MPDD_ERR_UNSUPPORTED
 
 
+def _digit_value(digits, wf, w):
+    """(hi, lo) of the dd value whose digits, as the slicing rounds them, are
+    `digits` (first digit wf bits wide, later ones w bits)."""
+    from fractions import Fraction
+    x = sum(Fraction(d, 2 ** (wf + w * t)) for t, d in enumerate(digits))
+    hi = float(x)
+    return hi, float(x - Fraction(hi))
+
+
+@pytest.mark.parametrize("k,digit", [(10922, 127), (43690, 63)], ids=["w8-k10922", "w7-k43690"])
+def test_int8_accumulators_at_the_exactness_limit(h, k, digit):
+    """Largest k of each INT8 digit width for 12 slices (12 k just below
+    2^17, then just below 2^19), with inputs whose digits are all at their
+    largest (first digit 63, later ones `digit`): every anti-diagonal sum of
+    the last diagonal reaches 90-97 % of 2^31.  The int32 accumulation on the
+    matrix cores must equal the oracle's int64 evaluation bit for bit, for
+    every product tiling, with all products positive and with all negative;
+    one more k for the 7-bit form is rejected."""
+    import torch
+    from paper_2109_13406_amd import binding as b
+    s, m, n = 12, 16, 16
+    wf, w, qmax = _widths("i8", k, s)
+    assert (wf, w) == ((6, 8) if digit == 127 else (6, 7))
+    hi, lo = _digit_value([63] + [digit] * (s - 1), wf, w)
+    # the largest last-diagonal sum: sum over t + u = 13 of q_t q_u, k times
+    top = (2 * 63 * digit + (s - 2) * digit * digit) * k
+    assert 0.9 * 2 ** 31 < top < 2 ** 31
+    for sign_a in (1.0, -1.0):
+        A = (np.full(m * k, sign_a * hi), np.full(m * k, sign_a * lo))
+        B = (np.full(k * n, hi), np.full(k * n, lo))
+        C = (np.zeros(m * n), np.zeros(m * n))
+        # the oracle's digits are the intended ones
+        _, q = oracle.ozaki_split(1, k, A, 0, 1, s, wf, w, qmax)
+        assert [int(v) for v in q[:, 0, 0]] == [int(sign_a) * v for v in [63] + [digit] * (s - 1)]
+        O = (C[0].copy(), C[1].copy())
+        assert oracle.ozaki_rgemm("N", "N", m, n, k, (1.0, 0.0), A, m, B, k, (0.0, 0.0), O, m,
+                                  s, wf, w, qmax) == 0
+        print(f"int8 limit k={k} digit={digit} sign={sign_a}", flush=True)
+        for var in VARIANTS:
+            Cd = dev(C)
+            info = b.mpdd_Rgemm_ex(h, dict(algo=b.MPDD_OZAKI_I8, nslices=s, tile_id=var), "N",
+                                   "N", m, n, k, (1.0, 0.0), dev(A), m, dev(B), k, (0.0, 0.0),
+                                   Cd, m)
+            assert info == 0
+            G = tuple(x.cpu().numpy() for x in Cd)
+            assert np.array_equal(bits(G[0]), bits(O[0])), (k, sign_a, var)
+            assert np.array_equal(bits(G[1]), bits(O[1])), (k, sign_a, var)
+    if w == 7:
+        # s * (k + 1) = 2^19: no exact width, nothing enqueued
+        with pytest.raises(ValueError):
+            b.mpdd_ozaki_digit_widths(b.MPDD_OZAKI_I8, k + 1, s)
+        z = lambda cnt: tuple(torch.zeros(cnt, dtype=torch.float64, device="cuda")
+                              for _ in range(2))
+        Cz = z(m * n)
+        info = b.mpdd_Rgemm_ex(h, dict(algo=b.MPDD_OZAKI_I8, nslices=s), "N", "N", m, n, k + 1,
+                               (1.0, 0.0), z(m * (k + 1)), m, z((k + 1) * n), k + 1, (0.0, 0.0),
+                               Cz, m)
+        assert info == b.MPDD_ERR_UNSUPPORTED
+        torch.cuda.synchronize()
+        assert not Cz[0].any() and not Cz[1].any()
+    log(f"PARITY ozaki int8 at the exactness limit k={k} (w={w}) bit-identical, all variants")
+
+
 def slice_search(h, kind, n, dist, start, stop):
     """Smallest slice count whose sampled ratio vs the dd oracle is <= 8, on
     the benchmark's config-3 inputs and entries (so the slice count the
