@@ -166,6 +166,92 @@ def bench_sizes(h, args, stream):
     return out
 
 
+# Counter passes behind profiles/dd_gemm_nn8192.json (run from the repository
+# root; each is its own rocprofv3 run, FETCH_SIZE and WRITE_SIZE with a 2 GiB
+# copy first, whose counts calibrate the byte counters)
+COUNTER_PASSES = {
+    "fetch": "rocprofv3 --pmc FETCH_SIZE -d {dir} -o fetch -f csv -- python bench.py --steps 1 "
+             "--warmup 0 --no-cpu --no-oracle --sections plain --copy-probe 2147483648",
+    "write": "rocprofv3 --pmc WRITE_SIZE -d {dir} -o write -f csv -- python bench.py --steps 1 "
+             "--warmup 0 --no-cpu --no-oracle --sections plain --copy-probe 2147483648",
+    "sq": "rocprofv3 --pmc SQ_INSTS_VALU_ADD_F64 SQ_INSTS_VALU_MUL_F64 SQ_INSTS_VALU_FMA_F64 "
+          "SQ_INSTS_VALU SQ_INSTS_VALU_MFMA_MOPS_F64 GRBM_GUI_ACTIVE -d {dir} -o sq -f csv -- "
+          "python bench.py --steps 1 --warmup 0 --no-cpu --no-oracle --sections plain",
+}
+PLAIN_KERNEL = "dd_gemm_kernel<64, 64, 16, 4, 4, true, false, false, false, false>"
+
+
+def _counter_rows(d):
+    """{(dispatch, kernel name, grid): {counter: summed value}} of one
+    rocprofv3 counter-collection directory."""
+    import csv
+    import glob
+    files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+    if not files:
+        raise SystemExit(f"no counter_collection.csv under {d}")
+    out = {}
+    for f in files:
+        with open(f) as fh:
+            for r in csv.DictReader(fh):
+                key = (r["Dispatch_Id"], r["Kernel_Name"], int(r["Grid_Size"]))
+                rec = out.setdefault(key, {})
+                rec[r["Counter_Name"]] = rec.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+    return out
+
+
+def write_counter_record(fetch_dir, write_dir, sq_dir, n=8192, copy_bytes=2147483648):
+    """profiles/dd_gemm_nn8192.json from the three counter passes above: per
+    launch of the plain NN kernel at n, FETCH_SIZE and WRITE_SIZE scaled by
+    what the same counters read for a plain copy of copy_bytes, and the FP64
+    issue slots per dd multiply-add from the SQ instruction counts (vector
+    F64 instructions x 64 lanes; F64 matrix MOPS x 512 / 2 FMAs)."""
+    grid = (n // 64) * (n // 64) * 256
+
+    def mean_of(rows, counter, pred):
+        vals = [v[counter] for k, v in rows.items() if pred(k) and counter in v]
+        if not vals:
+            raise SystemExit(f"no dispatch with {counter}")
+        return sum(vals) / len(vals)
+    def copy_of(rows, counter):
+        # the device-to-device copy of the probe: the largest copyBuffer dispatch
+        vals = [v[counter] for k, v in rows.items() if "copyBuffer" in k[1] and counter in v]
+        if not vals:
+            raise SystemExit(f"no copy dispatch with {counter}: run the pass with --copy-probe")
+        return max(vals)
+    plain = lambda k: PLAIN_KERNEL in k[1] and k[2] == grid
+    fr, wr, sr = _counter_rows(fetch_dir), _counter_rows(write_dir), _counter_rows(sq_dir)
+    fetch_kib, write_kib = mean_of(fr, "FETCH_SIZE", plain), mean_of(wr, "WRITE_SIZE", plain)
+    cfetch, cwrite = copy_of(fr, "FETCH_SIZE"), copy_of(wr, "WRITE_SIZE")
+    fscale = copy_bytes / 1024.0 / cfetch
+    wscale = copy_bytes / 1024.0 / cwrite
+    madds = float(n) ** 3
+    sq = {c: mean_of(sr, c, plain) for c in ("SQ_INSTS_VALU_ADD_F64", "SQ_INSTS_VALU_MUL_F64",
+                                             "SQ_INSTS_VALU_FMA_F64", "SQ_INSTS_VALU",
+                                             "SQ_INSTS_VALU_MFMA_MOPS_F64", "GRBM_GUI_ACTIVE")}
+    vec = (sq["SQ_INSTS_VALU_ADD_F64"] + sq["SQ_INSTS_VALU_MUL_F64"] +
+           sq["SQ_INSTS_VALU_FMA_F64"]) * 64 / madds
+    mfma = sq["SQ_INSTS_VALU_MFMA_MOPS_F64"] * 512 / 2 / madds
+    fb, wb = fetch_kib * fscale * 1024, write_kib * wscale * 1024
+    rec = {"kernel": f"{PLAIN_KERNEL} (Rgemm NN, plain form, tile entry 4)",
+           "workload": f"Rgemm NN m=n=k={n}, lda=ldb=ldc={n + 3}, beta != 0",
+           "kernel_sha": kernel_sha(),
+           "fetch_kib_raw": round(fetch_kib, 4), "write_kib_raw": round(write_kib, 4),
+           "copy_probe_bytes": copy_bytes, "copy_fetch_kib_raw": round(cfetch, 4),
+           "copy_write_kib_raw": round(cwrite, 4), "fetch_scale": round(fscale, 5),
+           "write_scale": round(wscale, 5), "fetch_bytes": int(fb), "write_bytes": int(wb),
+           "bytes_per_launch": int(fb + wb), "algorithmic_bytes": 16 * 4 * n * n,
+           "sq_counters": {k: v for k, v in sq.items()},
+           "fp64_valu_ops_per_madd": round(vec, 3), "mfma_fp64_fma_per_madd": round(mfma, 3),
+           "commands": [COUNTER_PASSES[p].format(dir=d) for p, d in
+                        (("fetch", fetch_dir), ("write", write_dir), ("sq", sq_dir))],
+           "written_by": "python bench.py --counter-record FETCH_DIR WRITE_DIR SQ_DIR"}
+    path = os.path.join(ROOT, "profiles", "dd_gemm_nn8192.json")
+    with open(path, "w") as f:
+        json.dump(rec, f, indent=1)
+        f.write("\n")
+    print(json.dumps(rec, indent=1))
+
+
 def cpu_baseline(case, n, cols=64):
     """Time the CPU oracle (as it stands) on all m rows x `cols` columns of the
     same product: A and the selected B columns copied to the host."""
@@ -627,9 +713,15 @@ def main():
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="first run one device-to-device copy of BYTES bytes (a kernel of known "
                          "traffic, to calibrate the HBM byte counters of a profiling pass)")
+    ap.add_argument("--counter-record", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "SQ_DIR"),
+                    help="write profiles/dd_gemm_nn8192.json from the three rocprofv3 counter "
+                         "passes (COUNTER_PASSES) and exit; no GPU is used")
     ap.add_argument("--serve-count", type=int, default=10000)
     ap.add_argument("--serve-count-slow", type=int, default=10000)
     args = ap.parse_args()
+    if args.counter_record:
+        write_counter_record(*args.counter_record)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(each request / product runs on a single MI355X)", file=sys.stderr)

@@ -435,33 +435,34 @@ dd_grouped_kernel(const char* __restrict__ base, const ServeReq* __restrict__ re
 }
 
 // Add the S k-split partials of every entry in a fixed order and apply the
-// alpha / beta update.  Lane groups of S lanes hold one entry's partials
-// (lane s reads partial s); a butterfly of cross-lane dd additions
-// (__shfl_xor, offsets 1, 2, 4, ...) combines them.  TwoSum and the dd add
-// are symmetric in their operands, so every lane of a group ends with the
-// same bits and the result does not depend on the schedule.
-__global__ void __launch_bounds__(256) dd_splitk_reduce(GemmParams p, int S) {
-  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int s = (int)(gid % S);
-  const int64_t e = gid / S;
+// alpha / beta update.  One thread per entry: partial s of consecutive
+// entries is one coalesced load per wave, and the S partials (S a power of
+// two) are summed in a balanced pairwise tree -- ((p0 + p1) + (p2 + p3)) +
+// ... -- by a carry-save stack of at most six pending sums: the sum of the
+// partials seen so far is held as sums over runs of 2^j partials, and a new
+// run is merged with the pending one of its size before it is pushed (the
+// earlier run always the left operand).  The order does not depend on the
+// schedule, so the result is deterministic.  S is a template parameter, so
+// the loop unrolls and the stack stays in registers.
+template <int S>
+__global__ void __launch_bounds__(256) dd_splitk_reduce(GemmParams p) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t total = p.m * p.n;
-  const bool live = e < total;
-  ddv v{0.0, 0.0};
-  if (live) {
-    const int64_t w = (int64_t)s * total + e;
-    v.hi = p.w_hi[w];
-    v.lo = p.w_lo[w];
-  }
-  for (int off = 1; off < S; off <<= 1) {
-    ddv o;
-    o.hi = __shfl_xor(v.hi, off);
-    o.lo = __shfl_xor(v.lo, off);
-    v = dd_add(v, o);
-  }
-  if (!live || s != 0) return;
+  if (e >= total) return;
   const int64_t i = e % p.m, j = e / p.m;
   if (p.tri == 1 && i > j) return;
   if (p.tri == 2 && i < j) return;
+  ddv st[7];
+  int depth = 0;
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    ddv v{p.w_hi[(int64_t)s * total + e], p.w_lo[(int64_t)s * total + e]};
+    // partial s closes a run of 2^t partials for every trailing one bit t of s + 1
+#pragma unroll
+    for (int t = s + 1; (t & 1) == 0; t >>= 1) v = dd_add(st[--depth], v);
+    st[depth++] = v;
+  }
+  const ddv v = st[0];
   ddv r = dd_mul(ddv{p.alpha_hi, p.alpha_lo}, v);
   const int64_t ci = i + j * p.ldc;
   if (!p.beta_zero) r = dd_add(r, dd_mul(ddv{p.beta_hi, p.beta_lo}, ddv{p.c_hi[ci], p.c_lo[ci]}));
@@ -607,9 +608,17 @@ hipError_t launch_grouped_list(int tile, const char* base, const ServeReq* reqs,
 }
 
 hipError_t launch_splitk_reduce(const GemmParams& p, int splitk, hipStream_t st) {
-  const int64_t threads = p.m * p.n * splitk;
-  const int64_t blocks = (threads + 255) / 256;
-  hipLaunchKernelGGL(dd_splitk_reduce, dim3((unsigned)blocks), dim3(256), 0, st, p, splitk);
+  const int64_t threads = p.m * p.n;
+  const dim3 grid((unsigned)((threads + 255) / 256)), block(256);
+  switch (splitk) {
+    case 2: hipLaunchKernelGGL(dd_splitk_reduce<2>, grid, block, 0, st, p); break;
+    case 4: hipLaunchKernelGGL(dd_splitk_reduce<4>, grid, block, 0, st, p); break;
+    case 8: hipLaunchKernelGGL(dd_splitk_reduce<8>, grid, block, 0, st, p); break;
+    case 16: hipLaunchKernelGGL(dd_splitk_reduce<16>, grid, block, 0, st, p); break;
+    case 32: hipLaunchKernelGGL(dd_splitk_reduce<32>, grid, block, 0, st, p); break;
+    case 64: hipLaunchKernelGGL(dd_splitk_reduce<64>, grid, block, 0, st, p); break;
+    default: return hipErrorInvalidValue;   // the callers split into 2 .. 64 (powers of two)
+  }
   return hipGetLastError();
 }
 
