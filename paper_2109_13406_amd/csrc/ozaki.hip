@@ -105,10 +105,13 @@ oz_scale_rows_wave(const double* __restrict__ x, int64_t sr, int64_t sl, int64_t
 // ---- slice -------------------------------------------------------------------------
 
 // One 64 x 64 block of the row operand per workgroup of 512 threads.
-// Elements are read with lanes along whichever index is contiguous in memory,
-// staged in LDS, then each thread turns 8 consecutive l of one row into
-// digits and writes them k-contiguously (8 int8 = one 8-byte store per digit,
-// or 8 doubles).  Rows >= rows and l >= k (padding) get zero digits.
+// Elements of both planes are read with lanes along whichever index is
+// contiguous in memory and staged in LDS; then each thread turns 4
+// consecutive l of two rows (8-bit digits kept in registers: one 4-byte
+// store per digit, 16 threads store a row's 64 digits of a slice together)
+// or 8 consecutive l of one row (the other forms: 8 int8 or 8 doubles per
+// digit) into digits and writes them k-contiguously.  Rows >= rows and
+// l >= k (padding) get zero digits.
 //
 // 8-bit int8 digits: a later digit of 128 does not fit, so it is carried into
 // the digit before it (it loses 2^w = 256, that digit gains one; the value
@@ -131,12 +134,13 @@ oz_scale_rows_wave(const double* __restrict__ x, int64_t sr, int64_t sl, int64_t
 constexpr int OZ_SLICE_REG_DIGITS = 16;
 
 template <typename T>
-__global__ void __launch_bounds__(512)
+__global__ void __launch_bounds__(512, 2)
 oz_slice(const double* __restrict__ xh, const double* __restrict__ xl, int64_t sr, int64_t sl,
          int64_t rows, int64_t k, const int* __restrict__ exps, int nslices, int wfirst, int w,
          T* __restrict__ q, int64_t ldq, int64_t plane) {
-  // one 33 KB staging buffer, used for the hi plane and then the lo plane
-  __shared__ double t[64][65];
+  // staging for the hi and the lo plane (66.5 KB: two workgroups fit a CU),
+  // so that both planes' loads are in flight together
+  __shared__ double t[2][64][65];
   const int tid = threadIdx.x;
   const int64_t r0 = (int64_t)blockIdx.y * 64;
   const int64_t l0 = (int64_t)blockIdx.x * 64;
@@ -145,82 +149,94 @@ oz_slice(const double* __restrict__ xh, const double* __restrict__ xl, int64_t s
   const int lb = (tid & 7) * 8;
   const int64_t r = r0 + rr;
   const int e = (r < rows) ? exps[r] : 0;
-  ddv y[8];
+  {
+    double v[2][8];
 #pragma unroll
-  for (int half = 0; half < 2; ++half) {
-    const double* __restrict__ src = half ? xl : xh;
-    double v[8];
+    for (int half = 0; half < 2; ++half) {
+      const double* __restrict__ src = half ? xl : xh;
 #pragma unroll
-    for (int c = 0; c < 8; ++c) {
-      const int a = tid & 63, b = (tid >> 6) + 8 * c;
-      const int ri = lanes_on_r ? a : b;
-      const int li = lanes_on_r ? b : a;
-      const int64_t rg = r0 + ri, lg = l0 + li;
-      v[c] = (rg < rows && lg < k) ? src[rg * sr + lg * sl] : 0.0;
+      for (int c = 0; c < 8; ++c) {
+        const int a = tid & 63, b = (tid >> 6) + 8 * c;
+        const int ri = lanes_on_r ? a : b;
+        const int li = lanes_on_r ? b : a;
+        const int64_t rg = r0 + ri, lg = l0 + li;
+        v[half][c] = (rg < rows && lg < k) ? src[rg * sr + lg * sl] : 0.0;
+      }
     }
-    if (half) __syncthreads();               // the hi values have been read
 #pragma unroll
-    for (int c = 0; c < 8; ++c) {
-      const int a = tid & 63, b = (tid >> 6) + 8 * c;
-      t[lanes_on_r ? a : b][lanes_on_r ? b : a] = v[c];
-    }
-    __syncthreads();
+    for (int half = 0; half < 2; ++half)
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      if (half)
-        y[i].lo = ldexp(t[rr][lb + i], -e);
-      else
-        y[i].hi = ldexp(t[rr][lb + i], -e);
-    }
+      for (int c = 0; c < 8; ++c) {
+        const int a = tid & 63, b = (tid >> 6) + 8 * c;
+        t[half][lanes_on_r ? a : b][lanes_on_r ? b : a] = v[half][c];
+      }
   }
+  __syncthreads();
+  // scaled element i of this thread's 8 (the staging is not written again)
+  auto scaled = [&](int i) {
+    return ddv{ldexp(t[0][rr][lb + i], -e), ldexp(t[1][rr][lb + i], -e)};
+  };
   T* out = q + r * ldq + l0 + lb;
   const bool carry = sizeof(T) == 1 && w > 7;
 
   if (carry && nslices <= OZ_SLICE_REG_DIGITS) {
-    // fw[g][t]: carried digit t of elements 4g .. 4g+3, one byte each
-    uint32_t fw[2][OZ_SLICE_REG_DIGITS];
+    // here a thread takes 4 consecutive l of two rows, rq and rq + 32, so
+    // that the 16 threads of a row store its 64 digits of a slice in one
+    // contiguous piece; fw[t]: carried digit t of the 4 elements, one byte
+    // each (one 4-byte store per digit)
+    const int rq = tid >> 4, lq = (tid & 15) * 4;
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      ddv z = y[i];
-      int raw[OZ_SLICE_REG_DIGITS];
-      uint32_t run = 0, cm = 0;                // bit t of cm: carry out of digit t
+    for (int g = 0; g < 2; ++g) {
+      const int row = rq + 32 * g;
+      const int eg = (r0 + row < rows) ? exps[r0 + row] : 0;
+      uint32_t fw[OZ_SLICE_REG_DIGITS];
 #pragma unroll
-      for (int d = 0; d < OZ_SLICE_REG_DIGITS; ++d) {
-        raw[d] = 0;
-        if (d < nslices) {
-          const int shift = (d == 0) ? wfirst : w;
-          const double zh = ldexp(z.hi, shift), zl = ldexp(z.lo, shift);
-          const double qd = rint(zh);
-          z = fast_two_sum(zh - qd, zl);
-          raw[d] = (int)qd;
-          if (d > 0) {
-            const uint32_t bit = 1u << d;
-            if (raw[d] >= 128) {
-              cm |= run | bit;
-              run = 0;
-            } else if (raw[d] == 127) {
-              run |= bit;
-            } else {
-              run = 0;
+      for (int i = 0; i < 4; ++i) {
+        ddv z{ldexp(t[0][row][lq + i], -eg), ldexp(t[1][row][lq + i], -eg)};
+        int raw[OZ_SLICE_REG_DIGITS];
+        uint32_t run = 0, cm = 0;              // bit t of cm: carry out of digit t
+#pragma unroll
+        for (int d = 0; d < OZ_SLICE_REG_DIGITS; ++d) {
+          raw[d] = 0;
+          if (d < nslices) {
+            const int shift = (d == 0) ? wfirst : w;
+            const double zh = ldexp(z.hi, shift), zl = ldexp(z.lo, shift);
+            const double qd = rint(zh);
+            z = fast_two_sum(zh - qd, zl);
+            raw[d] = (int)qd;
+            if (d > 0) {
+              const uint32_t bit = 1u << d;
+              if (raw[d] >= 128) {
+                cm |= run | bit;
+                run = 0;
+              } else if (raw[d] == 127) {
+                run |= bit;
+              } else {
+                run = 0;
+              }
             }
           }
         }
-      }
 #pragma unroll
-      for (int d = 0; d < OZ_SLICE_REG_DIGITS; ++d) {
-        const uint32_t byte = (uint32_t)(raw[d] + (int)((cm >> (d + 1)) & 1u)) & 0xFFu;
-        if ((i & 3) == 0)
-          fw[i >> 2][d] = byte;
-        else
-          fw[i >> 2][d] |= byte << (8 * (i & 3));
+        for (int d = 0; d < OZ_SLICE_REG_DIGITS; ++d) {
+          const uint32_t byte = (uint32_t)(raw[d] + (int)((cm >> (d + 1)) & 1u)) & 0xFFu;
+          if (i == 0)
+            fw[d] = byte;
+          else
+            fw[d] |= byte << (8 * i);
+        }
       }
+      T* o = q + (r0 + row) * ldq + l0 + lq;
+#pragma unroll
+      for (int d = 0; d < OZ_SLICE_REG_DIGITS; ++d)
+        if (d < nslices) *(uint32_t*)(o + (int64_t)d * plane) = fw[d];
     }
-#pragma unroll
-    for (int d = 0; d < OZ_SLICE_REG_DIGITS; ++d)
-      if (d < nslices) *(uint2*)(out + (int64_t)d * plane) = uint2{fw[0][d], fw[1][d]};
     return;
   }
 
+  ddv y[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) y[i] = scaled(i);
   // (longer 8-bit digit strings) first pass: the carries; bit d of cm[i] is
   // the carry out of digit d of element i
   uint64_t cm[8];
@@ -738,9 +754,11 @@ oz_gemm_f64(const double* __restrict__ qa, const double* __restrict__ qb, double
 // Four consecutive rows i0 .. i0+3 of one column j per thread: each
 // anti-diagonal sum is one 16-byte (int32) or 32-byte (fp64) load per thread
 // (plane rows are padded to a multiple of 256, so the four are in range and
-// aligned), four anti-diagonals are loaded before any is added.  Per entry
-// the steps are the same as one entry at a time: smallest weight first
-// (d = nslices+1 down to 2), DWPlusFP, then the scale and alpha / beta.
+// aligned); the C entries (when read) are loaded first and a batch of NB
+// anti-diagonals (8 int32, 4 fp64) is loaded before any is added, so that
+// many loads are in flight at once.  Per entry the steps are the same as one
+// entry at a time: smallest weight first (d = nslices+1 down to 2),
+// DWPlusFP, then the scale and alpha / beta.
 template <typename XT>
 __global__ void __launch_bounds__(256)
 oz_combine(const XT* __restrict__ x, int64_t mp, int64_t np, int nslices, int wfirst, int w,
@@ -748,22 +766,33 @@ oz_combine(const XT* __restrict__ x, int64_t mp, int64_t np, int nslices, int wf
            double alpha_hi, double alpha_lo, double beta_hi, double beta_lo, int beta_zero,
            double* __restrict__ c_hi, double* __restrict__ c_lo, int64_t ldc) {
   typedef XT xv4 __attribute__((ext_vector_type(4)));
+  constexpr int NB = sizeof(XT) == 4 ? 8 : 4;
   const int64_t mq = (m + 3) / 4;
   const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (gid >= mq * n) return;
   const int64_t i0 = (gid % mq) * 4, j = gid / mq;
   const XT* xp = x + j * mp + i0;
   const int64_t plane = mp * np;
+  const int nr = (m - i0 < 4) ? (int)(m - i0) : 4;   // rows of this thread inside C
+  double ch[4] = {0.0, 0.0, 0.0, 0.0}, cl[4] = {0.0, 0.0, 0.0, 0.0};
+  if (!beta_zero) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      if (r < nr) {
+        ch[r] = c_hi[i0 + r + j * ldc];
+        cl[r] = c_lo[i0 + r + j * ldc];
+      }
+  }
   ddv p[4];
 #pragma unroll
   for (int r = 0; r < 4; ++r) p[r] = ddv{0.0, 0.0};
-  for (int d0 = nslices + 1; d0 >= 2; d0 -= 4) {
-    xv4 v[4];
+  for (int d0 = nslices + 1; d0 >= 2; d0 -= NB) {
+    xv4 v[NB];
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+    for (int u = 0; u < NB; ++u)
       v[u] = d0 - u >= 2 ? *(const xv4*)(xp + (int64_t)(d0 - u - 2) * plane) : xv4{0, 0, 0, 0};
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < NB; ++u) {
       if (d0 - u < 2) continue;
       const int sh = -(2 * wfirst + w * (d0 - u - 2));
 #pragma unroll
@@ -773,13 +802,13 @@ oz_combine(const XT* __restrict__ x, int64_t mp, int64_t np, int nslices, int wf
   const ddv alpha{alpha_hi, alpha_lo}, beta{beta_hi, beta_lo};
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
+    if (r >= nr) break;
     const int64_t i = i0 + r;
-    if (i >= m) break;
     const int e = ea[i] + eb[j];
     ddv pr{ldexp(p[r].hi, e), ldexp(p[r].lo, e)};
     ddv res = dd_mul(alpha, pr);
     const int64_t ci = i + j * ldc;
-    if (!beta_zero) res = dd_add(res, dd_mul(beta, ddv{c_hi[ci], c_lo[ci]}));
+    if (!beta_zero) res = dd_add(res, dd_mul(beta, ddv{ch[r], cl[r]}));
     c_hi[ci] = res.hi;
     c_lo[ci] = res.lo;
   }
