@@ -179,59 +179,61 @@ oz_slice(const double* __restrict__ xh, const double* __restrict__ xl, int64_t s
   T* out = q + r * ldq + l0 + lb;
   const bool carry = sizeof(T) == 1 && w > 7;
 
-  if (carry && nslices <= OZ_SLICE_REG_DIGITS) {
-    // here a thread takes 4 consecutive l of two rows, rq and rq + 32, so
-    // that the 16 threads of a row store its 64 digits of a slice in one
-    // contiguous piece; fw[t]: carried digit t of the 4 elements, one byte
-    // each (one 4-byte store per digit)
-    const int rq = tid >> 4, lq = (tid & 15) * 4;
+  if constexpr (sizeof(T) == 1) {
+    if (carry && nslices <= OZ_SLICE_REG_DIGITS) {
+      // here a thread takes 4 consecutive l of two rows, rq and rq + 32, so
+      // that the 16 threads of a row store its 64 digits of a slice in one
+      // contiguous piece; fw[t]: carried digit t of the 4 elements, one byte
+      // each (one 4-byte store per digit)
+      const int rq = tid >> 4, lq = (tid & 15) * 4;
 #pragma unroll
-    for (int g = 0; g < 2; ++g) {
-      const int row = rq + 32 * g;
-      const int eg = (r0 + row < rows) ? exps[r0 + row] : 0;
-      uint32_t fw[OZ_SLICE_REG_DIGITS];
+      for (int g = 0; g < 2; ++g) {
+        const int row = rq + 32 * g;
+        const int eg = (r0 + row < rows) ? exps[r0 + row] : 0;
+        uint32_t fw[OZ_SLICE_REG_DIGITS];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        ddv z{ldexp(t[0][row][lq + i], -eg), ldexp(t[1][row][lq + i], -eg)};
-        int raw[OZ_SLICE_REG_DIGITS];
-        uint32_t run = 0, cm = 0;              // bit t of cm: carry out of digit t
+        for (int i = 0; i < 4; ++i) {
+          ddv z{ldexp(t[0][row][lq + i], -eg), ldexp(t[1][row][lq + i], -eg)};
+          int raw[OZ_SLICE_REG_DIGITS];
+          uint32_t run = 0, cm = 0;              // bit t of cm: carry out of digit t
 #pragma unroll
-        for (int d = 0; d < OZ_SLICE_REG_DIGITS; ++d) {
-          raw[d] = 0;
-          if (d < nslices) {
-            const int shift = (d == 0) ? wfirst : w;
-            const double zh = ldexp(z.hi, shift), zl = ldexp(z.lo, shift);
-            const double qd = rint(zh);
-            z = fast_two_sum(zh - qd, zl);
-            raw[d] = (int)qd;
-            if (d > 0) {
-              const uint32_t bit = 1u << d;
-              if (raw[d] >= 128) {
-                cm |= run | bit;
-                run = 0;
-              } else if (raw[d] == 127) {
-                run |= bit;
-              } else {
-                run = 0;
+          for (int d = 0; d < OZ_SLICE_REG_DIGITS; ++d) {
+            raw[d] = 0;
+            if (d < nslices) {
+              const int shift = (d == 0) ? wfirst : w;
+              const double zh = ldexp(z.hi, shift), zl = ldexp(z.lo, shift);
+              const double qd = rint(zh);
+              z = fast_two_sum(zh - qd, zl);
+              raw[d] = (int)qd;
+              if (d > 0) {
+                const uint32_t bit = 1u << d;
+                if (raw[d] >= 128) {
+                  cm |= run | bit;
+                  run = 0;
+                } else if (raw[d] == 127) {
+                  run |= bit;
+                } else {
+                  run = 0;
+                }
               }
             }
           }
-        }
 #pragma unroll
-        for (int d = 0; d < OZ_SLICE_REG_DIGITS; ++d) {
-          const uint32_t byte = (uint32_t)(raw[d] + (int)((cm >> (d + 1)) & 1u)) & 0xFFu;
-          if (i == 0)
-            fw[d] = byte;
-          else
-            fw[d] |= byte << (8 * i);
+          for (int d = 0; d < OZ_SLICE_REG_DIGITS; ++d) {
+            const uint32_t byte = (uint32_t)(raw[d] + (int)((cm >> (d + 1)) & 1u)) & 0xFFu;
+            if (i == 0)
+              fw[d] = byte;
+            else
+              fw[d] |= byte << (8 * i);
+          }
         }
+        T* o = q + (r0 + row) * ldq + l0 + lq;
+#pragma unroll
+        for (int d = 0; d < OZ_SLICE_REG_DIGITS; ++d)
+          if (d < nslices) *(uint32_t*)(o + (int64_t)d * plane) = fw[d];
       }
-      T* o = q + (r0 + row) * ldq + l0 + lq;
-#pragma unroll
-      for (int d = 0; d < OZ_SLICE_REG_DIGITS; ++d)
-        if (d < nslices) *(uint32_t*)(o + (int64_t)d * plane) = fw[d];
+      return;
     }
-    return;
   }
 
   ddv y[8];
