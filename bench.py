@@ -273,16 +273,17 @@ def cpu_baseline(case, n, cols=64):
                       f"timed product), beta=0, {dt:.2f} s wall, OpenMP threads={ncores}"}
 
 
-def oracle_sample(case, count, seed):
-    """Oracle values of sampled entries (workloads.sample_indices) of a
-    device-resident Rgemm case's update, from its current C; with the input C
-    and the componentwise denominators |op(A)| |op(B)| at those entries."""
+def oracle_sample(case, count, seed, tri=None):
+    """Oracle values of sampled entries (workloads.sample_indices; for tri
+    "U" / "L" entries of that triangle) of a device-resident Rgemm case's
+    update, from its current C; with the input C and the componentwise
+    denominators |op(A)| |op(B)| at those entries."""
     import numpy as np
     import oracle
     import torch
     import workloads as W
     m, n, k, ldc = case["m"], case["n"], case["k"], case["ldc"]
-    ii, jj = W.sample_indices(m, n, count, seed)
+    ii, jj = W.sample_indices(m, n, count, seed, tri)
     flat = ii + jj * ldc
     idx = torch.as_tensor(flat, device=case["C"][0].device)
     cin = tuple(p[idx].cpu().numpy() for p in case["C"])
@@ -409,7 +410,60 @@ def bench_syrk(h, args, stream):
                 log(f"rsyrk {rec}")
                 del case
                 torch.cuda.empty_cache()
+    out["split_i8"] = bench_syrk_split(h, args, stream, out.get("ms"))
     return out
+
+
+def bench_syrk_split(h, args, stream, plain_ms):
+    """The headline Rsyrk shape (U N, n = k = args.n, config-2 inputs) in the
+    INT8 split form: the slice count is searched upward until the sampled
+    entries of the triangle are within 8 k 2^-104 of the CPU oracle (the
+    plain dd evaluation), then that call is timed.  Slice products per
+    anti-diagonal only for the tiles that meet the triangle."""
+    import torch
+    import workloads as W
+    from paper_2109_13406_amd import binding as b
+    n = k = args.n
+    case = W.syrk_case_device(W.BASE_SEED + 2, "U", "N", n, k)
+    C0 = tuple(x.clone() for x in case["C"])
+    # the Rsyrk update is the Rgemm of op(A) and op(A)^T on the triangle
+    g = dict(m=n, n=n, k=k, ldc=case["ldc"], C=case["C"], transa="N", transb="T",
+             A=case["A"], lda=case["lda"], B=case["A"], ldb=case["lda"], alpha=case["alpha"],
+             beta=case["beta"])
+    smp = oracle_sample(g, W.CONFIG3_SAMPLE, W.BASE_SEED + 2, tri="U")
+    args_ = ("U", "N", n, k, case["alpha"], case["A"], case["lda"], case["beta"], case["C"],
+             case["ldc"])
+    found = None
+    for sl in range(10, 25):
+        for dst, src in zip(case["C"], C0):
+            dst.copy_(src)
+        if b.mpdd_Rsyrk_ex(h, dict(algo=b.MPDD_OZAKI_I8, nslices=sl), *args_,
+                           stream=stream) != 0:
+            break
+        r, c = oracle_compare(smp, case["C"])
+        if r <= RATIO_MAX:
+            found = (sl, r, c)
+            break
+    if found is None:
+        return {"nslices": None}
+    sl, r, c = found
+
+    def step():
+        if b.mpdd_Rsyrk_ex(h, dict(algo=b.MPDD_OZAKI_I8, nslices=sl), *args_, stream=stream):
+            raise RuntimeError("split-form Rsyrk failed")
+    _, per = timed_calls(step, 3, 1, stream)
+    t = sum(per) / len(per)
+    rec = {"workload": f"Rsyrk U N n={n} k={k} ld={W.ld_padded(n)}, INT8 split form",
+           "nslices": sl, "ratio_vs_oracle": round(r, 4), "componentwise_vs_oracle": round(c, 2),
+           "oracle_sample": len(smp["flat"]), "ms": round(t * 1e3, 2),
+           "dd_gflops": round(float(n) * (n + 1) * k / t / 1e9, 1)}
+    if plain_ms:
+        rec["plain_ms"] = plain_ms
+        rec["speedup_vs_plain"] = round(plain_ms / (t * 1e3), 3)
+    log(f"rsyrk split {rec}")
+    del case, C0
+    torch.cuda.empty_cache()
+    return rec
 
 
 def bench_cgemm(h, args, stream):

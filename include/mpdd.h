@@ -191,7 +191,14 @@ int mpdd_Rgemm_noalloc(mpdd_handle h, const mpdd_opts *opts, const char *transa,
                        const double *B_hi, const double *B_lo, mpdd_int ldb, mpdd_dd beta,
                        double *C_hi, double *C_lo, mpdd_int ldc, void *stream);
 
-/* As mpdd_Rsyrk with explicit options (plain forms only). */
+/* As mpdd_Rsyrk with explicit options.  The split forms (MPDD_OZAKI_I8 /
+ * MPDD_OZAKI_F64, see the split-form building blocks below) slice op(A) once
+ * and use its slices and row exponents for op(B) = op(A)^T as well, compute
+ * only the slice products of the tiles that meet the uplo triangle, and
+ * read and write only that triangle of C; their result is that of the
+ * split-form mpdd_Rgemm_ex of op(A) and op(A)^T, on the triangle.  INT8
+ * product tiling tile_id 1 (256 x 128 tiles) returns MPDD_ERR_UNSUPPORTED
+ * here (a triangle is walked in square tiles). */
 int mpdd_Rsyrk_ex(mpdd_handle h, const mpdd_opts *opts, const char *uplo, const char *trans,
                   mpdd_int n, mpdd_int k, mpdd_dd alpha, const double *A_hi,
                   const double *A_lo, mpdd_int lda, mpdd_dd beta, double *C_hi,

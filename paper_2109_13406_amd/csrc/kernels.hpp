@@ -115,8 +115,10 @@ hipError_t launch_join_pairs(const double* hi, const double* lo, double* pairs, 
 
 namespace mpdd {
 
-// Split-form (Ozaki) Rgemm (ozaki.hip).  Returns 0 or an MPDD_ERR_* code.
-int ozaki_gemm(const void* opts, bool ta, bool tb, int64_t m, int64_t n, int64_t k,
+// Split-form (Ozaki) Rgemm (ozaki.hip), or with tri = 1 / 2 the upper / lower
+// triangle of an Rsyrk (m == n, B == A, tb == !ta).  Returns 0 or an
+// MPDD_ERR_* code.
+int ozaki_gemm(const void* opts, int tri, bool ta, bool tb, int64_t m, int64_t n, int64_t k,
                double alpha_hi, double alpha_lo, const double* a_hi, const double* a_lo,
                int64_t lda, const double* b_hi, const double* b_lo, int64_t ldb,
                double beta_hi, double beta_lo, double* c_hi, double* c_lo, int64_t ldc,

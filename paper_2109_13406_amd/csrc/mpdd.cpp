@@ -369,7 +369,7 @@ int mpdd_Rgemm_ex(mpdd_handle h, const mpdd_opts* opts, const char* transa, cons
   const bool ta = !lsame(transa, 'N'), tb = !lsame(transb, 'N');
   hipStream_t st = (hipStream_t)stream;
   if (algo == MPDD_OZAKI_I8 || algo == MPDD_OZAKI_F64)
-    return ozaki_gemm(opts, ta, tb, m, n, k, alpha.hi, alpha.lo, A_hi, A_lo, lda, B_hi, B_lo,
+    return ozaki_gemm(opts, 0, ta, tb, m, n, k, alpha.hi, alpha.lo, A_hi, A_lo, lda, B_hi, B_lo,
                       ldb, beta.hi, beta.lo, C_hi, C_lo, ldc, st, h->pool);
   return run_plain(h, opts, ta, tb, 0, m, n, k, alpha, A_hi, A_lo, lda, B_hi, B_lo, ldb, beta,
                    C_hi, C_lo, ldc, st);
@@ -412,7 +412,9 @@ int mpdd_Rsyrk_ex(mpdd_handle h, const mpdd_opts* opts, const char* uplo, const 
   if (info) return info;
   if (!handle_ok(h)) return MPDD_ERR_HANDLE;
   const int algo = opts ? opts->algo : MPDD_PLAIN;
-  if (algo != MPDD_PLAIN && algo != MPDD_PLAIN_ACCURATE) return MPDD_ERR_ARG;
+  if (algo != MPDD_PLAIN && algo != MPDD_PLAIN_ACCURATE && algo != MPDD_OZAKI_I8 &&
+      algo != MPDD_OZAKI_F64)
+    return MPDD_ERR_ARG;
   if (n == 0 || ((is_zero(alpha) || k == 0) && is_one(beta))) return 0;
   if (!C_hi || !C_lo) return MPDD_ERR_ARG;
   if (!is_zero(alpha) && k > 0 && (!A_hi || !A_lo)) return MPDD_ERR_ARG;
@@ -420,6 +422,9 @@ int mpdd_Rsyrk_ex(mpdd_handle h, const mpdd_opts* opts, const char* uplo, const 
   const bool ta = !lsame(trans, 'N');
   const bool tb = !ta;
   const int tri = lsame(uplo, 'U') ? 1 : 2;
+  if (algo == MPDD_OZAKI_I8 || algo == MPDD_OZAKI_F64)
+    return ozaki_gemm(opts, tri, ta, tb, n, n, k, alpha.hi, alpha.lo, A_hi, A_lo, lda, A_hi,
+                      A_lo, lda, beta.hi, beta.lo, C_hi, C_lo, ldc, (hipStream_t)stream, h->pool);
   return run_plain(h, opts, ta, tb, tri, n, n, k, alpha, A_hi, A_lo, lda, A_hi, A_lo, lda, beta,
                    C_hi, C_lo, ldc, (hipStream_t)stream);
 }

@@ -295,20 +295,62 @@ oz_slice(const double* __restrict__ xh, const double* __restrict__ xl, int64_t s
   }
 }
 
-// Workgroup b -> (anti-diagonal d, C tile (bi, bj)).  Groups of tiles_m *
-// tiles_n workgroups share one d, largest d (longest sum) first.  Inside a
-// group, each of the 8 XCDs (workgroups are dealt to them round-robin)
-// receives a contiguous run of the tile sequence, and that sequence walks the
-// C grid in 8 x 8 super-tiles (bi fastest inside one): the workgroups an XCD
-// runs at the same time then cover a compact block of C and read a few row
-// panels of op(A) and column panels of op(B), which its L2 holds, instead of
-// every row panel of op(A) against one column panel.
-__device__ __forceinline__ void oz_tile_of(int b, int tiles_m, int tiles_n, int nslices, int& d,
-                                           int& bi, int& bj) {
-  const int tiles = tiles_m * tiles_n;
+// Largest y with y (y + 1) / 2 <= t.
+__device__ __forceinline__ int oz_tri_root(int t) {
+  int y = (int)((__builtin_sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+  while ((y + 1) * (y + 2) / 2 <= t) ++y;
+  while (y * (y + 1) / 2 > t) --y;
+  return y;
+}
+
+// Tiles of one anti-diagonal group: the whole tiles_m x tiles_n grid, or for
+// a triangle (tri 1: upper, tile row <= tile column; 2: lower; square
+// tiles, tiles_m == tiles_n) only the tiles_m (tiles_m + 1) / 2 tiles that
+// meet it.
+__host__ __device__ __forceinline__ int oz_group_tiles(int tri, int tiles_m, int tiles_n) {
+  return tri ? tiles_m * (tiles_m + 1) / 2 : tiles_m * tiles_n;
+}
+
+// Workgroup b -> (anti-diagonal d, C tile (bi, bj)).  Groups of
+// oz_group_tiles workgroups share one d, largest d (longest sum) first.
+// Inside a group, each of the 8 XCDs (workgroups are dealt to them
+// round-robin) receives a contiguous run of the tile sequence, and that
+// sequence walks the C grid in 8 x 8 super-tiles (bi fastest inside one):
+// the workgroups an XCD runs at the same time then cover a compact block of
+// C and read a few row panels of op(A) and column panels of op(B), which its
+// L2 holds, instead of every row panel of op(A) against one column panel.
+// A triangle with tiles_m a multiple of 8 is walked in the same 8 x 8
+// blocks: first the blocks off the diagonal (64 tiles each, blocks column by
+// column), then the diagonal blocks (their 36 tiles each), so that every
+// XCD's run holds an equal number of tiles; other triangles column by column.
+__device__ __forceinline__ void oz_tile_of(int b, int tri, int tiles_m, int tiles_n, int nslices,
+                                           int& d, int& bi, int& bj) {
+  const int tiles = oz_group_tiles(tri, tiles_m, tiles_n);
   d = nslices + 1 - b / tiles;
   int r = b % tiles;
   if ((tiles & 7) == 0) r = (r & 7) * (tiles >> 3) + (r >> 3);
+  if (tri) {
+    int x, y;                                  // tile (x, y) with x <= y
+    if ((tiles_m & 7) == 0) {
+      const int s8 = tiles_m >> 3, off = 64 * (s8 * (s8 - 1) / 2);
+      if (r < off) {
+        const int by = oz_tri_root(r >> 6) + 1, bx = (r >> 6) - by * (by - 1) / 2;
+        x = bx * 8 + (r & 7);
+        y = by * 8 + ((r >> 3) & 7);
+      } else {
+        const int db = (r - off) / 36, w = (r - off) % 36;
+        const int yy = oz_tri_root(w);
+        x = db * 8 + (w - yy * (yy + 1) / 2);
+        y = db * 8 + yy;
+      }
+    } else {
+      y = oz_tri_root(r);
+      x = r - y * (y + 1) / 2;
+    }
+    bi = (tri == 1) ? x : y;
+    bj = (tri == 1) ? y : x;
+    return;
+  }
   if ((tiles_m & 7) == 0 && (tiles_n & 7) == 0) {
     const int st = r >> 6, w = r & 63, stm = tiles_m >> 3;
     bi = (st % stm) * 8 + (w & 7);
@@ -357,7 +399,7 @@ template <int WM, int WN, int GM, int GN>
 __global__ void __launch_bounds__(64 * GM * GN, (WM * WN / (GM * GN) > 128 * 64) ? 1 : (GM * GN > 8 ? 4 : 2))
 oz_gemm_i8(const int8_t* __restrict__ qa, const int8_t* __restrict__ qb, int32_t* __restrict__ x,
            int64_t kp, int64_t plane_a, int64_t plane_b, int64_t mp, int64_t np, int nslices,
-           int tiles_m, int tiles_n) {
+           int tiles_m, int tiles_n, int tri) {
   constexpr int NT = 64 * GM * GN;             // threads: a GM x GN grid of waves
   constexpr int WR = WM / GM, WC = WN / GN;    // outputs per wave
   constexpr int FA = WR / 16, FB = WC / 16;    // 16-row fragments per wave
@@ -372,7 +414,7 @@ oz_gemm_i8(const int8_t* __restrict__ qa, const int8_t* __restrict__ qb, int32_t
   const int wm = wave % GM, wn = wave / GM;
 
   int d, bi, bj;
-  oz_tile_of(blockIdx.x, tiles_m, tiles_n, nslices, d, bi, bj);
+  oz_tile_of(blockIdx.x, tri, tiles_m, tiles_n, nslices, d, bi, bj);
   const int64_t i0 = (int64_t)bi * WM, j0 = (int64_t)bj * WN;
 
   v4i acc[FA][FB];
@@ -481,7 +523,7 @@ template <int WM, int WN, int GM, int GN, int NS, bool PF, bool M32>
 __global__ void __launch_bounds__(64 * GM * GN, 1)
 oz_gemm_i8_dma(const int8_t* __restrict__ qa, const int8_t* __restrict__ qb,
                int32_t* __restrict__ x, int64_t kp, int64_t plane_a, int64_t plane_b, int64_t mp,
-               int64_t np, int nslices, int tiles_m, int tiles_n) {
+               int64_t np, int nslices, int tiles_m, int tiles_n, int tri) {
   constexpr int NW = GM * GN;                  // waves
   constexpr int WR = WM / GM, WC = WN / GN;    // outputs per wave
   constexpr int MT = M32 ? 32 : 16;            // MFMA tile edge
@@ -498,7 +540,7 @@ oz_gemm_i8_dma(const int8_t* __restrict__ qa, const int8_t* __restrict__ qb,
   const int wm = wave % GM, wn = wave / GM;
 
   int d, bi, bj;
-  oz_tile_of(blockIdx.x, tiles_m, tiles_n, nslices, d, bi, bj);
+  oz_tile_of(blockIdx.x, tri, tiles_m, tiles_n, nslices, d, bi, bj);
   const int64_t i0 = (int64_t)bi * WM, j0 = (int64_t)bj * WN;
 
   typedef int v16i __attribute__((ext_vector_type(16)));
@@ -672,7 +714,7 @@ constexpr int F64_PITCH = 17;
 __global__ void __launch_bounds__(256)
 oz_gemm_f64(const double* __restrict__ qa, const double* __restrict__ qb, double* __restrict__ x,
             int64_t kp, int64_t plane_a, int64_t plane_b, int64_t mp, int64_t np, int nslices,
-            int tiles_m, int tiles_n) {
+            int tiles_m, int tiles_n, int tri) {
   __shared__ double As[2][OZ_BM * F64_PITCH];
   __shared__ double Bs[2][OZ_BN * F64_PITCH];
   const int tid = threadIdx.x;
@@ -681,7 +723,7 @@ oz_gemm_f64(const double* __restrict__ qa, const double* __restrict__ qb, double
   const int wm = wave & 1, wn = wave >> 1;
 
   int d, bi, bj;
-  oz_tile_of(blockIdx.x, tiles_m, tiles_n, nslices, d, bi, bj);
+  oz_tile_of(blockIdx.x, tri, tiles_m, tiles_n, nslices, d, bi, bj);
   const int64_t i0 = (int64_t)bi * OZ_BM, j0 = (int64_t)bj * OZ_BN;
 
   v4d acc[4][4];
@@ -753,7 +795,8 @@ oz_gemm_f64(const double* __restrict__ qa, const double* __restrict__ qb, double
 
 // ---- combine -------------------------------------------------------------------------
 
-// Four consecutive rows i0 .. i0+3 of one column j per thread: each
+// Four consecutive rows i0 .. i0+3 of one column j per thread (for a
+// triangle, only its entries are read and written): each
 // anti-diagonal sum is one 16-byte (int32) or 32-byte (fp64) load per thread
 // (plane rows are padded to a multiple of 256, so the four are in range and
 // aligned); the C entries (when read) are loaded first and a batch of NB
@@ -766,21 +809,26 @@ __global__ void __launch_bounds__(256)
 oz_combine(const XT* __restrict__ x, int64_t mp, int64_t np, int nslices, int wfirst, int w,
            const int* __restrict__ ea, const int* __restrict__ eb, int64_t m, int64_t n,
            double alpha_hi, double alpha_lo, double beta_hi, double beta_lo, int beta_zero,
-           double* __restrict__ c_hi, double* __restrict__ c_lo, int64_t ldc) {
+           double* __restrict__ c_hi, double* __restrict__ c_lo, int64_t ldc, int tri) {
   typedef XT xv4 __attribute__((ext_vector_type(4)));
   constexpr int NB = sizeof(XT) == 4 ? 8 : 4;
   const int64_t mq = (m + 3) / 4;
   const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (gid >= mq * n) return;
   const int64_t i0 = (gid % mq) * 4, j = gid / mq;
+  // rows of column j that are updated: all, or the triangle's (tri 1:
+  // upper, i <= j; 2: lower, i >= j); a thread with none of them returns
+  // before reading anything (its tile may not have been computed)
+  const int64_t ilo = (tri == 2) ? j : 0, ihi = (tri == 1) ? j : m - 1;
+  if (i0 > ihi || i0 + 3 < ilo) return;
+  auto updated = [&](int64_t i) { return i < m && i >= ilo && i <= ihi; };
   const XT* xp = x + j * mp + i0;
   const int64_t plane = mp * np;
-  const int nr = (m - i0 < 4) ? (int)(m - i0) : 4;   // rows of this thread inside C
   double ch[4] = {0.0, 0.0, 0.0, 0.0}, cl[4] = {0.0, 0.0, 0.0, 0.0};
   if (!beta_zero) {
 #pragma unroll
     for (int r = 0; r < 4; ++r)
-      if (r < nr) {
+      if (updated(i0 + r)) {
         ch[r] = c_hi[i0 + r + j * ldc];
         cl[r] = c_lo[i0 + r + j * ldc];
       }
@@ -804,8 +852,8 @@ oz_combine(const XT* __restrict__ x, int64_t mp, int64_t np, int nslices, int wf
   const ddv alpha{alpha_hi, alpha_lo}, beta{beta_hi, beta_lo};
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
-    if (r >= nr) break;
     const int64_t i = i0 + r;
+    if (!updated(i)) continue;
     const int e = ea[i] + eb[j];
     ddv pr{ldexp(p[r].hi, e), ldexp(p[r].lo, e)};
     ddv res = dd_mul(alpha, pr);
@@ -868,7 +916,7 @@ static size_t part_bytes(int64_t rows, int64_t k) {
   return (size_t)((rows * std::max<int64_t>(nchunks, 1) * 8 + 255) / 256 * 256);
 }
 
-int ozaki_gemm(const void* opts_v, bool ta, bool tb, int64_t m, int64_t n, int64_t k,
+int ozaki_gemm(const void* opts_v, int tri, bool ta, bool tb, int64_t m, int64_t n, int64_t k,
                double alpha_hi, double alpha_lo, const double* a_hi, const double* a_lo,
                int64_t lda, const double* b_hi, const double* b_lo, int64_t ldb, double beta_hi,
                double beta_lo, double* c_hi, double* c_lo, int64_t ldc, hipStream_t st,
@@ -882,6 +930,7 @@ int ozaki_gemm(const void* opts_v, bool ta, bool tb, int64_t m, int64_t n, int64
     p.beta_hi = beta_hi; p.beta_lo = beta_lo;
     p.c_hi = c_hi; p.c_lo = c_lo; p.ldc = ldc;
     p.beta_zero = beta_zero;
+    p.tri = tri;
     return launch_scale(p, st) == hipSuccess ? 0 : MPDD_ERR_HIP;
   }
   int s = opts->nslices;
@@ -900,13 +949,17 @@ int ozaki_gemm(const void* opts_v, bool ta, bool tb, int64_t m, int64_t n, int64
   // previous step's MFMAs; fastest measured at n = 4096 and 8192)
   const int var = (i8 && opts->tile_id >= 0) ? opts->tile_id : 6;
   if (i8 && var > 8) return MPDD_ERR_UNSUPPORTED;
+  // a triangle is walked in square tiles (variant 1's are 256 x 128)
+  if (tri && i8 && var == 1) return MPDD_ERR_UNSUPPORTED;
   const int64_t tbm = i8 ? (var == 2 ? 128 : 256) : OZ_BM;
   const int64_t tbn = i8 ? ((var == 0 || var >= 3) ? 256 : 128) : OZ_BN;
   const int64_t mp = round_up(m, i8 ? I8_PAD : OZ_BM), np = round_up(n, i8 ? I8_PAD : OZ_BN);
   const size_t esz = i8 ? 1 : 8;
   const size_t xsz = i8 ? 4 : 8;
+  // a triangle (Rsyrk: op(B) = op(A)^T, m == n) uses op(A)'s slices and
+  // exponents for op(B) as well: the columns of op(B) are the rows of op(A)
   const size_t qa_bytes = (size_t)s * mp * kp * esz;
-  const size_t qb_bytes = (size_t)s * np * kp * esz;
+  const size_t qb_bytes = tri ? 0 : (size_t)s * np * kp * esz;
   const size_t x_bytes = (size_t)s * mp * np * xsz;
   const size_t e_bytes = round_up((m + n) * sizeof(int), 256);
   const size_t p_bytes = std::max(part_bytes(m, k), part_bytes(n, k));
@@ -916,10 +969,10 @@ int ozaki_gemm(const void* opts_v, bool ta, bool tb, int64_t m, int64_t n, int64
   if (hipMallocFromPoolAsync(&ws, total, pool, st) != hipSuccess) return MPDD_ERR_ALLOC;
   char* base = (char*)ws;
   void* qa = base;
-  void* qb = base + round_up(qa_bytes, 256);
+  void* qb = tri ? qa : base + round_up(qa_bytes, 256);
   void* x = base + round_up(qa_bytes, 256) + round_up(qb_bytes, 256);
   int* ea = (int*)((char*)x + x_bytes);
-  int* eb = ea + m;
+  int* eb = tri ? ea : ea + m;
   double* part = (double*)((char*)ea + e_bytes);
 
   // row operand of A: op(A)(i, l); of B: op(B)(l, j) as element (j, l)
@@ -929,18 +982,18 @@ int ozaki_gemm(const void* opts_v, bool ta, bool tb, int64_t m, int64_t n, int64
   if (i8) {
     e = split_operand<int8_t>(a_hi, a_lo, a_sr, a_sl, m, k, ea, (int8_t*)qa, kp, mp, s, wfirst, w,
                               part, st);
-    if (e == hipSuccess)
+    if (e == hipSuccess && !tri)
       e = split_operand<int8_t>(b_hi, b_lo, b_sr, b_sl, n, k, eb, (int8_t*)qb, kp, np, s, wfirst,
                                 w, part, st);
   } else {
     e = split_operand<double>(a_hi, a_lo, a_sr, a_sl, m, k, ea, (double*)qa, kp, mp, s, wfirst, w,
                               part, st);
-    if (e == hipSuccess)
+    if (e == hipSuccess && !tri)
       e = split_operand<double>(b_hi, b_lo, b_sr, b_sl, n, k, eb, (double*)qb, kp, np, s, wfirst,
                                 w, part, st);
   }
   const int tiles_m = (int)(mp / tbm), tiles_n = (int)(np / tbn);
-  const unsigned nblocks = (unsigned)(tiles_m * tiles_n * s);
+  const unsigned nblocks = (unsigned)(oz_group_tiles(tri, tiles_m, tiles_n) * s);
   if (e == hipSuccess) {
     if (i8) {
       auto kern = (var == 0)   ? oz_gemm_i8<256, 256, 2, 2>
@@ -955,12 +1008,12 @@ int ozaki_gemm(const void* opts_v, bool ta, bool tb, int64_t m, int64_t n, int64
       const unsigned nthreads = (var == 4) ? 1024 : (var >= 3 && var != 7) ? 512 : 256;
       hipLaunchKernelGGL(kern, dim3(nblocks), dim3(nthreads), 0, st, (const int8_t*)qa,
                          (const int8_t*)qb, (int32_t*)x, kp, mp * kp, np * kp, mp, np, s, tiles_m,
-                         tiles_n);
+                         tiles_n, tri);
     }
     else
       hipLaunchKernelGGL(oz_gemm_f64, dim3(nblocks), dim3(256), 0, st, (const double*)qa,
                          (const double*)qb, (double*)x, kp, mp * kp, np * kp, mp, np, s, tiles_m,
-                         tiles_n);
+                         tiles_n, tri);
     e = hipGetLastError();
   }
   if (e == hipSuccess) {
@@ -968,11 +1021,11 @@ int ozaki_gemm(const void* opts_v, bool ta, bool tb, int64_t m, int64_t n, int64
     if (i8)
       hipLaunchKernelGGL(oz_combine<int32_t>, dim3(cb), dim3(256), 0, st, (const int32_t*)x, mp,
                          np, s, wfirst, w, ea, eb, m, n, alpha_hi, alpha_lo, beta_hi, beta_lo,
-                         (int)beta_zero, c_hi, c_lo, ldc);
+                         (int)beta_zero, c_hi, c_lo, ldc, tri);
     else
       hipLaunchKernelGGL(oz_combine<double>, dim3(cb), dim3(256), 0, st, (const double*)x, mp, np,
                          s, wfirst, w, ea, eb, m, n, alpha_hi, alpha_lo, beta_hi, beta_lo,
-                         (int)beta_zero, c_hi, c_lo, ldc);
+                         (int)beta_zero, c_hi, c_lo, ldc, tri);
     e = hipGetLastError();
   }
   hipError_t ef = hipFreeAsync(ws, st);

@@ -14,7 +14,8 @@ import pytest
 
 import oracle
 import workloads as W
-from gpu_util import compare_full, dev, gemm_gpu, gemm_oracle, log, sampled_gemm_check
+from gpu_util import (compare_full, dev, entries_mask, gemm_gpu, gemm_oracle, log,
+                      sampled_gemm_check, sampled_syrk_check, syrk_gpu, syrk_oracle)
 from oracle.compare import RATIO_MAX, bits
 
 pytestmark = pytest.mark.gpu
@@ -172,6 +173,109 @@ def test_split_semantics(h):
     info, _ = gemm_gpu(h, W.gemm_case(74, "N", "N", 8, 8, 8),
                        opts=dict(algo=b.MPDD_OZAKI_I8, nslices=12, tile_id=9))
     assert info == b.MPDD_ERR_UNSUPPORTED
+
+
+SYRK_SHAPES = [(1, 1), (70, 33), (130, 200), (300, 130)]
+SYRK_VARIANTS = (0, 2, 3, 4, 5, 6, 7, 8)   # INT8 tilings with square tiles
+
+
+def _split_syrk_reference(case, kind, s):
+    """The split oracle's Rgemm of op(A) and op(A)^T (the whole square; only
+    the case's triangle is compared)."""
+    n, k, trans = case["n"], case["k"], case["trans"].upper()
+    wf, w, qmax = _widths(kind, k, s)
+    O = (case["C"][0].copy(), case["C"][1].copy())
+    assert oracle.ozaki_rgemm(trans, "T" if trans == "N" else "N", n, n, k, case["alpha"],
+                              case["A"], case["lda"], case["A"], case["lda"], case["beta"], O,
+                              case["ldc"], s, wf, w, qmax) == 0
+    return O
+
+
+def _check_split_syrk(G, O, case, what):
+    """Triangle bit-identical to O; every other stored word (the opposite
+    triangle's NaN sentinel, the padding rows) bit-identical to the input."""
+    idx = entries_mask(case["n"], case["n"], case["ldc"], case["uplo"].upper())
+    rest = np.ones(G[0].shape[0], bool)
+    rest[idx] = False
+    for p in (0, 1):
+        assert np.array_equal(bits(G[p])[idx], bits(O[p])[idx]), what
+        assert np.array_equal(bits(G[p])[rest], bits(case["C"][p])[rest]), what
+
+
+@pytest.mark.parametrize("kind", ["i8", "f64"])
+@pytest.mark.parametrize("uplo", ["U", "L"])
+@pytest.mark.parametrize("trans", ["N", "T"])
+def test_split_syrk_bit_identical_to_split_oracle(h, kind, uplo, trans):
+    """Split-form Rsyrk: op(B) = op(A)^T takes op(A)'s slices, only the
+    triangle's tiles are multiplied and only the triangle is combined; the
+    triangle equals the split oracle's Rgemm of op(A) and op(A)^T bit for bit
+    for every square INT8 tiling, and nothing else of C changes."""
+    algo = KINDS[kind]
+    s = 9 if kind == "i8" else 4
+    for (n, k) in SYRK_SHAPES:
+        for dist in ("uniform", "wide"):
+            case = W.syrk_case(80 + n + k, uplo, trans, n, k, dist=dist)
+            O = _split_syrk_reference(case, kind, s)
+            for var in (SYRK_VARIANTS if kind == "i8" else (-1,)):
+                info, G = syrk_gpu(h, case, opts=dict(algo=algo, nslices=s, tile_id=var))
+                assert info == 0
+                _check_split_syrk(G, O, case, (kind, uplo, trans, n, k, dist, var))
+    log(f"PARITY ozaki syrk {kind} {uplo}{trans} bit-identical to the split oracle")
+
+
+@pytest.mark.parametrize("kind,n", [("i8", 2048), ("f64", 1024)])
+@pytest.mark.parametrize("uplo", ["U", "L"])
+def test_split_syrk_blocked_triangle_walk(h, kind, n, uplo):
+    """With a multiple of 8 tiles per side the triangle's tiles are walked in
+    8 x 8 blocks (off-diagonal blocks, then diagonal ones) dealt to the XCDs
+    in equal runs: every tile of the triangle is computed once, bit for bit
+    as the split oracle; beta = 0 never reads C (all NaN)."""
+    algo = KINDS[kind]
+    s, k = 6, 64
+    for trans, beta_zero in (("N", False), ("T", True)):
+        case = W.syrk_case(90 + n, uplo, trans, n, k, beta_zero=beta_zero)
+        O = _split_syrk_reference(case, kind, s)
+        info, G = syrk_gpu(h, case, opts=dict(algo=algo, nslices=s))
+        assert info == 0
+        _check_split_syrk(G, O, case, (kind, n, uplo, trans, beta_zero))
+    log(f"PARITY ozaki syrk {kind} n={n} {uplo} blocked triangle walk bit-identical")
+
+
+def test_split_syrk_semantics(h):
+    """alpha = 0 scales the triangle only (bit-identical to the oracle's
+    Rsyrk); the 256 x 128 INT8 tiling is rejected for a triangle, nothing
+    enqueued."""
+    from paper_2109_13406_amd import binding as b
+    case = W.syrk_case(91, "U", "T", 60, 40)
+    case["alpha"] = (0.0, 0.0)
+    O = syrk_oracle(case)
+    for algo in (b.MPDD_OZAKI_I8, b.MPDD_OZAKI_F64):
+        info, G = syrk_gpu(h, case, opts=dict(algo=algo, nslices=8))
+        assert info == 0
+        for p in (0, 1):
+            assert np.array_equal(bits(G[p]), bits(O[p]))
+    case = W.syrk_case(92, "L", "N", 60, 40)
+    info, G = syrk_gpu(h, case, opts=dict(algo=b.MPDD_OZAKI_I8, nslices=8, tile_id=1))
+    assert info == b.MPDD_ERR_UNSUPPORTED
+    for p in (0, 1):
+        assert np.array_equal(bits(G[p]), bits(case["C"][p]))
+
+
+@pytest.mark.parametrize("uplo,trans", [("U", "N"), ("L", "N"), ("U", "T"), ("L", "T")])
+def test_split_syrk_config2_size(h, uplo, trans):
+    """Config-2 shape n = k = 8192 in the INT8 split form with the slice count
+    the benchmark times (12): within 8 k 2^-104 of the plain dd oracle on
+    sampled entries of the triangle."""
+    import torch
+    from paper_2109_13406_amd import binding as b
+    n = k = 8192
+    case = W.syrk_case_device(W.BASE_SEED + 2, uplo, trans, n, k)
+    r = sampled_syrk_check(h, f"config2 ozaki syrk i8 {uplo}{trans} n={n} k={k} s=12", case,
+                           opts=dict(algo=b.MPDD_OZAKI_I8, nslices=12), count=W.CONFIG3_SAMPLE,
+                           seed=W.BASE_SEED + 2)
+    del case
+    torch.cuda.empty_cache()
+    assert r <= RATIO_MAX
 
 
 def _digit_value(digits, wf, w):
