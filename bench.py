@@ -494,9 +494,39 @@ def bench_cgemm(h, args, stream):
     return out
 
 
+def potrf_residual_sample(A0, F, n, ld, count, seed):
+    """Worst sampled backward error of a lower Cholesky factor: for entries
+    (i, j), i >= j, |(L L^T - A)(i, j)| / (n 2^-104 sqrt(A(i,i) A(j,j))), with
+    L L^T formed in dd by the CPU oracle's Rgemm from the device factor's
+    rows (LAPACK's test ratios are compared with 30)."""
+    import numpy as np
+    import oracle
+    from oracle.compare import EPS_DD
+    rng = np.random.default_rng(seed)
+    ii = rng.integers(0, n, count)
+    jj = (rng.random(count) * (ii + 1)).astype(np.int64)
+    ii = np.concatenate([ii, [n - 1, n - 1, n - 1]])
+    jj = np.concatenate([jj, [0, n - 2, n - 1]])
+    Lv = [p[: n * ld].view(n, ld) for p in F]        # Lv[l, i] = L(i, l)
+    Av = [p[: n * ld].view(n, ld) for p in A0]
+    worst = 0.0
+    for i, j in zip(ii.tolist(), jj.tolist()):
+        kk = j + 1
+        Li = [np.ascontiguousarray(x[:kk, i].cpu().numpy()) for x in Lv]
+        Lj = [np.ascontiguousarray(x[:kk, j].cpu().numpy()) for x in Lv]
+        C = (np.array([float(Av[0][j, i])]), np.array([float(Av[1][j, i])]))
+        assert oracle.rgemm("N", "T", 1, 1, kk, (1.0, 0.0), Li, 1, Lj, 1, (-1.0, 0.0), C, 1) == 0
+        den = n * EPS_DD * np.sqrt(float(Av[0][i, i]) * float(Av[0][j, j]))
+        worst = max(worst, abs(C[0][0] + C[1][0]) / den)
+    return worst
+
+
 def bench_potrf(h, args, stream):
-    """Blocked dd Cholesky Rpotrf L at n (synchronous call: it reads each
-    diagonal block's info back).  dd-flops n^3/3 (LAWN 41, leading term)."""
+    """Blocked dd Cholesky Rpotrf L at n (synchronous call), in the plain
+    form (left-looking, look-ahead) and with split-form (INT8, 12 slices)
+    trailing updates over 1024-column panels; each factor's sampled backward
+    error (potrf_residual_sample) is reported.  dd-flops n^3/3 (LAWN 41,
+    leading term)."""
     import torch
     import workloads as W
     from paper_2109_13406_amd import binding as b
@@ -504,24 +534,40 @@ def bench_potrf(h, args, stream):
     case = W.spd_case_device(W.BASE_SEED + 7, n, "L")
     A0 = tuple(x.clone() for x in case["A"])
     torch.cuda.synchronize()
-    times = []
-    for rep in range(1 + max(1, args.steps // 2)):
-        for dst, src in zip(case["A"], A0):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        rc, info = b.mpdd_Rpotrf(h, "L", n, case["A"], case["lda"], stream=stream)
-        torch.cuda.synchronize()
-        if rc != 0 or info != 0:
-            raise RuntimeError(f"mpdd_Rpotrf rc={rc} info={info}")
-        if rep > 0:                      # the first call is warm-up
-            times.append(time.perf_counter() - t0)
-    t = sum(times) / len(times)
+
+    def run(opts):
+        times = []
+        for rep in range(1 + max(1, args.steps // 2)):
+            for dst, src in zip(case["A"], A0):
+                dst.copy_(src)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rc, info = b.mpdd_Rpotrf(h, "L", n, case["A"], case["lda"], stream=stream, opts=opts)
+            torch.cuda.synchronize()
+            if rc != 0 or info != 0:
+                raise RuntimeError(f"mpdd_Rpotrf rc={rc} info={info}")
+            if rep > 0:                      # the first call is warm-up
+                times.append(time.perf_counter() - t0)
+        t = sum(times) / len(times)
+        res = potrf_residual_sample(A0, case["A"], n, case["lda"], 48, W.BASE_SEED + 7)
+        return t, res
+
+    t, res = run(None)
+    out = {"workload": f"Rpotrf L n={n} ld={W.ld_padded(n)} (SPD: dd U[-1,1) off-diagonal, "
+                       f"n + U[0,1) diagonal)", "ms": round(t * 1e3, 3),
+           "dd_gflops": round(float(n) ** 3 / 3.0 / t / 1e9, 1),
+           "residual_sampled_worst": round(res, 5), "residual_bound": 30.0,
+           "residual_unit": "n 2^-104 sqrt(A(i,i) A(j,j)), 51 sampled entries of L L^T - A"}
+    ts, rs = run(dict(algo=b.MPDD_OZAKI_I8, nslices=12))
+    out["split_i8"] = {"form": "right-looking, 1024-column panels, trailing updates as split-form "
+                               "Rsyrk (INT8, 12 slices)", "nslices": 12,
+                       "ms": round(ts * 1e3, 3), "dd_gflops": round(float(n) ** 3 / 3.0 / ts / 1e9, 1),
+                       "speedup_vs_plain": round(t / ts, 3),
+                       "residual_sampled_worst": round(rs, 5)}
+    log(f"rpotrf {out}")
     del case, A0
     torch.cuda.empty_cache()
-    return {"workload": f"Rpotrf L n={n} ld={W.ld_padded(n)} (SPD: dd U[-1,1) off-diagonal, "
-                        f"n + U[0,1) diagonal)", "ms": round(t * 1e3, 3),
-            "dd_gflops": round(float(n) ** 3 / 3.0 / t / 1e9, 1)}
+    return out
 
 
 def bench_qd(h, args, stream):

@@ -298,6 +298,20 @@ int mpdd_Rpotrf(mpdd_handle h, const char *uplo, mpdd_int n, double *A_hi, doubl
 int mpdd_Rpotrf_nb(mpdd_handle h, const char *uplo, mpdd_int n, double *A_hi, double *A_lo,
                    mpdd_int lda, mpdd_int nb, mpdd_int *info, void *stream);
 
+/* As mpdd_Rpotrf_nb with options (opts may be NULL = MPDD_PLAIN, the form
+ * above).  opts->algo MPDD_OZAKI_I8 / MPDD_OZAKI_F64: right-looking over
+ * panels of 16 blocks (1024 columns for nb = 64) -- each panel is factored
+ * as above inside the trailing matrix, then the rest of the trailing matrix
+ * takes the panel's update in one split-form mpdd_Rsyrk_ex with
+ * opts->nslices slices (lower: A22 -= L21 L21^T; upper: A22 -= U12^T U12);
+ * the panels are enqueued without host round trips and the failure word is
+ * read once, at the end.  Same arguments, info and synchronisation as
+ * mpdd_Rpotrf; MPDD_ERR_ARG for any other algo; errors of a trailing update
+ * are returned as they are. */
+int mpdd_Rpotrf_ex(mpdd_handle h, const mpdd_opts *opts, const char *uplo, mpdd_int n,
+                   double *A_hi, double *A_lo, mpdd_int lda, mpdd_int nb, mpdd_int *info,
+                   void *stream);
+
 /* ---- split-form building blocks ------------------------------------------------ *
  *
  * The split form (algo MPDD_OZAKI_I8 / MPDD_OZAKI_F64) cuts every row of op(A)

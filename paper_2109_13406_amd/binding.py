@@ -109,6 +109,8 @@ SIGNATURES = {
                                   _P, _I, mpdd_qd, _P, _P, _P, _P, _I, _P]),
     "mpdd_Rpotrf": (ctypes.c_int, [_P, _C, _I, _P, _P, _I, ctypes.POINTER(_I), _P]),
     "mpdd_Rpotrf_nb": (ctypes.c_int, [_P, _C, _I, _P, _P, _I, _I, ctypes.POINTER(_I), _P]),
+    "mpdd_Rpotrf_ex": (ctypes.c_int, [_P, ctypes.POINTER(mpdd_opts), _C, _I, _P, _P, _I, _I,
+                                      ctypes.POINTER(_I), _P]),
     "mpdd_ozaki_digit_widths": (ctypes.c_int, [ctypes.c_int, _I, ctypes.c_int,
                                                 ctypes.POINTER(ctypes.c_int),
                                                 ctypes.POINTER(ctypes.c_int)]),
@@ -399,14 +401,20 @@ def mpdd_Qgemm(h, transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, 
                              bt, *pc, ldc, _stream(stream))
 
 
-def mpdd_Rpotrf(h, uplo, n, A, lda, nb=0, stream=None):
+def mpdd_Rpotrf(h, uplo, n, A, lda, nb=0, stream=None, opts=None):
     """A: (hi, lo) pair of tensors or device pointers.  Returns (rc, info):
-    rc = 0 or MPDD_ERR_*, info = LAPACK's info."""
+    rc = 0 or MPDD_ERR_*, info = LAPACK's info.  With opts (an mpdd_opts or
+    a dict of its fields) the call goes to mpdd_Rpotrf_ex."""
     info = _I(0)
     ok = _first(uplo) in ("U", "L") and n >= 0 and lda >= max(1, n)
     pa = _planes(A, _extent(n, n, lda) if ok else 0, "A")
-    rc = load().mpdd_Rpotrf_nb(h, _flag(uplo), n, pa[0], pa[1], lda, nb, ctypes.byref(info),
-                               _stream(stream))
+    if opts is None:
+        rc = load().mpdd_Rpotrf_nb(h, _flag(uplo), n, pa[0], pa[1], lda, nb, ctypes.byref(info),
+                                   _stream(stream))
+    else:
+        o = opts if isinstance(opts, mpdd_opts) else _opts(**opts)
+        rc = load().mpdd_Rpotrf_ex(h, ctypes.byref(o), _flag(uplo), n, pa[0], pa[1], lda, nb,
+                                   ctypes.byref(info), _stream(stream))
     return rc, info.value
 
 

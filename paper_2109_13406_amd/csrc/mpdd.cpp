@@ -579,37 +579,200 @@ int mpdd_Cgemm(mpdd_handle h, const char* transa, const char* transb, mpdd_int m
 // POTRF_CHECK blocks and at the end, and stops launching once it is set.
 // After a failure, the columns before the failing block hold the factor and
 // A(k,k) the pivot; later columns are unspecified.
-int mpdd_Rpotrf_nb(mpdd_handle h, const char* uplo, mpdd_int n, double* A_hi, double* A_lo,
-                   mpdd_int lda, mpdd_int nb, mpdd_int* info, void* stream) {
-  if (!info) return MPDD_ERR_ARG;
-  *info = 0;
-  const bool upper = lsame(uplo, 'U');
-  if (!upper && !lsame(uplo, 'L')) { *info = -1; return 0; }
-  if (n < 0) { *info = -2; return 0; }
-  if (lda < std::max<mpdd_int>(1, n)) { *info = -4; return 0; }
-  if (!handle_ok(h)) return MPDD_ERR_HANDLE;
-  if (nb == 0) nb = 64;
-  if (nb < 1 || nb > 64) return MPDD_ERR_UNSUPPORTED;
-  if (n == 0) return 0;
-  if (!A_hi || !A_lo) return MPDD_ERR_ARG;
-  hipStream_t st = (hipStream_t)stream;
-  // Bulk updates alternate between two streams, so that one block's bulk
-  // product can start while the previous block's is still running; block b
-  // keeps its column in P[b % NP], so the bulk update of block b may start as
-  // soon as block b-2 is finished while blocks b-1 and b-2 still hold theirs.
-  constexpr int NP = 3;
+// One blocked Cholesky in progress: the streams, events and scratch of the
+// left-looking schedule with look-ahead, kept for every panel of a call.
+//
+// Bulk updates alternate between two streams, so that one block's bulk
+// product can start while the previous block's is still running; block b
+// keeps its column in P[b % NP], so the bulk update of block b may start as
+// soon as block b-2 is finished while blocks b-1 and b-2 still hold theirs.
+struct PotrfRun {
+  static constexpr int NP = 3;
+  static constexpr int64_t CHECK = 16;   // blocks between host reads of the failure word
+  mpdd_handle h = nullptr;
+  bool upper = false;
+  int64_t lda = 0, nb = 0;
+  hipStream_t st = nullptr;
   hipStream_t sb[2] = {nullptr, nullptr};
   hipEvent_t ev_bulk[NP] = {}, ev_done[NP] = {};
   hipEvent_t ev_start = nullptr, ev_end[2] = {nullptr, nullptr};
-  auto make_event = [](hipEvent_t& e) {
-    return hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess;
-  };
-  bool ok = true;
-  for (int t = 0; t < 2 && ok; ++t)
-    ok = hipStreamCreateWithFlags(&sb[t], hipStreamNonBlocking) == hipSuccess;
-  for (int t = 0; t < NP && ok; ++t) ok = make_event(ev_bulk[t]) && make_event(ev_done[t]);
-  ok = ok && make_event(ev_start) && make_event(ev_end[0]) && make_event(ev_end[1]);
-  auto release = [&]() {
+  void* ws = nullptr;
+  double *w_hi = nullptr, *w_lo = nullptr;
+  double* p_hi[NP] = {};
+  double* p_lo[NP] = {};
+  long long* d_info = nullptr;
+  long long hinfo = 0;       // the failure word as last read by the host
+  bool joined = true;        // the bulk streams' work is ordered before st's
+
+  // Streams, events and scratch for matrices of order <= n (W: nb x nb, the
+  // block-column copies P: n x nb, two planes each); the failure word is
+  // cleared on st.
+  int open(mpdd_handle h_, bool upper_, int64_t n, int64_t lda_, int64_t nb_, hipStream_t st_) {
+    h = h_;
+    upper = upper_;
+    lda = lda_;
+    nb = nb_;
+    st = st_;
+    auto make_event = [](hipEvent_t& e) {
+      return hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess;
+    };
+    bool ok = true;
+    for (int t = 0; t < 2 && ok; ++t)
+      ok = hipStreamCreateWithFlags(&sb[t], hipStreamNonBlocking) == hipSuccess;
+    for (int t = 0; t < NP && ok; ++t) ok = make_event(ev_bulk[t]) && make_event(ev_done[t]);
+    ok = ok && make_event(ev_start) && make_event(ev_end[0]) && make_event(ev_end[1]);
+    if (!ok) return MPDD_ERR_HIP;
+    const size_t wb = (size_t)nb * nb * sizeof(double);
+    const size_t pb = (size_t)n * nb * sizeof(double);
+    if (hipMallocFromPoolAsync(&ws, 2 * wb + 2 * NP * pb + 256, h->pool, st) != hipSuccess) {
+      ws = nullptr;
+      return MPDD_ERR_ALLOC;
+    }
+    w_hi = (double*)ws;
+    w_lo = (double*)((char*)ws + wb);
+    for (int t = 0; t < NP; ++t) {
+      p_hi[t] = (double*)((char*)ws + 2 * wb + 2 * t * pb);
+      p_lo[t] = (double*)((char*)ws + 2 * wb + (2 * t + 1) * pb);
+    }
+    d_info = (long long*)((char*)ws + 2 * wb + 2 * NP * pb);
+    return hipMemsetAsync(d_info, 0, sizeof(long long), st) == hipSuccess ? 0 : MPDD_ERR_HIP;
+  }
+
+  // Enqueue the factorisation of the first ncols columns (upper: rows) of the
+  // n x n matrix A (n no larger than open's), uplo triangle, on st: a failing
+  // pivot is recorded as its column + col0 + 1 in the failure word, and later
+  // block kernels leave their blocks alone.  With ncols = n this is the whole
+  // factorisation; with fewer, the factored columns are a panel of a
+  // right-looking factorisation, whose trailing matrix has received the
+  // updates of the panels before it.  The bulk streams start after the work
+  // already on st and are joined back into st at the end.  With `checks`,
+  // the host reads the failure word every CHECK blocks and stops at a
+  // failure (synchronising st); without, nothing waits on the host.
+  int factor(double* A_hi, double* A_lo, int64_t n, int64_t ncols, int64_t col0, bool checks) {
+    int rc = 0;
+    if (hipEventRecord(ev_start, st) != hipSuccess ||
+        hipStreamWaitEvent(sb[0], ev_start, 0) != hipSuccess ||
+        hipStreamWaitEvent(sb[1], ev_start, 0) != hipSuccess)
+      return MPDD_ERR_HIP;
+    const mpdd_dd one{1.0, 0.0}, mone{-1.0, 0.0}, zero{0.0, 0.0};
+    // the panel solve is a skinny product with k = jb: 32 x 32 tiles give the
+    // CUs more workgroups
+    mpdd_opts small{MPDD_PLAIN, 0, 2, 1};
+    auto at = [&](double* base, int64_t i, int64_t j) { return base + i + j * lda; };
+    const int64_t nblk = (ncols + nb - 1) / nb;
+    // copy block column b into P[b % NP] on stream s
+    auto load_block = [&](int64_t b, hipStream_t s) -> int {
+      const int64_t j = b * nb, jb = std::min<int64_t>(nb, ncols - j), rows = n - j;
+      const int64_t ldp = upper ? jb : rows;
+      const int64_t w = upper ? jb : rows, hgt = upper ? rows : jb;
+      for (int t = 0; t < 2; ++t) {
+        double* dst = t ? p_lo[b % NP] : p_hi[b % NP];
+        const double* src = t ? at(A_lo, j, j) : at(A_hi, j, j);
+        if (hipMemcpy2DAsync(dst, ldp * sizeof(double), src, lda * sizeof(double),
+                             w * sizeof(double), hgt, hipMemcpyDeviceToDevice, s) != hipSuccess)
+          return MPDD_ERR_HIP;
+      }
+      return 0;
+    };
+    // P[b % NP] -= contributions of block columns [c0, c1) (c1 > c0) on stream s
+    auto update_block = [&](int64_t b, int64_t c0, int64_t c1, hipStream_t s) -> int {
+      const int64_t j = b * nb, jb = std::min<int64_t>(nb, ncols - j), rows = n - j;
+      const int64_t k0 = c0 * nb, kk = c1 * nb - k0;
+      double* ph = p_hi[b % NP];
+      double* pl = p_lo[b % NP];
+      if (!upper)
+        return run_plain(h, nullptr, false, true, 0, rows, jb, kk, mone, at(A_hi, j, k0),
+                         at(A_lo, j, k0), lda, at(A_hi, j, k0), at(A_lo, j, k0), lda, one, ph,
+                         pl, rows, s);
+      return run_plain(h, nullptr, true, false, 0, jb, rows, kk, mone, at(A_hi, k0, j),
+                       at(A_lo, k0, j), lda, at(A_hi, k0, j), at(A_lo, k0, j), lda, one, ph, pl,
+                       jb, s);
+    };
+    // bulk stream t & 1, block t: load P_t and apply block columns [0, t-1),
+    // once block t-2 is finished (which also frees P[t % NP], last used by
+    // block t-3)
+    auto bulk = [&](int64_t t) -> int {
+      hipStream_t s = sb[t & 1];
+      if (t >= 2 && hipStreamWaitEvent(s, ev_done[(t - 2) % NP], 0) != hipSuccess)
+        return MPDD_ERR_HIP;
+      int r = load_block(t, s);
+      if (!r && t >= 2) r = update_block(t, 0, t - 1, s);
+      if (!r && hipEventRecord(ev_bulk[t % NP], s) != hipSuccess) r = MPDD_ERR_HIP;
+      return r;
+    };
+    joined = false;
+    rc = bulk(0);
+    if (!rc && nblk > 1) rc = bulk(1);
+    for (int64_t b = 0; b < nblk && !rc; ++b) {
+      const int64_t j = b * nb, jb = std::min<int64_t>(nb, ncols - j), rows = n - j;
+      const int64_t ldp = upper ? jb : rows;
+      // critical path of block b on the caller's stream
+      if (hipStreamWaitEvent(st, ev_bulk[b % NP], 0) != hipSuccess) {
+        rc = MPDD_ERR_HIP;
+        break;
+      }
+      if (b >= 1 && (rc = update_block(b, b - 1, b, st)) != 0) break;
+      if (launch_potf2_block(p_hi[b % NP], p_lo[b % NP], ldp, at(A_hi, j, j), at(A_lo, j, j),
+                             lda, (int)jb, upper ? 1 : 0, w_hi, w_lo, d_info,
+                             (long long)(col0 + j), st) != hipSuccess) {
+        rc = MPDD_ERR_HIP;
+        break;
+      }
+      if (rows > jb) {
+        // panel solve: lower A(j+jb:n, j:j+jb) = P(jb:, :) W^T; upper
+        // A(j:j+jb, j+jb:n) = W P(:, jb:)   (W = U^-T in the lower view)
+        if (!upper)
+          rc = run_plain(h, &small, false, true, 0, rows - jb, jb, jb, one, p_hi[b % NP] + jb,
+                         p_lo[b % NP] + jb, ldp, w_hi, w_lo, jb, zero, at(A_hi, j + jb, j),
+                         at(A_lo, j + jb, j), lda, st);
+        else
+          rc = run_plain(h, &small, false, false, 0, jb, rows - jb, jb, one, w_hi, w_lo, jb,
+                         p_hi[b % NP] + jb * jb, p_lo[b % NP] + jb * jb, ldp, zero,
+                         at(A_hi, j, j + jb), at(A_lo, j, j + jb), lda, st);
+        if (rc) break;
+      }
+      // block b finished: block b+2's bulk update may start
+      if (hipEventRecord(ev_done[b % NP], st) != hipSuccess) {
+        rc = MPDD_ERR_HIP;
+        break;
+      }
+      if (b + 2 < nblk && (rc = bulk(b + 2)) != 0) break;
+      // every CHECK blocks: stop once a pivot has failed
+      if (checks && b % CHECK == CHECK - 1) {
+        if (hipMemcpyAsync(&hinfo, d_info, sizeof(long long), hipMemcpyDeviceToHost, st) !=
+                hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess) {
+          rc = MPDD_ERR_HIP;
+          break;
+        }
+        if (hinfo) break;
+      }
+    }
+    // st waits for the bulk streams (later work on st, and the release of
+    // the scratch, come after them)
+    bool ok = true;
+    for (int t = 0; t < 2; ++t)
+      ok = ok && hipEventRecord(ev_end[t], sb[t]) == hipSuccess &&
+           hipStreamWaitEvent(st, ev_end[t], 0) == hipSuccess;
+    joined = ok;
+    if (!rc && !ok) rc = MPDD_ERR_HIP;
+    return rc;
+  }
+
+  // Read the failure word (unless rc != 0 or a failure has been read),
+  // free the scratch, wait for st and release the streams and events.
+  // Returns rc, or the first error of these steps.
+  int close(int rc) {
+    if (ws && !rc && !hinfo &&
+        (hipMemcpyAsync(&hinfo, d_info, sizeof(long long), hipMemcpyDeviceToHost, st) !=
+             hipSuccess ||
+         hipStreamSynchronize(st) != hipSuccess))
+      rc = MPDD_ERR_HIP;
+    if (!joined)
+      for (int t = 0; t < 2; ++t)
+        if (sb[t]) (void)hipStreamSynchronize(sb[t]);
+    const hipError_t ef = ws ? hipFreeAsync(ws, st) : hipSuccess;
+    const hipError_t es = hipStreamSynchronize(st);
     for (int t = 0; t < NP; ++t) {
       if (ev_bulk[t]) (void)hipEventDestroy(ev_bulk[t]);
       if (ev_done[t]) (void)hipEventDestroy(ev_done[t]);
@@ -619,147 +782,68 @@ int mpdd_Rpotrf_nb(mpdd_handle h, const char* uplo, mpdd_int n, double* A_hi, do
       if (ev_end[t]) (void)hipEventDestroy(ev_end[t]);
       if (sb[t]) (void)hipStreamDestroy(sb[t]);
     }
-  };
-  if (!ok) {
-    release();
-    return MPDD_ERR_HIP;
+    if (rc) return rc;
+    return (ef != hipSuccess || es != hipSuccess) ? MPDD_ERR_HIP : 0;
   }
-  const size_t wb = (size_t)nb * nb * sizeof(double);
-  const size_t pb = (size_t)n * nb * sizeof(double);
-  void* ws = nullptr;
-  if (hipMallocFromPoolAsync(&ws, 2 * wb + 2 * NP * pb + 256, h->pool, st) != hipSuccess) {
-    release();
-    return MPDD_ERR_ALLOC;
-  }
-  double* w_hi = (double*)ws;
-  double* w_lo = (double*)((char*)ws + wb);
-  double* p_hi[NP];
-  double* p_lo[NP];
-  for (int t = 0; t < NP; ++t) {
-    p_hi[t] = (double*)((char*)ws + 2 * wb + 2 * t * pb);
-    p_lo[t] = (double*)((char*)ws + 2 * wb + (2 * t + 1) * pb);
-  }
-  long long* d_info = (long long*)((char*)ws + 2 * wb + 2 * NP * pb);
-  int rc = 0;
-  if (hipMemsetAsync(d_info, 0, sizeof(long long), st) != hipSuccess ||
-      hipEventRecord(ev_start, st) != hipSuccess ||
-      hipStreamWaitEvent(sb[0], ev_start, 0) != hipSuccess ||
-      hipStreamWaitEvent(sb[1], ev_start, 0) != hipSuccess)
-    rc = MPDD_ERR_HIP;
-  constexpr int64_t POTRF_CHECK = 16;   // blocks between host reads of the failure word
-  long long hinfo = 0;
-  const mpdd_dd one{1.0, 0.0}, mone{-1.0, 0.0}, zero{0.0, 0.0};
-  // the panel solve is a skinny product with k = jb: 32 x 32 tiles give the
-  // CUs more workgroups
-  mpdd_opts small{MPDD_PLAIN, 0, 2, 1};
-  auto at = [&](double* base, int64_t i, int64_t j) { return base + i + j * lda; };
-  const int64_t nblk = (n + nb - 1) / nb;
-  // copy block column b into P[b % NP] on stream s
-  auto load_block = [&](int64_t b, hipStream_t s) -> int {
-    const int64_t j = b * nb, jb = std::min<int64_t>(nb, n - j), rows = n - j;
-    const int64_t ldp = upper ? jb : rows;
-    const int64_t w = upper ? jb : rows, hgt = upper ? rows : jb;
-    for (int t = 0; t < 2; ++t) {
-      double* dst = t ? p_lo[b % NP] : p_hi[b % NP];
-      const double* src = t ? at(A_lo, j, j) : at(A_hi, j, j);
-      if (hipMemcpy2DAsync(dst, ldp * sizeof(double), src, lda * sizeof(double),
-                           w * sizeof(double), hgt, hipMemcpyDeviceToDevice, s) != hipSuccess)
-        return MPDD_ERR_HIP;
-    }
-    return 0;
-  };
-  // P[b % NP] -= contributions of block columns [c0, c1) (c1 > c0) on stream s
-  auto update_block = [&](int64_t b, int64_t c0, int64_t c1, hipStream_t s) -> int {
-    const int64_t j = b * nb, jb = std::min<int64_t>(nb, n - j), rows = n - j;
-    const int64_t k0 = c0 * nb, kk = c1 * nb - k0;
-    double* ph = p_hi[b % NP];
-    double* pl = p_lo[b % NP];
-    if (!upper)
-      return run_plain(h, nullptr, false, true, 0, rows, jb, kk, mone, at(A_hi, j, k0),
-                       at(A_lo, j, k0), lda, at(A_hi, j, k0), at(A_lo, j, k0), lda, one, ph, pl,
-                       rows, s);
-    return run_plain(h, nullptr, true, false, 0, jb, rows, kk, mone, at(A_hi, k0, j),
-                     at(A_lo, k0, j), lda, at(A_hi, k0, j), at(A_lo, k0, j), lda, one, ph, pl, jb,
-                     s);
-  };
-  // bulk stream t & 1, block t: load P_t and apply block columns [0, t-1),
-  // once block t-2 is finished (which also frees P[t % NP], last used by
-  // block t-3)
-  auto bulk = [&](int64_t t) -> int {
-    hipStream_t s = sb[t & 1];
-    if (t >= 2 && hipStreamWaitEvent(s, ev_done[(t - 2) % NP], 0) != hipSuccess)
-      return MPDD_ERR_HIP;
-    int r = load_block(t, s);
-    if (!r && t >= 2) r = update_block(t, 0, t - 1, s);
-    if (!r && hipEventRecord(ev_bulk[t % NP], s) != hipSuccess) r = MPDD_ERR_HIP;
-    return r;
-  };
-  if (!rc) rc = bulk(0);
-  if (!rc && nblk > 1) rc = bulk(1);
-  for (int64_t b = 0; b < nblk && !rc; ++b) {
-    const int64_t j = b * nb, jb = std::min<int64_t>(nb, n - j), rows = n - j;
-    const int64_t ldp = upper ? jb : rows;
-    // critical path of block b on the caller's stream
-    if (hipStreamWaitEvent(st, ev_bulk[b % NP], 0) != hipSuccess) {
-      rc = MPDD_ERR_HIP;
-      break;
-    }
-    if (b >= 1 && (rc = update_block(b, b - 1, b, st)) != 0) break;
-    if (launch_potf2_block(p_hi[b % NP], p_lo[b % NP], ldp, at(A_hi, j, j), at(A_lo, j, j), lda,
-                           (int)jb, upper ? 1 : 0, w_hi, w_lo, d_info, (long long)j,
-                           st) != hipSuccess) {
-      rc = MPDD_ERR_HIP;
-      break;
-    }
-    if (rows > jb) {
-      // panel solve: lower A(j+jb:n, j:j+jb) = P(jb:, :) W^T; upper
-      // A(j:j+jb, j+jb:n) = W P(:, jb:)   (W = U^-T in the lower view)
-      if (!upper)
-        rc = run_plain(h, &small, false, true, 0, rows - jb, jb, jb, one, p_hi[b % NP] + jb,
-                       p_lo[b % NP] + jb, ldp, w_hi, w_lo, jb, zero, at(A_hi, j + jb, j),
-                       at(A_lo, j + jb, j), lda, st);
-      else
-        rc = run_plain(h, &small, false, false, 0, jb, rows - jb, jb, one, w_hi, w_lo, jb,
-                       p_hi[b % NP] + jb * jb, p_lo[b % NP] + jb * jb, ldp, zero,
-                       at(A_hi, j, j + jb), at(A_lo, j, j + jb), lda, st);
-      if (rc) break;
-    }
-    // block b finished: block b+2's bulk update may start
-    if (hipEventRecord(ev_done[b % NP], st) != hipSuccess) {
-      rc = MPDD_ERR_HIP;
-      break;
-    }
-    if (b + 2 < nblk && (rc = bulk(b + 2)) != 0) break;
-    // every POTRF_CHECK blocks: stop once a pivot has failed
-    if (b % POTRF_CHECK == POTRF_CHECK - 1) {
-      if (hipMemcpyAsync(&hinfo, d_info, sizeof(long long), hipMemcpyDeviceToHost, st) !=
-              hipSuccess ||
-          hipStreamSynchronize(st) != hipSuccess) {
-        rc = MPDD_ERR_HIP;
-        break;
+};
+
+int mpdd_Rpotrf_nb(mpdd_handle h, const char* uplo, mpdd_int n, double* A_hi, double* A_lo,
+                   mpdd_int lda, mpdd_int nb, mpdd_int* info, void* stream) {
+  return mpdd_Rpotrf_ex(h, nullptr, uplo, n, A_hi, A_lo, lda, nb, info, stream);
+}
+
+// Blocks per panel of the right-looking form (split-form trailing updates):
+// 1024 columns for nb = 64 (measured at n = 8192 against 512 and 2048).
+constexpr int64_t POTRF_PANEL_BLOCKS = 16;
+
+int mpdd_Rpotrf_ex(mpdd_handle h, const mpdd_opts* opts, const char* uplo, mpdd_int n,
+                   double* A_hi, double* A_lo, mpdd_int lda, mpdd_int nb, mpdd_int* info,
+                   void* stream) {
+  if (!info) return MPDD_ERR_ARG;
+  *info = 0;
+  const bool upper = lsame(uplo, 'U');
+  if (!upper && !lsame(uplo, 'L')) { *info = -1; return 0; }
+  if (n < 0) { *info = -2; return 0; }
+  if (lda < std::max<mpdd_int>(1, n)) { *info = -4; return 0; }
+  if (!handle_ok(h)) return MPDD_ERR_HANDLE;
+  const int algo = opts ? opts->algo : MPDD_PLAIN;
+  if (algo != MPDD_PLAIN && algo != MPDD_OZAKI_I8 && algo != MPDD_OZAKI_F64) return MPDD_ERR_ARG;
+  if (nb == 0) nb = 64;
+  if (nb < 1 || nb > 64) return MPDD_ERR_UNSUPPORTED;
+  if (n == 0) return 0;
+  if (!A_hi || !A_lo) return MPDD_ERR_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  PotrfRun run;
+  int rc = run.open(h, upper, n, lda, nb, st);
+  if (!rc && algo == MPDD_PLAIN) {
+    rc = run.factor(A_hi, A_lo, n, n, 0, true);
+  } else if (!rc) {
+    // Right-looking over panels of POTRF_PANEL_BLOCKS blocks: the panel's
+    // columns (rows for 'U') are factored left-looking inside the trailing
+    // matrix, then the rest of the trailing matrix takes the panel's update
+    // in one split-form Rsyrk: lower A22 -= L21 L21^T, upper A22 -= U12^T U12.
+    // Everything is enqueued on st without host round trips; a failing pivot
+    // stays recorded in the failure word, read at the end (the factor beyond
+    // it is unspecified, as for the plain form).
+    const int64_t pw = nb * POTRF_PANEL_BLOCKS;
+    const mpdd_opts so{algo, opts->nslices, -1, 0};
+    const mpdd_dd one{1.0, 0.0}, mone{-1.0, 0.0};
+    for (int64_t j0 = 0; j0 < n && !rc; j0 += pw) {
+      const int64_t rest = n - j0, w = std::min(pw, rest);
+      double* ah = A_hi + j0 + j0 * lda;
+      double* al = A_lo + j0 + j0 * lda;
+      rc = run.factor(ah, al, rest, w, j0, false);
+      if (!rc && rest > w) {
+        const int64_t off = upper ? w * lda : w;      // U12 or L21
+        rc = mpdd_Rsyrk_ex(h, &so, upper ? "U" : "L", upper ? "T" : "N", rest - w, w, mone,
+                           ah + off, al + off, lda, one, ah + w + w * lda, al + w + w * lda,
+                           lda, stream);
       }
-      if (hinfo) break;
     }
   }
-  // the caller's stream waits for the bulk streams before the scratch is freed
-  bool joined = true;
-  for (int t = 0; t < 2; ++t)
-    joined = joined && hipEventRecord(ev_end[t], sb[t]) == hipSuccess &&
-             hipStreamWaitEvent(st, ev_end[t], 0) == hipSuccess;
-  if (!rc && !joined) rc = MPDD_ERR_HIP;
-  if (!rc && !hinfo &&
-      (hipMemcpyAsync(&hinfo, d_info, sizeof(long long), hipMemcpyDeviceToHost, st) !=
-           hipSuccess ||
-       hipStreamSynchronize(st) != hipSuccess))
-    rc = MPDD_ERR_HIP;
-  if (!joined)
-    for (int t = 0; t < 2; ++t) (void)hipStreamSynchronize(sb[t]);
-  const hipError_t ef = hipFreeAsync(ws, st);
-  const hipError_t es = hipStreamSynchronize(st);
-  release();
+  rc = run.close(rc);
   if (rc) return rc;
-  if (ef != hipSuccess || es != hipSuccess) return MPDD_ERR_HIP;
-  *info = (mpdd_int)hinfo;
+  *info = (mpdd_int)run.hinfo;
   return 0;
 }
 

@@ -52,12 +52,16 @@ def residual_ratio(F, A, n, ld, uplo):
     return float(np.linalg.norm(d) / (n * np.linalg.norm(A[0][idx]) * EPS_DD))
 
 
-def run_gpu(h, c, nb=0):
+def run_gpu(h, c, nb=0, opts=None):
     from paper_2109_13406_amd import binding as b
     A = dev(c["A"])
-    rc, info = b.mpdd_Rpotrf(h, c["uplo"], c["n"], A, c["lda"], nb=nb)
+    rc, info = b.mpdd_Rpotrf(h, c["uplo"], c["n"], A, c["lda"], nb=nb, opts=opts)
     assert rc == 0
     return info, host(A)
+
+
+# right-looking form with split-form (INT8, 12 slices) trailing updates
+SPLIT = dict(algo=1, nslices=12)
 
 
 def run_oracle(c):
@@ -87,6 +91,52 @@ def test_potrf_vs_oracle(h, uplo, n):
         rest[idx] = False
         assert np.array_equal(bits(G[0])[rest], bits(c["A"][0])[rest])
         assert np.array_equal(bits(G[1])[rest], bits(c["A"][1])[rest])
+
+
+@pytest.mark.parametrize("uplo", "LU")
+@pytest.mark.parametrize("n,nb", [(65, 0), (1100, 0), (1100, 32), (700, 16)])
+def test_potrf_split_updates_vs_oracle(h, uplo, n, nb):
+    """Right-looking Rpotrf over panels of 16 blocks whose trailing updates
+    are split-form Rsyrk calls (INT8 with 12 slices, FP64 with 5): the
+    factor within 8 n 2^-104 of the oracle's, the residual within LAPACK's
+    threshold, nothing outside the triangle touched; n = 1100 takes two
+    panels with nb = 64 and three with nb = 32, n = 700 three with nb = 16
+    (the last ragged)."""
+    for opts in (SPLIT, dict(algo=2, nslices=5)):
+        c = W.spd_case(5500 + n, n, uplo)
+        io, O = run_oracle(c)
+        ig, G = run_gpu(h, c, nb=nb, opts=opts)
+        assert io == 0 and ig == 0
+        idx = tri_idx(n, c["lda"], uplo)
+        d = (G[0][idx] - O[0][idx]) + (G[1][idx] - O[1][idx])
+        r = float(np.linalg.norm(d) / np.linalg.norm(O[0][idx]) / (n * EPS_DD))
+        res = residual_ratio(G, c["A"], n, c["lda"], uplo)
+        log(f"PARITY potrf split {opts['algo']} {uplo} n={n} nb={nb}: factor ratio {r:.4g}, "
+            f"residual {res:.4g}")
+        assert r <= 8.0, (uplo, n, opts, r)
+        assert res <= THRESH, (uplo, n, opts, res)
+        rest = np.ones(G[0].shape[0], bool)
+        rest[idx] = False
+        assert np.array_equal(bits(G[0])[rest], bits(c["A"][0])[rest])
+        assert np.array_equal(bits(G[1])[rest], bits(c["A"][1])[rest])
+
+
+@pytest.mark.parametrize("uplo", "LU")
+def test_potrf_split_updates_info(h, uplo):
+    """Failing pivots in the first, second and third panel (and at panel
+    boundaries: 1024-column panels with nb = 64, 512-column ones with
+    nb = 32) give the oracle's info; an unknown algo is rejected."""
+    from paper_2109_13406_amd import binding as b
+    n = 1100
+    for k in (1, 300, 512, 513, 1024, 1025, 1100):
+        for nb in (0, 32):
+            c = W.spd_case(5600 + k, n, uplo, fail_at=k)
+            io, _ = run_oracle(c)
+            ig, _ = run_gpu(h, c, nb=nb, opts=SPLIT)
+            assert io == k and ig == k, (uplo, k, nb, io, ig)
+    c = W.spd_case(5700, 8, uplo)
+    rc, _ = b.mpdd_Rpotrf(h, uplo, 8, dev(c["A"]), c["lda"], opts=dict(algo=3))
+    assert rc == b.MPDD_ERR_ARG
 
 
 @pytest.mark.parametrize("uplo", "LU")
@@ -127,8 +177,9 @@ def test_potrf_1024(h, uplo):
     assert r <= 8.0
 
 
+@pytest.mark.parametrize("form", ["plain", "split"])
 @pytest.mark.parametrize("uplo", "LU")
-def test_potrf_8192_sampled(h, uplo):
+def test_potrf_8192_sampled(h, uplo, form):
     """The benchmarked size (n = 8192, ld = 8195), checked where the oracle can
     follow it: the leading 256 x 256 block equals the oracle's factor of the
     leading principal submatrix, the first 256 entries of sampled later rows
@@ -161,7 +212,7 @@ def test_potrf_8192_sampled(h, uplo):
     A_ij = [(float(A0[0][i, j]), float(A0[1][i, j])) for i, j in zip(ii, jj)]
     diag = A0[0].diagonal().cpu().numpy().copy()
 
-    rc, info = b.mpdd_Rpotrf(h, uplo, n, c["A"], ld)
+    rc, info = b.mpdd_Rpotrf(h, uplo, n, c["A"], ld, opts=SPLIT if form == "split" else None)
     torch.cuda.synchronize()
     assert rc == 0 and info == 0
     L = lower_view(c["A"])
@@ -179,7 +230,7 @@ def test_potrf_8192_sampled(h, uplo):
     idx = tri_idx(n0, n0, uplo)
     d = (Gf[0][idx] - O[0][idx]) + (Gf[1][idx] - O[1][idx])
     r = float(np.linalg.norm(d) / np.linalg.norm(O[0][idx]) / (n0 * EPS_DD))
-    log(f"PARITY potrf {uplo} n={n} leading {n0}: factor ratio {r:.4g}")
+    log(f"PARITY potrf {form} {uplo} n={n} leading {n0}: factor ratio {r:.4g}")
     assert r <= 8.0
 
     # sampled rows, first n0 columns
@@ -196,7 +247,7 @@ def test_potrf_8192_sampled(h, uplo):
         grow = [x[i, :n0].cpu().numpy() for x in L]
         d = (grow[0] - orow[0]) + (grow[1] - orow[1])
         r = float(np.linalg.norm(d) / np.linalg.norm(orow[0]) / (n0 * EPS_DD))
-        log(f"PARITY potrf {uplo} n={n} row {i} cols <{n0}: ratio {r:.4g}")
+        log(f"PARITY potrf {form} {uplo} n={n} row {i} cols <{n0}: ratio {r:.4g}")
         assert r <= 8.0, (i, r)
 
     # sampled residual entries (L L^T - A)(i, j), i >= j
@@ -209,5 +260,5 @@ def test_potrf_8192_sampled(h, uplo):
         assert oracle.rgemm("N", "T", 1, 1, kk, (1.0, 0.0), Li, 1, Lj, 1, (-1.0, 0.0), C, 1) == 0
         res = abs(C[0][0] + C[1][0]) / (n * EPS_DD * np.sqrt(diag[i] * diag[j]))
         worst = max(worst, res)
-    log(f"PARITY potrf {uplo} n={n}: worst sampled residual ratio {worst:.4g}")
+    log(f"PARITY potrf {form} {uplo} n={n}: worst sampled residual ratio {worst:.4g}")
     assert worst <= THRESH
