@@ -300,7 +300,7 @@ int mpdd_Rpotrf_nb(mpdd_handle h, const char *uplo, mpdd_int n, double *A_hi, do
 
 /* As mpdd_Rpotrf_nb with options (opts may be NULL = MPDD_PLAIN, the form
  * above).  opts->algo MPDD_OZAKI_I8 / MPDD_OZAKI_F64: right-looking over
- * panels of 16 blocks (1024 columns for nb = 64) -- each panel is factored
+ * panels of 1024 columns (rounded down to whole blocks) -- each panel is factored
  * as above inside the trailing matrix, then the rest of the trailing matrix
  * takes the panel's update in one split-form mpdd_Rsyrk_ex with
  * opts->nslices slices (lower: A22 -= L21 L21^T; upper: A22 -= U12^T U12);

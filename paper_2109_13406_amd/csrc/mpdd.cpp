@@ -792,9 +792,10 @@ int mpdd_Rpotrf_nb(mpdd_handle h, const char* uplo, mpdd_int n, double* A_hi, do
   return mpdd_Rpotrf_ex(h, nullptr, uplo, n, A_hi, A_lo, lda, nb, info, stream);
 }
 
-// Blocks per panel of the right-looking form (split-form trailing updates):
-// 1024 columns for nb = 64 (measured at n = 8192 against 512 and 2048).
-constexpr int64_t POTRF_PANEL_BLOCKS = 16;
+// Panel width of the right-looking form (split-form trailing updates), in
+// columns, rounded down to whole blocks (measured at n = 8192 with nb = 64:
+// 1024 against 512 and 2048).
+constexpr int64_t POTRF_PANEL_COLUMNS = 1024;
 
 int mpdd_Rpotrf_ex(mpdd_handle h, const mpdd_opts* opts, const char* uplo, mpdd_int n,
                    double* A_hi, double* A_lo, mpdd_int lda, mpdd_int nb, mpdd_int* info,
@@ -818,14 +819,14 @@ int mpdd_Rpotrf_ex(mpdd_handle h, const mpdd_opts* opts, const char* uplo, mpdd_
   if (!rc && algo == MPDD_PLAIN) {
     rc = run.factor(A_hi, A_lo, n, n, 0, true);
   } else if (!rc) {
-    // Right-looking over panels of POTRF_PANEL_BLOCKS blocks: the panel's
+    // Right-looking over panels of POTRF_PANEL_COLUMNS columns: the panel's
     // columns (rows for 'U') are factored left-looking inside the trailing
     // matrix, then the rest of the trailing matrix takes the panel's update
     // in one split-form Rsyrk: lower A22 -= L21 L21^T, upper A22 -= U12^T U12.
     // Everything is enqueued on st without host round trips; a failing pivot
     // stays recorded in the failure word, read at the end (the factor beyond
     // it is unspecified, as for the plain form).
-    const int64_t pw = nb * POTRF_PANEL_BLOCKS;
+    const int64_t pw = std::max<int64_t>(1, POTRF_PANEL_COLUMNS / nb) * nb;
     const mpdd_opts so{algo, opts->nslices, -1, 0};
     const mpdd_dd one{1.0, 0.0}, mone{-1.0, 0.0};
     for (int64_t j0 = 0; j0 < n && !rc; j0 += pw) {
