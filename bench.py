@@ -477,7 +477,20 @@ def bench_cgemm(h, args, stream):
     case = W.cgemm_case_device(W.BASE_SEED + 5, "N", "N", n, n, n)
     torch.cuda.synchronize()
     out = {"workload": f"Cgemm NN m=n=k={n} ld={W.ld_padded(n)} (four real dd planes each)"}
-    for form, opts in (("4m", None), ("3m", dict(algo=b.MPDD_COMPLEX_3M))):
+    C0 = tuple(x.clone() for x in case["C"])
+    for form, opts in (("4m", None), ("3m", dict(algo=b.MPDD_COMPLEX_3M)),
+                       ("split_i8", dict(algo=b.MPDD_OZAKI_I8, nslices=12))):
+        # one call from the saved C, checked against the CPU oracle on 32 x 32
+        # sampled entries, then the timed calls
+        for dst, src in zip(case["C"], C0):
+            dst.copy_(src)
+        if b.mpdd_Cgemm_ex(h, opts, "N", "N", n, n, n, case["alpha"], case["A"], case["lda"],
+                           case["B"], case["ldb"], case["beta"], case["C"], case["ldc"],
+                           stream=stream) != 0:
+            raise RuntimeError("mpdd_Cgemm_ex failed")
+        torch.cuda.synchronize()
+        out[f"ratio_vs_oracle_{form}"] = round(cgemm_sample_ratio(case, C0, 32, W.BASE_SEED + 5), 4)
+
         def step():
             info = b.mpdd_Cgemm_ex(h, opts, "N", "N", n, n, n, case["alpha"], case["A"],
                                    case["lda"], case["B"], case["ldb"], case["beta"], case["C"],
@@ -489,9 +502,42 @@ def bench_cgemm(h, args, stream):
         t = sum(per) / len(per)
         out[f"ms_{form}"] = round(t * 1e3, 3)
         out[f"complex_dd_gflops_{form}"] = round(8.0 * n ** 3 / t / 1e9, 1)
-    del case
+    out["nslices_split_i8"] = 12
+    out["oracle_sample"] = "32 x 32 entries; ratio over their real and imaginary parts, units of k 2^-104"
+    log(f"cgemm {out}")
+    del case, C0
     torch.cuda.empty_cache()
     return out
+
+
+def cgemm_sample_ratio(case, C0, count, seed):
+    """Normwise ratio (units of k 2^-104, over real and imaginary parts) of a
+    device Cgemm NN result at count x count sampled entries against the CPU
+    oracle run on the gathered rows of A and columns of B, from C0."""
+    import numpy as np
+    import oracle
+    import torch
+    from oracle.compare import ratio
+    m, n, k = case["m"], case["n"], case["k"]
+    lda, ldb, ldc = case["lda"], case["ldb"], case["ldc"]
+    rng = np.random.default_rng(seed)
+    I = np.sort(rng.choice(m, count, replace=False))
+    J = np.sort(rng.choice(n, count, replace=False))
+    ti, tj = (torch.as_tensor(x, device=case["C"][0].device) for x in (I, J))
+    # count x k rows of A (ld count), k x count columns of B (ld k)
+    As = tuple(p[: k * lda].view(k, lda)[:, ti].contiguous().cpu().numpy().ravel()
+               for p in case["A"])
+    Bs = tuple(p[: n * ldb].view(n, ldb)[tj, :k].contiguous().cpu().numpy().ravel()
+               for p in case["B"])
+    # entry (I[a], J[b]) at position b count + a: column-major count x count
+    idx = (ti[:, None] + tj[None, :] * ldc).t().contiguous().ravel()
+    Cs = tuple(p[idx].cpu().numpy() for p in C0)
+    got = tuple(p[idx].cpu().numpy() for p in case["C"])
+    O = tuple(x.copy() for x in Cs)
+    assert oracle.cgemm("N", "N", count, count, k, case["alpha"], As, count, Bs, k, case["beta"],
+                        O, count) == 0
+    return ratio(np.concatenate([got[0], got[2]]), np.concatenate([got[1], got[3]]),
+                 np.concatenate([O[0], O[2]]), np.concatenate([O[1], O[3]]), k)
 
 
 def potrf_residual_sample(A0, F, n, ld, count, seed):

@@ -235,7 +235,10 @@ int mpdd_Cgemm(mpdd_handle h, const char *transa, const char *transb, mpdd_int m
  * Re P = R1 - R2, Im P = R3 - R1 - R2; a quarter less arithmetic, with the
  * error of Im P relative to |Ar + Ai| |Br + Bi|; extra scratch
  * 16 (m k + k n) bytes); tile_id / splitk choose the real products' tiling as
- * in mpdd_Rgemm_ex.  MPDD_ERR_ARG for another algo. */
+ * in mpdd_Rgemm_ex.  MPDD_OZAKI_I8 / MPDD_OZAKI_F64: the four real products
+ * of MPDD_PLAIN, each a split-form product (opts->nslices, tile_id as in
+ * mpdd_Rgemm_ex), then the same complex epilogue.  MPDD_ERR_ARG for another
+ * algo. */
 int mpdd_Cgemm_ex(mpdd_handle h, const mpdd_opts *opts, const char *transa, const char *transb,
                   mpdd_int m, mpdd_int n, mpdd_int k, mpdd_ddc alpha, const double *A_re_hi,
                   const double *A_re_lo, const double *A_im_hi, const double *A_im_lo,

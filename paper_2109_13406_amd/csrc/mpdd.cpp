@@ -453,7 +453,10 @@ int mpdd_Cgemm_ex(mpdd_handle h, const mpdd_opts* opts, const char* transa, cons
   if (info) return info;
   if (!handle_ok(h)) return MPDD_ERR_HANDLE;
   const int algo = opts ? opts->algo : MPDD_PLAIN;
-  if (algo != MPDD_PLAIN && algo != MPDD_COMPLEX_3M) return MPDD_ERR_ARG;
+  if (algo != MPDD_PLAIN && algo != MPDD_COMPLEX_3M && algo != MPDD_OZAKI_I8 &&
+      algo != MPDD_OZAKI_F64)
+    return MPDD_ERR_ARG;
+  const bool split = algo == MPDD_OZAKI_I8 || algo == MPDD_OZAKI_F64;
   const bool alpha_zero = is_zero(alpha.re) && is_zero(alpha.im);
   const bool beta_zero = is_zero(beta.re) && is_zero(beta.im);
   const bool beta_one = is_one(beta.re) && is_zero(beta.im);
@@ -483,24 +486,27 @@ int mpdd_Cgemm_ex(mpdd_handle h, const mpdd_opts* opts, const char* transa, cons
   const size_t plane = (size_t)m * (size_t)n * sizeof(double);
   const mpdd_dd zero{0.0, 0.0}, one{1.0, 0.0};
   e.ldp = m;
-  if (algo == MPDD_PLAIN) {
+  if (algo != MPDD_COMPLEX_3M) {
+    // four real products (plain, or split form: each an Rgemm_ex of the
+    // caller's split algo, slice count and INT8 tiling)
+    auto product = [&](mpdd_dd a, const double* xh, const double* xl, const double* yh,
+                       const double* yl, mpdd_dd b, double* ph, double* pl) -> int {
+      if (split)
+        return ozaki_gemm(opts, 0, ta, tb, m, n, k, a.hi, a.lo, xh, xl, lda, yh, yl, ldb, b.hi,
+                          b.lo, ph, pl, m, st, h->pool);
+      return run_plain(h, &ro, ta, tb, 0, m, n, k, a, xh, xl, lda, yh, yl, ldb, b, ph, pl, m, st);
+    };
     void* w = nullptr;
     if (hipMallocFromPoolAsync(&w, 4 * plane, h->pool, st) != hipSuccess) return MPDD_ERR_ALLOC;
     double* prh = (double*)w;
     double* prl = (double*)((char*)w + plane);
     double* pih = (double*)((char*)w + 2 * plane);
     double* pil = (double*)((char*)w + 3 * plane);
-    int rc = run_plain(h, &ro, ta, tb, 0, m, n, k, one, A_re_hi, A_re_lo, lda, B_re_hi,
-                       B_re_lo, ldb, zero, prh, prl, m, st);
+    int rc = product(one, A_re_hi, A_re_lo, B_re_hi, B_re_lo, zero, prh, prl);
     if (!rc)
-      rc = run_plain(h, &ro, ta, tb, 0, m, n, k, mpdd_dd{-sa * sb, 0.0}, A_im_hi, A_im_lo, lda,
-                     B_im_hi, B_im_lo, ldb, one, prh, prl, m, st);
-    if (!rc)
-      rc = run_plain(h, &ro, ta, tb, 0, m, n, k, mpdd_dd{sb, 0.0}, A_re_hi, A_re_lo, lda,
-                     B_im_hi, B_im_lo, ldb, zero, pih, pil, m, st);
-    if (!rc)
-      rc = run_plain(h, &ro, ta, tb, 0, m, n, k, mpdd_dd{sa, 0.0}, A_im_hi, A_im_lo, lda,
-                     B_re_hi, B_re_lo, ldb, one, pih, pil, m, st);
+      rc = product(mpdd_dd{-sa * sb, 0.0}, A_im_hi, A_im_lo, B_im_hi, B_im_lo, one, prh, prl);
+    if (!rc) rc = product(mpdd_dd{sb, 0.0}, A_re_hi, A_re_lo, B_im_hi, B_im_lo, zero, pih, pil);
+    if (!rc) rc = product(mpdd_dd{sa, 0.0}, A_im_hi, A_im_lo, B_re_hi, B_re_lo, one, pih, pil);
     if (!rc) {
       e.p_rh = prh; e.p_rl = prl; e.p_ih = pih; e.p_il = pil;
       rc = hip_status(launch_cgemm_epilogue(e, st));

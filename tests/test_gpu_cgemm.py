@@ -122,11 +122,12 @@ def test_worked_example(h):
 SHAPES = [(1, 1, 1), (97, 131, 77), (65, 1, 300), (130, 70, 33), (200, 190, 1)]
 
 
-@pytest.mark.parametrize("form", ["4M", "3M"])
+@pytest.mark.parametrize("form", ["4M", "3M", "split"])
 @pytest.mark.parametrize("op", W.COPS, ids=[a + b for a, b in W.COPS])
 def test_cgemm_ragged(h, op, form):
     from paper_2109_13406_amd import binding as b
-    opts = None if form == "4M" else dict(algo=b.MPDD_COMPLEX_3M)
+    opts = {"4M": None, "3M": dict(algo=b.MPDD_COMPLEX_3M),
+            "split": dict(algo=b.MPDD_OZAKI_I8, nslices=22)}[form]
     for (m, n, k) in SHAPES:
         for dist in ("uniform", "wide"):
             c = W.cgemm_case(4000 + m + k, op[0], op[1], m, n, k, dist=dist)
@@ -139,7 +140,7 @@ def test_cgemm_ragged(h, op, form):
 
 def test_cgemm_3m_options(h):
     """The three-product form at 512^3 (k-split and tile choices passed on),
-    and an unknown algo rejected before any work."""
+    and an algo Cgemm does not take rejected before any work."""
     from paper_2109_13406_amd import binding as b
     c = W.cgemm_case(W.BASE_SEED + 5, "C", "N", 512, 512, 512)
     O = cgemm_oracle(c)
@@ -148,7 +149,8 @@ def test_cgemm_3m_options(h):
         assert info == 0
         assert compare(f"3M 512^3 CN tile{tile}", G, O, c["C"], 512, 512, 512,
                        c["ldc"]) <= RATIO_MAX
-    info, G = cgemm_gpu(h, W.cgemm_case(1, "N", "N", 4, 4, 4), dict(algo=b.MPDD_OZAKI_I8))
+    info, G = cgemm_gpu(h, W.cgemm_case(1, "N", "N", 4, 4, 4),
+                        dict(algo=b.MPDD_PLAIN_ACCURATE))
     assert info == b.MPDD_ERR_ARG
 
 
@@ -229,13 +231,15 @@ def test_cgemm_2048_sampled(h):
 
 
 def test_cgemm_4096_sampled(h):
-    """The benchmarked size and inputs (4096^3 NN, device-generated operands,
-    both the four- and the three-product form) on 32 x 32 sampled entries: the
-    oracle runs on the gathered rows of op(A) and columns of op(B)."""
+    """The benchmarked size and inputs (4096^3 NN, device-generated operands;
+    the four- and the three-product form, and the four products in the INT8
+    split form with the benchmark's 12 slices) on 32 x 32 sampled entries:
+    the oracle runs on the gathered rows of op(A) and columns of op(B)."""
     import torch
     from paper_2109_13406_amd import binding as b
     n = 4096
-    for form, opts in (("4M", None), ("3M", dict(algo=b.MPDD_COMPLEX_3M))):
+    for form, opts in (("4M", None), ("3M", dict(algo=b.MPDD_COMPLEX_3M)),
+                       ("split", dict(algo=b.MPDD_OZAKI_I8, nslices=12))):
         c = W.cgemm_case_device(W.BASE_SEED + 5, "N", "N", n, n, n)
         rng = np.random.default_rng(11)
         I = np.sort(rng.choice(n, 32, replace=False))
