@@ -266,6 +266,25 @@ int mpdd_Qgemm(mpdd_handle h, const char *transa, const char *transb, mpdd_int m
                const double *B2, const double *B3, mpdd_int ldb, mpdd_qd beta, double *C0,
                double *C1, double *C2, double *C3, mpdd_int ldc, void *stream);
 
+/* As mpdd_Qgemm with options (opts may be NULL = MPDD_PLAIN, the kernel
+ * above).  opts->algo MPDD_OZAKI_I8: the split form (see the split-form
+ * building blocks below) for quad-double operands -- every row of op(A) and
+ * column of op(B) is scaled by the exponent of its largest |x0| and cut into
+ * opts->nslices INT8 digit slices (0 = 32; at most 48; digit widths as
+ * mpdd_ozaki_digit_widths gives them for k), the same exact slice products
+ * per anti-diagonal as the dd split form, then the anti-diagonal sums are
+ * added in qd from the smallest weight up, scaled back and C = alpha P +
+ * beta C is formed in qd.  Device scratch of about
+ * nslices ((m + n) k + 4 m n) bytes (padded), stream ordered.  MPDD_ERR_ARG
+ * for another algo; MPDD_ERR_UNSUPPORTED for a slice count or tile_id out
+ * of range or nslices * k >= 2^19. */
+int mpdd_Qgemm_ex(mpdd_handle h, const mpdd_opts *opts, const char *transa, const char *transb,
+                  mpdd_int m, mpdd_int n, mpdd_int k, mpdd_qd alpha, const double *A0,
+                  const double *A1, const double *A2, const double *A3, mpdd_int lda,
+                  const double *B0, const double *B1, const double *B2, const double *B3,
+                  mpdd_int ldb, mpdd_qd beta, double *C0, double *C1, double *C2, double *C3,
+                  mpdd_int ldc, void *stream);
+
 /* ---- Cholesky factorisation: Rpotrf -------------------------------------------------
  *
  * Rpotrf: the dd Cholesky factorisation of a symmetric positive definite

@@ -107,6 +107,9 @@ SIGNATURES = {
                                      _P, _I, _P]),
     "mpdd_Qgemm": (ctypes.c_int, [_P, _C, _C, _I, _I, _I, mpdd_qd, _P, _P, _P, _P, _I, _P, _P, _P,
                                   _P, _I, mpdd_qd, _P, _P, _P, _P, _I, _P]),
+    "mpdd_Qgemm_ex": (ctypes.c_int, [_P, ctypes.POINTER(mpdd_opts), _C, _C, _I, _I, _I, mpdd_qd,
+                                     _P, _P, _P, _P, _I, _P, _P, _P, _P, _I, mpdd_qd, _P, _P, _P,
+                                     _P, _I, _P]),
     "mpdd_Rpotrf": (ctypes.c_int, [_P, _C, _I, _P, _P, _I, ctypes.POINTER(_I), _P]),
     "mpdd_Rpotrf_nb": (ctypes.c_int, [_P, _C, _I, _P, _P, _I, _I, ctypes.POINTER(_I), _P]),
     "mpdd_Rpotrf_ex": (ctypes.c_int, [_P, ctypes.POINTER(mpdd_opts), _C, _I, _P, _P, _I, _I,
@@ -391,14 +394,21 @@ def _qd(x):
     return mpdd_qd((ctypes.c_double * 4)(*[float(v) for v in x]))
 
 
-def mpdd_Qgemm(h, transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, stream=None):
+def mpdd_Qgemm(h, transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, stream=None,
+               opts=None):
     """Quad-double Rgemm.  A, B, C: 4-tuples of planes (x0..x3) as tensors or
-    device pointers; alpha, beta: 4-tuples of floats.  Returns info."""
+    device pointers; alpha, beta: 4-tuples of floats.  With opts (an
+    mpdd_opts or a dict of its fields) the call goes to mpdd_Qgemm_ex.
+    Returns info."""
     a, bt = _qd(alpha), _qd(beta)
     pa, pb, pc = _gemm_ptrs(4, transa, transb, m, n, k, all(v == 0.0 for v in a.x),
                             list(bt.x) == [1.0, 0.0, 0.0, 0.0], A, lda, B, ldb, C, ldc)
-    return load().mpdd_Qgemm(h, _flag(transa), _flag(transb), m, n, k, a, *pa, lda, *pb, ldb,
-                             bt, *pc, ldc, _stream(stream))
+    if opts is None:
+        return load().mpdd_Qgemm(h, _flag(transa), _flag(transb), m, n, k, a, *pa, lda, *pb, ldb,
+                                 bt, *pc, ldc, _stream(stream))
+    o = opts if isinstance(opts, mpdd_opts) else _opts(**opts)
+    return load().mpdd_Qgemm_ex(h, ctypes.byref(o), _flag(transa), _flag(transb), m, n, k, a,
+                                *pa, lda, *pb, ldb, bt, *pc, ldc, _stream(stream))
 
 
 def mpdd_Rpotrf(h, uplo, n, A, lda, nb=0, stream=None, opts=None):

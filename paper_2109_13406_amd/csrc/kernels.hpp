@@ -124,6 +124,13 @@ int ozaki_gemm(const void* opts, int tri, bool ta, bool tb, int64_t m, int64_t n
                double beta_hi, double beta_lo, double* c_hi, double* c_lo, int64_t ldc,
                hipStream_t st, hipMemPool_t pool);
 
+// Split-form qd Rgemm (ozaki.hip; INT8 slices): alpha, beta four parts each,
+// a, b, c four planes each; alpha != 0 and k > 0.  Returns 0 or MPDD_ERR_*.
+int ozaki_qgemm(const void* opts, bool ta, bool tb, int64_t m, int64_t n, int64_t k,
+                const double* alpha, const double* const* a, int64_t lda,
+                const double* const* b, int64_t ldb, const double* beta, int beta_zero,
+                double* const* c, int64_t ldc, hipStream_t st, hipMemPool_t pool);
+
 // Split-form building blocks (ozaki.hip).
 int ozaki_split_entry(int algo, bool trans, int64_t rows, int64_t k, const double* hi,
                       const double* lo, int64_t ld, int nslices, int wfirst, int w, int* exps,

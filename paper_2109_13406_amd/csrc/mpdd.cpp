@@ -866,9 +866,21 @@ int mpdd_Qgemm(mpdd_handle h, const char* transa, const char* transb, mpdd_int m
                const double* A3, mpdd_int lda, const double* B0, const double* B1,
                const double* B2, const double* B3, mpdd_int ldb, mpdd_qd beta, double* C0,
                double* C1, double* C2, double* C3, mpdd_int ldc, void* stream) {
+  return mpdd_Qgemm_ex(h, nullptr, transa, transb, m, n, k, alpha, A0, A1, A2, A3, lda, B0, B1,
+                       B2, B3, ldb, beta, C0, C1, C2, C3, ldc, stream);
+}
+
+int mpdd_Qgemm_ex(mpdd_handle h, const mpdd_opts* opts, const char* transa, const char* transb,
+                  mpdd_int m, mpdd_int n, mpdd_int k, mpdd_qd alpha, const double* A0,
+                  const double* A1, const double* A2, const double* A3, mpdd_int lda,
+                  const double* B0, const double* B1, const double* B2, const double* B3,
+                  mpdd_int ldb, mpdd_qd beta, double* C0, double* C1, double* C2, double* C3,
+                  mpdd_int ldc, void* stream) {
   const int info = check_gemm(transa, transb, m, n, k, lda, ldb, ldc);
   if (info) return info;
   if (!handle_ok(h)) return MPDD_ERR_HANDLE;
+  const int algo = opts ? opts->algo : MPDD_PLAIN;
+  if (algo != MPDD_PLAIN && algo != MPDD_OZAKI_I8) return MPDD_ERR_ARG;
   auto qzero = [](const mpdd_qd& x) { return x.x[0] == 0 && x.x[1] == 0 && x.x[2] == 0 && x.x[3] == 0; };
   const bool alpha_zero = qzero(alpha), beta_zero = qzero(beta);
   const bool beta_one = beta.x[0] == 1.0 && beta.x[1] == 0 && beta.x[2] == 0 && beta.x[3] == 0;
@@ -887,6 +899,10 @@ int mpdd_Qgemm(mpdd_handle h, const char* transa, const char* transb, mpdd_int m
   p.c[0] = C0; p.c[1] = C1; p.c[2] = C2; p.c[3] = C3; p.ldc = ldc;
   p.beta_zero = beta_zero ? 1 : 0;
   p.scale_only = use_ab ? 0 : 1;
+  if (algo == MPDD_OZAKI_I8 && use_ab)
+    return ozaki_qgemm(opts, !lsame(transa, 'N'), !lsame(transb, 'N'), m, n, k, p.alpha, p.a,
+                       lda, p.b, ldb, p.beta, p.beta_zero, p.c, ldc, (hipStream_t)stream,
+                       h->pool);
   return hip_status(launch_qgemm(p, !lsame(transa, 'N'), !lsame(transb, 'N'),
                                  (hipStream_t)stream));
 }

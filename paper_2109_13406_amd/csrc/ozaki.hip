@@ -30,6 +30,7 @@
 #include "../../include/mpdd.h"
 #include "dd.hpp"
 #include "kernels.hpp"
+#include "qd.hpp"
 
 #pragma clang fp contract(off)
 
@@ -864,6 +865,160 @@ oz_combine(const XT* __restrict__ x, int64_t mp, int64_t np, int nslices, int wf
   }
 }
 
+// ---- split form for quad-double operands -------------------------------------------
+
+// Slices of a row operand of quad-doubles (x0 + x1 + x2 + x3, four planes),
+// INT8 digits only.  Staging as in oz_slice (one 33 KB buffer, each part in
+// turn); each thread then turns 8 consecutive l of one row into digits.
+// Digit t: z = y 2^w_t (exact), q_t = rint(z0), z0 - q_t (exact), then two
+// TwoSum sweeps renormalise the four parts: every TwoSum is error-free, so
+// the remainder stays exact, and after the bottom-up sweep z0 is the
+// rounded value of the remainder with the rest below about ulp(z0), which
+// keeps the next digit within the balanced range of oz_slice.  8-bit digits
+// are carried as there, in two passes (the carries first; digit strings up
+// to 64 long); 7-bit digits need no carries.
+constexpr int OZ_QD_MAX_SLICES = 48;
+
+__global__ void __launch_bounds__(512)
+oz_slice_qd(const double* __restrict__ x0, const double* __restrict__ x1,
+            const double* __restrict__ x2, const double* __restrict__ x3, int64_t sr, int64_t sl,
+            int64_t rows, int64_t k, const int* __restrict__ exps, int nslices, int wfirst, int w,
+            int8_t* __restrict__ q, int64_t ldq, int64_t plane) {
+  __shared__ double t[64][65];
+  const int tid = threadIdx.x;
+  const int64_t r0 = (int64_t)blockIdx.y * 64;
+  const int64_t l0 = (int64_t)blockIdx.x * 64;
+  const bool lanes_on_r = (sr == 1);
+  const int rr = tid >> 3;
+  const int lb = (tid & 7) * 8;
+  const int64_t r = r0 + rr;
+  const int e = (r < rows) ? exps[r] : 0;
+  qacc y[8];
+#pragma unroll
+  for (int part = 0; part < 4; ++part) {
+    const double* __restrict__ src = part == 0 ? x0 : part == 1 ? x1 : part == 2 ? x2 : x3;
+    double v[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const int a = tid & 63, b = (tid >> 6) + 8 * c;
+      const int ri = lanes_on_r ? a : b;
+      const int li = lanes_on_r ? b : a;
+      const int64_t rg = r0 + ri, lg = l0 + li;
+      v[c] = (rg < rows && lg < k) ? src[rg * sr + lg * sl] : 0.0;
+    }
+    if (part) __syncthreads();                 // the previous part has been read
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const int a = tid & 63, b = (tid >> 6) + 8 * c;
+      t[lanes_on_r ? a : b][lanes_on_r ? b : a] = v[c];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const double xv = ldexp(t[rr][lb + i], -e);
+      if (part == 0) y[i].s0 = xv;
+      else if (part == 1) y[i].s1 = xv;
+      else if (part == 2) y[i].s2 = xv;
+      else y[i].s3 = xv;
+    }
+  }
+  // one digit of z (in place: z becomes the remainder)
+  auto digit = [](qacc& z, int shift) -> int {
+    z.s0 = ldexp(z.s0, shift);
+    z.s1 = ldexp(z.s1, shift);
+    z.s2 = ldexp(z.s2, shift);
+    z.s3 = ldexp(z.s3, shift);
+    const double qd = rint(z.s0);
+    z.s0 = z.s0 - qd;
+    qd_renorm(z);
+    return (int)qd;
+  };
+  // bit d of cm[i]: the carry out of digit d of element i (8-bit digits)
+  uint64_t cm[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) cm[i] = 0;
+  if (w > 7) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      qacc z = y[i];
+      uint64_t run = 0, c = 0;
+      for (int d = 0; d < nslices; ++d) {
+        const int qv = digit(z, d == 0 ? wfirst : w);
+        if (d == 0) continue;
+        const uint64_t bit = (uint64_t)1 << d;
+        if (qv >= 128) {
+          c |= run | bit;
+          run = 0;
+        } else if (qv == 127) {
+          run |= bit;
+        } else {
+          run = 0;
+        }
+      }
+      cm[i] = c;
+    }
+  }
+  int8_t* out = q + r * ldq + l0 + lb;
+  for (int d = 0; d < nslices; ++d) {
+    const int shift = (d == 0) ? wfirst : w;
+    uint32_t lo = 0, hi = 0;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int qv = digit(y[i], shift);
+      const int cin = (int)((cm[i] >> (d + 1)) & 1), cout = (int)((cm[i] >> d) & 1);
+      const uint32_t byte = (uint32_t)(qv + cin - (cout << w)) & 0xFFu;
+      if (i < 4)
+        lo |= byte << (8 * i);
+      else
+        hi |= byte << (8 * (i - 4));
+    }
+    *(uint2*)(out + (int64_t)d * plane) = uint2{lo, hi};
+  }
+}
+
+// qd combine: one output (i, j) per thread.  The anti-diagonal sums are
+// added in qd from the smallest weight up (each X_d 2^-e_d is an exact
+// binary64: TwoSum into the leading part, the errors passed down the
+// levels, renormalised), then the exact power-of-two scale, then
+// C = alpha P + beta C as qd products by levels (beta = 0: C not read).
+__global__ void __launch_bounds__(256)
+oz_combine_qd(const int32_t* __restrict__ x, int64_t mp, int64_t np, int nslices, int wfirst,
+              int w, const int* __restrict__ ea, const int* __restrict__ eb, int64_t m, int64_t n,
+              double4 alpha, double4 beta, int beta_zero, double* __restrict__ c0,
+              double* __restrict__ c1, double* __restrict__ c2, double* __restrict__ c3,
+              int64_t ldc) {
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= m * n) return;
+  const int64_t i = gid % m, j = gid / m;
+  const int64_t plane = mp * np;
+  const int32_t* xp = x + j * mp + i;
+  qacc p{0.0, 0.0, 0.0, 0.0};
+  for (int d = nslices + 1; d >= 2; --d) {
+    const double v = ldexp((double)xp[(int64_t)(d - 2) * plane], -(2 * wfirst + w * (d - 2)));
+    double e;
+    ts(p.s0, v, p.s0, e);
+    ts(p.s1, e, p.s1, e);
+    ts(p.s2, e, p.s2, e);
+    p.s3 = p.s3 + e;
+    qd_renorm(p);
+  }
+  const double4 pf = qd_final(p);
+  const int sc = ea[i] + eb[j];
+  const double4 ps{ldexp(pf.x, sc), ldexp(pf.y, sc), ldexp(pf.z, sc), ldexp(pf.w, sc)};
+  const int64_t ci = i + j * ldc;
+  qacc r{0.0, 0.0, 0.0, 0.0};
+  qd_madd(r, alpha, ps);
+  if (!beta_zero) {
+    qd_renorm(r);
+    qd_madd(r, beta, double4{c0[ci], c1[ci], c2[ci], c3[ci]});
+  }
+  const double4 o = qd_final(r);
+  c0[ci] = o.x;
+  c1[ci] = o.y;
+  c2[ci] = o.z;
+  c3[ci] = o.w;
+}
+
 // ---- host orchestration -------------------------------------------------------------
 
 static int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
@@ -890,11 +1045,9 @@ static bool digit_widths(int algo, int64_t k, int nslices, int& wfirst, int& w) 
 // Scale exponents + slices of one row operand (rows x k) into padded buffers.
 // `part` is scratch for the chunked maxima (rows * ceil(k / OZ_SCALE_CHUNK)
 // doubles, only used when the rows are contiguous across lanes).
-template <typename T>
-static hipError_t split_operand(const double* hi, const double* lo, int64_t sr, int64_t sl,
-                                int64_t rows, int64_t k, int* exps, T* q, int64_t ldq,
-                                int64_t rows_p, int nslices, int wfirst, int w, double* part,
-                                hipStream_t st) {
+// Scale exponents of one row operand (rows x k) from its leading plane.
+static void scale_operand(const double* hi, int64_t sr, int64_t sl, int64_t rows, int64_t k,
+                          int* exps, double* part, hipStream_t st) {
   if (sl == 1 || k == 0) {
     hipLaunchKernelGGL(oz_scale_rows_wave, dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, st,
                        hi, sr, sl, rows, k, exps);
@@ -905,6 +1058,14 @@ static hipError_t split_operand(const double* hi, const double* lo, int64_t sr, 
     hipLaunchKernelGGL(oz_scale_finish, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, st,
                        part, rows, nchunks, exps);
   }
+}
+
+template <typename T>
+static hipError_t split_operand(const double* hi, const double* lo, int64_t sr, int64_t sl,
+                                int64_t rows, int64_t k, int* exps, T* q, int64_t ldq,
+                                int64_t rows_p, int nslices, int wfirst, int w, double* part,
+                                hipStream_t st) {
+  scale_operand(hi, sr, sl, rows, k, exps, part, st);
   dim3 grid((unsigned)(ldq / 64), (unsigned)(rows_p / 64));
   hipLaunchKernelGGL(oz_slice<T>, grid, dim3(512), 0, st, hi, lo, sr, sl, rows, k, exps, nslices,
                      wfirst, w, q, ldq, rows_p * ldq);
@@ -914,6 +1075,28 @@ static hipError_t split_operand(const double* hi, const double* lo, int64_t sr, 
 static size_t part_bytes(int64_t rows, int64_t k) {
   const int64_t nchunks = (k + OZ_SCALE_CHUNK - 1) / OZ_SCALE_CHUNK;
   return (size_t)((rows * std::max<int64_t>(nchunks, 1) * 8 + 255) / 256 * 256);
+}
+
+// Workgroup tile (rows, columns) of an INT8 product variant.
+static int i8_tile_rows(int var) { return var == 2 ? 128 : 256; }
+static int i8_tile_cols(int var) { return (var == 0 || var >= 3) ? 256 : 128; }
+
+// One launch of the INT8 slice products of every anti-diagonal (variant var).
+static void launch_i8_products(int var, unsigned nblocks, const int8_t* qa, const int8_t* qb,
+                               int32_t* x, int64_t kp, int64_t mp, int64_t np, int s, int tiles_m,
+                               int tiles_n, int tri, hipStream_t st) {
+  auto kern = (var == 0)   ? oz_gemm_i8<256, 256, 2, 2>
+              : (var == 1) ? oz_gemm_i8<256, 128, 2, 2>
+              : (var == 2) ? oz_gemm_i8<128, 128, 2, 2>
+              : (var == 3) ? oz_gemm_i8<256, 256, 2, 4>
+              : (var == 4) ? oz_gemm_i8<256, 256, 4, 4>
+              : (var == 5) ? oz_gemm_i8_dma<256, 256, 2, 4, 4, false, false>
+              : (var == 6) ? oz_gemm_i8_dma<256, 256, 2, 4, 4, true, false>
+              : (var == 7) ? oz_gemm_i8_dma<256, 256, 2, 2, 4, true, false>
+                           : oz_gemm_i8_dma<256, 256, 2, 4, 4, true, true>;
+  const unsigned nthreads = (var == 4) ? 1024 : (var >= 3 && var != 7) ? 512 : 256;
+  hipLaunchKernelGGL(kern, dim3(nblocks), dim3(nthreads), 0, st, qa, qb, x, kp, mp * kp, np * kp,
+                     mp, np, s, tiles_m, tiles_n, tri);
 }
 
 int ozaki_gemm(const void* opts_v, int tri, bool ta, bool tb, int64_t m, int64_t n, int64_t k,
@@ -951,8 +1134,8 @@ int ozaki_gemm(const void* opts_v, int tri, bool ta, bool tb, int64_t m, int64_t
   if (i8 && var > 8) return MPDD_ERR_UNSUPPORTED;
   // a triangle is walked in square tiles (variant 1's are 256 x 128)
   if (tri && i8 && var == 1) return MPDD_ERR_UNSUPPORTED;
-  const int64_t tbm = i8 ? (var == 2 ? 128 : 256) : OZ_BM;
-  const int64_t tbn = i8 ? ((var == 0 || var >= 3) ? 256 : 128) : OZ_BN;
+  const int64_t tbm = i8 ? i8_tile_rows(var) : OZ_BM;
+  const int64_t tbn = i8 ? i8_tile_cols(var) : OZ_BN;
   const int64_t mp = round_up(m, i8 ? I8_PAD : OZ_BM), np = round_up(n, i8 ? I8_PAD : OZ_BN);
   const size_t esz = i8 ? 1 : 8;
   const size_t xsz = i8 ? 4 : 8;
@@ -995,21 +1178,9 @@ int ozaki_gemm(const void* opts_v, int tri, bool ta, bool tb, int64_t m, int64_t
   const int tiles_m = (int)(mp / tbm), tiles_n = (int)(np / tbn);
   const unsigned nblocks = (unsigned)(oz_group_tiles(tri, tiles_m, tiles_n) * s);
   if (e == hipSuccess) {
-    if (i8) {
-      auto kern = (var == 0)   ? oz_gemm_i8<256, 256, 2, 2>
-                  : (var == 1) ? oz_gemm_i8<256, 128, 2, 2>
-                  : (var == 2) ? oz_gemm_i8<128, 128, 2, 2>
-                  : (var == 3) ? oz_gemm_i8<256, 256, 2, 4>
-                  : (var == 4) ? oz_gemm_i8<256, 256, 4, 4>
-                  : (var == 5) ? oz_gemm_i8_dma<256, 256, 2, 4, 4, false, false>
-                  : (var == 6) ? oz_gemm_i8_dma<256, 256, 2, 4, 4, true, false>
-                  : (var == 7) ? oz_gemm_i8_dma<256, 256, 2, 2, 4, true, false>
-                               : oz_gemm_i8_dma<256, 256, 2, 4, 4, true, true>;
-      const unsigned nthreads = (var == 4) ? 1024 : (var >= 3 && var != 7) ? 512 : 256;
-      hipLaunchKernelGGL(kern, dim3(nblocks), dim3(nthreads), 0, st, (const int8_t*)qa,
-                         (const int8_t*)qb, (int32_t*)x, kp, mp * kp, np * kp, mp, np, s, tiles_m,
-                         tiles_n, tri);
-    }
+    if (i8)
+      launch_i8_products(var, nblocks, (const int8_t*)qa, (const int8_t*)qb, (int32_t*)x, kp, mp,
+                         np, s, tiles_m, tiles_n, tri, st);
     else
       hipLaunchKernelGGL(oz_gemm_f64, dim3(nblocks), dim3(256), 0, st, (const double*)qa,
                          (const double*)qb, (double*)x, kp, mp * kp, np * kp, mp, np, s, tiles_m,
@@ -1031,6 +1202,64 @@ int ozaki_gemm(const void* opts_v, int tri, bool ta, bool tb, int64_t m, int64_t
   hipError_t ef = hipFreeAsync(ws, st);
   if (e != hipSuccess) return MPDD_ERR_HIP;
   return ef == hipSuccess ? 0 : MPDD_ERR_HIP;
+}
+
+// Split-form qd Rgemm (INT8 slices): scale and slice op(A) and op(B) from
+// their quad-double planes, the same exact slice products per anti-diagonal
+// as the dd form, combined in qd.  alpha = 0 and k = 0 are the caller's.
+int ozaki_qgemm(const void* opts_v, bool ta, bool tb, int64_t m, int64_t n, int64_t k,
+                const double* alpha, const double* const* a, int64_t lda,
+                const double* const* b, int64_t ldb, const double* beta, int beta_zero,
+                double* const* c, int64_t ldc, hipStream_t st, hipMemPool_t pool) {
+  const mpdd_opts* opts = (const mpdd_opts*)opts_v;
+  if (opts->algo != MPDD_OZAKI_I8) return MPDD_ERR_UNSUPPORTED;
+  int s = opts->nslices;
+  if (s == 0) s = 32;
+  if (s < 1 || s > OZ_QD_MAX_SLICES) return MPDD_ERR_UNSUPPORTED;
+  int wfirst, w;
+  if (!digit_widths(MPDD_OZAKI_I8, k, s, wfirst, w)) return MPDD_ERR_UNSUPPORTED;
+  const int var = opts->tile_id >= 0 ? opts->tile_id : 6;
+  if (var > 8) return MPDD_ERR_UNSUPPORTED;
+  const int64_t kp = round_up(k, 2 * I8_BK);
+  const int64_t mp = round_up(m, I8_PAD), np = round_up(n, I8_PAD);
+  const size_t qa_bytes = (size_t)s * mp * kp, qb_bytes = (size_t)s * np * kp;
+  const size_t x_bytes = (size_t)s * mp * np * sizeof(int32_t);
+  const size_t e_bytes = round_up((m + n) * sizeof(int), 256);
+  const size_t p_bytes = std::max(part_bytes(m, k), part_bytes(n, k));
+  void* ws = nullptr;
+  if (hipMallocFromPoolAsync(&ws, round_up(qa_bytes, 256) + round_up(qb_bytes, 256) + x_bytes +
+                                      e_bytes + p_bytes,
+                             pool, st) != hipSuccess)
+    return MPDD_ERR_ALLOC;
+  int8_t* qa = (int8_t*)ws;
+  int8_t* qb = qa + round_up(qa_bytes, 256);
+  int32_t* x = (int32_t*)(qb + round_up(qb_bytes, 256));
+  int* ea = (int*)((char*)x + x_bytes);
+  int* eb = ea + m;
+  double* part = (double*)((char*)ea + e_bytes);
+  // row operand of A: op(A)(i, l); of B: op(B)(l, j) as element (j, l)
+  const int64_t a_sr = ta ? lda : 1, a_sl = ta ? 1 : lda;
+  const int64_t b_sr = tb ? 1 : ldb, b_sl = tb ? ldb : 1;
+  scale_operand(a[0], a_sr, a_sl, m, k, ea, part, st);
+  hipLaunchKernelGGL(oz_slice_qd, dim3((unsigned)(kp / 64), (unsigned)(mp / 64)), dim3(512), 0,
+                     st, a[0], a[1], a[2], a[3], a_sr, a_sl, m, k, ea, s, wfirst, w, qa, kp,
+                     mp * kp);
+  scale_operand(b[0], b_sr, b_sl, n, k, eb, part, st);
+  hipLaunchKernelGGL(oz_slice_qd, dim3((unsigned)(kp / 64), (unsigned)(np / 64)), dim3(512), 0,
+                     st, b[0], b[1], b[2], b[3], b_sr, b_sl, n, k, eb, s, wfirst, w, qb, kp,
+                     np * kp);
+  const int tiles_m = (int)(mp / i8_tile_rows(var)), tiles_n = (int)(np / i8_tile_cols(var));
+  launch_i8_products(var, (unsigned)(tiles_m * tiles_n * s), qa, qb, x, kp, mp, np, s, tiles_m,
+                     tiles_n, 0, st);
+  hipLaunchKernelGGL(oz_combine_qd, dim3((unsigned)((m * n + 255) / 256)), dim3(256), 0, st, x,
+                     mp, np, s, wfirst, w, ea, eb, m, n,
+                     double4{alpha[0], alpha[1], alpha[2], alpha[3]},
+                     double4{beta[0], beta[1], beta[2], beta[3]}, beta_zero, c[0], c[1], c[2],
+                     c[3], ldc);
+  const hipError_t e = hipGetLastError();
+  const hipError_t ef = hipFreeAsync(ws, st);
+  if (e != hipSuccess || ef != hipSuccess) return MPDD_ERR_HIP;
+  return 0;
 }
 
 // Exposed building block: scale exponents and digit slices of op(X).

@@ -188,3 +188,93 @@ def test_qgemm_2048_sampled(h):
     r = qratio(Gs, O, np.arange(24 * 24), k)
     log(f"PARITY qgemm {n}^3 NN sampled 24x24: ratio {r:.4g}")
     assert r <= RATIO_MAX
+
+
+# ---- split form (INT8 slices of quad-double operands) -----------------------------------
+
+def qgemm_split_gpu(h, c, s, tile_id=-1):
+    from paper_2109_13406_amd import binding as b
+    C = dev4(c["C"])
+    info = b.mpdd_Qgemm(h, c["transa"], c["transb"], c["m"], c["n"], c["k"], c["alpha"],
+                        dev4(c["A"]), c["lda"], dev4(c["B"]), c["ldb"], c["beta"], C, c["ldc"],
+                        opts=dict(algo=b.MPDD_OZAKI_I8, nslices=s, tile_id=tile_id))
+    return info, host4(C)
+
+
+@pytest.mark.parametrize("op", W.OPS)
+def test_qgemm_split_ragged(h, op):
+    """Split-form qd Rgemm with 28 slices: within 8 k 2^-209 of the exactly
+    rounded oracle on ragged shapes, both input sets, every op form; padding
+    rows untouched; the register-staged tiling (tile_id 3) agrees too."""
+    for (m, n, k) in SHAPES:
+        for dist in ("uniform", "wide"):
+            c = W.qgemm_case(7000 + m + k, op[0], op[1], m, n, k, dist=dist)
+            O = qgemm_oracle(c)
+            for tile in (-1, 3):
+                info, G = qgemm_split_gpu(h, c, 28, tile)
+                assert info == 0
+                r = compare(f"split s=28 tile {tile} {op} {m}x{n}x{k} {dist}", G, O, c["C"], m,
+                            n, k, c["ldc"])
+                assert r <= RATIO_MAX, (op, m, n, k, dist, tile, r)
+
+
+def test_qgemm_split_semantics(h):
+    """beta = 0 never reads C (all NaN); alpha = 0 scales C as the plain
+    form does; slice counts outside 1..48, nslices * k >= 2^19 and the FP64
+    split form are rejected with nothing written."""
+    from paper_2109_13406_amd import binding as b
+    zero = (0.0,) * 4
+    c = W.qgemm_case(7200, "T", "N", 21, 18, 12, beta_zero=True, c_nan=True)
+    O = qgemm_oracle(c)
+    info, G = qgemm_split_gpu(h, c, 28)
+    assert info == 0
+    assert compare("split beta0", G, O, c["C"], 21, 18, 12, c["ldc"]) <= RATIO_MAX
+    c = W.qgemm_case(7201, "N", "T", 13, 11, 7)
+    c["alpha"] = zero
+    O = qgemm_oracle(c)
+    info, G = qgemm_split_gpu(h, c, 28)
+    assert info == 0
+    assert compare("split alpha0", G, O, c["C"], 13, 11, 1, c["ldc"]) <= RATIO_MAX
+    c = W.qgemm_case(7202, "N", "N", 9, 9, 9)
+    for s, algo, want in ((49, b.MPDD_OZAKI_I8, b.MPDD_ERR_UNSUPPORTED),
+                          (28, b.MPDD_OZAKI_F64, b.MPDD_ERR_ARG)):
+        C = dev4(c["C"])
+        assert b.mpdd_Qgemm(h, "N", "N", 9, 9, 9, c["alpha"], dev4(c["A"]), c["lda"],
+                            dev4(c["B"]), c["ldb"], c["beta"], C, c["ldc"],
+                            opts=dict(algo=algo, nslices=s)) == want
+        for g, c0 in zip(host4(C), c["C"]):
+            assert np.array_equal(bits(g), bits(c0))
+    # 40 slices x 13108 terms >= 2^19: no exact digit width
+    k = 13108
+    c = W.qgemm_case(7203, "N", "N", 2, 2, k)
+    C = dev4(c["C"])
+    assert b.mpdd_Qgemm(h, "N", "N", 2, 2, k, c["alpha"], dev4(c["A"]), c["lda"], dev4(c["B"]),
+                        c["ldb"], c["beta"], C, c["ldc"],
+                        opts=dict(algo=b.MPDD_OZAKI_I8, nslices=40)) == b.MPDD_ERR_UNSUPPORTED
+    for g, c0 in zip(host4(C), c["C"]):
+        assert np.array_equal(bits(g), bits(c0))
+
+
+@pytest.mark.parametrize("dist", ["uniform", "wide"])
+def test_qgemm_split_2048_slice_search(h, dist):
+    """The benchmarked size (2048^3 NN, both input sets) on 24 x 24 sampled
+    entries against the oracle: the slice count is searched from 24 upward
+    until the ratio is within 8; 24 fails, and the count found (the one the
+    benchmark times) passes."""
+    n = k = 2048
+    c = W.qgemm_case(W.BASE_SEED + 10, "N", "N", n, n, k, dist=dist)
+    rng = np.random.default_rng(12)
+    I = np.sort(rng.choice(n, 24, replace=False))
+    J = np.sort(rng.choice(n, 24, replace=False))
+    O = qgemm_oracle(csub(c, I, J))
+    idx = (I[:, None] + J[None, :] * c["ldc"]).ravel(order="F")
+    found = None
+    for s in range(24, 33):
+        info, G = qgemm_split_gpu(h, c, s)
+        assert info == 0
+        r = qratio(tuple(p[idx] for p in G), O, np.arange(24 * 24), k)
+        log(f"QD SPLIT {n}^3 {dist} s={s}: sampled ratio {r:.4g}")
+        if r <= RATIO_MAX:
+            found = s
+            break
+    assert found is not None and found > 24
