@@ -5,7 +5,8 @@ import this package.  It loads oracle/liboracle.so (plain C: dd_oracle.c for
 Rgemm / Rsyrk, ozaki_oracle.c for the split form, cdd_oracle.c for the
 complex Cgemm, potrf_oracle.c for the Cholesky Rpotrf, qd_oracle.c for the
 quad-double Rgemm) and exposes
-numpy-facing wrappers.  It never
+numpy-facing wrappers.  The modular (Chinese-remainder) split form has its
+oracle in oracle/crt.py: Python integers and numpy, small sizes.  It never
 imports, links or calls the GPU library.
 
 Matrices are passed as pairs (hi, lo) of float64 numpy arrays holding the

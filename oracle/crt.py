@@ -1,0 +1,181 @@
+"""CPU oracle for the modular (Chinese-remainder) split form of dd Rgemm --
+TEST INFRASTRUCTURE.
+
+Only the test suite, the smoke check and the benchmark's CPU-baseline leg may
+import this module; it shares no code with the GPU library.  Exact integers
+are Python ints; numpy serves for the float64 steps and for the per-modulus
+integer products.  Small sizes only (the reconstruction loops over entries).
+
+The manual has no split method.  This form follows the integer modular
+emulation of a floating-point matrix product by Ozaki, Uchino and Imamura
+(Ozaki scheme II, 2025), applied to dd operands:
+
+1. Scale.  sigma_r: the frexp exponent of the largest |hi| of row r of the
+   row operand (a row of op(A), or a column of op(B)); |x_rl| < 2^sigma_r.
+   An all-zero row gets 0.
+2. Integers.  With P bits (`exponent`), z = x 2^(P - sigma) (exact, two
+   binary64 parts zh, zl); t1 = rint(zh), t2 = rint((zh - t1) + zl) in
+   binary64 (ties to even); the integer is X' = t1 + t2, within 1/2 + 2^-52 of
+   z, so |X'| <= 2^P.
+3. Residues.  For each modulus m of the list (`moduli`: the largest first,
+   each pairwise coprime to those before it), the balanced residue of X'
+   modulo m: the representative in [-(m-1)/2, (m-1)/2] for odd m, in
+   [-128, 127] for m = 256.  All fit int8.
+4. Products.  For each modulus, R_A R_B^T over the k terms, exact in
+   integers (|.| <= k 2^14).
+5. Reconstruction.  The unique X in [-M/2, M/2) (M the product of the
+   moduli) congruent to every product modulo its modulus.  P is chosen so
+   that 4 k 2^(2P) <= M; then X equals the exact integer product
+   sum_l A'_il B'_jl.
+6. Result.  C = alpha (X 2^(sigma_i + tau_j - 2P)) + beta C, evaluated exactly
+   and rounded to the nearest dd (hi nearest binary64, lo nearest binary64 of
+   the rest).
+"""
+from fractions import Fraction
+from math import gcd
+
+import numpy as np
+
+MAX_MODULI = 32     # the most moduli the form uses
+MAX_BITS = 104      # the widest integer grid: t2 and the chunks of X' stay exact
+
+
+def moduli(count):
+    """The first `count` moduli: from 256 downward, every integer that is
+    coprime to all moduli taken before it (step 3)."""
+    if count < 1 or count > MAX_MODULI:
+        raise ValueError("count out of range")
+    out = []
+    m = 256
+    while len(out) < count:
+        if all(gcd(m, q) == 1 for q in out):
+            out.append(m)
+        m -= 1
+    return out
+
+
+def modulus_product(count):
+    M = 1
+    for m in moduli(count):
+        M *= m
+    return M
+
+
+def exponent(k, count):
+    """P (step 5): the largest P <= MAX_BITS with 4 k 2^(2P) <= M, or None
+    when there is none >= 1."""
+    M = modulus_product(count)
+    lk = max(0, (max(k, 1) - 1).bit_length())       # ceil(log2 k)
+    p = ((M.bit_length() - 1) - 2 - lk) // 2
+    p = min(p, MAX_BITS)
+    return p if p >= 1 else None
+
+
+def scale_exponents(hi_rows):
+    """Step 1 for a (rows x k) float64 array of leading parts."""
+    mx = np.max(np.abs(hi_rows), axis=1) if hi_rows.shape[1] else np.zeros(hi_rows.shape[0])
+    _, e = np.frexp(mx)
+    return np.where(mx == 0.0, 0, e).astype(np.int64)
+
+
+def integers(hi_rows, lo_rows, exps, p):
+    """Step 2: the integers X' (Python ints, object array rows x k)."""
+    sh = (p - exps).astype(np.int64)[:, None]
+    zh = np.ldexp(hi_rows, sh)
+    zl = np.ldexp(lo_rows, sh)
+    t1 = np.rint(zh)
+    t2 = np.rint((zh - t1) + zl)
+    out = np.empty(hi_rows.shape, dtype=object)
+    for idx in np.ndindex(hi_rows.shape):
+        out[idx] = int(t1[idx]) + int(t2[idx])
+    return out
+
+
+def balanced(x, m):
+    """Step 3's representative of the Python int x modulo m."""
+    r = x % m
+    if m % 2:
+        return r - m if r > (m - 1) // 2 else r
+    return r - m if r >= m // 2 else r
+
+
+def residues(ints, count):
+    """Step 3: int64 array (count, rows, k) of balanced residues."""
+    ms = moduli(count)
+    out = np.zeros((count,) + ints.shape, dtype=np.int64)
+    for t, m in enumerate(ms):
+        for idx in np.ndindex(ints.shape):
+            out[(t,) + idx] = balanced(ints[idx], m)
+    return out
+
+
+def reconstruct(prods, count):
+    """Step 5 for one entry: prods[t] an int congruent to X modulo modulus t."""
+    ms = moduli(count)
+    M = modulus_product(count)
+    x = 0
+    for r, m in zip(prods, ms):
+        Mt = M // m
+        x += int(r) * Mt * pow(Mt, -1, m)
+    x %= M
+    return x - M if x >= (M + 1) // 2 else x
+
+
+def row_operand(trans, rows, k, X, ld):
+    """Row operand (rows x k) of a column-major dd matrix: trans 'N' takes
+    element (r, l) from X[r + l ld], 'T' from X[l + r ld]."""
+    hi, lo = X
+    r = np.arange(rows)[:, None]
+    l = np.arange(k)[None, :]
+    idx = (r + l * ld) if trans.upper() == "N" else (l + r * ld)
+    return hi[idx], lo[idx]
+
+
+def _nearest_dd(v):
+    h = float(v)
+    return h, float(v - Fraction(h))
+
+
+def integer_product(transa, transb, m, n, k, A, lda, B, ldb, count):
+    """Steps 1-5: exponents (sigma, tau), P and the exact integer product X
+    (object array m x n) obtained from the residue products."""
+    p = exponent(k, count)
+    if p is None:
+        raise ValueError("too few moduli for k")
+    ah, al = row_operand(transa, m, k, A, lda)
+    bt = "T" if transb.upper() == "N" else "N"   # columns of op(B) as rows
+    bh, bl = row_operand(bt, n, k, B, ldb)
+    ea, eb = scale_exponents(ah), scale_exponents(bh)
+    ra = residues(integers(ah, al, ea, p), count)
+    rb = residues(integers(bh, bl, eb, p), count)
+    prods = [ra[t] @ rb[t].T for t in range(count)]  # exact in int64
+    X = np.empty((m, n), dtype=object)
+    for i in range(m):
+        for j in range(n):
+            X[i, j] = reconstruct([pr[i, j] for pr in prods], count)
+    return ea, eb, p, X
+
+
+def crt_rgemm(transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, count):
+    """Step 6 on top of integer_product: C updated in place (column-major
+    planes C = (hi, lo), leading dimension ldc); returns C."""
+    ch, cl = C
+    if m == 0 or n == 0:
+        return C
+    a = Fraction(alpha[0]) + Fraction(alpha[1])
+    b = Fraction(beta[0]) + Fraction(beta[1])
+    if k == 0 or a == 0:
+        ea = eb = None
+        p = 0
+        X = np.zeros((m, n), dtype=object)
+    else:
+        ea, eb, p, X = integer_product(transa, transb, m, n, k, A, lda, B, ldb, count)
+    for j in range(n):
+        for i in range(m):
+            v = Fraction(0)
+            if X[i, j]:
+                v = a * X[i, j] * Fraction(2) ** int(ea[i] + eb[j] - 2 * p)
+            if b != 0:
+                v += b * (Fraction(ch[i + j * ldc]) + Fraction(cl[i + j * ldc]))
+            ch[i + j * ldc], cl[i + j * ldc] = _nearest_dd(v)
+    return C

@@ -1,0 +1,290 @@
+"""Pins of the modular split-form oracle (oracle/crt.py) against what the
+mathematics fixes: a hand-derived moduli list, pairwise coprimality and the
+greedy rule, the bound that fixes P, the rounding of each dd entry to its
+integer (checked with exact rationals), congruence and range of the
+residues, Chinese remaindering of random integers, the residue route against
+the plain big-integer matrix product, and the final result against the exact
+product of the dd inputs within the rounding bound of the integer grids.
+A second set plants plausible mistakes in copies of the oracle and checks
+that these pins catch each one.  CPU only."""
+import importlib.util
+import os
+import random
+import tempfile
+from fractions import Fraction
+from math import gcd
+
+import numpy as np
+import pytest
+
+from oracle import crt as CRT
+
+# Moduli by hand: from 256 down, skipping 254, 252, 250, 248, 246, 244, 242,
+# 240, ... (even), 249 = 3*83 and 243 (3 | 255), 245 = 5*7^2 and 235 = 5*47
+# (5 | 255), 231 = 3*7*11 (3), 221 = 13*17 (17 | 255), 225, 219 = 3*73 ...;
+# 217 = 7*31 is coprime to everything before it.
+HAND_MODULI = [256, 255, 253, 251, 247, 241, 239, 233, 229, 227, 223, 217]
+
+
+def _dd_matrix(rng, rows, cols, wide=False):
+    """Column-major dd planes (ld = rows) with hi uniform in (-1, 1) or, for
+    wide, scaled by 2^e with e in [-20, 20] per entry; lo below ulp(hi)/2."""
+    hi = rng.uniform(-1.0, 1.0, rows * cols)
+    if wide:
+        hi = np.ldexp(hi, rng.integers(-20, 21, rows * cols))
+    lo = hi * rng.uniform(-1.0, 1.0, rows * cols) * 2.0 ** -54
+    hi, lo = hi + lo, lo - ((hi + lo) - hi)       # renormalise the pair
+    return hi, lo
+
+
+def check_moduli(crt):
+    assert crt.moduli(len(HAND_MODULI)) == HAND_MODULI
+    ms = crt.moduli(crt.MAX_MODULI)
+    for i, a in enumerate(ms):
+        for b in ms[:i]:
+            assert gcd(a, b) == 1
+    # greedy: every skipped integer shares a factor with an earlier modulus
+    for x in range(ms[-1] + 1, 257):
+        if x not in ms:
+            assert any(gcd(x, q) > 1 for q in ms if q > x)
+    assert all(2 <= m <= 256 for m in ms)
+
+
+def check_exponent(crt):
+    for count in range(1, crt.MAX_MODULI + 1):
+        M = 1
+        for m in crt.moduli(count):
+            M *= m
+        for k in (1, 2, 3, 100, 1024, 1025, 8192, 131071):
+            p = crt.exponent(k, count)
+            k2 = 1 << max(0, (k - 1).bit_length())
+            if p is None:
+                assert 4 * k2 * 4 > M      # no P >= 1 fits
+                continue
+            assert 1 <= p <= crt.MAX_BITS
+            assert 4 * k * 2 ** (2 * p) <= M
+            if p < crt.MAX_BITS:
+                # the largest such P for the power of two at or above k
+                assert 4 * k2 * 2 ** (2 * p + 2) > M
+
+
+def check_integers(crt, rng):
+    for wide in (False, True):
+        hi, lo = _dd_matrix(rng, 7, 33, wide)
+        hi, lo = hi.reshape(7, 33), lo.reshape(7, 33)
+        hi[3] = 0.0
+        lo[3] = 0.0
+        e = crt.scale_exponents(hi)
+        for r in range(7):
+            mx = max(abs(float(v)) for v in hi[r])
+            if mx == 0:
+                assert e[r] == 0
+            else:
+                assert 2.0 ** (int(e[r]) - 1) <= mx < 2.0 ** int(e[r])
+        for p in (20, 61, 95, 104):
+            X = crt.integers(hi, lo, e, p)
+            for r in range(7):
+                for l in range(33):
+                    z = (Fraction(float(hi[r, l])) + Fraction(float(lo[r, l]))) \
+                        * Fraction(2) ** (p - int(e[r]))
+                    assert abs(X[r, l] - z) <= Fraction(1, 2) + Fraction(1, 2 ** 50)
+                    assert abs(X[r, l]) <= 2 ** p
+
+
+def check_residues(crt, rng):
+    count = 12
+    ints = np.empty((3, 40), dtype=object)
+    for idx in np.ndindex(ints.shape):
+        ints[idx] = random.Random(int(rng.integers(1 << 30))).randrange(-2 ** 100, 2 ** 100)
+    ints[0, 0] = 0
+    ints[0, 1] = 128
+    ints[0, 2] = -128
+    ints[0, 3] = 2 ** 100
+    R = crt.residues(ints, count)
+    for t, m in enumerate(crt.moduli(count)):
+        for idx in np.ndindex(ints.shape):
+            r = int(R[(t,) + idx])
+            assert (r - ints[idx]) % m == 0
+            assert -128 <= r <= 127
+            assert abs(r) <= m // 2
+    assert int(R[0, 0, 1]) == -128 and int(R[0, 0, 2]) == -128    # modulo 256
+
+
+def check_reconstruct(crt):
+    rnd = random.Random(7)
+    for count in (2, 5, 12, 27, 32):
+        ms = crt.moduli(count)
+        M = 1
+        for m in ms:
+            M *= m
+        for _ in range(40):
+            x = rnd.randrange(-(M // 4), M // 4)
+            # any representatives: the plain remainders plus random multiples
+            prods = [x % m + m * rnd.randrange(-1000, 1000) for m in ms]
+            assert crt.reconstruct(prods, count) == x
+        assert crt.reconstruct([0] * count, count) == 0
+
+
+def check_integer_product(crt, rng):
+    m, n, k, count = 5, 4, 9, 14
+    A = _dd_matrix(rng, m, k)
+    B = _dd_matrix(rng, n, k, wide=True)          # op(B) = B^T (transb 'T')
+    ea, eb, p, X = crt.integer_product("N", "T", m, n, k, A, m, B, n, count)
+    assert p == crt.exponent(k, count)
+    ah, al = crt.row_operand("N", m, k, A, m)
+    bh, bl = crt.row_operand("N", n, k, B, n)
+    Ai = crt.integers(ah, al, ea, p)
+    Bi = crt.integers(bh, bl, eb, p)
+    plain = Ai.dot(Bi.T)                          # big-integer product
+    for i in range(m):
+        for j in range(n):
+            assert X[i, j] == plain[i, j]
+
+
+def check_rgemm(crt, rng):
+    for (ta, tb, m, n, k, count, wide) in (("N", "N", 6, 5, 11, 27, False),
+                                          ("T", "N", 4, 7, 16, 20, True),
+                                          ("N", "T", 3, 3, 1, 3, False)):
+        A = _dd_matrix(rng, m * k, 1, wide)
+        B = _dd_matrix(rng, k * n, 1)
+        C = _dd_matrix(rng, m * n, 1)
+        lda = m if ta == "N" else k
+        ldb = k if tb == "N" else n
+        alpha = (0.75, 2.0 ** -60)
+        beta = (-1.25, 0.0)
+        c0 = (C[0].copy(), C[1].copy())
+        out = crt.crt_rgemm(ta, tb, m, n, k, alpha, A, lda, B, ldb, beta,
+                            (C[0].copy(), C[1].copy()), m, count)
+        p = crt.exponent(k, count)
+        ah, al = crt.row_operand(ta, m, k, A, lda)
+        bh, bl = crt.row_operand("T" if tb == "N" else "N", n, k, B, ldb)
+        ea, eb = crt.scale_exponents(ah), crt.scale_exponents(bh)
+        a = Fraction(alpha[0]) + Fraction(alpha[1])
+        b = Fraction(beta[0]) + Fraction(beta[1])
+        half = Fraction(1, 2) + Fraction(1, 2 ** 50)
+        for i in range(m):
+            for j in range(n):
+                exact = sum((Fraction(float(ah[i, l])) + Fraction(float(al[i, l])))
+                            * (Fraction(float(bh[j, l])) + Fraction(float(bl[j, l])))
+                            for l in range(k))
+                da = half * Fraction(2) ** (int(ea[i]) - p)
+                db = half * Fraction(2) ** (int(eb[j]) - p)
+                bound = sum(da * abs(Fraction(float(bh[j, l])) + Fraction(float(bl[j, l])))
+                            + db * abs(Fraction(float(ah[i, l])) + Fraction(float(al[i, l])))
+                            + da * db for l in range(k))
+                cij = Fraction(float(c0[0][i + j * m])) + Fraction(float(c0[1][i + j * m]))
+                want = a * exact + b * cij
+                got = Fraction(float(out[0][i + j * m])) + Fraction(float(out[1][i + j * m]))
+                tol = abs(a) * bound + abs(want) * Fraction(1, 2 ** 104)
+                assert abs(got - want) <= tol, (ta, tb, i, j)
+
+
+def test_moduli():
+    check_moduli(CRT)
+
+
+def test_exponent():
+    check_exponent(CRT)
+
+
+def test_integers_round_to_nearest():
+    check_integers(CRT, np.random.default_rng(11))
+
+
+def test_residues():
+    check_residues(CRT, np.random.default_rng(12))
+
+
+def test_reconstruct():
+    check_reconstruct(CRT)
+
+
+def test_integer_product_equals_big_integer_product():
+    check_integer_product(CRT, np.random.default_rng(13))
+
+
+def test_rgemm_within_grid_rounding_of_exact_product():
+    check_rgemm(CRT, np.random.default_rng(14))
+
+
+def test_quick_cases():
+    rng = np.random.default_rng(15)
+    C = _dd_matrix(rng, 6, 1)
+    A = _dd_matrix(rng, 6, 1)
+    # alpha = 0: C = beta C; k = 0 likewise
+    for (alpha, k) in (((0.0, 0.0), 3), ((1.0, 0.0), 0)):
+        out = CRT.crt_rgemm("N", "N", 2, 3, k, alpha, A, 2, A, max(k, 1), (2.0, 0.0),
+                            (C[0].copy(), C[1].copy()), 2, 20)
+        assert np.array_equal(out[0], 2.0 * C[0]) and np.array_equal(out[1], 2.0 * C[1])
+    # beta = 0 never reads C
+    nan = (np.full(6, np.nan), np.full(6, np.nan))
+    out = CRT.crt_rgemm("N", "N", 2, 3, 1, (1.0, 0.0), A, 2, A, 1, (0.0, 0.0), nan, 2, 20)
+    assert np.all(np.isfinite(out[0]))
+    assert CRT.exponent(8192, 2) is None
+
+
+# ---- planted mistakes ------------------------------------------------------------------
+
+MUTANTS = [
+    ("if all(gcd(m, q) == 1 for q in out):", "if all(gcd(m, q) == 1 for q in out[1:]):",
+     "moduli not pairwise coprime"),
+    ("p = ((M.bit_length() - 1) - 2 - lk) // 2", "p = ((M.bit_length() - 1) - lk) // 2",
+     "no margin in P"),
+    ("t2 = np.rint((zh - t1) + zl)", "t2 = np.rint(zh - t1)", "low part dropped"),
+    ("sh = (p - exps).astype(np.int64)[:, None]", "sh = (p + exps).astype(np.int64)[:, None]",
+     "scale sign"),
+    ("return r - m if r >= m // 2 else r", "return r - m if r > m // 2 else r",
+     "residue 128 out of int8"),
+    ("x += int(r) * Mt * pow(Mt, -1, m)", "x += int(r) * Mt",
+     "weights without the inverse"),
+    ("return x - M if x >= (M + 1) // 2 else x", "return x",
+     "reconstruction not balanced"),
+    ("bt = \"T\" if transb.upper() == \"N\" else \"N\"", "bt = transb.upper()",
+     "op(B) transposed"),
+    ("v = a * X[i, j] * Fraction(2) ** int(ea[i] + eb[j] - 2 * p)",
+     "v = a * X[i, j] * Fraction(2) ** int(ea[i] + eb[j] - p)", "wrong result scale"),
+    ("v += b * (Fraction(ch[i + j * ldc]) + Fraction(cl[i + j * ldc]))",
+     "v += b * Fraction(ch[i + j * ldc])", "low part of C dropped"),
+]
+
+CHECKS = [("moduli", lambda c, r: check_moduli(c)),
+          ("exponent", lambda c, r: check_exponent(c)),
+          ("integers", check_integers),
+          ("residues", check_residues),
+          ("reconstruct", lambda c, r: check_reconstruct(c)),
+          ("integer_product", check_integer_product),
+          ("rgemm", check_rgemm)]
+
+
+def _load_copy(text, tmp):
+    path = os.path.join(tmp, "crt_mutant.py")
+    with open(path, "w") as f:
+        f.write(text)
+    spec = importlib.util.spec_from_file_location("crt_mutant", path)
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+def _caught(mod):
+    for name, check in CHECKS:
+        try:
+            check(mod, np.random.default_rng(21))
+        except Exception:
+            return name
+    return None
+
+
+@pytest.mark.parametrize("orig,mut,what", MUTANTS, ids=[m[2] for m in MUTANTS])
+def test_crt_mutant_is_caught(orig, mut, what):
+    src = open(CRT.__file__).read()
+    assert src.count(orig) == 1, what
+    with tempfile.TemporaryDirectory() as tmp:
+        mod = _load_copy(src.replace(orig, mut), tmp)
+        assert _caught(mod) is not None, what
+
+
+def test_crt_unmutated_copy_passes():
+    with tempfile.TemporaryDirectory() as tmp:
+        mod = _load_copy(open(CRT.__file__).read(), tmp)
+        assert _caught(mod) is None
