@@ -728,7 +728,8 @@ def bench_ozaki(h, args, stream, t_plain_main):
     each kind the slice count is searched upward from a small start until the
     normwise error of sampled entries against the CPU oracle is <= 8 k 2^-104
     (the entries and the inputs are those of the GPU test that repeats this
-    search), then that call is timed.  Reported per (kind, n, input set): the
+    search), then that call is timed; the modular form ("crt") searches its
+    moduli count the same way.  Reported per (kind, n, input set): the
     slice count, the ratio and componentwise error against the oracle, the
     ratio against the plain kernel's result (all entries), time and speedup
     over the plain kernel."""
@@ -736,7 +737,8 @@ def bench_ozaki(h, args, stream, t_plain_main):
     import workloads as W
     from paper_2109_13406_amd import binding as b
     out = {}
-    kinds = (("i8", b.MPDD_OZAKI_I8, range(10, 25)), ("f64", b.MPDD_OZAKI_F64, range(3, 11)))
+    kinds = (("i8", b.MPDD_OZAKI_I8, range(10, 25)), ("f64", b.MPDD_OZAKI_F64, range(3, 11)),
+             ("crt", b.MPDD_OZAKI_CRT, range(22, 33)))
     for n in sorted({2048, args.n}):
         for dist in ("uniform", "wide"):
             case = W.gemm_case_device(W.BASE_SEED + 3, "N", "N", n, n, n, dist=dist)
@@ -785,7 +787,9 @@ def bench_ozaki(h, args, stream, t_plain_main):
                         raise RuntimeError(info)
                 _, per = timed_calls(step, 3, 1, stream)
                 t = sum(per) / len(per)
-                pairs = sl * (sl + 1) // 2
+                # products: one per anti-diagonal pair of slices, or one per
+                # modulus (modular form)
+                pairs = sl if kind == "crt" else sl * (sl + 1) // 2
                 rec = {"n": n, "nslices": sl, "ratio_vs_oracle": round(r, 4),
                        "componentwise_vs_oracle": round(c, 2),
                        "oracle_sample": len(smp["flat"]),
@@ -794,7 +798,7 @@ def bench_ozaki(h, args, stream, t_plain_main):
                        "ms": round(t * 1e3, 2), "dd_gflops": round(2.0 * n ** 3 / t / 1e9, 1),
                        "plain_ms": round(t_plain * 1e3, 2),
                        "speedup_vs_plain": round(t_plain / t, 3), "slice_products": pairs}
-                if kind == "i8":
+                if kind != "f64":
                     rec["int8_tops_whole_call"] = round(pairs * 2.0 * n ** 3 / t / 1e12, 1)
                     rec["int8_peak_tops"] = INT8_PEAK_TOPS
                 else:

@@ -138,10 +138,16 @@ int mpdd_Rsyrk_host(mpdd_handle h, const char *uplo, const char *trans, mpdd_int
 #define MPDD_COMPLEX_3M 4     /* Cgemm only: three real products (see mpdd_Cgemm_ex) */
 #define MPDD_PLAIN_ACCURATE 3 /* accurate dd add + mul per term (same steps as the
                                  reference evaluation; 29 binary64 ops) */
+#define MPDD_OZAKI_CRT 5      /* split form, residues modulo nslices pairwise coprime
+                                 moduli <= 256 on the INT8 matrix cores, one product
+                                 per modulus, Chinese-remainder reconstruction (see
+                                 mpdd_ozaki_crt_exponent) */
 
 typedef struct {
-  int algo;     /* MPDD_PLAIN, MPDD_OZAKI_I8, MPDD_OZAKI_F64, MPDD_PLAIN_ACCURATE */
-  int nslices;  /* split form: slices per operand, 0 = default for the input */
+  int algo;     /* MPDD_PLAIN, MPDD_OZAKI_I8, MPDD_OZAKI_F64, MPDD_OZAKI_CRT,
+                   MPDD_PLAIN_ACCURATE */
+  int nslices;  /* split form: slices per operand (MPDD_OZAKI_CRT: moduli, 1..32),
+                   0 = default for the input */
   int tile_id;  /* plain forms: index into the tile table, -1 = tuned choice;
                    INT8 split form: product workgroup tile, 0 = 256x256,
                    1 = 256x128, 2 = 128x128, 3 = 256x256 with 8 waves,
@@ -150,7 +156,9 @@ typedef struct {
                    the next step's fragments read during the MFMAs,
                    7 = as 6 with 4 waves (128x128 each), 8 = as 6 with
                    32x32x32 matrix instructions, -1 = default (6);
-                   all give the same bits; ignored by the FP64 split form */
+                   all give the same bits; MPDD_OZAKI_CRT: 5, 6 or 8
+                   (-1 = 6), others MPDD_ERR_UNSUPPORTED; ignored by
+                   the FP64 split form */
   int splitk;   /* plain forms: k-split factor, 0 = automatic, 1 = none */
 } mpdd_opts;
 
@@ -357,13 +365,39 @@ int mpdd_Rpotrf_ex(mpdd_handle h, const mpdd_opts *opts, const char *uplo, mpdd_
  * w = 7 from there). */
 int mpdd_ozaki_digit_widths(int algo, mpdd_int k, int nslices, int *wfirst, int *w);
 
+/* The modular split form (algo MPDD_OZAKI_CRT; published basis: the integer
+ * modular emulation of Ozaki, Uchino and Imamura, "Ozaki scheme II", 2025).
+ * With sigma as above and P = mpdd_ozaki_crt_exponent(k, nslices), each
+ * element becomes the integer x' = t1 + t2, z = x 2^(P - sigma) (binary64
+ * parts zh + zl), t1 = rint(zh), t2 = rint((zh - t1) + zl), so |x' - z| <=
+ * 1/2 + 2^-52 and |x'| <= 2^P.  The moduli are 256, 255, 253, 251, 247, ...:
+ * from 256 down, each integer coprime to all moduli before it; the first
+ * nslices are used, M their product.  x' is reduced to balanced residues
+ * (odd m: [-(m-1)/2, (m-1)/2]; 256: [-128, 127]), one exact INT8 product per
+ * modulus gives the integer product modulo that modulus, and the exact
+ * integer product (|.| <= k 2^(2P) <= M/4) is rebuilt by Chinese
+ * remaindering and rounded to dd, then scaled by 2^(sigma_i + tau_j - 2P) and
+ * C = alpha P + beta C.  Error against the exact product of the dd inputs:
+ * at most sum_l (|dA_il| |B_lj| + |A_il| |dB_lj| + |dA_il| |dB_lj|) with
+ * |dA_il| <= (1/2 + 2^-52) 2^(sigma_i - P), plus dd rounding.  k must be
+ * below 2^17 (k 128^2 < 2^31).  nslices 0 = the fewest moduli whose P
+ * reaches 104 (30 at k = 8192). */
+
+/* P of the modular split form: the largest P <= 104 with 4 k 2^(2P) <= M for
+ * the first nmoduli moduli.  Returns 0, MPDD_ERR_ARG for k < 0, a NULL p or
+ * nmoduli outside 1..32, MPDD_ERR_UNSUPPORTED when k >= 2^17 or no P >= 1
+ * fits. */
+int mpdd_ozaki_crt_exponent(mpdd_int k, int nmoduli, int *p);
+
 /* Scale exponents and digit slices of a "row operand" R (rows x k): element
  * (r, l) of R is X[r + l*ld] for trans "N" and X[l + r*ld] for trans "T"
  * (rows of op(A) are R with trans = transa; columns of op(B) are R with the
  * flag opposite to transb).  Device outputs: exps[rows] (int32) and
  * `nslices` planes of rows_p x ldq digits, plane t (0-based) at
  * slices + t*rows_p*ldq, digit (r, l) at [r*ldq + l]; int8 for
- * MPDD_OZAKI_I8, double for MPDD_OZAKI_F64.  ldq must be a multiple of 64 and
+ * MPDD_OZAKI_I8, double for MPDD_OZAKI_F64; for MPDD_OZAKI_CRT the planes are
+ * the int8 balanced residues of x' modulo the first `nslices` moduli (1..32),
+ * plane t for modulus t.  ldq must be a multiple of 64 and
  * >= k, rows_p a multiple of 64 and >= rows; padding digits are written as 0.
  * Returns 0, a BLAS-style position (3 rows, 4 k, 8 ld, 9 nslices, 12 ldq,
  * 13 rows_p) for an invalid argument, or MPDD_ERR_*. */

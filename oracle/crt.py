@@ -4,7 +4,7 @@ TEST INFRASTRUCTURE.
 Only the test suite, the smoke check and the benchmark's CPU-baseline leg may
 import this module; it shares no code with the GPU library.  Exact integers
 are Python ints; numpy serves for the float64 steps and for the per-modulus
-integer products.  Small sizes only (the reconstruction loops over entries).
+integer products.  Small sizes only (Python-integer arrays).
 
 The manual has no split method.  This form follows the integer modular
 emulation of a floating-point matrix product by Ozaki, Uchino and Imamura
@@ -78,6 +78,9 @@ def scale_exponents(hi_rows):
     return np.where(mx == 0.0, 0, e).astype(np.int64)
 
 
+_to_int = np.frompyfunc(int, 1, 1)     # elementwise exact float -> Python int
+
+
 def integers(hi_rows, lo_rows, exps, p):
     """Step 2: the integers X' (Python ints, object array rows x k)."""
     sh = (p - exps).astype(np.int64)[:, None]
@@ -85,18 +88,15 @@ def integers(hi_rows, lo_rows, exps, p):
     zl = np.ldexp(lo_rows, sh)
     t1 = np.rint(zh)
     t2 = np.rint((zh - t1) + zl)
-    out = np.empty(hi_rows.shape, dtype=object)
-    for idx in np.ndindex(hi_rows.shape):
-        out[idx] = int(t1[idx]) + int(t2[idx])
-    return out
+    return _to_int(t1) + _to_int(t2)
 
 
 def balanced(x, m):
-    """Step 3's representative of the Python int x modulo m."""
+    """Step 3's representative modulo m of x (a Python int, or an object
+    array of them, elementwise)."""
     r = x % m
-    if m % 2:
-        return r - m if r > (m - 1) // 2 else r
-    return r - m if r >= m // 2 else r
+    top = (m - 1) // 2 if m % 2 else m // 2 - 1      # largest representative
+    return np.where(r > top, r - m, r) if isinstance(r, np.ndarray) else (r - m if r > top else r)
 
 
 def residues(ints, count):
@@ -104,21 +104,23 @@ def residues(ints, count):
     ms = moduli(count)
     out = np.zeros((count,) + ints.shape, dtype=np.int64)
     for t, m in enumerate(ms):
-        for idx in np.ndindex(ints.shape):
-            out[(t,) + idx] = balanced(ints[idx], m)
+        out[t] = balanced(ints, m).astype(np.int64)
     return out
 
 
 def reconstruct(prods, count):
-    """Step 5 for one entry: prods[t] an int congruent to X modulo modulus t."""
+    """Step 5: prods[t] congruent to X modulo modulus t -- Python ints, or
+    integer arrays of one shape (then elementwise, Python ints out)."""
     ms = moduli(count)
     M = modulus_product(count)
     x = 0
     for r, m in zip(prods, ms):
         Mt = M // m
-        x += int(r) * Mt * pow(Mt, -1, m)
-    x %= M
-    return x - M if x >= (M + 1) // 2 else x
+        r = np.asarray(r).astype(object) if isinstance(r, np.ndarray) else int(r)
+        x = x + r * (Mt * pow(Mt, -1, m))
+    x = x % M
+    half = (M + 1) // 2
+    return np.where(x >= half, x - M, x) if isinstance(x, np.ndarray) else (x - M if x >= half else x)
 
 
 def row_operand(trans, rows, k, X, ld):
@@ -149,11 +151,7 @@ def integer_product(transa, transb, m, n, k, A, lda, B, ldb, count):
     ra = residues(integers(ah, al, ea, p), count)
     rb = residues(integers(bh, bl, eb, p), count)
     prods = [ra[t] @ rb[t].T for t in range(count)]  # exact in int64
-    X = np.empty((m, n), dtype=object)
-    for i in range(m):
-        for j in range(n):
-            X[i, j] = reconstruct([pr[i, j] for pr in prods], count)
-    return ea, eb, p, X
+    return ea, eb, p, reconstruct(prods, count)
 
 
 def crt_rgemm(transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, count):

@@ -19,6 +19,7 @@ MPDD_OZAKI_I8 = 1
 MPDD_OZAKI_F64 = 2
 MPDD_PLAIN_ACCURATE = 3
 MPDD_COMPLEX_3M = 4
+MPDD_OZAKI_CRT = 5
 
 MPDD_ERR_HIP = -1
 MPDD_ERR_ALLOC = -2
@@ -117,6 +118,7 @@ SIGNATURES = {
     "mpdd_ozaki_digit_widths": (ctypes.c_int, [ctypes.c_int, _I, ctypes.c_int,
                                                 ctypes.POINTER(ctypes.c_int),
                                                 ctypes.POINTER(ctypes.c_int)]),
+    "mpdd_ozaki_crt_exponent": (ctypes.c_int, [_I, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),
     "mpdd_ozaki_split": (ctypes.c_int, [_P, ctypes.c_int, _C, _I, _I, _P, _P, _I, ctypes.c_int,
                                         _P, _P, _I, _I, _P]),
     "mpdd_Rgemm_host": (ctypes.c_int, [_P, _C, _C, _I, _I, _I, mpdd_dd, _P, _I, _P, _I, mpdd_dd,
@@ -496,20 +498,30 @@ def mpdd_ozaki_digit_widths(algo, k, nslices):
     return a.value, b.value
 
 
+def mpdd_ozaki_crt_exponent(k, nmoduli):
+    """Grid width P of the modular split form; raises if none."""
+    p = ctypes.c_int()
+    info = load().mpdd_ozaki_crt_exponent(k, nmoduli, ctypes.byref(p))
+    if info != 0:
+        raise ValueError(f"no modular grid for k={k} nmoduli={nmoduli}: {info}")
+    return p.value
+
+
 def mpdd_ozaki_split(h, algo, trans, rows, k, X, ld, nslices, exps, slices, ldq, rows_p,
                      stream=None):
-    """Scale exponents (int32 tensor) and slices (int8 / float64 tensor) of a row
-    operand, see include/mpdd.h.  Returns info."""
+    """Scale exponents (int32 tensor) and slices (int8 / float64 tensor; the
+    modular form: int8 residues) of a row operand, see include/mpdd.h.
+    Returns info."""
     import torch
     ft = _first(trans)
     nr, nc = (rows, k) if ft == "N" else (k, rows)
     ok = (ft in ("N", "T", "C") and rows >= 0 and k >= 0 and ld >= max(1, nr) and nslices >= 1
           and ldq >= k and ldq % 64 == 0 and rows_p >= rows and rows_p % 64 == 0
-          and algo in (MPDD_OZAKI_I8, MPDD_OZAKI_F64))
+          and algo in (MPDD_OZAKI_I8, MPDD_OZAKI_F64, MPDD_OZAKI_CRT))
     px = _planes(X, _extent(nr, nc, ld) if ok else 0, "X")
     pe = _dev(exps, rows if ok else 0, "exps", torch.int32)
     pq = _dev(slices, nslices * rows_p * ldq if ok else 0, "slices",
-              torch.int8 if algo == MPDD_OZAKI_I8 else torch.float64)
+              torch.float64 if algo == MPDD_OZAKI_F64 else torch.int8)
     return load().mpdd_ozaki_split(h, algo, _flag(trans), rows, k, px[0], px[1], ld, nslices,
                                    pe, pq, ldq, rows_p, _stream(stream))
 

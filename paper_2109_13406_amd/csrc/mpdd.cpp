@@ -17,6 +17,7 @@
 #include <new>
 
 #include "../../include/mpdd.h"
+#include "crt.hpp"
 #include "kernels.hpp"
 #include "tuner.hpp"
 
@@ -96,6 +97,10 @@ bool lsame(const char* s, char ref) {
 }
 
 bool is_zero(mpdd_dd x) { return x.hi == 0.0 && x.lo == 0.0; }
+// The split forms (slices or residues on the matrix cores).
+bool split_algo(int a) {
+  return a == MPDD_OZAKI_I8 || a == MPDD_OZAKI_F64 || a == MPDD_OZAKI_CRT;
+}
 bool is_one(mpdd_dd x) { return x.hi == 1.0 && x.lo == 0.0; }
 
 int check_gemm(const char* ta, const char* tb, mpdd_int m, mpdd_int n, mpdd_int k, mpdd_int lda,
@@ -283,23 +288,36 @@ int mpdd_ozaki_digit_widths(int algo, mpdd_int k, int nslices, int* wfirst, int*
   return ozaki_digit_widths(algo, k, nslices, wfirst, w);
 }
 
+int mpdd_ozaki_crt_exponent(mpdd_int k, int nmoduli, int* p) {
+  if (!p || k < 0 || nmoduli < 1 || nmoduli > CRT_MAX_MODULI) return MPDD_ERR_ARG;
+  if (k > CRT_MAX_K) return MPDD_ERR_UNSUPPORTED;
+  const int e = crt_exponent(k, nmoduli);
+  if (e == 0) return MPDD_ERR_UNSUPPORTED;
+  *p = e;
+  return 0;
+}
+
 int mpdd_ozaki_split(mpdd_handle h, int algo, const char* trans, mpdd_int rows, mpdd_int k,
                      const double* X_hi, const double* X_lo, mpdd_int ld, int nslices,
                      int* exps, void* slices, mpdd_int ldq, mpdd_int rows_p, void* stream) {
-  if (algo != MPDD_OZAKI_I8 && algo != MPDD_OZAKI_F64) return MPDD_ERR_ARG;
+  if (!split_algo(algo)) return MPDD_ERR_ARG;
   const bool nt = lsame(trans, 'N');
   if (!nt && !lsame(trans, 'T') && !lsame(trans, 'C')) return 2;
   if (rows < 0) return 3;
   if (k < 0) return 4;
   if (ld < std::max<mpdd_int>(1, nt ? rows : k)) return 8;
-  if (nslices < 1 || nslices > 40) return 9;
+  if (nslices < 1 || nslices > (algo == MPDD_OZAKI_CRT ? CRT_MAX_MODULI : 40)) return 9;
   if (ldq < k || ldq % 64 != 0 || ldq < 64) return 12;
   if (rows_p < rows || rows_p % 64 != 0 || rows_p < 64) return 13;
   if (!handle_ok(h)) return MPDD_ERR_HANDLE;
   if (rows == 0) return 0;
-  int wf, w;
-  const int e = ozaki_digit_widths(algo, k, nslices, &wf, &w);
-  if (e) return e;
+  int wf = 0, w = 0;
+  if (algo == MPDD_OZAKI_CRT) {
+    if (k > CRT_MAX_K || crt_exponent(k, nslices) == 0) return MPDD_ERR_UNSUPPORTED;
+  } else {
+    const int e = ozaki_digit_widths(algo, k, nslices, &wf, &w);
+    if (e) return e;
+  }
   if (!exps || !slices || (k > 0 && (!X_hi || !X_lo))) return MPDD_ERR_ARG;
   return ozaki_split_entry(algo, !nt, rows, k, X_hi, X_lo, ld, nslices, wf, w, exps, slices, ldq,
                            rows_p, (hipStream_t)stream, h->pool);
@@ -360,15 +378,13 @@ int mpdd_Rgemm_ex(mpdd_handle h, const mpdd_opts* opts, const char* transa, cons
   if (info) return info;
   if (!handle_ok(h)) return MPDD_ERR_HANDLE;
   const int algo = opts ? opts->algo : MPDD_PLAIN;
-  if (algo != MPDD_PLAIN && algo != MPDD_PLAIN_ACCURATE && algo != MPDD_OZAKI_I8 &&
-      algo != MPDD_OZAKI_F64)
-    return MPDD_ERR_ARG;
+  if (algo != MPDD_PLAIN && algo != MPDD_PLAIN_ACCURATE && !split_algo(algo)) return MPDD_ERR_ARG;
   if (m == 0 || n == 0 || ((is_zero(alpha) || k == 0) && is_one(beta))) return 0;
   if (!C_hi || !C_lo) return MPDD_ERR_ARG;
   if (!is_zero(alpha) && k > 0 && (!A_hi || !A_lo || !B_hi || !B_lo)) return MPDD_ERR_ARG;
   const bool ta = !lsame(transa, 'N'), tb = !lsame(transb, 'N');
   hipStream_t st = (hipStream_t)stream;
-  if (algo == MPDD_OZAKI_I8 || algo == MPDD_OZAKI_F64)
+  if (split_algo(algo))
     return ozaki_gemm(opts, 0, ta, tb, m, n, k, alpha.hi, alpha.lo, A_hi, A_lo, lda, B_hi, B_lo,
                       ldb, beta.hi, beta.lo, C_hi, C_lo, ldc, st, h->pool);
   return run_plain(h, opts, ta, tb, 0, m, n, k, alpha, A_hi, A_lo, lda, B_hi, B_lo, ldb, beta,
@@ -392,7 +408,7 @@ int mpdd_Rgemm_noalloc(mpdd_handle h, const mpdd_opts* opts, const char* transa,
   if (info) return info;
   if (!handle_ok(h)) return MPDD_ERR_HANDLE;
   const int algo = opts ? opts->algo : MPDD_PLAIN;
-  if (algo == MPDD_OZAKI_I8 || algo == MPDD_OZAKI_F64) return MPDD_ERR_UNSUPPORTED;
+  if (split_algo(algo)) return MPDD_ERR_UNSUPPORTED;
   if (algo != MPDD_PLAIN && algo != MPDD_PLAIN_ACCURATE) return MPDD_ERR_ARG;
   if (m == 0 || n == 0 || ((is_zero(alpha) || k == 0) && is_one(beta))) return 0;
   if (!C_hi || !C_lo) return MPDD_ERR_ARG;
@@ -412,9 +428,7 @@ int mpdd_Rsyrk_ex(mpdd_handle h, const mpdd_opts* opts, const char* uplo, const 
   if (info) return info;
   if (!handle_ok(h)) return MPDD_ERR_HANDLE;
   const int algo = opts ? opts->algo : MPDD_PLAIN;
-  if (algo != MPDD_PLAIN && algo != MPDD_PLAIN_ACCURATE && algo != MPDD_OZAKI_I8 &&
-      algo != MPDD_OZAKI_F64)
-    return MPDD_ERR_ARG;
+  if (algo != MPDD_PLAIN && algo != MPDD_PLAIN_ACCURATE && !split_algo(algo)) return MPDD_ERR_ARG;
   if (n == 0 || ((is_zero(alpha) || k == 0) && is_one(beta))) return 0;
   if (!C_hi || !C_lo) return MPDD_ERR_ARG;
   if (!is_zero(alpha) && k > 0 && (!A_hi || !A_lo)) return MPDD_ERR_ARG;
@@ -422,7 +436,7 @@ int mpdd_Rsyrk_ex(mpdd_handle h, const mpdd_opts* opts, const char* uplo, const 
   const bool ta = !lsame(trans, 'N');
   const bool tb = !ta;
   const int tri = lsame(uplo, 'U') ? 1 : 2;
-  if (algo == MPDD_OZAKI_I8 || algo == MPDD_OZAKI_F64)
+  if (split_algo(algo))
     return ozaki_gemm(opts, tri, ta, tb, n, n, k, alpha.hi, alpha.lo, A_hi, A_lo, lda, A_hi,
                       A_lo, lda, beta.hi, beta.lo, C_hi, C_lo, ldc, (hipStream_t)stream, h->pool);
   return run_plain(h, opts, ta, tb, tri, n, n, k, alpha, A_hi, A_lo, lda, A_hi, A_lo, lda, beta,
@@ -453,10 +467,8 @@ int mpdd_Cgemm_ex(mpdd_handle h, const mpdd_opts* opts, const char* transa, cons
   if (info) return info;
   if (!handle_ok(h)) return MPDD_ERR_HANDLE;
   const int algo = opts ? opts->algo : MPDD_PLAIN;
-  if (algo != MPDD_PLAIN && algo != MPDD_COMPLEX_3M && algo != MPDD_OZAKI_I8 &&
-      algo != MPDD_OZAKI_F64)
-    return MPDD_ERR_ARG;
-  const bool split = algo == MPDD_OZAKI_I8 || algo == MPDD_OZAKI_F64;
+  if (algo != MPDD_PLAIN && algo != MPDD_COMPLEX_3M && !split_algo(algo)) return MPDD_ERR_ARG;
+  const bool split = split_algo(algo);
   const bool alpha_zero = is_zero(alpha.re) && is_zero(alpha.im);
   const bool beta_zero = is_zero(beta.re) && is_zero(beta.im);
   const bool beta_one = is_one(beta.re) && is_zero(beta.im);
@@ -814,7 +826,7 @@ int mpdd_Rpotrf_ex(mpdd_handle h, const mpdd_opts* opts, const char* uplo, mpdd_
   if (lda < std::max<mpdd_int>(1, n)) { *info = -4; return 0; }
   if (!handle_ok(h)) return MPDD_ERR_HANDLE;
   const int algo = opts ? opts->algo : MPDD_PLAIN;
-  if (algo != MPDD_PLAIN && algo != MPDD_OZAKI_I8 && algo != MPDD_OZAKI_F64) return MPDD_ERR_ARG;
+  if (algo != MPDD_PLAIN && !split_algo(algo)) return MPDD_ERR_ARG;
   if (nb == 0) nb = 64;
   if (nb < 1 || nb > 64) return MPDD_ERR_UNSUPPORTED;
   if (n == 0) return 0;

@@ -29,6 +29,7 @@
 
 #include "../../include/mpdd.h"
 #include "dd.hpp"
+#include "crt.hpp"
 #include "kernels.hpp"
 #include "qd.hpp"
 
@@ -364,6 +365,36 @@ __device__ __forceinline__ void oz_tile_of(int b, int tri, int tiles_m, int tile
 
 // ---- products: INT8 ---------------------------------------------------------------------
 
+// Modular split form (oz_gemm_i8_dma with CRT): group g of workgroups
+// computes the single product of residue plane t = nslices - 1 - g of both
+// operands.  It is the anti-diagonal d = 2 of the planes offset by t, so the
+// kernel runs it unchanged up to the epilogue, which stores the product's
+// entries reduced to balanced residues modulo m_t as int8 (crt_store4) in
+// plane t of x.  Returns t.
+__device__ __forceinline__ int crt_product_of(int& d, const int8_t* __restrict__& qa,
+                                              const int8_t* __restrict__& qb, int64_t plane_a,
+                                              int64_t plane_b) {
+  const int t = d - 2;
+  qa += (int64_t)t * plane_a;
+  qb += (int64_t)t * plane_b;
+  d = 2;
+  return t;
+}
+
+// Four consecutive entries (rows i..i+3 of one column) of a residue product,
+// |X| < 2^31, reduced modulo m: X (1/m) is within 2^-29 of X/m, so rint gives
+// the nearest integer and X - q m (one exact fma) is the balanced residue (for
+// m = 256 possibly +128, whose byte is that of -128: the same class).  One
+// 4-byte store of the four int8 residues.
+__device__ __forceinline__ void crt_store4(int8_t* p, int v0, int v1, int v2, int v3, double m,
+                                           double minv) {
+  auto red = [&](int v) {
+    const double xv = (double)v;
+    return (uint32_t)(int)fma(-rint(xv * minv), m, xv) & 0xFFu;
+  };
+  *(uint32_t*)p = red(v0) | (red(v1) << 8) | (red(v2) << 16) | (red(v3) << 24);
+}
+
 // X_d tile (WM x WN) for anti-diagonal d: sum over t of Q_t(rows) Q'_{d-t}(cols)^T
 // with k-contiguous int8 rows.  GM x GN waves; each wave owns (WM/GM) x (WN/GN)
 // outputs = (WM/GM/16) x (WN/GN/16) v_mfma_i32_16x16x64_i8
@@ -520,11 +551,11 @@ __device__ __forceinline__ void i8_sync() {
   asm volatile("s_waitcnt vmcnt(%0) lgkmcnt(%1)\n\ts_barrier" ::"n"(VM), "n"(LGKM) : "memory");
 }
 
-template <int WM, int WN, int GM, int GN, int NS, bool PF, bool M32>
+template <int WM, int WN, int GM, int GN, int NS, bool PF, bool M32, bool CRT = false>
 __global__ void __launch_bounds__(64 * GM * GN, 1)
 oz_gemm_i8_dma(const int8_t* __restrict__ qa, const int8_t* __restrict__ qb,
                int32_t* __restrict__ x, int64_t kp, int64_t plane_a, int64_t plane_b, int64_t mp,
-               int64_t np, int nslices, int tiles_m, int tiles_n, int tri) {
+               int64_t np, int nslices, int tiles_m, int tiles_n, int tri, CrtModuli cm) {
   constexpr int NW = GM * GN;                  // waves
   constexpr int WR = WM / GM, WC = WN / GN;    // outputs per wave
   constexpr int MT = M32 ? 32 : 16;            // MFMA tile edge
@@ -542,6 +573,7 @@ oz_gemm_i8_dma(const int8_t* __restrict__ qa, const int8_t* __restrict__ qb,
 
   int d, bi, bj;
   oz_tile_of(blockIdx.x, tri, tiles_m, tiles_n, nslices, d, bi, bj);
+  const int ct = CRT ? crt_product_of(d, qa, qb, plane_a, plane_b) : -1;
   const int64_t i0 = (int64_t)bi * WM, j0 = (int64_t)bj * WN;
 
   typedef int v16i __attribute__((ext_vector_type(16)));
@@ -683,6 +715,29 @@ oz_gemm_i8_dma(const int8_t* __restrict__ qa, const int8_t* __restrict__ qb,
   // C layout: 16 x 16 tile, lane l holds rows 4 (l / 16) + 0..3 of column
   // l % 16; 32 x 32 tile, lane l holds rows 8 g + 4 (l / 32) + 0..3 of column
   // l % 32 in registers 4 g .. 4 g + 3
+  if constexpr (CRT) {
+    int8_t* xq = (int8_t*)x + (int64_t)ct * mp * np;
+    const double mm = cm.m[ct], mi = cm.minv[ct];
+#pragma unroll
+    for (int a = 0; a < FA; ++a)
+#pragma unroll
+      for (int c = 0; c < FB; ++c) {
+        const int64_t j = j0 + wn * WC + c * MT + (lane & (MT - 1));
+        if constexpr (M32) {
+#pragma unroll
+          for (int g = 0; g < 4; ++g) {
+            const int64_t i = i0 + wm * WR + a * MT + 8 * g + 4 * (lane >> 5);
+            crt_store4(xq + j * mp + i, acc[a][c][4 * g], acc[a][c][4 * g + 1],
+                       acc[a][c][4 * g + 2], acc[a][c][4 * g + 3], mm, mi);
+          }
+        } else {
+          const int64_t i = i0 + wm * WR + a * MT + (lane >> 4) * 4;
+          crt_store4(xq + j * mp + i, acc[a][c][0], acc[a][c][1], acc[a][c][2], acc[a][c][3],
+                     mm, mi);
+        }
+      }
+    return;
+  }
   int32_t* xd = x + (int64_t)(d - 2) * mp * np;
 #pragma unroll
   for (int a = 0; a < FA; ++a)
@@ -1019,6 +1074,199 @@ oz_combine_qd(const int32_t* __restrict__ x, int64_t mp, int64_t np, int nslices
   c3[ci] = o.w;
 }
 
+// ---- modular split form ------------------------------------------------------------
+
+// Residues of a row operand.  Element x of row r becomes the integer
+// x' = t1 + t2 on the grid of P bits below 2^sigma_r: z = x 2^(P - sigma_r)
+// (exact, zh + zl), t1 = rint(zh), t2 = rint((zh - t1) + zl), |x'| <= 2^P.
+// Plane t (0-based) receives x' modulo modulus t, balanced (odd m: in
+// [-(m-1)/2, (m-1)/2]; m = 256: the low byte), as int8 at
+// q + t*plane + r*ldq + l; padding rows and columns get 0.
+//
+// x' is handled in 26-bit chunks: t1 = u 2^52 + v (u = rint(t1 2^-52); v is
+// an integer with |v| <= 2^51, so the fma that forms it is exact),
+// w = v + t2 (exact: |w| < 2^53 while P <= 104), u = u1 2^26 + u0 and
+// w = w1 2^26 + w0 (|u0|, |w0| <= 2^25).  Then x' = u1 2^78 + u0 2^52 +
+// w1 2^26 + w0, and y = u1 c78 + u0 c52 + w1 c26 + w0 (c_j = 2^j mod m) is
+// congruent to x' and below 2^37 in magnitude, exact in binary64.  For odd m,
+// y/m lies at least 1/(2m) from a half-integer while y * (1/m) is within
+// 2^-23 of it, so q = rint(y * (1/m)) is the nearest integer and y - q m
+// (one exact fma) the balanced residue.  m = 256 is plane 0: the low byte of
+// w0 (w0 = x' modulo 2^26).
+//
+// Staging as in oz_slice (both planes of a 64 x 64 block through LDS, lanes
+// along the contiguous index); each thread then takes 4 consecutive l of
+// rows rq and rq + 32 and stores one 4-byte word per plane and row, so the
+// 16 threads of a row write its 64 residues of a plane in one piece.
+__global__ void __launch_bounds__(512, 2)
+oz_crt_residues(const double* __restrict__ xh, const double* __restrict__ xl, int64_t sr,
+                int64_t sl, int64_t rows, int64_t k, const int* __restrict__ exps, int count,
+                int p, CrtResidueConsts cst, int8_t* __restrict__ q, int64_t ldq,
+                int64_t plane) {
+  __shared__ double t[2][64][65];
+  const int tid = threadIdx.x;
+  const int64_t r0 = (int64_t)blockIdx.y * 64;
+  const int64_t l0 = (int64_t)blockIdx.x * 64;
+  const bool lanes_on_r = (sr == 1);
+  {
+    double v[2][8];
+#pragma unroll
+    for (int half = 0; half < 2; ++half) {
+      const double* __restrict__ src = half ? xl : xh;
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        const int a = tid & 63, b = (tid >> 6) + 8 * c;
+        const int ri = lanes_on_r ? a : b;
+        const int li = lanes_on_r ? b : a;
+        const int64_t rg = r0 + ri, lg = l0 + li;
+        v[half][c] = (rg < rows && lg < k) ? src[rg * sr + lg * sl] : 0.0;
+      }
+    }
+#pragma unroll
+    for (int half = 0; half < 2; ++half)
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        const int a = tid & 63, b = (tid >> 6) + 8 * c;
+        t[half][lanes_on_r ? a : b][lanes_on_r ? b : a] = v[half][c];
+      }
+  }
+  __syncthreads();
+  const int rq = tid >> 4, lq = (tid & 15) * 4;
+#pragma unroll
+  for (int g = 0; g < 2; ++g) {
+    const int row = rq + 32 * g;
+    const int sh = p - ((r0 + row < rows) ? exps[r0 + row] : 0);
+    double u1[4], u0[4], w1[4], w0[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const double zh = ldexp(t[0][row][lq + i], sh), zl = ldexp(t[1][row][lq + i], sh);
+      const double t1 = rint(zh);
+      const double t2 = rint((zh - t1) + zl);
+      const double u = rint(t1 * 0x1p-52);
+      const double w = fma(-u, 0x1p52, t1) + t2;
+      u1[i] = rint(u * 0x1p-26);
+      u0[i] = fma(-u1[i], 0x1p26, u);
+      w1[i] = rint(w * 0x1p-26);
+      w0[i] = fma(-w1[i], 0x1p26, w);
+    }
+    int8_t* o = q + (r0 + row) * ldq + l0 + lq;
+    {
+      uint32_t word = 0;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) word |= ((uint32_t)(int)w0[i] & 0xFFu) << (8 * i);
+      *(uint32_t*)o = word;
+    }
+#pragma unroll
+    for (int m = 1; m < CRT_MAX_MODULI; ++m) {
+      if (m >= count) break;
+      uint32_t word = 0;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const double y =
+            fma(u1[i], cst.c78[m], fma(u0[i], cst.c52[m], fma(w1[i], cst.c26[m], w0[i])));
+        const double qq = rint(y * cst.minv[m]);
+        const double r = fma(-qq, cst.m[m], y);
+        word |= ((uint32_t)(int)r & 0xFFu) << (8 * i);
+      }
+      *(uint32_t*)(o + (int64_t)m * plane) = word;
+    }
+  }
+}
+
+// Reconstruction: entry (i, j) from the balanced residues r_t of its
+// `count` per-modulus products (int8 planes, entry at plane t, [j*mp + i]).
+// S = sum_t r_t W_t is congruent to the product X modulo M, and
+// |S| <= 32 * 128 * M; it is accumulated exactly in L limbs of 39 bits
+// (S_l = sum_t r_t W_t,l, |S_l| < 2^51, exact in binary64).  q = rint(S / M)
+// (estimated as sum_l S_l g_l, error far below the 1/4 margin: |X| <= M/4)
+// is removed limb by limb (|q M_l| < 2^51: exact), which leaves the exact
+// integer product X = S - q M in limbs; carries bring every limb but the top
+// one into [-2^38, 2^38] (each step exact), and the limbs are added into a
+// dd from the lowest up (DWPlusFP: relative error about 2^-104 overall).
+// Finally X 2^(sigma_i + tau_j - 2P) and C = alpha X' + beta C, as in
+// oz_combine.  Four consecutive rows per thread (one 4-byte load per
+// modulus); a triangle (tri 1 upper, 2 lower) updates only its entries.
+template <int L>
+__global__ void __launch_bounds__(256)
+oz_crt_combine(const int8_t* __restrict__ x, int64_t mp, int64_t np, int count, int p,
+               CrtCombineConsts cst, const int* __restrict__ ea, const int* __restrict__ eb,
+               int64_t m, int64_t n, double alpha_hi, double alpha_lo, double beta_hi,
+               double beta_lo, int beta_zero, double* __restrict__ c_hi,
+               double* __restrict__ c_lo, int64_t ldc, int tri) {
+  constexpr int NB = 8;
+  const int64_t mq = (m + 3) / 4;
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= mq * n) return;
+  const int64_t i0 = (gid % mq) * 4, j = gid / mq;
+  const int64_t ilo = (tri == 2) ? j : 0, ihi = (tri == 1) ? j : m - 1;
+  if (i0 > ihi || i0 + 3 < ilo) return;
+  auto updated = [&](int64_t i) { return i < m && i >= ilo && i <= ihi; };
+  const int8_t* xp = x + j * mp + i0;
+  const int64_t plane = mp * np;
+  double ch[4] = {0.0, 0.0, 0.0, 0.0}, cl[4] = {0.0, 0.0, 0.0, 0.0};
+  if (!beta_zero) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      if (updated(i0 + r)) {
+        ch[r] = c_hi[i0 + r + j * ldc];
+        cl[r] = c_lo[i0 + r + j * ldc];
+      }
+  }
+  double s[4][L];
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int l = 0; l < L; ++l) s[r][l] = 0.0;
+#pragma unroll
+  for (int t0 = 0; t0 < CRT_MAX_MODULI; t0 += NB) {
+    if (t0 >= count) break;
+    uint32_t v[NB];
+#pragma unroll
+    for (int u = 0; u < NB; ++u)
+      v[u] = (t0 + u < count) ? *(const uint32_t*)(xp + (int64_t)(t0 + u) * plane) : 0u;
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+      const int tt = t0 + u;
+      if (tt >= count) break;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const double res = (double)(int)(int8_t)(v[u] >> (8 * r));
+#pragma unroll
+        for (int l = 0; l < L; ++l) s[r][l] = fma(res, cst.w[tt][l], s[r][l]);
+      }
+    }
+  }
+  const ddv alpha{alpha_hi, alpha_lo}, beta{beta_hi, beta_lo};
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int64_t i = i0 + r;
+    if (!updated(i)) continue;
+    double est = 0.0;
+#pragma unroll
+    for (int l = L - 1; l >= 0; --l) est = fma(s[r][l], cst.g[l], est);
+    const double qm = rint(est);
+    double xl[L];
+#pragma unroll
+    for (int l = 0; l < L; ++l) xl[l] = fma(-qm, cst.ml[l], s[r][l]);
+#pragma unroll
+    for (int l = 0; l + 1 < L; ++l) {
+      const double c = rint(xl[l] * 0x1p-39);
+      xl[l] = fma(-c, 0x1p39, xl[l]);
+      xl[l + 1] += c;
+    }
+    ddv acc{xl[0], 0.0};
+#pragma unroll
+    for (int l = 1; l < L; ++l) acc = dd_add_d(acc, ldexp(xl[l], CRT_LIMB_BITS * l));
+    const int e = ea[i] + eb[j] - 2 * p;
+    ddv pr{ldexp(acc.hi, e), ldexp(acc.lo, e)};
+    ddv res = dd_mul(alpha, pr);
+    const int64_t ci = i + j * ldc;
+    if (!beta_zero) res = dd_add(res, dd_mul(beta, ddv{ch[r], cl[r]}));
+    c_hi[ci] = res.hi;
+    c_lo[ci] = res.lo;
+  }
+}
+
 // ---- host orchestration -------------------------------------------------------------
 
 static int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
@@ -1085,18 +1333,124 @@ static int i8_tile_cols(int var) { return (var == 0 || var >= 3) ? 256 : 128; }
 static void launch_i8_products(int var, unsigned nblocks, const int8_t* qa, const int8_t* qb,
                                int32_t* x, int64_t kp, int64_t mp, int64_t np, int s, int tiles_m,
                                int tiles_n, int tri, hipStream_t st) {
+  if (var >= 5) {
+    auto kern = (var == 5)   ? oz_gemm_i8_dma<256, 256, 2, 4, 4, false, false>
+                : (var == 6) ? oz_gemm_i8_dma<256, 256, 2, 4, 4, true, false>
+                : (var == 7) ? oz_gemm_i8_dma<256, 256, 2, 2, 4, true, false>
+                             : oz_gemm_i8_dma<256, 256, 2, 4, 4, true, true>;
+    hipLaunchKernelGGL(kern, dim3(nblocks), dim3(var == 7 ? 256 : 512), 0, st, qa, qb, x, kp,
+                       mp * kp, np * kp, mp, np, s, tiles_m, tiles_n, tri, CrtModuli{});
+    return;
+  }
   auto kern = (var == 0)   ? oz_gemm_i8<256, 256, 2, 2>
               : (var == 1) ? oz_gemm_i8<256, 128, 2, 2>
               : (var == 2) ? oz_gemm_i8<128, 128, 2, 2>
               : (var == 3) ? oz_gemm_i8<256, 256, 2, 4>
-              : (var == 4) ? oz_gemm_i8<256, 256, 4, 4>
-              : (var == 5) ? oz_gemm_i8_dma<256, 256, 2, 4, 4, false, false>
-              : (var == 6) ? oz_gemm_i8_dma<256, 256, 2, 4, 4, true, false>
-              : (var == 7) ? oz_gemm_i8_dma<256, 256, 2, 2, 4, true, false>
-                           : oz_gemm_i8_dma<256, 256, 2, 4, 4, true, true>;
-  const unsigned nthreads = (var == 4) ? 1024 : (var >= 3 && var != 7) ? 512 : 256;
+                           : oz_gemm_i8<256, 256, 4, 4>;
+  const unsigned nthreads = (var == 4) ? 1024 : (var >= 3) ? 512 : 256;
   hipLaunchKernelGGL(kern, dim3(nblocks), dim3(nthreads), 0, st, qa, qb, x, kp, mp * kp, np * kp,
                      mp, np, s, tiles_m, tiles_n, tri);
+}
+
+// The residue products of the modular form: one group of workgroups per
+// modulus, entries reduced to int8 residues (variants 5, 6 and 8; 6 is the
+// default).
+static bool crt_variant(int var) { return var == 5 || var == 6 || var == 8; }
+
+static void launch_crt_products(int var, unsigned nblocks, const int8_t* qa, const int8_t* qb,
+                                int8_t* x, int64_t kp, int64_t mp, int64_t np, int count,
+                                int tiles_m, int tiles_n, int tri, const CrtModuli& cm,
+                                hipStream_t st) {
+  auto kern = (var == 5)   ? oz_gemm_i8_dma<256, 256, 2, 4, 4, false, false, true>
+              : (var == 6) ? oz_gemm_i8_dma<256, 256, 2, 4, 4, true, false, true>
+                           : oz_gemm_i8_dma<256, 256, 2, 4, 4, true, true, true>;
+  hipLaunchKernelGGL(kern, dim3(nblocks), dim3(512), 0, st, qa, qb, (int32_t*)x, kp, mp * kp,
+                     np * kp, mp, np, count, tiles_m, tiles_n, tri, cm);
+}
+
+// Residues of one row operand (scale exponents first).
+static hipError_t crt_operand(const double* hi, const double* lo, int64_t sr, int64_t sl,
+                              int64_t rows, int64_t k, int* exps, int8_t* q, int64_t ldq,
+                              int64_t rows_p, int count, int p, const CrtResidueConsts& rc,
+                              double* part, hipStream_t st) {
+  scale_operand(hi, sr, sl, rows, k, exps, part, st);
+  dim3 grid((unsigned)(ldq / 64), (unsigned)(rows_p / 64));
+  hipLaunchKernelGGL(oz_crt_residues, grid, dim3(512), 0, st, hi, lo, sr, sl, rows, k, exps,
+                     count, p, rc, q, ldq, rows_p * ldq);
+  return hipGetLastError();
+}
+
+static void launch_crt_combine(int limbs, const int8_t* x, int64_t mp, int64_t np, int count,
+                               int p, const CrtCombineConsts& cc, const int* ea, const int* eb,
+                               int64_t m, int64_t n, double alpha_hi, double alpha_lo,
+                               double beta_hi, double beta_lo, int beta_zero, double* c_hi,
+                               double* c_lo, int64_t ldc, int tri, hipStream_t st) {
+  auto kern = (limbs <= 1)   ? oz_crt_combine<1>
+              : (limbs == 2) ? oz_crt_combine<2>
+              : (limbs == 3) ? oz_crt_combine<3>
+              : (limbs == 4) ? oz_crt_combine<4>
+              : (limbs == 5) ? oz_crt_combine<5>
+              : (limbs == 6) ? oz_crt_combine<6>
+                             : oz_crt_combine<7>;
+  const unsigned cb = (unsigned)(((m + 3) / 4 * n + 255) / 256);
+  hipLaunchKernelGGL(kern, dim3(cb), dim3(256), 0, st, x, mp, np, count, p, cc, ea, eb, m, n,
+                     alpha_hi, alpha_lo, beta_hi, beta_lo, beta_zero, c_hi, c_lo, ldc, tri);
+}
+
+// Modular split form (MPDD_OZAKI_CRT): residues of op(A) and op(B) (a
+// triangle: op(A)'s serve both), one INT8 product per modulus, reconstruction.
+// alpha = 0 and k = 0 are the caller's.
+static int ozaki_crt_gemm(const mpdd_opts* opts, int tri, bool ta, bool tb, int64_t m,
+                          int64_t n, int64_t k, double alpha_hi, double alpha_lo,
+                          const double* a_hi, const double* a_lo, int64_t lda,
+                          const double* b_hi, const double* b_lo, int64_t ldb, double beta_hi,
+                          double beta_lo, double* c_hi, double* c_lo, int64_t ldc,
+                          hipStream_t st, hipMemPool_t pool) {
+  const int count = opts->nslices ? opts->nslices : crt_default_count(k);
+  if (count < 1 || count > CRT_MAX_MODULI || k > CRT_MAX_K) return MPDD_ERR_UNSUPPORTED;
+  const int p = crt_exponent(k, count);
+  if (p == 0) return MPDD_ERR_UNSUPPORTED;
+  const int var = opts->tile_id >= 0 ? opts->tile_id : 6;
+  if (!crt_variant(var)) return MPDD_ERR_UNSUPPORTED;
+  CrtResidueConsts rc;
+  CrtModuli cm;
+  CrtCombineConsts cc;
+  const int limbs = crt_constants(count, &rc, &cm, &cc);
+  const bool beta_zero = beta_hi == 0.0 && beta_lo == 0.0;
+  const int64_t kp = round_up(k, 2 * I8_BK);
+  const int64_t mp = round_up(m, I8_PAD), np = round_up(n, I8_PAD);
+  const size_t qa_bytes = (size_t)count * mp * kp;
+  const size_t qb_bytes = tri ? 0 : (size_t)count * np * kp;
+  const size_t x_bytes = (size_t)count * mp * np;   // int8 residues of the products
+  const size_t e_bytes = round_up((m + n) * sizeof(int), 256);
+  const size_t p_bytes = std::max(part_bytes(m, k), part_bytes(n, k));
+  void* ws = nullptr;
+  if (hipMallocFromPoolAsync(&ws, round_up(qa_bytes, 256) + round_up(qb_bytes, 256) + x_bytes +
+                                      e_bytes + p_bytes,
+                             pool, st) != hipSuccess)
+    return MPDD_ERR_ALLOC;
+  int8_t* qa = (int8_t*)ws;
+  int8_t* qb = tri ? qa : qa + round_up(qa_bytes, 256);
+  int8_t* x = (int8_t*)ws + round_up(qa_bytes, 256) + round_up(qb_bytes, 256);
+  int* ea = (int*)((char*)x + x_bytes);
+  int* eb = tri ? ea : ea + m;
+  double* part = (double*)((char*)ea + e_bytes);
+  const int64_t a_sr = ta ? lda : 1, a_sl = ta ? 1 : lda;
+  const int64_t b_sr = tb ? 1 : ldb, b_sl = tb ? ldb : 1;
+  hipError_t e = crt_operand(a_hi, a_lo, a_sr, a_sl, m, k, ea, qa, kp, mp, count, p, rc, part, st);
+  if (e == hipSuccess && !tri)
+    e = crt_operand(b_hi, b_lo, b_sr, b_sl, n, k, eb, qb, kp, np, count, p, rc, part, st);
+  if (e == hipSuccess) {
+    const int tiles_m = (int)(mp / i8_tile_rows(var)), tiles_n = (int)(np / i8_tile_cols(var));
+    launch_crt_products(var, (unsigned)(oz_group_tiles(tri, tiles_m, tiles_n) * count), qa, qb,
+                        x, kp, mp, np, count, tiles_m, tiles_n, tri, cm, st);
+    launch_crt_combine(limbs, x, mp, np, count, p, cc, ea, eb, m, n, alpha_hi, alpha_lo, beta_hi,
+                       beta_lo, (int)beta_zero, c_hi, c_lo, ldc, tri, st);
+    e = hipGetLastError();
+  }
+  const hipError_t ef = hipFreeAsync(ws, st);
+  if (e != hipSuccess || ef != hipSuccess) return MPDD_ERR_HIP;
+  return 0;
 }
 
 int ozaki_gemm(const void* opts_v, int tri, bool ta, bool tb, int64_t m, int64_t n, int64_t k,
@@ -1116,6 +1470,9 @@ int ozaki_gemm(const void* opts_v, int tri, bool ta, bool tb, int64_t m, int64_t
     p.tri = tri;
     return launch_scale(p, st) == hipSuccess ? 0 : MPDD_ERR_HIP;
   }
+  if (algo == MPDD_OZAKI_CRT)
+    return ozaki_crt_gemm(opts, tri, ta, tb, m, n, k, alpha_hi, alpha_lo, a_hi, a_lo, lda, b_hi,
+                          b_lo, ldb, beta_hi, beta_lo, c_hi, c_lo, ldc, st, pool);
   int s = opts->nslices;
   if (s == 0) s = (algo == MPDD_OZAKI_I8) ? 16 : 7;
   if (s < 1 || s > 40) return MPDD_ERR_UNSUPPORTED;
@@ -1272,7 +1629,15 @@ int ozaki_split_entry(int algo, bool trans, int64_t rows, int64_t k, const doubl
   if (hipMallocFromPoolAsync(&part, part_bytes(rows, k), pool, st) != hipSuccess)
     return MPDD_ERR_ALLOC;
   hipError_t e;
-  if (algo == MPDD_OZAKI_I8)
+  if (algo == MPDD_OZAKI_CRT) {
+    // residues: nslices moduli, the grid of crt_exponent (checked by the caller)
+    CrtResidueConsts rc;
+    CrtModuli cm;
+    CrtCombineConsts cc;
+    crt_constants(nslices, &rc, &cm, &cc);
+    e = crt_operand(hi, lo, sr, sl, rows, k, exps, (int8_t*)slices, ldq, rows_p, nslices,
+                    crt_exponent(k, nslices), rc, (double*)part, st);
+  } else if (algo == MPDD_OZAKI_I8)
     e = split_operand<int8_t>(hi, lo, sr, sl, rows, k, exps, (int8_t*)slices, ldq, rows_p,
                               nslices, wfirst, w, (double*)part, st);
   else

@@ -123,6 +123,10 @@ def check_reconstruct(crt):
             prods = [x % m + m * rnd.randrange(-1000, 1000) for m in ms]
             assert crt.reconstruct(prods, count) == x
         assert crt.reconstruct([0] * count, count) == 0
+        # arrays: elementwise, the same values
+        xs = [rnd.randrange(-(M // 4), M // 4) for _ in range(6)]
+        arr = [np.array([x % m for x in xs], dtype=np.int64) for m in ms]
+        assert list(crt.reconstruct(arr, count)) == xs
 
 
 def check_integer_product(crt, rng):
@@ -233,12 +237,11 @@ MUTANTS = [
     ("t2 = np.rint((zh - t1) + zl)", "t2 = np.rint(zh - t1)", "low part dropped"),
     ("sh = (p - exps).astype(np.int64)[:, None]", "sh = (p + exps).astype(np.int64)[:, None]",
      "scale sign"),
-    ("return r - m if r >= m // 2 else r", "return r - m if r > m // 2 else r",
+    ("top = (m - 1) // 2 if m % 2 else m // 2 - 1", "top = (m - 1) // 2 if m % 2 else m // 2",
      "residue 128 out of int8"),
-    ("x += int(r) * Mt * pow(Mt, -1, m)", "x += int(r) * Mt",
+    ("x = x + r * (Mt * pow(Mt, -1, m))", "x = x + r * Mt",
      "weights without the inverse"),
-    ("return x - M if x >= (M + 1) // 2 else x", "return x",
-     "reconstruction not balanced"),
+    ("half = (M + 1) // 2", "half = M + 1", "reconstruction not balanced"),
     ("bt = \"T\" if transb.upper() == \"N\" else \"N\"", "bt = transb.upper()",
      "op(B) transposed"),
     ("v = a * X[i, j] * Fraction(2) ** int(ea[i] + eb[j] - 2 * p)",
