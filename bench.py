@@ -29,6 +29,8 @@ HBM_PEAK_GBS = 8000.0
 INT8_PEAK_TOPS = 5000.0          # dense INT8 matrix peak, ops/s (MAC = 2 ops)
 OPS_PER_MADD_ALG = 20            # FP64 issue slots per dd multiply-add (the dd roofline unit)
 RATIO_MAX = 8.0                  # normwise parity bound, units of k * 2^-104
+CRT_MODULI = 26                  # modular split form in Cgemm / Rpotrf (the count
+                                 # the Rgemm search needs at 8192^3 on the wide set)
 # sources whose code or build flags shape the plain kernel: a counter record
 # taken on other sources is not used
 KERNEL_SOURCES = ["paper_2109_13406_amd/csrc/gemm_plain.hip", "paper_2109_13406_amd/csrc/dd.hpp",
@@ -410,19 +412,22 @@ def bench_syrk(h, args, stream):
                 log(f"rsyrk {rec}")
                 del case
                 torch.cuda.empty_cache()
-    out["split_i8"] = bench_syrk_split(h, args, stream, out.get("ms"))
+    out["split_i8"] = bench_syrk_split(h, args, stream, out.get("ms"), "i8")
+    out["split_crt"] = bench_syrk_split(h, args, stream, out.get("ms"), "crt")
     return out
 
 
-def bench_syrk_split(h, args, stream, plain_ms):
+def bench_syrk_split(h, args, stream, plain_ms, kind):
     """The headline Rsyrk shape (U N, n = k = args.n, config-2 inputs) in the
-    INT8 split form: the slice count is searched upward until the sampled
-    entries of the triangle are within 8 k 2^-104 of the CPU oracle (the
-    plain dd evaluation), then that call is timed.  Slice products per
-    anti-diagonal only for the tiles that meet the triangle."""
+    INT8 split form (kind "i8") or the modular one ("crt"): the slice (moduli)
+    count is searched upward until the sampled entries of the triangle are
+    within 8 k 2^-104 of the CPU oracle (the plain dd evaluation), then that
+    call is timed.  Products only for the tiles that meet the triangle."""
     import torch
     import workloads as W
     from paper_2109_13406_amd import binding as b
+    algo, counts, name = {"i8": (b.MPDD_OZAKI_I8, range(10, 25), "INT8 split form"),
+                          "crt": (b.MPDD_OZAKI_CRT, range(22, 33), "modular split form")}[kind]
     n = k = args.n
     case = W.syrk_case_device(W.BASE_SEED + 2, "U", "N", n, k)
     C0 = tuple(x.clone() for x in case["C"])
@@ -434,11 +439,10 @@ def bench_syrk_split(h, args, stream, plain_ms):
     args_ = ("U", "N", n, k, case["alpha"], case["A"], case["lda"], case["beta"], case["C"],
              case["ldc"])
     found = None
-    for sl in range(10, 25):
+    for sl in counts:
         for dst, src in zip(case["C"], C0):
             dst.copy_(src)
-        if b.mpdd_Rsyrk_ex(h, dict(algo=b.MPDD_OZAKI_I8, nslices=sl), *args_,
-                           stream=stream) != 0:
+        if b.mpdd_Rsyrk_ex(h, dict(algo=algo, nslices=sl), *args_, stream=stream) != 0:
             break
         r, c = oracle_compare(smp, case["C"])
         if r <= RATIO_MAX:
@@ -449,18 +453,18 @@ def bench_syrk_split(h, args, stream, plain_ms):
     sl, r, c = found
 
     def step():
-        if b.mpdd_Rsyrk_ex(h, dict(algo=b.MPDD_OZAKI_I8, nslices=sl), *args_, stream=stream):
+        if b.mpdd_Rsyrk_ex(h, dict(algo=algo, nslices=sl), *args_, stream=stream):
             raise RuntimeError("split-form Rsyrk failed")
     _, per = timed_calls(step, 3, 1, stream)
     t = sum(per) / len(per)
-    rec = {"workload": f"Rsyrk U N n={n} k={k} ld={W.ld_padded(n)}, INT8 split form",
+    rec = {"workload": f"Rsyrk U N n={n} k={k} ld={W.ld_padded(n)}, {name}",
            "nslices": sl, "ratio_vs_oracle": round(r, 4), "componentwise_vs_oracle": round(c, 2),
            "oracle_sample": len(smp["flat"]), "ms": round(t * 1e3, 2),
            "dd_gflops": round(float(n) * (n + 1) * k / t / 1e9, 1)}
     if plain_ms:
         rec["plain_ms"] = plain_ms
         rec["speedup_vs_plain"] = round(plain_ms / (t * 1e3), 3)
-    log(f"rsyrk split {rec}")
+    log(f"rsyrk split {kind} {rec}")
     del case, C0
     torch.cuda.empty_cache()
     return rec
@@ -479,7 +483,8 @@ def bench_cgemm(h, args, stream):
     out = {"workload": f"Cgemm NN m=n=k={n} ld={W.ld_padded(n)} (four real dd planes each)"}
     C0 = tuple(x.clone() for x in case["C"])
     for form, opts in (("4m", None), ("3m", dict(algo=b.MPDD_COMPLEX_3M)),
-                       ("split_i8", dict(algo=b.MPDD_OZAKI_I8, nslices=12))):
+                       ("split_i8", dict(algo=b.MPDD_OZAKI_I8, nslices=12)),
+                       ("split_crt", dict(algo=b.MPDD_OZAKI_CRT, nslices=CRT_MODULI))):
         # one call from the saved C, checked against the CPU oracle on 32 x 32
         # sampled entries, then the timed calls
         for dst, src in zip(case["C"], C0):
@@ -503,6 +508,7 @@ def bench_cgemm(h, args, stream):
         out[f"ms_{form}"] = round(t * 1e3, 3)
         out[f"complex_dd_gflops_{form}"] = round(8.0 * n ** 3 / t / 1e9, 1)
     out["nslices_split_i8"] = 12
+    out["moduli_split_crt"] = CRT_MODULI
     out["oracle_sample"] = "32 x 32 entries; ratio over their real and imaginary parts, units of k 2^-104"
     log(f"cgemm {out}")
     del case, C0
@@ -569,8 +575,8 @@ def potrf_residual_sample(A0, F, n, ld, count, seed):
 
 def bench_potrf(h, args, stream):
     """Blocked dd Cholesky Rpotrf L at n (synchronous call), in the plain
-    form (left-looking, look-ahead) and with split-form (INT8, 12 slices)
-    trailing updates over 1024-column panels; each factor's sampled backward
+    form (left-looking, look-ahead) and with split-form (INT8, 12 slices;
+    modular, CRT_MODULI moduli) trailing updates over 1024-column panels; each factor's sampled backward
     error (potrf_residual_sample) is reported.  dd-flops n^3/3 (LAWN 41,
     leading term)."""
     import torch
@@ -610,6 +616,13 @@ def bench_potrf(h, args, stream):
                        "ms": round(ts * 1e3, 3), "dd_gflops": round(float(n) ** 3 / 3.0 / ts / 1e9, 1),
                        "speedup_vs_plain": round(t / ts, 3),
                        "residual_sampled_worst": round(rs, 5)}
+    tc, rc_ = run(dict(algo=b.MPDD_OZAKI_CRT, nslices=CRT_MODULI))
+    out["split_crt"] = {"form": "as split_i8 with the modular split form "
+                                f"({CRT_MODULI} moduli)", "moduli": CRT_MODULI,
+                        "ms": round(tc * 1e3, 3),
+                        "dd_gflops": round(float(n) ** 3 / 3.0 / tc / 1e9, 1),
+                        "speedup_vs_plain": round(t / tc, 3),
+                        "residual_sampled_worst": round(rc_, 5)}
     log(f"rpotrf {out}")
     del case, A0
     torch.cuda.empty_cache()
@@ -737,8 +750,10 @@ def bench_ozaki(h, args, stream, t_plain_main):
     import workloads as W
     from paper_2109_13406_amd import binding as b
     out = {}
-    kinds = (("i8", b.MPDD_OZAKI_I8, range(10, 25)), ("f64", b.MPDD_OZAKI_F64, range(3, 11)),
-             ("crt", b.MPDD_OZAKI_CRT, range(22, 33)))
+    kinds = tuple(kd for kd in (("i8", b.MPDD_OZAKI_I8, range(10, 25)),
+                                ("f64", b.MPDD_OZAKI_F64, range(3, 11)),
+                                ("crt", b.MPDD_OZAKI_CRT, range(22, 33)))
+                  if kd[0] in args.ozaki_kinds.split(","))
     for n in sorted({2048, args.n}):
         for dist in ("uniform", "wide"):
             case = W.gemm_case_device(W.BASE_SEED + 3, "N", "N", n, n, n, dist=dist)
@@ -917,6 +932,8 @@ def main():
     ap.add_argument("--no-oracle", action="store_true",
                     help="skip the oracle check of the headline product (profiling runs)")
     ap.add_argument("--sections", default="plain,sizes,syrk,cgemm,potrf,qd,ozaki,host,serve")
+    ap.add_argument("--ozaki-kinds", default="i8,f64,crt",
+                    help="split forms of the ozaki section (i8, f64, crt)")
     ap.add_argument("--tile", type=int, default=-1,
                     help="tile-table entry for the plain product (-1: the library's choice)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",

@@ -200,8 +200,9 @@ int mpdd_Rgemm_noalloc(mpdd_handle h, const mpdd_opts *opts, const char *transa,
                        double *C_hi, double *C_lo, mpdd_int ldc, void *stream);
 
 /* As mpdd_Rsyrk with explicit options.  The split forms (MPDD_OZAKI_I8 /
- * MPDD_OZAKI_F64, see the split-form building blocks below) slice op(A) once
- * and use its slices and row exponents for op(B) = op(A)^T as well, compute
+ * MPDD_OZAKI_F64 / MPDD_OZAKI_CRT, see the split-form building blocks below)
+ * slice op(A) once (the modular form: its residues) and use its slices and
+ * row exponents for op(B) = op(A)^T as well, compute
  * only the slice products of the tiles that meet the uplo triangle, and
  * read and write only that triangle of C; their result is that of the
  * split-form mpdd_Rgemm_ex of op(A) and op(A)^T, on the triangle.  INT8
@@ -243,8 +244,8 @@ int mpdd_Cgemm(mpdd_handle h, const char *transa, const char *transb, mpdd_int m
  * Re P = R1 - R2, Im P = R3 - R1 - R2; a quarter less arithmetic, with the
  * error of Im P relative to |Ar + Ai| |Br + Bi|; extra scratch
  * 16 (m k + k n) bytes); tile_id / splitk choose the real products' tiling as
- * in mpdd_Rgemm_ex.  MPDD_OZAKI_I8 / MPDD_OZAKI_F64: the four real products
- * of MPDD_PLAIN, each a split-form product (opts->nslices, tile_id as in
+ * in mpdd_Rgemm_ex.  MPDD_OZAKI_I8 / MPDD_OZAKI_F64 / MPDD_OZAKI_CRT: the four
+ * real products of MPDD_PLAIN, each a split-form product (opts->nslices, tile_id as in
  * mpdd_Rgemm_ex), then the same complex epilogue.  MPDD_ERR_ARG for another
  * algo. */
 int mpdd_Cgemm_ex(mpdd_handle h, const mpdd_opts *opts, const char *transa, const char *transb,
@@ -329,11 +330,13 @@ int mpdd_Rpotrf_nb(mpdd_handle h, const char *uplo, mpdd_int n, double *A_hi, do
                    mpdd_int lda, mpdd_int nb, mpdd_int *info, void *stream);
 
 /* As mpdd_Rpotrf_nb with options (opts may be NULL = MPDD_PLAIN, the form
- * above).  opts->algo MPDD_OZAKI_I8 / MPDD_OZAKI_F64: right-looking over
+ * above).  opts->algo MPDD_OZAKI_I8 / MPDD_OZAKI_F64 / MPDD_OZAKI_CRT:
+ * right-looking over
  * panels of 1024 columns (rounded down to whole blocks) -- each panel is factored
  * as above inside the trailing matrix, then the rest of the trailing matrix
  * takes the panel's update in one split-form mpdd_Rsyrk_ex with
- * opts->nslices slices (lower: A22 -= L21 L21^T; upper: A22 -= U12^T U12);
+ * opts->nslices slices or moduli (lower: A22 -= L21 L21^T; upper:
+ * A22 -= U12^T U12);
  * the panels are enqueued without host round trips and the failure word is
  * read once, at the end.  Same arguments, info and synchronisation as
  * mpdd_Rpotrf; MPDD_ERR_ARG for any other algo; errors of a trailing update

@@ -122,12 +122,13 @@ def test_worked_example(h):
 SHAPES = [(1, 1, 1), (97, 131, 77), (65, 1, 300), (130, 70, 33), (200, 190, 1)]
 
 
-@pytest.mark.parametrize("form", ["4M", "3M", "split"])
+@pytest.mark.parametrize("form", ["4M", "3M", "split", "crt"])
 @pytest.mark.parametrize("op", W.COPS, ids=[a + b for a, b in W.COPS])
 def test_cgemm_ragged(h, op, form):
     from paper_2109_13406_amd import binding as b
     opts = {"4M": None, "3M": dict(algo=b.MPDD_COMPLEX_3M),
-            "split": dict(algo=b.MPDD_OZAKI_I8, nslices=22)}[form]
+            "split": dict(algo=b.MPDD_OZAKI_I8, nslices=22),
+            "crt": dict(algo=b.MPDD_OZAKI_CRT, nslices=30)}[form]
     for (m, n, k) in SHAPES:
         for dist in ("uniform", "wide"):
             c = W.cgemm_case(4000 + m + k, op[0], op[1], m, n, k, dist=dist)
@@ -233,13 +234,15 @@ def test_cgemm_2048_sampled(h):
 def test_cgemm_4096_sampled(h):
     """The benchmarked size and inputs (4096^3 NN, device-generated operands;
     the four- and the three-product form, and the four products in the INT8
-    split form with the benchmark's 12 slices) on 32 x 32 sampled entries:
+    split form with the benchmark's 12 slices and in the modular form with
+    its 26 moduli) on 32 x 32 sampled entries:
     the oracle runs on the gathered rows of op(A) and columns of op(B)."""
     import torch
     from paper_2109_13406_amd import binding as b
     n = 4096
     for form, opts in (("4M", None), ("3M", dict(algo=b.MPDD_COMPLEX_3M)),
-                       ("split", dict(algo=b.MPDD_OZAKI_I8, nslices=12))):
+                       ("split", dict(algo=b.MPDD_OZAKI_I8, nslices=12)),
+                       ("crt", dict(algo=b.MPDD_OZAKI_CRT, nslices=26))):
         c = W.cgemm_case_device(W.BASE_SEED + 5, "N", "N", n, n, n)
         rng = np.random.default_rng(11)
         I = np.sort(rng.choice(n, 32, replace=False))

@@ -62,6 +62,7 @@ def run_gpu(h, c, nb=0, opts=None):
 
 # right-looking form with split-form (INT8, 12 slices) trailing updates
 SPLIT = dict(algo=1, nslices=12)
+CRT = dict(algo=5, nslices=26)      # modular split form, the benchmark's 26 moduli
 
 
 def run_oracle(c):
@@ -97,12 +98,13 @@ def test_potrf_vs_oracle(h, uplo, n):
 @pytest.mark.parametrize("n,nb", [(65, 0), (1100, 0), (1100, 32), (2100, 48)])
 def test_potrf_split_updates_vs_oracle(h, uplo, n, nb):
     """Right-looking Rpotrf over 1024-column panels whose trailing updates
-    are split-form Rsyrk calls (INT8 with 12 slices, FP64 with 5): the
+    are split-form Rsyrk calls (INT8 with 12 slices, FP64 with 5, modular
+    with 26 moduli): the
     factor within 8 n 2^-104 of the oracle's, the residual within LAPACK's
     threshold (formed by the oracle up to n = 1100), nothing outside the
     triangle touched; n = 1100 takes two panels (the last ragged), n = 2100
     three, n = 65 one."""
-    for opts in (SPLIT, dict(algo=2, nslices=5)):
+    for opts in (SPLIT, dict(algo=2, nslices=5), CRT):
         c = W.spd_case(5500 + n, n, uplo)
         io, O = run_oracle(c)
         ig, G = run_gpu(h, c, nb=nb, opts=opts)
@@ -177,7 +179,7 @@ def test_potrf_1024(h, uplo):
     assert r <= 8.0
 
 
-@pytest.mark.parametrize("form", ["plain", "split"])
+@pytest.mark.parametrize("form", ["plain", "split", "crt"])
 @pytest.mark.parametrize("uplo", "LU")
 def test_potrf_8192_sampled(h, uplo, form):
     """The benchmarked size (n = 8192, ld = 8195), checked where the oracle can
@@ -212,7 +214,8 @@ def test_potrf_8192_sampled(h, uplo, form):
     A_ij = [(float(A0[0][i, j]), float(A0[1][i, j])) for i, j in zip(ii, jj)]
     diag = A0[0].diagonal().cpu().numpy().copy()
 
-    rc, info = b.mpdd_Rpotrf(h, uplo, n, c["A"], ld, opts=SPLIT if form == "split" else None)
+    rc, info = b.mpdd_Rpotrf(h, uplo, n, c["A"], ld,
+                             opts={"plain": None, "split": SPLIT, "crt": CRT}[form])
     torch.cuda.synchronize()
     assert rc == 0 and info == 0
     L = lower_view(c["A"])
