@@ -1094,30 +1094,39 @@ oz_combine_qd(const int32_t* __restrict__ x, int64_t mp, int64_t np, int nslices
 // (one exact fma) the balanced residue.  m = 256 is plane 0: the low byte of
 // w0 (w0 = x' modulo 2^26).
 //
-// Staging as in oz_slice (both planes of a 64 x 64 block through LDS, lanes
-// along the contiguous index); each thread then takes 4 consecutive l of
-// rows rq and rq + 32 and stores one 4-byte word per plane and row, so the
-// 16 threads of a row write its 64 residues of a plane in one piece.
+// A workgroup takes a block of 32 rows x 128 l: both planes are loaded with
+// lanes along the contiguous index and staged in LDS (74 KB: two workgroups
+// per CU); each thread then converts 8 consecutive l of one row and stores
+// one 8-byte word per modulus, so the 16 threads of a row write its 128
+// residues of a plane as one 128-byte line.  Columns l >= ldq (ldq is a
+// multiple of 64) are neither stored nor, beyond k, read.
 __global__ void __launch_bounds__(512, 2)
 oz_crt_residues(const double* __restrict__ xh, const double* __restrict__ xl, int64_t sr,
                 int64_t sl, int64_t rows, int64_t k, const int* __restrict__ exps, int count,
                 int p, CrtResidueConsts cst, int8_t* __restrict__ q, int64_t ldq,
                 int64_t plane) {
-  __shared__ double t[2][64][65];
+  // element l of a staged row sits at column l + l/8 (one padding double
+  // every 8), so the 16 threads of a row, reading 8 consecutive elements each,
+  // hit distinct banks; the odd row pitch staggers the rows
+  constexpr int PITCH = 145;
+  __shared__ double t[2][32][PITCH];
+  auto col = [](int l) { return l + (l >> 3); };
   const int tid = threadIdx.x;
-  const int64_t r0 = (int64_t)blockIdx.y * 64;
-  const int64_t l0 = (int64_t)blockIdx.x * 64;
+  const int64_t r0 = (int64_t)blockIdx.y * 32;
+  const int64_t l0 = (int64_t)blockIdx.x * 128;
   const bool lanes_on_r = (sr == 1);
   {
+    // entry e of the block: lanes on r, 32 consecutive rows per half-wave;
+    // else 64 consecutive l of one row per wave
     double v[2][8];
 #pragma unroll
     for (int half = 0; half < 2; ++half) {
       const double* __restrict__ src = half ? xl : xh;
 #pragma unroll
       for (int c = 0; c < 8; ++c) {
-        const int a = tid & 63, b = (tid >> 6) + 8 * c;
-        const int ri = lanes_on_r ? a : b;
-        const int li = lanes_on_r ? b : a;
+        const int e = tid + 512 * c;             // 0 .. 4095 over the 32 x 128 block
+        const int ri = lanes_on_r ? (e & 31) : (e >> 7);
+        const int li = lanes_on_r ? (e >> 5) : (e & 127);
         const int64_t rg = r0 + ri, lg = l0 + li;
         v[half][c] = (rg < rows && lg < k) ? src[rg * sr + lg * sl] : 0.0;
       }
@@ -1126,50 +1135,53 @@ oz_crt_residues(const double* __restrict__ xh, const double* __restrict__ xl, in
     for (int half = 0; half < 2; ++half)
 #pragma unroll
       for (int c = 0; c < 8; ++c) {
-        const int a = tid & 63, b = (tid >> 6) + 8 * c;
-        t[half][lanes_on_r ? a : b][lanes_on_r ? b : a] = v[half][c];
+        const int e = tid + 512 * c;
+        const int ri = lanes_on_r ? (e & 31) : (e >> 7);
+        const int li = lanes_on_r ? (e >> 5) : (e & 127);
+        t[half][ri][col(li)] = v[half][c];
       }
   }
   __syncthreads();
-  const int rq = tid >> 4, lq = (tid & 15) * 4;
+  const int row = tid >> 4, lq = (tid & 15) * 8;
+  if (l0 + lq >= ldq) return;
+  const int sh = p - ((r0 + row < rows) ? exps[r0 + row] : 0);
+  double u1[8], u0[8], w1[8], w0[8];
 #pragma unroll
-  for (int g = 0; g < 2; ++g) {
-    const int row = rq + 32 * g;
-    const int sh = p - ((r0 + row < rows) ? exps[r0 + row] : 0);
-    double u1[4], u0[4], w1[4], w0[4];
+  for (int i = 0; i < 8; ++i) {
+    const int c = col(lq) + i;                 // lq is a multiple of 8
+    const double zh = ldexp(t[0][row][c], sh), zl = ldexp(t[1][row][c], sh);
+    const double t1 = rint(zh);
+    const double t2 = rint((zh - t1) + zl);
+    const double u = rint(t1 * 0x1p-52);
+    const double w = fma(-u, 0x1p52, t1) + t2;
+    u1[i] = rint(u * 0x1p-26);
+    u0[i] = fma(-u1[i], 0x1p26, u);
+    w1[i] = rint(w * 0x1p-26);
+    w0[i] = fma(-w1[i], 0x1p26, w);
+  }
+  int8_t* o = q + (r0 + row) * ldq + l0 + lq;
+  {
+    uint32_t lo = 0, hi = 0;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const double zh = ldexp(t[0][row][lq + i], sh), zl = ldexp(t[1][row][lq + i], sh);
-      const double t1 = rint(zh);
-      const double t2 = rint((zh - t1) + zl);
-      const double u = rint(t1 * 0x1p-52);
-      const double w = fma(-u, 0x1p52, t1) + t2;
-      u1[i] = rint(u * 0x1p-26);
-      u0[i] = fma(-u1[i], 0x1p26, u);
-      w1[i] = rint(w * 0x1p-26);
-      w0[i] = fma(-w1[i], 0x1p26, w);
+      lo |= ((uint32_t)(int)w0[i] & 0xFFu) << (8 * i);
+      hi |= ((uint32_t)(int)w0[i + 4] & 0xFFu) << (8 * i);
     }
-    int8_t* o = q + (r0 + row) * ldq + l0 + lq;
-    {
-      uint32_t word = 0;
+    *(uint2*)o = uint2{lo, hi};
+  }
 #pragma unroll
-      for (int i = 0; i < 4; ++i) word |= ((uint32_t)(int)w0[i] & 0xFFu) << (8 * i);
-      *(uint32_t*)o = word;
+  for (int m = 1; m < CRT_MAX_MODULI; ++m) {
+    if (m >= count) break;
+    uint32_t word[2] = {0u, 0u};
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const double y =
+          fma(u1[i], cst.c78[m], fma(u0[i], cst.c52[m], fma(w1[i], cst.c26[m], w0[i])));
+      const double qq = rint(y * cst.minv[m]);
+      const double r = fma(-qq, cst.m[m], y);
+      word[i >> 2] |= ((uint32_t)(int)r & 0xFFu) << (8 * (i & 3));
     }
-#pragma unroll
-    for (int m = 1; m < CRT_MAX_MODULI; ++m) {
-      if (m >= count) break;
-      uint32_t word = 0;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const double y =
-            fma(u1[i], cst.c78[m], fma(u0[i], cst.c52[m], fma(w1[i], cst.c26[m], w0[i])));
-        const double qq = rint(y * cst.minv[m]);
-        const double r = fma(-qq, cst.m[m], y);
-        word |= ((uint32_t)(int)r & 0xFFu) << (8 * i);
-      }
-      *(uint32_t*)(o + (int64_t)m * plane) = word;
-    }
+    *(uint2*)(o + (int64_t)m * plane) = uint2{word[0], word[1]};
   }
 }
 
@@ -1374,7 +1386,7 @@ static hipError_t crt_operand(const double* hi, const double* lo, int64_t sr, in
                               int64_t rows_p, int count, int p, const CrtResidueConsts& rc,
                               double* part, hipStream_t st) {
   scale_operand(hi, sr, sl, rows, k, exps, part, st);
-  dim3 grid((unsigned)(ldq / 64), (unsigned)(rows_p / 64));
+  dim3 grid((unsigned)((ldq + 127) / 128), (unsigned)(rows_p / 32));
   hipLaunchKernelGGL(oz_crt_residues, grid, dim3(512), 0, st, hi, lo, sr, sl, rows, k, exps,
                      count, p, rc, q, ldq, rows_p * ldq);
   return hipGetLastError();
