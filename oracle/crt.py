@@ -30,6 +30,16 @@ emulation of a floating-point matrix product by Ozaki, Uchino and Imamura
 6. Result.  C = alpha (X 2^(sigma_i + tau_j - 2P)) + beta C, evaluated exactly
    and rounded to the nearest dd (hi nearest binary64, lo nearest binary64 of
    the rest).
+
+Complex operands (crt_cgemm): the real and imaginary parts of a row share
+one exponent (that of the largest |hi| over both parts), each part becomes
+its grid integers (a conjugated operand negates the imaginary integers), and
+with T1 = Ar' Br'^T, T2 = Ai' Bi'^T, T3 = (Ar' + Ai')(Br' + Bi')^T (three
+exact integer products) the product is Re X = T1 - T2, Im X = T3 - T1 - T2,
+both exact; |Re X|, |Im X| <= 2 k 2^(2P), so P follows 8 k 2^(2P) <= M.
+Each part is reconstructed from its residues (T1 - T2 and T3 - T1 - T2
+modulo every modulus); then C = alpha X 2^(sigma_i + tau_j - 2P) + beta C in
+exact complex arithmetic, each part rounded to the nearest dd.
 """
 from fractions import Fraction
 from math import gcd
@@ -61,12 +71,13 @@ def modulus_product(count):
     return M
 
 
-def exponent(k, count):
-    """P (step 5): the largest P <= MAX_BITS with 4 k 2^(2P) <= M, or None
-    when there is none >= 1."""
+def exponent(k, count, margin_bits=2):
+    """P (step 5): the largest P <= MAX_BITS with 2^margin_bits k 2^(2P) <= M
+    (margin 2 for real products, 3 for complex ones), or None when there is
+    none >= 1."""
     M = modulus_product(count)
     lk = max(0, (max(k, 1) - 1).bit_length())       # ceil(log2 k)
-    p = ((M.bit_length() - 1) - 2 - lk) // 2
+    p = ((M.bit_length() - 1) - margin_bits - lk) // 2
     p = min(p, MAX_BITS)
     return p if p >= 1 else None
 
@@ -176,4 +187,83 @@ def crt_rgemm(transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, coun
             if b != 0:
                 v += b * (Fraction(ch[i + j * ldc]) + Fraction(cl[i + j * ldc]))
             ch[i + j * ldc], cl[i + j * ldc] = _nearest_dd(v)
+    return C
+
+
+def complex_row_operand(trans, rows, k, X, ld):
+    """Row operand of a complex matrix X = (re.hi, re.lo, im.hi, im.lo) as
+    (re hi, re lo, im hi, im lo) arrays rows x k; trans 'C' conjugates."""
+    rh, rl = row_operand("N" if trans.upper() == "N" else "T", rows, k, X[:2], ld)
+    ih, il = row_operand("N" if trans.upper() == "N" else "T", rows, k, X[2:], ld)
+    if trans.upper() == "C":
+        ih, il = -ih, -il
+    return rh, rl, ih, il
+
+
+def complex_scale_exponents(rh, ih):
+    """One exponent per row over both parts: that of the largest |hi|."""
+    return scale_exponents(np.concatenate([rh, ih], axis=1))
+
+
+def complex_integer_product(transa, transb, m, n, k, A, lda, B, ldb, count):
+    """Exponents, P and the exact integer parts (Re X, Im X) of the complex
+    product, from the residues of the three products T1, T2, T3."""
+    p = exponent(k, count, margin_bits=3)
+    if p is None:
+        raise ValueError("too few moduli for k")
+    ms = moduli(count)
+    arh, arl, aih, ail = complex_row_operand(transa, m, k, A, lda)
+    # columns of op(B) as rows: op(B) = B ('N'), B^T ('T'), conj(B)^T ('C')
+    bt = {"N": "T", "T": "N", "C": "C"}[transb.upper()]
+    if bt == "C":
+        brh, brl, bih, bil = complex_row_operand("N", n, k, B, ldb)
+        bih, bil = -bih, -bil
+    else:
+        brh, brl, bih, bil = complex_row_operand(bt, n, k, B, ldb)
+    ea, eb = complex_scale_exponents(arh, aih), complex_scale_exponents(brh, bih)
+    Ar, Ai = integers(arh, arl, ea, p), integers(aih, ail, ea, p)
+    Br, Bi = integers(brh, brl, eb, p), integers(bih, bil, eb, p)
+    ra, ia, sa = residues(Ar, count), residues(Ai, count), residues(Ar + Ai, count)
+    rb, ib, sb = residues(Br, count), residues(Bi, count), residues(Br + Bi, count)
+    re, im = [], []
+    for t in range(count):
+        t1, t2, t3 = ra[t] @ rb[t].T, ia[t] @ ib[t].T, sa[t] @ sb[t].T
+        re.append(t1 - t2)
+        im.append(t3 - t1 - t2)
+    return ea, eb, p, reconstruct(re, count), reconstruct(im, count)
+
+
+def crt_cgemm(transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, count):
+    """Complex form of crt_rgemm: A, B, C are (re.hi, re.lo, im.hi, im.lo)
+    column-major planes, alpha and beta ((re.hi, re.lo), (im.hi, im.lo));
+    C updated in place and returned."""
+    crh, crl, cih, cil = C
+    if m == 0 or n == 0:
+        return C
+    fr = lambda x: Fraction(x[0]) + Fraction(x[1])
+    ar, ai = fr(alpha[0]), fr(alpha[1])
+    br, bi = fr(beta[0]), fr(beta[1])
+    if k == 0 or (ar == 0 and ai == 0):
+        ea = eb = None
+        p = 0
+        XR = XI = np.zeros((m, n), dtype=object)
+    else:
+        ea, eb, p, XR, XI = complex_integer_product(transa, transb, m, n, k, A, lda, B, ldb,
+                                                    count)
+    for j in range(n):
+        for i in range(m):
+            vr = vi = Fraction(0)
+            if XR[i, j] or XI[i, j]:
+                sc = Fraction(2) ** int(ea[i] + eb[j] - 2 * p)
+                pr, pi = XR[i, j] * sc, XI[i, j] * sc
+                vr, vi = ar * pr - ai * pi, ar * pi + ai * pr
+            if br != 0 or bi != 0:
+                q = i + j * ldc
+                cr = Fraction(crh[q]) + Fraction(crl[q])
+                ci = Fraction(cih[q]) + Fraction(cil[q])
+                vr += br * cr - bi * ci
+                vi += br * ci + bi * cr
+            q = i + j * ldc
+            crh[q], crl[q] = _nearest_dd(vr)
+            cih[q], cil[q] = _nearest_dd(vi)
     return C

@@ -183,8 +183,131 @@ def check_rgemm(crt, rng):
                 assert abs(got - want) <= tol, (ta, tb, i, j)
 
 
+def _cdd_matrix(rng, size, wide=False):
+    return _dd_matrix(rng, size, 1, wide) + _dd_matrix(rng, size, 1, wide)
+
+
+def _celem(X, ld, r, c, conj):
+    q = r + c * ld
+    re = Fraction(float(X[0][q])) + Fraction(float(X[1][q]))
+    im = Fraction(float(X[2][q])) + Fraction(float(X[3][q]))
+    return re, (-im if conj else im)
+
+
+def _op_elem(X, ld, trans, i, l, row):
+    """op(X)(i, l) for op(A) (row=True) or op(X)(l, i) for op(B)."""
+    t = trans.upper()
+    if t == "N":
+        return _celem(X, ld, i, l, False) if row else _celem(X, ld, l, i, False)
+    return _celem(X, ld, l, i, t == "C") if row else _celem(X, ld, i, l, t == "C")
+
+
+def check_complex_exponents(crt):
+    # a row whose imaginary part is zero takes the real part's exponent, and
+    # the other way round; an all-zero row gets 0
+    rh = np.array([[2.0 ** -30, -2.0 ** -31], [0.0, 0.0], [0.0, 0.0]])
+    ih = np.array([[0.0, 0.0], [0.0, 3.0], [0.0, 0.0]])
+    assert list(crt.complex_scale_exponents(rh, ih)) == [-29, 2, 0]
+    for count in (20, 27, 32):
+        for k in (7, 4096, 8192):
+            p = crt.exponent(k, count, margin_bits=3)
+            if p is not None and p < crt.MAX_BITS:
+                M = crt.modulus_product(count)
+                k2 = 1 << max(0, (k - 1).bit_length())
+                assert 8 * k * 2 ** (2 * p) <= M < 8 * k2 * 2 ** (2 * p + 2)
+
+
+def check_complex_integer_product(crt, rng):
+    m, n, k, count = 4, 3, 6, 20
+    for ta, tb in (("N", "N"), ("C", "T"), ("T", "C")):
+        A = _cdd_matrix(rng, m * k, wide=True)
+        B = _cdd_matrix(rng, k * n)
+        lda = m if ta == "N" else k
+        ldb = k if tb == "N" else n
+        ea, eb, p, XR, XI = crt.complex_integer_product(ta, tb, m, n, k, A, lda, B, ldb, count)
+        assert p == crt.exponent(k, count, margin_bits=3)
+        # the grid integers of each part, taken element by element
+        for i in range(m):
+            for j in range(n):
+                wr = wi = 0
+                for l in range(k):
+                    a = _op_elem(A, lda, ta, i, l, True)
+                    b = _op_elem(B, ldb, tb, j, l, False)
+                    ga = [crt.integers(np.array([[float(v)]]), np.array([[float(v - Fraction(float(v)))]]),
+                                       np.array([int(ea[i])]), p)[0, 0] for v in a]
+                    gb = [crt.integers(np.array([[float(v)]]), np.array([[float(v - Fraction(float(v)))]]),
+                                       np.array([int(eb[j])]), p)[0, 0] for v in b]
+                    wr += ga[0] * gb[0] - ga[1] * gb[1]      # the textbook product
+                    wi += ga[0] * gb[1] + ga[1] * gb[0]
+                assert XR[i, j] == wr and XI[i, j] == wi, (ta, tb, i, j)
+
+
+def check_cgemm(crt, rng):
+    for (ta, tb, m, n, k, count) in (("N", "N", 4, 3, 9, 27), ("C", "T", 3, 4, 5, 22),
+                                      ("T", "C", 2, 2, 6, 30), ("C", "C", 3, 2, 4, 25)):
+        A = _cdd_matrix(rng, m * k, wide=True)
+        B = _cdd_matrix(rng, k * n)
+        C = _cdd_matrix(rng, m * n)
+        lda = m if ta == "N" else k
+        ldb = k if tb == "N" else n
+        alpha = ((0.75, 2.0 ** -60), (-0.5, 0.0))
+        beta = ((-1.25, 0.0), (0.25, 0.0))
+        out = crt.crt_cgemm(ta, tb, m, n, k, alpha, A, lda, B, ldb, beta,
+                            tuple(x.copy() for x in C), m, count)
+        p = crt.exponent(k, count, margin_bits=3)
+        # exponents by hand: the largest |hi| over both parts of each row
+        def exps(rows, get):
+            out_e = []
+            for r in range(rows):
+                mx = max(max(abs(float(v)) for v in get(r, l)) for l in range(k))
+                out_e.append(0 if mx == 0 else int(np.frexp(mx)[1]))
+            return out_e
+        ea = exps(m, lambda r, l: _op_elem(A, lda, ta, r, l, True))
+        eb = exps(n, lambda r, l: _op_elem(B, ldb, tb, r, l, False))
+        fr = lambda x: Fraction(x[0]) + Fraction(x[1])
+        a_r, a_i, b_r, b_i = fr(alpha[0]), fr(alpha[1]), fr(beta[0]), fr(beta[1])
+        half = Fraction(1, 2) + Fraction(1, 2 ** 50)
+        for i in range(m):
+            for j in range(n):
+                sr = si = Fraction(0)
+                bound = Fraction(0)
+                da = half * Fraction(2) ** (ea[i] - p)
+                db = half * Fraction(2) ** (eb[j] - p)
+                for l in range(k):
+                    a = _op_elem(A, lda, ta, i, l, True)
+                    b = _op_elem(B, ldb, tb, j, l, False)
+                    sr += a[0] * b[0] - a[1] * b[1]
+                    si += a[0] * b[1] + a[1] * b[0]
+                    bound += 2 * (da * (abs(b[0]) + abs(b[1])) + db * (abs(a[0]) + abs(a[1]))
+                                  + 2 * da * db)
+                q = i + j * m
+                cr = Fraction(float(C[0][q])) + Fraction(float(C[1][q]))
+                ci = Fraction(float(C[2][q])) + Fraction(float(C[3][q]))
+                want_r = a_r * sr - a_i * si + b_r * cr - b_i * ci
+                want_i = a_r * si + a_i * sr + b_r * ci + b_i * cr
+                got_r = Fraction(float(out[0][q])) + Fraction(float(out[1][q]))
+                got_i = Fraction(float(out[2][q])) + Fraction(float(out[3][q]))
+                tol = (abs(a_r) + abs(a_i)) * bound
+                assert abs(got_r - want_r) <= tol + abs(want_r) * Fraction(1, 2 ** 104), \
+                    (ta, tb, i, j)
+                assert abs(got_i - want_i) <= tol + abs(want_i) * Fraction(1, 2 ** 104), \
+                    (ta, tb, i, j)
+
+
 def test_moduli():
     check_moduli(CRT)
+
+
+def test_complex_exponents_and_margin():
+    check_complex_exponents(CRT)
+
+
+def test_complex_integer_product_equals_textbook_product():
+    check_complex_integer_product(CRT, np.random.default_rng(16))
+
+
+def test_cgemm_within_grid_rounding_of_exact_product():
+    check_cgemm(CRT, np.random.default_rng(17))
 
 
 def test_exponent():
@@ -232,8 +355,8 @@ def test_quick_cases():
 MUTANTS = [
     ("if all(gcd(m, q) == 1 for q in out):", "if all(gcd(m, q) == 1 for q in out[1:]):",
      "moduli not pairwise coprime"),
-    ("p = ((M.bit_length() - 1) - 2 - lk) // 2", "p = ((M.bit_length() - 1) - lk) // 2",
-     "no margin in P"),
+    ("p = ((M.bit_length() - 1) - margin_bits - lk) // 2",
+     "p = ((M.bit_length() - 1) - lk) // 2", "no margin in P"),
     ("t2 = np.rint((zh - t1) + zl)", "t2 = np.rint(zh - t1)", "low part dropped"),
     ("sh = (p - exps).astype(np.int64)[:, None]", "sh = (p + exps).astype(np.int64)[:, None]",
      "scale sign"),
@@ -248,6 +371,18 @@ MUTANTS = [
      "v = a * X[i, j] * Fraction(2) ** int(ea[i] + eb[j] - p)", "wrong result scale"),
     ("v += b * (Fraction(ch[i + j * ldc]) + Fraction(cl[i + j * ldc]))",
      "v += b * Fraction(ch[i + j * ldc])", "low part of C dropped"),
+    ("im.append(t3 - t1 - t2)", "im.append(t3 - t1 + t2)", "three-product sign"),
+    ("return scale_exponents(np.concatenate([rh, ih], axis=1))", "return scale_exponents(rh)",
+     "complex exponent from the real part only"),
+    ("p = exponent(k, count, margin_bits=3)", "p = exponent(k, count)",
+     "complex margin too small"),
+    ("    if trans.upper() == \"C\":\n        ih, il = -ih, -il", "    if False:\n        ih, il = -ih, -il",
+     "conjugation of op(A) lost"),
+    ("bt = {\"N\": \"T\", \"T\": \"N\", \"C\": \"C\"}[transb.upper()]",
+     "bt = {\"N\": \"T\", \"T\": \"N\", \"C\": \"N\"}[transb.upper()]",
+     "conjugation of op(B) lost"),
+    ("vr, vi = ar * pr - ai * pi, ar * pi + ai * pr", "vr, vi = ar * pr + ai * pi, ar * pi + ai * pr",
+     "complex alpha sign"),
 ]
 
 CHECKS = [("moduli", lambda c, r: check_moduli(c)),
@@ -256,7 +391,10 @@ CHECKS = [("moduli", lambda c, r: check_moduli(c)),
           ("residues", check_residues),
           ("reconstruct", lambda c, r: check_reconstruct(c)),
           ("integer_product", check_integer_product),
-          ("rgemm", check_rgemm)]
+          ("rgemm", check_rgemm),
+          ("complex_exponents", lambda c, r: check_complex_exponents(c)),
+          ("complex_integer_product", check_complex_integer_product),
+          ("cgemm", check_cgemm)]
 
 
 def _load_copy(text, tmp):
