@@ -471,8 +471,9 @@ def bench_syrk_split(h, args, stream, plain_ms, kind):
 
 
 def bench_cgemm(h, args, stream):
-    """Complex dd Cgemm NN at n/2, four-product (default) and three-product
-    forms.  Complex flops: 8 mnk (LAWN 41: 6 real multiplies + 2 adds per
+    """Complex dd Cgemm NN at n/2: four-product (default) and three-product
+    plain forms, the four products in the INT8 split form, and the complex
+    modular form (three residue products per modulus).  Complex flops: 8 mnk (LAWN 41: 6 real multiplies + 2 adds per
     complex multiply-add), for both forms."""
     import torch
     import workloads as W

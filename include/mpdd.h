@@ -244,7 +244,14 @@ int mpdd_Cgemm(mpdd_handle h, const char *transa, const char *transb, mpdd_int m
  * Re P = R1 - R2, Im P = R3 - R1 - R2; a quarter less arithmetic, with the
  * error of Im P relative to |Ar + Ai| |Br + Bi|; extra scratch
  * 16 (m k + k n) bytes); tile_id / splitk choose the real products' tiling as
- * in mpdd_Rgemm_ex.  MPDD_OZAKI_I8 / MPDD_OZAKI_F64 / MPDD_OZAKI_CRT: the four
+ * in mpdd_Rgemm_ex.  MPDD_OZAKI_CRT: the modular split form on complex
+ * operands -- one exponent per row of op(A) (column of op(B)) over both
+ * parts, grid integers per part (a conjugated operand negates the imaginary
+ * ones), three residue products per modulus, T1 = Ar'Br', T2 = Ai'Bi',
+ * T3 = (Ar' + Ai')(Br' + Bi'), and Re = T1 - T2, Im = T3 - T1 - T2 rebuilt
+ * exactly (P from 8 k 2^(2P) <= M; nslices 0 = the fewest moduli whose P
+ * reaches 104), then the same complex epilogue; tile_id 5, 6 or 8.
+ * MPDD_OZAKI_I8 / MPDD_OZAKI_F64: the four
  * real products of MPDD_PLAIN, each a split-form product (opts->nslices, tile_id as in
  * mpdd_Rgemm_ex), then the same complex epilogue.  MPDD_ERR_ARG for another
  * algo. */

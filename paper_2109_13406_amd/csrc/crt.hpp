@@ -11,6 +11,8 @@
 // one exact INT8 product per modulus; the exact integer product is rebuilt
 // from the residues of its entries by Chinese remaindering and rounded to dd.
 #pragma once
+#include <hip/hip_runtime.h>
+
 #include <cmath>
 #include <cstdint>
 
@@ -115,12 +117,14 @@ inline CrtBig crt_modulus_product(int count) {
 // entry of the integer product, at most k 2^(2P) in magnitude, lies in
 // [-M/4, M/4] and is recovered exactly); 0 when count is out of range or
 // no P >= 1 fits.
-inline int crt_exponent(int64_t k, int count) {
+// A complex product (margin 3) needs 8 k 2^(2P) <= M: its parts are sums of
+// two products, at most 2 k 2^(2P) in magnitude.
+inline int crt_exponent(int64_t k, int count, int margin = 2) {
   if (count < 1 || count > CRT_MAX_MODULI) return 0;
   int lk = 0;
   while (((int64_t)1 << lk) < k) ++lk;            // ceil(log2 k), k >= 1
   const int fl = crt_modulus_product(count).bits() - 1;
-  int p = (fl - 2 - lk);
+  int p = (fl - margin - lk);
   p = p >= 0 ? p / 2 : -1;
   if (p > CRT_MAX_BITS) p = CRT_MAX_BITS;
   return p >= 1 ? p : 0;
@@ -128,9 +132,9 @@ inline int crt_exponent(int64_t k, int count) {
 
 // Moduli count used when the caller passes 0: the fewest whose grid reaches
 // CRT_MAX_BITS for this k (CRT_MAX_MODULI if none does).
-inline int crt_default_count(int64_t k) {
+inline int crt_default_count(int64_t k, int margin = 2) {
   for (int c = 1; c <= CRT_MAX_MODULI; ++c)
-    if (crt_exponent(k, c) == CRT_MAX_BITS) return c;
+    if (crt_exponent(k, c, margin) == CRT_MAX_BITS) return c;
   return CRT_MAX_MODULI;
 }
 
@@ -181,5 +185,14 @@ inline int crt_constants(int count, CrtResidueConsts* rc, CrtModuli* cm, CrtComb
   }
   return limbs;
 }
+
+// Complex modular product (ozaki.hip): P = op(A) op(B) of complex dd
+// operands (planes re.hi, re.lo, im.hi, im.lo; op 0 'N', 1 'T', 2 'C') into
+// the dd planes (prh, prl) + i (pih, pil), leading dimension m, with three
+// residue products per modulus (Re = T1 - T2, Im = T3 - T1 - T2).  k >= 1.
+int ozaki_crt_cgemm(const void* opts, int opa, int opb, int64_t m, int64_t n, int64_t k,
+                    const double* const* a, int64_t lda, const double* const* b, int64_t ldb,
+                    double* prh, double* prl, double* pih, double* pil, hipStream_t st,
+                    hipMemPool_t pool);
 
 }  // namespace mpdd

@@ -498,6 +498,27 @@ int mpdd_Cgemm_ex(mpdd_handle h, const mpdd_opts* opts, const char* transa, cons
   const size_t plane = (size_t)m * (size_t)n * sizeof(double);
   const mpdd_dd zero{0.0, 0.0}, one{1.0, 0.0};
   e.ldp = m;
+  if (algo == MPDD_OZAKI_CRT) {
+    // modular form: the complex product from three residue products per
+    // modulus, exact in integers, into P; then the same complex epilogue
+    void* w = nullptr;
+    if (hipMallocFromPoolAsync(&w, 4 * plane, h->pool, st) != hipSuccess) return MPDD_ERR_ALLOC;
+    double* pp[4];
+    for (int q = 0; q < 4; ++q) pp[q] = (double*)((char*)w + q * plane);
+    const int opa = !ta ? 0 : lsame(transa, 'C') ? 2 : 1;
+    const int opb = !tb ? 0 : lsame(transb, 'C') ? 2 : 1;
+    const double* av[4] = {A_re_hi, A_re_lo, A_im_hi, A_im_lo};
+    const double* bv[4] = {B_re_hi, B_re_lo, B_im_hi, B_im_lo};
+    int rc = ozaki_crt_cgemm(opts, opa, opb, m, n, k, av, lda, bv, ldb, pp[0], pp[1], pp[2],
+                             pp[3], st, h->pool);
+    if (!rc) {
+      e.p_rh = pp[0]; e.p_rl = pp[1]; e.p_ih = pp[2]; e.p_il = pp[3];
+      rc = hip_status(launch_cgemm_epilogue(e, st));
+    }
+    const hipError_t ef = hipFreeAsync(w, st);
+    if (rc) return rc;
+    return hip_status(ef);
+  }
   if (algo != MPDD_COMPLEX_3M) {
     // four real products (plain, or split form: each an Rgemm_ex of the
     // caller's split algo, slice count and INT8 tiling)

@@ -57,16 +57,19 @@ constexpr int OZ_KPAD = 64;     // k padding of the slice rows
 constexpr int OZ_SCALE_CHUNK = 512;
 
 __global__ void __launch_bounds__(256)
-oz_scale_part_cols(const double* __restrict__ x, int64_t sr, int64_t sl, int64_t rows,
-                   int64_t k, double* __restrict__ part) {
+oz_scale_part_cols(const double* __restrict__ x, const double* __restrict__ x2, int64_t sr,
+                   int64_t sl, int64_t rows, int64_t k, double* __restrict__ part) {
   __shared__ double red[4][64];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t r = (int64_t)blockIdx.x * 64 + lane;
   const int64_t l0 = (int64_t)blockIdx.y * OZ_SCALE_CHUNK;
   const int64_t l1 = (l0 + OZ_SCALE_CHUNK < k) ? l0 + OZ_SCALE_CHUNK : k;
   double mx = 0.0;
-  if (r < rows)
+  if (r < rows) {
     for (int64_t l = l0 + wave; l < l1; l += 4) mx = fmax(mx, fabs(x[r * sr + l * sl]));
+    if (x2)
+      for (int64_t l = l0 + wave; l < l1; l += 4) mx = fmax(mx, fabs(x2[r * sr + l * sl]));
+  }
   red[wave][lane] = mx;
   __syncthreads();
   if (wave == 0 && r < rows) {
@@ -88,14 +91,18 @@ oz_scale_finish(const double* __restrict__ part, int64_t rows, int nchunks,
 }
 
 // Rows contiguous along l (sl == 1): one wave per row, lanes walk l.
+// x2 (may be null): a second plane whose entries count as well (the
+// imaginary parts of a complex row operand).
 __global__ void __launch_bounds__(256)
-oz_scale_rows_wave(const double* __restrict__ x, int64_t sr, int64_t sl, int64_t rows,
-                   int64_t k, int* __restrict__ exps) {
+oz_scale_rows_wave(const double* __restrict__ x, const double* __restrict__ x2, int64_t sr,
+                   int64_t sl, int64_t rows, int64_t k, int* __restrict__ exps) {
   const int lane = threadIdx.x & 63;
   const int64_t r = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
   if (r >= rows) return;
   double mx = 0.0;
   for (int64_t l = lane; l < k; l += 64) mx = fmax(mx, fabs(x[r * sr + l * sl]));
+  if (x2)
+    for (int64_t l = lane; l < k; l += 64) mx = fmax(mx, fabs(x2[r * sr + l * sl]));
   for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off));
   if (lane == 0) {
     int e = 0;
@@ -555,7 +562,8 @@ template <int WM, int WN, int GM, int GN, int NS, bool PF, bool M32, bool CRT = 
 __global__ void __launch_bounds__(64 * GM * GN, 1)
 oz_gemm_i8_dma(const int8_t* __restrict__ qa, const int8_t* __restrict__ qb,
                int32_t* __restrict__ x, int64_t kp, int64_t plane_a, int64_t plane_b, int64_t mp,
-               int64_t np, int nslices, int tiles_m, int tiles_n, int tri, CrtModuli cm) {
+               int64_t np, int nslices, int tiles_m, int tiles_n, int tri, CrtModuli cm,
+               int crt_count) {
   constexpr int NW = GM * GN;                  // waves
   constexpr int WR = WM / GM, WC = WN / GN;    // outputs per wave
   constexpr int MT = M32 ? 32 : 16;            // MFMA tile edge
@@ -716,8 +724,11 @@ oz_gemm_i8_dma(const int8_t* __restrict__ qa, const int8_t* __restrict__ qb,
   // l % 16; 32 x 32 tile, lane l holds rows 8 g + 4 (l / 32) + 0..3 of column
   // l % 32 in registers 4 g .. 4 g + 3
   if constexpr (CRT) {
+    // plane ct holds a product modulo modulus ct % crt_count (a complex
+    // product runs three products per modulus, planes t, count + t, 2 count + t)
     int8_t* xq = (int8_t*)x + (int64_t)ct * mp * np;
-    const double mm = cm.m[ct], mi = cm.minv[ct];
+    const int mt = ct % crt_count;
+    const double mm = cm.m[mt], mi = cm.minv[mt];
 #pragma unroll
     for (int a = 0; a < FA; ++a)
 #pragma unroll
@@ -1100,11 +1111,17 @@ oz_combine_qd(const int32_t* __restrict__ x, int64_t mp, int64_t np, int nslices
 // one 8-byte word per modulus, so the 16 threads of a row write its 128
 // residues of a plane as one 128-byte line.  Columns l >= ldq (ldq is a
 // multiple of 64) are neither stored nor, beyond k, read.
+//
+// Complex operands: sign = -1 negates every entry (a conjugated imaginary
+// part; the grid integer of -x is -x'); with add_q non-null the kernel also
+// writes sum_q = add_q + these residues, reduced to the balanced range
+// (the residues of the sum of the two grid integers, e.g. Ar' + Ai').
 __global__ void __launch_bounds__(512, 2)
 oz_crt_residues(const double* __restrict__ xh, const double* __restrict__ xl, int64_t sr,
                 int64_t sl, int64_t rows, int64_t k, const int* __restrict__ exps, int count,
                 int p, CrtResidueConsts cst, int8_t* __restrict__ q, int64_t ldq,
-                int64_t plane) {
+                int64_t plane, double sign, const int8_t* __restrict__ add_q,
+                int8_t* __restrict__ sum_q) {
   // element l of a staged row sits at column l + l/8 (one padding double
   // every 8), so the 16 threads of a row, reading 8 consecutive elements each,
   // hit distinct banks; the odd row pitch staggers the rows
@@ -1149,7 +1166,7 @@ oz_crt_residues(const double* __restrict__ xh, const double* __restrict__ xl, in
 #pragma unroll
   for (int i = 0; i < 8; ++i) {
     const int c = col(lq) + i;                 // lq is a multiple of 8
-    const double zh = ldexp(t[0][row][c], sh), zl = ldexp(t[1][row][c], sh);
+    const double zh = ldexp(sign * t[0][row][c], sh), zl = ldexp(sign * t[1][row][c], sh);
     const double t1 = rint(zh);
     const double t2 = rint((zh - t1) + zl);
     const double u = rint(t1 * 0x1p-52);
@@ -1159,15 +1176,29 @@ oz_crt_residues(const double* __restrict__ xh, const double* __restrict__ xl, in
     w1[i] = rint(w * 0x1p-26);
     w0[i] = fma(-w1[i], 0x1p26, w);
   }
-  int8_t* o = q + (r0 + row) * ldq + l0 + lq;
-  {
-    uint32_t lo = 0, hi = 0;
+  const int64_t off = (r0 + row) * ldq + l0 + lq;
+  int8_t* o = q + off;
+  // residues of the sum: byte-wise add, then one correction into the
+  // balanced range (|a + b| <= m - 1 for odd m; modulo 256 the byte add wraps)
+  auto add_store = [&](int m, const uint32_t (&word)[2]) {
+    const uint2 a = *(const uint2*)(add_q + (int64_t)m * plane + off);
+    const int mm = (int)cst.m[m], h = (mm - 1) / 2;
+    uint32_t out[2] = {0u, 0u};
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      lo |= ((uint32_t)(int)w0[i] & 0xFFu) << (8 * i);
-      hi |= ((uint32_t)(int)w0[i + 4] & 0xFFu) << (8 * i);
+    for (int i = 0; i < 8; ++i) {
+      const uint32_t aw = (i < 4) ? a.x : a.y;
+      int v = (int)(int8_t)(aw >> (8 * (i & 3))) + (int)(int8_t)(word[i >> 2] >> (8 * (i & 3)));
+      if (m > 0) v = (v > h) ? v - mm : (v < -h) ? v + mm : v;
+      out[i >> 2] |= ((uint32_t)v & 0xFFu) << (8 * (i & 3));
     }
-    *(uint2*)o = uint2{lo, hi};
+    *(uint2*)(sum_q + (int64_t)m * plane + off) = uint2{out[0], out[1]};
+  };
+  {
+    uint32_t word[2] = {0u, 0u};
+#pragma unroll
+    for (int i = 0; i < 8; ++i) word[i >> 2] |= ((uint32_t)(int)w0[i] & 0xFFu) << (8 * (i & 3));
+    *(uint2*)o = uint2{word[0], word[1]};
+    if (add_q) add_store(0, word);
   }
 #pragma unroll
   for (int m = 1; m < CRT_MAX_MODULI; ++m) {
@@ -1182,7 +1213,33 @@ oz_crt_residues(const double* __restrict__ xh, const double* __restrict__ xl, in
       word[i >> 2] |= ((uint32_t)(int)r & 0xFFu) << (8 * (i & 3));
     }
     *(uint2*)(o + (int64_t)m * plane) = uint2{word[0], word[1]};
+    if (add_q) add_store(m, word);
   }
+}
+
+// The exact integer X = S - q M from its limb sums S_l (S = sum_l S_l 2^(39 l)
+// congruent to X modulo M, |S_l| < 2^51, |X| <= M/4), rounded to a dd: q =
+// rint(sum_l S_l g_l), X_l = S_l - q M_l (exact), carries into balanced limbs,
+// then DWPlusFP from the lowest limb up.
+template <int L>
+__device__ __forceinline__ ddv crt_limbs_to_dd(const double (&s)[L], const CrtCombineConsts& cst) {
+  double est = 0.0;
+#pragma unroll
+  for (int l = L - 1; l >= 0; --l) est = fma(s[l], cst.g[l], est);
+  const double qm = rint(est);
+  double xl[L];
+#pragma unroll
+  for (int l = 0; l < L; ++l) xl[l] = fma(-qm, cst.ml[l], s[l]);
+#pragma unroll
+  for (int l = 0; l + 1 < L; ++l) {
+    const double c = rint(xl[l] * 0x1p-39);
+    xl[l] = fma(-c, 0x1p39, xl[l]);
+    xl[l + 1] += c;
+  }
+  ddv acc{xl[0], 0.0};
+#pragma unroll
+  for (int l = 1; l < L; ++l) acc = dd_add_d(acc, ldexp(xl[l], CRT_LIMB_BITS * l));
+  return acc;
 }
 
 // Reconstruction: entry (i, j) from the balanced residues r_t of its
@@ -1253,22 +1310,7 @@ oz_crt_combine(const int8_t* __restrict__ x, int64_t mp, int64_t np, int count, 
   for (int r = 0; r < 4; ++r) {
     const int64_t i = i0 + r;
     if (!updated(i)) continue;
-    double est = 0.0;
-#pragma unroll
-    for (int l = L - 1; l >= 0; --l) est = fma(s[r][l], cst.g[l], est);
-    const double qm = rint(est);
-    double xl[L];
-#pragma unroll
-    for (int l = 0; l < L; ++l) xl[l] = fma(-qm, cst.ml[l], s[r][l]);
-#pragma unroll
-    for (int l = 0; l + 1 < L; ++l) {
-      const double c = rint(xl[l] * 0x1p-39);
-      xl[l] = fma(-c, 0x1p39, xl[l]);
-      xl[l + 1] += c;
-    }
-    ddv acc{xl[0], 0.0};
-#pragma unroll
-    for (int l = 1; l < L; ++l) acc = dd_add_d(acc, ldexp(xl[l], CRT_LIMB_BITS * l));
+    const ddv acc = crt_limbs_to_dd<L>(s[r], cst);
     const int e = ea[i] + eb[j] - 2 * p;
     ddv pr{ldexp(acc.hi, e), ldexp(acc.lo, e)};
     ddv res = dd_mul(alpha, pr);
@@ -1276,6 +1318,78 @@ oz_crt_combine(const int8_t* __restrict__ x, int64_t mp, int64_t np, int count, 
     if (!beta_zero) res = dd_add(res, dd_mul(beta, ddv{ch[r], cl[r]}));
     c_hi[ci] = res.hi;
     c_lo[ci] = res.lo;
+  }
+}
+
+// Complex reconstruction: plane t, count + t and 2 count + t hold the
+// residues of T1 = Ar' Br', T2 = Ai' Bi' and T3 = (Ar' + Ai')(Br' + Bi')
+// modulo modulus t; Re X = T1 - T2 and Im X = T3 - T1 - T2 modulo it
+// (|.| <= 384 before the reduction, which rint(y (1/m)) m makes balanced
+// exactly), each part rebuilt as in oz_crt_combine and scaled by
+// 2^(sigma_i + tau_j - 2P) into the dd planes of P (leading dimension ldp);
+// the complex alpha / beta update is the caller's.  Four rows per thread.
+template <int L>
+__global__ void __launch_bounds__(256)
+oz_crt_combine_c(const int8_t* __restrict__ x, int64_t mp, int64_t np, int count, int p,
+                 CrtCombineConsts cst, CrtModuli cm, const int* __restrict__ ea,
+                 const int* __restrict__ eb, int64_t m, int64_t n, double* __restrict__ prh,
+                 double* __restrict__ prl, double* __restrict__ pih, double* __restrict__ pil,
+                 int64_t ldp) {
+  constexpr int NB = 4;
+  const int64_t mq = (m + 3) / 4;
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= mq * n) return;
+  const int64_t i0 = (gid % mq) * 4, j = gid / mq;
+  const int64_t plane = mp * np;
+  const int8_t* xp = x + j * mp + i0;
+  double sr[4][L], si[4][L];
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int l = 0; l < L; ++l) sr[r][l] = si[r][l] = 0.0;
+#pragma unroll
+  for (int t0 = 0; t0 < CRT_MAX_MODULI; t0 += NB) {
+    if (t0 >= count) break;
+    uint32_t v1[NB], v2[NB], v3[NB];
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+      const bool on = t0 + u < count;
+      const int8_t* q = xp + (int64_t)(t0 + u) * plane;
+      v1[u] = on ? *(const uint32_t*)q : 0u;
+      v2[u] = on ? *(const uint32_t*)(q + (int64_t)count * plane) : 0u;
+      v3[u] = on ? *(const uint32_t*)(q + (int64_t)2 * count * plane) : 0u;
+    }
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+      const int tt = t0 + u;
+      if (tt >= count) break;
+      const double mm = cm.m[tt], mi = cm.minv[tt];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int a1 = (int)(int8_t)(v1[u] >> (8 * r));
+        const int a2 = (int)(int8_t)(v2[u] >> (8 * r));
+        const int a3 = (int)(int8_t)(v3[u] >> (8 * r));
+        const double yr = (double)(a1 - a2), yi = (double)(a3 - a1 - a2);
+        const double re = fma(-rint(yr * mi), mm, yr), im = fma(-rint(yi * mi), mm, yi);
+#pragma unroll
+        for (int l = 0; l < L; ++l) {
+          sr[r][l] = fma(re, cst.w[tt][l], sr[r][l]);
+          si[r][l] = fma(im, cst.w[tt][l], si[r][l]);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int64_t i = i0 + r;
+    if (i >= m) continue;
+    const int e = ea[i] + eb[j] - 2 * p;
+    const ddv xr = crt_limbs_to_dd<L>(sr[r], cst), xi = crt_limbs_to_dd<L>(si[r], cst);
+    const int64_t pi = i + j * ldp;
+    prh[pi] = ldexp(xr.hi, e);
+    prl[pi] = ldexp(xr.lo, e);
+    pih[pi] = ldexp(xi.hi, e);
+    pil[pi] = ldexp(xi.lo, e);
   }
 }
 
@@ -1306,15 +1420,17 @@ static bool digit_widths(int algo, int64_t k, int nslices, int& wfirst, int& w) 
 // `part` is scratch for the chunked maxima (rows * ceil(k / OZ_SCALE_CHUNK)
 // doubles, only used when the rows are contiguous across lanes).
 // Scale exponents of one row operand (rows x k) from its leading plane.
+// hi2 (may be null): a second plane of the same layout whose entries count
+// as well (one exponent for the real and imaginary parts of a complex row).
 static void scale_operand(const double* hi, int64_t sr, int64_t sl, int64_t rows, int64_t k,
-                          int* exps, double* part, hipStream_t st) {
+                          int* exps, double* part, hipStream_t st, const double* hi2 = nullptr) {
   if (sl == 1 || k == 0) {
     hipLaunchKernelGGL(oz_scale_rows_wave, dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, st,
-                       hi, sr, sl, rows, k, exps);
+                       hi, hi2, sr, sl, rows, k, exps);
   } else {
     const int nchunks = (int)((k + OZ_SCALE_CHUNK - 1) / OZ_SCALE_CHUNK);
     hipLaunchKernelGGL(oz_scale_part_cols, dim3((unsigned)((rows + 63) / 64), nchunks), dim3(256),
-                       0, st, hi, sr, sl, rows, k, part);
+                       0, st, hi, hi2, sr, sl, rows, k, part);
     hipLaunchKernelGGL(oz_scale_finish, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, st,
                        part, rows, nchunks, exps);
   }
@@ -1351,7 +1467,7 @@ static void launch_i8_products(int var, unsigned nblocks, const int8_t* qa, cons
                 : (var == 7) ? oz_gemm_i8_dma<256, 256, 2, 2, 4, true, false>
                              : oz_gemm_i8_dma<256, 256, 2, 4, 4, true, true>;
     hipLaunchKernelGGL(kern, dim3(nblocks), dim3(var == 7 ? 256 : 512), 0, st, qa, qb, x, kp,
-                       mp * kp, np * kp, mp, np, s, tiles_m, tiles_n, tri, CrtModuli{});
+                       mp * kp, np * kp, mp, np, s, tiles_m, tiles_n, tri, CrtModuli{}, 1);
     return;
   }
   auto kern = (var == 0)   ? oz_gemm_i8<256, 256, 2, 2>
@@ -1369,26 +1485,36 @@ static void launch_i8_products(int var, unsigned nblocks, const int8_t* qa, cons
 // default).
 static bool crt_variant(int var) { return var == 5 || var == 6 || var == 8; }
 
+// nprod products of residue planes (plane t of both operands into plane t
+// of x), plane t modulo modulus t % count.
 static void launch_crt_products(int var, unsigned nblocks, const int8_t* qa, const int8_t* qb,
-                                int8_t* x, int64_t kp, int64_t mp, int64_t np, int count,
-                                int tiles_m, int tiles_n, int tri, const CrtModuli& cm,
-                                hipStream_t st) {
+                                int8_t* x, int64_t kp, int64_t mp, int64_t np, int nprod,
+                                int count, int tiles_m, int tiles_n, int tri,
+                                const CrtModuli& cm, hipStream_t st) {
   auto kern = (var == 5)   ? oz_gemm_i8_dma<256, 256, 2, 4, 4, false, false, true>
               : (var == 6) ? oz_gemm_i8_dma<256, 256, 2, 4, 4, true, false, true>
                            : oz_gemm_i8_dma<256, 256, 2, 4, 4, true, true, true>;
   hipLaunchKernelGGL(kern, dim3(nblocks), dim3(512), 0, st, qa, qb, (int32_t*)x, kp, mp * kp,
-                     np * kp, mp, np, count, tiles_m, tiles_n, tri, cm);
+                     np * kp, mp, np, nprod, tiles_m, tiles_n, tri, cm, count);
 }
 
 // Residues of one row operand (scale exponents first).
+static void launch_crt_residues(const double* hi, const double* lo, int64_t sr, int64_t sl,
+                                int64_t rows, int64_t k, const int* exps, int8_t* q, int64_t ldq,
+                                int64_t rows_p, int count, int p, const CrtResidueConsts& rc,
+                                hipStream_t st, double sign = 1.0,
+                                const int8_t* add_q = nullptr, int8_t* sum_q = nullptr) {
+  dim3 grid((unsigned)((ldq + 127) / 128), (unsigned)(rows_p / 32));
+  hipLaunchKernelGGL(oz_crt_residues, grid, dim3(512), 0, st, hi, lo, sr, sl, rows, k, exps,
+                     count, p, rc, q, ldq, rows_p * ldq, sign, add_q, sum_q);
+}
+
 static hipError_t crt_operand(const double* hi, const double* lo, int64_t sr, int64_t sl,
                               int64_t rows, int64_t k, int* exps, int8_t* q, int64_t ldq,
                               int64_t rows_p, int count, int p, const CrtResidueConsts& rc,
                               double* part, hipStream_t st) {
   scale_operand(hi, sr, sl, rows, k, exps, part, st);
-  dim3 grid((unsigned)((ldq + 127) / 128), (unsigned)(rows_p / 32));
-  hipLaunchKernelGGL(oz_crt_residues, grid, dim3(512), 0, st, hi, lo, sr, sl, rows, k, exps,
-                     count, p, rc, q, ldq, rows_p * ldq);
+  launch_crt_residues(hi, lo, sr, sl, rows, k, exps, q, ldq, rows_p, count, p, rc, st);
   return hipGetLastError();
 }
 
@@ -1455,11 +1581,76 @@ static int ozaki_crt_gemm(const mpdd_opts* opts, int tri, bool ta, bool tb, int6
   if (e == hipSuccess) {
     const int tiles_m = (int)(mp / i8_tile_rows(var)), tiles_n = (int)(np / i8_tile_cols(var));
     launch_crt_products(var, (unsigned)(oz_group_tiles(tri, tiles_m, tiles_n) * count), qa, qb,
-                        x, kp, mp, np, count, tiles_m, tiles_n, tri, cm, st);
+                        x, kp, mp, np, count, count, tiles_m, tiles_n, tri, cm, st);
     launch_crt_combine(limbs, x, mp, np, count, p, cc, ea, eb, m, n, alpha_hi, alpha_lo, beta_hi,
                        beta_lo, (int)beta_zero, c_hi, c_lo, ldc, tri, st);
     e = hipGetLastError();
   }
+  const hipError_t ef = hipFreeAsync(ws, st);
+  if (e != hipSuccess || ef != hipSuccess) return MPDD_ERR_HIP;
+  return 0;
+}
+
+int ozaki_crt_cgemm(const void* opts_v, int opa, int opb, int64_t m, int64_t n, int64_t k,
+                    const double* const* a, int64_t lda, const double* const* b, int64_t ldb,
+                    double* prh, double* prl, double* pih, double* pil, hipStream_t st,
+                    hipMemPool_t pool) {
+  const mpdd_opts* opts = (const mpdd_opts*)opts_v;
+  const int count = opts->nslices ? opts->nslices : crt_default_count(k, 3);
+  if (count < 1 || count > CRT_MAX_MODULI || k > CRT_MAX_K) return MPDD_ERR_UNSUPPORTED;
+  const int p = crt_exponent(k, count, 3);
+  if (p == 0) return MPDD_ERR_UNSUPPORTED;
+  const int var = opts->tile_id >= 0 ? opts->tile_id : 6;
+  if (!crt_variant(var)) return MPDD_ERR_UNSUPPORTED;
+  CrtResidueConsts rc;
+  CrtModuli cm;
+  CrtCombineConsts cc;
+  const int limbs = crt_constants(count, &rc, &cm, &cc);
+  const int64_t kp = round_up(k, 2 * I8_BK);
+  const int64_t mp = round_up(m, I8_PAD), np = round_up(n, I8_PAD);
+  // three residue sets per operand (re, im, re + im) and three products
+  const size_t qa_bytes = (size_t)3 * count * mp * kp, qb_bytes = (size_t)3 * count * np * kp;
+  const size_t x_bytes = (size_t)3 * count * mp * np;
+  const size_t e_bytes = round_up((m + n) * sizeof(int), 256);
+  const size_t p_bytes = std::max(part_bytes(m, k), part_bytes(n, k));
+  void* ws = nullptr;
+  if (hipMallocFromPoolAsync(&ws, round_up(qa_bytes, 256) + round_up(qb_bytes, 256) + x_bytes +
+                                      e_bytes + p_bytes,
+                             pool, st) != hipSuccess)
+    return MPDD_ERR_ALLOC;
+  int8_t* qa = (int8_t*)ws;
+  int8_t* qb = qa + round_up(qa_bytes, 256);
+  int8_t* x = qb + round_up(qb_bytes, 256);
+  int* ea = (int*)(x + x_bytes);
+  int* eb = ea + m;
+  double* part = (double*)((char*)ea + e_bytes);
+  const int64_t a_sr = opa ? lda : 1, a_sl = opa ? 1 : lda;
+  const int64_t b_sr = opb ? 1 : ldb, b_sl = opb ? ldb : 1;
+  const int64_t sa = (int64_t)count * mp * kp, sb = (int64_t)count * np * kp;
+  // one exponent per row over both parts; the imaginary residues negated for
+  // a conjugated operand, and the residues of re + im formed beside them
+  scale_operand(a[0], a_sr, a_sl, m, k, ea, part, st, a[2]);
+  launch_crt_residues(a[0], a[1], a_sr, a_sl, m, k, ea, qa, kp, mp, count, p, rc, st);
+  launch_crt_residues(a[2], a[3], a_sr, a_sl, m, k, ea, qa + sa, kp, mp, count, p, rc, st,
+                      opa == 2 ? -1.0 : 1.0, qa, qa + 2 * sa);
+  scale_operand(b[0], b_sr, b_sl, n, k, eb, part, st, b[2]);
+  launch_crt_residues(b[0], b[1], b_sr, b_sl, n, k, eb, qb, kp, np, count, p, rc, st);
+  launch_crt_residues(b[2], b[3], b_sr, b_sl, n, k, eb, qb + sb, kp, np, count, p, rc, st,
+                      opb == 2 ? -1.0 : 1.0, qb, qb + 2 * sb);
+  const int tiles_m = (int)(mp / i8_tile_rows(var)), tiles_n = (int)(np / i8_tile_cols(var));
+  launch_crt_products(var, (unsigned)(tiles_m * tiles_n * 3 * count), qa, qb, x, kp, mp, np,
+                      3 * count, count, tiles_m, tiles_n, 0, cm, st);
+  auto kern = (limbs <= 1)   ? oz_crt_combine_c<1>
+              : (limbs == 2) ? oz_crt_combine_c<2>
+              : (limbs == 3) ? oz_crt_combine_c<3>
+              : (limbs == 4) ? oz_crt_combine_c<4>
+              : (limbs == 5) ? oz_crt_combine_c<5>
+              : (limbs == 6) ? oz_crt_combine_c<6>
+                             : oz_crt_combine_c<7>;
+  const unsigned cbk = (unsigned)(((m + 3) / 4 * n + 255) / 256);
+  hipLaunchKernelGGL(kern, dim3(cbk), dim3(256), 0, st, x, mp, np, count, p, cc, cm, ea, eb, m, n,
+                     prh, prl, pih, pil, m);
+  const hipError_t e = hipGetLastError();
   const hipError_t ef = hipFreeAsync(ws, st);
   if (e != hipSuccess || ef != hipSuccess) return MPDD_ERR_HIP;
   return 0;

@@ -276,3 +276,53 @@ def test_crt_moduli_count_search(h, n, dist):
     count, r = crt_search(h, n, dist, 22, 32)
     log(f"CRT n={n} {dist}: moduli={count} ratio={r}")
     assert count is not None and count > 22
+
+
+def _check_close_c(G, R, RP, C0, alpha, beta, idx, what):
+    """Complex entries: each part within 2^-99 ((|alpha_r| + |alpha_i|) |P|_1
+    + (|beta_r| + |beta_i|) |C0|_1) of the oracle's, |.|_1 = |re| + |im|, P the
+    oracle's alpha = 1, beta = 0 product."""
+    pmag = np.abs(RP[0][idx]) + np.abs(RP[2][idx])
+    cmag = np.abs(C0[0][idx]) + np.abs(C0[2][idx])
+    tol = 2.0 ** -99 * ((abs(alpha[0][0]) + abs(alpha[1][0])) * pmag
+                        + (abs(beta[0][0]) + abs(beta[1][0])) * cmag)
+    for part in (0, 2):
+        diff = np.abs((G[part][idx] - R[part][idx]) + (G[part + 1][idx] - R[part + 1][idx]))
+        bad = ~(diff <= tol)
+        assert not bad.any(), (what, part, int(bad.sum()))
+
+
+@pytest.mark.parametrize("op", W.COPS, ids=[a + b for a, b in W.COPS])
+def test_crt_cgemm_matches_crt_oracle(h, op):
+    """Complex modular form (three residue products per modulus): every op
+    form, ragged shapes over several tiles, within the dd rounding of the
+    final steps of the exactly rounded complex modular oracle; the 256 x 256
+    tilings give the same bits."""
+    from paper_2109_13406_amd import binding as b
+    count = 26
+    for (m, n, k, dist) in [(1, 1, 1, "uniform"), (70, 90, 33, "wide"),
+                            (260, 270, 64, "uniform")]:
+        c = W.cgemm_case(4100 + m + k, op[0], op[1], m, n, k, dist=dist)
+        print(f"crt cgemm {op} {m}x{n}x{k} {dist}", flush=True)
+        R = tuple(x.copy() for x in c["C"])
+        CRT.crt_cgemm(op[0], op[1], m, n, k, c["alpha"], c["A"], c["lda"], c["B"], c["ldb"],
+                      c["beta"], R, c["ldc"], count)
+        RP = tuple(np.zeros_like(x) for x in c["C"])
+        CRT.crt_cgemm(op[0], op[1], m, n, k, ((1.0, 0.0), (0.0, 0.0)), c["A"], c["lda"], c["B"],
+                      c["ldb"], ((0.0, 0.0), (0.0, 0.0)), RP, c["ldc"], count)
+        idx = entries_mask(m, n, c["ldc"])
+        first = None
+        for var in TILINGS:
+            A, B, C = (tuple(dev((x,))[0] for x in c[key]) for key in ("A", "B", "C"))
+            info = b.mpdd_Cgemm_ex(h, dict(algo=_algo(), nslices=count, tile_id=var), op[0],
+                                   op[1], m, n, k, c["alpha"], A, c["lda"], B, c["ldb"],
+                                   c["beta"], C, c["ldc"])
+            assert info == 0
+            G = tuple(x.cpu().numpy() for x in C)
+            if first is None:
+                _check_close_c(G, R, RP, c["C"], c["alpha"], c["beta"], idx, (op, m, n, k))
+                first = G
+            else:
+                for p in range(4):
+                    assert np.array_equal(bits(G[p]), bits(first[p])), (op, m, n, k, var)
+    log(f"PARITY crt cgemm {op} within 2^-99 of the complex modular oracle")
