@@ -833,8 +833,11 @@ int mpdd_Rpotrf_nb(mpdd_handle h, const char* uplo, mpdd_int n, double* A_hi, do
 
 // Panel width of the right-looking form (split-form trailing updates), in
 // columns, rounded down to whole blocks (measured at n = 8192 with nb = 64:
-// 1024 against 512 and 2048).
-constexpr int64_t POTRF_PANEL_COLUMNS = 1024;
+// 1024 against 512 and 2048).  A compile-time knob for measurements.
+#ifndef MPDD_POTRF_PANEL_COLUMNS
+#define MPDD_POTRF_PANEL_COLUMNS 1024
+#endif
+constexpr int64_t POTRF_PANEL_COLUMNS = MPDD_POTRF_PANEL_COLUMNS;
 
 int mpdd_Rpotrf_ex(mpdd_handle h, const mpdd_opts* opts, const char* uplo, mpdd_int n,
                    double* A_hi, double* A_lo, mpdd_int lda, mpdd_int nb, mpdd_int* info,

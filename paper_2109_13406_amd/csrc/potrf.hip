@@ -13,8 +13,9 @@
 //   forward elimination of L W = I proceeds in the column order of the
 //   factorisation).  Finishing column c means: pivot d = L(c,c) (after the
 //   updates of columns < c); d <= 0 or NaN -> info = offset + c+1 and stop
-//   (d stays in place); p = sqrt(d); L(c,c) = p; L(i,c) /= p for i > c; row
-//   c of W is divided by p (W(c,c) = 1/p).  Column c then updates the
+//   (d stays in place); p = sqrt(d); L(c,c) = p; L(i,c) *= 1/p for i > c
+//   and row c of W is multiplied by 1/p (W(c,c) = 1/p), with 1/p the dd
+//   reciprocal, formed once.  Column c then updates the
 //   trailing triangle, L(i,l) -= L(i,c) L(l,c) for c < l <= i, and W(i,t) -=
 //   L(i,c) W(c,t) for i > c, t <= c.
 //
@@ -76,19 +77,21 @@ dd_potf2_block(const double* __restrict__ s_hi, const double* __restrict__ s_lo,
   __syncthreads();
 
   const int lane = tid & 63;
-  // finish column 0 (wave 0); a failing pivot is left in place
+  // finish column 0 (wave 0); a failing pivot is left in place.  The column
+  // is scaled by the dd reciprocal of the pivot, which every lane forms (one
+  // division on the dependent path instead of two divergent ones)
   if (tid < 64) {
     const ddv d{lh[0], ll[0]};
     if (d.hi > 0.0) {
       const ddv piv = dd_sqrt(d);
+      const ddv inv = dd_div(ddv{1.0, 0.0}, piv);
       if (lane >= 1 && lane < jb) {
-        const ddv q = dd_div(ddv{lh[pk(lane, 0)], ll[pk(lane, 0)]}, piv);
+        const ddv q = dd_mul(ddv{lh[pk(lane, 0)], ll[pk(lane, 0)]}, inv);
         lh[pk(lane, 0)] = q.hi;
         ll[pk(lane, 0)] = q.lo;
       } else if (lane == 0) {
-        const ddv w = dd_div(ddv{1.0, 0.0}, piv);
-        wh[0] = w.hi;
-        wl[0] = w.lo;
+        wh[0] = inv.hi;
+        wl[0] = inv.lo;
         lh[0] = piv.hi;
         ll[0] = piv.lo;
       }
@@ -127,13 +130,13 @@ dd_potf2_block(const double* __restrict__ s_hi, const double* __restrict__ s_lo,
         const ddv d{__shfl(z.hi, 0), __shfl(z.lo, 0)};
         if (d.hi > 0.0) {
           const ddv piv = dd_sqrt(d);
+          const ddv inv = dd_div(ddv{1.0, 0.0}, piv);     // W(c+1,c+1) = 1 / p
           if (lane == 0) {
-            const ddv w = dd_div(ddv{1.0, 0.0}, piv);     // W(c+1,c+1) = 1 / p
-            wh[pk(c + 1, c + 1)] = w.hi;
-            wl[pk(c + 1, c + 1)] = w.lo;
+            wh[pk(c + 1, c + 1)] = inv.hi;
+            wl[pk(c + 1, c + 1)] = inv.lo;
             z = piv;
           } else if (active) {
-            z = dd_div(z, piv);
+            z = dd_mul(z, inv);
           }
         }
         if (active) {
