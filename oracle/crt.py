@@ -267,3 +267,118 @@ def crt_cgemm(transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, coun
             crh[q], crl[q] = _nearest_dd(vr)
             cih[q], cil[q] = _nearest_dd(vi)
     return C
+
+
+# ---- quad-double operands ------------------------------------------------------------
+#
+# A qd entry x = x0 + x1 + x2 + x3 (four binary64 parts) of row r becomes
+# the integer X' = sum_p rint(x_p 2^(QD_GRID_BITS - sigma_r)) (sigma_r from
+# the row's largest |x0|), |X' - z| <= 2 for the exact scaled value z.  Each
+# part's integer t_p is cut into 26-bit chunks from the top (j = 7 .. 1:
+# c_j = rint(t 2^(-26 j)), t -= c_j 2^(26 j), exact; c_0 = t), C_j = sum_p c_pj,
+# and X' = X1 2^104 + X0 with X0 = sum_{j<4} C_j 2^(26 j), X1 = sum_{j>=4}
+# C_j 2^(26 (j - 4)); |X0|, |X1| < 2^105.01.  The product of two such rows is
+# A 2^208 + (C - A - B) 2^104 + B with A = X1 Y1, B = X0 Y0 and
+# C = (X1 + X0)(Y1 + Y0) (three exact integer products, each below 2^212 k
+# in magnitude), every one rebuilt from its residues: the moduli count must
+# give M >= 2^(215 + ceil(log2 k)).  The result is rounded to the nearest qd
+# greedily (x0 = RN(V), x1 = RN(V - x0), ...).
+
+QD_GRID_BITS = 208
+QD_CHUNK_BITS = 26
+QD_SPLIT_BITS = 104
+
+
+def qd_count_ok(k, count):
+    """Whether `count` moduli recover the three qd sub-products for k terms."""
+    if count < 1 or count > MAX_MODULI:
+        return False
+    lk = max(0, (max(k, 1) - 1).bit_length())
+    return modulus_product(count).bit_length() - 1 >= 215 + lk
+
+
+def qd_scale_exponents(x0_rows):
+    return scale_exponents(x0_rows)
+
+
+def qd_chunks(parts, exps):
+    """The chunk sums C_j (int64 array (8, rows, k)) of the grid integers of a
+    qd row operand given as four (rows x k) part arrays."""
+    sh = (QD_GRID_BITS - exps).astype(np.int64)[:, None]
+    out = np.zeros((8,) + parts[0].shape, dtype=np.int64)
+    for x in parts:
+        t = np.rint(np.ldexp(x, sh))
+        for j in range(7, 0, -1):
+            c = np.rint(np.ldexp(t, -QD_CHUNK_BITS * j))
+            t = t - np.ldexp(c, QD_CHUNK_BITS * j)
+            out[j] += c.astype(np.int64)
+        out[0] += t.astype(np.int64)
+    return out
+
+
+def qd_split(chunks):
+    """(X1, X0) as object arrays of Python ints from the chunk sums."""
+    obj = chunks.astype(object)
+    x0 = sum(obj[j] * (1 << (QD_CHUNK_BITS * j)) for j in range(4))
+    x1 = sum(obj[j] * (1 << (QD_CHUNK_BITS * (j - 4))) for j in range(4, 8))
+    return x1, x0
+
+
+def qd_row_operand(trans, rows, k, X, ld):
+    """The four parts of a qd row operand (rows x k)."""
+    r = np.arange(rows)[:, None]
+    l = np.arange(k)[None, :]
+    idx = (r + l * ld) if trans.upper() == "N" else (l + r * ld)
+    return [p[idx] for p in X]
+
+
+def qd_integer_product(transa, transb, m, n, k, A, lda, B, ldb, count):
+    """Exponents and the exact integer product of the grid integers of op(A)
+    and op(B), from the residues of the three sub-products."""
+    if not qd_count_ok(k, count):
+        raise ValueError("too few moduli for k")
+    pa = qd_row_operand(transa, m, k, A, lda)
+    pb = qd_row_operand("T" if transb.upper() == "N" else "N", n, k, B, ldb)
+    ea, eb = qd_scale_exponents(pa[0]), qd_scale_exponents(pb[0])
+    a1, a0 = qd_split(qd_chunks(pa, ea))
+    b1, b0 = qd_split(qd_chunks(pb, eb))
+    ra = [residues(v, count) for v in (a1, a0, a1 + a0)]
+    rb = [residues(v, count) for v in (b1, b0, b1 + b0)]
+    prods = [[ra[s][t] @ rb[s][t].T for t in range(count)] for s in range(3)]
+    hi, lo, mid = (reconstruct(p, count) for p in prods)
+    X = hi * (1 << (2 * QD_SPLIT_BITS)) + (mid - hi - lo) * (1 << QD_SPLIT_BITS) + lo
+    return ea, eb, X
+
+
+def _nearest_qd(v):
+    out = []
+    for _ in range(4):
+        h = float(v)
+        out.append(h)
+        v = v - Fraction(h)
+    return out
+
+
+def crt_qgemm(transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, count):
+    """qd Rgemm of the modular form: A, B, C four column-major planes, alpha
+    and beta 4-tuples of binary64 parts; C updated in place and returned."""
+    if m == 0 or n == 0:
+        return C
+    a = sum(Fraction(x) for x in alpha)
+    b = sum(Fraction(x) for x in beta)
+    if k == 0 or a == 0:
+        ea = eb = None
+        X = np.zeros((m, n), dtype=object)
+    else:
+        ea, eb, X = qd_integer_product(transa, transb, m, n, k, A, lda, B, ldb, count)
+    for j in range(n):
+        for i in range(m):
+            q = i + j * ldc
+            v = Fraction(0)
+            if X[i, j]:
+                v = a * X[i, j] * Fraction(2) ** int(ea[i] + eb[j] - 2 * QD_GRID_BITS)
+            if b != 0:
+                v += b * sum(Fraction(float(p[q])) for p in C)
+            for p, x in zip(C, _nearest_qd(v)):
+                p[q] = x
+    return C

@@ -294,8 +294,122 @@ def check_cgemm(crt, rng):
                     (ta, tb, i, j)
 
 
+def _qd_matrix(rng, size, wide=False):
+    x0 = rng.uniform(-1.0, 1.0, size)
+    if wide:
+        x0 = np.ldexp(x0, rng.integers(-20, 21, size))
+    parts = [x0]
+    for _ in range(3):
+        parts.append(parts[-1] * rng.uniform(-1.0, 1.0, size) * 2.0 ** -53)
+    return parts
+
+
+def _qd_value(X, q):
+    return sum(Fraction(float(p[q])) for p in X)
+
+
+def check_qd_split(crt, rng):
+    for wide in (False, True):
+        X = _qd_matrix(rng, 6 * 11, wide)
+        parts = [p.reshape(6, 11) for p in X]
+        parts[0][2] = 0.0
+        for p in parts[1:]:
+            p[2] = 0.0
+        e = crt.qd_scale_exponents(parts[0])
+        ch = crt.qd_chunks(parts, e)
+        x1, x0 = crt.qd_split(ch)
+        for r in range(6):
+            for l in range(11):
+                z = sum(Fraction(float(p[r, l])) for p in parts) \
+                    * Fraction(2) ** (crt.QD_GRID_BITS - int(e[r]))
+                xi = sum(int(np.rint(np.ldexp(float(p[r, l]), crt.QD_GRID_BITS - int(e[r]))))
+                         for p in parts)
+                assert sum(int(ch[j, r, l]) << (26 * j) for j in range(8)) == xi
+                assert x1[r, l] * 2 ** 104 + x0[r, l] == xi
+                assert abs(xi - z) <= 2
+                assert abs(x1[r, l]) < Fraction(2) ** 105 * Fraction(1001, 1000)
+                assert abs(x0[r, l]) < Fraction(2) ** 105 * Fraction(1001, 1000)
+
+
+def check_qd_count(crt):
+    for k in (1, 100, 2048, 8192, 131071):
+        k2 = 1 << max(0, (k - 1).bit_length())
+        for count in range(20, crt.MAX_MODULI + 1):
+            M = crt.modulus_product(count)
+            ok = crt.qd_count_ok(k, count)
+            # the three sub-products lie in [-M/4, M/4]: 4 k (2 * 2^105.01)^2 <= M
+            big = 4 * k2 * (2 ** 106 + 2 ** 99) ** 2
+            assert ok == (M.bit_length() - 1 >= 215 + (k2.bit_length() - 1))
+            if ok:
+                assert big <= M
+
+
+def check_qd_integer_product(crt, rng):
+    m, n, k, count = 3, 4, 7, 31
+    A = _qd_matrix(rng, m * k, wide=True)
+    B = _qd_matrix(rng, n * k)
+    ea, eb, X = crt.qd_integer_product("N", "T", m, n, k, A, m, B, n, count)
+    pa = crt.qd_row_operand("N", m, k, A, m)
+    pb = crt.qd_row_operand("N", n, k, B, n)
+    a1, a0 = crt.qd_split(crt.qd_chunks(pa, ea))
+    b1, b0 = crt.qd_split(crt.qd_chunks(pb, eb))
+    plain = (a1 * 2 ** 104 + a0).dot((b1 * 2 ** 104 + b0).T)     # big-integer product
+    for i in range(m):
+        for j in range(n):
+            assert X[i, j] == plain[i, j]
+
+
+def check_qgemm(crt, rng):
+    for (ta, tb, m, n, k, count) in (("N", "N", 3, 4, 6, 30), ("T", "T", 2, 3, 5, 31)):
+        A = _qd_matrix(rng, m * k, wide=True)
+        B = _qd_matrix(rng, k * n)
+        C = _qd_matrix(rng, m * n)
+        lda = m if ta == "N" else k
+        ldb = k if tb == "N" else n
+        alpha = (0.75, 2.0 ** -60, 0.0, 0.0)
+        beta = (-1.25, 0.0, 0.0, 0.0)
+        out = crt.crt_qgemm(ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, [p.copy() for p in C],
+                            m, count)
+        a = sum(Fraction(x) for x in alpha)
+        b = sum(Fraction(x) for x in beta)
+        def opa(i, l):
+            return _qd_value(A, i + l * lda if ta == "N" else l + i * lda)
+        def opb(l, j):
+            return _qd_value(B, l + j * ldb if tb == "N" else j + l * ldb)
+        ea = [int(np.frexp(max(abs(float(A[0][i + l * lda if ta == "N" else l + i * lda]))
+                                  for l in range(k)))[1]) for i in range(m)]
+        eb = [int(np.frexp(max(abs(float(B[0][l + j * ldb if tb == "N" else j + l * ldb]))
+                                  for l in range(k)))[1]) for j in range(n)]
+        for i in range(m):
+            for j in range(n):
+                da = 2 * Fraction(2) ** (ea[i] - crt.QD_GRID_BITS)
+                db = 2 * Fraction(2) ** (eb[j] - crt.QD_GRID_BITS)
+                exact = sum(opa(i, l) * opb(l, j) for l in range(k))
+                bound = sum(da * abs(opb(l, j)) + db * abs(opa(i, l)) + da * db for l in range(k))
+                want = a * exact + b * _qd_value(C, i + j * m)
+                got = _qd_value(out, i + j * m)
+                assert abs(got - want) <= abs(a) * bound + abs(want) * Fraction(1, 2 ** 210), \
+                    (ta, tb, i, j)
+
+
 def test_moduli():
     check_moduli(CRT)
+
+
+def test_qd_split_chunks_and_bounds():
+    check_qd_split(CRT, np.random.default_rng(18))
+
+
+def test_qd_moduli_count():
+    check_qd_count(CRT)
+
+
+def test_qd_integer_product_equals_big_integer_product():
+    check_qd_integer_product(CRT, np.random.default_rng(19))
+
+
+def test_qgemm_within_grid_rounding_of_exact_product():
+    check_qgemm(CRT, np.random.default_rng(20))
 
 
 def test_complex_exponents_and_margin():
@@ -383,6 +497,17 @@ MUTANTS = [
      "conjugation of op(B) lost"),
     ("vr, vi = ar * pr - ai * pi, ar * pi + ai * pr", "vr, vi = ar * pr + ai * pi, ar * pi + ai * pr",
      "complex alpha sign"),
+    ("            t = t - np.ldexp(c, QD_CHUNK_BITS * j)",
+     "            t = t - np.ldexp(c, QD_CHUNK_BITS * j - 1)", "qd chunk removed at the wrong weight"),
+    ("    for x in parts:\n        t = np.rint", "    for x in parts[:3]:\n        t = np.rint",
+     "qd last part dropped"),
+    ("(mid - hi - lo) * (1 << QD_SPLIT_BITS)", "(mid - hi + lo) * (1 << QD_SPLIT_BITS)",
+     "qd three-product sign"),
+    ("return modulus_product(count).bit_length() - 1 >= 215 + lk",
+     "return modulus_product(count).bit_length() - 1 >= 205 + lk", "qd moduli margin"),
+    ("    x1 = sum(obj[j] * (1 << (QD_CHUNK_BITS * (j - 4))) for j in range(4, 8))",
+     "    x1 = sum(obj[j] * (1 << (QD_CHUNK_BITS * (j - 3))) for j in range(4, 8))",
+     "qd high half misplaced"),
 ]
 
 CHECKS = [("moduli", lambda c, r: check_moduli(c)),
@@ -394,7 +519,11 @@ CHECKS = [("moduli", lambda c, r: check_moduli(c)),
           ("rgemm", check_rgemm),
           ("complex_exponents", lambda c, r: check_complex_exponents(c)),
           ("complex_integer_product", check_complex_integer_product),
-          ("cgemm", check_cgemm)]
+          ("cgemm", check_cgemm),
+          ("qd_split", check_qd_split),
+          ("qd_count", lambda c, r: check_qd_count(c)),
+          ("qd_integer_product", check_qd_integer_product),
+          ("qgemm", check_qgemm)]
 
 
 def _load_copy(text, tmp):
