@@ -695,6 +695,15 @@ def bench_qd(h, args, stream):
                            "speedup_vs_plain": round(t / ts, 3)}
     else:
         out["split_i8"] = {"nslices": None}
+    # modular form: the fewest moduli that recover its three sub-products
+    # (the library's default), checked against the oracle, then timed
+    opts_c = dict(algo=b.MPDD_OZAKI_CRT, nslices=0)
+    rc_ = checked(opts_c)
+    tc = timed(opts_c)
+    out["split_crt"] = {"moduli": "default (30 at k = 2048)", "residue_products": 90,
+                        "ratio_vs_oracle": round(rc_, 5), "ms": round(tc * 1e3, 3),
+                        "qd_gflops": round(2.0 * n ** 3 / tc / 1e9, 1),
+                        "speedup_vs_plain": round(t / tc, 3)}
     log(f"qgemm {out}")
     del A, B, C, C0
     torch.cuda.empty_cache()

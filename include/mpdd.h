@@ -293,7 +293,16 @@ int mpdd_Qgemm(mpdd_handle h, const char *transa, const char *transb, mpdd_int m
  * beta C is formed in qd.  Device scratch of about
  * nslices ((m + n) k + 4 m n) bytes (padded), stream ordered.  MPDD_ERR_ARG
  * for another algo; MPDD_ERR_UNSUPPORTED for a slice count or tile_id out
- * of range or nslices * k >= 2^19. */
+ * of range or nslices * k >= 2^19.
+ * opts->algo MPDD_OZAKI_CRT: the modular form -- each entry becomes the
+ * integer X' = sum_p rint(x_p 2^(208 - sigma)) (sigma from the row's largest
+ * |x0|), cut at 2^104 into X1 2^104 + X0 by 26-bit chunks; residues of X1,
+ * X0 and X1 + X0 modulo opts->nslices moduli (0 = the fewest that recover
+ * the sub-products: M >= 2^(215 + ceil(log2 k)), 30 at k = 2048; fewer return
+ * MPDD_ERR_UNSUPPORTED), three INT8 residue products per modulus, the exact
+ * product A 2^208 + (C - A - B) 2^104 + B rebuilt from A = X1 Y1, B = X0 Y0,
+ * C = (X1 + X0)(Y1 + Y0), summed into a qd, scaled back, C = alpha P +
+ * beta C in qd; tile_id 5, 6 or 8; k < 2^17. */
 int mpdd_Qgemm_ex(mpdd_handle h, const mpdd_opts *opts, const char *transa, const char *transb,
                   mpdd_int m, mpdd_int n, mpdd_int k, mpdd_qd alpha, const double *A0,
                   const double *A1, const double *A2, const double *A3, mpdd_int lda,

@@ -31,6 +31,20 @@ struct CrtResidueConsts {
   double c26[CRT_MAX_MODULI], c52[CRT_MAX_MODULI], c78[CRT_MAX_MODULI];
 };
 
+// Reconstruction constants in 26-bit limbs (the qd form, whose three
+// sub-products are recombined limb-wise at offsets of 104 = 4 x 26 bits).
+constexpr int CRT_LIMB26 = 26;
+constexpr int CRT_MAX_LIMBS26 = 10;     // 10 * 26 >= 257
+struct CrtCombineConsts26 {
+  double w[CRT_MAX_MODULI][CRT_MAX_LIMBS26];
+  double ml[CRT_MAX_LIMBS26], g[CRT_MAX_LIMBS26];
+};
+
+// The qd form: grid of 208 bits, split at 2^104; its three sub-products
+// (each below 2^212 k in magnitude) are recovered when M >= 2^(215 +
+// ceil(log2 k)).
+constexpr int CRT_QD_GRID_BITS = 208;
+
 // The moduli and their reciprocals, for the products' reduction.
 struct CrtModuli {
   double m[CRT_MAX_MODULI], minv[CRT_MAX_MODULI];
@@ -186,6 +200,52 @@ inline int crt_constants(int count, CrtResidueConsts* rc, CrtModuli* cm, CrtComb
   return limbs;
 }
 
+inline bool crt_qd_count_ok(int64_t k, int count) {
+  if (count < 1 || count > CRT_MAX_MODULI) return false;
+  int lk = 0;
+  while (((int64_t)1 << lk) < k) ++lk;
+  return crt_modulus_product(count).bits() - 1 >= 215 + lk;
+}
+
+inline int crt_qd_default_count(int64_t k) {
+  for (int c = 1; c <= CRT_MAX_MODULI; ++c)
+    if (crt_qd_count_ok(k, c)) return c;
+  return 0;
+}
+
+// CRT weights and M in 26-bit limbs for `count` moduli.
+inline void crt_constants26(int count, CrtCombineConsts26* cc) {
+  int ms[CRT_MAX_MODULI];
+  crt_moduli(count, ms);
+  const CrtBig M = crt_modulus_product(count);
+  for (int t = 0; t < CRT_MAX_MODULI; ++t) {
+    for (int l = 0; l < CRT_MAX_LIMBS26; ++l) cc->w[t][l] = 0.0;
+    if (t >= count) continue;
+    const int m = ms[t];
+    CrtBig Mt = M;
+    Mt.divmod((uint32_t)m);
+    CrtBig tmp = Mt;
+    const int64_t r = tmp.divmod((uint32_t)m);
+    int64_t a = r, b = m, x0 = 1, x1 = 0;
+    while (b) {
+      const int64_t q = a / b, ta = a - q * b, tx = x0 - q * x1;
+      a = b;
+      b = ta;
+      x0 = x1;
+      x1 = tx;
+    }
+    CrtBig W = Mt;
+    W.mul((uint32_t)(((x0 % m) + m) % m));
+    for (int l = 0; l < CRT_MAX_LIMBS26; ++l)
+      cc->w[t][l] = (double)W.field(CRT_LIMB26 * l, CRT_LIMB26);
+  }
+  const double minv = 1.0 / M.approx();
+  for (int l = 0; l < CRT_MAX_LIMBS26; ++l) {
+    cc->ml[l] = (double)M.field(CRT_LIMB26 * l, CRT_LIMB26);
+    cc->g[l] = std::ldexp(minv, CRT_LIMB26 * l);
+  }
+}
+
 // Complex modular product (ozaki.hip): P = op(A) op(B) of complex dd
 // operands (planes re.hi, re.lo, im.hi, im.lo; op 0 'N', 1 'T', 2 'C') into
 // the dd planes (prh, prl) + i (pih, pil), leading dimension m, with three
@@ -194,5 +254,13 @@ int ozaki_crt_cgemm(const void* opts, int opa, int opb, int64_t m, int64_t n, in
                     const double* const* a, int64_t lda, const double* const* b, int64_t ldb,
                     double* prh, double* prl, double* pih, double* pil, hipStream_t st,
                     hipMemPool_t pool);
+
+// qd modular product (ozaki.hip): C = alpha op(A) op(B) + beta C on qd
+// planes (x0..x3), three residue products per modulus (Karatsuba on the
+// 2^104 split).  k >= 1, alpha != 0.
+int ozaki_crt_qgemm(const void* opts, bool ta, bool tb, int64_t m, int64_t n, int64_t k,
+                    const double* alpha, const double* const* a, int64_t lda,
+                    const double* const* b, int64_t ldb, const double* beta, int beta_zero,
+                    double* const* c, int64_t ldc, hipStream_t st, hipMemPool_t pool);
 
 }  // namespace mpdd

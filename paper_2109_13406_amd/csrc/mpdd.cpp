@@ -916,7 +916,7 @@ int mpdd_Qgemm_ex(mpdd_handle h, const mpdd_opts* opts, const char* transa, cons
   if (info) return info;
   if (!handle_ok(h)) return MPDD_ERR_HANDLE;
   const int algo = opts ? opts->algo : MPDD_PLAIN;
-  if (algo != MPDD_PLAIN && algo != MPDD_OZAKI_I8) return MPDD_ERR_ARG;
+  if (algo != MPDD_PLAIN && algo != MPDD_OZAKI_I8 && algo != MPDD_OZAKI_CRT) return MPDD_ERR_ARG;
   auto qzero = [](const mpdd_qd& x) { return x.x[0] == 0 && x.x[1] == 0 && x.x[2] == 0 && x.x[3] == 0; };
   const bool alpha_zero = qzero(alpha), beta_zero = qzero(beta);
   const bool beta_one = beta.x[0] == 1.0 && beta.x[1] == 0 && beta.x[2] == 0 && beta.x[3] == 0;
@@ -935,6 +935,10 @@ int mpdd_Qgemm_ex(mpdd_handle h, const mpdd_opts* opts, const char* transa, cons
   p.c[0] = C0; p.c[1] = C1; p.c[2] = C2; p.c[3] = C3; p.ldc = ldc;
   p.beta_zero = beta_zero ? 1 : 0;
   p.scale_only = use_ab ? 0 : 1;
+  if (algo == MPDD_OZAKI_CRT && use_ab)
+    return ozaki_crt_qgemm(opts, !lsame(transa, 'N'), !lsame(transb, 'N'), m, n, k, p.alpha,
+                           p.a, lda, p.b, ldb, p.beta, p.beta_zero, p.c, ldc,
+                           (hipStream_t)stream, h->pool);
   if (algo == MPDD_OZAKI_I8 && use_ab)
     return ozaki_qgemm(opts, !lsame(transa, 'N'), !lsame(transb, 'N'), m, n, k, p.alpha, p.a,
                        lda, p.b, ldb, p.beta, p.beta_zero, p.c, ldc, (hipStream_t)stream,

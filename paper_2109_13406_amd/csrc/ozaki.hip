@@ -1393,6 +1393,199 @@ oz_crt_combine_c(const int8_t* __restrict__ x, int64_t mp, int64_t np, int count
   }
 }
 
+// qd row operand: residues of X1, X0 and X1 + X0, where X' = X1 2^104 + X0
+// is the entry's integer on the grid of 208 bits below 2^sigma_r: each part
+// x_p gives t_p = rint(x_p 2^(208 - sigma_r)) (exact scaling), cut into 26-bit
+// chunks from the top (j = 7 .. 1: c = rint(t 2^(-26 j)), t -= c 2^(26 j),
+// exact; the rest is chunk 0); C_j = sum_p c_pj (|C_j| < 2^28), X0 = sum_{j<4}
+// C_j 2^(26 j), X1 = sum_{j>=4} C_j 2^(26 (j-4)).  Per modulus
+// y1 = C4 + C5 c26 + C6 c52 + C7 c78 and y0 likewise (< 2^38, exact), each
+// reduced as in oz_crt_residues, and the balanced sum of the two residues.
+// Planes: X1 residues at q1, X0 at q0, the sums at qs (each count planes of
+// rows_p x ldq).  Two of the four parts are staged in LDS at a time
+// (37 KB, so the registers, not the LDS, bound the workgroups per CU); a
+// thread converts 4 consecutive l of one row (block: 32 rows x
+// 64 l) and stores one 4-byte word per modulus and set.
+__global__ void __launch_bounds__(512, 2)
+oz_crt_residues_qd(const double* __restrict__ x0, const double* __restrict__ x1,
+                   const double* __restrict__ x2, const double* __restrict__ x3, int64_t sr,
+                   int64_t sl, int64_t rows, int64_t k, const int* __restrict__ exps, int count,
+                   CrtResidueConsts cst, int8_t* __restrict__ q1, int8_t* __restrict__ q0,
+                   int8_t* __restrict__ qs, int64_t ldq, int64_t plane) {
+  constexpr int PITCH = 73;                    // 64 columns + one pad per 8
+  __shared__ double t[2][32][PITCH];
+  auto col = [](int l) { return l + (l >> 3); };
+  const int tid = threadIdx.x;
+  const int64_t r0 = (int64_t)blockIdx.y * 32;
+  const int64_t l0 = (int64_t)blockIdx.x * 64;
+  const bool lanes_on_r = (sr == 1);
+  const int row = tid >> 4, lq = (tid & 15) * 4;
+  const int sh = CRT_QD_GRID_BITS - ((r0 + row < rows) ? exps[r0 + row] : 0);
+  double C[8][4];
+#pragma unroll
+  for (int j = 0; j < 8; ++j)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) C[j][i] = 0.0;
+#pragma unroll
+  for (int pair = 0; pair < 2; ++pair) {
+    if (pair) __syncthreads();                 // the first pair has been read
+    double v[2][4];
+#pragma unroll
+    for (int half = 0; half < 2; ++half) {
+      const double* __restrict__ src = pair ? (half ? x3 : x2) : (half ? x1 : x0);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const int e = tid + 512 * c;           // 0 .. 2047 over the 32 x 64 block
+        const int ri = lanes_on_r ? (e & 31) : (e >> 6);
+        const int li = lanes_on_r ? (e >> 5) : (e & 63);
+        const int64_t rg = r0 + ri, lg = l0 + li;
+        v[half][c] = (rg < rows && lg < k) ? src[rg * sr + lg * sl] : 0.0;
+      }
+    }
+#pragma unroll
+    for (int half = 0; half < 2; ++half)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const int e = tid + 512 * c;
+        const int ri = lanes_on_r ? (e & 31) : (e >> 6);
+        const int li = lanes_on_r ? (e >> 5) : (e & 63);
+        t[half][ri][col(li)] = v[half][c];
+      }
+    __syncthreads();
+#pragma unroll
+    for (int half = 0; half < 2; ++half)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        double tv = rint(ldexp(t[half][row][col(lq) + i], sh));
+#pragma unroll
+        for (int j = 7; j >= 1; --j) {
+          const double c = rint(ldexp(tv, -26 * j));
+          tv = fma(-c, ldexp(1.0, 26 * j), tv);
+          C[j][i] += c;
+        }
+        C[0][i] += tv;
+      }
+  }
+  if (l0 + lq >= ldq) return;
+  const int64_t off = (r0 + row) * ldq + l0 + lq;
+#pragma unroll
+  for (int m = 0; m < CRT_MAX_MODULI; ++m) {
+    if (m >= count) break;
+    const double mm = cst.m[m], mi = cst.minv[m];
+    const int mint = (int)mm, h = (mint - 1) / 2;
+    uint32_t w1 = 0u, w0 = 0u, ws = 0u;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const double y1 = fma(C[7][i], cst.c78[m], fma(C[6][i], cst.c52[m],
+                                                      fma(C[5][i], cst.c26[m], C[4][i])));
+      const double y0 = fma(C[3][i], cst.c78[m], fma(C[2][i], cst.c52[m],
+                                                      fma(C[1][i], cst.c26[m], C[0][i])));
+      const int a = (int)fma(-rint(y1 * mi), mm, y1), b = (int)fma(-rint(y0 * mi), mm, y0);
+      int sum = a + b;
+      if (m > 0) sum = (sum > h) ? sum - mint : (sum < -h) ? sum + mint : sum;
+      w1 |= ((uint32_t)a & 0xFFu) << (8 * i);
+      w0 |= ((uint32_t)b & 0xFFu) << (8 * i);
+      ws |= ((uint32_t)sum & 0xFFu) << (8 * i);
+    }
+    *(uint32_t*)(q1 + (int64_t)m * plane + off) = w1;
+    *(uint32_t*)(q0 + (int64_t)m * plane + off) = w0;
+    *(uint32_t*)(qs + (int64_t)m * plane + off) = ws;
+  }
+}
+
+// qd reconstruction, one entry per thread: the residues of A = X1 Y1 (planes
+// 0 .. count-1), B = X0 Y0 (count ..) and C = (X1 + X0)(Y1 + Y0) (2 count ..)
+// give each of the three exactly in 26-bit limbs, as in crt_limbs_to_dd
+// (|S_l| < 2^39; q M_l < 2^39), with carries into balanced limbs; then the
+// product A 2^208 + (C - A - B) 2^104 + B limb by limb (offsets 8 and 4
+// limbs), carried again, and the limbs, scaled by 2^(26 l + sigma_i + tau_j
+// - 416), added into a qd from the lowest up (TwoSum cascade and
+// renormalisation per limb); then C = alpha P + beta C in qd as
+// oz_combine_qd.
+__global__ void __launch_bounds__(256)
+oz_crt_combine_qdm(const int8_t* __restrict__ x, int64_t mp, int64_t np, int count,
+                   CrtCombineConsts26 cst, const int* __restrict__ ea,
+                   const int* __restrict__ eb, int64_t m, int64_t n, double4 alpha, double4 beta,
+                   int beta_zero, double* __restrict__ c0, double* __restrict__ c1,
+                   double* __restrict__ c2, double* __restrict__ c3, int64_t ldc) {
+  constexpr int L = CRT_MAX_LIMBS26;
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= m * n) return;
+  const int64_t i = gid % m, j = gid / m;
+  const int64_t plane = mp * np;
+  const int8_t* xp = x + j * mp + i;
+  double sa[L], sb[L], sc[L];
+#pragma unroll
+  for (int l = 0; l < L; ++l) sa[l] = sb[l] = sc[l] = 0.0;
+#pragma unroll
+  for (int t = 0; t < CRT_MAX_MODULI; ++t) {
+    if (t >= count) break;
+    const double ra = (double)xp[(int64_t)t * plane];
+    const double rb = (double)xp[(int64_t)(count + t) * plane];
+    const double rc = (double)xp[(int64_t)(2 * count + t) * plane];
+#pragma unroll
+    for (int l = 0; l < L; ++l) {
+      sa[l] = fma(ra, cst.w[t][l], sa[l]);
+      sb[l] = fma(rb, cst.w[t][l], sb[l]);
+      sc[l] = fma(rc, cst.w[t][l], sc[l]);
+    }
+  }
+  // each sum minus its multiple of M, exact limbs
+  auto finish = [&](double (&s)[L]) {
+    double est = 0.0;
+#pragma unroll
+    for (int l = L - 1; l >= 0; --l) est = fma(s[l], cst.g[l], est);
+    const double qm = rint(est);
+#pragma unroll
+    for (int l = 0; l < L; ++l) s[l] = fma(-qm, cst.ml[l], s[l]);
+  };
+  finish(sa);
+  finish(sb);
+  finish(sc);
+  // P = A 2^208 + (C - A - B) 2^104 + B in limbs of 26 bits
+  constexpr int T = L + 8;
+  double tl[T];
+#pragma unroll
+  for (int l = 0; l < T; ++l) tl[l] = 0.0;
+#pragma unroll
+  for (int l = 0; l < L; ++l) {
+    tl[l] += sb[l];
+    tl[l + 4] += sc[l] - sa[l] - sb[l];
+    tl[l + 8] += sa[l];
+  }
+#pragma unroll
+  for (int l = 0; l + 1 < T; ++l) {
+    const double c = rint(tl[l] * 0x1p-26);
+    tl[l] = fma(-c, 0x1p26, tl[l]);
+    tl[l + 1] += c;
+  }
+  const int e = ea[i] + eb[j] - 2 * CRT_QD_GRID_BITS;
+  qacc p{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int l = 0; l < T; ++l) {
+    const double v = ldexp(tl[l], 26 * l + e);
+    double er;
+    ts(p.s0, v, p.s0, er);
+    ts(p.s1, er, p.s1, er);
+    ts(p.s2, er, p.s2, er);
+    p.s3 = p.s3 + er;
+    qd_renorm(p);
+  }
+  const double4 ps = qd_final(p);
+  const int64_t ci = i + j * ldc;
+  qacc r{0.0, 0.0, 0.0, 0.0};
+  qd_madd(r, alpha, ps);
+  if (!beta_zero) {
+    qd_renorm(r);
+    qd_madd(r, beta, double4{c0[ci], c1[ci], c2[ci], c3[ci]});
+  }
+  const double4 o = qd_final(r);
+  c0[ci] = o.x;
+  c1[ci] = o.y;
+  c2[ci] = o.z;
+  c3[ci] = o.w;
+}
+
 // ---- host orchestration -------------------------------------------------------------
 
 static int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
@@ -1650,6 +1843,64 @@ int ozaki_crt_cgemm(const void* opts_v, int opa, int opb, int64_t m, int64_t n, 
   const unsigned cbk = (unsigned)(((m + 3) / 4 * n + 255) / 256);
   hipLaunchKernelGGL(kern, dim3(cbk), dim3(256), 0, st, x, mp, np, count, p, cc, cm, ea, eb, m, n,
                      prh, prl, pih, pil, m);
+  const hipError_t e = hipGetLastError();
+  const hipError_t ef = hipFreeAsync(ws, st);
+  if (e != hipSuccess || ef != hipSuccess) return MPDD_ERR_HIP;
+  return 0;
+}
+
+int ozaki_crt_qgemm(const void* opts_v, bool ta, bool tb, int64_t m, int64_t n, int64_t k,
+                    const double* alpha, const double* const* a, int64_t lda,
+                    const double* const* b, int64_t ldb, const double* beta, int beta_zero,
+                    double* const* c, int64_t ldc, hipStream_t st, hipMemPool_t pool) {
+  const mpdd_opts* opts = (const mpdd_opts*)opts_v;
+  const int count = opts->nslices ? opts->nslices : crt_qd_default_count(k);
+  if (k > CRT_MAX_K || !crt_qd_count_ok(k, count)) return MPDD_ERR_UNSUPPORTED;
+  const int var = opts->tile_id >= 0 ? opts->tile_id : 6;
+  if (!crt_variant(var)) return MPDD_ERR_UNSUPPORTED;
+  CrtResidueConsts rc;
+  CrtModuli cm;
+  CrtCombineConsts cc;
+  crt_constants(count, &rc, &cm, &cc);
+  CrtCombineConsts26 c26;
+  crt_constants26(count, &c26);
+  const int64_t kp = round_up(k, 2 * I8_BK);
+  const int64_t mp = round_up(m, I8_PAD), np = round_up(n, I8_PAD);
+  const size_t qa_bytes = (size_t)3 * count * mp * kp, qb_bytes = (size_t)3 * count * np * kp;
+  const size_t x_bytes = (size_t)3 * count * mp * np;
+  const size_t e_bytes = round_up((m + n) * sizeof(int), 256);
+  const size_t p_bytes = std::max(part_bytes(m, k), part_bytes(n, k));
+  void* ws = nullptr;
+  if (hipMallocFromPoolAsync(&ws, round_up(qa_bytes, 256) + round_up(qb_bytes, 256) + x_bytes +
+                                      e_bytes + p_bytes,
+                             pool, st) != hipSuccess)
+    return MPDD_ERR_ALLOC;
+  int8_t* qa = (int8_t*)ws;
+  int8_t* qb = qa + round_up(qa_bytes, 256);
+  int8_t* x = qb + round_up(qb_bytes, 256);
+  int* ea = (int*)(x + x_bytes);
+  int* eb = ea + m;
+  double* part = (double*)((char*)ea + e_bytes);
+  const int64_t a_sr = ta ? lda : 1, a_sl = ta ? 1 : lda;
+  const int64_t b_sr = tb ? 1 : ldb, b_sl = tb ? ldb : 1;
+  const int64_t sa = (int64_t)count * mp * kp, sb = (int64_t)count * np * kp;
+  // residue sets: X1 (planes 0 ..), X0 (count ..), X1 + X0 (2 count ..)
+  scale_operand(a[0], a_sr, a_sl, m, k, ea, part, st);
+  hipLaunchKernelGGL(oz_crt_residues_qd, dim3((unsigned)(kp / 64), (unsigned)(mp / 32)),
+                     dim3(512), 0, st, a[0], a[1], a[2], a[3], a_sr, a_sl, m, k, ea, count, rc,
+                     qa, qa + sa, qa + 2 * sa, kp, mp * kp);
+  scale_operand(b[0], b_sr, b_sl, n, k, eb, part, st);
+  hipLaunchKernelGGL(oz_crt_residues_qd, dim3((unsigned)(kp / 64), (unsigned)(np / 32)),
+                     dim3(512), 0, st, b[0], b[1], b[2], b[3], b_sr, b_sl, n, k, eb, count, rc,
+                     qb, qb + sb, qb + 2 * sb, kp, np * kp);
+  const int tiles_m = (int)(mp / i8_tile_rows(var)), tiles_n = (int)(np / i8_tile_cols(var));
+  launch_crt_products(var, (unsigned)(tiles_m * tiles_n * 3 * count), qa, qb, x, kp, mp, np,
+                      3 * count, count, tiles_m, tiles_n, 0, cm, st);
+  hipLaunchKernelGGL(oz_crt_combine_qdm, dim3((unsigned)((m * n + 255) / 256)), dim3(256), 0, st,
+                     x, mp, np, count, c26, ea, eb, m, n,
+                     double4{alpha[0], alpha[1], alpha[2], alpha[3]},
+                     double4{beta[0], beta[1], beta[2], beta[3]}, beta_zero, c[0], c[1], c[2],
+                     c[3], ldc);
   const hipError_t e = hipGetLastError();
   const hipError_t ef = hipFreeAsync(ws, st);
   if (e != hipSuccess || ef != hipSuccess) return MPDD_ERR_HIP;

@@ -278,3 +278,94 @@ def test_qgemm_split_2048_slice_search(h, dist):
             found = s
             break
     assert found is not None and found > 24
+
+
+# ---- modular split form (residues of the 2^104 halves, three products) ------------------
+
+def qgemm_crt_gpu(h, c, count=0, tile_id=-1):
+    from paper_2109_13406_amd import binding as b
+    C = dev4(c["C"])
+    info = b.mpdd_Qgemm(h, c["transa"], c["transb"], c["m"], c["n"], c["k"], c["alpha"],
+                        dev4(c["A"]), c["lda"], dev4(c["B"]), c["ldb"], c["beta"], C, c["ldc"],
+                        opts=dict(algo=b.MPDD_OZAKI_CRT, nslices=count, tile_id=tile_id))
+    return info, host4(C)
+
+
+@pytest.mark.parametrize("op", W.OPS)
+def test_qgemm_crt_matches_modular_oracle(h, op):
+    """qd modular form with 30 moduli: within 2^-200 (|alpha| |P| + |beta| |C|)
+    of the modular oracle's exactly rounded result (the three sub-products
+    are exact; only the limb sum in qd and the alpha / beta update round) on
+    ragged shapes over several tiles, both input sets; within 8 k 2^-209 of
+    the plain qd oracle; the 256 x 256 tilings give the same bits."""
+    from oracle import crt as CRT
+    count = 30
+    for (m, n, k, dist) in [(1, 1, 1, "uniform"), (70, 90, 33, "wide"), (260, 270, 64, "uniform")]:
+        c = W.qgemm_case(7300 + m + k, op[0], op[1], m, n, k, dist=dist)
+        print(f"crt qgemm {op} {m}x{n}x{k} {dist}", flush=True)
+        R = [p.copy() for p in c["C"]]
+        CRT.crt_qgemm(op[0], op[1], m, n, k, c["alpha"], c["A"], c["lda"], c["B"], c["ldb"],
+                      c["beta"], R, c["ldc"], count)
+        RP = [np.zeros_like(p) for p in c["C"]]
+        CRT.crt_qgemm(op[0], op[1], m, n, k, (1.0, 0.0, 0.0, 0.0), c["A"], c["lda"], c["B"],
+                      c["ldb"], (0.0,) * 4, RP, c["ldc"], count)
+        idx = stored(m, n, c["ldc"])
+        first = None
+        for tile in (5, 6, 8):
+            info, G = qgemm_crt_gpu(h, c, count, tile)
+            assert info == 0
+            if first is None:
+                d = sum(G[t][idx] - R[t][idx] for t in range(4))
+                tol = 2.0 ** -200 * (abs(c["alpha"][0]) * np.abs(RP[0][idx])
+                                     + abs(c["beta"][0]) * np.abs(c["C"][0][idx]))
+                assert np.all(np.abs(d) <= tol), (op, m, n, k, dist)
+                O = qgemm_oracle(c)
+                r = compare(f"crt {count} {op} {m}x{n}x{k} {dist}", G, O, c["C"], m, n, k,
+                            c["ldc"])
+                assert r <= RATIO_MAX, (op, m, n, k, dist, r)
+                first = G
+            else:
+                for g, f in zip(G, first):
+                    assert np.array_equal(bits(g), bits(f)), (op, m, n, k, tile)
+
+
+def test_qgemm_crt_semantics(h):
+    """beta = 0 never reads C (all NaN); alpha = 0 as the plain form; too few
+    moduli for k, more than 32, and the tilings the form does not run on are
+    rejected with nothing written."""
+    from paper_2109_13406_amd import binding as b
+    c = W.qgemm_case(7400, "T", "N", 21, 18, 12, beta_zero=True, c_nan=True)
+    O = qgemm_oracle(c)
+    info, G = qgemm_crt_gpu(h, c)
+    assert info == 0
+    assert compare("crt beta0", G, O, c["C"], 21, 18, 12, c["ldc"]) <= RATIO_MAX
+    c = W.qgemm_case(7401, "N", "T", 13, 11, 7)
+    c["alpha"] = (0.0,) * 4
+    O = qgemm_oracle(c)
+    info, G = qgemm_crt_gpu(h, c)
+    assert info == 0
+    assert compare("crt alpha0", G, O, c["C"], 13, 11, 1, c["ldc"]) <= RATIO_MAX
+    c = W.qgemm_case(7402, "N", "N", 9, 9, 9)
+    for count, tile in ((28, -1), (33, -1), (30, 0), (30, 7)):
+        info, G = qgemm_crt_gpu(h, c, count, tile)
+        assert info == b.MPDD_ERR_UNSUPPORTED, (count, tile)
+        for g, c0 in zip(G, c["C"]):
+            assert np.array_equal(bits(g), bits(c0))
+
+
+@pytest.mark.parametrize("dist", ["uniform", "wide"])
+def test_qgemm_crt_2048_sampled(h, dist):
+    """The benchmarked size (2048^3 NN) with the default moduli count, 24 x 24
+    sampled entries within 8 k 2^-209 of the oracle."""
+    n = k = 2048
+    c = W.qgemm_case(W.BASE_SEED + 10, "N", "N", n, n, k, dist=dist)
+    rng = np.random.default_rng(12)
+    I = np.sort(rng.choice(n, 24, replace=False))
+    J = np.sort(rng.choice(n, 24, replace=False))
+    O = qgemm_oracle(csub(c, I, J))
+    idx = (I[:, None] + J[None, :] * c["ldc"]).ravel(order="F")
+    info, G = qgemm_crt_gpu(h, c)
+    assert info == 0
+    r = qratio(tuple(p[idx] for p in G), O, np.arange(24 * 24), k)
+    log(f"QD CRT {n}^3 {dist}: sampled ratio {r:.4g}")
+    assert r <= RATIO_MAX
