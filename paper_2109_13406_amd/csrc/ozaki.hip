@@ -372,22 +372,6 @@ __device__ __forceinline__ void oz_tile_of(int b, int tri, int tiles_m, int tile
 
 // ---- products: INT8 ---------------------------------------------------------------------
 
-// Modular split form (oz_gemm_i8_dma with CRT): group g of workgroups
-// computes the single product of residue plane t = nslices - 1 - g of both
-// operands.  It is the anti-diagonal d = 2 of the planes offset by t, so the
-// kernel runs it unchanged up to the epilogue, which stores the product's
-// entries reduced to balanced residues modulo m_t as int8 (crt_store4) in
-// plane t of x.  Returns t.
-__device__ __forceinline__ int crt_product_of(int& d, const int8_t* __restrict__& qa,
-                                              const int8_t* __restrict__& qb, int64_t plane_a,
-                                              int64_t plane_b) {
-  const int t = d - 2;
-  qa += (int64_t)t * plane_a;
-  qb += (int64_t)t * plane_b;
-  d = 2;
-  return t;
-}
-
 // Four consecutive entries (rows i..i+3 of one column) of a residue product,
 // |X| < 2^31, reduced modulo m: X (1/m) is within 2^-29 of X/m, so rint gives
 // the nearest integer and X - q m (one exact fma) is the balanced residue (for
@@ -563,7 +547,7 @@ __global__ void __launch_bounds__(64 * GM * GN, 1)
 oz_gemm_i8_dma(const int8_t* __restrict__ qa, const int8_t* __restrict__ qb,
                int32_t* __restrict__ x, int64_t kp, int64_t plane_a, int64_t plane_b, int64_t mp,
                int64_t np, int nslices, int tiles_m, int tiles_n, int tri, CrtModuli cm,
-               int crt_count) {
+               int crt_count, int crt_total, int crt_group) {
   constexpr int NW = GM * GN;                  // waves
   constexpr int WR = WM / GM, WC = WN / GN;    // outputs per wave
   constexpr int MT = M32 ? 32 : 16;            // MFMA tile edge
@@ -581,7 +565,18 @@ oz_gemm_i8_dma(const int8_t* __restrict__ qa, const int8_t* __restrict__ qb,
 
   int d, bi, bj;
   oz_tile_of(blockIdx.x, tri, tiles_m, tiles_n, nslices, d, bi, bj);
-  const int ct = CRT ? crt_product_of(d, qa, qb, plane_a, plane_b) : -1;
+  // modular form: group d - 2 of crt_group consecutive residue planes; the
+  // workgroup multiplies plane ct0 + g of both operands for each g in turn
+  // (one k-sweep each, slice it - 1 of both operands below), storing each
+  // product when its sweep ends
+  int ct0 = 0;
+  if constexpr (CRT) {
+    ct0 = (d - 2) * crt_group;
+    const int here = min(crt_group, crt_total - ct0);
+    qa += (int64_t)ct0 * plane_a;
+    qb += (int64_t)ct0 * plane_b;
+    d = here + 1;
+  }
   const int64_t i0 = (int64_t)bi * WM, j0 = (int64_t)bj * WN;
 
   typedef int v16i __attribute__((ext_vector_type(16)));
@@ -610,7 +605,8 @@ oz_gemm_i8_dma(const int8_t* __restrict__ qa, const int8_t* __restrict__ qb,
   int64_t il0 = 0, inext = 0;
   auto issue = [&]() {
     const int8_t* pa = ga + (int64_t)(it - 1) * plane_a + il0;
-    const int8_t* pb = gb + (int64_t)(d - it - 1) * plane_b + il0;   // op(B) slice d - t
+    // op(B) slice d - t (the modular form: the same plane as op(A))
+    const int8_t* pb = gb + (int64_t)(CRT ? it - 1 : d - it - 1) * plane_b + il0;
     int8_t* st = smem + ibuf * STAGE;
 #pragma unroll
     for (int e = 0; e < LA; ++e)
@@ -672,6 +668,39 @@ oz_gemm_i8_dma(const int8_t* __restrict__ qa, const int8_t* __restrict__ qb,
     __builtin_amdgcn_s_waitcnt(0xC07F);        // lgkmcnt(0); vmcnt, expcnt not waited on
     __builtin_amdgcn_sched_barrier(0);
   };
+  // modular form: store the finished product of plane ct as int8 residues
+  // modulo modulus ct % crt_count (a complex or qd product runs three products
+  // per modulus, planes t, count + t, 2 count + t) and clear the accumulators
+  // C layout: 16 x 16 tile, lane l holds rows 4 (l / 16) + 0..3 of column
+  // l % 16; 32 x 32 tile, lane l holds rows 8 g + 4 (l / 32) + 0..3 of column
+  // l % 32 in registers 4 g .. 4 g + 3
+  auto crt_epilogue = [&](int ct) {
+    int8_t* xq = (int8_t*)x + (int64_t)ct * mp * np;
+    const int mt = ct % crt_count;
+    const double mm = cm.m[mt], mi = cm.minv[mt];
+#pragma unroll
+    for (int a = 0; a < FA; ++a)
+#pragma unroll
+      for (int c = 0; c < FB; ++c) {
+        const int64_t j = j0 + wn * WC + c * MT + (lane & (MT - 1));
+        if constexpr (M32) {
+#pragma unroll
+          for (int g = 0; g < 4; ++g) {
+            const int64_t i = i0 + wm * WR + a * MT + 8 * g + 4 * (lane >> 5);
+            crt_store4(xq + j * mp + i, acc[a][c][4 * g], acc[a][c][4 * g + 1],
+                       acc[a][c][4 * g + 2], acc[a][c][4 * g + 3], mm, mi);
+          }
+        } else {
+          const int64_t i = i0 + wm * WR + a * MT + (lane >> 4) * 4;
+          crt_store4(xq + j * mp + i, acc[a][c][0], acc[a][c][1], acc[a][c][2], acc[a][c][3],
+                     mm, mi);
+        }
+        acc[a][c] = accv{};
+      }
+  };
+  int64_t next_end = ksteps;                   // step count at which the current product ends
+  int done = 0;                                // products of the group stored so far
+
   constexpr int PER = LA + LB;                 // DMA instructions per step and wave
   // LDS reads that may stay in flight at a barrier: the prefetch (FA + FB
   // reads), capped by the 4-bit counter (waiting for its oldest read as well
@@ -690,6 +719,12 @@ oz_gemm_i8_dma(const int8_t* __restrict__ qa, const int8_t* __restrict__ qb,
       v4i af[KS * FA], bf[KS * FB];
       fetch((int)(s % NS), af, bf);
       mfma(af, bf);
+      if constexpr (CRT) {
+        if (s + 1 == next_end && s + 1 < total) {
+          crt_epilogue(ct0 + done++);
+          next_end += ksteps;
+        }
+      }
     }
   } else {
     // fragments of step s + 1 are read from LDS while the MFMAs of step s run
@@ -714,39 +749,21 @@ oz_gemm_i8_dma(const int8_t* __restrict__ qa, const int8_t* __restrict__ qb,
       frags_landed();
       fetch((int)((s + 2) % NS), af0, bf0);
       mfma(af1, bf1);
+      if constexpr (CRT) {
+        // a sweep ends after an even step count (ksteps is even)
+        if (s + 2 == next_end && s + 2 < total) {
+          crt_epilogue(ct0 + done++);
+          next_end += ksteps;
+        }
+      }
     }
   }
   // the loads past the end must land before the workgroup's LDS is released
   __builtin_amdgcn_s_waitcnt(0x0F70);          // vmcnt(0), lgkmcnt not waited on
   __builtin_amdgcn_sched_barrier(0);
 
-  // C layout: 16 x 16 tile, lane l holds rows 4 (l / 16) + 0..3 of column
-  // l % 16; 32 x 32 tile, lane l holds rows 8 g + 4 (l / 32) + 0..3 of column
-  // l % 32 in registers 4 g .. 4 g + 3
   if constexpr (CRT) {
-    // plane ct holds a product modulo modulus ct % crt_count (a complex
-    // product runs three products per modulus, planes t, count + t, 2 count + t)
-    int8_t* xq = (int8_t*)x + (int64_t)ct * mp * np;
-    const int mt = ct % crt_count;
-    const double mm = cm.m[mt], mi = cm.minv[mt];
-#pragma unroll
-    for (int a = 0; a < FA; ++a)
-#pragma unroll
-      for (int c = 0; c < FB; ++c) {
-        const int64_t j = j0 + wn * WC + c * MT + (lane & (MT - 1));
-        if constexpr (M32) {
-#pragma unroll
-          for (int g = 0; g < 4; ++g) {
-            const int64_t i = i0 + wm * WR + a * MT + 8 * g + 4 * (lane >> 5);
-            crt_store4(xq + j * mp + i, acc[a][c][4 * g], acc[a][c][4 * g + 1],
-                       acc[a][c][4 * g + 2], acc[a][c][4 * g + 3], mm, mi);
-          }
-        } else {
-          const int64_t i = i0 + wm * WR + a * MT + (lane >> 4) * 4;
-          crt_store4(xq + j * mp + i, acc[a][c][0], acc[a][c][1], acc[a][c][2], acc[a][c][3],
-                     mm, mi);
-        }
-      }
+    crt_epilogue(ct0 + done);
     return;
   }
   int32_t* xd = x + (int64_t)(d - 2) * mp * np;
@@ -1660,7 +1677,7 @@ static void launch_i8_products(int var, unsigned nblocks, const int8_t* qa, cons
                 : (var == 7) ? oz_gemm_i8_dma<256, 256, 2, 2, 4, true, false>
                              : oz_gemm_i8_dma<256, 256, 2, 4, 4, true, true>;
     hipLaunchKernelGGL(kern, dim3(nblocks), dim3(var == 7 ? 256 : 512), 0, st, qa, qb, x, kp,
-                       mp * kp, np * kp, mp, np, s, tiles_m, tiles_n, tri, CrtModuli{}, 1);
+                       mp * kp, np * kp, mp, np, s, tiles_m, tiles_n, tri, CrtModuli{}, 1, 0, 1);
     return;
   }
   auto kern = (var == 0)   ? oz_gemm_i8<256, 256, 2, 2>
@@ -1679,16 +1696,23 @@ static void launch_i8_products(int var, unsigned nblocks, const int8_t* qa, cons
 static bool crt_variant(int var) { return var == 5 || var == 6 || var == 8; }
 
 // nprod products of residue planes (plane t of both operands into plane t
-// of x), plane t modulo modulus t % count.
-static void launch_crt_products(int var, unsigned nblocks, const int8_t* qa, const int8_t* qb,
-                                int8_t* x, int64_t kp, int64_t mp, int64_t np, int nprod,
-                                int count, int tiles_m, int tiles_n, int tri,
-                                const CrtModuli& cm, hipStream_t st) {
+// of x), plane t modulo modulus t % count.  A workgroup takes a group of
+// consecutive planes of its tile when the k-sweep is short (k <= 4096: 2,
+// k <= 2048: 4), so that the pipeline fill and drain are paid once per
+// group.
+static void launch_crt_products(int var, const int8_t* qa, const int8_t* qb, int8_t* x,
+                                int64_t kp, int64_t mp, int64_t np, int nprod, int count,
+                                int tiles_m, int tiles_n, int tri, const CrtModuli& cm,
+                                hipStream_t st) {
   auto kern = (var == 5)   ? oz_gemm_i8_dma<256, 256, 2, 4, 4, false, false, true>
               : (var == 6) ? oz_gemm_i8_dma<256, 256, 2, 4, 4, true, false, true>
                            : oz_gemm_i8_dma<256, 256, 2, 4, 4, true, true, true>;
+  const int64_t ksteps = kp / I8_BK;
+  const int group = (ksteps <= 32) ? 4 : (ksteps <= 64) ? 2 : 1;
+  const int ngroups = (nprod + group - 1) / group;
+  const unsigned nblocks = (unsigned)(oz_group_tiles(tri, tiles_m, tiles_n) * ngroups);
   hipLaunchKernelGGL(kern, dim3(nblocks), dim3(512), 0, st, qa, qb, (int32_t*)x, kp, mp * kp,
-                     np * kp, mp, np, nprod, tiles_m, tiles_n, tri, cm, count);
+                     np * kp, mp, np, ngroups, tiles_m, tiles_n, tri, cm, count, nprod, group);
 }
 
 // Residues of one row operand (scale exponents first).
@@ -1773,8 +1797,7 @@ static int ozaki_crt_gemm(const mpdd_opts* opts, int tri, bool ta, bool tb, int6
     e = crt_operand(b_hi, b_lo, b_sr, b_sl, n, k, eb, qb, kp, np, count, p, rc, part, st);
   if (e == hipSuccess) {
     const int tiles_m = (int)(mp / i8_tile_rows(var)), tiles_n = (int)(np / i8_tile_cols(var));
-    launch_crt_products(var, (unsigned)(oz_group_tiles(tri, tiles_m, tiles_n) * count), qa, qb,
-                        x, kp, mp, np, count, count, tiles_m, tiles_n, tri, cm, st);
+    launch_crt_products(var, qa, qb, x, kp, mp, np, count, count, tiles_m, tiles_n, tri, cm, st);
     launch_crt_combine(limbs, x, mp, np, count, p, cc, ea, eb, m, n, alpha_hi, alpha_lo, beta_hi,
                        beta_lo, (int)beta_zero, c_hi, c_lo, ldc, tri, st);
     e = hipGetLastError();
@@ -1831,8 +1854,7 @@ int ozaki_crt_cgemm(const void* opts_v, int opa, int opb, int64_t m, int64_t n, 
   launch_crt_residues(b[2], b[3], b_sr, b_sl, n, k, eb, qb + sb, kp, np, count, p, rc, st,
                       opb == 2 ? -1.0 : 1.0, qb, qb + 2 * sb);
   const int tiles_m = (int)(mp / i8_tile_rows(var)), tiles_n = (int)(np / i8_tile_cols(var));
-  launch_crt_products(var, (unsigned)(tiles_m * tiles_n * 3 * count), qa, qb, x, kp, mp, np,
-                      3 * count, count, tiles_m, tiles_n, 0, cm, st);
+  launch_crt_products(var, qa, qb, x, kp, mp, np, 3 * count, count, tiles_m, tiles_n, 0, cm, st);
   auto kern = (limbs <= 1)   ? oz_crt_combine_c<1>
               : (limbs == 2) ? oz_crt_combine_c<2>
               : (limbs == 3) ? oz_crt_combine_c<3>
@@ -1894,8 +1916,7 @@ int ozaki_crt_qgemm(const void* opts_v, bool ta, bool tb, int64_t m, int64_t n, 
                      dim3(512), 0, st, b[0], b[1], b[2], b[3], b_sr, b_sl, n, k, eb, count, rc,
                      qb, qb + sb, qb + 2 * sb, kp, np * kp);
   const int tiles_m = (int)(mp / i8_tile_rows(var)), tiles_n = (int)(np / i8_tile_cols(var));
-  launch_crt_products(var, (unsigned)(tiles_m * tiles_n * 3 * count), qa, qb, x, kp, mp, np,
-                      3 * count, count, tiles_m, tiles_n, 0, cm, st);
+  launch_crt_products(var, qa, qb, x, kp, mp, np, 3 * count, count, tiles_m, tiles_n, 0, cm, st);
   hipLaunchKernelGGL(oz_crt_combine_qdm, dim3((unsigned)((m * n + 255) / 256)), dim3(256), 0, st,
                      x, mp, np, count, c26, ea, eb, m, n,
                      double4{alpha[0], alpha[1], alpha[2], alpha[3]},
