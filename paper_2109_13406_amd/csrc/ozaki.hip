@@ -1516,8 +1516,8 @@ oz_crt_residues_qd(const double* __restrict__ x0, const double* __restrict__ x1,
 // (|S_l| < 2^39; q M_l < 2^39), with carries into balanced limbs; then the
 // product A 2^208 + (C - A - B) 2^104 + B limb by limb (offsets 8 and 4
 // limbs), carried again, and the limbs, scaled by 2^(26 l + sigma_i + tau_j
-// - 416), added into a qd from the lowest up (TwoSum cascade and
-// renormalisation per limb); then C = alpha P + beta C in qd as
+// - 416), added into a qd from the lowest up, two limbs at a time (TwoSum
+// cascade and renormalisation per pair); then C = alpha P + beta C in qd as
 // oz_combine_qd.
 __global__ void __launch_bounds__(256)
 oz_crt_combine_qdm(const int8_t* __restrict__ x, int64_t mp, int64_t np, int count,
@@ -1576,11 +1576,14 @@ oz_crt_combine_qdm(const int8_t* __restrict__ x, int64_t mp, int64_t np, int cou
     tl[l] = fma(-c, 0x1p26, tl[l]);
     tl[l + 1] += c;
   }
+  // two balanced limbs make one exact binary64 (|l0 + l1 2^26| < 2^52), so
+  // the qd takes T / 2 additions
   const int e = ea[i] + eb[j] - 2 * CRT_QD_GRID_BITS;
   qacc p{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-  for (int l = 0; l < T; ++l) {
-    const double v = ldexp(tl[l], 26 * l + e);
+  for (int l = 0; l < T; l += 2) {
+    const double pair = fma(tl[l + 1], 0x1p26, tl[l]);
+    const double v = ldexp(pair, 26 * l + e);
     double er;
     ts(p.s0, v, p.s0, er);
     ts(p.s1, er, p.s1, er);
