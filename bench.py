@@ -1032,6 +1032,18 @@ def main():
         log(f"cgemm: {out['cgemm']}")
     if "ozaki" in sections:
         out["ozaki"] = bench_ozaki(h, args, stream, t_kernel)
+        # the fastest split form at the headline size that met the oracle bound
+        best = None
+        for key, rec in out["ozaki"].items():
+            if rec.get("n") == n and rec.get("dd_gflops") and (
+                    best is None or rec["dd_gflops"] > best[1]["dd_gflops"]):
+                best = (key, rec)
+        if best is not None:
+            out["split_best"] = {"form_and_inputs": best[0], "value": best[1]["dd_gflops"],
+                                 "unit": "dd-GFLOPS", "ms": best[1]["ms"],
+                                 "nslices_or_moduli": best[1]["nslices"],
+                                 "ratio_vs_oracle": best[1]["ratio_vs_oracle"],
+                                 "speedup_vs_plain": best[1]["speedup_vs_plain"]}
     if "host" in sections:
         out["host_api"] = bench_host(h, args)
         log(f"host api: {out['host_api']}")
