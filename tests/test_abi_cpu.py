@@ -252,3 +252,26 @@ def test_noalloc_info_codes_before_handle(lib):
     hdr = open(os.path.join(ROOT, "include", "mpdd.h")).read()
     assert "#define MPDD_STATIC_SCRATCH_BYTES ((size_t)64 << 20)" in hdr
     assert "#define MPDD_ERR_SCRATCH (-8)" in hdr
+
+
+def test_crt_exponent_matches_the_modular_oracle(lib):
+    """The library's grid width P of the modular form (host arithmetic on the
+    moduli product) equals the oracle's for every moduli count and a range of
+    k, and the same rejections: k >= 2^17, too few moduli, counts outside
+    1..32, a null output."""
+    from oracle import crt as CRT
+    from paper_2109_13406_amd import binding as b
+    p = ctypes.c_int()
+    for count in range(1, CRT.MAX_MODULI + 1):
+        for k in (0, 1, 2, 3, 7, 64, 100, 1000, 2048, 4097, 8192, 65536, 131071):
+            want = CRT.exponent(k, count)
+            rc = lib.mpdd_ozaki_crt_exponent(k, count, ctypes.byref(p))
+            if want is None:
+                assert rc == b.MPDD_ERR_UNSUPPORTED, (k, count)
+            else:
+                assert rc == 0 and p.value == want, (k, count, p.value, want)
+    assert lib.mpdd_ozaki_crt_exponent(131072, 32, ctypes.byref(p)) == b.MPDD_ERR_UNSUPPORTED
+    for bad in (0, 33):
+        assert lib.mpdd_ozaki_crt_exponent(64, bad, ctypes.byref(p)) == b.MPDD_ERR_ARG
+    assert lib.mpdd_ozaki_crt_exponent(-1, 10, ctypes.byref(p)) == b.MPDD_ERR_ARG
+    assert lib.mpdd_ozaki_crt_exponent(64, 10, None) == b.MPDD_ERR_ARG

@@ -326,3 +326,35 @@ def test_crt_cgemm_matches_crt_oracle(h, op):
                 for p in range(4):
                     assert np.array_equal(bits(G[p]), bits(first[p])), (op, m, n, k, var)
     log(f"PARITY crt cgemm {op} within 2^-99 of the complex modular oracle")
+
+
+@pytest.mark.parametrize("uplo,trans", [("U", "N"), ("L", "N"), ("U", "T"), ("L", "T")])
+def test_crt_syrk_config2_size(h, uplo, trans):
+    """Rsyrk n = k = 8192 (the headline Rsyrk shape) in the modular form with
+    the moduli count the benchmark finds (25): within 8 k 2^-104 of the dd
+    oracle on sampled entries of the triangle."""
+    import torch
+    from gpu_util import sampled_syrk_check
+    n = k = 8192
+    case = W.syrk_case_device(W.BASE_SEED + 2, uplo, trans, n, k)
+    r = sampled_syrk_check(h, f"crt syrk {uplo}{trans} n={n} k={k} moduli=25", case,
+                           opts=dict(algo=_algo(), nslices=25), count=W.CONFIG3_SAMPLE,
+                           seed=W.BASE_SEED + 2)
+    del case
+    torch.cuda.empty_cache()
+    assert r <= RATIO_MAX
+
+
+@pytest.mark.parametrize("op", ["TN", "NT", "TT"])
+def test_crt_gemm_8192_op_forms(h, op):
+    """The other op forms at 8192^3 with the benchmark's 25 moduli, sampled
+    against the dd oracle."""
+    import torch
+    n = 8192
+    case = W.gemm_case_device(W.BASE_SEED + 3, op[0], op[1], n, n, n)
+    r = sampled_gemm_check(h, f"crt {op} n={n} moduli=25", case,
+                           opts=dict(algo=_algo(), nslices=25), count=W.CONFIG3_SAMPLE,
+                           seed=W.BASE_SEED + 3)
+    del case
+    torch.cuda.empty_cache()
+    assert r <= RATIO_MAX
