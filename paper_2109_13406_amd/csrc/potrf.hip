@@ -58,6 +58,9 @@ dd_potf2_block(const double* __restrict__ s_hi, const double* __restrict__ s_lo,
                int upper, double* __restrict__ w_hi, double* __restrict__ w_lo,
                long long* __restrict__ info, long long offset) {
   __shared__ double lh[POTF2_PACK], ll[POTF2_PACK], wh[POTF2_PACK], wl[POTF2_PACK];
+  // row r of packed index q = r (r + 1) / 2 + x (x <= r) of a triangle, for
+  // the trailing updates (filled once; replaces a square root per entry)
+  __shared__ unsigned char tri_row[POTF2_PACK];
   // This workgroup is the critical path of the factorisation and shares its
   // CU with the workgroups of the bulk update running beside it: raise its
   // waves' issue priority so that their dependent chains are not starved.
@@ -65,6 +68,12 @@ dd_potf2_block(const double* __restrict__ s_hi, const double* __restrict__ s_lo,
   // an earlier block of this factorisation failed: leave this one alone
   if (*info != 0) return;
   const int tid = threadIdx.x;
+  for (int q = tid; q < POTF2_PACK; q += POTF2_THREADS) {
+    int r = (int)((__builtin_sqrtf(8.0f * (float)q + 1.0f) - 1.0f) * 0.5f);
+    if ((r + 1) * (r + 2) / 2 <= q) ++r;
+    if (r * (r + 1) / 2 > q) --r;
+    tri_row[q] = (unsigned char)r;
+  }
   for (int t = tid; t < jb * jb; t += POTF2_THREADS) {
     const int i = t % jb, l = t / jb;
     if (i < l) continue;
@@ -154,11 +163,13 @@ dd_potf2_block(const double* __restrict__ s_hi, const double* __restrict__ s_lo,
       // row), then W(i,t), i >= c+2, t <= c
       const int m2 = m - 1;
       const int nl = m2 * (m2 + 1) / 2, nw = m2 * (c + 1);
+      // W entries: r0 = t m2 + (i - c - 2); (r0 + 1/2) / m2 is at least
+      // 1/(2 m2) from an integer and the float product is within 2^-16 of
+      // it, so the truncation gives t exactly (no integer division)
+      const float inv_m2 = 1.0f / (float)m2;
       for (int q = tid - 64; q < nl + nw; q += POTF2_THREADS - 64) {
         if (q < nl) {
-          int r = (int)((__builtin_sqrtf(8.0f * (float)q + 1.0f) - 1.0f) * 0.5f);
-          if ((r + 1) * (r + 2) / 2 <= q) ++r;
-          if (r * (r + 1) / 2 > q) --r;
+          const int r = tri_row[q];
           const int i = c + 2 + r, l = c + 2 + (q - r * (r + 1) / 2);
           const ddv p = dd_mul(ddv{lh[pk(i, c)], ll[pk(i, c)]}, ddv{lh[pk(l, c)], ll[pk(l, c)]});
           const ddv v = dd_add(ddv{lh[pk(i, l)], ll[pk(i, l)]}, dd_neg(p));
@@ -166,7 +177,8 @@ dd_potf2_block(const double* __restrict__ s_hi, const double* __restrict__ s_lo,
           ll[pk(i, l)] = v.lo;
         } else {
           const int r0 = q - nl;
-          const int i = c + 2 + r0 % m2, t = r0 / m2;
+          const int t = (int)(((float)r0 + 0.5f) * inv_m2);
+          const int i = c + 2 + (r0 - t * m2);
           const ddv p = dd_mul(ddv{lh[pk(i, c)], ll[pk(i, c)]}, ddv{wh[pk(c, t)], wl[pk(c, t)]});
           const ddv v = dd_add(ddv{wh[pk(i, t)], wl[pk(i, t)]}, dd_neg(p));
           wh[pk(i, t)] = v.hi;
