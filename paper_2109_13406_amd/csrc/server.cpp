@@ -473,7 +473,11 @@ void scheduler(mpdd_server_s* s) {
       s->admitted.erase(s->admitted.begin(), s->admitted.begin() + take);
       int rc = launch_group(s, *free_sl, g);
       if (rc != 0 && g.size() > 1) {
-        // isolate the failure: run the requests one by one
+        // isolate the failure: run the requests one by one.  The slot stays
+        // marked busy meanwhile (holding no requests), so the submit path,
+        // which may run while the fake device's wait below drops the lock,
+        // cannot launch on it.
+        free_sl->busy = true;
         for (Req* q : g) {
           std::vector<Req*> one{q};
           int r1 = launch_group(s, *free_sl, one);
@@ -482,13 +486,15 @@ void scheduler(mpdd_server_s* s) {
             if (w != hipSuccess) r1 = MPDD_ERR_HIP;
           }
           if (r1 == 0 && s->fake) {
+            const double until = free_sl->fake_done;
             lk.unlock();
-            while (now_s() < free_sl->fake_done) std::this_thread::yield();
+            while (now_s() < until) std::this_thread::yield();
             lk.lock();
           }
           finish(s, q, r1, now_s());
           release(s, q);
         }
+        free_sl->busy = false;
         s->cv_done.notify_all();
       } else if (rc != 0) {
         finish(s, g[0], rc, now_s());
