@@ -861,9 +861,24 @@ def bench_host(h, args):
         if it > 0:
             times.append(dt)
     t = min(times)
+    # the same call with the modular split form's device products
+    opts = dict(algo=b.MPDD_OZAKI_CRT, nslices=CRT_MODULI)
+    times = []
+    for it in range(3):
+        t0 = time.perf_counter()
+        info = b.mpdd_Rgemm_host_ex(h, opts, "N", "N", n, n, n, (0.5, 0.0), A, ld, B, ld,
+                                    (0.25, 0.0), C, ld)
+        dt = time.perf_counter() - t0
+        if info != 0:
+            raise RuntimeError(f"mpdd_Rgemm_host_ex info={info}")
+        if it > 0:
+            times.append(dt)
+    tc = min(times)
     return {"workload": f"Rgemm NN m=n=k={n} ld={ld}, dd_real pairs in pageable host memory",
             "ms": round(t * 1e3, 2), "dd_gflops_with_transfer": round(2.0 * n ** 3 / t / 1e9, 1),
-            "host_bytes_moved": 16 * ld * n * 4}
+            "host_bytes_moved": 16 * ld * n * 4,
+            "split_crt": {"moduli": CRT_MODULI, "ms": round(tc * 1e3, 2),
+                          "dd_gflops_with_transfer": round(2.0 * n ** 3 / tc / 1e9, 1)}}
 
 
 def bench_serve(args):

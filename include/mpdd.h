@@ -213,6 +213,25 @@ int mpdd_Rsyrk_ex(mpdd_handle h, const mpdd_opts *opts, const char *uplo, const 
                   const double *A_lo, mpdd_int lda, mpdd_dd beta, double *C_hi,
                   double *C_lo, mpdd_int ldc, void *stream);
 
+/* The host-pointer calls with explicit options: mpdd_Rgemm_host /
+ * mpdd_Rsyrk_host (same arguments, info codes, copies and pipelining) whose
+ * device products are mpdd_Rgemm_ex / mpdd_Rsyrk_ex with opts (NULL =
+ * defaults); an option the device call rejects returns its code with C
+ * unchanged.  With a split form Rgemm does not multiply its first column
+ * chunk in k-slices (the split scales each row of op(A) over all of k and
+ * sizes its slices or moduli for k), so every chunk gets the same exponents,
+ * slices or moduli as one device call on the whole matrix and C is bit for
+ * bit that call's result; the copies then overlap the products of the later
+ * chunks only.  Meant for the split forms, whose device time at large sizes
+ * falls below the time of the copies. */
+int mpdd_Rgemm_host_ex(mpdd_handle h, const mpdd_opts *opts, const char *transa,
+                       const char *transb, mpdd_int m, mpdd_int n, mpdd_int k, mpdd_dd alpha,
+                       const mpdd_dd *A, mpdd_int lda, const mpdd_dd *B, mpdd_int ldb,
+                       mpdd_dd beta, mpdd_dd *C, mpdd_int ldc);
+int mpdd_Rsyrk_host_ex(mpdd_handle h, const mpdd_opts *opts, const char *uplo,
+                       const char *trans, mpdd_int n, mpdd_int k, mpdd_dd alpha,
+                       const mpdd_dd *A, mpdd_int lda, mpdd_dd beta, mpdd_dd *C, mpdd_int ldc);
+
 /* ---- complex dd: Cgemm ------------------------------------------------------------
  *
  * Cgemm: C <- alpha*op(A)*op(B) + beta*C on complex dd values (manual,

@@ -124,6 +124,10 @@ SIGNATURES = {
     "mpdd_Rgemm_host": (ctypes.c_int, [_P, _C, _C, _I, _I, _I, mpdd_dd, _P, _I, _P, _I, mpdd_dd,
                                        _P, _I]),
     "mpdd_Rsyrk_host": (ctypes.c_int, [_P, _C, _C, _I, _I, mpdd_dd, _P, _I, mpdd_dd, _P, _I]),
+    "mpdd_Rgemm_host_ex": (ctypes.c_int, [_P, ctypes.POINTER(mpdd_opts), _C, _C, _I, _I, _I,
+                                          mpdd_dd, _P, _I, _P, _I, mpdd_dd, _P, _I]),
+    "mpdd_Rsyrk_host_ex": (ctypes.c_int, [_P, ctypes.POINTER(mpdd_opts), _C, _C, _I, _I,
+                                          mpdd_dd, _P, _I, mpdd_dd, _P, _I]),
     "mpdd_struct_size": (ctypes.c_size_t, [_C]),
     "mpdd_clock": (ctypes.c_double, []),
     "mpdd_server_create": (ctypes.c_int, [ctypes.POINTER(_P), _P, ctypes.c_size_t, ctypes.c_int,
@@ -466,27 +470,50 @@ def _host_pairs(x, need=0, name="array"):
     return x.ctypes.data
 
 
+def _opts_ref(opts):
+    o = opts if opts is None or isinstance(opts, mpdd_opts) else _opts(**opts)
+    return ctypes.byref(o) if o is not None else None
+
+
 def mpdd_Rgemm_host(h, transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc):
     """MPBLAS-shaped Rgemm on host dd_real arrays (numpy float64, {hi, lo}
     interleaved).  Synchronous; returns info."""
+    return mpdd_Rgemm_host_ex(h, None, transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C,
+                              ldc, _entry="mpdd_Rgemm_host")
+
+
+def mpdd_Rgemm_host_ex(h, opts, transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc,
+                       _entry="mpdd_Rgemm_host_ex"):
+    """As mpdd_Rgemm_host with explicit options (an mpdd_opts, a dict of its
+    fields, or None)."""
     a, bt = _dd(alpha), _dd(beta)
     ext = _gemm_extents(transa, transb, m, n, k, lda, ldb, ldc)
     ab, ct = _touches(ext, _dd_zero(a), _dd_one(bt), k, m, n)
     ea, eb, ec = ext if ext else (0, 0, 0)
-    return load().mpdd_Rgemm_host(h, _flag(transa), _flag(transb), m, n, k, a,
-                                  _host_pairs(A, ea if ab else 0, "A"), lda,
-                                  _host_pairs(B, eb if ab else 0, "B"), ldb, bt,
-                                  _host_pairs(C, ec if ct else 0, "C"), ldc)
+    args = (_flag(transa), _flag(transb), m, n, k, a, _host_pairs(A, ea if ab else 0, "A"), lda,
+            _host_pairs(B, eb if ab else 0, "B"), ldb, bt, _host_pairs(C, ec if ct else 0, "C"),
+            ldc)
+    if _entry == "mpdd_Rgemm_host":
+        return load().mpdd_Rgemm_host(h, *args)
+    return load().mpdd_Rgemm_host_ex(h, _opts_ref(opts), *args)
 
 
 def mpdd_Rsyrk_host(h, uplo, trans, n, k, alpha, A, lda, beta, C, ldc):
+    return mpdd_Rsyrk_host_ex(h, None, uplo, trans, n, k, alpha, A, lda, beta, C, ldc,
+                              _entry="mpdd_Rsyrk_host")
+
+
+def mpdd_Rsyrk_host_ex(h, opts, uplo, trans, n, k, alpha, A, lda, beta, C, ldc,
+                       _entry="mpdd_Rsyrk_host_ex"):
     a, bt = _dd(alpha), _dd(beta)
     ext = _syrk_extents(uplo, trans, n, k, lda, ldc)
     ab, ct = _touches(ext, _dd_zero(a), _dd_one(bt), k, n, n)
     ea, ec = ext if ext else (0, 0)
-    return load().mpdd_Rsyrk_host(h, _flag(uplo), _flag(trans), n, k, a,
-                                  _host_pairs(A, ea if ab else 0, "A"), lda, bt,
-                                  _host_pairs(C, ec if ct else 0, "C"), ldc)
+    args = (_flag(uplo), _flag(trans), n, k, a, _host_pairs(A, ea if ab else 0, "A"), lda, bt,
+            _host_pairs(C, ec if ct else 0, "C"), ldc)
+    if _entry == "mpdd_Rsyrk_host":
+        return load().mpdd_Rsyrk_host(h, *args)
+    return load().mpdd_Rsyrk_host_ex(h, _opts_ref(opts), *args)
 
 
 def mpdd_ozaki_digit_widths(algo, k, nslices):

@@ -258,9 +258,10 @@ int finish(Staged* bufs, int nb, int rc, hipStream_t st) {
 
 extern "C" {
 
-int mpdd_Rgemm_host(mpdd_handle h, const char* transa, const char* transb, mpdd_int m, mpdd_int n,
-                    mpdd_int k, mpdd_dd alpha, const mpdd_dd* A, mpdd_int lda, const mpdd_dd* B,
-                    mpdd_int ldb, mpdd_dd beta, mpdd_dd* C, mpdd_int ldc) {
+int mpdd_Rgemm_host_ex(mpdd_handle h, const mpdd_opts* opts, const char* transa,
+                       const char* transb, mpdd_int m, mpdd_int n, mpdd_int k, mpdd_dd alpha,
+                       const mpdd_dd* A, mpdd_int lda, const mpdd_dd* B, mpdd_int ldb,
+                       mpdd_dd beta, mpdd_dd* C, mpdd_int ldc) {
   // BLAS argument checks before any allocation or copy (same codes as the
   // device routine, which checks again)
   const bool nota = lsame(transa, 'N'), notb = lsame(transb, 'N');
@@ -290,7 +291,10 @@ int mpdd_Rgemm_host(mpdd_handle h, const char* transa, const char* transb, mpdd_
   // and A's copy overlaps that product.
   const int64_t nchunk = std::max<int64_t>(1, std::min<int64_t>(8, n / 512));
   const int64_t cw = (n + nchunk - 1) / nchunk;          // columns per chunk
-  const bool slice_a = use_ab && nota && k >= 1024;
+  // (plain forms only: a split form scales each row of op(A) over all of k
+  // and sizes its slices or moduli for k, so its chunks take the whole k)
+  const bool plain = !opts || opts->algo == MPDD_PLAIN || opts->algo == MPDD_PLAIN_ACCURATE;
+  const bool slice_a = use_ab && nota && k >= 1024 && plain;
   const int64_t nks = slice_a ? std::min<int64_t>(8, k / 512) : 1;
   const int64_t kcs = (k + nks - 1) / nks;               // k per slice
   hipStream_t sc = nullptr, sx = nullptr;
@@ -340,8 +344,9 @@ int mpdd_Rgemm_host(mpdd_handle h, const char* transa, const char* transb, mpdd_
     const int t = (int)(c & 1);
     if (hipStreamWaitEvent(sc, ev_in[t], 0) != hipSuccess) return MPDD_ERR_HIP;
     const mpdd_int ldbc = notb ? ldb : (mpdd_int)w;
-    int r = mpdd_Rgemm(h, transa, transb, m, w, k, alpha, sa.hi, sa.lo, lda, sbuf[t].hi,
-                       sbuf[t].lo, ldbc, beta, scb[t].hi, scb[t].lo, ldc, (void*)sc);
+    int r = mpdd_Rgemm_ex(h, opts, transa, transb, m, w, k, alpha, sa.hi, sa.lo, lda,
+                          sbuf[t].hi, sbuf[t].lo, ldbc, beta, scb[t].hi, scb[t].lo, ldc,
+                          (void*)sc);
     if (r) return r;
     if (mpdd::launch_join_pairs(scb[t].hi, scb[t].lo, (double*)scb[t].pairs, (int64_t)scb[t].n,
                                 sc) != hipSuccess ||
@@ -366,9 +371,9 @@ int mpdd_Rgemm_host(mpdd_handle h, const char* transa, const char* transb, mpdd_
           hipStreamWaitEvent(sc, ev_a[sl], 0) != hipSuccess)
         return MPDD_ERR_HIP;
       const size_t boff = notb ? (size_t)k0 : (size_t)k0 * (size_t)w;
-      int r = mpdd_Rgemm(h, transa, transb, m, w, kk, alpha, sa.hi + off, sa.lo + off, lda,
-                         sbuf[0].hi + boff, sbuf[0].lo + boff, ldbc, sl == 0 ? beta : one,
-                         scb[0].hi, scb[0].lo, ldc, (void*)sc);
+      int r = mpdd_Rgemm_ex(h, opts, transa, transb, m, w, kk, alpha, sa.hi + off,
+                            sa.lo + off, lda, sbuf[0].hi + boff, sbuf[0].lo + boff, ldbc,
+                            sl == 0 ? beta : one, scb[0].hi, scb[0].lo, ldc, (void*)sc);
       if (r) return r;
     }
     if (mpdd::launch_join_pairs(scb[0].hi, scb[0].lo, (double*)scb[0].pairs, (int64_t)scb[0].n,
@@ -411,9 +416,16 @@ int mpdd_Rgemm_host(mpdd_handle h, const char* transa, const char* transb, mpdd_
   return rc;
 }
 
-int mpdd_Rsyrk_host(mpdd_handle h, const char* uplo, const char* trans, mpdd_int n, mpdd_int k,
-                    mpdd_dd alpha, const mpdd_dd* A, mpdd_int lda, mpdd_dd beta, mpdd_dd* C,
-                    mpdd_int ldc) {
+int mpdd_Rgemm_host(mpdd_handle h, const char* transa, const char* transb, mpdd_int m, mpdd_int n,
+                    mpdd_int k, mpdd_dd alpha, const mpdd_dd* A, mpdd_int lda, const mpdd_dd* B,
+                    mpdd_int ldb, mpdd_dd beta, mpdd_dd* C, mpdd_int ldc) {
+  return mpdd_Rgemm_host_ex(h, nullptr, transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C,
+                            ldc);
+}
+
+int mpdd_Rsyrk_host_ex(mpdd_handle h, const mpdd_opts* opts, const char* uplo,
+                       const char* trans, mpdd_int n, mpdd_int k, mpdd_dd alpha,
+                       const mpdd_dd* A, mpdd_int lda, mpdd_dd beta, mpdd_dd* C, mpdd_int ldc) {
   const bool upper = lsame(uplo, 'U');
   const bool nt = lsame(trans, 'N');
   const mpdd_int nrowa = nt ? n : k, ncola = nt ? k : n;
@@ -441,10 +453,16 @@ int mpdd_Rsyrk_host(mpdd_handle h, const char* uplo, const char* trans, mpdd_int
   if (!rc) rc = upload(bufs[0], A, st, stg);
   if (!rc) rc = upload(bufs[1], C, st, stg);
   if (!rc)
-    rc = mpdd_Rsyrk(h, uplo, trans, n, k, alpha, bufs[0].hi, bufs[0].lo, lda, beta, bufs[1].hi,
-                    bufs[1].lo, ldc, (void*)st);
+    rc = mpdd_Rsyrk_ex(h, opts, uplo, trans, n, k, alpha, bufs[0].hi, bufs[0].lo, lda, beta,
+                       bufs[1].hi, bufs[1].lo, ldc, (void*)st);
   if (!rc) rc = download(bufs[1], C, st, stg);
   return finish(bufs, 2, rc, st);
+}
+
+int mpdd_Rsyrk_host(mpdd_handle h, const char* uplo, const char* trans, mpdd_int n, mpdd_int k,
+                    mpdd_dd alpha, const mpdd_dd* A, mpdd_int lda, mpdd_dd beta, mpdd_dd* C,
+                    mpdd_int ldc) {
+  return mpdd_Rsyrk_host_ex(h, nullptr, uplo, trans, n, k, alpha, A, lda, beta, C, ldc);
 }
 
 }  // extern "C"

@@ -275,3 +275,70 @@ def test_rsyrk_host_exact_extent(h, trans):
     idx = (i + j * case["ldc"])[i <= j]
     assert ratio(G[0][idx], G[1][idx], O[0][idx], O[1][idx], k) <= RATIO_MAX
     log(f"PARITY host-pointer Rsyrk U {trans} exact-extent arrays ok")
+
+
+SPLIT_FORMS = {"i8": dict(algo=1), "f64": dict(algo=2), "crt": dict(algo=5)}
+
+
+@pytest.mark.parametrize("form", sorted(SPLIT_FORMS))
+@pytest.mark.parametrize("op", ["NN", "TN", "NT"])
+def test_rgemm_host_ex_split_equals_device_call(h, form, op):
+    """mpdd_Rgemm_host_ex with a split form: two column chunks, op(A) = A with
+    k >= 1024 (the shape that k-slices the first chunk in the plain forms);
+    C equals the device mpdd_Rgemm_ex result with the same options bit for
+    bit, padding rows included."""
+    from paper_2109_13406_amd import binding as b
+    from gpu_util import gemm_gpu
+    m, n, k = 300, 1100, 1090
+    opts = SPLIT_FORMS[form]
+    case = W.gemm_case(1950 + len(form), op[0], op[1], m, n, k, dist="wide")
+    info, D = gemm_gpu(h, case, opts=opts)
+    assert info == 0
+    C = pairs(case["C"])
+    assert b.mpdd_Rgemm_host_ex(h, opts, op[0], op[1], m, n, k, case["alpha"], pairs(case["A"]),
+                                case["lda"], pairs(case["B"]), case["ldb"], case["beta"], C,
+                                case["ldc"]) == 0
+    G = planes(C)
+    assert np.array_equal(bits(G[0]), bits(D[0])) and np.array_equal(bits(G[1]), bits(D[1]))
+    log(f"PARITY host-pointer Rgemm_ex {form} {op} {m}x{n}x{k} == device call")
+
+
+@pytest.mark.parametrize("form", sorted(SPLIT_FORMS))
+def test_rsyrk_host_ex_split_equals_device_call(h, form):
+    from paper_2109_13406_amd import binding as b
+    from gpu_util import syrk_gpu
+    n, k = 700, 1030
+    opts = SPLIT_FORMS[form]
+    case = W.syrk_case(1960 + len(form), "U", "T", n, k, dist="wide")
+    info, D = syrk_gpu(h, case, opts=opts)
+    assert info == 0
+    C = pairs(case["C"])
+    assert b.mpdd_Rsyrk_host_ex(h, opts, "U", "T", n, k, case["alpha"], pairs(case["A"]),
+                                case["lda"], case["beta"], C, case["ldc"]) == 0
+    G = planes(C)
+    assert np.array_equal(bits(G[0]), bits(D[0])) and np.array_equal(bits(G[1]), bits(D[1]))
+
+
+def test_host_ex_plain_and_rejected_options(h):
+    """NULL options give mpdd_Rgemm_host's bits; an unknown algo returns
+    MPDD_ERR_ARG and an out-of-range moduli count MPDD_ERR_UNSUPPORTED, with
+    C unchanged."""
+    from paper_2109_13406_amd import binding as b
+    m, n, k = 130, 600, 1100
+    case = W.gemm_case(1970, "N", "N", m, n, k, dist="wide")
+    args = lambda C: ("N", "N", m, n, k, case["alpha"], pairs(case["A"]), case["lda"],
+                      pairs(case["B"]), case["ldb"], case["beta"], C, case["ldc"])
+    C1, C2 = pairs(case["C"]), pairs(case["C"])
+    assert b.mpdd_Rgemm_host(h, *args(C1)) == 0
+    assert b.mpdd_Rgemm_host_ex(h, None, *args(C2)) == 0
+    assert np.array_equal(bits(C1), bits(C2))
+    C0 = pairs(case["C"])
+    for bad, code in ((dict(algo=9), b.MPDD_ERR_ARG),
+                      (dict(algo=5, nslices=33), b.MPDD_ERR_UNSUPPORTED)):
+        C3 = C0.copy()
+        assert b.mpdd_Rgemm_host_ex(h, bad, *args(C3)) == code
+        assert np.array_equal(bits(C3), bits(C0))
+        C3 = C0.copy()
+        assert b.mpdd_Rsyrk_host_ex(h, bad, "L", "N", m, k, case["alpha"], pairs(case["A"]),
+                                    case["lda"], case["beta"], C3, case["ldc"]) == code
+        assert np.array_equal(bits(C3), bits(C0))
