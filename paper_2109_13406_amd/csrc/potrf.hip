@@ -19,14 +19,14 @@
 //   trailing triangle, L(i,l) -= L(i,c) L(l,c) for c < l <= i, and W(i,t) -=
 //   L(i,c) W(c,t) for i > c, t <= c.
 //
-//   Look-ahead, one barrier per column: while waves 1-7 apply column c to the
+//   Look-ahead, one barrier per column: while waves 1-15 apply column c to the
 //   trailing entries outside column c+1 and row c+1 of W, wave 0 applies it to
 //   column c+1 and row c+1 of W (jb entries, one per lane), takes the updated
 //   pivot from lane 0 by a cross-lane broadcast and finishes column c+1.
 //   Every entry receives the same operations in the same order as in the
 //   plain column sweep.
 //
-// One workgroup of 512 threads.  The block's lower triangle and W live in LDS
+// One workgroup of 1024 threads.  The block's lower triangle and W live in LDS
 // (packed by rows, 4 x 16.6 KB), so each of the O(jb) dependent steps costs
 // LDS latency, not a global-memory round trip; the block is read once and
 // written once.  All arithmetic is the
@@ -42,7 +42,7 @@ namespace mpdd {
 namespace {
 
 constexpr int POTF2_MAX = 64;       // largest block order
-constexpr int POTF2_THREADS = 512;
+constexpr int POTF2_THREADS = 1024;
 constexpr int POTF2_PACK = POTF2_MAX * (POTF2_MAX + 1) / 2;
 
 __device__ __forceinline__ int64_t lv(int upper, int64_t i, int64_t l, int64_t lda) {
@@ -51,6 +51,15 @@ __device__ __forceinline__ int64_t lv(int upper, int64_t i, int64_t l, int64_t l
 
 // packed lower triangle, row by row: (i, l), l <= i
 __device__ __forceinline__ int pk(int i, int l) { return i * (i + 1) / 2 + l; }
+
+// x of the wave's first active lane, to every lane (two scalar reads; no
+// LDS round trip)
+__device__ __forceinline__ double first_lane(double x) {
+  const unsigned long long u = __builtin_bit_cast(unsigned long long, x);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)u);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(u >> 32));
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
 
 __global__ void __launch_bounds__(POTF2_THREADS)
 dd_potf2_block(const double* __restrict__ s_hi, const double* __restrict__ s_lo, int64_t lds,
@@ -63,8 +72,12 @@ dd_potf2_block(const double* __restrict__ s_hi, const double* __restrict__ s_lo,
   __shared__ unsigned char tri_row[POTF2_PACK];
   // This workgroup is the critical path of the factorisation and shares its
   // CU with the workgroups of the bulk update running beside it: raise its
-  // waves' issue priority so that their dependent chains are not starved.
-  __builtin_amdgcn_s_setprio(3);
+  // waves' issue priority so that their dependent chains are not starved,
+  // wave 0 (which finishes each next column) above the others.
+  if (threadIdx.x < 64)
+    __builtin_amdgcn_s_setprio(3);
+  else
+    __builtin_amdgcn_s_setprio(2);
   // an earlier block of this factorisation failed: leave this one alone
   if (*info != 0) return;
   const int tid = threadIdx.x;
@@ -135,8 +148,9 @@ dd_potf2_block(const double* __restrict__ s_hi, const double* __restrict__ s_lo,
           in_w = true;
           z = dd_add(ddv{wh[o], wl[o]}, dd_neg(dd_mul(lc1, ddv{wh[pk(c, t)], wl[pk(c, t)]})));
         }
-        // the updated pivot, from lane 0 to the whole wave
-        const ddv d{__shfl(z.hi, 0), __shfl(z.lo, 0)};
+        // the updated pivot, from lane 0 (every lane of the wave is active
+        // here) to the whole wave
+        const ddv d{first_lane(z.hi), first_lane(z.lo)};
         if (d.hi > 0.0) {
           const ddv piv = dd_sqrt(d);
           const ddv inv = dd_div(ddv{1.0, 0.0}, piv);     // W(c+1,c+1) = 1 / p
