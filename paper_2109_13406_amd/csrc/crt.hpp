@@ -13,8 +13,10 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <array>
 #include <cmath>
 #include <cstdint>
+#include <mutex>
 
 namespace mpdd {
 
@@ -58,23 +60,34 @@ struct CrtCombineConsts {
   double ml[CRT_MAX_LIMBS], g[CRT_MAX_LIMBS];
 };
 
-// The first `count` moduli: from 256 down, every integer coprime to all the
-// moduli already taken.
-inline void crt_moduli(int count, int* out) {
-  int got = 0;
-  for (int m = 256; got < count && m >= 2; --m) {
-    bool ok = true;
-    for (int i = 0; i < got && ok; ++i) {
-      int a = m, b = out[i];
-      while (b) {
-        const int t = a % b;
-        a = b;
-        b = t;
+// The moduli: from 256 down, every integer coprime to all the moduli
+// already taken (the list is built once per process).
+inline const std::array<int, CRT_MAX_MODULI>& crt_moduli_list() {
+  static const std::array<int, CRT_MAX_MODULI> list = [] {
+    std::array<int, CRT_MAX_MODULI> out{};
+    int got = 0;
+    for (int m = 256; got < CRT_MAX_MODULI && m >= 2; --m) {
+      bool ok = true;
+      for (int i = 0; i < got && ok; ++i) {
+        int a = m, b = out[i];
+        while (b) {
+          const int t = a % b;
+          a = b;
+          b = t;
+        }
+        ok = (a == 1);
       }
-      ok = (a == 1);
+      if (ok) out[got++] = m;
     }
-    if (ok) out[got++] = m;
-  }
+    return out;
+  }();
+  return list;
+}
+
+// The first `count` moduli (count <= CRT_MAX_MODULI).
+inline void crt_moduli(int count, int* out) {
+  const auto& list = crt_moduli_list();
+  for (int t = 0; t < count && t < CRT_MAX_MODULI; ++t) out[t] = list[t];
 }
 
 // Unsigned multiword integer, 32-bit words, least significant first (enough
@@ -127,6 +140,16 @@ inline CrtBig crt_modulus_product(int count) {
   return M;
 }
 
+// Bit length of M for 1 .. CRT_MAX_MODULI moduli (built once per process).
+inline int crt_modulus_bits(int count) {
+  static const std::array<int, CRT_MAX_MODULI + 1> bits = [] {
+    std::array<int, CRT_MAX_MODULI + 1> b{};
+    for (int c = 1; c <= CRT_MAX_MODULI; ++c) b[c] = crt_modulus_product(c).bits();
+    return b;
+  }();
+  return bits[count];
+}
+
 // P: the largest P <= CRT_MAX_BITS with 4 k 2^(2P) <= M (so that every
 // entry of the integer product, at most k 2^(2P) in magnitude, lies in
 // [-M/4, M/4] and is recovered exactly); 0 when count is out of range or
@@ -137,7 +160,7 @@ inline int crt_exponent(int64_t k, int count, int margin = 2) {
   if (count < 1 || count > CRT_MAX_MODULI) return 0;
   int lk = 0;
   while (((int64_t)1 << lk) < k) ++lk;            // ceil(log2 k), k >= 1
-  const int fl = crt_modulus_product(count).bits() - 1;
+  const int fl = crt_modulus_bits(count) - 1;
   int p = (fl - margin - lk);
   p = p >= 0 ? p / 2 : -1;
   if (p > CRT_MAX_BITS) p = CRT_MAX_BITS;
@@ -153,7 +176,8 @@ inline int crt_default_count(int64_t k, int margin = 2) {
 }
 
 // The constant sets for `count` moduli; returns the number of limbs.
-inline int crt_constants(int count, CrtResidueConsts* rc, CrtModuli* cm, CrtCombineConsts* cc) {
+inline int crt_constants_build(int count, CrtResidueConsts* rc, CrtModuli* cm,
+                               CrtCombineConsts* cc) {
   int ms[CRT_MAX_MODULI];
   crt_moduli(count, ms);
   const CrtBig M = crt_modulus_product(count);
@@ -204,7 +228,7 @@ inline bool crt_qd_count_ok(int64_t k, int count) {
   if (count < 1 || count > CRT_MAX_MODULI) return false;
   int lk = 0;
   while (((int64_t)1 << lk) < k) ++lk;
-  return crt_modulus_product(count).bits() - 1 >= 215 + lk;
+  return crt_modulus_bits(count) - 1 >= 215 + lk;
 }
 
 inline int crt_qd_default_count(int64_t k) {
@@ -214,7 +238,7 @@ inline int crt_qd_default_count(int64_t k) {
 }
 
 // CRT weights and M in 26-bit limbs for `count` moduli.
-inline void crt_constants26(int count, CrtCombineConsts26* cc) {
+inline void crt_constants26_build(int count, CrtCombineConsts26* cc) {
   int ms[CRT_MAX_MODULI];
   crt_moduli(count, ms);
   const CrtBig M = crt_modulus_product(count);
@@ -244,6 +268,38 @@ inline void crt_constants26(int count, CrtCombineConsts26* cc) {
     cc->ml[l] = (double)M.field(CRT_LIMB26 * l, CRT_LIMB26);
     cc->g[l] = std::ldexp(minv, CRT_LIMB26 * l);
   }
+}
+
+// crt_constants / crt_constants26 with each count's constants built once per
+// process and copied out afterwards (they depend on the count only; building
+// them costs tens of microseconds of host time per call).  count must lie in
+// 1 .. CRT_MAX_MODULI.
+inline int crt_constants(int count, CrtResidueConsts* rc, CrtModuli* cm, CrtCombineConsts* cc) {
+  struct Entry {
+    std::once_flag once;
+    int limbs = 0;
+    CrtResidueConsts rc;
+    CrtModuli cm;
+    CrtCombineConsts cc;
+  };
+  static Entry table[CRT_MAX_MODULI + 1];
+  Entry& e = table[count];
+  std::call_once(e.once, [&] { e.limbs = crt_constants_build(count, &e.rc, &e.cm, &e.cc); });
+  *rc = e.rc;
+  *cm = e.cm;
+  *cc = e.cc;
+  return e.limbs;
+}
+
+inline void crt_constants26(int count, CrtCombineConsts26* cc) {
+  struct Entry {
+    std::once_flag once;
+    CrtCombineConsts26 cc;
+  };
+  static Entry table[CRT_MAX_MODULI + 1];
+  Entry& e = table[count];
+  std::call_once(e.once, [&] { crt_constants26_build(count, &e.cc); });
+  *cc = e.cc;
 }
 
 // Complex modular product (ozaki.hip): P = op(A) op(B) of complex dd
