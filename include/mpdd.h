@@ -113,14 +113,16 @@ int mpdd_Rsyrk(mpdd_handle h, const char *uplo, const char *trans, mpdd_int n, m
  * entries (a tightly sized array is enough); C is copied both ways over that
  * extent, so padding rows inside it and (Rsyrk) the opposite triangle come
  * back unchanged, and nothing past it is read or written.  Scratch device memory
- * is allocated and freed inside the call.  Copies go through a ring of four
- * 16 MiB pinned host buffers and three copy threads owned by the handle
- * (created by its first host-pointer call, released by mpdd_destroy); the
- * host-pointer calls on one handle are serialised.  Rgemm works on up to 8
- * column chunks of B and C (at least 512 columns each): the copies of one
- * chunk overlap the product of the previous one on a second stream, and
- * with transa = 'N' and k >= 1024 the first chunk is multiplied in k-slices
- * as the matching columns of A arrive (its C accumulated over the slices). */
+ * is allocated and freed inside the call.  Copies go through two rings (one
+ * per direction) of four 16 MiB pinned host buffers, each with three copy
+ * threads, owned by the handle (created by its first host-pointer call,
+ * released by mpdd_destroy); the host-pointer calls on one handle are
+ * serialised.  Rgemm works on up to 8 column chunks of B and C (at least 512
+ * columns each): the copies of one chunk in overlap the product of the
+ * previous one on a second stream and the copy of the one before back (a
+ * helper thread, a third stream), and with transa = 'N' and k >= 1024 the
+ * first chunk is multiplied in k-slices as the matching columns of A arrive
+ * (its C accumulated over the slices). */
 int mpdd_Rgemm_host(mpdd_handle h, const char *transa, const char *transb, mpdd_int m,
                     mpdd_int n, mpdd_int k, mpdd_dd alpha, const mpdd_dd *A, mpdd_int lda,
                     const mpdd_dd *B, mpdd_int ldb, mpdd_dd beta, mpdd_dd *C, mpdd_int ldc);

@@ -228,10 +228,10 @@ int download(Staged& s, mpdd_dd* host, hipStream_t st, mpdd::HostStager* stg) {
   return stg->d2h(host, s.pairs, s.n * sizeof(mpdd_dd), st);
 }
 
-// The handle's stager, created on first use (the caller holds the handle's
-// host-call lock).
-int stager_of(mpdd_handle h, mpdd::HostStager*& out) {
-  mpdd::HostStager** slot = handle_stager(h);
+// One of the handle's two stagers (0: copies to the device, 1: copies
+// back), created on first use (the caller holds the handle's host-call lock).
+int stager_of(mpdd_handle h, mpdd::HostStager*& out, int which = 0) {
+  mpdd::HostStager** slot = handle_stager(h, which);
   if (!*slot) {
     auto* st = new (std::nothrow) mpdd::HostStager();
     if (!st) return MPDD_ERR_ALLOC;
@@ -280,15 +280,20 @@ int mpdd_Rgemm_host_ex(mpdd_handle h, const mpdd_opts* opts, const char* transa,
   const bool use_ab = !dd_zero(alpha) && k > 0;
   if (!C || (use_ab && (!A || !B))) return MPDD_ERR_ARG;
   std::lock_guard<std::mutex> host_lock(*handle_host_mutex(h));
-  mpdd::HostStager* stg = nullptr;
-  if (int r = stager_of(h, stg)) return r;
+  mpdd::HostStager* stg = nullptr;      // copies to the device
+  mpdd::HostStager* stg_d = nullptr;    // copies back
+  if (int r = stager_of(h, stg, 0)) return r;
+  if (int r = stager_of(h, stg_d, 1)) return r;
 
-  // Pipelined over column chunks of C: while chunk c is multiplied on the
-  // compute stream, chunk c+1's operands are copied in and chunk c-1's result
-  // copied out on the copy stream.  A is copied in once; when op(A) = A its
+  // Pipelined over column chunks of C, three chunk buffers in turn: while
+  // chunk c is copied in (copy stream, this thread) and multiplied (compute
+  // stream), chunk c-1's result is copied out by a helper thread through the
+  // second stager on a third stream, so the two copy directions overlap.  A
+  // is copied in once; when op(A) = A and the form is a plain one, its
   // columns are k-slices of the product, so chunk 0 is multiplied slice by
-  // slice as they arrive (accumulating into C with beta = 1 after the first),
-  // and A's copy overlaps that product.
+  // slice as they arrive (accumulating into C with beta = 1 after the
+  // first), and A's copy overlaps that product.
+  constexpr int NBUF = 3;
   const int64_t nchunk = std::max<int64_t>(1, std::min<int64_t>(8, n / 512));
   const int64_t cw = (n + nchunk - 1) / nchunk;          // columns per chunk
   // (plain forms only: a split form scales each row of op(A) over all of k
@@ -297,30 +302,36 @@ int mpdd_Rgemm_host_ex(mpdd_handle h, const mpdd_opts* opts, const char* transa,
   const bool slice_a = use_ab && nota && k >= 1024 && plain;
   const int64_t nks = slice_a ? std::min<int64_t>(8, k / 512) : 1;
   const int64_t kcs = (k + nks - 1) / nks;               // k per slice
-  hipStream_t sc = nullptr, sx = nullptr;
-  hipEvent_t ev_in[2] = {nullptr, nullptr}, ev_out[2] = {nullptr, nullptr};
+  hipStream_t sc = nullptr, sx = nullptr, sd = nullptr;
+  hipEvent_t ev_in[NBUF] = {}, ev_out[NBUF] = {};
   hipEvent_t ev_a[8] = {};
   bool ok = hipStreamCreateWithFlags(&sc, hipStreamNonBlocking) == hipSuccess &&
-            hipStreamCreateWithFlags(&sx, hipStreamNonBlocking) == hipSuccess;
-  for (int t = 0; t < 2 && ok; ++t)
+            hipStreamCreateWithFlags(&sx, hipStreamNonBlocking) == hipSuccess &&
+            hipStreamCreateWithFlags(&sd, hipStreamNonBlocking) == hipSuccess;
+  for (int t = 0; t < NBUF && ok; ++t)
     ok = hipEventCreateWithFlags(&ev_in[t], hipEventDisableTiming) == hipSuccess &&
          hipEventCreateWithFlags(&ev_out[t], hipEventDisableTiming) == hipSuccess;
   for (int64_t t = 0; t < nks && slice_a && ok; ++t)
     ok = hipEventCreateWithFlags(&ev_a[t], hipEventDisableTiming) == hipSuccess;
-  Staged sa, sbuf[2], scb[2];
+  Staged sa, sbuf[NBUF], scb[NBUF];
   int rc = ok ? 0 : MPDD_ERR_HIP;
   // B chunk: columns j0.. of op(B): for 'N' the columns of B, for 'T' its rows
   const size_t nb_chunk = use_ab ? (notb ? (size_t)ldb * cw : (size_t)cw * k) : 0;
   const size_t nc_chunk = (size_t)ldc * cw;
   if (!rc && use_ab) rc = stage_alloc(sa, mpdd::blas_extent(lda, nrowa, ncola), sx, handle_pool(h));
-  for (int t = 0; t < 2 && !rc; ++t) {
+  for (int t = 0; t < NBUF && !rc; ++t) {
     rc = stage_alloc(sbuf[t], nb_chunk, sx, handle_pool(h));
     if (!rc) rc = stage_alloc(scb[t], nc_chunk, sx, handle_pool(h));
   }
+  // the buffers were allocated in stream order on sx: the download stream
+  // starts after that
+  if (!rc && (hipEventRecord(ev_in[0], sx) != hipSuccess ||
+              hipStreamWaitEvent(sd, ev_in[0], 0) != hipSuccess))
+    rc = MPDD_ERR_HIP;
   if (!rc && use_ab && !slice_a) rc = upload(sa, A, sx, stg);
   auto upload_chunk = [&](int64_t c) -> int {
     const int64_t j0 = c * cw, w = std::min<int64_t>(cw, n - j0);
-    const int t = (int)(c & 1);
+    const int t = (int)(c % NBUF);
     if (use_ab) {
       if (notb) {
         sbuf[t].n = mpdd::blas_extent(ldb, k, w);
@@ -341,7 +352,7 @@ int mpdd_Rgemm_host_ex(mpdd_handle h, const mpdd_opts* opts, const char* transa,
   };
   auto multiply_chunk = [&](int64_t c) -> int {
     const int64_t j0 = c * cw, w = std::min<int64_t>(cw, n - j0);
-    const int t = (int)(c & 1);
+    const int t = (int)(c % NBUF);
     if (hipStreamWaitEvent(sc, ev_in[t], 0) != hipSuccess) return MPDD_ERR_HIP;
     const mpdd_int ldbc = notb ? ldb : (mpdd_int)w;
     int r = mpdd_Rgemm_ex(h, opts, transa, transb, m, w, k, alpha, sa.hi, sa.lo, lda,
@@ -382,30 +393,59 @@ int mpdd_Rgemm_host_ex(mpdd_handle h, const mpdd_opts* opts, const char* transa,
       return MPDD_ERR_HIP;
     return 0;
   };
+  // copy chunk c's result back (download stream, second stager)
   auto download_chunk = [&](int64_t c) -> int {
     const int64_t j0 = c * cw;
-    const int t = (int)(c & 1);
-    if (hipStreamWaitEvent(sx, ev_out[t], 0) != hipSuccess) return MPDD_ERR_HIP;
-    return stg->d2h(C + (size_t)j0 * ldc, scb[t].pairs, scb[t].n * sizeof(mpdd_dd), sx);
+    const int t = (int)(c % NBUF);
+    if (hipStreamWaitEvent(sd, ev_out[t], 0) != hipSuccess) return MPDD_ERR_HIP;
+    return stg_d->d2h(C + (size_t)j0 * ldc, scb[t].pairs, scb[t].n * sizeof(mpdd_dd), sd);
+  };
+  // at most one download in flight on the helper thread; joined before the
+  // next one starts (so its buffer, NBUF - 1 chunks back, is free by the time
+  // it is filled again) and before anything is released
+  std::thread helper;
+  int rc_dl = 0;
+  int dev = 0;                   // HIP's current device is per thread
+  if (!rc && hipGetDevice(&dev) != hipSuccess) rc = MPDD_ERR_HIP;
+  auto join_download = [&]() {
+    if (helper.joinable()) helper.join();
+    if (!rc && rc_dl) rc = rc_dl;
+  };
+  auto start_download = [&](int64_t c) {
+    join_download();
+    if (rc) return;
+    try {
+      helper = std::thread([&, c] {
+        rc_dl = hipSetDevice(dev) == hipSuccess ? download_chunk(c) : MPDD_ERR_HIP;
+      });
+    } catch (...) {              // no thread: copy it back here
+      rc = download_chunk(c);
+    }
   };
   if (!rc) rc = upload_chunk(0);
   if (!rc) rc = slice_a ? multiply_chunk0_sliced() : multiply_chunk(0);
   for (int64_t c = 1; c < nchunk && !rc; ++c) {
-    // buffer c & 1 was last used by chunk c-2, downloaded (synchronously)
-    // in the previous iteration
+    // buffer c % NBUF was last used by chunk c - NBUF, whose download was
+    // joined when chunk c - 1's started
     rc = upload_chunk(c);
     if (!rc) rc = multiply_chunk(c);
-    if (!rc) rc = download_chunk(c - 1);
+    if (!rc) start_download(c - 1);
   }
+  join_download();
   if (!rc) rc = download_chunk(nchunk - 1);
-  // release (after both streams have drained; the scratch was allocated
+  // release (after every stream has drained; the scratch was allocated
   // stream-ordered on the copy stream)
   if (sc) (void)hipStreamSynchronize(sc);
-  Staged* all[5] = {&sa, &sbuf[0], &sbuf[1], &scb[0], &scb[1]};
+  if (sd) (void)hipStreamSynchronize(sd);
+  Staged* all[1 + 2 * NBUF] = {&sa};
+  for (int t = 0; t < NBUF; ++t) {
+    all[1 + 2 * t] = &sbuf[t];
+    all[2 + 2 * t] = &scb[t];
+  }
   for (Staged* b : all)
     if (b->base) (void)hipFreeAsync(b->base, sx);
   if (sx && hipStreamSynchronize(sx) != hipSuccess && !rc) rc = MPDD_ERR_HIP;
-  for (int t = 0; t < 2; ++t) {
+  for (int t = 0; t < NBUF; ++t) {
     if (ev_in[t]) (void)hipEventDestroy(ev_in[t]);
     if (ev_out[t]) (void)hipEventDestroy(ev_out[t]);
   }
@@ -413,6 +453,7 @@ int mpdd_Rgemm_host_ex(mpdd_handle h, const mpdd_opts* opts, const char* transa,
     if (e) (void)hipEventDestroy(e);
   if (sc) (void)hipStreamDestroy(sc);
   if (sx) (void)hipStreamDestroy(sx);
+  if (sd) (void)hipStreamDestroy(sd);
   return rc;
 }
 

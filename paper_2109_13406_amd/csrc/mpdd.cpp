@@ -71,12 +71,14 @@ struct mpdd_handle_s {
   // mpdd_destroy.
   hipMemPool_t pool = nullptr;
   std::mutex host_mu;           // serialises the host-pointer calls on this handle
-  HostStager* stager = nullptr; // their pinned staging (created on first use)
+  // their pinned staging (created on first use): [0] for copies to the
+  // device, [1] for copies back, so that the two directions can overlap
+  HostStager* stager[2] = {nullptr, nullptr};
 };
 
 std::mutex* handle_host_mutex(mpdd_handle_s* h) { return &h->host_mu; }
 hipMemPool_t handle_pool(const mpdd_handle_s* h) { return h->pool; }
-HostStager** handle_stager(mpdd_handle_s* h) { return &h->stager; }
+HostStager** handle_stager(mpdd_handle_s* h, int which) { return &h->stager[which]; }
 
 bool handle_valid(const mpdd_handle_s* h) { return h != nullptr && h->magic == 0x6d706464; }
 
@@ -362,7 +364,8 @@ int mpdd_create(mpdd_handle* h, const char* tuner_cache_path) {
 int mpdd_destroy(mpdd_handle h) {
   if (!handle_ok(h)) return MPDD_ERR_HANDLE;
   h->magic = 0;
-  destroy_stager(h->stager);
+  destroy_stager(h->stager[0]);
+  destroy_stager(h->stager[1]);
   // (allocations still being freed on a stream release with their frees)
   (void)hipMemPoolDestroy(h->pool);
   delete h;

@@ -49,7 +49,8 @@ namespace mpdd { class HostStager; }
 std::mutex* handle_host_mutex(mpdd_handle_s* h);
 // The handle's stream-ordered scratch pool.
 hipMemPool_t handle_pool(const mpdd_handle_s* h);
-mpdd::HostStager** handle_stager(mpdd_handle_s* h);
+// which = 0: the stager of copies to the device, 1: of copies back
+mpdd::HostStager** handle_stager(mpdd_handle_s* h, int which);
 void destroy_stager(mpdd::HostStager* st);
 // Handle accessors for other translation units (mpdd.cpp owns the struct).
 bool handle_valid(const mpdd_handle_s* h);
