@@ -342,3 +342,24 @@ def test_host_ex_plain_and_rejected_options(h):
         assert b.mpdd_Rsyrk_host_ex(h, bad, "L", "N", m, k, case["alpha"], pairs(case["A"]),
                                     case["lda"], case["beta"], C3, case["ldc"]) == code
         assert np.array_equal(bits(C3), bits(C0))
+
+
+@pytest.mark.parametrize("form,op", [("crt", "NT"), ("i8", "NN"), ("crt", "TT")])
+def test_rgemm_host_ex_eight_chunks(h, form, op):
+    """Eight column chunks (n = 4096 = 8 x 512) through the three chunk
+    buffers, the copies back overlapping the next chunk's copies in: C equals
+    the device call bit for bit, padding rows included."""
+    from paper_2109_13406_amd import binding as b
+    from gpu_util import gemm_gpu
+    m, n, k = 70, 4096, 300
+    opts = SPLIT_FORMS[form]
+    case = W.gemm_case(1980 + len(form), op[0], op[1], m, n, k, dist="wide")
+    info, D = gemm_gpu(h, case, opts=opts)
+    assert info == 0
+    C = pairs(case["C"])
+    assert b.mpdd_Rgemm_host_ex(h, opts, op[0], op[1], m, n, k, case["alpha"], pairs(case["A"]),
+                                case["lda"], pairs(case["B"]), case["ldb"], case["beta"], C,
+                                case["ldc"]) == 0
+    G = planes(C)
+    assert np.array_equal(bits(G[0]), bits(D[0])) and np.array_equal(bits(G[1]), bits(D[1]))
+    log(f"PARITY host-pointer Rgemm_ex {form} {op} {m}x{n}x{k}, eight chunks == device call")
