@@ -140,8 +140,10 @@ inline CrtBig crt_modulus_product(int count) {
   return M;
 }
 
-// Bit length of M for 1 .. CRT_MAX_MODULI moduli (built once per process).
+// Bit length of M for 1 .. CRT_MAX_MODULI moduli (built once per process;
+// 0 for a count outside that range).
 inline int crt_modulus_bits(int count) {
+  if (count < 1 || count > CRT_MAX_MODULI) return 0;
   static const std::array<int, CRT_MAX_MODULI + 1> bits = [] {
     std::array<int, CRT_MAX_MODULI + 1> b{};
     for (int c = 1; c <= CRT_MAX_MODULI; ++c) b[c] = crt_modulus_product(c).bits();
@@ -272,8 +274,8 @@ inline void crt_constants26_build(int count, CrtCombineConsts26* cc) {
 
 // crt_constants / crt_constants26 with each count's constants built once per
 // process and copied out afterwards (they depend on the count only; building
-// them costs tens of microseconds of host time per call).  count must lie in
-// 1 .. CRT_MAX_MODULI.
+// them costs tens of microseconds of host time per call).  A count outside
+// 1 .. CRT_MAX_MODULI is built each time, uncached.
 inline int crt_constants(int count, CrtResidueConsts* rc, CrtModuli* cm, CrtCombineConsts* cc) {
   struct Entry {
     std::once_flag once;
@@ -283,6 +285,7 @@ inline int crt_constants(int count, CrtResidueConsts* rc, CrtModuli* cm, CrtComb
     CrtCombineConsts cc;
   };
   static Entry table[CRT_MAX_MODULI + 1];
+  if (count < 1 || count > CRT_MAX_MODULI) return crt_constants_build(count, rc, cm, cc);
   Entry& e = table[count];
   std::call_once(e.once, [&] { e.limbs = crt_constants_build(count, &e.rc, &e.cm, &e.cc); });
   *rc = e.rc;
@@ -297,6 +300,7 @@ inline void crt_constants26(int count, CrtCombineConsts26* cc) {
     CrtCombineConsts26 cc;
   };
   static Entry table[CRT_MAX_MODULI + 1];
+  if (count < 1 || count > CRT_MAX_MODULI) return crt_constants26_build(count, cc);
   Entry& e = table[count];
   std::call_once(e.once, [&] { crt_constants26_build(count, &e.cc); });
   *cc = e.cc;
