@@ -363,3 +363,48 @@ def test_rgemm_host_ex_eight_chunks(h, form, op):
     G = planes(C)
     assert np.array_equal(bits(G[0]), bits(D[0])) and np.array_equal(bits(G[1]), bits(D[1]))
     log(f"PARITY host-pointer Rgemm_ex {form} {op} {m}x{n}x{k}, eight chunks == device call")
+
+
+@pytest.mark.parametrize("op", ["NN", "TT"])
+def test_host_ex_modular_exact_extent(h, op):
+    """The modular form through the host-pointer calls on arrays sized exactly
+    to their BLAS extent: nothing past any extent is written, and C equals
+    the device call bit for bit (Rgemm over two column chunks; Rsyrk)."""
+    from paper_2109_13406_amd import binding as b
+    from gpu_util import gemm_gpu, syrk_gpu
+    opts = SPLIT_FORMS["crt"]
+    m, n, k = 300, 1100, 1090
+    case = W.gemm_case(1990, op[0], op[1], m, n, k, dist="wide")
+    ra, ca = (m, k) if op[0] == "N" else (k, m)
+    rb, cb = (k, n) if op[1] == "N" else (n, k)
+    ea = case["lda"] * (ca - 1) + ra
+    eb = case["ldb"] * (cb - 1) + rb
+    ec = case["ldc"] * (n - 1) + m
+    info, D = gemm_gpu(h, case, opts=opts)
+    assert info == 0
+    bufs = [tight(case["A"], ea), tight(case["B"], eb), tight(case["C"], ec)]
+    before = [x[0].copy() for x in bufs]
+    assert b.mpdd_Rgemm_host_ex(h, opts, op[0], op[1], m, n, k, case["alpha"], bufs[0][1],
+                                case["lda"], bufs[1][1], case["ldb"], case["beta"], bufs[2][1],
+                                case["ldc"]) == 0
+    for (full, _), old, e in zip(bufs, before, (ea, eb, ec)):
+        assert np.array_equal(bits(full[e:].ravel()), bits(old[e:].ravel())), op
+    G = planes(bufs[2][1])
+    assert np.array_equal(bits(G[0]), bits(D[0][:ec])) and np.array_equal(bits(G[1]), bits(D[1][:ec]))
+    trans = "N" if op[0] == "N" else "T"
+    ns, ks = 260, 300
+    case = W.syrk_case(1991, "L", trans, ns, ks, dist="wide")
+    ra, ca = (ns, ks) if trans == "N" else (ks, ns)
+    ea = case["lda"] * (ca - 1) + ra
+    ec = case["ldc"] * (ns - 1) + ns
+    info, D = syrk_gpu(h, case, opts=opts)
+    assert info == 0
+    bufs = [tight(case["A"], ea), tight(case["C"], ec)]
+    before = [x[0].copy() for x in bufs]
+    assert b.mpdd_Rsyrk_host_ex(h, opts, "L", trans, ns, ks, case["alpha"], bufs[0][1],
+                                case["lda"], case["beta"], bufs[1][1], case["ldc"]) == 0
+    for (full, _), old, e in zip(bufs, before, (ea, ec)):
+        assert np.array_equal(bits(full[e:].ravel()), bits(old[e:].ravel())), trans
+    G = planes(bufs[1][1])
+    assert np.array_equal(bits(G[0]), bits(D[0][:ec])) and np.array_equal(bits(G[1]), bits(D[1][:ec]))
+    log(f"PARITY host-pointer modular Rgemm {op} / Rsyrk L {trans} exact-extent arrays ok")
