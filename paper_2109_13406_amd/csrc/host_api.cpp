@@ -6,7 +6,8 @@
 // operands to the device, splits them into hi/lo planes, runs the device
 // Rgemm / Rsyrk, interleaves C again and copies it back; it returns when C
 // is complete, like the CPU routine.  Rgemm pipelines the copies of column
-// chunks of B and C with the products of the chunks before them.
+// chunks of B and C with the products of the chunks before them and with the
+// copies back of the chunks before those.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -28,8 +29,9 @@ namespace mpdd {
 // pinned buffers.  A DMA from or to pageable memory runs at about half the
 // pinned rate (measured on MI355X: 29 / 17 GB/s H2D / D2H against 58 / 57),
 // so each piece is copied by host threads into a pinned buffer, and the DMA
-// of one piece overlaps the host copy of the next.  One stager per handle,
-// created by its first host-pointer call; the calls on a handle are
+// of one piece overlaps the host copy of the next.  Two stagers per handle
+// (one per copy direction, so that copies in and copies back can run at
+// once), created by its first host-pointer call; the calls on a handle are
 // serialised.
 class HostStager {
  public:
